@@ -1,0 +1,751 @@
+/*
+ * sdp_oracle.c -- plain CPU FP64 oracle for chordal-decomposed primal ADMM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the GPU
+ * path: the two meet only through the seeded instance generator (sdpgen).
+ *
+ * Paper: Zheng, Fantuzzi, Papachristodoulou, Goulart, Wynn, "Chordal
+ * decomposition in operator-splitting methods for sparse semidefinite
+ * programs".  What is computed, and where it comes from:
+ *
+ *   - Problem: the domain-space decomposition of the primal SDP (Section
+ *     "Domain-space decomposition", problem (DecomposedPrimalSDP)) in the
+ *     vectorised form (DecomposedPrimalVector): min <c,x> s.t. Ax = b,
+ *     x_k = H_k x, x_k in S_k.
+ *   - Iteration: Algorithm 1 ("ADMM for the domain-space decomposition"):
+ *     x-update by the KKT system (OptCondMinYPrimal) solved by block
+ *     elimination with a cached Cholesky factor of A D^-1 A^T
+ *     (ADMMprimalFatorization; the two-step form (KKTflops) of the proof of
+ *     Proposition 1), then the clique PSD projections (XkUpdate), then the
+ *     multiplier update (LambdakUpdate), then the stopping test on
+ *     eps_c and eps_lambda (PrimalConsensusResidual).
+ *   - Optional adaptive penalty of the Section "Adaptive penalty strategy".
+ *   - Diagnostics eps_p, eps_d, eps_g (HSDEerror) and eps_alpha
+ *     (PSD-violation), as the paper reports them for its primal solver.
+ *
+ * Storage.  The global variable x = vec(X) is kept on the lower-triangle
+ * pattern coordinates only ("u"), because X is symmetric and every entry off
+ * the chordal pattern appears in no C, A_i or H_k.  With w_j = 1 on the
+ * diagonal and 2 off it, the KKT system (OptCondMinYPrimal) reads, entry by
+ * entry,
+ *     D_j u_j + sum_i A_ij y_i = bhat_j,          sum_j w_j A_ij u_j = b_i,
+ * with bhat_j = sum_k (X_k + Lambda_k/rho)[at j] - c_j/rho and D_j the number
+ * of cliques holding both endpoints of j.  Eliminating u gives
+ *     (A W D^-1 A^T) y = A (W D^-1 bhat) - b,   u = D^-1 (bhat - A^T y),
+ * which is (KKTflops) written on the compact coordinates; A W D^-1 A^T equals
+ * the paper's A D^-1 A^T on full vectors.  Clique blocks X_k and Lambda_k are
+ * kept as full s_k x s_k row-major matrices and all norms are full Frobenius
+ * norms, exactly as in the vectorised problem.
+ *
+ * Readings where the paper is silent (the same readings the GPU path takes):
+ *   initial guesses X_k = Lambda_k = 0 (x^(0) is never read); eps ratios with
+ *   a zero denominator are 0 when the numerator is 0 and +inf otherwise; the
+ *   adaptive rule uses eps_c as the primal and eps_lambda as the dual
+ *   residual, is applied after the stopping test every rho_period iterations
+ *   and never rescales Lambda (the multipliers are unscaled); the dual
+ *   variable reported is y_dual = -rho * y (the KKT multiplier of Ax = b is
+ *   rho*y).
+ *
+ * Eigen-solver: the paper projects with a library eigendecomposition.  Here
+ * the symmetric eigenproblem is solved by the cyclic-by-row two-sided Jacobi
+ * method with the stable 2x2 rotation of Rutishauser (Golub and Van Loan,
+ * Matrix Computations, sections on the symmetric Schur decomposition and
+ * cyclic Jacobi).  The PSD projection is unique, so the eigenvector basis the
+ * solver returns does not matter.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Status codes: the numeric values are part of the library interface, restated
+ * here (not included) so that the oracle stays independent of the GPU path. */
+enum {
+  ORC_OK = 0,
+  ORC_MAX_ITER = 1,
+  ORC_ERR_ARG = -1,
+  ORC_ERR_PATTERN_UNCOVERED = -2,
+  ORC_ERR_OFF_PATTERN = -3,
+  ORC_ERR_CLIQUE_ORDER = -4,
+  ORC_ERR_RANK_DEFICIENT = -5,
+  ORC_ERR_NONFINITE = -6,
+  ORC_ERR_UNSUPPORTED = -7,
+};
+
+#define ORC_MAX_CLIQUE 128
+
+typedef struct orc_problem {
+  int n, m, p;
+  int64_t nnz;
+  int *pat_row, *pat_col;
+  int *cptr, *cvert;
+  int64_t *blk_off;   /* offset of clique k's s_k*s_k block in X, Lam      */
+  int *loc;           /* loc[blk_off[k] + a*s+b] = pattern index of (v_a,v_b) */
+  double *D, *w;      /* overlap counts and symmetric-storage weights          */
+  int a_format;       /* 0 dense m x nnz row-major, 1 CSR                     */
+  int64_t *a_rowptr;
+  int *a_col;
+  double *a_val;
+  double *b, *c;
+  double *L;          /* m x m Cholesky factor (row-major, lower)              */
+  /* ADMM state */
+  double rho;
+  double *X, *Lam, *Xprev;
+  double *u, *y, *bhat, *r, *tmp;
+  int64_t nblk;       /* sum s_k^2 */
+  int iters;
+  double eps_c, eps_l;
+  /* Jacobi controls and statistics */
+  int jac_max_sweeps;
+  double jac_tol;
+  int64_t total_sweeps;
+  int max_sweeps_seen;
+} orc_problem;
+
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
+
+int orc_get_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Symmetric eigenproblem: cyclic Jacobi                                      */
+/* ------------------------------------------------------------------------- */
+
+/* Stable symmetric 2x2 Schur rotation (c, s) that zeroes A[p][q] of
+ * J^T A J with J = [[c, s], [-s, c]] acting on rows/columns p, q. */
+static void sym_schur2(double app, double aqq, double apq, double *c, double *s) {
+  if (apq == 0.0) { *c = 1.0; *s = 0.0; return; }
+  double tau = (aqq - app) / (2.0 * apq);
+  double t;
+  if (fabs(tau) > 1e150) {
+    t = 0.5 / tau;                     /* sqrt(1 + tau^2) would overflow */
+  } else if (tau >= 0.0) {
+    t = 1.0 / (tau + sqrt(1.0 + tau * tau));
+  } else {
+    t = -1.0 / (-tau + sqrt(1.0 + tau * tau));
+  }
+  *c = 1.0 / sqrt(1.0 + t * t);
+  *s = t * (*c);
+}
+
+static double off_norm2(int s, const double *A) {
+  double acc = 0.0;
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j)
+      if (i != j) acc += A[i * s + j] * A[i * s + j];
+  return acc;
+}
+
+static double frob2(int s, const double *A) {
+  double acc = 0.0;
+  for (int i = 0; i < s * s; ++i) acc += A[i] * A[i];
+  return acc;
+}
+
+/* Eigendecomposition A = V diag(theta) V^T of a symmetric s x s matrix
+ * (row-major, overwritten).  Returns the number of sweeps done. */
+int orc_jacobi_eig(int s, double *A, double *V, double *theta, int max_sweeps,
+                   double tol) {
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) V[i * s + j] = (i == j) ? 1.0 : 0.0;
+  double nrm2 = frob2(s, A);
+  int sweep = 0;
+  while (sweep < max_sweeps && off_norm2(s, A) > tol * tol * nrm2) {
+    for (int p = 0; p < s - 1; ++p) {
+      for (int q = p + 1; q < s; ++q) {
+        double c, sn;
+        sym_schur2(A[p * s + p], A[q * s + q], A[p * s + q], &c, &sn);
+        if (sn == 0.0) continue;
+        /* A <- A J (columns p, q) */
+        for (int k = 0; k < s; ++k) {
+          double akp = A[k * s + p], akq = A[k * s + q];
+          A[k * s + p] = c * akp - sn * akq;
+          A[k * s + q] = sn * akp + c * akq;
+        }
+        /* A <- J^T A (rows p, q) */
+        for (int k = 0; k < s; ++k) {
+          double apk = A[p * s + k], aqk = A[q * s + k];
+          A[p * s + k] = c * apk - sn * aqk;
+          A[q * s + k] = sn * apk + c * aqk;
+        }
+        /* V <- V J */
+        for (int k = 0; k < s; ++k) {
+          double vkp = V[k * s + p], vkq = V[k * s + q];
+          V[k * s + p] = c * vkp - sn * vkq;
+          V[k * s + q] = sn * vkp + c * vkq;
+        }
+      }
+    }
+    ++sweep;
+  }
+  for (int i = 0; i < s; ++i) theta[i] = A[i * s + i];
+  return sweep;
+}
+
+/* Projection onto the PSD cone (XkUpdate): X = V diag(max(theta,0)) V^T.
+ * W is s x s symmetric row-major (not modified).  Optionally returns theta
+ * and V.  Returns the number of Jacobi sweeps. */
+int orc_psd_project(int s, const double *W, double *X, double *theta_out,
+                    double *V_out, int max_sweeps, double tol) {
+  double *A = (double *)malloc(sizeof(double) * s * s);
+  double *V = (double *)malloc(sizeof(double) * s * s);
+  double *th = (double *)malloc(sizeof(double) * (s > 0 ? s : 1));
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j)
+      A[i * s + j] = 0.5 * (W[i * s + j] + W[j * s + i]);
+  int sw = orc_jacobi_eig(s, A, V, th, max_sweeps, tol);
+  for (int i = 0; i < s; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k)
+        if (th[k] > 0.0) acc += V[i * s + k] * th[k] * V[j * s + k];
+      X[i * s + j] = acc;
+      X[j * s + i] = acc;
+    }
+  }
+  if (theta_out) memcpy(theta_out, th, sizeof(double) * s);
+  if (V_out) memcpy(V_out, V, sizeof(double) * s * s);
+  free(A); free(V); free(th);
+  return sw;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense Cholesky and triangular solves (the cached factorisation)            */
+/* ------------------------------------------------------------------------- */
+
+/* M = L L^T, column by column (Cholesky-Crout).  M row-major m x m, only the
+ * lower triangle is read.  Returns ORC_ERR_RANK_DEFICIENT on a non-positive
+ * pivot (the paper assumes linearly independent A_i). */
+int orc_cholesky(int m, const double *M, double *L) {
+  memset(L, 0, sizeof(double) * (size_t)m * m);
+  for (int j = 0; j < m; ++j) {
+    double d = M[(size_t)j * m + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+    if (!(d > 0.0)) return ORC_ERR_RANK_DEFICIENT;
+    double ljj = sqrt(d);
+    L[(size_t)j * m + j] = ljj;
+#pragma omp parallel for schedule(static)
+    for (int i = j + 1; i < m; ++i) {
+      double acc = M[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) acc -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+      L[(size_t)i * m + j] = acc / ljj;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Solve L L^T y = r by forward then backward substitution. */
+void orc_chol_solve(int m, const double *L, const double *r, double *y) {
+  double *z = (double *)malloc(sizeof(double) * (m > 0 ? m : 1));
+  for (int i = 0; i < m; ++i) {
+    double acc = r[i];
+    for (int k = 0; k < i; ++k) acc -= L[(size_t)i * m + k] * z[k];
+    z[i] = acc / L[(size_t)i * m + i];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double acc = z[i];
+    for (int k = i + 1; k < m; ++k) acc -= L[(size_t)k * m + i] * y[k];
+    y[i] = acc / L[(size_t)i * m + i];
+  }
+  free(z);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Products with A on the compact coordinates                                 */
+/* ------------------------------------------------------------------------- */
+
+/* out_i = sum_j A_ij v_j */
+static void a_times(const orc_problem *P, const double *v, double *out) {
+  if (P->a_format == 0) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < P->m; ++i) {
+      const double *row = P->a_val + (size_t)i * P->nnz;
+      double acc = 0.0;
+      for (int64_t j = 0; j < P->nnz; ++j) acc += row[j] * v[j];
+      out[i] = acc;
+    }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < P->m; ++i) {
+      double acc = 0.0;
+      for (int64_t t = P->a_rowptr[i]; t < P->a_rowptr[i + 1]; ++t)
+        acc += P->a_val[t] * v[P->a_col[t]];
+      out[i] = acc;
+    }
+  }
+}
+
+/* out_j = sum_i A_ij y_i  (rows visited in increasing i for every j) */
+static void at_times(const orc_problem *P, const double *y, double *out) {
+  if (P->a_format == 0) {
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < P->nnz; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < P->m; ++i) acc += P->a_val[(size_t)i * P->nnz + j] * y[i];
+      out[j] = acc;
+    }
+  } else {
+    for (int64_t j = 0; j < P->nnz; ++j) out[j] = 0.0;
+    for (int i = 0; i < P->m; ++i)
+      for (int64_t t = P->a_rowptr[i]; t < P->a_rowptr[i + 1]; ++t)
+        out[P->a_col[t]] += P->a_val[t] * y[i];
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Set-up (Algorithm 1, data preprocessing)                                   */
+/* ------------------------------------------------------------------------- */
+
+void orc_free(orc_problem *P) {
+  if (!P) return;
+  free(P->pat_row); free(P->pat_col); free(P->cptr); free(P->cvert);
+  free(P->blk_off); free(P->loc); free(P->D); free(P->w);
+  free(P->a_rowptr); free(P->a_col); free(P->a_val); free(P->b); free(P->c);
+  free(P->L); free(P->X); free(P->Lam); free(P->Xprev);
+  free(P->u); free(P->y); free(P->bhat); free(P->r); free(P->tmp);
+  free(P);
+}
+
+static int finite_all(const double *v, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) if (!isfinite(v[i])) return 0;
+  return 1;
+}
+
+/* Validate the data, build the clique index maps, D, w, and factor
+ * M = A W D^-1 A^T.  All input arrays are copied. */
+int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col,
+               int p, const int *clique_ptr, const int *clique_vert,
+               int a_format, const int64_t *a_rowptr, const int *a_col,
+               const double *a_val, const double *b, const double *c,
+               orc_problem **out) {
+  *out = NULL;
+  if (n <= 0 || m < 0 || nnz <= 0 || p <= 0 || !pat_row || !pat_col ||
+      !clique_ptr || !clique_vert || !a_val || !b || !c ||
+      (a_format != 0 && a_format != 1) ||
+      (a_format == 1 && (!a_rowptr || !a_col)))
+    return ORC_ERR_ARG;
+  /* pattern: lower, in range, strictly sorted by (col, row), diagonal present */
+  int ndiag = 0;
+  for (int64_t j = 0; j < nnz; ++j) {
+    int r = pat_row[j], cc = pat_col[j];
+    if (r < 0 || r >= n || cc < 0 || cc > r) return ORC_ERR_ARG;
+    if (j > 0) {
+      int pr = pat_row[j - 1], pc = pat_col[j - 1];
+      if (cc < pc || (cc == pc && r <= pr)) return ORC_ERR_ARG;
+    }
+    if (r == cc) ++ndiag;
+  }
+  if (ndiag != n) return ORC_ERR_ARG;
+  /* cliques */
+  if (clique_ptr[0] != 0) return ORC_ERR_ARG;
+  for (int k = 0; k < p; ++k) {
+    int s = clique_ptr[k + 1] - clique_ptr[k];
+    if (s <= 0) return ORC_ERR_ARG;
+  }
+  for (int k = 0; k < p; ++k) {
+    int s = clique_ptr[k + 1] - clique_ptr[k];
+    const int *v = clique_vert + clique_ptr[k];
+    for (int a = 0; a < s; ++a) {
+      if (v[a] < 0 || v[a] >= n) return ORC_ERR_CLIQUE_ORDER;
+      if (a > 0 && v[a] <= v[a - 1]) return ORC_ERR_CLIQUE_ORDER;
+    }
+  }
+  for (int k = 0; k < p; ++k)
+    if (clique_ptr[k + 1] - clique_ptr[k] > ORC_MAX_CLIQUE) return ORC_ERR_UNSUPPORTED;
+  /* A in CSR: row pointers monotone, columns in range */
+  int64_t annz = (a_format == 0) ? (int64_t)m * nnz : a_rowptr[m];
+  if (a_format == 1) {
+    if (a_rowptr[0] != 0) return ORC_ERR_ARG;
+    for (int i = 0; i < m; ++i) if (a_rowptr[i + 1] < a_rowptr[i]) return ORC_ERR_ARG;
+    for (int64_t t = 0; t < annz; ++t) if (a_col[t] < 0 || a_col[t] >= nnz) return ORC_ERR_ARG;
+  }
+  if (!finite_all(a_val, annz) || !finite_all(b, m) || !finite_all(c, nnz))
+    return ORC_ERR_NONFINITE;
+
+  orc_problem *P = (orc_problem *)calloc(1, sizeof(orc_problem));
+  P->n = n; P->m = m; P->p = p; P->nnz = nnz;
+  P->pat_row = (int *)malloc(sizeof(int) * nnz);
+  P->pat_col = (int *)malloc(sizeof(int) * nnz);
+  memcpy(P->pat_row, pat_row, sizeof(int) * nnz);
+  memcpy(P->pat_col, pat_col, sizeof(int) * nnz);
+  P->cptr = (int *)malloc(sizeof(int) * (p + 1));
+  memcpy(P->cptr, clique_ptr, sizeof(int) * (p + 1));
+  P->cvert = (int *)malloc(sizeof(int) * (clique_ptr[p] > 0 ? clique_ptr[p] : 1));
+  memcpy(P->cvert, clique_vert, sizeof(int) * clique_ptr[p]);
+  P->a_format = a_format;
+  P->a_val = (double *)malloc(sizeof(double) * (annz > 0 ? annz : 1));
+  memcpy(P->a_val, a_val, sizeof(double) * annz);
+  if (a_format == 1) {
+    P->a_rowptr = (int64_t *)malloc(sizeof(int64_t) * (m + 1));
+    memcpy(P->a_rowptr, a_rowptr, sizeof(int64_t) * (m + 1));
+    P->a_col = (int *)malloc(sizeof(int) * (annz > 0 ? annz : 1));
+    memcpy(P->a_col, a_col, sizeof(int) * annz);
+  }
+  P->b = (double *)malloc(sizeof(double) * (m > 0 ? m : 1));
+  memcpy(P->b, b, sizeof(double) * m);
+  P->c = (double *)malloc(sizeof(double) * nnz);
+  memcpy(P->c, c, sizeof(double) * nnz);
+
+  /* index of every lower coordinate: position table over (col, row) */
+  int64_t *index = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * n);
+  for (size_t t = 0; t < (size_t)n * n; ++t) index[t] = -1;
+  for (int64_t j = 0; j < nnz; ++j) index[(size_t)pat_row[j] * n + pat_col[j]] = j;
+
+  /* H_k as index lists: block entry (a, b) of clique k is pattern coordinate
+   * (max(v_a, v_b), min(v_a, v_b)) -- the entry selector E_Ck of the
+   * Section "Sparse matrix cones and chordal decomposition". */
+  P->blk_off = (int64_t *)malloc(sizeof(int64_t) * (p + 1));
+  P->blk_off[0] = 0;
+  for (int k = 0; k < p; ++k) {
+    int64_t s = clique_ptr[k + 1] - clique_ptr[k];
+    P->blk_off[k + 1] = P->blk_off[k] + s * s;
+  }
+  P->nblk = P->blk_off[p];
+  P->loc = (int *)malloc(sizeof(int) * P->nblk);
+  int rc = ORC_OK;
+  for (int k = 0; k < p && rc == ORC_OK; ++k) {
+    int s = clique_ptr[k + 1] - clique_ptr[k];
+    const int *v = clique_vert + clique_ptr[k];
+    for (int a = 0; a < s && rc == ORC_OK; ++a)
+      for (int bb = 0; bb < s; ++bb) {
+        int r = v[a] > v[bb] ? v[a] : v[bb];
+        int cc = v[a] > v[bb] ? v[bb] : v[a];
+        int64_t j = index[(size_t)r * n + cc];
+        if (j < 0) { rc = ORC_ERR_OFF_PATTERN; break; }
+        P->loc[P->blk_off[k] + (int64_t)a * s + bb] = (int)j;
+      }
+  }
+  free(index);
+  if (rc != ORC_OK) { orc_free(P); return rc; }
+
+  /* D = sum_k H_k^T H_k: per coordinate, the number of cliques covering it.
+   * Counting the lower-triangle block entries (a >= b) visits each covered
+   * coordinate exactly once per clique. */
+  P->D = (double *)calloc(nnz, sizeof(double));
+  P->w = (double *)malloc(sizeof(double) * nnz);
+  for (int k = 0; k < p; ++k) {
+    int s = clique_ptr[k + 1] - clique_ptr[k];
+    for (int a = 0; a < s; ++a)
+      for (int bb = 0; bb <= a; ++bb) P->D[P->loc[P->blk_off[k] + (int64_t)a * s + bb]] += 1.0;
+  }
+  for (int64_t j = 0; j < nnz; ++j) {
+    if (P->D[j] == 0.0) { orc_free(P); return ORC_ERR_PATTERN_UNCOVERED; }
+    P->w[j] = (pat_row[j] == pat_col[j]) ? 1.0 : 2.0;
+  }
+
+  /* M = A W D^-1 A^T (the matrix A D^-1 A^T of ADMMprimalFatorization on the
+   * compact coordinates), then M = L L^T. */
+  double *M = (double *)calloc((size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1), sizeof(double));
+  if (a_format == 0) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < m; ++i) {
+      const double *ri = P->a_val + (size_t)i * nnz;
+      for (int k = 0; k <= i; ++k) {
+        const double *rk = P->a_val + (size_t)k * nnz;
+        double acc = 0.0;
+        for (int64_t j = 0; j < nnz; ++j) acc += ri[j] * (P->w[j] / P->D[j]) * rk[j];
+        M[(size_t)i * m + k] = acc;
+        M[(size_t)k * m + i] = acc;
+      }
+    }
+  } else {
+    /* the same sum over j in increasing order, skipping the zero terms */
+    int64_t *cptrA = (int64_t *)calloc(nnz + 1, sizeof(int64_t));
+    for (int64_t t = 0; t < annz; ++t) cptrA[P->a_col[t] + 1]++;
+    for (int64_t j = 0; j < nnz; ++j) cptrA[j + 1] += cptrA[j];
+    int *rowA = (int *)malloc(sizeof(int) * (annz > 0 ? annz : 1));
+    double *valA = (double *)malloc(sizeof(double) * (annz > 0 ? annz : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * nnz);
+    memcpy(fill, cptrA, sizeof(int64_t) * nnz);
+    for (int i = 0; i < m; ++i)
+      for (int64_t t = P->a_rowptr[i]; t < P->a_rowptr[i + 1]; ++t) {
+        int64_t pos = fill[P->a_col[t]]++;
+        rowA[pos] = i; valA[pos] = P->a_val[t];
+      }
+    for (int64_t j = 0; j < nnz; ++j) {
+      double wd = P->w[j] / P->D[j];
+      for (int64_t s1 = cptrA[j]; s1 < cptrA[j + 1]; ++s1)
+        for (int64_t s2 = cptrA[j]; s2 <= s1; ++s2) {
+          int i = rowA[s1], k = rowA[s2];
+          M[(size_t)i * m + k] += valA[s1] * wd * valA[s2];
+        }
+    }
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < i; ++k) M[(size_t)k * m + i] = M[(size_t)i * m + k];
+    free(cptrA); free(rowA); free(valA); free(fill);
+  }
+  P->L = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
+  rc = orc_cholesky(m, M, P->L);
+  free(M);
+  if (rc != ORC_OK) { orc_free(P); return rc; }
+
+  P->X = (double *)calloc(P->nblk, sizeof(double));
+  P->Lam = (double *)calloc(P->nblk, sizeof(double));
+  P->Xprev = (double *)calloc(P->nblk, sizeof(double));
+  P->u = (double *)calloc(nnz, sizeof(double));
+  P->bhat = (double *)calloc(nnz, sizeof(double));
+  P->tmp = (double *)calloc(nnz, sizeof(double));
+  P->y = (double *)calloc(m > 0 ? m : 1, sizeof(double));
+  P->r = (double *)calloc(m > 0 ? m : 1, sizeof(double));
+  P->rho = 1.0;
+  P->jac_max_sweeps = 50;
+  P->jac_tol = 1e-14;
+  *out = P;
+  return ORC_OK;
+}
+
+/* Initial guesses X_k = Lambda_k = 0 and penalty rho0. */
+void orc_reset(orc_problem *P, double rho0) {
+  memset(P->X, 0, sizeof(double) * P->nblk);
+  memset(P->Lam, 0, sizeof(double) * P->nblk);
+  memset(P->Xprev, 0, sizeof(double) * P->nblk);
+  memset(P->u, 0, sizeof(double) * P->nnz);
+  memset(P->y, 0, sizeof(double) * (P->m > 0 ? P->m : 1));
+  P->rho = rho0;
+  P->iters = 0;
+  P->eps_c = P->eps_l = INFINITY;
+  P->total_sweeps = 0;
+  P->max_sweeps_seen = 0;
+}
+
+void orc_set_jacobi(orc_problem *P, int max_sweeps, double tol) {
+  P->jac_max_sweeps = max_sweeps;
+  P->jac_tol = tol;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One ADMM iteration (Algorithm 1)                                           */
+/* ------------------------------------------------------------------------- */
+
+/* bhat = sum_k H_k^T (x_k + lambda_k / rho) - c / rho   (right-hand side of
+ * OptCondMinYPrimal).  Cliques are summed in increasing k. */
+void orc_form_bhat(const orc_problem *P, const double *X, const double *Lam,
+                   double rho, double *bhat) {
+  for (int64_t j = 0; j < P->nnz; ++j) bhat[j] = 0.0;
+  for (int k = 0; k < P->p; ++k) {
+    int s = P->cptr[k + 1] - P->cptr[k];
+    int64_t o = P->blk_off[k];
+    for (int a = 0; a < s; ++a)
+      for (int bb = 0; bb <= a; ++bb) {
+        int64_t e = o + (int64_t)a * s + bb;
+        bhat[P->loc[e]] += X[e] + Lam[e] / rho;
+      }
+  }
+  for (int64_t j = 0; j < P->nnz; ++j) bhat[j] -= P->c[j] / rho;
+}
+
+/* Solve the KKT system (OptCondMinYPrimal) for given bhat by block
+ * elimination (KKTflops): L L^T y = A W D^-1 bhat - b, u = D^-1(bhat - A^T y). */
+void orc_affine(orc_problem *P, const double *bhat, const double *bvec,
+                double *u, double *y) {
+  for (int64_t j = 0; j < P->nnz; ++j) P->tmp[j] = P->w[j] * bhat[j] / P->D[j];
+  a_times(P, P->tmp, P->r);
+  for (int i = 0; i < P->m; ++i) P->r[i] -= bvec[i];
+  orc_chol_solve(P->m, P->L, P->r, y);
+  at_times(P, y, P->tmp);
+  for (int64_t j = 0; j < P->nnz; ++j) u[j] = (bhat[j] - P->tmp[j]) / P->D[j];
+}
+
+/* E_k U E_k^T as a full s x s block. */
+static void gather_block(const orc_problem *P, int k, const double *u, double *Uk) {
+  int s = P->cptr[k + 1] - P->cptr[k];
+  int64_t o = P->blk_off[k];
+  for (int e = 0; e < s * s; ++e) Uk[e] = u[P->loc[o + e]];
+}
+
+static double ratio(double num, double den) {
+  if (den > 0.0) return num / den;
+  return (num == 0.0) ? 0.0 : INFINITY;
+}
+
+/* Runs up to max_iter iterations of Algorithm 1 from the current state.
+ * Stops when max(eps_c, eps_lambda) <= tol.  Returns ORC_OK when it stopped
+ * on the tolerance, ORC_MAX_ITER otherwise.  Optional per-iteration history
+ * (length max_iter) of eps_c, eps_lambda and the rho used in the iteration. */
+int orc_run(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
+            double nu, int rho_period, int *iters_done, double *hist_eps_c,
+            double *hist_eps_l, double *hist_rho) {
+  int p = P->p;
+  double *part = (double *)calloc((size_t)p * 5, sizeof(double));
+  int *sweeps = (int *)calloc(p, sizeof(int));
+  int done = 0, it;
+  for (it = 0; it < max_iter; ++it) {
+    double rho = P->rho;
+    /* x-update */
+    orc_form_bhat(P, P->X, P->Lam, rho, P->bhat);
+    orc_affine(P, P->bhat, P->b, P->u, P->y);
+    memcpy(P->Xprev, P->X, sizeof(double) * P->nblk);
+    /* clique projections and multiplier updates (independent over k) */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      double *Uk = (double *)malloc(sizeof(double) * s * s);
+      double *Wk = (double *)malloc(sizeof(double) * s * s);
+      gather_block(P, k, P->u, Uk);
+      for (int e = 0; e < s * s; ++e) Wk[e] = Uk[e] - P->Lam[o + e] / rho;
+      sweeps[k] = orc_psd_project(s, Wk, P->X + o, NULL, NULL, P->jac_max_sweeps,
+                                  P->jac_tol);
+      double r_c = 0, n_x = 0, n_hx = 0, r_d = 0, n_l = 0;
+      for (int e = 0; e < s * s; ++e) {
+        double xk = P->X[o + e];
+        P->Lam[o + e] += rho * (xk - Uk[e]);
+        double dc = xk - Uk[e], dx = xk - P->Xprev[o + e], lk = P->Lam[o + e];
+        r_c += dc * dc; n_x += xk * xk; n_hx += Uk[e] * Uk[e];
+        r_d += dx * dx; n_l += lk * lk;
+      }
+      part[5 * k + 0] = r_c; part[5 * k + 1] = n_x; part[5 * k + 2] = n_hx;
+      part[5 * k + 3] = r_d; part[5 * k + 4] = n_l;
+      free(Uk); free(Wk);
+    }
+    double S[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < p; ++k) {
+      for (int t = 0; t < 5; ++t) S[t] += part[5 * k + t];
+      P->total_sweeps += sweeps[k];
+      if (sweeps[k] > P->max_sweeps_seen) P->max_sweeps_seen = sweeps[k];
+    }
+    /* residuals (PrimalConsensusResidual) */
+    double den_c = sqrt(S[1]) > sqrt(S[2]) ? sqrt(S[1]) : sqrt(S[2]);
+    P->eps_c = ratio(sqrt(S[0]), den_c);
+    P->eps_l = ratio(rho * sqrt(S[3]), sqrt(S[4]));
+    if (hist_eps_c) hist_eps_c[it] = P->eps_c;
+    if (hist_eps_l) hist_eps_l[it] = P->eps_l;
+    if (hist_rho) hist_rho[it] = rho;
+    P->iters++;
+    double e = P->eps_c > P->eps_l ? P->eps_c : P->eps_l;
+    if (e <= tol) { done = 1; ++it; break; }
+    /* adaptive penalty */
+    if (adaptive && rho_period > 0 && (P->iters % rho_period) == 0) {
+      if (P->eps_c >= nu * P->eps_l) P->rho = mu * rho;
+      else if (P->eps_l >= nu * P->eps_c) P->rho = rho / mu;
+    }
+  }
+  if (iters_done) *iters_done = it;
+  free(part); free(sweeps);
+  return done ? ORC_OK : ORC_MAX_ITER;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Accessors and diagnostics                                                 */
+/* ------------------------------------------------------------------------- */
+
+int64_t orc_nblk(const orc_problem *P) { return P->nblk; }
+double orc_rho(const orc_problem *P) { return P->rho; }
+int orc_iters(const orc_problem *P) { return P->iters; }
+double orc_eps_c(const orc_problem *P) { return P->eps_c; }
+double orc_eps_l(const orc_problem *P) { return P->eps_l; }
+int64_t orc_total_sweeps(const orc_problem *P) { return P->total_sweeps; }
+int orc_max_sweeps_seen(const orc_problem *P) { return P->max_sweeps_seen; }
+
+void orc_get_u(const orc_problem *P, double *u) { memcpy(u, P->u, sizeof(double) * P->nnz); }
+void orc_get_y(const orc_problem *P, double *y) { memcpy(y, P->y, sizeof(double) * P->m); }
+void orc_get_D(const orc_problem *P, double *D) { memcpy(D, P->D, sizeof(double) * P->nnz); }
+void orc_get_L(const orc_problem *P, double *L) {
+  memcpy(L, P->L, sizeof(double) * (size_t)P->m * P->m);
+}
+void orc_get_blocks(const orc_problem *P, double *X, double *Lam) {
+  if (X) memcpy(X, P->X, sizeof(double) * P->nblk);
+  if (Lam) memcpy(Lam, P->Lam, sizeof(double) * P->nblk);
+}
+void orc_set_blocks(orc_problem *P, const double *X, const double *Lam) {
+  if (X) memcpy(P->X, X, sizeof(double) * P->nblk);
+  if (Lam) memcpy(P->Lam, Lam, sizeof(double) * P->nblk);
+}
+void orc_set_rho(orc_problem *P, double rho) { P->rho = rho; }
+
+/* W_k = E_k U E_k^T - Lambda_k/rho for the current state, blocks concatenated
+ * (the inputs of the projections of the next iteration). */
+void orc_next_w(orc_problem *P, double *W) {
+  orc_form_bhat(P, P->X, P->Lam, P->rho, P->bhat);
+  double *u = (double *)malloc(sizeof(double) * P->nnz);
+  double *y = (double *)malloc(sizeof(double) * (P->m > 0 ? P->m : 1));
+  orc_affine(P, P->bhat, P->b, u, y);
+  for (int k = 0; k < P->p; ++k) {
+    int s = P->cptr[k + 1] - P->cptr[k];
+    int64_t o = P->blk_off[k];
+    gather_block(P, k, u, W + o);
+    for (int e = 0; e < s * s; ++e) W[o + e] -= P->Lam[o + e] / P->rho;
+  }
+  free(u); free(y);
+}
+
+/* <C, X> on the compact coordinates: sum_j w_j c_j u_j. */
+double orc_objective(const orc_problem *P) {
+  double acc = 0.0;
+  for (int64_t j = 0; j < P->nnz; ++j) acc += P->w[j] * P->c[j] * P->u[j];
+  return acc;
+}
+
+/* Diagnostics of the current iterate: out[0] = eps_p, out[1] = eps_d,
+ * out[2] = eps_g (HSDEerror with x = u, y_dual = -rho*y and
+ * z = sum_k H_k^T lambda_k), out[3] = eps_alpha (PSD-violation),
+ * out[4] = objective <C,X>, out[5] = b^T y_dual.  Norms of symmetric
+ * matrices are full (off-diagonal entries weighted by 2). */
+void orc_diagnostics(orc_problem *P, double *out) {
+  int m = P->m;
+  int64_t nnz = P->nnz;
+  double *ax = (double *)calloc(m > 0 ? m : 1, sizeof(double));
+  double *tmp = (double *)calloc(nnz, sizeof(double));
+  double *z = (double *)calloc(nnz, sizeof(double));
+  double *yd = (double *)calloc(m > 0 ? m : 1, sizeof(double));
+  for (int64_t j = 0; j < nnz; ++j) tmp[j] = P->w[j] * P->u[j];
+  a_times(P, tmp, ax);
+  double np = 0, nb = 0;
+  for (int i = 0; i < m; ++i) { double d = ax[i] - P->b[i]; np += d * d; nb += P->b[i] * P->b[i]; }
+  for (int i = 0; i < m; ++i) yd[i] = -P->rho * P->y[i];
+  for (int k = 0; k < P->p; ++k) {
+    int s = P->cptr[k + 1] - P->cptr[k];
+    int64_t o = P->blk_off[k];
+    for (int a = 0; a < s; ++a)
+      for (int bb = 0; bb <= a; ++bb) z[P->loc[o + (int64_t)a * s + bb]] += P->Lam[o + (int64_t)a * s + bb];
+  }
+  at_times(P, yd, tmp);
+  double nd = 0, nc = 0, ctx = 0, bty = 0, nx = 0;
+  for (int64_t j = 0; j < nnz; ++j) {
+    double d = tmp[j] + z[j] - P->c[j];
+    nd += P->w[j] * d * d;
+    nc += P->w[j] * P->c[j] * P->c[j];
+    ctx += P->w[j] * P->c[j] * P->u[j];
+    nx += P->w[j] * P->u[j] * P->u[j];
+  }
+  for (int i = 0; i < m; ++i) bty += P->b[i] * yd[i];
+  double lmin = 0.0;
+  for (int k = 0; k < P->p; ++k) {
+    int s = P->cptr[k + 1] - P->cptr[k];
+    double *Uk = (double *)malloc(sizeof(double) * s * s);
+    double *V = (double *)malloc(sizeof(double) * s * s);
+    double *th = (double *)malloc(sizeof(double) * s);
+    gather_block(P, k, P->u, Uk);
+    orc_jacobi_eig(s, Uk, V, th, P->jac_max_sweeps, P->jac_tol);
+    for (int i = 0; i < s; ++i) if (th[i] < lmin) lmin = th[i];
+    free(Uk); free(V); free(th);
+  }
+  out[0] = sqrt(np) / (1.0 + sqrt(nb));
+  out[1] = sqrt(nd) / (1.0 + sqrt(nc));
+  out[2] = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
+  out[3] = (-lmin) / (1.0 + sqrt(nx));
+  out[4] = ctx;
+  out[5] = bty;
+  free(ax); free(tmp); free(z); free(yd);
+}
+
+/* E_k U E_k^T for every clique (blocks concatenated, full s_k x s_k). */
+void orc_gather_blocks(const orc_problem *P, const double *u, double *blocks) {
+  for (int k = 0; k < P->p; ++k) gather_block(P, k, u, blocks + P->blk_off[k]);
+}
