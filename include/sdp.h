@@ -1,0 +1,181 @@
+/*
+ * sdp.h -- C ABI of libsdp: chordal-decomposed primal ADMM for sparse SDPs on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zheng, Fantuzzi, Papachristodoulou, Goulart, Wynn, "Chordal
+ * decomposition in operator-splitting methods for sparse semidefinite
+ * programs", Algorithm 1 (ADMM for the domain-space decomposition of sparse
+ * primal-form SDPs).
+ *
+ * The problem (the primal SDP of the Introduction, decomposed as in Section
+ * "Domain-space decomposition"):
+ *     minimise <C, X>  subject to  <A_i, X> = b_i (i = 1..m),
+ *                                  E_k X E_k^T  PSD  for every maximal clique C_k
+ * of the chordal aggregate sparsity pattern E (Theorem 1).
+ *
+ * Conventions shared by every entry point:
+ *  - Symmetric matrices on the pattern are given by their lower-triangle
+ *    coordinates (row >= col) sorted by column, then row; every diagonal
+ *    entry (i, i) is present.  The pattern must equal the union of all clique
+ *    pairs (a chordal graph or a chordal extension).
+ *  - Cliques are 0-based vertex lists in strictly increasing order, at most
+ *    128 vertices each (96 for the SDP_FP64 projection).
+ *  - A clique block X_k (s x s) is stored "packed": lower triangle row by
+ *    row, entry (i, j), i >= j, at i*(i+1)/2 + j.
+ *  - All functions return an int status: 0 = SDP_OK, >0 informational,
+ *    <0 error.  No C++ exception crosses the boundary.  After a non-zero
+ *    status, sdp_last_error() returns a thread-local message.
+ */
+#ifndef SDP_H
+#define SDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+  SDP_OK = 0,
+  SDP_MAX_ITER = 1,              /* iteration limit reached before tol      */
+  SDP_ERR_ARG = -1,              /* bad size/pointer/ordering of an input   */
+  SDP_ERR_PATTERN_UNCOVERED = -2,/* a pattern entry lies in no clique (D_jj=0) */
+  SDP_ERR_OFF_PATTERN = -3,      /* a clique holds a pair not in the pattern */
+  SDP_ERR_CLIQUE_ORDER = -4,     /* clique vertices not strictly increasing / out of range */
+  SDP_ERR_RANK_DEFICIENT = -5,   /* A D^-1 A^T not positive definite (A_i dependent) */
+  SDP_ERR_NONFINITE = -6,        /* NaN/Inf in A, b or C                    */
+  SDP_ERR_UNSUPPORTED = -7,      /* clique too large for the chosen precision */
+  SDP_ERR_HIP = -8,              /* a HIP runtime call failed (message has the HIP error) */
+  SDP_ERR_OOM = -9               /* device allocation failed                */
+};
+
+enum { SDP_A_DENSE = 0, SDP_A_CSR = 1 };
+/* precision of the PSD projections (eigensolve + rebuild); the affine step,
+ * multipliers and residuals are always FP64 */
+enum { SDP_FP64 = 0, SDP_FP32_EIG = 1 };
+enum { SDP_DTYPE_FP64 = 0, SDP_DTYPE_FP32 = 1 };
+
+typedef struct sdp_handle sdp_handle;   /* opaque; owns every device buffer it allocates */
+
+/* One SDP instance.  Host memory, caller-owned, copied during sdp_setup. */
+typedef struct {
+  int32_t n;                    /* cone size                                   */
+  int32_t m;                    /* number of equality constraints             */
+  int64_t nnz_pattern;          /* number of lower pattern coordinates        */
+  const int32_t *pat_row;       /* [nnz_pattern]                              */
+  const int32_t *pat_col;       /* [nnz_pattern]                              */
+  int32_t p;                    /* number of maximal cliques                  */
+  const int32_t *clique_ptr;    /* [p+1], clique_ptr[0] = 0                   */
+  const int32_t *clique_vert;   /* [clique_ptr[p]]                            */
+  int32_t a_format;             /* SDP_A_DENSE: a_val is m x nnz_pattern row-major;
+                                   SDP_A_CSR: a_rowptr/a_col/a_val over pattern coordinates */
+  const int64_t *a_rowptr;      /* [m+1] (CSR only)                           */
+  const int32_t *a_col;         /* [a_rowptr[m]] (CSR only)                   */
+  const double *a_val;          /* lower-triangle values (A_i)_{row,col}      */
+  const double *b;              /* [m]                                        */
+  const double *c;              /* [nnz_pattern] lower-triangle values of C   */
+} sdp_instance;
+
+/* Solver options (Algorithm 1, first step: rho, eps_tol, n_max; adaptive
+ * penalty parameters mu, nu of the Section "Adaptive penalty strategy"). */
+typedef struct {
+  double rho;                   /* initial penalty rho_0 (> 0)                */
+  double tol;                   /* stop when max(eps_c, eps_lambda) <= tol    */
+  int32_t max_iter;             /* n_max                                      */
+  int32_t precision;            /* SDP_FP64 or SDP_FP32_EIG                   */
+  int32_t adaptive_rho;         /* 0/1                                        */
+  double mu, nu;                /* adaptive rule factors (>= 1)               */
+  int32_t rho_period;           /* apply the rule every rho_period iterations */
+  int32_t graph_chunk;          /* iterations per captured HIP graph (0: plain launches) */
+  void *stream;                 /* hipStream_t to run on (NULL: the library's own stream) */
+  int32_t jacobi_max_sweeps;    /* 0: default (30 for FP32, 40 for FP64)     */
+  double jacobi_tol;            /* 0: default; off(A) <= tol * ||A||_F stops the sweeps */
+} sdp_options;
+
+/* Per-instance result. */
+typedef struct {
+  int32_t iters;                /* iterations executed                        */
+  int32_t status;               /* SDP_OK (converged) or SDP_MAX_ITER         */
+  double eps_c, eps_lambda;     /* residuals of the last iteration            */
+  double objective;             /* <C, X> = sum_j w_j c_j u_j                  */
+  double rho;                   /* penalty after the last iteration           */
+  double eps_p, eps_d, eps_g;   /* primal/dual residuals and gap (NaN unless computed) */
+  double eps_alpha;             /* PSD-completability violation (NaN unless computed) */
+} sdp_result;
+
+/* Fills *opt with defaults: rho 1, tol 1e-4, max_iter 20000, SDP_FP64,
+ * adaptive off, mu 2, nu 10, rho_period 1, graph_chunk 25, own stream. */
+void sdp_default_options(sdp_options *opt);
+
+/* Validates `batch` instances, copies them to the device, builds the clique
+ * index lists, the overlap counts D = sum_k H_k^T H_k (Section "Minimization
+ * over X"), factors A D^-1 A^T = L L^T once in FP64 on the GPU and caches the
+ * inverse factor, and sets X_k = Lambda_k = 0.  Instances are independent and
+ * are iterated together.  On error nothing is allocated and *out is NULL. */
+int sdp_setup(int32_t batch, const sdp_instance *inst, const sdp_options *opt,
+              sdp_handle **out);
+
+/* Restores the initial state (X_k = Lambda_k = 0, rho = rho_0, 0 iterations)
+ * without redoing the factorisation. */
+int sdp_reset(sdp_handle *h);
+
+/* Enqueues n_steps iterations of Algorithm 1 on the handle's stream: the
+ * x-update through the KKT system (OptCondMinYPrimal) with the cached factor,
+ * the clique projections (XkUpdate), the multiplier update (LambdakUpdate),
+ * the residuals (PrimalConsensusResidual) and the stopping test.  Instances
+ * that have met the tolerance (or max_iter) stay frozen.  With res != NULL
+ * (batch entries) it synchronises and fills the results; with res == NULL it
+ * returns without synchronising. */
+int sdp_admm_step(sdp_handle *h, int32_t n_steps, sdp_result *res);
+
+/* Iterates until every instance meets the tolerance or max_iter; fills res
+ * (batch entries).  Returns SDP_OK if all converged, SDP_MAX_ITER otherwise. */
+int sdp_solve(sdp_handle *h, sdp_result *res);
+
+/* Standalone PSD projection of `count` symmetric blocks (XkUpdate):
+ * out_k = V diag(max(theta, 0)) V^T for in_k = V diag(theta) V^T.
+ * sizes (int32[count]) and offsets (int64[count], element offsets of each
+ * full s x s row-major block) are DEVICE pointers; in/out are device buffers
+ * of `dtype`; every size must be <= max_size <= 128 (96 for FP64).  Blocks
+ * must not overlap between in and out.  Asynchronous on `stream`. */
+int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *sizes,
+                            const int64_t *offsets, const void *in, void *out,
+                            int32_t dtype, void *stream);
+
+/* Copies instance `inst`'s iterate to host memory (any pointer may be NULL):
+ * u[nnz_pattern] the lower values of X; y_dual[m] = -rho*y (the dual
+ * multipliers of <A_i, X> = b_i); Xk/Lk the packed clique blocks of all p
+ * cliques concatenated.  Synchronises. */
+int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual,
+                     double *Xk_packed, double *Lk_packed);
+
+/* Overwrites instance `inst`'s clique blocks (packed, host memory) and its
+ * penalty (rho > 0) -- a warm start.  Synchronises. */
+int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk_packed,
+                  const double *Lk_packed, double rho);
+
+/* Per-instance residual history of the iterations run since setup/reset:
+ * eps_c, eps_lambda and the rho used, up to `cap` entries each (any pointer may
+ * be NULL).  Returns the number of entries written through *count. */
+int sdp_get_history(sdp_handle *h, int32_t inst, int32_t cap, double *eps_c,
+                    double *eps_lambda, double *rho, int32_t *count);
+
+/* Computes the diagnostics eps_p, eps_d, eps_g (HSDEerror, with
+ * z = sum_k H_k^T lambda_k) and eps_alpha (PSD-violation) of the current
+ * iterate on the GPU and stores them in res (batch entries). */
+int sdp_diagnostics(sdp_handle *h, sdp_result *res);
+
+/* Statistics of the last solve: total Jacobi sweeps and projections run. */
+int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
+
+/* Releases every device buffer of the handle. */
+void sdp_destroy(sdp_handle *h);
+
+/* Thread-local message of the last non-zero status ("" if none). */
+const char *sdp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDP_H */

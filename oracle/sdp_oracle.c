@@ -335,7 +335,7 @@ int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col
                const double *a_val, const double *b, const double *c,
                orc_problem **out) {
   *out = NULL;
-  if (n <= 0 || m < 0 || nnz <= 0 || p <= 0 || !pat_row || !pat_col ||
+  if (n <= 0 || m < 1 || nnz <= 0 || p <= 0 || !pat_row || !pat_col ||
       !clique_ptr || !clique_vert || !a_val || !b || !c ||
       (a_format != 0 && a_format != 1) ||
       (a_format == 1 && (!a_rowptr || !a_col)))

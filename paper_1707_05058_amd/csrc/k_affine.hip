@@ -1,0 +1,451 @@
+// The X-step of Algorithm 1 on gfx950: the KKT system (OptCondMinYPrimal)
+// solved by block elimination with the cached factor (the two-step form
+// (KKTflops) of the proof of Proposition 1), written on the compact lower
+// coordinates with weights w (1 on the diagonal, 2 off it):
+//   bhat = sum_k H_k^T (x_k + lambda_k / rho) - c / rho        (k_scatter)
+//   r    = A (w bhat / D) - b                                   (k_rowdot<A>)
+//   y    = L^-T (L^-1 r)   with T = L^-1 cached                 (k_rowdot<T>, k_coldot<T>)
+//   u    = (bhat - A^T y) / D                                   (k_coldot<A>)
+// plus the per-instance residual reduction, stopping test and adaptive
+// penalty (k_residual_reduce).  Every kernel reads the instance's `done`
+// flag first, so a converged instance is frozen at its stopping iterate.
+//
+// All of these passes stream HBM: A is read twice per iteration (row-wise,
+// then column-wise) and T twice; vectors are small and L2-resident.
+// Reductions use a fixed order, so results are bitwise reproducible.
+#include "sdp_internal.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int ROW_NT = 256;   // threads of a row-dot workgroup
+constexpr int COL_NT = 256;   // threads of a column-dot workgroup (4 waves)
+constexpr int COL_W = 128;    // columns per column-dot tile (2 per lane)
+constexpr int MAX_R = 8;      // max rows per row-dot tile
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// bhat and v = w * bhat / D (owner-computes: one thread per coordinate sums
+// its contributors in clique order; no atomics)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= a.ncoord) return;
+  const int inst = a.coord_inst[j];
+  const InstState &st = a.state[inst];
+  if (st.done) return;
+  const double rho = st.rho;
+  double acc = 0.0;
+  const int64_t t0 = a.contrib_ptr[j], t1 = a.contrib_ptr[j + 1];
+  for (int64_t t = t0; t < t1; ++t) {
+    const int32_t e = a.contrib_idx[t];
+    acc += a.X[e] + a.Lam[e] / rho;
+  }
+  const double bh = acc - a.c[j] / rho;
+  a.bhat[j] = bh;
+  a.v[j] = a.w[j] * bh / a.D[j];
+}
+
+// ---------------------------------------------------------------------------
+// Row-oriented dot products over a dense row-major matrix.
+//   MODE 0:  r[i]  = sum_j A[i][j] v[j] - b[i]       (A: m x ld, per instance)
+//   MODE 1:  y1[i] = sum_{k<=i} T[i][k] r[k]         (T: ldm x ldm, lower)
+// One tile = R consecutive rows of one instance; lanes stride the columns
+// with 16-byte loads, so every wave reads contiguous 1 KiB segments.
+// ---------------------------------------------------------------------------
+template <int MODE, int R>
+__global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
+  const int inst = MODE == 0 ? a.row_tiles[2 * blockIdx.x] : a.trow_tiles[2 * blockIdx.x];
+  const int row0 = MODE == 0 ? a.row_tiles[2 * blockIdx.x + 1] : a.trow_tiles[2 * blockIdx.x + 1];
+  if (!a.ignore_done && a.state[inst].done) return;
+  const InstDesc d = a.inst[inst];
+  const int nrow = min(R, d.m - row0);
+  const double *mat;
+  const double *vec;
+  int64_t pitch;
+  int len;
+  if (MODE == 0) {
+    mat = a.A + d.a_off + (int64_t)row0 * d.ld;
+    vec = a.v + d.coord_off;
+    pitch = d.ld;
+    len = d.ld;
+  } else {
+    mat = a.T + d.t_off + (int64_t)row0 * d.ldm;
+    vec = a.r + d.row_off;
+    pitch = d.ldm;
+    len = min(d.ldm, ((row0 + R + 63) / 64) * 64);   // T is zero above the diagonal
+  }
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  const double2 *v2 = reinterpret_cast<const double2 *>(vec);
+  const int len2 = len / 2;
+  for (int c = threadIdx.x; c < len2; c += ROW_NT) {
+    const double2 x = v2[c];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r < nrow) {
+        const double2 m2 = reinterpret_cast<const double2 *>(mat + r * pitch)[c];
+        acc[r] += m2.x * x.x + m2.y * x.y;
+      }
+    }
+  }
+  __shared__ double red[ROW_NT / 64][R];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double s = wave_sum(acc[r]);
+    if (l == 0) red[w][r] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nrow) {
+    const int r = threadIdx.x;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < ROW_NT / 64; ++i) s += red[i][r];
+    if (MODE == 0) {
+      a.r[d.row_off + row0 + r] = s - a.b[d.row_off + row0 + r];
+    } else {
+      a.y1[d.row_off + row0 + r] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column-oriented dot products (transposed products) over the same matrices.
+//   MODE 0:  u[j] = (bhat[j] - sum_i A[i][j] y[i]) / D[j]
+//   MODE 1:  y[j] = sum_{i>=j} T[i][j] y1[i]
+// One tile = 128 columns of one instance; lane l owns columns 2l, 2l+1 and
+// the 4 waves split the rows, so each wave reads contiguous 1 KiB segments.
+// ---------------------------------------------------------------------------
+//   MODE 2:  u[j] = sum_i A[i][j] y[i]               (diagnostics: raw A^T y)
+template <int MODE>
+__global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
+  const int inst = MODE != 1 ? a.col_tiles[2 * blockIdx.x] : a.tcol_tiles[2 * blockIdx.x];
+  const int col0 = MODE != 1 ? a.col_tiles[2 * blockIdx.x + 1] : a.tcol_tiles[2 * blockIdx.x + 1];
+  if (!a.ignore_done && a.state[inst].done) return;
+  const InstDesc d = a.inst[inst];
+  const double *mat;
+  const double *vec;
+  int64_t pitch;
+  int ncols, row_begin, row_end;
+  if (MODE != 1) {
+    mat = a.A + d.a_off;
+    vec = a.y + d.row_off;
+    pitch = d.ld;
+    ncols = d.ld;
+    row_begin = 0;
+    row_end = d.m;
+  } else {
+    mat = a.T + d.t_off;
+    vec = a.y1 + d.row_off;
+    pitch = d.ldm;
+    ncols = d.ldm;
+    row_begin = col0;      // T[i][j] = 0 for i < j
+    row_end = d.ldm;
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int col = col0 + 2 * l;
+  double ax = 0.0, ay = 0.0;
+  if (col < ncols) {
+    const double *base = mat + col;
+    int i = row_begin + w;
+#pragma unroll 4
+    for (; i < row_end; i += 4) {
+      const double2 m2 = *reinterpret_cast<const double2 *>(base + (int64_t)i * pitch);
+      const double yi = vec[i];
+      ax += m2.x * yi;
+      ay += m2.y * yi;
+    }
+  }
+  __shared__ double2 red[4][64];
+  red[w][l] = make_double2(ax, ay);
+  __syncthreads();
+  if (w == 0 && col < ncols) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sx += red[k][l].x;
+      sy += red[k][l].y;
+    }
+    if (MODE == 0) {
+      const int64_t g = d.coord_off + col;
+      a.u[g] = (a.bhat[g] - sx) / a.D[g];
+      a.u[g + 1] = (a.bhat[g + 1] - sy) / a.D[g + 1];
+    } else if (MODE == 2) {
+      const int64_t g = d.coord_off + col;
+      a.u[g] = sx;
+      a.u[g + 1] = sy;
+    } else {
+      a.y[d.row_off + col] = sx;
+      a.y[d.row_off + col + 1] = sy;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sparse A (CSR rows, CSC columns) for instances stored in SDP_A_CSR.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= a.n_csr_rows) return;
+  const int inst = a.csr_rows[2 * wid], row = a.csr_rows[2 * wid + 1];
+  if (!a.ignore_done && a.state[inst].done) return;
+  const InstDesc d = a.inst[inst];
+  const int l = threadIdx.x & 63;
+  const int64_t t0 = a.a_rowptr[d.a_off + row], t1 = a.a_rowptr[d.a_off + row + 1];
+  const double *v = a.v + d.coord_off;
+  double acc = 0.0;
+  for (int64_t t = t0 + l; t < t1; t += 64) acc += a.a_val[t] * v[a.a_col[t]];
+  acc = wave_sum(acc);
+  if (l == 0) a.r[d.row_off + row] = acc - a.b[d.row_off + row];
+}
+
+template <int RAW>
+__global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
+  const int inst = a.csc_cols[2 * blockIdx.x], col0 = a.csc_cols[2 * blockIdx.x + 1];
+  if (!a.ignore_done && a.state[inst].done) return;
+  const InstDesc d = a.inst[inst];
+  const int col = col0 + threadIdx.x;
+  if (col >= d.ld) return;
+  const int64_t g = d.coord_off + col;
+  const double *y = a.y + d.row_off;
+  double acc = 0.0;
+  for (int64_t t = a.a_colptr[g]; t < a.a_colptr[g + 1]; ++t) acc += a.a_cval[t] * y[a.a_row[t]];
+  a.u[g] = RAW ? acc : (a.bhat[g] - acc) / a.D[g];
+}
+
+// ---------------------------------------------------------------------------
+// Residuals (PrimalConsensusResidual), stopping test and adaptive penalty.
+// One workgroup per instance sums its cliques' partials in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ inline double ratio(double num, double den) {
+  if (den > 0.0) return num / den;
+  return num == 0.0 ? 0.0 : INFINITY;
+}
+
+__global__ __launch_bounds__(256) void k_residual_reduce(AffineArgs a) {
+  const int inst = blockIdx.x;
+  InstState &st = a.state[inst];
+  if (st.done) return;
+  const int64_t c0 = a.inst_cl_first[inst], c1 = a.inst_cl_first[inst + 1];
+  double s[NPART] = {0, 0, 0, 0, 0, 0};
+  for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {
+#pragma unroll
+    for (int t = 0; t < NPART; ++t) s[t] += a.part[NPART * k + t];
+  }
+  __shared__ double red[4][NPART];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < NPART; ++t) {
+    const double v = wave_sum(s[t]);
+    if (l == 0) red[w][t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double S[NPART];
+#pragma unroll
+  for (int t = 0; t < NPART; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  const double rho = st.rho;
+  const double nx = sqrt(S[1]), nhx = sqrt(S[2]);
+  const double eps_c = ratio(sqrt(S[0]), nx > nhx ? nx : nhx);
+  const double eps_l = ratio(rho * sqrt(S[3]), sqrt(S[4]));
+  const int it = st.iter + 1;
+  const SolverParams &P = a.params;
+  if (a.hist && it - 1 < P.hist_cap) {
+    double *h = a.hist + ((int64_t)inst * P.hist_cap + (it - 1)) * 3;
+    h[0] = eps_c;
+    h[1] = eps_l;
+    h[2] = rho;
+  }
+  st.eps_c = eps_c;
+  st.eps_l = eps_l;
+  st.iter = it;
+  st.total_sweeps += S[5];
+  const double e = eps_c > eps_l ? eps_c : eps_l;
+  if (e <= P.tol) {
+    st.done = 1;
+    return;
+  }
+  if (P.adaptive && P.rho_period > 0 && (it % P.rho_period) == 0) {
+    if (eps_c >= P.nu * eps_l) st.rho = P.mu * rho;
+    else if (eps_l >= P.nu * eps_c) st.rho = rho / P.mu;
+  }
+  if (it >= P.max_iter) st.done = 2;
+}
+
+// <C, X> = sum_j w_j c_j u_j per instance.
+__global__ __launch_bounds__(256) void k_objective(AffineArgs a, double *obj) {
+  const int inst = blockIdx.x;
+  const InstDesc d = a.inst[inst];
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < d.ld; j += 256) {
+    const int64_t g = d.coord_off + j;
+    s += a.w[g] * a.c[g] * a.u[g];
+  }
+  __shared__ double red[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) obj[inst] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics of the current iterate (the residuals eps_p, eps_d, eps_g
+// (HSDEerror) with x = u, y_dual = -rho y, z = sum_k H_k^T lambda_k, and the
+// PSD-completability violation eps_alpha (PSD-violation)).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_diag_coord(AffineArgs a, DiagScratch s) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= a.ncoord) return;
+  double z = 0.0;
+  for (int64_t t = a.contrib_ptr[j]; t < a.contrib_ptr[j + 1]; ++t) z += a.Lam[a.contrib_idx[t]];
+  s.z[j] = z;
+  s.wu[j] = a.w[j] * a.u[j];
+}
+
+__global__ __launch_bounds__(256) void k_diag_rows(AffineArgs a, DiagScratch s, int64_t nrow) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nrow) return;
+  // instance of row i: rows are padded per instance, scan the descriptors
+  int inst = 0;
+  while (inst + 1 < a.batch && a.inst[inst + 1].row_off <= i) ++inst;
+  s.yd[i] = -a.state[inst].rho * a.y[i];
+}
+
+__global__ __launch_bounds__(256) void k_diag_reduce(AffineArgs a, DiagScratch s,
+                                                     const int64_t *cl_first, double *out) {
+  const int inst = blockIdx.x;
+  const InstDesc d = a.inst[inst];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t j = threadIdx.x; j < d.nnz; j += 256) {
+    const int64_t g = d.coord_off + j;
+    const double w = a.w[g], c = a.c[g], u = a.u[g];
+    const double dd = s.aty[g] + s.z[g] - c;
+    acc[0] += w * dd * dd;      // ||A^T y + z - c||^2 (full vec)
+    acc[1] += w * c * c;        // ||c||^2
+    acc[2] += w * c * u;        // c^T x
+    acc[3] += w * u * u;        // ||X||_F^2 on the pattern
+  }
+  for (int i = threadIdx.x; i < d.m; i += 256) {
+    const double r = s.ax[d.row_off + i], b = a.b[d.row_off + i];
+    acc[4] += r * r;            // ||A x - b||^2
+    acc[5] += b * b;
+    acc[6] += b * s.yd[d.row_off + i];   // b^T y_dual
+  }
+  double mn = 0.0;
+  for (int64_t k = cl_first[inst] + threadIdx.x; k < cl_first[inst + 1]; k += 256)
+    mn = fmin(mn, s.lmin[k]);
+  __shared__ double red[4][8];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int t = 0; t < 7; ++t) {
+    const double v = wave_sum(acc[t]);
+    if (l == 0) red[w][t] = v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+  if (l == 0) red[w][7] = mn;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double S[8];
+  for (int t = 0; t < 7; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  S[7] = fmin(fmin(red[0][7], red[1][7]), fmin(red[2][7], red[3][7]));
+  out[4 * inst + 0] = sqrt(S[4]) / (1.0 + sqrt(S[5]));
+  out[4 * inst + 1] = sqrt(S[0]) / (1.0 + sqrt(S[1]));
+  out[4 * inst + 2] = fabs(S[2] - S[6]) / (1.0 + fabs(S[2]) + fabs(S[6]));
+  out[4 * inst + 3] = -S[7] / (1.0 + sqrt(S[3]));
+}
+
+__global__ __launch_bounds__(256) void k_scaled_copy(const double *src, double *dst, int64_t n,
+                                                     const InstState *state, int inst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = -state[inst].rho * src[i];
+}
+
+}  // namespace
+
+hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st) {
+  const int nb = (int)((a.ncoord + 255) / 256);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a);
+  if (a.n_row_tiles > 0) {
+    switch (a.rows_per_tile) {
+      case 1: hipLaunchKernelGGL((k_rowdot<0, 1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((k_rowdot<0, 2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+      case 4: hipLaunchKernelGGL((k_rowdot<0, 4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_rowdot<0, MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+    }
+  }
+  if (a.n_csr_rows > 0)
+    hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
+  switch (a.trows_per_tile) {
+    case 1: hipLaunchKernelGGL((k_rowdot<1, 1>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_rowdot<1, 2>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_rowdot<1, 4>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_rowdot<1, MAX_R>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+  }
+  hipLaunchKernelGGL(k_coldot<1>, dim3(a.n_tcol_tiles), dim3(COL_NT), 0, st, a);
+  if (a.n_col_tiles > 0)
+    hipLaunchKernelGGL(k_coldot<0>, dim3(a.n_col_tiles), dim3(COL_NT), 0, st, a);
+  if (a.n_csc_cols > 0)
+    hipLaunchKernelGGL(k_csc_coldot<0>, dim3(a.n_csc_cols), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_reduce, dim3(a.batch), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const AffineArgs &a, double *obj, hipStream_t st) {
+  hipLaunchKernelGGL(k_objective, dim3(a.batch), dim3(256), 0, st, a, obj);
+  return hipGetLastError();
+}
+
+int affine_col_tile_width() { return COL_W; }
+int affine_max_rows_per_tile() { return MAX_R; }
+
+// Diagnostics: needs the per-clique minimum eigenvalues in s.lmin already.
+hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const int64_t *cl_first,
+                              int64_t nrow, double *out, hipStream_t st) {
+  AffineArgs a = a0;
+  a.ignore_done = 1;
+  const int nb = (int)((a.ncoord + 255) / 256);
+  hipLaunchKernelGGL(k_diag_coord, dim3(nb), dim3(256), 0, st, a, s);
+  hipLaunchKernelGGL(k_diag_rows, dim3((nrow + 255) / 256), dim3(256), 0, st, a, s, nrow);
+  AffineArgs ar = a;          // A (w u) - b
+  ar.v = s.wu;
+  ar.r = s.ax;
+  if (ar.n_row_tiles > 0) {
+    switch (ar.rows_per_tile) {
+      case 1: hipLaunchKernelGGL((k_rowdot<0, 1>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      case 2: hipLaunchKernelGGL((k_rowdot<0, 2>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      case 4: hipLaunchKernelGGL((k_rowdot<0, 4>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      default: hipLaunchKernelGGL((k_rowdot<0, MAX_R>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+    }
+  }
+  if (ar.n_csr_rows > 0)
+    hipLaunchKernelGGL(k_csr_rowdot, dim3((ar.n_csr_rows + 3) / 4), dim3(256), 0, st, ar);
+  AffineArgs at = a;          // A^T y_dual
+  at.y = s.yd;
+  at.u = s.aty;
+  if (at.n_col_tiles > 0)
+    hipLaunchKernelGGL(k_coldot<2>, dim3(at.n_col_tiles), dim3(COL_NT), 0, st, at);
+  if (at.n_csc_cols > 0)
+    hipLaunchKernelGGL(k_csc_coldot<1>, dim3(at.n_csc_cols), dim3(256), 0, st, at);
+  hipLaunchKernelGGL(k_diag_reduce, dim3(a.batch), dim3(256), 0, st, a, s, cl_first, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scaled_copy(const double *src, double *dst, int64_t n, const InstState *state,
+                              int inst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scaled_copy, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, state,
+                     inst);
+  return hipGetLastError();
+}

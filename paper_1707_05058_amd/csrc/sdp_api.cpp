@@ -1,0 +1,865 @@
+// Host side of libsdp: validation, index construction, device layout, the
+// iteration driver (HIP graphs) and the C ABI of include/sdp.h.
+//
+// Everything numerical runs in the HIP kernels of k_project.hip, k_affine.hip
+// and k_factor.hip; this file only builds integer index structures, moves
+// data and launches work.
+#include "../../include/sdp.h"
+#include "sdp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct SdpError : std::runtime_error {
+  int code;
+  SdpError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw SdpError(code, msg); }
+
+void hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    fail(SDP_ERR_OOM, std::string(what) + ": " + hipGetErrorString(e));
+  fail(SDP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x)
+
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// One instance after validation: host-side index structures.
+struct HostInst {
+  const sdp_instance *src;
+  int32_t n, m, p, fmt, ld, ldm;
+  int64_t nnz;
+  std::vector<int32_t> blk_loc;     // packed entries of all cliques -> local coordinate
+  std::vector<int64_t> cl_off;      // packed offset of each clique (local)
+  std::vector<int32_t> D;           // overlap counts
+  int64_t npk;
+};
+
+int validate_and_index(const sdp_instance &I, int precision, HostInst &H) {
+  H.src = &I;
+  if (I.n <= 0 || I.m <= 0 || I.nnz_pattern <= 0 || I.p <= 0 || !I.pat_row || !I.pat_col ||
+      !I.clique_ptr || !I.clique_vert || !I.a_val || !I.b || !I.c ||
+      (I.a_format != SDP_A_DENSE && I.a_format != SDP_A_CSR) ||
+      (I.a_format == SDP_A_CSR && (!I.a_rowptr || !I.a_col)))
+    fail(SDP_ERR_ARG, "invalid sizes, pointers or A format");
+  if (I.nnz_pattern >= (int64_t)1 << 31) fail(SDP_ERR_ARG, "pattern too large");
+  const int n = I.n;
+  const int64_t nnz = I.nnz_pattern;
+  int ndiag = 0;
+  for (int64_t j = 0; j < nnz; ++j) {
+    const int r = I.pat_row[j], c = I.pat_col[j];
+    if (r < 0 || r >= n || c < 0 || c > r) fail(SDP_ERR_ARG, "pattern coordinate out of range or not lower");
+    if (j > 0) {
+      const int pr = I.pat_row[j - 1], pc = I.pat_col[j - 1];
+      if (c < pc || (c == pc && r <= pr)) fail(SDP_ERR_ARG, "pattern not sorted by (col, row)");
+    }
+    if (r == c) ++ndiag;
+  }
+  if (ndiag != n) fail(SDP_ERR_ARG, "pattern misses a diagonal entry");
+  if (I.clique_ptr[0] != 0) fail(SDP_ERR_ARG, "clique_ptr[0] != 0");
+  for (int k = 0; k < I.p; ++k)
+    if (I.clique_ptr[k + 1] - I.clique_ptr[k] <= 0) fail(SDP_ERR_ARG, "empty clique");
+  for (int k = 0; k < I.p; ++k) {
+    const int s = I.clique_ptr[k + 1] - I.clique_ptr[k];
+    const int32_t *v = I.clique_vert + I.clique_ptr[k];
+    for (int a = 0; a < s; ++a) {
+      if (v[a] < 0 || v[a] >= n) fail(SDP_ERR_CLIQUE_ORDER, "clique vertex out of range");
+      if (a > 0 && v[a] <= v[a - 1]) fail(SDP_ERR_CLIQUE_ORDER, "clique vertices not increasing");
+    }
+  }
+  const int smax = projection_max_size(precision);
+  for (int k = 0; k < I.p; ++k)
+    if (I.clique_ptr[k + 1] - I.clique_ptr[k] > smax)
+      fail(SDP_ERR_UNSUPPORTED, "clique larger than " + std::to_string(smax) +
+                                    " for this projection precision");
+  int64_t annz;
+  if (I.a_format == SDP_A_CSR) {
+    if (I.a_rowptr[0] != 0) fail(SDP_ERR_ARG, "a_rowptr[0] != 0");
+    for (int i = 0; i < I.m; ++i)
+      if (I.a_rowptr[i + 1] < I.a_rowptr[i]) fail(SDP_ERR_ARG, "a_rowptr not monotone");
+    annz = I.a_rowptr[I.m];
+    for (int64_t t = 0; t < annz; ++t)
+      if (I.a_col[t] < 0 || I.a_col[t] >= nnz) fail(SDP_ERR_ARG, "a_col out of range");
+  } else {
+    annz = (int64_t)I.m * nnz;
+  }
+  for (int64_t t = 0; t < annz; ++t)
+    if (!std::isfinite(I.a_val[t])) fail(SDP_ERR_NONFINITE, "non-finite value in A");
+  for (int i = 0; i < I.m; ++i)
+    if (!std::isfinite(I.b[i])) fail(SDP_ERR_NONFINITE, "non-finite value in b");
+  for (int64_t j = 0; j < nnz; ++j)
+    if (!std::isfinite(I.c[j])) fail(SDP_ERR_NONFINITE, "non-finite value in C");
+
+  // column starts of the sorted pattern, for coordinate lookup
+  std::vector<int64_t> colstart(n + 1, 0);
+  for (int64_t j = 0; j < nnz; ++j) colstart[I.pat_col[j] + 1]++;
+  for (int c = 0; c < n; ++c) colstart[c + 1] += colstart[c];
+  auto lookup = [&](int r, int c) -> int64_t {
+    const int32_t *b = I.pat_row + colstart[c], *e = I.pat_row + colstart[c + 1];
+    const int32_t *it = std::lower_bound(b, e, r);
+    if (it == e || *it != r) return -1;
+    return colstart[c] + (it - b);
+  };
+  H.n = n; H.m = I.m; H.p = I.p; H.fmt = I.a_format; H.nnz = nnz;
+  H.ld = (int32_t)round_up(nnz, 64);
+  H.ldm = (int32_t)round_up(I.m, 64);
+  H.cl_off.resize(I.p + 1);
+  H.cl_off[0] = 0;
+  for (int k = 0; k < I.p; ++k) {
+    const int64_t s = I.clique_ptr[k + 1] - I.clique_ptr[k];
+    H.cl_off[k + 1] = H.cl_off[k] + s * (s + 1) / 2;
+  }
+  H.npk = H.cl_off[I.p];
+  H.blk_loc.resize(H.npk);
+  H.D.assign(nnz, 0);
+  // entry selectors E_Ck: packed block entry (a, b), a >= b, of clique k is
+  // the pattern coordinate (v_a, v_b) (v_a > v_b since vertices increase)
+  for (int k = 0; k < I.p; ++k) {
+    const int s = I.clique_ptr[k + 1] - I.clique_ptr[k];
+    const int32_t *v = I.clique_vert + I.clique_ptr[k];
+    int64_t e = H.cl_off[k];
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b <= a; ++b, ++e) {
+        const int64_t j = lookup(v[a], v[b]);
+        if (j < 0) fail(SDP_ERR_OFF_PATTERN, "clique pair outside the pattern");
+        H.blk_loc[e] = (int32_t)j;
+      }
+  }
+  for (int64_t e = 0; e < H.npk; ++e) H.D[H.blk_loc[e]]++;
+  for (int64_t j = 0; j < nnz; ++j)
+    if (H.D[j] == 0) fail(SDP_ERR_PATTERN_UNCOVERED, "pattern coordinate covered by no clique");
+  return SDP_OK;
+}
+
+template <typename T>
+T *dev_upload(const std::vector<T> &v, std::vector<void *> &owned) {
+  T *p = nullptr;
+  const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+  HIPCHK(hipMalloc((void **)&p, bytes));
+  owned.push_back(p);
+  if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+template <typename T>
+T *dev_zeros(size_t count, std::vector<void *> &owned) {
+  T *p = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  HIPCHK(hipMalloc((void **)&p, bytes));
+  owned.push_back(p);
+  HIPCHK(hipMemset(p, 0, bytes));
+  return p;
+}
+
+}  // namespace
+
+struct sdp_handle {
+  int B = 0;
+  sdp_options opt{};
+  int precision = 0;
+  int max_sweeps = 30;
+  double jac_tol = 1e-6;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<void *> owned;
+  std::vector<InstDesc> desc;
+  std::vector<int64_t> npk_off;          // per instance, packed offset of its first clique
+  std::vector<int64_t> inst_npk;
+  std::vector<int32_t> inst_p;
+  int64_t ncoord = 0, nrow = 0, npk = 0, ncl = 0;
+  InstDesc *d_desc = nullptr;
+  InstState *d_state = nullptr;
+  InstState *h_state = nullptr;          // pinned
+  double *d_obj = nullptr;
+  double *h_obj = nullptr;               // pinned
+  AffineArgs aff{};
+  ProjArgs proj{};
+  std::vector<int> bucket_size;
+  std::vector<int32_t *> bucket_list;
+  std::vector<int> bucket_count;
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+  int hist_cap = 0;
+  bool have_diag = false;
+  std::vector<double> diag;              // 4 per instance
+  double *d_diag = nullptr;
+  DiagScratch dscr{};
+  int64_t iters_enqueued = 0;
+};
+
+namespace {
+
+void enqueue_iteration(sdp_handle *h, hipStream_t st) {
+  HIPCHK(launch_iteration_affine(h->aff, st));
+  for (size_t b = 0; b < h->bucket_size.size(); ++b)
+    HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+                                  h->bucket_count[b], h->proj, st));
+  HIPCHK(launch_residual_reduce(h->aff, st));
+}
+
+void build_graph(sdp_handle *h) {
+  if (h->graph || h->opt.graph_chunk <= 0) return;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int i = 0; i < h->opt.graph_chunk; ++i) enqueue_iteration(h, h->cap_stream);
+  } catch (...) {
+    hipGraph_t dummy;
+    (void)hipStreamEndCapture(h->cap_stream, &dummy);
+    if (dummy) (void)hipGraphDestroy(dummy);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+  HIPCHK(hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphDestroy(g));
+  h->graph_iters = h->opt.graph_chunk;
+}
+
+void enqueue_steps(sdp_handle *h, int64_t n) {
+  if (h->opt.graph_chunk > 0 && n >= h->opt.graph_chunk) {
+    build_graph(h);
+    while (n >= h->graph_iters) {
+      HIPCHK(hipGraphLaunch(h->graph, h->stream));
+      n -= h->graph_iters;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) enqueue_iteration(h, h->stream);
+}
+
+void pull_state(sdp_handle *h) {
+  HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(InstState) * h->B, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+}
+
+void fill_results(sdp_handle *h, sdp_result *res) {
+  HIPCHK(launch_objective(h->aff, h->d_obj, h->stream));
+  HIPCHK(hipMemcpyAsync(h->h_obj, h->d_obj, sizeof(double) * h->B, hipMemcpyDeviceToHost,
+                        h->stream));
+  pull_state(h);
+  for (int i = 0; i < h->B; ++i) {
+    const InstState &s = h->h_state[i];
+    sdp_result &r = res[i];
+    r.iters = s.iter;
+    r.status = s.done == 1 ? SDP_OK : SDP_MAX_ITER;
+    r.eps_c = s.eps_c;
+    r.eps_lambda = s.eps_l;
+    r.objective = h->h_obj[i];
+    r.rho = s.rho;
+    if (h->have_diag) {
+      r.eps_p = h->diag[4 * i + 0];
+      r.eps_d = h->diag[4 * i + 1];
+      r.eps_g = h->diag[4 * i + 2];
+      r.eps_alpha = h->diag[4 * i + 3];
+    } else {
+      r.eps_p = r.eps_d = r.eps_g = r.eps_alpha = NAN;
+    }
+  }
+}
+
+void reset_state(sdp_handle *h) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<InstState> st(h->B);
+  for (auto &s : st) {
+    std::memset(&s, 0, sizeof(s));
+    s.rho = h->opt.rho;
+    s.eps_c = s.eps_l = INFINITY;
+  }
+  HIPCHK(hipMemcpy(h->d_state, st.data(), sizeof(InstState) * h->B, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(h->proj.X, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
+  HIPCHK(hipMemset(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
+  HIPCHK(hipMemset(h->aff.u, 0, sizeof(double) * h->ncoord));
+  HIPCHK(hipMemset(h->aff.y, 0, sizeof(double) * h->nrow));
+  h->have_diag = false;
+  h->iters_enqueued = 0;
+}
+
+void destroy_handle(sdp_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  for (void *p : h->owned) (void)hipFree(p);
+  if (h->h_state) (void)hipHostFree(h->h_state);
+  if (h->h_obj) (void)hipHostFree(h->h_obj);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_in,
+                sdp_handle **out) {
+  if (!out) fail(SDP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (batch <= 0 || !inst) fail(SDP_ERR_ARG, "batch must be positive");
+  sdp_options opt;
+  sdp_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (!(opt.rho > 0) || !(opt.tol >= 0) || opt.max_iter <= 0 ||
+      (opt.precision != SDP_FP64 && opt.precision != SDP_FP32_EIG) ||
+      (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
+      opt.graph_chunk < 0)
+    fail(SDP_ERR_ARG, "invalid options");
+
+  // ---- validation and host indices (nothing touches the GPU before this) ----
+  std::vector<HostInst> H(batch);
+  for (int i = 0; i < batch; ++i) {
+    try {
+      validate_and_index(inst[i], opt.precision, H[i]);
+    } catch (SdpError &e) {
+      throw SdpError(e.code, "instance " + std::to_string(i) + ": " + e.what());
+    }
+  }
+
+  sdp_handle *h = new sdp_handle();
+  try {
+    h->B = batch;
+    h->opt = opt;
+    h->precision = opt.precision;
+    h->max_sweeps = opt.jacobi_max_sweeps > 0 ? opt.jacobi_max_sweeps
+                                              : (opt.precision == SDP_FP32_EIG ? 30 : 40);
+    h->jac_tol = opt.jacobi_tol > 0 ? opt.jacobi_tol : (opt.precision == SDP_FP32_EIG ? 1e-6 : 1e-14);
+    if (opt.stream) {
+      h->stream = (hipStream_t)opt.stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+
+    // ---- global layout ----
+    h->desc.resize(batch);
+    int64_t coord = 0, row = 0, aoff = 0, toff = 0, cl = 0, pk = 0, csr_ptr_off = 0;
+    int max_ldm = 0;
+    for (int i = 0; i < batch; ++i) {
+      InstDesc &d = h->desc[i];
+      const HostInst &hi = H[i];
+      d.n = hi.n; d.m = hi.m; d.p = hi.p; d.a_format = hi.fmt;
+      d.ld = hi.ld; d.ldm = hi.ldm; d.nnz = hi.nnz;
+      d.coord_off = coord; d.row_off = row; d.t_off = toff; d.clique_off = cl;
+      if (hi.fmt == SDP_A_DENSE) {
+        d.a_off = aoff;
+        aoff += (int64_t)hi.m * hi.ld;
+      } else {
+        d.a_off = csr_ptr_off;          // row pointer block of m+1 entries
+        csr_ptr_off += hi.m + 1;
+      }
+      coord += hi.ld;
+      row += hi.ldm;
+      toff += (int64_t)hi.ldm * hi.ldm;
+      cl += hi.p;
+      h->npk_off.push_back(pk);
+      h->inst_npk.push_back(hi.npk);
+      h->inst_p.push_back(hi.p);
+      pk += hi.npk;
+      max_ldm = std::max(max_ldm, hi.ldm);
+    }
+    h->ncoord = coord; h->nrow = row; h->npk = pk; h->ncl = cl;
+    if (pk >= ((int64_t)1 << 31)) fail(SDP_ERR_UNSUPPORTED, "too many packed clique entries");
+
+    // ---- coordinate-space arrays ----
+    std::vector<int32_t> coord_inst(coord);
+    std::vector<double> c(coord, 0.0), D(coord, 1.0), w(coord, 0.0), wd(coord, 0.0);
+    std::vector<int64_t> cptr(coord + 1, 0);
+    for (int i = 0; i < batch; ++i) {
+      const InstDesc &d = h->desc[i];
+      const HostInst &hi = H[i];
+      for (int64_t j = 0; j < d.ld; ++j) coord_inst[d.coord_off + j] = i;
+      for (int64_t j = 0; j < hi.nnz; ++j) {
+        const int64_t g = d.coord_off + j;
+        c[g] = inst[i].c[j];
+        D[g] = (double)hi.D[j];
+        w[g] = inst[i].pat_row[j] == inst[i].pat_col[j] ? 1.0 : 2.0;
+        wd[g] = w[g] / D[g];
+        cptr[g + 1] = hi.D[j];
+      }
+    }
+    for (int64_t g = 0; g < coord; ++g) cptr[g + 1] += cptr[g];
+    std::vector<int32_t> cidx(cptr[coord]);
+    {
+      std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+      for (int i = 0; i < batch; ++i)
+        for (int64_t e = 0; e < H[i].npk; ++e) {
+          const int64_t g = h->desc[i].coord_off + H[i].blk_loc[e];
+          cidx[fill[g]++] = (int32_t)(h->npk_off[i] + e);
+        }
+    }
+    // ---- clique arrays ----
+    std::vector<int32_t> cl_inst(cl), cl_size(cl), blk_loc(pk);
+    std::vector<int64_t> cl_off(cl), cl_first(batch + 1);
+    {
+      int64_t k = 0;
+      for (int i = 0; i < batch; ++i) {
+        cl_first[i] = k;
+        for (int q = 0; q < H[i].p; ++q, ++k) {
+          cl_inst[k] = i;
+          cl_size[k] = inst[i].clique_ptr[q + 1] - inst[i].clique_ptr[q];
+          cl_off[k] = h->npk_off[i] + H[i].cl_off[q];
+        }
+        for (int64_t e = 0; e < H[i].npk; ++e)
+          blk_loc[h->npk_off[i] + e] = (int32_t)(h->desc[i].coord_off + H[i].blk_loc[e]);
+      }
+      cl_first[batch] = k;
+    }
+    // size buckets
+    std::vector<std::vector<int32_t>> lists;
+    for (int64_t k = 0; k < cl; ++k) {
+      const int bs = projection_bucket(h->precision, cl_size[k]);
+      auto it = std::find(h->bucket_size.begin(), h->bucket_size.end(), bs);
+      size_t bi;
+      if (it == h->bucket_size.end()) {
+        h->bucket_size.push_back(bs);
+        lists.emplace_back();
+        bi = lists.size() - 1;
+      } else {
+        bi = it - h->bucket_size.begin();
+      }
+      lists[bi].push_back((int32_t)k);
+    }
+    // ---- row-space arrays ----
+    std::vector<double> b(row, 0.0);
+    for (int i = 0; i < batch; ++i)
+      for (int r = 0; r < H[i].m; ++r) b[h->desc[i].row_off + r] = inst[i].b[r];
+
+    // ---- tiles ----
+    int64_t dense_rows = 0;
+    for (int i = 0; i < batch; ++i)
+      if (H[i].fmt == SDP_A_DENSE) dense_rows += H[i].m;
+    auto pick_r = [](int64_t rows) {
+      int r = 1;
+      while (r < affine_max_rows_per_tile() && rows / (2 * r) >= 2048) r *= 2;
+      return r;
+    };
+    const int R = pick_r(dense_rows);
+    const int TR = pick_r(row);
+    const int CW = affine_col_tile_width();
+    std::vector<int32_t> row_tiles, col_tiles, trow_tiles, tcol_tiles, csr_rows, csc_cols, syrk_tiles,
+        syrk_rows;
+    for (int i = 0; i < batch; ++i) {
+      const HostInst &hi = H[i];
+      for (int r = 0; r < hi.m; r += TR) { trow_tiles.push_back(i); trow_tiles.push_back(r); }
+      for (int cc = 0; cc < hi.ldm; cc += CW) { tcol_tiles.push_back(i); tcol_tiles.push_back(cc); }
+      if (hi.fmt == SDP_A_DENSE) {
+        for (int r = 0; r < hi.m; r += R) { row_tiles.push_back(i); row_tiles.push_back(r); }
+        for (int cc = 0; cc < hi.ld; cc += CW) { col_tiles.push_back(i); col_tiles.push_back(cc); }
+        for (int ti = 0; ti < hi.ldm / 64; ++ti)
+          for (int tj = 0; tj <= ti; ++tj) {
+            syrk_tiles.push_back(i); syrk_tiles.push_back(ti); syrk_tiles.push_back(tj);
+          }
+      } else {
+        for (int r = 0; r < hi.m; ++r) {
+          csr_rows.push_back(i); csr_rows.push_back(r);
+          syrk_rows.push_back(i); syrk_rows.push_back(r);
+        }
+        for (int cc = 0; cc < hi.ld; cc += 256) { csc_cols.push_back(i); csc_cols.push_back(cc); }
+      }
+    }
+    if (max_ldm * sizeof(double) > 160 * 1024 && !syrk_rows.empty())
+      fail(SDP_ERR_UNSUPPORTED, "sparse A with m > 20480 is not supported");
+
+    // ---- CSR and CSC of sparse A ----
+    std::vector<int64_t> a_rowptr, a_colptr;
+    std::vector<int32_t> a_col, a_row;
+    std::vector<double> a_val, a_cval;
+    bool any_csr = !csr_rows.empty();
+    if (any_csr) {
+      a_colptr.assign(coord + 1, 0);
+      for (int i = 0; i < batch; ++i) {
+        if (H[i].fmt != SDP_A_CSR) continue;
+        const sdp_instance &I = inst[i];
+        const int64_t base = (int64_t)a_val.size();
+        for (int r = 0; r <= I.m; ++r) a_rowptr.push_back(base + I.a_rowptr[r]);
+        const int64_t annz = I.a_rowptr[I.m];
+        a_col.insert(a_col.end(), I.a_col, I.a_col + annz);
+        a_val.insert(a_val.end(), I.a_val, I.a_val + annz);
+        for (int64_t t = 0; t < annz; ++t) a_colptr[h->desc[i].coord_off + I.a_col[t] + 1]++;
+      }
+      for (int64_t g = 0; g < coord; ++g) a_colptr[g + 1] += a_colptr[g];
+      a_row.resize(a_colptr[coord]);
+      a_cval.resize(a_colptr[coord]);
+      std::vector<int64_t> fill(a_colptr.begin(), a_colptr.end() - 1);
+      for (int i = 0; i < batch; ++i) {
+        if (H[i].fmt != SDP_A_CSR) continue;
+        const sdp_instance &I = inst[i];
+        for (int r = 0; r < I.m; ++r)
+          for (int64_t t = I.a_rowptr[r]; t < I.a_rowptr[r + 1]; ++t) {
+            const int64_t pos = fill[h->desc[i].coord_off + I.a_col[t]]++;
+            a_row[pos] = r;
+            a_cval[pos] = I.a_val[t];
+          }
+      }
+    }
+
+    // ---- device allocation and upload ----
+    auto &own = h->owned;
+    h->d_desc = dev_upload(h->desc, own);
+    h->d_state = dev_zeros<InstState>(batch, own);
+    HIPCHK(hipHostMalloc((void **)&h->h_state, sizeof(InstState) * batch, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h->h_obj, sizeof(double) * batch, hipHostMallocDefault));
+    h->d_obj = dev_zeros<double>(batch, own);
+    double *d_A = nullptr;
+    if (aoff > 0) {
+      d_A = dev_zeros<double>(aoff, own);
+      for (int i = 0; i < batch; ++i) {
+        if (H[i].fmt != SDP_A_DENSE) continue;
+        const InstDesc &d = h->desc[i];
+        HIPCHK(hipMemcpy2D(d_A + d.a_off, sizeof(double) * d.ld, inst[i].a_val,
+                           sizeof(double) * d.nnz, sizeof(double) * d.nnz, d.m,
+                           hipMemcpyHostToDevice));
+      }
+    }
+    double *d_T = dev_zeros<double>(toff, own);
+    double *d_wd = dev_upload(wd, own);
+
+    AffineArgs &a = h->aff;
+    a.inst = h->d_desc;
+    a.state = h->d_state;
+    a.params.tol = opt.tol;
+    a.params.mu = opt.mu;
+    a.params.nu = opt.nu;
+    a.params.max_iter = opt.max_iter;
+    a.params.adaptive = opt.adaptive_rho;
+    a.params.rho_period = opt.rho_period;
+    h->hist_cap = std::min(opt.max_iter, 100000);
+    a.params.hist_cap = h->hist_cap;
+    a.coord_inst = dev_upload(coord_inst, own);
+    a.c = dev_upload(c, own);
+    a.D = dev_upload(D, own);
+    a.w = dev_upload(w, own);
+    a.bhat = dev_zeros<double>(coord, own);
+    a.v = dev_zeros<double>(coord, own);
+    a.u = dev_zeros<double>(coord, own);
+    a.contrib_ptr = dev_upload(cptr, own);
+    a.contrib_idx = dev_upload(cidx, own);
+    a.ncoord = coord;
+    a.b = dev_upload(b, own);
+    a.r = dev_zeros<double>(row, own);
+    a.y1 = dev_zeros<double>(row, own);
+    a.y = dev_zeros<double>(row, own);
+    a.A = d_A;
+    if (any_csr) {
+      a.a_rowptr = dev_upload(a_rowptr, own);
+      a.a_col = dev_upload(a_col, own);
+      a.a_val = dev_upload(a_val, own);
+      a.a_colptr = dev_upload(a_colptr, own);
+      a.a_row = dev_upload(a_row, own);
+      a.a_cval = dev_upload(a_cval, own);
+    }
+    a.T = d_T;
+    a.row_tiles = dev_upload(row_tiles, own);
+    a.n_row_tiles = (int)(row_tiles.size() / 2);
+    a.rows_per_tile = R;
+    a.col_tiles = dev_upload(col_tiles, own);
+    a.n_col_tiles = (int)(col_tiles.size() / 2);
+    a.trow_tiles = dev_upload(trow_tiles, own);
+    a.n_trow_tiles = (int)(trow_tiles.size() / 2);
+    a.trows_per_tile = TR;
+    a.tcol_tiles = dev_upload(tcol_tiles, own);
+    a.n_tcol_tiles = (int)(tcol_tiles.size() / 2);
+    a.csr_rows = dev_upload(csr_rows, own);
+    a.n_csr_rows = (int)(csr_rows.size() / 2);
+    a.csc_cols = dev_upload(csc_cols, own);
+    a.n_csc_cols = (int)(csc_cols.size() / 2);
+    double *d_part = dev_zeros<double>((size_t)cl * NPART, own);
+    a.part = d_part;
+    a.inst_cl_first = dev_upload(cl_first, own);
+    a.hist = dev_zeros<double>((size_t)batch * h->hist_cap * 3, own);
+    a.batch = batch;
+
+    ProjArgs &p = h->proj;
+    p.cl_inst = dev_upload(cl_inst, own);
+    p.cl_size = dev_upload(cl_size, own);
+    p.cl_off = dev_upload(cl_off, own);
+    p.blk_loc = dev_upload(blk_loc, own);
+    p.u = a.u;
+    p.X = dev_zeros<double>(pk, own);
+    p.Lam = dev_zeros<double>(pk, own);
+    p.part = d_part;
+    p.state = h->d_state;
+    p.max_sweeps = h->max_sweeps;
+    p.tol = h->jac_tol;
+    a.X = p.X;
+    a.Lam = p.Lam;
+    for (auto &l : lists) {
+      h->bucket_list.push_back(dev_upload(l, own));
+      h->bucket_count.push_back((int)l.size());
+    }
+    h->d_diag = dev_zeros<double>((size_t)4 * batch, own);
+    h->diag.assign(4 * batch, NAN);
+
+    // ---- one-time factorisation: M = A W D^-1 A^T = L L^T, T = L^-1 ----
+    {
+      double *d_M = nullptr;
+      HIPCHK(hipMalloc((void **)&d_M, sizeof(double) * std::max<int64_t>(toff, 1)));
+      HIPCHK(hipMemset(d_M, 0, sizeof(double) * std::max<int64_t>(toff, 1)));
+      int32_t *d_fail = nullptr;
+      HIPCHK(hipMalloc((void **)&d_fail, sizeof(int32_t) * batch));
+      HIPCHK(hipMemset(d_fail, 0, sizeof(int32_t) * batch));
+      std::vector<void *> tmp;
+      FactorArgs f{};
+      f.inst = h->d_desc;
+      f.batch = batch;
+      f.A = d_A;
+      f.a_rowptr = a.a_rowptr; f.a_col = a.a_col; f.a_val = a.a_val;
+      f.a_colptr = a.a_colptr; f.a_row = a.a_row; f.a_cval = a.a_cval;
+      f.wd = d_wd;
+      f.M = d_M;
+      f.T = d_T;
+      f.fail = d_fail;
+      int32_t *d_syrk_tiles = dev_upload(syrk_tiles, tmp);
+      int32_t *d_syrk_rows = dev_upload(syrk_rows, tmp);
+      hipError_t e1 = launch_syrk_dense(f, d_syrk_tiles, (int)(syrk_tiles.size() / 3), h->stream);
+      hipError_t e2 = e1 == hipSuccess
+                          ? launch_syrk_csr(f, d_syrk_rows, (int)(syrk_rows.size() / 2), max_ldm,
+                                            h->stream)
+                          : e1;
+      hipError_t e3 = e2 == hipSuccess
+                          ? launch_cholesky_and_inverse(f, max_ldm / 64, h->stream)
+                          : e2;
+      hipError_t e4 = hipStreamSynchronize(h->stream);
+      std::vector<int32_t> failed(batch, 0);
+      hipError_t e5 = hipMemcpy(failed.data(), d_fail, sizeof(int32_t) * batch, hipMemcpyDeviceToHost);
+      (void)hipFree(d_M);
+      (void)hipFree(d_fail);
+      for (void *q : tmp) (void)hipFree(q);
+      HIPCHK(e3);
+      HIPCHK(e4);
+      HIPCHK(e5);
+      for (int i = 0; i < batch; ++i)
+        if (failed[i])
+          fail(SDP_ERR_RANK_DEFICIENT, "instance " + std::to_string(i) +
+                                           ": A D^-1 A^T is not positive definite");
+    }
+    (void)wd;
+    reset_state(h);
+    *out = h;
+  } catch (...) {
+    destroy_handle(h);
+    throw;
+  }
+}
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (SdpError &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return SDP_ERR_OOM;
+  } catch (std::exception &e) {
+    g_last_error = e.what();
+    return SDP_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void sdp_default_options(sdp_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->rho = 1.0;
+  opt->tol = 1e-4;
+  opt->max_iter = 20000;
+  opt->precision = SDP_FP64;
+  opt->adaptive_rho = 0;
+  opt->mu = 2.0;
+  opt->nu = 10.0;
+  opt->rho_period = 1;
+  opt->graph_chunk = 25;
+  opt->stream = nullptr;
+  opt->jacobi_max_sweeps = 0;
+  opt->jacobi_tol = 0.0;
+}
+
+int sdp_setup(int32_t batch, const sdp_instance *inst, const sdp_options *opt, sdp_handle **out) {
+  return guarded([&] {
+    setup_impl(batch, inst, opt, out);
+    return SDP_OK;
+  });
+}
+
+int sdp_reset(sdp_handle *h) {
+  return guarded([&] {
+    if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    reset_state(h);
+    return SDP_OK;
+  });
+}
+
+int sdp_admm_step(sdp_handle *h, int32_t n_steps, sdp_result *res) {
+  return guarded([&] {
+    if (!h || n_steps < 0) fail(SDP_ERR_ARG, "NULL handle or negative step count");
+    h->have_diag = false;
+    enqueue_steps(h, n_steps);
+    h->iters_enqueued += n_steps;
+    if (res) fill_results(h, res);
+    return SDP_OK;
+  });
+}
+
+int sdp_solve(sdp_handle *h, sdp_result *res) {
+  return guarded([&] {
+    if (!h || !res) fail(SDP_ERR_ARG, "NULL handle or result array");
+    h->have_diag = false;
+    pull_state(h);
+    const int chunk = h->opt.graph_chunk > 0 ? h->opt.graph_chunk : 25;
+    for (;;) {
+      bool all_done = true;
+      int max_left = 0;
+      for (int i = 0; i < h->B; ++i) {
+        if (!h->h_state[i].done) {
+          all_done = false;
+          max_left = std::max(max_left, h->opt.max_iter - h->h_state[i].iter);
+        }
+      }
+      if (all_done) break;
+      enqueue_steps(h, std::min(chunk, std::max(max_left, 1)));
+      pull_state(h);
+    }
+    fill_results(h, res);
+    int st = SDP_OK;
+    for (int i = 0; i < h->B; ++i)
+      if (res[i].status != SDP_OK) st = SDP_MAX_ITER;
+    return st;
+  });
+}
+
+int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *sizes,
+                            const int64_t *offsets, const void *in, void *out, int32_t dtype,
+                            void *stream) {
+  return guarded([&] {
+    if (count < 0 || (count > 0 && (!sizes || !offsets || !in || !out)))
+      fail(SDP_ERR_ARG, "invalid arguments");
+    if (dtype != SDP_DTYPE_FP64 && dtype != SDP_DTYPE_FP32) fail(SDP_ERR_ARG, "invalid dtype");
+    const int prec = dtype == SDP_DTYPE_FP32 ? 1 : 0;
+    if (max_size <= 0 || max_size > projection_max_size(prec))
+      fail(SDP_ERR_UNSUPPORTED, "max_size out of range for this dtype");
+    if (count == 0) return SDP_OK;
+    const int bucket = projection_bucket(prec, max_size);
+    const int msw = prec ? 30 : 40;
+    const double tol = prec ? 1e-6 : 1e-14;
+    HIPCHK(launch_standalone_projection(prec, bucket, count, sizes, offsets, in, out, msw, tol,
+                                        (hipStream_t)stream));
+    return SDP_OK;
+  });
+}
+
+int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual, double *Xk,
+                     double *Lk) {
+  return guarded([&] {
+    if (!h || inst < 0 || inst >= h->B) fail(SDP_ERR_ARG, "invalid handle or instance");
+    const InstDesc &d = h->desc[inst];
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (u) HIPCHK(hipMemcpy(u, h->aff.u + d.coord_off, sizeof(double) * d.nnz, hipMemcpyDeviceToHost));
+    if (y_dual) {
+      HIPCHK(launch_scaled_copy(h->aff.y + d.row_off, h->aff.y1 + d.row_off, d.m, h->d_state, inst,
+                                h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      HIPCHK(hipMemcpy(y_dual, h->aff.y1 + d.row_off, sizeof(double) * d.m, hipMemcpyDeviceToHost));
+    }
+    const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
+    if (Xk) HIPCHK(hipMemcpy(Xk, h->proj.X + o, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (Lk) HIPCHK(hipMemcpy(Lk, h->proj.Lam + o, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return SDP_OK;
+  });
+}
+
+int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *Lk, double rho) {
+  return guarded([&] {
+    if (!h || inst < 0 || inst >= h->B || !(rho > 0)) fail(SDP_ERR_ARG, "invalid arguments");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
+    if (Xk) HIPCHK(hipMemcpy(h->proj.X + o, Xk, sizeof(double) * n, hipMemcpyHostToDevice));
+    if (Lk) HIPCHK(hipMemcpy(h->proj.Lam + o, Lk, sizeof(double) * n, hipMemcpyHostToDevice));
+    pull_state(h);
+    InstState s = h->h_state[inst];
+    s.rho = rho;
+    s.done = 0;
+    HIPCHK(hipMemcpy(h->d_state + inst, &s, sizeof(InstState), hipMemcpyHostToDevice));
+    h->have_diag = false;
+    return SDP_OK;
+  });
+}
+
+int sdp_get_history(sdp_handle *h, int32_t inst, int32_t cap, double *eps_c, double *eps_lambda,
+                    double *rho, int32_t *count) {
+  return guarded([&] {
+    if (!h || inst < 0 || inst >= h->B || cap < 0) fail(SDP_ERR_ARG, "invalid arguments");
+    pull_state(h);
+    const int n = std::min({cap, h->h_state[inst].iter, h->hist_cap});
+    std::vector<double> buf((size_t)std::max(n, 1) * 3);
+    if (n > 0)
+      HIPCHK(hipMemcpy(buf.data(), h->aff.hist + (size_t)inst * h->hist_cap * 3,
+                       sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+      if (eps_c) eps_c[i] = buf[3 * i];
+      if (eps_lambda) eps_lambda[i] = buf[3 * i + 1];
+      if (rho) rho[i] = buf[3 * i + 2];
+    }
+    if (count) *count = n;
+    return SDP_OK;
+  });
+}
+
+int sdp_diagnostics(sdp_handle *h, sdp_result *res) {
+  return guarded([&] {
+    if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    if (!h->dscr.wu) {
+      h->dscr.wu = dev_zeros<double>(h->ncoord, h->owned);
+      h->dscr.z = dev_zeros<double>(h->ncoord, h->owned);
+      h->dscr.aty = dev_zeros<double>(h->ncoord, h->owned);
+      h->dscr.ax = dev_zeros<double>(h->nrow, h->owned);
+      h->dscr.yd = dev_zeros<double>(h->nrow, h->owned);
+      h->dscr.lmin = dev_zeros<double>(h->ncl, h->owned);
+    }
+    for (size_t b = 0; b < h->bucket_size.size(); ++b)
+      HIPCHK(launch_min_eig(h->precision, h->bucket_size[b], h->bucket_list[b], h->bucket_count[b],
+                            h->proj, h->dscr.lmin, h->stream));
+    HIPCHK(launch_diagnostics(h->aff, h->dscr, h->aff.inst_cl_first, h->nrow, h->d_diag,
+                              h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(h->diag.data(), h->d_diag, sizeof(double) * 4 * h->B, hipMemcpyDeviceToHost));
+    h->have_diag = true;
+    if (res) fill_results(h, res);
+    return SDP_OK;
+  });
+}
+
+int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections) {
+  return guarded([&] {
+    if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    pull_state(h);
+    int64_t sw = 0, pr = 0;
+    for (int i = 0; i < h->B; ++i) {
+      sw += (int64_t)h->h_state[i].total_sweeps;
+      pr += (int64_t)h->h_state[i].iter * h->inst_p[i];
+    }
+    if (jacobi_sweeps) *jacobi_sweeps = sw;
+    if (projections) *projections = pr;
+    return SDP_OK;
+  });
+}
+
+void sdp_destroy(sdp_handle *h) { destroy_handle(h); }
+
+const char *sdp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+// Internal declarations shared by the libsdp translation units.
+//
+// Device data layout (all instances of a batch concatenated):
+//  * coordinate space: instance i owns `ld` consecutive slots starting at
+//    coord_off (ld = nnz rounded up to a multiple of 64; padding slots have
+//    D = 1, c = 0, w/D = 0 and no contributors, so they stay exactly zero).
+//    Arrays: c, D, wd (= w/D), bhat, v (= wd*bhat), u, coord_inst.
+//  * row space: instance i owns `ldm` slots (m rounded up to 64) from row_off.
+//    Arrays: b, r (= A v - b), y1 (= L^-1 r), y (= L^-T y1).
+//  * dense A: row-major m x ld per instance at a_off (zero padded).
+//    CSR A: global row pointers (int64) with instance-local column indices,
+//    plus a CSC copy for A^T y.
+//  * factor: T = L^-1 (m x m row-major, pitch ldm, upper part zero) at t_off.
+//  * cliques: global list; packed lower blocks X, Lambda (FP64) at cl_off;
+//    blk_loc maps a packed entry to its global coordinate; the contributor
+//    CSR (coordinate -> packed entries, sorted by clique) drives the scatter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SDP_WAVE 64
+// per-clique partial sums: ||X_k - H_k x||^2, ||X_k||^2, ||H_k x||^2,
+// ||X_k - X_k^prev||^2, ||Lambda_k||^2 (full Frobenius), Jacobi sweeps
+#define NPART 6
+
+struct InstDesc {
+  int32_t n, m, p, a_format;
+  int32_t ld;          // padded coordinate count (pitch of dense A)
+  int32_t ldm;         // padded row count (pitch of T)
+  int64_t nnz;
+  int64_t coord_off;
+  int64_t row_off;
+  int64_t a_off;       // dense: element offset; csr: offset into row pointer array
+  int64_t t_off;
+  int64_t clique_off;  // first global clique
+};
+
+// Per-instance mutable scalars live in one struct array on the device.
+struct InstState {
+  double rho;
+  double eps_c, eps_l;
+  double total_sweeps;
+  int32_t iter;
+  int32_t done;        // 1: converged, 2: iteration limit reached
+};
+
+struct SolverParams {
+  double tol;
+  double mu, nu;
+  int32_t max_iter;
+  int32_t adaptive;
+  int32_t rho_period;
+  int32_t hist_cap;    // capacity of the per-instance history ring
+};
+
+// ----------------------------------------------------------------------------
+// Projection (k_project.hip)
+// ----------------------------------------------------------------------------
+struct ProjArgs {
+  const int32_t *cl_inst;
+  const int32_t *cl_size;
+  const int64_t *cl_off;
+  const int32_t *blk_loc;
+  const double *u;
+  double *X;
+  double *Lam;
+  double *part;        // NPART doubles per clique
+  const InstState *state;
+  int max_sweeps;
+  double tol;
+};
+
+// Launch the ADMM projection for the cliques in `list` (all of one size
+// bucket `bucket_size`).  precision: 0 = FP64, 1 = FP32.
+hipError_t launch_admm_projection(int precision, int bucket_size, const int32_t *list,
+                                  int count, const ProjArgs &a, hipStream_t st);
+
+// Standalone batched projection of full row-major blocks.
+hipError_t launch_standalone_projection(int dtype, int bucket_size, int count,
+                                        const int32_t *sizes, const int64_t *offsets,
+                                        const void *in, void *out, int max_sweeps,
+                                        double tol, hipStream_t st);
+
+// Minimum eigenvalue of each E_k U E_k^T (for eps_alpha); FP64.
+hipError_t launch_min_eig(int precision, int bucket_size, const int32_t *list, int count,
+                          const ProjArgs &a, double *lmin_out, hipStream_t st);
+
+int projection_bucket(int precision, int s);   // 0 if unsupported
+int projection_max_size(int precision);
+
+// ----------------------------------------------------------------------------
+// Affine step and reductions (k_affine.hip)
+// ----------------------------------------------------------------------------
+struct AffineArgs {
+  const InstDesc *inst;
+  InstState *state;
+  SolverParams params;
+  // coordinate space
+  const int32_t *coord_inst;
+  const double *c, *D, *w;
+  double *bhat, *v, *u;
+  const int64_t *contrib_ptr;
+  const int32_t *contrib_idx;
+  const double *X, *Lam;
+  int64_t ncoord;
+  // rows
+  const double *b;
+  double *r, *y1, *y;
+  // matrices
+  const double *A;        // dense
+  const int64_t *a_rowptr; const int32_t *a_col; const double *a_val;     // CSR
+  const int64_t *a_colptr; const int32_t *a_row; const double *a_cval;    // CSC (per instance blocks)
+  const double *T;
+  // tiles: (inst, start) pairs
+  const int32_t *row_tiles; int n_row_tiles; int rows_per_tile;
+  const int32_t *col_tiles; int n_col_tiles;
+  const int32_t *trow_tiles; int n_trow_tiles; int trows_per_tile;
+  const int32_t *tcol_tiles; int n_tcol_tiles;
+  const int32_t *csr_rows; int n_csr_rows;   // (inst, row) pairs for CSR instances
+  const int32_t *csc_cols; int n_csc_cols;   // (inst, col-chunk) pairs for CSR instances
+  // residual partials
+  const double *part;
+  const int64_t *inst_cl_first;               // [B+1]
+  double *hist;                               // B x hist_cap x 3
+  int batch;
+  int ignore_done;                            // diagnostics: run on frozen instances too
+};
+
+// Scratch of the diagnostics pass (allocated on first use).
+struct DiagScratch {
+  double *wu;     // ncoord: w .* u
+  double *z;      // ncoord: sum_k H_k^T lambda_k
+  double *aty;    // ncoord: A^T y_dual
+  double *ax;     // nrow: A (w .* u) - b
+  double *yd;     // nrow: y_dual = -rho y
+  double *lmin;   // ncl: min eigenvalue of E_k U E_k^T
+};
+
+hipError_t launch_diagnostics(const AffineArgs &a, const DiagScratch &s,
+                              const int64_t *inst_cl_first, int64_t nrow, double *out,
+                              hipStream_t st);
+hipError_t launch_scaled_copy(const double *src, double *dst, int64_t n, const InstState *state,
+                              int inst, hipStream_t st);
+
+hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st);
+hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st);
+hipError_t launch_objective(const AffineArgs &a, double *obj, hipStream_t st);
+
+// ----------------------------------------------------------------------------
+// One-time factorisation (k_factor.hip)
+// ----------------------------------------------------------------------------
+struct FactorArgs {
+  const InstDesc *inst;          // device
+  int batch;
+  int max_m;
+  const double *A;               // dense A (or NULL)
+  const int64_t *a_rowptr; const int32_t *a_col; const double *a_val;
+  const int64_t *a_colptr; const int32_t *a_row; const double *a_cval;
+  const double *wd;              // w/D per coordinate
+  double *M;                     // work: per instance m x m (pitch ldm) at t_off
+  double *T;                     // out: L^-1 at t_off
+  int32_t *fail;                 // per instance: 1 if a pivot <= 0
+};
+
+hipError_t launch_syrk_dense(const FactorArgs &f, const int32_t *tiles, int ntiles,
+                             hipStream_t st);
+hipError_t launch_syrk_csr(const FactorArgs &f, const int32_t *rows, int nrows, int max_ldm,
+                           hipStream_t st);
+hipError_t launch_cholesky_and_inverse(const FactorArgs &f, int max_nblk, hipStream_t st);
+
+int affine_col_tile_width();
+int affine_max_rows_per_tile();

@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/sdp.h declares, its structs have the header's
+layout, and the validation layer returns the same status codes as the oracle
+(validation runs before any device call)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import sdpgen
+from cases import invalid_instances
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdp_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(sdp):
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(sdp.lib, n), n
+    assert set(names) == set(sdp.EXPORTS)
+    out = subprocess.check_output(["nm", "-D", "--defined-only", sdp.lib._name], text=True)
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, flags=re.M), n
+
+
+def test_struct_layout_matches_header(sdp, tmp_path):
+    import ctypes as C
+    from paper_1707_05058_amd import _native as nat
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sdp.h"', 'int main(void){']
+    for st in (nat.sdp_instance, nat.sdp_options, nat.sdp_result):
+        lines.append(f'printf("{st.__name__} %zu\\n", sizeof({st.__name__}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{st.__name__}.{f} %zu\\n", offsetof({st.__name__}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for st in (nat.sdp_instance, nat.sdp_options, nat.sdp_result):
+        assert int(got[st.__name__]) == C.sizeof(st)
+        for f, _ in st._fields_:
+            assert int(got[f"{st.__name__}.{f}"]) == getattr(st, f).offset, f
+
+
+def test_default_options(sdp):
+    o = sdp.default_options()
+    assert o.rho == 1.0 and o.tol == 1e-4 and o.max_iter == 20000
+    assert o.precision == sdp.FP64 and o.adaptive_rho == 0
+    assert o.mu == 2.0 and o.nu == 10.0 and o.rho_period == 1 and o.graph_chunk > 0
+
+
+@pytest.mark.parametrize("case", invalid_instances(), ids=lambda c: c[0])
+def test_validation_codes_match_oracle(sdp, oracle_mod, case):
+    name, inst, code = case
+    assert oracle_mod.create_status(inst) == code
+    assert sdp.setup_status([inst]) == code
+
+
+def test_invalid_options_rejected(sdp):
+    inst = sdpgen.block_arrow_instance(2, 2, 1, 3, seed=0)
+    assert sdp.setup_status([inst], rho=-1.0) == -1
+    assert sdp.setup_status([inst], max_iter=0) == -1
+    assert sdp.setup_status([inst], precision=7) == -1
+
+
+def test_fp64_projection_size_limit(sdp):
+    """The FP64 projection keeps the block and V in LDS up to 96 x 96."""
+    inst = sdpgen.lovasz_theta_odd_cycle(97)
+    assert sdp.setup_status([inst], precision=sdp.FP64) == -7
+
+
+def test_batch_error_names_instance(sdp):
+    good = sdpgen.block_arrow_instance(2, 2, 1, 3, seed=0)
+    bad = invalid_instances()[2][1]
+    assert sdp.setup_status([good, bad]) == -4
+    assert "instance 1" in sdp.lib.sdp_last_error().decode()
+
+
+def test_projection_argument_checks(sdp):
+    import ctypes as C
+    lib = sdp.lib
+    assert lib.sdp_psd_project_batched(0, 16, None, None, None, None, 0, None) == 0
+    assert lib.sdp_psd_project_batched(-1, 16, None, None, None, None, 0, None) == -1
+    assert lib.sdp_psd_project_batched(0, 16, None, None, None, None, 5, None) == -1
+    assert lib.sdp_psd_project_batched(0, 129, None, None, None, None, 1, None) == -7
+    assert lib.sdp_psd_project_batched(0, 97, None, None, None, None, 0, None) == -7
+
+
+def test_null_handle_is_rejected(sdp):
+    assert sdp.lib.sdp_reset(None) == -1
+    assert sdp.lib.sdp_admm_step(None, 1, None) == -1
+    assert sdp.lib.sdp_get_stats(None, None, None) == -1

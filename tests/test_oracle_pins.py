@@ -401,65 +401,14 @@ def test_small_blockarrow_workload_converges(oracle_mod):
 # Validation status codes
 # ----------------------------------------------------------------------------
 
-def _rebuild(inst, pr, pc, keep_cols=None, extra_cols=0):
-    a = inst.a_val if keep_cols is None else inst.a_val[:, keep_cols]
-    c = inst.c if keep_cols is None else inst.c[keep_cols]
-    return a, c
-
-
-def invalid_instances():
-    """(name, instance, expected status) -- shared with the library's tests."""
-    import copy
-    base = sdpgen.block_arrow_instance(3, 3, 2, 5, seed=0)
-    out = []
-    # a pattern coordinate no clique covers: (row 2 of block 0) x (col of block 1)
-    n = base.n
-    keys = list(zip(base.pat_col.tolist(), base.pat_row.tolist()))
-    new = (0, 4)                                  # (col, row): X_40, blocks 0 and 1
-    assert (new[0], new[1]) not in keys
-    keys2 = sorted(keys + [new])
-    pos = keys2.index(new)
-    inst = copy.deepcopy(base)
-    inst.pat_col = np.array([k[0] for k in keys2], dtype=np.int32)
-    inst.pat_row = np.array([k[1] for k in keys2], dtype=np.int32)
-    inst.a_val = np.insert(base.a_val, pos, 0.0, axis=1)
-    inst.c = np.insert(base.c, pos, 0.0)
-    out.append(("uncovered", inst, -2))
-    # a clique pair missing from the pattern
-    inst = copy.deepcopy(base)
-    drop = int(np.nonzero((base.pat_row == 1) & (base.pat_col == 0))[0][0])
-    keep = np.array([j for j in range(base.nnz) if j != drop])
-    inst.pat_row, inst.pat_col = base.pat_row[keep], base.pat_col[keep]
-    inst.a_val, inst.c = base.a_val[:, keep], base.c[keep]
-    out.append(("off_pattern", inst, -3))
-    # clique vertices out of order
-    inst = copy.deepcopy(base)
-    cv = inst.clique_vert.copy()
-    cv[0], cv[1] = cv[1], cv[0]
-    inst.clique_vert = cv
-    out.append(("clique_order", inst, -4))
-    # linearly dependent A_i
-    inst = copy.deepcopy(base)
-    inst.a_val = base.a_val.copy()
-    inst.a_val[3] = 2.0 * inst.a_val[1]
-    out.append(("rank_deficient", inst, -5))
-    # non-finite data
-    inst = copy.deepcopy(base)
-    inst.c = base.c.copy()
-    inst.c[2] = np.nan
-    out.append(("nonfinite", inst, -6))
-    # clique larger than 128
-    big = sdpgen.lovasz_theta_odd_cycle(129)
-    out.append(("too_large", big, -7))
-    # unsorted pattern
-    inst = copy.deepcopy(base)
-    inst.pat_row = base.pat_row[::-1].copy()
-    inst.pat_col = base.pat_col[::-1].copy()
-    out.append(("unsorted_pattern", inst, -1))
-    return out
+from cases import invalid_instances, rank_deficient_instance  # noqa: E402
 
 
 @pytest.mark.parametrize("case", invalid_instances(), ids=lambda c: c[0])
 def test_oracle_validation_codes(oracle_mod, case):
     name, inst, code = case
     assert oracle_mod.create_status(inst) == code
+
+
+def test_oracle_rank_deficient(oracle_mod):
+    assert oracle_mod.create_status(rank_deficient_instance()) == oracle_mod.ERR_RANK_DEFICIENT
