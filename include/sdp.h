@@ -166,8 +166,16 @@ int sdp_get_history(sdp_handle *h, int32_t inst, int32_t cap, double *eps_c,
  * iterate on the GPU and stores them in res (batch entries). */
 int sdp_diagnostics(sdp_handle *h, sdp_result *res);
 
-/* Statistics of the last solve: total Jacobi sweeps and projections run. */
+/* Statistics since setup/reset: total Jacobi sweeps and clique projections run. */
 int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
+
+/* Runs n_iter iterations with plain launches, timing every stage with HIP
+ * events recorded on the handle's stream, and writes the mean milliseconds
+ * per iteration of each stage to ms[0..6]: 0 scatter (bhat), 1 A v - b,
+ * 2 L^-1 r, 3 L^-T y1, 4 u = (bhat - A^T y)/D, 5 clique projections (all size
+ * buckets), 6 residual reduction.  The iterations advance the state exactly
+ * like sdp_admm_step.  Synchronises. */
+int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms);
 
 /* Releases every device buffer of the handle. */
 void sdp_destroy(sdp_handle *h);

@@ -68,7 +68,10 @@ class sdp_result(C.Structure):
 
 EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sdp_solve",
            "sdp_psd_project_batched", "sdp_get_solution", "sdp_set_state", "sdp_get_history",
-           "sdp_diagnostics", "sdp_get_stats", "sdp_destroy", "sdp_last_error"]
+           "sdp_diagnostics", "sdp_get_stats", "sdp_time_stages", "sdp_destroy",
+           "sdp_last_error"]
+
+STAGES = ["scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "projection", "residual"]
 
 
 def _load():
@@ -90,6 +93,7 @@ def _load():
     lib.sdp_get_history.argtypes = [_p, C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32)]
     lib.sdp_diagnostics.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_get_stats.argtypes = [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.sdp_time_stages.argtypes = [_p, C.c_int32, dp]
     lib.sdp_destroy.argtypes = [_p]
     lib.sdp_destroy.restype = None
     lib.sdp_last_error.argtypes = []
@@ -252,6 +256,12 @@ class Solver:
         _check(lib.sdp_get_history(self._h, i, cap, _dptr(ec), _dptr(el), _dptr(rh), C.byref(n)))
         k = n.value
         return ec[:k], el[:k], rh[:k]
+
+    def time_stages(self, n_iter: int):
+        """Mean ms per iteration of each stage (HIP events on the solver's stream)."""
+        ms = np.zeros(len(STAGES))
+        _check(lib.sdp_time_stages(self._h, int(n_iter), _dptr(ms)))
+        return dict(zip(STAGES, ms.tolist()))
 
     def stats(self):
         sw, pr = C.c_int64(0), C.c_int64(0)

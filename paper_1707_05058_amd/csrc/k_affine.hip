@@ -370,31 +370,56 @@ __global__ __launch_bounds__(256) void k_scaled_copy(const double *src, double *
 
 }  // namespace
 
-hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st) {
-  const int nb = (int)((a.ncoord + 255) / 256);
-  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a);
-  if (a.n_row_tiles > 0) {
-    switch (a.rows_per_tile) {
-      case 1: hipLaunchKernelGGL((k_rowdot<0, 1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-      case 2: hipLaunchKernelGGL((k_rowdot<0, 2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-      case 4: hipLaunchKernelGGL((k_rowdot<0, 4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-      default: hipLaunchKernelGGL((k_rowdot<0, MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+// Stages of the X-step, launched in this order every iteration:
+//   0 scatter (bhat, v)   1 A v - b   2 T r   3 T^T y1   4 (bhat - A^T y)/D
+hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
+  switch (stage) {
+    case 0: {
+      const int nb = (int)((a.ncoord + 255) / 256);
+      hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a);
+      break;
     }
+    case 1:
+      if (a.n_row_tiles > 0) {
+        switch (a.rows_per_tile) {
+          case 1: hipLaunchKernelGGL((k_rowdot<0, 1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          case 2: hipLaunchKernelGGL((k_rowdot<0, 2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          case 4: hipLaunchKernelGGL((k_rowdot<0, 4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          default: hipLaunchKernelGGL((k_rowdot<0, MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+        }
+      }
+      if (a.n_csr_rows > 0)
+        hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
+      break;
+    case 2:
+      switch (a.trows_per_tile) {
+        case 1: hipLaunchKernelGGL((k_rowdot<1, 1>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_rowdot<1, 2>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_rowdot<1, 4>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_rowdot<1, MAX_R>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
+      }
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_coldot<1>, dim3(a.n_tcol_tiles), dim3(COL_NT), 0, st, a);
+      break;
+    case 4:
+      if (a.n_col_tiles > 0)
+        hipLaunchKernelGGL(k_coldot<0>, dim3(a.n_col_tiles), dim3(COL_NT), 0, st, a);
+      if (a.n_csc_cols > 0)
+        hipLaunchKernelGGL(k_csc_coldot<0>, dim3(a.n_csc_cols), dim3(256), 0, st, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-  if (a.n_csr_rows > 0)
-    hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
-  switch (a.trows_per_tile) {
-    case 1: hipLaunchKernelGGL((k_rowdot<1, 1>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_rowdot<1, 2>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_rowdot<1, 4>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_rowdot<1, MAX_R>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-  }
-  hipLaunchKernelGGL(k_coldot<1>, dim3(a.n_tcol_tiles), dim3(COL_NT), 0, st, a);
-  if (a.n_col_tiles > 0)
-    hipLaunchKernelGGL(k_coldot<0>, dim3(a.n_col_tiles), dim3(COL_NT), 0, st, a);
-  if (a.n_csc_cols > 0)
-    hipLaunchKernelGGL(k_csc_coldot<0>, dim3(a.n_csc_cols), dim3(256), 0, st, a);
   return hipGetLastError();
+}
+
+hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st) {
+  for (int stage = 0; stage < 5; ++stage) {
+    const hipError_t e = launch_affine_stage(a, stage, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st) {

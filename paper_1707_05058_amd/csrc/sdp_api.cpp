@@ -858,6 +858,45 @@ int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections) {
   });
 }
 
+int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
+  return guarded([&] {
+    if (!h || n_iter <= 0 || !ms) fail(SDP_ERR_ARG, "invalid arguments");
+    constexpr int NS = 7;
+    hipEvent_t ev[NS + 1];
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    double acc[NS] = {0, 0, 0, 0, 0, 0, 0};
+    try {
+      for (int it = 0; it < n_iter; ++it) {
+        HIPCHK(hipEventRecord(ev[0], h->stream));
+        for (int s = 0; s < 5; ++s) {
+          HIPCHK(launch_affine_stage(h->aff, s, h->stream));
+          HIPCHK(hipEventRecord(ev[s + 1], h->stream));
+        }
+        for (size_t b = 0; b < h->bucket_size.size(); ++b)
+          HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+                                        h->bucket_count[b], h->proj, h->stream));
+        HIPCHK(hipEventRecord(ev[6], h->stream));
+        HIPCHK(launch_residual_reduce(h->aff, h->stream));
+        HIPCHK(hipEventRecord(ev[7], h->stream));
+        HIPCHK(hipEventSynchronize(ev[7]));
+        for (int s = 0; s < NS; ++s) {
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, ev[s], ev[s + 1]));
+          acc[s] += t;
+        }
+      }
+    } catch (...) {
+      for (auto &e : ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    for (int s = 0; s < NS; ++s) ms[s] = acc[s] / n_iter;
+    h->iters_enqueued += n_iter;
+    h->have_diag = false;
+    return SDP_OK;
+  });
+}
+
 void sdp_destroy(sdp_handle *h) { destroy_handle(h); }
 
 const char *sdp_last_error(void) { return g_last_error.c_str(); }
