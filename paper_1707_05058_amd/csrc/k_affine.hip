@@ -3,15 +3,15 @@
 // (KKTflops) of the proof of Proposition 1), written on the compact lower
 // coordinates with weights w (1 on the diagonal, 2 off it):
 //   bhat = sum_k H_k^T (x_k + lambda_k / rho) - c / rho        (k_scatter)
-//   r    = A (w bhat / D) - b                                   (k_rowdot<A>)
-//   y    = L^-T (L^-1 r)   with T = L^-1 cached                 (k_rowdot<T>, k_coldot<T>)
-//   u    = (bhat - A^T y) / D                                   (k_coldot<A>)
+//   r    = A (w bhat / D) - b                                   (k_rowdot)
+//   y    = L^-T (L^-1 r)   with L^-1, L^-T cached               (k_trmv_wave)
+//   u    = (bhat - A^T y) / D                                   (k_coldot)
 // plus the per-instance residual reduction, stopping test and adaptive
 // penalty (k_residual_reduce).  Every kernel reads the instance's `done`
 // flag first, so a converged instance is frozen at its stopping iterate.
 //
 // All of these passes stream HBM: A is read twice per iteration (row-wise,
-// then column-wise) and T twice; vectors are small and L2-resident.
+// then column-wise) and the factor twice; vectors are small and L2-resident.
 // Reductions use a fixed order, so results are bitwise reproducible.
 #include "sdp_internal.h"
 
@@ -41,57 +41,53 @@ __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
   const InstState &st = a.state[inst];
   if (st.done) return;
   const double rho = st.rho;
-  double acc = 0.0;
-  const int64_t t0 = a.contrib_ptr[j], t1 = a.contrib_ptr[j + 1];
-  for (int64_t t = t0; t < t1; ++t) {
-    const int32_t e = a.contrib_idx[t];
-    acc += a.X[e] + a.Lam[e] / rho;
+  // sum_k (x_k + lambda_k / rho) - c / rho = sum_k x_k + (sum_k lambda_k - c) / rho;
+  // the contributor loads are issued four at a time to overlap their latency
+  double sx = 0.0, sl = 0.0;
+  int64_t t = a.contrib_ptr[j];
+  const int64_t t1 = a.contrib_ptr[j + 1];
+  for (; t + 4 <= t1; t += 4) {
+    const int32_t e0 = a.contrib_idx[t], e1 = a.contrib_idx[t + 1];
+    const int32_t e2 = a.contrib_idx[t + 2], e3 = a.contrib_idx[t + 3];
+    const double x0 = a.X[e0], x1 = a.X[e1], x2 = a.X[e2], x3 = a.X[e3];
+    const double l0 = a.Lam[e0], l1 = a.Lam[e1], l2 = a.Lam[e2], l3 = a.Lam[e3];
+    sx += x0; sx += x1; sx += x2; sx += x3;
+    sl += l0; sl += l1; sl += l2; sl += l3;
   }
-  const double bh = acc - a.c[j] / rho;
+  for (; t < t1; ++t) {
+    const int32_t e = a.contrib_idx[t];
+    sx += a.X[e];
+    sl += a.Lam[e];
+  }
+  const double bh = sx + (sl - a.c[j]) / rho;
   a.bhat[j] = bh;
   a.v[j] = a.w[j] * bh / a.D[j];
 }
 
 // ---------------------------------------------------------------------------
-// Row-oriented dot products over a dense row-major matrix.
-//   MODE 0:  r[i]  = sum_j A[i][j] v[j] - b[i]       (A: m x ld, per instance)
-//   MODE 1:  y1[i] = sum_{k<=i} T[i][k] r[k]         (T: ldm x ldm, lower)
-// One tile = R consecutive rows of one instance; lanes stride the columns
-// with 16-byte loads, so every wave reads contiguous 1 KiB segments.
+// r = A v - b for dense A (m x ld row-major per instance).  One tile = R
+// consecutive rows of one instance; lanes stride the columns with 16-byte
+// loads, so every wave reads contiguous 1 KiB segments of A.
 // ---------------------------------------------------------------------------
-template <int MODE, int R>
+template <int R>
 __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
-  const int inst = MODE == 0 ? a.row_tiles[2 * blockIdx.x] : a.trow_tiles[2 * blockIdx.x];
-  const int row0 = MODE == 0 ? a.row_tiles[2 * blockIdx.x + 1] : a.trow_tiles[2 * blockIdx.x + 1];
+  const int inst = a.row_tiles[2 * blockIdx.x];
+  const int row0 = a.row_tiles[2 * blockIdx.x + 1];
   if (!a.ignore_done && a.state[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int nrow = min(R, d.m - row0);
-  const double *mat;
-  const double *vec;
-  int64_t pitch;
-  int len;
-  if (MODE == 0) {
-    mat = a.A + d.a_off + (int64_t)row0 * d.ld;
-    vec = a.v + d.coord_off;
-    pitch = d.ld;
-    len = d.ld;
-  } else {
-    mat = a.T + d.t_off + (int64_t)row0 * d.ldm;
-    vec = a.r + d.row_off;
-    pitch = d.ldm;
-    len = min(d.ldm, ((row0 + R + 63) / 64) * 64);   // T is zero above the diagonal
-  }
+  const double *mat = a.A + d.a_off + (int64_t)row0 * d.ld;
+  const double2 *v2 = reinterpret_cast<const double2 *>(a.v + d.coord_off);
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  const double2 *v2 = reinterpret_cast<const double2 *>(vec);
-  const int len2 = len / 2;
+  const int len2 = d.ld / 2;
   for (int c = threadIdx.x; c < len2; c += ROW_NT) {
     const double2 x = v2[c];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (r < nrow) {
-        const double2 m2 = reinterpret_cast<const double2 *>(mat + r * pitch)[c];
+        const double2 m2 = reinterpret_cast<const double2 *>(mat + (int64_t)r * d.ld)[c];
         acc[r] += m2.x * x.x + m2.y * x.y;
       }
     }
@@ -109,56 +105,32 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < ROW_NT / 64; ++i) s += red[i][r];
-    if (MODE == 0) {
-      a.r[d.row_off + row0 + r] = s - a.b[d.row_off + row0 + r];
-    } else {
-      a.y1[d.row_off + row0 + r] = s;
-    }
+    a.r[d.row_off + row0 + r] = s - a.b[d.row_off + row0 + r];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Column-oriented dot products (transposed products) over the same matrices.
-//   MODE 0:  u[j] = (bhat[j] - sum_i A[i][j] y[i]) / D[j]
-//   MODE 1:  y[j] = sum_{i>=j} T[i][j] y1[i]
+// Column-oriented (transposed) products over dense A.
+//   RAW = 0:  u[j] = (bhat[j] - sum_i A[i][j] y[i]) / D[j]
+//   RAW = 1:  u[j] = sum_i A[i][j] y[i]            (diagnostics: A^T y)
 // One tile = 128 columns of one instance; lane l owns columns 2l, 2l+1 and
 // the 4 waves split the rows, so each wave reads contiguous 1 KiB segments.
 // ---------------------------------------------------------------------------
-//   MODE 2:  u[j] = sum_i A[i][j] y[i]               (diagnostics: raw A^T y)
-template <int MODE>
+template <int RAW>
 __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
-  const int inst = MODE != 1 ? a.col_tiles[2 * blockIdx.x] : a.tcol_tiles[2 * blockIdx.x];
-  const int col0 = MODE != 1 ? a.col_tiles[2 * blockIdx.x + 1] : a.tcol_tiles[2 * blockIdx.x + 1];
+  const int inst = a.col_tiles[2 * blockIdx.x];
+  const int col0 = a.col_tiles[2 * blockIdx.x + 1];
   if (!a.ignore_done && a.state[inst].done) return;
   const InstDesc d = a.inst[inst];
-  const double *mat;
-  const double *vec;
-  int64_t pitch;
-  int ncols, row_begin, row_end;
-  if (MODE != 1) {
-    mat = a.A + d.a_off;
-    vec = a.y + d.row_off;
-    pitch = d.ld;
-    ncols = d.ld;
-    row_begin = 0;
-    row_end = d.m;
-  } else {
-    mat = a.T + d.t_off;
-    vec = a.y1 + d.row_off;
-    pitch = d.ldm;
-    ncols = d.ldm;
-    row_begin = col0;      // T[i][j] = 0 for i < j
-    row_end = d.ldm;
-  }
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = col0 + 2 * l;
+  const double *vec = a.y + d.row_off;
   double ax = 0.0, ay = 0.0;
-  if (col < ncols) {
-    const double *base = mat + col;
-    int i = row_begin + w;
+  if (col < d.ld) {
+    const double *base = a.A + d.a_off + col;
 #pragma unroll 4
-    for (; i < row_end; i += 4) {
-      const double2 m2 = *reinterpret_cast<const double2 *>(base + (int64_t)i * pitch);
+    for (int i = w; i < d.m; i += 4) {
+      const double2 m2 = *reinterpret_cast<const double2 *>(base + (int64_t)i * d.ld);
       const double yi = vec[i];
       ax += m2.x * yi;
       ay += m2.y * yi;
@@ -167,26 +139,54 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
   __shared__ double2 red[4][64];
   red[w][l] = make_double2(ax, ay);
   __syncthreads();
-  if (w == 0 && col < ncols) {
+  if (w == 0 && col < d.ld) {
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       sx += red[k][l].x;
       sy += red[k][l].y;
     }
-    if (MODE == 0) {
-      const int64_t g = d.coord_off + col;
-      a.u[g] = (a.bhat[g] - sx) / a.D[g];
-      a.u[g + 1] = (a.bhat[g + 1] - sy) / a.D[g + 1];
-    } else if (MODE == 2) {
-      const int64_t g = d.coord_off + col;
+    const int64_t g = d.coord_off + col;
+    if (RAW) {
       a.u[g] = sx;
       a.u[g + 1] = sy;
     } else {
-      a.y[d.row_off + col] = sx;
-      a.y[d.row_off + col + 1] = sy;
+      a.u[g] = (a.bhat[g] - sx) / a.D[g];
+      a.u[g + 1] = (a.bhat[g + 1] - sy) / a.D[g + 1];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// The two substitutions with the cached factor, as triangular mat-vecs with
+// the inverse factor (one wave per row, 16-byte loads, no LDS):
+//   UPPER = 0:  y1[i] = sum_{k<=i} T[i][k] r[k]      (T = L^-1)
+//   UPPER = 1:  y[i]  = sum_{k>=i} U[i][k] y1[k]     (U = L^-T)
+// ---------------------------------------------------------------------------
+template <int UPPER>
+__global__ __launch_bounds__(256) void k_trmv_wave(AffineArgs a) {
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= a.n_t_rows) return;
+  const int inst = a.t_rows[2 * wid], row = a.t_rows[2 * wid + 1];
+  if (!a.ignore_done && a.state[inst].done) return;
+  const InstDesc d = a.inst[inst];
+  const int l = threadIdx.x & 63;
+  const double *mat = (UPPER ? a.U : a.T) + d.t_off + (int64_t)row * d.ldm;
+  const double *vec = (UPPER ? a.y1 : a.r) + d.row_off;
+  // the matrix is zero outside [begin, end); both ends are even
+  const int begin = UPPER ? (row & ~1) : 0;
+  const int end = UPPER ? ((d.m + 1) & ~1) : ((row + 2) & ~1);
+  const double2 *m2 = reinterpret_cast<const double2 *>(mat);
+  const double2 *v2 = reinterpret_cast<const double2 *>(vec);
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 8
+  for (int c = begin / 2 + l; c < end / 2; c += 64) {
+    const double2 x = m2[c], y = v2[c];
+    acc0 += x.x * y.x;
+    acc1 += x.y * y.y;
+  }
+  const double sum = wave_sum(acc0 + acc1);
+  if (l == 0) (UPPER ? a.y : a.y1)[d.row_off + row] = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -230,17 +230,18 @@ __device__ inline double ratio(double num, double den) {
   return num == 0.0 ? 0.0 : INFINITY;
 }
 
-__global__ __launch_bounds__(256) void k_residual_reduce(AffineArgs a) {
+__global__ __launch_bounds__(1024) void k_residual_reduce(AffineArgs a) {
   const int inst = blockIdx.x;
   InstState &st = a.state[inst];
   if (st.done) return;
   const int64_t c0 = a.inst_cl_first[inst], c1 = a.inst_cl_first[inst + 1];
   double s[NPART] = {0, 0, 0, 0, 0, 0};
-  for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {
-#pragma unroll
-    for (int t = 0; t < NPART; ++t) s[t] += a.part[NPART * k + t];
+  for (int64_t k = c0 + threadIdx.x; k < c1; k += 1024) {
+    const double2 *pk = reinterpret_cast<const double2 *>(a.part + NPART * k);
+    const double2 q0 = pk[0], q1 = pk[1], q2 = pk[2];
+    s[0] += q0.x; s[1] += q0.y; s[2] += q1.x; s[3] += q1.y; s[4] += q2.x; s[5] += q2.y;
   }
-  __shared__ double red[4][NPART];
+  __shared__ double red[16][NPART];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int t = 0; t < NPART; ++t) {
@@ -251,7 +252,11 @@ __global__ __launch_bounds__(256) void k_residual_reduce(AffineArgs a) {
   if (threadIdx.x != 0) return;
   double S[NPART];
 #pragma unroll
-  for (int t = 0; t < NPART; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  for (int t = 0; t < NPART; ++t) {
+    double acc = 0.0;
+    for (int i = 0; i < 16; ++i) acc += red[i][t];
+    S[t] = acc;
+  }
   const double rho = st.rho;
   const double nx = sqrt(S[1]), nhx = sqrt(S[2]);
   const double eps_c = ratio(sqrt(S[0]), nx > nhx ? nx : nhx);
@@ -382,25 +387,20 @@ hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
     case 1:
       if (a.n_row_tiles > 0) {
         switch (a.rows_per_tile) {
-          case 1: hipLaunchKernelGGL((k_rowdot<0, 1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-          case 2: hipLaunchKernelGGL((k_rowdot<0, 2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-          case 4: hipLaunchKernelGGL((k_rowdot<0, 4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-          default: hipLaunchKernelGGL((k_rowdot<0, MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          case 2: hipLaunchKernelGGL((k_rowdot<2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          case 4: hipLaunchKernelGGL((k_rowdot<4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+          default: hipLaunchKernelGGL((k_rowdot<MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
         }
       }
       if (a.n_csr_rows > 0)
         hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 2:
-      switch (a.trows_per_tile) {
-        case 1: hipLaunchKernelGGL((k_rowdot<1, 1>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_rowdot<1, 2>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_rowdot<1, 4>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_rowdot<1, MAX_R>), dim3(a.n_trow_tiles), dim3(ROW_NT), 0, st, a); break;
-      }
+      hipLaunchKernelGGL(k_trmv_wave<0>, dim3((a.n_t_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 3:
-      hipLaunchKernelGGL(k_coldot<1>, dim3(a.n_tcol_tiles), dim3(COL_NT), 0, st, a);
+      hipLaunchKernelGGL(k_trmv_wave<1>, dim3((a.n_t_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 4:
       if (a.n_col_tiles > 0)
@@ -423,7 +423,7 @@ hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_reduce, dim3(a.batch), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_residual_reduce, dim3(a.batch), dim3(1024), 0, st, a);
   return hipGetLastError();
 }
 
@@ -448,10 +448,10 @@ hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const 
   ar.r = s.ax;
   if (ar.n_row_tiles > 0) {
     switch (ar.rows_per_tile) {
-      case 1: hipLaunchKernelGGL((k_rowdot<0, 1>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-      case 2: hipLaunchKernelGGL((k_rowdot<0, 2>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-      case 4: hipLaunchKernelGGL((k_rowdot<0, 4>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-      default: hipLaunchKernelGGL((k_rowdot<0, MAX_R>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      case 2: hipLaunchKernelGGL((k_rowdot<2>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      case 4: hipLaunchKernelGGL((k_rowdot<4>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
+      default: hipLaunchKernelGGL((k_rowdot<MAX_R>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
     }
   }
   if (ar.n_csr_rows > 0)
@@ -460,7 +460,7 @@ hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const 
   at.y = s.yd;
   at.u = s.aty;
   if (at.n_col_tiles > 0)
-    hipLaunchKernelGGL(k_coldot<2>, dim3(at.n_col_tiles), dim3(COL_NT), 0, st, at);
+    hipLaunchKernelGGL(k_coldot<1>, dim3(at.n_col_tiles), dim3(COL_NT), 0, st, at);
   if (at.n_csc_cols > 0)
     hipLaunchKernelGGL(k_csc_coldot<1>, dim3(at.n_csc_cols), dim3(256), 0, st, at);
   hipLaunchKernelGGL(k_diag_reduce, dim3(a.batch), dim3(256), 0, st, a, s, cl_first, out);

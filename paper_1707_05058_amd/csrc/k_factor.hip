@@ -295,6 +295,22 @@ __global__ __launch_bounds__(256) void k_trtri_offdiag(FactorArgs f, int dlt) {
     for (int b = 0; b < 4; ++b) dst[(int64_t)(ty * 4 + a) * d.ldm + tx * 4 + b] = -out[a][b];
 }
 
+// U = T^T, tile by tile through LDS.
+__global__ __launch_bounds__(256) void k_transpose_factor(FactorArgs f) {
+  const int inst = blockIdx.x, ib = blockIdx.y, jb = blockIdx.z;
+  const InstDesc d = f.inst[inst];
+  const int nblk = d.ldm / NB;
+  if (ib >= nblk || jb >= nblk) return;
+  __shared__ double X[NB][LP];
+  load_tile(X, f.T + d.t_off + (int64_t)ib * NB * d.ldm + jb * NB, d.ldm);
+  __syncthreads();
+  double *dst = f.U + d.t_off + (int64_t)jb * NB * d.ldm + ib * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    dst[(int64_t)r * d.ldm + c] = X[c][r];
+  }
+}
+
 }  // namespace
 
 // The launch sequence needs host-side tile lists; it is driven from the host
@@ -327,5 +343,6 @@ hipError_t launch_cholesky_and_inverse(const FactorArgs &f, int max_nblk, hipStr
   hipLaunchKernelGGL(k_trtri_diag, dim3(f.batch, max_nblk), dim3(256), 0, st, f);
   for (int dlt = 1; dlt < max_nblk; ++dlt)
     hipLaunchKernelGGL(k_trtri_offdiag, dim3(f.batch, max_nblk - dlt), dim3(256), 0, st, f, dlt);
+  hipLaunchKernelGGL(k_transpose_factor, dim3(f.batch, max_nblk, max_nblk), dim3(256), 0, st, f);
   return hipGetLastError();
 }

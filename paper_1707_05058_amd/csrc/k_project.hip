@@ -2,15 +2,24 @@
 // Algorithm 1, fused with the multiplier update (LambdakUpdate) and the
 // per-clique partial sums of the residuals (PrimalConsensusResidual)).
 //
-// One workgroup owns one clique block.  The block W_k (padded to even size N,
-// zero padding is exact: a rotation whose off-diagonal entry is exactly zero
-// is the identity) and its eigenvector matrix V live in LDS.  The symmetric
-// eigenproblem is solved by the two-sided Jacobi method in parallel
-// (round-robin) order: in each of the N-1 rounds of a sweep the N/2 disjoint
-// index pairs are rotated at once, so J^T A J splits into independent 2x2
-// block updates.  Rotations use the stable formulas of Rutishauser (the 2x2
-// symmetric Schur decomposition).  Sweeps stop when off(A) <= tol * ||A||_F.
-// The projection is rebuilt as X = V diag(max(theta, 0)) V^T.
+// One workgroup owns one clique block W_k, zero-padded to the bucket size N
+// (padding is exact: a rotation whose off-diagonal entry is exactly zero is
+// the identity, so padded rows/columns never mix with real ones).  The
+// symmetric eigenproblem is solved by the two-sided Jacobi method in parallel
+// order.  The N indices sit in N "slots"; in every round the K = N/2 slot
+// pairs (2k, 2k+1) are rotated at once, so J^T A J splits into independent
+// 2x2 block updates.  Between rounds a fixed slot permutation moves the
+// indices (one index stays, the others advance around a circle), which makes
+// every pair of indices meet exactly once per sweep of N-1 rounds.
+//
+// Work split: thread t owns the 2x2 blocks (row pair a_j, column pair b) of A
+// and of V in registers, b = t mod K, a_j = t / K + (NT/K) j.  A round is:
+// owners of diagonal blocks compute the rotation (Rutishauser's stable 2x2
+// Schur formulas) and publish (c, s) in LDS; every thread applies
+// R_a^T B R_b to its A blocks and B R_b to its V blocks; then A and V are
+// written to LDS at their permuted positions and read back.  V's rows keep
+// the original index order, so X = V diag(max(theta, 0)) V^T needs no
+// un-permutation.  Sweeps stop when off(A) <= tol * ||A||_F.
 #include "sdp_internal.h"
 
 #include <math.h>
@@ -19,40 +28,43 @@ namespace {
 
 enum Mode { MODE_ADMM = 0, MODE_STANDALONE = 1, MODE_MINEIG = 2 };
 
-template <typename T> struct Big;
-template <> struct Big<float> { static constexpr float v = 1e18f; };
-template <> struct Big<double> { static constexpr double v = 1e150; };
+template <typename T> struct Num;
+template <> struct Num<float> {
+  static constexpr float big = 1e18f;
+  static constexpr float tiny = 1.17549435e-38f;
+  __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  __device__ static float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+  __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+template <> struct Num<double> {
+  static constexpr double big = 1e150;
+  static constexpr double tiny = 2.2250738585072014e-308;
+  __device__ static double rcp(double x) { return 1.0 / x; }
+  __device__ static double rsq(double x) { return 1.0 / sqrt(x); }
+  __device__ static double sqrt_(double x) { return sqrt(x); }
+};
 
-__device__ inline float tsqrt(float x) { return sqrtf(x); }
-__device__ inline double tsqrt(double x) { return sqrt(x); }
-
-// (c, s) zeroing a_pq of J^T A J with J = [[c, s], [-s, c]] on (p, q); t = s/c.
+// (c, s, t) zeroing a_pq of J^T A J with J = [[c, s], [-s, c]] on (p, q),
+// written without branches (both alternatives are evaluated and selected).
+// |a_pq| below the smallest normal number counts as zero: no rotation.
 template <typename T>
 __device__ inline void sym_rotation(T app, T aqq, T apq, T &c, T &s, T &t) {
-  if (apq == T(0)) {
-    c = T(1); s = T(0); t = T(0);
-    return;
-  }
-  const T tau = (aqq - app) / (T(2) * apq);
+  const bool z = !(fabs(apq) >= Num<T>::tiny);
+  const T tau = (aqq - app) * T(0.5) * Num<T>::rcp(z ? T(1) : apq);
   const T at = fabs(tau);
-  const T tt = (at > Big<T>::v) ? T(0.5) / at : T(1) / (at + tsqrt(T(1) + tau * tau));
-  t = (tau >= T(0)) ? tt : -tt;
-  c = T(1) / tsqrt(T(1) + t * t);
+  const T t_big = T(0.5) * Num<T>::rcp(at);
+  const T t_std = Num<T>::rcp(at + Num<T>::sqrt_(T(1) + tau * tau));
+  const T tt = (at > Num<T>::big) ? t_big : t_std;
+  t = z ? T(0) : ((tau >= T(0)) ? tt : -tt);
+  c = z ? T(1) : Num<T>::rsq(T(1) + t * t);
   s = t * c;
 }
 
-// Round-robin tournament: the k-th pair of round r among N (even) indices.
-__device__ inline void rr_pair(int N, int r, int k, int &p, int &q) {
-  int a, b;
-  if (k == 0) {
-    a = N - 1;
-    b = r;
-  } else {
-    a = (r + k) % (N - 1);
-    b = (r - k + N - 1) % (N - 1);
-  }
-  p = a < b ? a : b;
-  q = a < b ? b : a;
+// Slot permutation applied after every round (see the file comment):
+// even slots advance one pair, odd slots move back one pair, slot 1 stays.
+__host__ __device__ constexpr int sigma_slot(int s, int N) {
+  return (s & 1) ? ((s >> 1) == 0 ? 1 : ((s >> 1) == 1 ? 0 : 2 * ((s >> 1) - 1) + 1))
+                 : ((s >> 1) < N / 2 - 1 ? 2 * ((s >> 1) + 1) : N - 1);
 }
 
 // t -> (a, b) with a >= b, t = a(a+1)/2 + b.
@@ -79,18 +91,24 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
-template <typename T, int S, int NT, int MODE>
+template <typename T, int N, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__restrict__ list,
                                                 const int32_t *__restrict__ sizes,
                                                 const int64_t *__restrict__ offsets,
                                                 const T *__restrict__ in, T *__restrict__ out,
                                                 double *__restrict__ lmin_out, int max_sweeps,
                                                 double tol) {
-  constexpr int P = S + 1;
-  __shared__ T As[S * P];
-  __shared__ T Vs[S * P];
-  __shared__ T rc[S / 2], rs[S / 2], rt[S / 2], th[S];
-  __shared__ int rp[S / 2], rq[S / 2];
+  constexpr int K = N / 2;
+  static_assert(NT % K == 0 && (K * K) % NT == 0, "block ownership must tile the matrix");
+  constexpr int BPT = K * K / NT;     // 2x2 blocks per thread
+  constexpr int AS = NT / K;          // row-pair stride between a thread's blocks
+  constexpr int P = N + 1;            // LDS pitch
+  constexpr bool WANT_V = MODE != MODE_MINEIG;
+
+  __shared__ T Abuf[N * P];
+  __shared__ T Vbuf[WANT_V ? N * P : 1];
+  __shared__ T prm_c[K], prm_s[K];
+  __shared__ T th[N];
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
@@ -100,7 +118,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   if (MODE == MODE_STANDALONE) {
     s = sizes[blockIdx.x];
     off = offsets[blockIdx.x];
-    if (s <= 0 || s > S) return;   // sizes beyond max_size are left untouched
+    if (s <= 0 || s > N) return;   // sizes beyond max_size are left untouched
   } else {
     cl = list[blockIdx.x];
     const int inst = a.cl_inst[cl];
@@ -109,107 +127,159 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     off = a.cl_off[cl];
     rho = a.state[inst].rho;
   }
-  const int N = s + (s & 1);
+
+  const int b = tid % K;
+  const int a0 = tid / K;
+  T A[BPT][2][2];
+  T V[BPT][2][2];
 
   // --- gather W_k = E_k U E_k^T - Lambda_k / rho (or the caller's block) ---
   double f2 = 0.0;
-  for (int e = tid; e < N * N; e += NT) {
-    const int i = e / N, j = e - (e / N) * N;
-    T w = T(0);
-    if (i < s && j < s) {
-      if (MODE == MODE_STANDALONE) {
-        w = T(0.5) * (in[off + (int64_t)i * s + j] + in[off + (int64_t)j * s + i]);
-      } else {
-        const int ii = i > j ? i : j, jj = i > j ? j : i;
-        const int64_t g = off + (int64_t)ii * (ii + 1) / 2 + jj;
-        double wd = a.u[a.blk_loc[g]];
-        if (MODE == MODE_ADMM) wd -= a.Lam[g] / rho;
-        w = (T)wd;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int aj = a0 + AS * j;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int i = 2 * aj + d, k = 2 * b + e;
+        T w = T(0);
+        if (i < s && k < s) {
+          if (MODE == MODE_STANDALONE) {
+            w = T(0.5) * (in[off + (int64_t)i * s + k] + in[off + (int64_t)k * s + i]);
+          } else {
+            const int ii = i > k ? i : k, kk = i > k ? k : i;
+            const int64_t g = off + (int64_t)ii * (ii + 1) / 2 + kk;
+            double wd = a.u[a.blk_loc[g]];
+            if (MODE == MODE_ADMM) wd -= a.Lam[g] / rho;
+            w = (T)wd;
+          }
+        }
+        A[j][d][e] = w;
+        V[j][d][e] = (i == k) ? T(1) : T(0);
+        f2 += (double)w * (double)w;
       }
-    }
-    As[i * P + j] = w;
-    Vs[i * P + j] = (i == j) ? T(1) : T(0);
-    f2 += (double)w * (double)w;
   }
-  __syncthreads();
-  const double nrm2 = block_sum<NT>(f2, red);   // includes the barrier
-  const double thr = tol * tol * nrm2;
-  const int K = N / 2;
-  const int nA = K * (K + 1) / 2;
-  const int nV = N * K;
+  const double thr = tol * tol * block_sum<NT>(f2, red);
 
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     double o2 = 0.0;
-    for (int e = tid; e < N * N; e += NT) {
-      const int i = e / N, j = e - (e / N) * N;
-      if (i != j) {
-        const double x = (double)As[i * P + j];
-        o2 += x * x;
-      }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const bool diag = (a0 + AS * j) == b;
+      o2 += (double)A[j][0][1] * A[j][0][1] + (double)A[j][1][0] * A[j][1][0];
+      if (!diag) o2 += (double)A[j][0][0] * A[j][0][0] + (double)A[j][1][1] * A[j][1][1];
     }
     o2 = block_sum<NT>(o2, red);
     if (!(o2 > thr)) break;
+
     for (int r = 0; r < N - 1; ++r) {
-      if (tid < K) {
-        int p, q;
-        rr_pair(N, r, tid, p, q);
-        T c, sn, t;
-        sym_rotation<T>(As[p * P + p], As[q * P + q], As[p * P + q], c, sn, t);
-        rc[tid] = c; rs[tid] = sn; rt[tid] = t; rp[tid] = p; rq[tid] = q;
+      T cb, sb;
+      {
+        // 1. rotations of the diagonal blocks, published in LDS
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+          if (a0 + AS * j == b) {
+            T c, sn, t;
+            const T apq = A[j][0][1];
+            sym_rotation<T>(A[j][0][0], A[j][1][1], apq, c, sn, t);
+            A[j][0][0] -= t * apq;
+            A[j][1][1] += t * apq;
+            A[j][0][1] = T(0);
+            A[j][1][0] = T(0);
+            prm_c[b] = c;
+            prm_s[b] = sn;
+          }
+        }
+        __syncthreads();
+        cb = prm_c[b];
+        sb = prm_s[b];
       }
-      __syncthreads();
-      for (int it = tid; it < nA; it += NT) {
-        int ia, ib;
-        tri_inv(it, ia, ib);
-        const int pa = rp[ia], qa = rq[ia];
-        if (ia == ib) {
-          const T t = rt[ia];
-          const T apq = As[pa * P + qa];
-          As[pa * P + pa] -= t * apq;
-          As[qa * P + qa] += t * apq;
-          As[pa * P + qa] = T(0);
-          As[qa * P + pa] = T(0);
-        } else {
-          const int pb = rp[ib], qb = rq[ib];
-          const T ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
-          const T b00 = As[pa * P + pb], b01 = As[pa * P + qb];
-          const T b10 = As[qa * P + pb], b11 = As[qa * P + qb];
+      // 2. two-sided update of the off-diagonal blocks, column update of V
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int aj = a0 + AS * j;
+        if (aj != b) {
+          const T ca = prm_c[aj], sa = prm_s[aj];
+          const T b00 = A[j][0][0], b01 = A[j][0][1], b10 = A[j][1][0], b11 = A[j][1][1];
           const T c00 = cb * b00 - sb * b01, c01 = sb * b00 + cb * b01;
           const T c10 = cb * b10 - sb * b11, c11 = sb * b10 + cb * b11;
-          const T d00 = ca * c00 - sa * c10, d01 = ca * c01 - sa * c11;
-          const T d10 = sa * c00 + ca * c10, d11 = sa * c01 + ca * c11;
-          As[pa * P + pb] = d00; As[pa * P + qb] = d01;
-          As[qa * P + pb] = d10; As[qa * P + qb] = d11;
-          As[pb * P + pa] = d00; As[qb * P + pa] = d01;
-          As[pb * P + qa] = d10; As[qb * P + qa] = d11;
+          A[j][0][0] = ca * c00 - sa * c10;
+          A[j][0][1] = ca * c01 - sa * c11;
+          A[j][1][0] = sa * c00 + ca * c10;
+          A[j][1][1] = sa * c01 + ca * c11;
+        }
+        if (WANT_V) {
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            const T vp = V[j][d][0], vq = V[j][d][1];
+            V[j][d][0] = cb * vp - sb * vq;
+            V[j][d][1] = sb * vp + cb * vq;
+          }
         }
       }
-      if (MODE != MODE_MINEIG) {
-        for (int it = tid; it < nV; it += NT) {
-          const int i = it / K, bb = it - (it / K) * K;
-          const int pb = rp[bb], qb = rq[bb];
-          const T cb = rc[bb], sb = rs[bb];
-          const T vp = Vs[i * P + pb], vq = Vs[i * P + qb];
-          Vs[i * P + pb] = cb * vp - sb * vq;
-          Vs[i * P + qb] = sb * vp + cb * vq;
+      // 3. move to the next round's slots: A' = P A P^T, V' = V P^T
+      T *An = Abuf;
+      T *Vn = Vbuf;
+      const int sb0 = sigma_slot(2 * b, N), sb1 = sigma_slot(2 * b + 1, N);
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int aj = a0 + AS * j;
+        const int sa0 = sigma_slot(2 * aj, N), sa1 = sigma_slot(2 * aj + 1, N);
+        An[sa0 * P + sb0] = A[j][0][0];
+        An[sa0 * P + sb1] = A[j][0][1];
+        An[sa1 * P + sb0] = A[j][1][0];
+        An[sa1 * P + sb1] = A[j][1][1];
+        if (WANT_V) {
+          Vn[(2 * aj) * P + sb0] = V[j][0][0];
+          Vn[(2 * aj) * P + sb1] = V[j][0][1];
+          Vn[(2 * aj + 1) * P + sb0] = V[j][1][0];
+          Vn[(2 * aj + 1) * P + sb1] = V[j][1][1];
         }
       }
       __syncthreads();
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int aj = a0 + AS * j;
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            A[j][d][e] = An[(2 * aj + d) * P + 2 * b + e];
+            if (WANT_V) V[j][d][e] = Vn[(2 * aj + d) * P + 2 * b + e];
+          }
+      }
     }
   }
 
+  // eigenvalues sit on the diagonal slots
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (a0 + AS * j == b) {
+      th[2 * b] = A[j][0][0];
+      th[2 * b + 1] = A[j][1][1];
+    }
+  }
   if (MODE == MODE_MINEIG) {
-    double mn = 0.0;
-    for (int k = 0; k < s; ++k) mn = fmin(mn, (double)As[k * P + k]);
-    if (tid == 0) lmin_out[cl] = mn;
+    __syncthreads();
+    if (tid == 0) {
+      double mn = 0.0;
+      for (int k = 0; k < N; ++k) mn = fmin(mn, (double)th[k]);
+      lmin_out[cl] = mn;
+    }
     return;
   }
-
-  for (int k = tid; k < N; k += NT) {
-    const T d = As[k * P + k];
-    th[k] = d > T(0) ? d : T(0);
+  __syncthreads();   // every thread has read Vbuf of the last round
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int aj = a0 + AS * j;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) Vbuf[(2 * aj + d) * P + 2 * b + e] = V[j][d][e];
   }
+  for (int k = tid; k < N; k += NT) th[k] = th[k] > T(0) ? th[k] : T(0);
   __syncthreads();
 
   // --- rebuild X = V diag(theta+) V^T on the packed lower triangle ---
@@ -219,7 +289,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     int i, j;
     tri_inv(e, i, j);
     T acc = T(0);
-    for (int k = 0; k < N; ++k) acc += Vs[i * P + k] * th[k] * Vs[j * P + k];
+#pragma unroll 8
+    for (int k = 0; k < N; ++k) acc += Vbuf[i * P + k] * th[k] * Vbuf[j * P + k];
     if (MODE == MODE_STANDALONE) {
       out[off + (int64_t)i * s + j] = acc;
       out[off + (int64_t)j * s + i] = acc;
@@ -254,20 +325,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
 }
 
-template <typename T, int S, int NT, int MODE>
+template <typename T, int N, int NT, int MODE>
 hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t *sizes,
                       const int64_t *offsets, const T *in, T *out, double *lmin, int msw,
                       double tol, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_project<T, S, NT, MODE>), dim3(count), dim3(NT), 0, st, a, list, sizes,
+  hipLaunchKernelGGL((k_project<T, N, NT, MODE>), dim3(count), dim3(NT), 0, st, a, list, sizes,
                      offsets, in, out, lmin, msw, tol);
   return hipGetLastError();
 }
-
-template <typename T, int MODE>
-hipError_t dispatch(int bucket, int count, ProjArgs a, const int32_t *list, const int32_t *sizes,
-                    const int64_t *offsets, const T *in, T *out, double *lmin, int msw,
-                    double tol, hipStream_t st);
 
 template <int MODE>
 hipError_t dispatch_f32(int bucket, int count, ProjArgs a, const int32_t *list,
@@ -275,7 +341,7 @@ hipError_t dispatch_f32(int bucket, int count, ProjArgs a, const int32_t *list,
                         double *lmin, int msw, double tol, hipStream_t st) {
   switch (bucket) {
     case 16: return launch_one<float, 16, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 32: return launch_one<float, 32, 128, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
+    case 32: return launch_one<float, 32, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
     case 64: return launch_one<float, 64, 256, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
     case 128: return launch_one<float, 128, 1024, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
     default: return hipErrorInvalidValue;
@@ -288,9 +354,9 @@ hipError_t dispatch_f64(int bucket, int count, ProjArgs a, const int32_t *list,
                         double *out, double *lmin, int msw, double tol, hipStream_t st) {
   switch (bucket) {
     case 16: return launch_one<double, 16, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 32: return launch_one<double, 32, 128, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
+    case 32: return launch_one<double, 32, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
     case 64: return launch_one<double, 64, 256, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 96: return launch_one<double, 96, 512, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
+    case 96: return launch_one<double, 96, 576, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
     default: return hipErrorInvalidValue;
   }
 }

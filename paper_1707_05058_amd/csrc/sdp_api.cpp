@@ -443,14 +443,11 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       return r;
     };
     const int R = pick_r(dense_rows);
-    const int TR = pick_r(row);
     const int CW = affine_col_tile_width();
-    std::vector<int32_t> row_tiles, col_tiles, trow_tiles, tcol_tiles, csr_rows, csc_cols, syrk_tiles,
-        syrk_rows;
+    std::vector<int32_t> row_tiles, col_tiles, t_rows, csr_rows, csc_cols, syrk_tiles, syrk_rows;
     for (int i = 0; i < batch; ++i) {
       const HostInst &hi = H[i];
-      for (int r = 0; r < hi.m; r += TR) { trow_tiles.push_back(i); trow_tiles.push_back(r); }
-      for (int cc = 0; cc < hi.ldm; cc += CW) { tcol_tiles.push_back(i); tcol_tiles.push_back(cc); }
+      for (int r = 0; r < hi.m; ++r) { t_rows.push_back(i); t_rows.push_back(r); }
       if (hi.fmt == SDP_A_DENSE) {
         for (int r = 0; r < hi.m; r += R) { row_tiles.push_back(i); row_tiles.push_back(r); }
         for (int cc = 0; cc < hi.ld; cc += CW) { col_tiles.push_back(i); col_tiles.push_back(cc); }
@@ -521,6 +518,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       }
     }
     double *d_T = dev_zeros<double>(toff, own);
+    double *d_U = dev_zeros<double>(toff, own);
     double *d_wd = dev_upload(wd, own);
 
     AffineArgs &a = h->aff;
@@ -558,16 +556,14 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       a.a_cval = dev_upload(a_cval, own);
     }
     a.T = d_T;
+    a.U = d_U;
     a.row_tiles = dev_upload(row_tiles, own);
     a.n_row_tiles = (int)(row_tiles.size() / 2);
     a.rows_per_tile = R;
     a.col_tiles = dev_upload(col_tiles, own);
     a.n_col_tiles = (int)(col_tiles.size() / 2);
-    a.trow_tiles = dev_upload(trow_tiles, own);
-    a.n_trow_tiles = (int)(trow_tiles.size() / 2);
-    a.trows_per_tile = TR;
-    a.tcol_tiles = dev_upload(tcol_tiles, own);
-    a.n_tcol_tiles = (int)(tcol_tiles.size() / 2);
+    a.t_rows = dev_upload(t_rows, own);
+    a.n_t_rows = (int)(t_rows.size() / 2);
     a.csr_rows = dev_upload(csr_rows, own);
     a.n_csr_rows = (int)(csr_rows.size() / 2);
     a.csc_cols = dev_upload(csc_cols, own);
@@ -617,6 +613,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       f.wd = d_wd;
       f.M = d_M;
       f.T = d_T;
+      f.U = d_U;
       f.fail = d_fail;
       int32_t *d_syrk_tiles = dev_upload(syrk_tiles, tmp);
       int32_t *d_syrk_rows = dev_upload(syrk_rows, tmp);

@@ -10,7 +10,8 @@
 //  * dense A: row-major m x ld per instance at a_off (zero padded).
 //    CSR A: global row pointers (int64) with instance-local column indices,
 //    plus a CSC copy for A^T y.
-//  * factor: T = L^-1 (m x m row-major, pitch ldm, upper part zero) at t_off.
+//  * factor: T = L^-1 (row-major, pitch ldm, zero above the diagonal) and its
+//    transpose U = L^-T (zero below the diagonal), both at t_off.
 //  * cliques: global list; packed lower blocks X, Lambda (FP64) at cl_off;
 //    blk_loc maps a packed entry to its global coordinate; the contributor
 //    CSR (coordinate -> packed entries, sorted by clique) drives the scatter.
@@ -111,12 +112,12 @@ struct AffineArgs {
   const double *A;        // dense
   const int64_t *a_rowptr; const int32_t *a_col; const double *a_val;     // CSR
   const int64_t *a_colptr; const int32_t *a_row; const double *a_cval;    // CSC (per instance blocks)
-  const double *T;
+  const double *T;        // L^-1, lower, row-major (pitch ldm)
+  const double *U;        // L^-T, upper, row-major (pitch ldm)
   // tiles: (inst, start) pairs
   const int32_t *row_tiles; int n_row_tiles; int rows_per_tile;
   const int32_t *col_tiles; int n_col_tiles;
-  const int32_t *trow_tiles; int n_trow_tiles; int trows_per_tile;
-  const int32_t *tcol_tiles; int n_tcol_tiles;
+  const int32_t *t_rows; int n_t_rows;      // (inst, row) per wave for the factor passes
   const int32_t *csr_rows; int n_csr_rows;   // (inst, row) pairs for CSR instances
   const int32_t *csc_cols; int n_csc_cols;   // (inst, col-chunk) pairs for CSR instances
   // residual partials
@@ -161,6 +162,7 @@ struct FactorArgs {
   const double *wd;              // w/D per coordinate
   double *M;                     // work: per instance m x m (pitch ldm) at t_off
   double *T;                     // out: L^-1 at t_off
+  double *U;                     // out: L^-T at t_off
   int32_t *fail;                 // per instance: 1 if a pivot <= 0
 };
 
