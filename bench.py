@@ -36,45 +36,53 @@ WORKLOADS = {
     "banded": "banded n=2000, half-bandwidth 15 (1985 cliques of 16), m=1000 dense N(0,1) "
               "constraints, seed 0",
     "small": "block-arrow l=10 d=10 h=5 (n=105, 10 cliques of 15), m=100, seed 0",
-    "large": "block-arrow l=40 d=120 h=8 (n=4808, 40 cliques of 128), m=4000, 0.5% dense A, seed 0",
+    "large": "block-arrow l=40 d=120 h=8 (n=4808, 40 cliques of 128), m=4000, 0.5% dense A, "
+             "seed 0",
+    "batched": "512 independent block-arrow SDPs, l~U[5,50], d~U[8,40], h~U[2,10], m=n//2, "
+               "seeds 0..511, solved together",
 }
+# precision forms each workload is timed in (FP64 blocks stop at 96 x 96)
+FORMS = {"banded": ("fp32", "fp64"), "small": ("fp32", "fp64"), "large": ("fp32",),
+         "batched": ("fp32", "fp64")}
 
 
-def make_instance(name):
+def make_instances(name, batch_count):
     import sdpgen
     if name == "banded":
-        return sdpgen.workload_banded()
+        return [sdpgen.workload_banded()]
     if name == "small":
-        return sdpgen.workload_small_blockarrow()
+        return [sdpgen.workload_small_blockarrow()]
     if name == "large":
-        return sdpgen.workload_large_cliques()
+        return [sdpgen.workload_large_cliques()]
+    if name == "batched":
+        return sdpgen.workload_batched(range(batch_count))
     raise SystemExit(f"unknown workload {name}")
 
 
-def stage_bytes_flops(inst, precision):
-    """Algorithmic HBM bytes (or FLOPs) per launch of each stage."""
+def stage_bytes_flops(insts, precision):
+    """Algorithmic HBM bytes (or FLOPs) per launch of each stage, summed over
+    the instances of the batch."""
     import numpy as np
-    m, nnz = inst.m, inst.nnz
-    sizes = inst.clique_sizes().astype(np.int64)
-    npk = int(np.sum(sizes * (sizes + 1) // 2))
-    if inst.a_format == 1:
-        abytes = 12 * int(inst.a_rowptr[-1])          # value + column index
-    else:
-        abytes = 8 * m * nnz
-    tri = 8 * m * (m + 1) // 2
-    d = {
-        "scatter": dict(bound="hbm", bytes=8 * 2 * npk + 4 * npk + 8 * 5 * nnz),
-        "A_v": dict(bound="hbm", bytes=abytes + 8 * nnz + 16 * m),
-        "Linv_r": dict(bound="hbm", bytes=tri + 16 * m),
-        "LinvT_y": dict(bound="hbm", bytes=tri + 16 * m),
-        "AT_y": dict(bound="hbm", bytes=abytes + 8 * m + 24 * nnz),
-    }
-    # projection: executed Jacobi flops are data dependent; the model count
-    # 10 s^3 per clique (symmetric eig with vectors ~9 s^3 + rebuild s^3)
-    d["projection"] = dict(bound="alu", flops=int(np.sum(10 * sizes ** 3)),
+    tot = {k: 0 for k in ("scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "residual", "proj")}
+    for inst in insts:
+        m, nnz = inst.m, inst.nnz
+        sizes = inst.clique_sizes().astype(np.int64)
+        npk = int(np.sum(sizes * (sizes + 1) // 2))
+        abytes = 12 * int(inst.a_rowptr[-1]) if inst.a_format == 1 else 8 * m * nnz
+        tri = 8 * m * (m + 1) // 2
+        tot["scatter"] += 8 * 2 * npk + 4 * npk + 8 * 5 * nnz
+        tot["A_v"] += abytes + 8 * nnz + 16 * m
+        tot["Linv_r"] += tri + 16 * m
+        tot["LinvT_y"] += tri + 16 * m
+        tot["AT_y"] += abytes + 8 * m + 24 * nnz
+        tot["residual"] += 8 * 6 * inst.p
+        # model count for the projections: 10 s^3 per clique (symmetric eig
+        # with vectors ~9 s^3 plus the rebuild s^3)
+        tot["proj"] += int(np.sum(10 * sizes ** 3))
+    d = {k: dict(bound="hbm", bytes=v) for k, v in tot.items() if k != "proj"}
+    d["projection"] = dict(bound="alu", flops=tot["proj"],
                            peak_tflops=FP32_VECTOR_TFLOPS if precision == "fp32"
                            else FP64_VECTOR_TFLOPS)
-    d["residual"] = dict(bound="hbm", bytes=8 * 6 * inst.p)
     return d
 
 
@@ -102,31 +110,38 @@ def load_traffic(workload, stage):
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
-def time_form(sdp, torch, inst, precision, steps, warmup, stage_iters, stream):
+def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, repeat_solve=True):
     out = {}
+    p_total = sum(i.p for i in insts)
     # --- solve to the 1e-4 residual from a cold start (second solve timed) ---
     t0 = time.perf_counter()
-    S = sdp.Solver([inst], tol=1e-4, max_iter=20000, precision=precision,
+    S = sdp.Solver(insts, tol=1e-4, max_iter=20000, precision=precision,
                    stream=stream.cuda_stream)
     torch.cuda.synchronize()
     out["setup_s"] = time.perf_counter() - t0
     with torch.cuda.stream(stream):
-        S.solve()
-        S.reset()
+        if repeat_solve:
+            S.solve()
+            S.reset()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        r = S.solve()[0]
+        rs = S.solve()
         e1.record(stream)
         e1.synchronize()
     t_sol = e0.elapsed_time(e1) / 1e3
-    out["solve"] = dict(iters_to_tol=r["iters"], status=r["status"], time_to_tol_s=t_sol,
-                        iter_per_s=r["iters"] / t_sol, objective=r["objective"],
-                        eps_c=r["eps_c"], eps_lambda=r["eps_lambda"])
+    its = [r["iters"] for r in rs]
+    out["solve"] = dict(iters_to_tol=max(its), iters_mean=sum(its) / len(its),
+                        converged=sum(r["status"] == 0 for r in rs), instances=len(rs),
+                        time_to_tol_s=t_sol, iter_per_s=max(its) / t_sol,
+                        instance_iter_per_s=sum(its) / t_sol,
+                        objective=rs[0]["objective"], eps_c=max(r["eps_c"] for r in rs),
+                        eps_lambda=max(r["eps_lambda"] for r in rs))
+    out["objectives"] = [r["objective"] for r in rs]
     out["jacobi_sweeps_per_projection"] = (S.stats()["jacobi_sweeps"] /
                                            max(S.stats()["projections"], 1))
     S.close()
     # --- the contract: W warm-up + exactly K timed iterations ---
-    S = sdp.Solver([inst], tol=0.0, max_iter=warmup + steps + stage_iters + 10,
+    S = sdp.Solver(insts, tol=0.0, max_iter=warmup + steps + stage_iters + 10,
                    precision=precision, stream=stream.cuda_stream)
     with torch.cuda.stream(stream):
         S.step(warmup, results=False)
@@ -140,25 +155,39 @@ def time_form(sdp, torch, inst, precision, steps, warmup, stage_iters, stream):
     ms = e0.elapsed_time(e1)
     out["ms_per_step"] = ms / steps
     out["iter_per_s"] = steps / (ms / 1e3)
-    out["projections_per_s"] = out["iter_per_s"] * inst.p
+    out["projections_per_s"] = out["iter_per_s"] * p_total
+    out["instance_iter_per_s"] = out["iter_per_s"] * len(insts)
     out["stages_ms"] = S.time_stages(stage_iters)
     S.close()
     return out
 
 
-def cpu_baseline(inst, seconds):
+def cpu_baseline(insts, seconds):
+    """The oracle on a bounded sample: the first instances of the workload,
+    a few iterations each; the per-iteration time of the whole batch is the
+    sum over instances, extrapolated from the sampled ones."""
     import oracle
-    P = oracle.Problem(inst)
-    done, t0 = 0, time.perf_counter()
-    while True:
-        P.run(5, tol=0.0)
-        done += 5
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return dict(value=done / el, unit="iter/s", cores=oracle.max_threads(), kind="oracle",
-                sample=f"first {done} iterations of Algorithm 1 from X_k = Lambda_k = 0 on the "
-                       f"same instance, FP64, setup excluded ({el:.1f} s)")
+    per_inst = seconds / min(len(insts), 4)
+    times, sampled, total_it = [], [], 0
+    for inst in insts[:4]:
+        P = oracle.Problem(inst)
+        done, t0 = 0, time.perf_counter()
+        while True:
+            P.run(2, tol=0.0)
+            done += 2
+            el = time.perf_counter() - t0
+            if el >= per_inst:
+                break
+        times.append(el / done)
+        total_it += done
+        sampled.append(inst.name)
+    t_iter = sum(times) / len(times) * len(insts)
+    what = (f"first {total_it} iterations of Algorithm 1 from X_k = Lambda_k = 0 on "
+            f"{len(sampled)} of {len(insts)} instance(s), FP64, setup excluded")
+    if len(insts) > len(sampled):
+        what += "; batch time per iteration extrapolated as mean x instance count"
+    return dict(value=1.0 / t_iter, unit="iter/s", cores=oracle.max_threads(), kind="oracle",
+                sample=what)
 
 
 def main():
@@ -170,6 +199,8 @@ def main():
     ap.add_argument("--stage-iters", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="instances of the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -181,15 +212,21 @@ def main():
     import paper_1707_05058_amd as sdp
 
     torch.cuda.set_device(0)
-    inst = make_instance(args.workload)
+    t0 = time.perf_counter()
+    insts = make_instances(args.workload, args.batch_count)
+    print(f"[bench] generated {len(insts)} instance(s) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     forms = {}
-    for precision in ("fp32", "fp64"):
+    for precision in FORMS[args.workload]:
         print(f"[bench] {args.workload} {precision}: timing", file=sys.stderr, flush=True)
-        forms[precision] = time_form(sdp, torch, inst, precision, args.steps, args.warmup,
-                                     args.stage_iters, stream)
+        forms[precision] = time_form(sdp, torch, insts, precision, args.steps, args.warmup,
+                                     args.stage_iters, stream,
+                                     repeat_solve=args.workload not in ("batched", "large"))
+        print(f"[bench] {args.workload} {precision}: {forms[precision]['iter_per_s']:.1f} iter/s",
+              file=sys.stderr, flush=True)
     head = forms["fp32"]
-    model = stage_bytes_flops(inst, "fp32")
+    model = stage_bytes_flops(insts, "fp32")
     stages = head["stages_ms"]
     dom = max(stages, key=lambda k: stages[k])
     t_launch = stages[dom] / 1e3
@@ -209,9 +246,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(inst, args.cpu_seconds)
+        cpu = cpu_baseline(insts, args.cpu_seconds)
 
-    f32, f64 = forms["fp32"], forms["fp64"]
+    f32, f64 = forms["fp32"], forms.get("fp64")
+    n_cl = sum(i.p for i in insts)
     line = {
         "metric": "ADMM iter/s + PSD clique projections/s at 1e-4 residual, FP32/batched vs FP64",
         "value": head["iter_per_s"],
@@ -226,18 +264,22 @@ def main():
         "dtype": "fp32-eig/fp64-affine",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "precision": "fp32-eig/fp64-affine",
-                   "tol": 1e-4, "rho": 1.0, "adaptive_rho": False, "n": inst.n, "m": inst.m,
-                   "cliques": inst.p, "pattern_nnz": inst.nnz},
+                   "tol": 1e-4, "rho": 1.0, "adaptive_rho": False, "instances": len(insts),
+                   "n": [i.n for i in insts[:4]], "m": [i.m for i in insts[:4]],
+                   "cliques": n_cl, "pattern_nnz": sum(i.nnz for i in insts)},
         "projections_per_s": head["projections_per_s"],
-        "fp32_eig": f32,
-        "fp64": f64,
-        "speedup_fp32_vs_fp64_iter_per_s": f32["iter_per_s"] / f64["iter_per_s"],
-        "speedup_fp32_vs_fp64_time_to_tol": f64["solve"]["time_to_tol_s"] / f32["solve"]["time_to_tol_s"],
-        "objective_rel_diff_fp32_vs_fp64": abs(f32["solve"]["objective"] - f64["solve"]["objective"])
-        / abs(f64["solve"]["objective"]),
+        "fp32_eig": {k: v for k, v in f32.items() if k != "objectives"},
+        "fp64": None if f64 is None else {k: v for k, v in f64.items() if k != "objectives"},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if f64 is not None:
+        import numpy as np
+        o32, o64 = np.array(f32["objectives"]), np.array(f64["objectives"])
+        line["speedup_fp32_vs_fp64_iter_per_s"] = f32["iter_per_s"] / f64["iter_per_s"]
+        line["speedup_fp32_vs_fp64_time_to_tol"] = (f64["solve"]["time_to_tol_s"] /
+                                                    f32["solve"]["time_to_tol_s"])
+        line["objective_rel_diff_fp32_vs_fp64"] = float(np.max(np.abs(o32 - o64) / np.abs(o64)))
     print(json.dumps(line), flush=True)
 
 

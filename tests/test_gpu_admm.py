@@ -203,3 +203,30 @@ def test_banded_workload_fixed_n_fp64_and_fp32(sdp, gpu, oracle_mod):
     inst = sdpgen.workload_banded()
     compare_fixed_n(sdp, oracle_mod, inst, 8, tol_rel=1e-8)
     compare_fixed_n(sdp, oracle_mod, inst, 8, precision="fp32", tol_rel=1e-4)
+
+
+def test_large_clique_workload_fixed_n_fp32(sdp, gpu, oracle_mod):
+    """n=4808 block-arrow with 40 cliques of 128 and sparse A (m=4000, 0.5%
+    density) at full size: FP32-eig iterates against the FP64 oracle."""
+    inst = sdpgen.workload_large_cliques()
+    compare_fixed_n(sdp, oracle_mod, inst, 2, precision="fp32", tol_rel=2e-4)
+
+
+def test_batched_workload_shapes_fixed_n_fp64(sdp, gpu, oracle_mod):
+    """The first 6 instances of the 512-instance batched workload (uneven
+    clique sizes 10..50, m up to ~1000) in one handle, iterate by iterate."""
+    insts = sdpgen.workload_batched(range(6))
+    log("batched shapes: " + ", ".join(i.name for i in insts))
+    n_iter = 6
+    with sdp.Solver(insts, tol=0.0, max_iter=1000, precision="fp64") as S:
+        S.step(n_iter)
+        sols = [S.solution(i) for i in range(len(insts))]
+    for inst, sol in zip(insts, sols):
+        P = oracle_mod.Problem(inst)
+        P.run(n_iter, tol=0.0)
+        Xo, Lo = packed_oracle_blocks(P)
+        errs = dict(u=rel_err(sol["u"], P.u()), y=rel_err(sol["y_dual"], P.y_dual()),
+                    X=rel_err(sol["X_packed"], Xo), L=rel_err(sol["L_packed"], Lo))
+        log(f"  {inst.name}: {errs}")
+        for k, v in errs.items():
+            assert v <= 1e-8, (inst.name, k, v)
