@@ -70,6 +70,10 @@ def _load():
     lib.orc_gather_blocks.argtypes = [C.c_void_p, _dp, _dp]
     lib.orc_set_blocks.argtypes = [C.c_void_p, _dp, _dp]
     lib.orc_set_rho.argtypes = [C.c_void_p, C.c_double]
+    lib.orc_psd_project_derivative.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+    lib.orc_unrolled_vjp.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, _dp, _dp]
+    lib.orc_unrolled_vjp.restype = C.c_int
+    lib.orc_set_cb.argtypes = [C.c_void_p, _dp, _dp]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_get_max_threads.restype = C.c_int
     for name, rt in (("orc_nblk", C.c_int64), ("orc_rho", C.c_double), ("orc_iters", C.c_int),
@@ -127,6 +131,17 @@ def psd_project(W, max_sweeps=50, tol=1e-14, return_eig=False):
     if return_eig:
         return X, th[:s], V, sw
     return X
+
+
+def psd_project_derivative(V, theta, G):
+    """Daleckii-Krein derivative of the PSD projection at V diag(theta) V^T,
+    applied to the symmetric direction G (also its vector-Jacobian product)."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    out = np.zeros_like(G)
+    _load().orc_psd_project_derivative(V.shape[0], _d(V), _d(th), _d(G), _d(out))
+    return out
 
 
 def cholesky(M):
@@ -314,6 +329,31 @@ class Problem:
 
     def objective(self):
         return float(_load().orc_objective(self._h))
+
+    def set_cb(self, c=None, b=None):
+        """Replace C (lower values) and/or b; A and the factor are unchanged."""
+        cc = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        _load().orc_set_cb(self._h, None if cc is None else _d(cc), None if bb is None else _d(bb))
+        if cc is not None:
+            self._c_keep = cc
+        if bb is not None:
+            self._b_keep = bb
+
+    def unrolled_vjp(self, T, rho, ubar):
+        """u_T of T unrolled iterations (fixed rho, from X = Lambda = 0) and the
+        VJP (cbar, bbar) for the cotangent ubar of u_T (Frobenius products)."""
+        ub = np.ascontiguousarray(ubar, dtype=np.float64)
+        uT = np.zeros(self.nnz)
+        cb = np.zeros(self.nnz)
+        bb = np.zeros(max(self.m, 1))
+        _load().orc_unrolled_vjp(self._h, int(T), float(rho), _d(ub), _d(uT), _d(cb), _d(bb))
+        return uT, cb, bb[:self.m]
+
+    def unrolled_forward(self, T, rho):
+        self.reset(rho)
+        self.run(T, tol=0.0)
+        return self.u()
 
     def diagnostics(self):
         out = np.zeros(6)

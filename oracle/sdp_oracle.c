@@ -749,3 +749,161 @@ void orc_diagnostics(orc_problem *P, double *out) {
 void orc_gather_blocks(const orc_problem *P, const double *u, double *blocks) {
   for (int k = 0; k < P->p; ++k) gather_block(P, k, u, blocks + P->blk_off[k]);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Reverse mode of the unrolled iteration (differentiation w.r.t. C and b)    */
+/* ------------------------------------------------------------------------- */
+
+/* Derivative of the PSD projection at W = V diag(theta) V^T applied to a
+ * symmetric direction G (Daleckii-Krein):  D P+(W)[G] = V (Gam o (V^T G V)) V^T
+ * with Gam_ij = (max(th_i,0) - max(th_j,0)) / (th_i - th_j) when the signs
+ * differ, 1 when both are positive and 0 when both are <= 0.  The map is
+ * self-adjoint, so it is also the vector-Jacobian product. */
+void orc_psd_project_derivative(int s, const double *V, const double *th, const double *G,
+                                double *out) {
+  double *T1 = (double *)calloc((size_t)s * s, sizeof(double));
+  double *T2 = (double *)calloc((size_t)s * s, sizeof(double));
+  /* T1 = V^T G */
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += V[k * s + i] * G[k * s + j];
+      T1[i * s + j] = acc;
+    }
+  /* T2 = (T1 V) o Gam */
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += T1[i * s + k] * V[k * s + j];
+      double gam;
+      if (th[i] > 0.0 && th[j] > 0.0) gam = 1.0;
+      else if (!(th[i] > 0.0) && !(th[j] > 0.0)) gam = 0.0;
+      else gam = ((th[i] > 0 ? th[i] : 0.0) - (th[j] > 0 ? th[j] : 0.0)) / (th[i] - th[j]);
+      T2[i * s + j] = acc * gam;
+    }
+  /* T1 = V T2 */
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += V[i * s + k] * T2[k * s + j];
+      T1[i * s + j] = acc;
+    }
+  /* out = T1 V^T */
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += T1[i * s + k] * V[j * s + k];
+      out[i * s + j] = acc;
+    }
+  free(T1);
+  free(T2);
+}
+
+/* T iterations of Algorithm 1 from X_k = Lambda_k = 0 with fixed rho (no
+ * stopping test), then the vector-Jacobian product of u_T.  Cotangents of
+ * symmetric-matrix quantities (u, c) are taken w.r.t. the Frobenius inner
+ * product, <x, x'> = sum_j w_j x_j x'_j on the compact coordinates; the
+ * cotangent of b is Euclidean.  Given ubar it returns u_T, cbar and bbar.
+ *
+ * Forward, per iteration: bhat = sum_k H_k^T (X_k + L_k/rho) - c/rho;
+ * (u, y) from the KKT system; U_k = H_k u; W_k = U_k - L_k/rho;
+ * X_k' = P+(W_k); L_k' = L_k + rho (X_k' - U_k).  The reverse sweep takes
+ * these steps backwards; the affine map u = P bhat + Q b is self-adjoint in
+ * bhat for the Frobenius product, so its VJP is one more KKT solve with
+ * b = 0, whose multiplier is the cotangent of b. */
+int orc_unrolled_vjp(orc_problem *P, int T, double rho, const double *ubar, double *u_T,
+                     double *cbar, double *bbar) {
+  const int p = P->p;
+  const int64_t nnz = P->nnz, nb = P->nblk;
+  orc_reset(P, rho);
+  double *Vst = (double *)malloc(sizeof(double) * (size_t)T * nb);
+  int64_t nth = 0;
+  for (int k = 0; k < p; ++k) nth += P->cptr[k + 1] - P->cptr[k];
+  double *thst = (double *)malloc(sizeof(double) * (size_t)T * nth);
+  int64_t *thoff = (int64_t *)malloc(sizeof(int64_t) * (p + 1));
+  thoff[0] = 0;
+  for (int k = 0; k < p; ++k) thoff[k + 1] = thoff[k] + (P->cptr[k + 1] - P->cptr[k]);
+  double *zero_b = (double *)calloc(P->m > 0 ? P->m : 1, sizeof(double));
+  /* forward */
+  for (int t = 0; t < T; ++t) {
+    orc_form_bhat(P, P->X, P->Lam, rho, P->bhat);
+    orc_affine(P, P->bhat, P->b, P->u, P->y);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      double *Uk = (double *)malloc(sizeof(double) * s * s);
+      double *Wk = (double *)malloc(sizeof(double) * s * s);
+      gather_block(P, k, P->u, Uk);
+      for (int e = 0; e < s * s; ++e) Wk[e] = Uk[e] - P->Lam[o + e] / rho;
+      orc_psd_project(s, Wk, P->X + o, thst + (size_t)t * nth + thoff[k],
+                      Vst + (size_t)t * nb + o, P->jac_max_sweeps, P->jac_tol);
+      for (int e = 0; e < s * s; ++e) P->Lam[o + e] += rho * (P->X[o + e] - Uk[e]);
+      free(Uk); free(Wk);
+    }
+  }
+  memcpy(u_T, P->u, sizeof(double) * nnz);
+  /* reverse */
+  double *Xb = (double *)calloc(nb, sizeof(double));
+  double *Lb = (double *)calloc(nb, sizeof(double));
+  double *Ub = (double *)calloc(nb, sizeof(double));
+  double *ub = (double *)malloc(sizeof(double) * nnz);
+  double *bhb = (double *)malloc(sizeof(double) * nnz);
+  double *yb = (double *)calloc(P->m > 0 ? P->m : 1, sizeof(double));
+  for (int64_t j = 0; j < nnz; ++j) cbar[j] = 0.0;
+  for (int i = 0; i < P->m; ++i) bbar[i] = 0.0;
+  for (int t = T - 1; t >= 0; --t) {
+    /* steps 6', 5', 4' for every clique (zero cotangents at t = T-1) */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      double *G = (double *)malloc(sizeof(double) * s * s);
+      double *Wb = (double *)malloc(sizeof(double) * s * s);
+      for (int e = 0; e < s * s; ++e) {
+        G[e] = Xb[o + e] + rho * Lb[o + e];   /* cotangent of X_k' */
+        Ub[o + e] = -rho * Lb[o + e];
+      }
+      orc_psd_project_derivative(s, Vst + (size_t)t * nb + o,
+                                 thst + (size_t)t * nth + thoff[k], G, Wb);
+      for (int e = 0; e < s * s; ++e) {
+        Ub[o + e] += Wb[e];
+        Lb[o + e] -= Wb[e] / rho;
+      }
+      free(G); free(Wb);
+    }
+    /* step 3': ubar of this iteration's u (the adjoint of the gather) */
+    for (int64_t j = 0; j < nnz; ++j) ub[j] = (t == T - 1) ? ubar[j] : 0.0;
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      for (int e = 0; e < s * s; ++e) {
+        int64_t j = P->loc[o + e];
+        ub[j] += Ub[o + e] / P->w[j];
+      }
+    }
+    /* step 2': one KKT solve with b = 0 */
+    orc_affine(P, ub, zero_b, bhb, yb);
+    for (int i = 0; i < P->m; ++i) bbar[i] += yb[i];
+    /* step 1': the adjoint of bhat = sum H_k^T (X_k + L_k/rho) - c/rho */
+    for (int64_t j = 0; j < nnz; ++j) cbar[j] -= bhb[j] / rho;
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      for (int e = 0; e < s * s; ++e) {
+        double g = bhb[P->loc[o + e]];
+        Xb[o + e] = g;
+        Lb[o + e] += g / rho;
+      }
+    }
+  }
+  free(Vst); free(thst); free(thoff); free(zero_b);
+  free(Xb); free(Lb); free(Ub); free(ub); free(bhb); free(yb);
+  return ORC_OK;
+}
+
+/* Replace C and b of the problem (A and the factor are unchanged). */
+void orc_set_cb(orc_problem *P, const double *c, const double *b) {
+  if (c) memcpy(P->c, c, sizeof(double) * P->nnz);
+  if (b) memcpy(P->b, b, sizeof(double) * P->m);
+}
