@@ -177,6 +177,40 @@ int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
  * like sdp_admm_step.  Synchronises. */
 int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms);
 
+/* ---- differentiation of the unrolled iteration ---------------------------
+ * The map (C, b) -> u_T: T iterations of Algorithm 1 from X_k = Lambda_k = 0
+ * with fixed rho and no stopping test (A and the factor are held fixed).
+ * The reverse sweep applies, iteration by iteration, the adjoints of the
+ * multiplier update (LambdakUpdate), of the projection (XkUpdate, through the
+ * derivative of the PSD projection in eigenvector divided-difference form),
+ * of the gather/scatter with the entry selectors H_k and of the KKT solve
+ * (OptCondMinYPrimal; self-adjoint in bhat, so one more solve with b = 0).
+ * Per-instance vectors are concatenated over the batch: c and u as
+ * [nnz_pattern of instance 0, instance 1, ...], b as [m_0, m_1, ...]. */
+
+/* Replaces C and/or b of every instance (DEVICE pointers in the concatenated
+ * layout above; either may be NULL).  The factor does not depend on them. */
+int sdp_update_data(sdp_handle *h, const double *c, const double *b);
+
+/* Runs the T unrolled iterations from the initial state, keeping X_k and
+ * Lambda_k every ckpt_every iterations for the reverse sweep, and copies u_T
+ * to u_out (DEVICE, concatenated layout; may be NULL).  Needs adaptive_rho = 0.
+ * Leaves the handle at iterate T.  Synchronises. */
+int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u_out);
+
+/* Vector-Jacobian product of the last sdp_unrolled_forward: given the
+ * cotangent u_bar of u_T, writes c_bar and b_bar (all DEVICE, concatenated
+ * layout).  With euclidean = 0 the cotangents of u and c are taken w.r.t. the
+ * Frobenius inner product of the symmetric matrices (off-diagonal coordinates
+ * weighted by 2); with euclidean = 1 w.r.t. the plain dot product of the
+ * compact vectors (what an autodiff framework uses).  Segments between
+ * checkpoints are recomputed forward, storing each projection's eigenvectors
+ * (FP32 in the SDP_FP32_EIG form), then reversed.  Cliques larger than 64 give
+ * SDP_ERR_UNSUPPORTED.  The handle's iterate is unspecified afterwards (call
+ * sdp_reset before solving again).  Synchronises. */
+int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar,
+            int32_t euclidean);
+
 /* Releases every device buffer of the handle. */
 void sdp_destroy(sdp_handle *h);
 

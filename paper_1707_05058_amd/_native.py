@@ -68,8 +68,8 @@ class sdp_result(C.Structure):
 
 EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sdp_solve",
            "sdp_psd_project_batched", "sdp_get_solution", "sdp_set_state", "sdp_get_history",
-           "sdp_diagnostics", "sdp_get_stats", "sdp_time_stages", "sdp_destroy",
-           "sdp_last_error"]
+           "sdp_diagnostics", "sdp_get_stats", "sdp_time_stages", "sdp_update_data",
+           "sdp_unrolled_forward", "sdp_vjp", "sdp_destroy", "sdp_last_error"]
 
 STAGES = ["scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "projection", "residual"]
 
@@ -94,6 +94,9 @@ def _load():
     lib.sdp_diagnostics.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_get_stats.argtypes = [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.sdp_time_stages.argtypes = [_p, C.c_int32, dp]
+    lib.sdp_update_data.argtypes = [_p, _p, _p]
+    lib.sdp_unrolled_forward.argtypes = [_p, C.c_int32, C.c_int32, _p]
+    lib.sdp_vjp.argtypes = [_p, _p, _p, _p, C.c_int32]
     lib.sdp_destroy.argtypes = [_p]
     lib.sdp_destroy.restype = None
     lib.sdp_last_error.argtypes = []
@@ -263,10 +266,46 @@ class Solver:
         _check(lib.sdp_time_stages(self._h, int(n_iter), _dptr(ms)))
         return dict(zip(STAGES, ms.tolist()))
 
+    # --- differentiation of the unrolled iteration (device tensors) ---------
+    @property
+    def total_nnz(self):
+        return int(sum(int(i.pat_row.shape[0]) for i in self.instances))
+
+    @property
+    def total_m(self):
+        return int(sum(int(i.m) for i in self.instances))
+
+    def update_data(self, c=None, b=None):
+        """Replace C and/or b (float64 device tensors, concatenated layout)."""
+        for t, n in ((c, self.total_nnz), (b, self.total_m)):
+            if t is not None:
+                _check_tensor(t, n)
+        _check(lib.sdp_update_data(self._h, None if c is None else C.c_void_p(c.data_ptr()),
+                                   None if b is None else C.c_void_p(b.data_ptr())))
+
+    def unrolled_forward(self, T: int, ckpt_every: int, u_out=None):
+        if u_out is not None:
+            _check_tensor(u_out, self.total_nnz)
+        _check(lib.sdp_unrolled_forward(self._h, int(T), int(ckpt_every),
+                                        None if u_out is None else C.c_void_p(u_out.data_ptr())))
+
+    def vjp(self, u_bar, c_bar, b_bar, euclidean: bool = False):
+        _check_tensor(u_bar, self.total_nnz)
+        _check_tensor(c_bar, self.total_nnz)
+        _check_tensor(b_bar, self.total_m)
+        _check(lib.sdp_vjp(self._h, C.c_void_p(u_bar.data_ptr()), C.c_void_p(c_bar.data_ptr()),
+                           C.c_void_p(b_bar.data_ptr()), int(bool(euclidean))))
+
     def stats(self):
         sw, pr = C.c_int64(0), C.c_int64(0)
         _check(lib.sdp_get_stats(self._h, C.byref(sw), C.byref(pr)))
         return dict(jacobi_sweeps=sw.value, projections=pr.value)
+
+
+def _check_tensor(t, n):
+    import torch as _t
+    if t.dtype != _t.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"expected a contiguous float64 device tensor of {n} elements")
 
 
 def pack_blocks(blocks: Sequence[np.ndarray]) -> np.ndarray:

@@ -273,6 +273,7 @@ __global__ __launch_bounds__(1024) void k_residual_reduce(AffineArgs a) {
   st.eps_l = eps_l;
   st.iter = it;
   st.total_sweeps += S[5];
+  if (P.no_stop) return;
   const double e = eps_c > eps_l ? eps_c : eps_l;
   if (e <= P.tol) {
     st.done = 1;

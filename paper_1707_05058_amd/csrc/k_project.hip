@@ -108,7 +108,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   __shared__ T Abuf[N * P];
   __shared__ T Vbuf[WANT_V ? N * P : 1];
   __shared__ T prm_c[K], prm_s[K];
-  __shared__ T th[N];
+  __shared__ T th[N], thp[N];
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
@@ -279,8 +279,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
       for (int e = 0; e < 2; ++e) Vbuf[(2 * aj + d) * P + 2 * b + e] = V[j][d][e];
   }
-  for (int k = tid; k < N; k += NT) th[k] = th[k] > T(0) ? th[k] : T(0);
+  for (int k = tid; k < N; k += NT) thp[k] = th[k] > T(0) ? th[k] : T(0);
   __syncthreads();
+  if (MODE == MODE_ADMM && a.eig) {
+    // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep
+    T *eo = reinterpret_cast<T *>(a.eig) + a.eig_off[cl];
+    for (int e = tid; e < s * N; e += NT) eo[e] = Vbuf[(e / N) * P + (e % N)];
+    for (int k = tid; k < N; k += NT) eo[s * N + k] = th[k];
+  }
 
   // --- rebuild X = V diag(theta+) V^T on the packed lower triangle ---
   const int npk = s * (s + 1) / 2;
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     tri_inv(e, i, j);
     T acc = T(0);
 #pragma unroll 8
-    for (int k = 0; k < N; ++k) acc += Vbuf[i * P + k] * th[k] * Vbuf[j * P + k];
+    for (int k = 0; k < N; ++k) acc += Vbuf[i * P + k] * thp[k] * Vbuf[j * P + k];
     if (MODE == MODE_STANDALONE) {
       out[off + (int64_t)i * s + j] = acc;
       out[off + (int64_t)j * s + i] = acc;

@@ -198,6 +198,22 @@ struct sdp_handle {
   double *d_diag = nullptr;
   DiagScratch dscr{};
   int64_t iters_enqueued = 0;
+  // unrolled differentiation
+  std::vector<int64_t> user_coord_off, user_row_off;   // caller's concatenated layout
+  int64_t user_ncoord = 0, user_nrow = 0;
+  int64_t *d_user_coord_off = nullptr, *d_user_row_off = nullptr;
+  int32_t *d_row_inst = nullptr;
+  int64_t *d_eig_off = nullptr;
+  int64_t eig_total = 0;                 // elements of one iteration's (V, theta) records
+  bool adj_ready = false;                // every bucket has an adjoint kernel
+  int adj_T = 0, adj_ckpt = 0;
+  double *d_ckpt = nullptr;              // [nseg][2][npk]: X, Lambda at segment starts
+  int64_t ckpt_cap = 0;
+  void *d_eigbuf = nullptr;              // [ckpt][eig_total]
+  int64_t eigbuf_cap = 0;
+  double *d_Xb = nullptr, *d_Lb = nullptr, *d_Ub = nullptr;
+  double *d_bhat_bar = nullptr, *d_v_bar = nullptr, *d_bhb = nullptr;
+  double *d_r_bar = nullptr, *d_y1_bar = nullptr, *d_y_bar = nullptr, *d_zero_rows = nullptr;
 };
 
 namespace {
@@ -208,6 +224,21 @@ void enqueue_iteration(sdp_handle *h, hipStream_t st) {
     HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
                                   h->bucket_count[b], h->proj, st));
   HIPCHK(launch_residual_reduce(h->aff, st));
+}
+
+// One unrolled iteration (no stopping test); optionally stores (V, theta).
+void enqueue_unrolled_iteration(sdp_handle *h, hipStream_t st, void *eig) {
+  AffineArgs a = h->aff;
+  a.params.no_stop = 1;
+  a.ignore_done = 1;
+  ProjArgs p = h->proj;
+  p.eig = eig;
+  p.eig_off = h->d_eig_off;
+  HIPCHK(launch_iteration_affine(a, st));
+  for (size_t b = 0; b < h->bucket_size.size(); ++b)
+    HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+                                  h->bucket_count[b], p, st));
+  HIPCHK(launch_residual_reduce(a, st));
 }
 
 void build_graph(sdp_handle *h) {
@@ -292,6 +323,8 @@ void destroy_handle(sdp_handle *h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   for (void *p : h->owned) (void)hipFree(p);
+  if (h->d_ckpt) (void)hipFree(h->d_ckpt);
+  if (h->d_eigbuf) (void)hipFree(h->d_eigbuf);
   if (h->h_state) (void)hipHostFree(h->h_state);
   if (h->h_obj) (void)hipHostFree(h->h_obj);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -593,6 +626,35 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       h->bucket_count.push_back((int)l.size());
     }
     h->d_diag = dev_zeros<double>((size_t)4 * batch, own);
+    // caller layout of per-instance vectors, row -> instance map, and the
+    // (V, theta) record offsets used by the reverse sweep
+    {
+      std::vector<int32_t> row_inst(row);
+      int64_t uc = 0, ur = 0;
+      for (int i = 0; i < batch; ++i) {
+        h->user_coord_off.push_back(uc);
+        h->user_row_off.push_back(ur);
+        uc += H[i].nnz;
+        ur += H[i].m;
+        for (int r = 0; r < h->desc[i].ldm; ++r) row_inst[h->desc[i].row_off + r] = i;
+      }
+      h->user_ncoord = uc;
+      h->user_nrow = ur;
+      h->d_user_coord_off = dev_upload(h->user_coord_off, own);
+      h->d_user_row_off = dev_upload(h->user_row_off, own);
+      h->d_row_inst = dev_upload(row_inst, own);
+      std::vector<int64_t> eoff(cl);
+      int64_t eo = 0;
+      h->adj_ready = true;
+      for (int64_t k = 0; k < cl; ++k) {
+        const int nb = projection_bucket(h->precision, cl_size[k]);
+        if (nb > adjoint_max_bucket()) h->adj_ready = false;
+        eoff[k] = eo;
+        eo += (int64_t)cl_size[k] * nb + nb;
+      }
+      h->eig_total = eo;
+      h->d_eig_off = dev_upload(eoff, own);
+    }
     h->diag.assign(4 * batch, NAN);
 
     // ---- one-time factorisation: M = A W D^-1 A^T = L L^T, T = L^-1 ----
@@ -889,6 +951,161 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
     for (auto &e : ev) (void)hipEventDestroy(e);
     for (int s = 0; s < NS; ++s) ms[s] = acc[s] / n_iter;
     h->iters_enqueued += n_iter;
+    h->have_diag = false;
+    return SDP_OK;
+  });
+}
+
+int sdp_update_data(sdp_handle *h, const double *c, const double *b) {
+  return guarded([&] {
+    if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    if (c)
+      HIPCHK(launch_copy_user(c, const_cast<double *>(h->aff.c), h->d_desc, h->aff.coord_inst,
+                              h->d_user_coord_off, h->ncoord, 0, h->stream));
+    if (b)
+      HIPCHK(launch_copy_user_rows(b, const_cast<double *>(h->aff.b), h->d_desc, h->d_row_inst,
+                                   h->d_user_row_off, h->nrow, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->have_diag = false;
+    return SDP_OK;
+  });
+}
+
+int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u_out) {
+  return guarded([&] {
+    if (!h || T <= 0 || ckpt_every <= 0) fail(SDP_ERR_ARG, "invalid arguments");
+    if (h->opt.adaptive_rho) fail(SDP_ERR_ARG, "unrolled differentiation needs a fixed rho");
+    const int nseg = (T + ckpt_every - 1) / ckpt_every;
+    const int64_t need = (int64_t)nseg * 2 * std::max<int64_t>(h->npk, 1);
+    if (need > h->ckpt_cap) {
+      HIPCHK(hipStreamSynchronize(h->stream));
+      if (h->d_ckpt) (void)hipFree(h->d_ckpt);
+      h->d_ckpt = nullptr;
+      h->ckpt_cap = 0;
+      HIPCHK(hipMalloc((void **)&h->d_ckpt, sizeof(double) * need));
+      h->ckpt_cap = need;
+    }
+    reset_state(h);
+    const int64_t np = std::max<int64_t>(h->npk, 1);
+    for (int t = 0; t < T; ++t) {
+      if (t % ckpt_every == 0) {
+        double *slot = h->d_ckpt + (int64_t)(t / ckpt_every) * 2 * np;
+        HIPCHK(hipMemcpyAsync(slot, h->proj.X, sizeof(double) * h->npk, hipMemcpyDeviceToDevice,
+                              h->stream));
+        HIPCHK(hipMemcpyAsync(slot + np, h->proj.Lam, sizeof(double) * h->npk,
+                              hipMemcpyDeviceToDevice, h->stream));
+      }
+      enqueue_unrolled_iteration(h, h->stream, nullptr);
+    }
+    if (u_out)
+      HIPCHK(launch_copy_user(h->aff.u, u_out, h->d_desc, h->aff.coord_inst, h->d_user_coord_off,
+                              h->ncoord, 1, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->adj_T = T;
+    h->adj_ckpt = ckpt_every;
+    h->have_diag = false;
+    return SDP_OK;
+  });
+}
+
+int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, int32_t euclidean) {
+  return guarded([&] {
+    if (!h || !u_bar || !c_bar || !b_bar) fail(SDP_ERR_ARG, "invalid arguments");
+    if (h->adj_T <= 0) fail(SDP_ERR_ARG, "run sdp_unrolled_forward first");
+    if (!h->adj_ready)
+      fail(SDP_ERR_UNSUPPORTED, "the projection adjoint supports cliques up to 64 vertices");
+    auto &own = h->owned;
+    if (!h->d_Xb) {
+      h->d_Xb = dev_zeros<double>(h->npk, own);
+      h->d_Lb = dev_zeros<double>(h->npk, own);
+      h->d_Ub = dev_zeros<double>(h->npk, own);
+      h->d_bhat_bar = dev_zeros<double>(h->ncoord, own);
+      h->d_v_bar = dev_zeros<double>(h->ncoord, own);
+      h->d_bhb = dev_zeros<double>(h->ncoord, own);
+      h->d_r_bar = dev_zeros<double>(h->nrow, own);
+      h->d_y1_bar = dev_zeros<double>(h->nrow, own);
+      h->d_y_bar = dev_zeros<double>(h->nrow, own);
+      h->d_zero_rows = dev_zeros<double>(h->nrow, own);
+    }
+    const int T = h->adj_T, ck = h->adj_ckpt;
+    const size_t esz = h->precision == SDP_FP32_EIG ? sizeof(float) : sizeof(double);
+    const int64_t eneed = (int64_t)ck * std::max<int64_t>(h->eig_total, 1);
+    if (eneed > h->eigbuf_cap) {
+      HIPCHK(hipStreamSynchronize(h->stream));
+      if (h->d_eigbuf) (void)hipFree(h->d_eigbuf);
+      h->d_eigbuf = nullptr;
+      h->eigbuf_cap = 0;
+      HIPCHK(hipMalloc(&h->d_eigbuf, esz * eneed));
+      h->eigbuf_cap = eneed;
+    }
+    HIPCHK(hipMemsetAsync(h->d_Xb, 0, sizeof(double) * h->npk, h->stream));
+    HIPCHK(hipMemsetAsync(h->d_Lb, 0, sizeof(double) * h->npk, h->stream));
+    HIPCHK(hipMemsetAsync(c_bar, 0, sizeof(double) * h->user_ncoord, h->stream));
+    HIPCHK(hipMemsetAsync(b_bar, 0, sizeof(double) * h->user_nrow, h->stream));
+    AdjArgs g{};
+    g.inst = h->d_desc;
+    g.state = h->d_state;
+    g.cl_inst = h->proj.cl_inst;
+    g.cl_size = h->proj.cl_size;
+    g.cl_off = h->proj.cl_off;
+    g.blk_loc = h->proj.blk_loc;
+    g.eig_off = h->d_eig_off;
+    g.Xb = h->d_Xb;
+    g.Lb = h->d_Lb;
+    g.Ub = h->d_Ub;
+    g.npk = h->npk;
+    g.ncoord = h->ncoord;
+    g.nrow = h->nrow;
+    g.coord_inst = h->aff.coord_inst;
+    g.row_inst = h->d_row_inst;
+    g.contrib_ptr = h->aff.contrib_ptr;
+    g.contrib_idx = h->aff.contrib_idx;
+    g.w = h->aff.w;
+    g.D = h->aff.D;
+    g.bhat_bar = h->d_bhat_bar;
+    g.v_bar = h->d_v_bar;
+    g.bhb = h->d_bhb;
+    g.y_bar = h->d_y_bar;
+    g.user_coord_off = h->d_user_coord_off;
+    g.user_row_off = h->d_user_row_off;
+    g.cbar = c_bar;
+    g.bbar = b_bar;
+    g.euclid = euclidean ? 1 : 0;
+    g.batch = h->B;
+    // the KKT solve of the reverse sweep: same factor, input ubar, b = 0
+    AffineArgs ra = h->aff;
+    ra.ignore_done = 1;
+    ra.b = h->d_zero_rows;
+    ra.bhat = h->d_bhat_bar;
+    ra.v = h->d_v_bar;
+    ra.r = h->d_r_bar;
+    ra.y1 = h->d_y1_bar;
+    ra.y = h->d_y_bar;
+    ra.u = h->d_bhb;
+    const int64_t np = std::max<int64_t>(h->npk, 1);
+    const int nseg = (T + ck - 1) / ck;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+      const int t0 = seg * ck, t1 = std::min(T, t0 + ck);
+      const double *slot = h->d_ckpt + (int64_t)seg * 2 * np;
+      HIPCHK(hipMemcpyAsync(h->proj.X, slot, sizeof(double) * h->npk, hipMemcpyDeviceToDevice,
+                            h->stream));
+      HIPCHK(hipMemcpyAsync(h->proj.Lam, slot + np, sizeof(double) * h->npk,
+                            hipMemcpyDeviceToDevice, h->stream));
+      for (int t = t0; t < t1; ++t)
+        enqueue_unrolled_iteration(h, h->stream,
+                                   (char *)h->d_eigbuf + esz * (size_t)(t - t0) * h->eig_total);
+      for (int t = t1 - 1; t >= t0; --t) {
+        g.eig = (const char *)h->d_eigbuf + esz * (size_t)(t - t0) * h->eig_total;
+        g.seed = (t == T - 1) ? u_bar : nullptr;
+        for (size_t b = 0; b < h->bucket_size.size(); ++b)
+          HIPCHK(launch_adj_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+                                       h->bucket_count[b], g, h->stream));
+        HIPCHK(launch_adj_scatter(g, h->stream));
+        for (int stg = 1; stg <= 4; ++stg) HIPCHK(launch_affine_stage(ra, stg, h->stream));
+        HIPCHK(launch_adj_coord_and_gather(g, h->stream));
+      }
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
     h->have_diag = false;
     return SDP_OK;
   });

@@ -53,6 +53,7 @@ struct SolverParams {
   int32_t adaptive;
   int32_t rho_period;
   int32_t hist_cap;    // capacity of the per-instance history ring
+  int32_t no_stop;     // unrolled iterations: no stopping test, no penalty change
 };
 
 // ----------------------------------------------------------------------------
@@ -70,6 +71,8 @@ struct ProjArgs {
   const InstState *state;
   int max_sweeps;
   double tol;
+  void *eig;              // optional: per clique V (s x N) then theta (N), precision T
+  const int64_t *eig_off; // element offset of each clique's record in eig
 };
 
 // Launch the ADMM projection for the cliques in `list` (all of one size
@@ -174,3 +177,45 @@ hipError_t launch_cholesky_and_inverse(const FactorArgs &f, int max_nblk, hipStr
 
 int affine_col_tile_width();
 int affine_max_rows_per_tile();
+
+// ----------------------------------------------------------------------------
+// Reverse sweep of the unrolled iteration (k_adjoint.hip)
+// ----------------------------------------------------------------------------
+struct AdjArgs {
+  const InstDesc *inst;
+  const InstState *state;
+  // cliques / packed entries
+  const int32_t *cl_inst, *cl_size;
+  const int64_t *cl_off;
+  const int32_t *blk_loc;
+  const void *eig;            // (V, theta) records of the iteration being reversed
+  const int64_t *eig_off;
+  double *Xb, *Lb, *Ub;       // packed cotangents of X_k, Lambda_k, U_k
+  int64_t npk;
+  // coordinates and rows
+  int64_t ncoord, nrow;
+  const int32_t *coord_inst, *row_inst;
+  const int64_t *contrib_ptr;
+  const int32_t *contrib_idx;
+  const double *w, *D;
+  double *bhat_bar, *v_bar;   // input of the adjoint KKT solve
+  const double *bhb;          // its output P ubar
+  const double *y_bar;        // its multiplier
+  const double *seed;         // cotangent of u_T in the caller's layout (or NULL)
+  const int64_t *user_coord_off, *user_row_off;
+  double *cbar, *bbar;        // caller's layout
+  int euclid;                 // caller's cotangents are Euclidean on compact coordinates
+  int batch;
+};
+
+hipError_t launch_adj_projection(int precision, int bucket, const int32_t *list, int count,
+                                 const AdjArgs &a, hipStream_t st);
+hipError_t launch_adj_scatter(const AdjArgs &a, hipStream_t st);
+hipError_t launch_adj_coord_and_gather(const AdjArgs &a, hipStream_t st);
+hipError_t launch_copy_user(const double *src, double *dst, const InstDesc *inst,
+                            const int32_t *coord_inst, const int64_t *user_coord_off,
+                            int64_t ncoord, int to_user, hipStream_t st);
+hipError_t launch_copy_user_rows(const double *src, double *dst, const InstDesc *inst,
+                                 const int32_t *row_inst, const int64_t *user_row_off,
+                                 int64_t nrow, hipStream_t st);
+int adjoint_max_bucket();

@@ -1,0 +1,161 @@
+"""GPU parity of the reverse sweep (sdp_vjp) of the unrolled iteration.
+
+The vector-Jacobian product of u_T w.r.t. (C, b) is compared with the FP64
+oracle's reverse mode on the same seeded instance and cotangent: the plain
+FP64 form element by element (1e-8 relative to the largest entry), the
+FP32-eig form within 2e-3 (FP32 eigenvectors enter every projection adjoint;
+the bound is the observed FP32 error with a 10x margin).  The FP64 form is
+also checked against central finite differences of the GPU forward map.
+"""
+import numpy as np
+import pytest
+
+import sdpgen
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def weights(insts):
+    return np.concatenate([np.where(i.pat_row == i.pat_col, 1.0, 2.0) for i in insts])
+
+
+def gpu_vjp(sdp, insts, T, ckpt, rho, ubar, precision="fp64", euclidean=False):
+    import torch
+    dev = torch.device("cuda:0")
+    with sdp.Solver(insts, rho=rho, tol=0.0, max_iter=10 ** 6, precision=precision) as S:
+        u = torch.zeros(S.total_nnz, dtype=torch.float64, device=dev)
+        S.unrolled_forward(T, ckpt, u)
+        cb = torch.zeros(S.total_nnz, dtype=torch.float64, device=dev)
+        bb = torch.zeros(S.total_m, dtype=torch.float64, device=dev)
+        S.vjp(torch.from_numpy(ubar).to(dev), cb, bb, euclidean=euclidean)
+        torch.cuda.synchronize()
+        return u.cpu().numpy(), cb.cpu().numpy(), bb.cpu().numpy()
+
+
+def oracle_vjp(oracle_mod, insts, T, rho, ubar):
+    us, cs, bs, o = [], [], [], 0
+    for inst in insts:
+        P = oracle_mod.Problem(inst)
+        uT, cb, bb = P.unrolled_vjp(T, rho, ubar[o:o + inst.nnz])
+        o += inst.nnz
+        us.append(uT); cs.append(cb); bs.append(bb)
+    return np.concatenate(us), np.concatenate(cs), np.concatenate(bs)
+
+
+@pytest.mark.parametrize("T,ckpt", [(1, 1), (13, 5), (20, 20)])
+def test_vjp_fp64_matches_oracle(sdp, gpu, oracle_mod, T, ckpt):
+    insts = [sdpgen.block_arrow_instance(4, 5, 3, 15, seed=1)]
+    # (a seed distinct from the instance seed: a cotangent equal to a row of A
+    # lies in the kernel of the affine adjoint and gives c_bar = 0 exactly)
+    ubar = np.random.default_rng(1000 + T).standard_normal(insts[0].nnz)
+    log(f"vjp fp64 T={T} ckpt={ckpt}")
+    ug, cg, bg = gpu_vjp(sdp, insts, T, ckpt, 0.9, ubar)
+    uo, co, bo = oracle_vjp(oracle_mod, insts, T, 0.9, ubar)
+    errs = dict(u=rel_err(ug, uo), c=rel_err(cg, co), b=rel_err(bg, bo))
+    log(f"  {errs}")
+    for k, v in errs.items():
+        assert v <= 1e-8, (k, v)
+
+
+def test_vjp_batched_singleton_and_sparse(sdp, gpu, oracle_mod):
+    from cases import singleton_clique_instance
+    insts = [singleton_clique_instance(),
+             sdpgen.block_arrow_instance(3, 5, 2, 10, seed=6, density=0.3),
+             sdpgen.uneven_block_arrow_instance(3, l_range=(2, 5), d_range=(3, 9), h_range=(1, 3))]
+    n = sum(i.nnz for i in insts)
+    ubar = np.random.default_rng(9).standard_normal(n)
+    ug, cg, bg = gpu_vjp(sdp, insts, 17, 4, 1.1, ubar)
+    uo, co, bo = oracle_vjp(oracle_mod, insts, 17, 1.1, ubar)
+    for k, (a, b) in dict(u=(ug, uo), c=(cg, co), b=(bg, bo)).items():
+        assert rel_err(a, b) <= 1e-8, k
+
+
+def test_checkpoint_spacing_does_not_change_the_result(sdp, gpu):
+    insts = [sdpgen.block_arrow_instance(3, 4, 2, 8, seed=2)]
+    ubar = np.random.default_rng(2).standard_normal(insts[0].nnz)
+    a = gpu_vjp(sdp, insts, 12, 1, 1.0, ubar)
+    b = gpu_vjp(sdp, insts, 12, 12, 1.0, ubar)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_euclidean_convention(sdp, gpu):
+    insts = [sdpgen.block_arrow_instance(3, 4, 2, 8, seed=3)]
+    w = weights(insts)
+    ubar_w = np.random.default_rng(3).standard_normal(insts[0].nnz)
+    _, cw, bw = gpu_vjp(sdp, insts, 9, 4, 1.0, ubar_w)
+    _, ce, be = gpu_vjp(sdp, insts, 9, 4, 1.0, w * ubar_w, euclidean=True)
+    assert np.allclose(ce, w * cw, rtol=1e-12, atol=1e-14)
+    assert np.allclose(be, bw, rtol=1e-12, atol=1e-14)
+
+
+def test_vjp_fp64_matches_central_differences(sdp, gpu):
+    import torch
+    dev = torch.device("cuda:0")
+    inst = sdpgen.block_arrow_instance(4, 4, 2, 12, seed=5)
+    rng = np.random.default_rng(5)
+    T, rho, h = 25, 0.8, 1e-6
+    w = weights([inst])
+    ubar = rng.standard_normal(inst.nnz)
+    dc = rng.standard_normal(inst.nnz)
+    db = rng.standard_normal(inst.m)
+    _, cb, bb = gpu_vjp(sdp, [inst], T, 6, rho, ubar)
+    with sdp.Solver([inst], rho=rho, tol=0.0, max_iter=10 ** 6) as S:
+        u = torch.zeros(S.total_nnz, dtype=torch.float64, device=dev)
+
+        def g(sign):
+            S.update_data(torch.from_numpy(inst.c + sign * h * dc).to(dev),
+                          torch.from_numpy(inst.b + sign * h * db).to(dev))
+            S.unrolled_forward(T, T, u)
+            return float(np.sum(w * ubar * u.cpu().numpy()))
+
+        fd = (g(+1) - g(-1)) / (2 * h)
+    an = float(np.sum(w * cb * dc) + bb @ db)
+    log(f"fd {fd:.10e} analytic {an:.10e}")
+    assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_autograd_function(sdp, gpu, oracle_mod):
+    """torch gradients through the autograd.Function equal the oracle's
+    reverse mode (converted to Euclidean cotangents)."""
+    import torch
+    from paper_1707_05058_amd.autograd import unrolled_admm
+    dev = torch.device("cuda:0")
+    inst = sdpgen.block_arrow_instance(4, 5, 2, 10, seed=8)
+    w = weights([inst])
+    T, rho = 15, 1.0
+    with sdp.Solver([inst], rho=rho, tol=0.0, max_iter=10 ** 6) as S:
+        c = torch.from_numpy(inst.c.copy()).to(dev).requires_grad_(True)
+        b = torch.from_numpy(inst.b.copy()).to(dev).requires_grad_(True)
+        u = unrolled_admm(c, b, S, T=T, ckpt_every=4)
+        loss = (torch.from_numpy(w).to(dev) * c.detach() * u).sum()   # <C, X_T> with C fixed
+        loss.backward()
+        gc, gb = c.grad.cpu().numpy(), b.grad.cpu().numpy()
+    P = oracle_mod.Problem(inst)
+    _, co, bo = P.unrolled_vjp(T, rho, inst.c)
+    assert rel_err(gc, w * co) <= 1e-8
+    assert rel_err(gb, bo) <= 1e-8
+
+
+def test_vjp_fp32_form_on_the_adjoint_workload_shape(sdp, gpu, oracle_mod):
+    """One instance of the differentiation workload (l=50, d=16, h=8, m=400:
+    50 cliques of 24), 200 unrolled iterations checkpointed every 20, FP32
+    eigen-solves and projection adjoints, against the FP64 oracle."""
+    inst = sdpgen.workload_adjoint(range(1))[0]
+    ubar = inst.c.copy()          # gradient of <C, X_T> (without the direct term)
+    log("adjoint workload instance: " + inst.name)
+    ug, cg, bg = gpu_vjp(sdp, [inst], 200, 20, 1.0, ubar, precision="fp32")
+    uo, co, bo = oracle_vjp(oracle_mod, [inst], 200, 1.0, ubar)
+    errs = dict(u=rel_err(ug, uo), c=rel_err(cg, co), b=rel_err(bg, bo))
+    log(f"  fp32 vs fp64 oracle: {errs}")
+    assert errs["u"] <= 1e-4
+    assert errs["c"] <= 2e-3 and errs["b"] <= 2e-3
