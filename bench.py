@@ -40,10 +40,12 @@ WORKLOADS = {
              "seed 0",
     "batched": "512 independent block-arrow SDPs, l~U[5,50], d~U[8,40], h~U[2,10], m=n//2, "
                "seeds 0..511, solved together",
+    "adjoint": "64 block-arrow SDPs l=50 d=16 h=8 (n=808, 50 cliques of 24), m=400, seeds 0..63: "
+               "200 unrolled iterations checkpointed every 20, forward + reverse sweep",
 }
 # precision forms each workload is timed in (FP64 blocks stop at 96 x 96)
 FORMS = {"banded": ("fp32", "fp64"), "small": ("fp32", "fp64"), "large": ("fp32",),
-         "batched": ("fp32", "fp64")}
+         "batched": ("fp32", "fp64"), "adjoint": ("fp32", "fp64")}
 
 
 def make_instances(name, batch_count):
@@ -56,6 +58,8 @@ def make_instances(name, batch_count):
         return [sdpgen.workload_large_cliques()]
     if name == "batched":
         return sdpgen.workload_batched(range(batch_count))
+    if name == "adjoint":
+        return sdpgen.workload_adjoint(range(min(batch_count, 64)))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -162,6 +166,39 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     return out
 
 
+def time_adjoint(sdp, torch, insts, precision, T, ckpt, stream):
+    """Unrolled forward (T iterations, checkpoints every ckpt) and the reverse
+    sweep of <C, X_T>, timed with HIP events on the solver's stream."""
+    out = {}
+    dev = torch.device("cuda:0")
+    S = sdp.Solver(insts, tol=0.0, max_iter=10 ** 7, precision=precision,
+                   stream=stream.cuda_stream)
+    u = torch.zeros(S.total_nnz, dtype=torch.float64, device=dev)
+    import numpy as np
+    ubar = torch.from_numpy(np.concatenate([i.c for i in insts])).to(dev)
+    cb = torch.zeros_like(u)
+    bb = torch.zeros(S.total_m, dtype=torch.float64, device=dev)
+    with torch.cuda.stream(stream):
+        S.unrolled_forward(2, 1, u)            # warm-up (allocations, code paths)
+        S.vjp(ubar, cb, bb)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        S.unrolled_forward(T, ckpt, u)
+        ev[1].record(stream)
+        S.vjp(ubar, cb, bb)
+        ev[2].record(stream)
+        ev[2].synchronize()
+    tf, tb = ev[0].elapsed_time(ev[1]) / 1e3, ev[1].elapsed_time(ev[2]) / 1e3
+    S.close()
+    p_total = sum(i.p for i in insts)
+    out.update(T=T, ckpt_every=ckpt, forward_s=tf, backward_s=tb,
+               iter_per_s=T / tf, ms_per_step=1e3 * tf / T,
+               projections_per_s=T * p_total / tf,
+               backward_iter_per_s=T / tb, backward_over_forward=tb / tf,
+               grad_norm_c=float(cb.norm()), grad_norm_b=float(bb.norm()))
+    return out, cb.cpu().numpy(), bb.cpu().numpy()
+
+
 def cpu_baseline(insts, seconds):
     """The oracle on a bounded sample: the first instances of the workload,
     a few iterations each; the per-iteration time of the whole batch is the
@@ -217,6 +254,9 @@ def main():
     print(f"[bench] generated {len(insts)} instance(s) in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
+    if args.workload == "adjoint":
+        run_adjoint(args, sdp, torch, insts, stream)
+        return
     forms = {}
     for precision in FORMS[args.workload]:
         print(f"[bench] {args.workload} {precision}: timing", file=sys.stderr, flush=True)
@@ -280,6 +320,42 @@ def main():
         line["speedup_fp32_vs_fp64_time_to_tol"] = (f64["solve"]["time_to_tol_s"] /
                                                     f32["solve"]["time_to_tol_s"])
         line["objective_rel_diff_fp32_vs_fp64"] = float(np.max(np.abs(o32 - o64) / np.abs(o64)))
+    print(json.dumps(line), flush=True)
+
+
+def run_adjoint(args, sdp, torch, insts, stream):
+    import numpy as np
+    res, grads = {}, {}
+    for precision in FORMS["adjoint"]:
+        print(f"[bench] adjoint {precision}", file=sys.stderr, flush=True)
+        res[precision], cb, bb = time_adjoint(sdp, torch, insts, precision, 200, 20, stream)
+        grads[precision] = (cb, bb)
+    (c32, b32), (c64, b64) = grads["fp32"], grads["fp64"]
+    head = res["fp32"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.Problem(insts[0])
+        t0 = time.perf_counter()
+        P.unrolled_vjp(200, 1.0, insts[0].c)
+        el = time.perf_counter() - t0
+        cpu = dict(value=200.0 / (el * len(insts)), unit="iter/s", cores=oracle.max_threads(),
+                   kind="oracle",
+                   sample=f"instance 0 only: 200 unrolled iterations + reverse sweep in {el:.1f} s, "
+                          f"FP64; batch rate extrapolated as 1 / (time x {len(insts)})")
+    line = {
+        "metric": "ADMM iter/s + PSD clique projections/s at 1e-4 residual, FP32/batched vs FP64",
+        "value": head["iter_per_s"], "unit": "iter/s", "n_gpus": 1, "steps": 200, "warmup": 2,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32-eig/fp64-affine", "data": "synthetic",
+        "config": {"workload": WORKLOADS["adjoint"], "instances": len(insts)},
+        "projections_per_s": head["projections_per_s"],
+        "fp32_eig": res["fp32"], "fp64": res["fp64"],
+        "grad_rel_diff_fp32_vs_fp64": {
+            "c": float(np.abs(c32 - c64).max() / np.abs(c64).max()),
+            "b": float(np.abs(b32 - b64).max() / np.abs(b64).max())},
+        "roofline": None, "cpu_baseline": cpu,
+    }
     print(json.dumps(line), flush=True)
 
 
