@@ -240,9 +240,9 @@ def main():
                     help="instances of the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(independent instances would shard across GPUs with no communication, see the "
-              "design notes)", file=sys.stderr, flush=True)
+        print(f"bench.py: this benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent instances would shard across GPUs with no communication; "
+              "nothing here drives a second GPU)", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import torch
