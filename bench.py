@@ -143,6 +143,7 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     out["objectives"] = [r["objective"] for r in rs]
     out["jacobi_sweeps_per_projection"] = (S.stats()["jacobi_sweeps"] /
                                            max(S.stats()["projections"], 1))
+    out["projection_plan"] = [dict(N=n, threads=t, cliques=c) for n, t, c in S.projection_plan()]
     S.close()
     # --- the contract: W warm-up + exactly K timed iterations ---
     S = sdp.Solver(insts, tol=0.0, max_iter=warmup + steps + stage_iters + 10,

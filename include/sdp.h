@@ -91,6 +91,9 @@ typedef struct {
   void *stream;                 /* hipStream_t to run on (NULL: the library's own stream) */
   int32_t jacobi_max_sweeps;    /* 0: default (30 for FP32, 40 for FP64)     */
   double jacobi_tol;            /* 0: default; off(A) <= tol * ||A||_F stops the sweeps */
+  int32_t autotune;             /* 1: time the projection kernel variants per clique size
+                                   at setup and keep the fastest (cached per process);
+                                   0: smallest fitting block size */
 } sdp_options;
 
 /* Per-instance result. */
@@ -105,7 +108,8 @@ typedef struct {
 } sdp_result;
 
 /* Fills *opt with defaults: rho 1, tol 1e-4, max_iter 20000, SDP_FP64,
- * adaptive off, mu 2, nu 10, rho_period 1, graph_chunk 25, own stream. */
+ * adaptive off, mu 2, nu 10, rho_period 1, graph_chunk 25, own stream,
+ * autotune on. */
 void sdp_default_options(sdp_options *opt);
 
 /* Validates `batch` instances, copies them to the device, builds the clique
@@ -143,6 +147,20 @@ int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *size
                             const int64_t *offsets, const void *in, void *out,
                             int32_t dtype, void *stream);
 
+/* The projection kernel variants built for `dtype`: padded block size N and
+ * threads per workgroup.  Writes up to `cap` entries and the number of
+ * variants through *count (host only, no GPU work). */
+int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_t *threads,
+                            int32_t *count);
+
+/* sdp_psd_project_batched with an explicit kernel variant (an index into the
+ * list of sdp_projection_variants); max_size must not exceed that variant's
+ * N.  The result is the same projection; the variants differ in how the work
+ * is spread over the workgroup. */
+int sdp_psd_project_variant(int32_t variant, int32_t count, int32_t max_size,
+                            const int32_t *sizes, const int64_t *offsets, const void *in,
+                            void *out, int32_t dtype, void *stream);
+
 /* Copies instance `inst`'s iterate to host memory (any pointer may be NULL):
  * u[nnz_pattern] the lower values of X; y_dual[m] = -rho*y (the dual
  * multipliers of <A_i, X> = b_i); Xk/Lk the packed clique blocks of all p
@@ -168,6 +186,13 @@ int sdp_diagnostics(sdp_handle *h, sdp_result *res);
 
 /* Statistics since setup/reset: total Jacobi sweeps and clique projections run. */
 int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
+
+/* The projection launch plan chosen at setup: one entry per launch list, with
+ * the padded block size N, the threads per workgroup NT and the number of
+ * cliques it covers.  Writes up to `cap` entries (pointers may be NULL when cap
+ * is 0) and the number of lists through *count. */
+int sdp_projection_plan(sdp_handle *h, int32_t cap, int32_t *block_n, int32_t *threads,
+                        int32_t *cliques, int32_t *count);
 
 /* Runs n_iter iterations with plain launches, timing every stage with HIP
  * events recorded on the handle's stream, and writes the mean milliseconds

@@ -7,8 +7,10 @@ behind the C ABI of include/sdp.h; this package is its thin Python binding.
 """
 from ._native import (A_CSR, A_DENSE, DTYPE_FP32, DTYPE_FP64, EXPORTS, FP32_EIG, FP64,
                       SdpError, Solver, default_options, lib, make_options, pack_blocks,
-                      psd_project_batched, sdp_result, setup_status, unpack_blocks)
+                      projection_variants, psd_project_batched, sdp_result, setup_status,
+                      unpack_blocks)
 
-__all__ = ["Solver", "SdpError", "psd_project_batched", "setup_status", "make_options",
+__all__ = ["Solver", "SdpError", "psd_project_batched", "projection_variants", "setup_status",
+           "make_options",
            "default_options", "pack_blocks", "unpack_blocks", "lib", "EXPORTS", "FP64",
            "FP32_EIG", "DTYPE_FP32", "DTYPE_FP64", "A_DENSE", "A_CSR", "sdp_result"]

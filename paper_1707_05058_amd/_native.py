@@ -53,7 +53,8 @@ class sdp_options(C.Structure):
     _fields_ = [("rho", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("adaptive_rho", C.c_int32), ("mu", C.c_double),
                 ("nu", C.c_double), ("rho_period", C.c_int32), ("graph_chunk", C.c_int32),
-                ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double)]
+                ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
+                ("autotune", C.c_int32)]
 
 
 class sdp_result(C.Structure):
@@ -67,9 +68,10 @@ class sdp_result(C.Structure):
 
 
 EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sdp_solve",
-           "sdp_psd_project_batched", "sdp_get_solution", "sdp_set_state", "sdp_get_history",
-           "sdp_diagnostics", "sdp_get_stats", "sdp_time_stages", "sdp_update_data",
-           "sdp_unrolled_forward", "sdp_vjp", "sdp_destroy", "sdp_last_error"]
+           "sdp_psd_project_batched", "sdp_projection_variants", "sdp_psd_project_variant",
+           "sdp_get_solution", "sdp_set_state", "sdp_get_history",
+           "sdp_diagnostics", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
+           "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_destroy", "sdp_last_error"]
 
 STAGES = ["scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "projection", "residual"]
 
@@ -88,11 +90,17 @@ def _load():
     lib.sdp_admm_step.argtypes = [_p, C.c_int32, C.POINTER(sdp_result)]
     lib.sdp_solve.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_psd_project_batched.argtypes = [C.c_int32, C.c_int32, _p, _p, _p, _p, C.c_int32, _p]
+    lib.sdp_psd_project_variant.argtypes = [C.c_int32, C.c_int32, C.c_int32, _p, _p, _p, _p,
+                                            C.c_int32, _p]
+    lib.sdp_projection_variants.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.sdp_get_solution.argtypes = [_p, C.c_int32, dp, dp, dp, dp]
     lib.sdp_set_state.argtypes = [_p, C.c_int32, dp, dp, C.c_double]
     lib.sdp_get_history.argtypes = [_p, C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32)]
     lib.sdp_diagnostics.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_get_stats.argtypes = [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    ip = C.POINTER(C.c_int32)
+    lib.sdp_projection_plan.argtypes = [_p, C.c_int32, ip, ip, ip, ip]
     lib.sdp_time_stages.argtypes = [_p, C.c_int32, dp]
     lib.sdp_update_data.argtypes = [_p, _p, _p]
     lib.sdp_unrolled_forward.argtypes = [_p, C.c_int32, C.c_int32, _p]
@@ -301,6 +309,15 @@ class Solver:
         _check(lib.sdp_get_stats(self._h, C.byref(sw), C.byref(pr)))
         return dict(jacobi_sweeps=sw.value, projections=pr.value)
 
+    def projection_plan(self):
+        """[(N, threads, cliques)] of the projection launch lists."""
+        n = C.c_int32(0)
+        _check(lib.sdp_projection_plan(self._h, 0, None, None, None, C.byref(n)))
+        k = n.value
+        N, NT, cnt = (C.c_int32 * k)(), (C.c_int32 * k)(), (C.c_int32 * k)()
+        _check(lib.sdp_projection_plan(self._h, k, N, NT, cnt, C.byref(n)))
+        return [(N[i], NT[i], cnt[i]) for i in range(k)]
+
 
 def _check_tensor(t, n):
     import torch as _t
@@ -332,11 +349,14 @@ def unpack_blocks(flat: np.ndarray, sizes) -> List[np.ndarray]:
     return out
 
 
-def psd_project_batched(sizes, offsets, inp, out, max_size: int, stream=None) -> None:
+def psd_project_batched(sizes, offsets, inp, out, max_size: int, stream=None,
+                        variant: Optional[int] = None) -> None:
     """Standalone PSD projection of full row-major blocks (torch CUDA tensors).
 
     sizes: int32 tensor [count]; offsets: int64 tensor [count] (element
-    offsets); inp/out: float32 or float64 tensors of the same dtype.
+    offsets); inp/out: float32 or float64 tensors of the same dtype.  variant:
+    an index into projection_variants(dtype) (None: the smallest block size
+    that fits max_size).
     """
     import torch as _t
     if inp.dtype == _t.float64:
@@ -354,6 +374,19 @@ def psd_project_batched(sizes, offsets, inp, out, max_size: int, stream=None) ->
     if count and int(offsets.shape[0]) != count:
         raise ValueError("sizes/offsets length mismatch")
     st = _t.cuda.current_stream().cuda_stream if stream is None else int(stream)
-    _check(lib.sdp_psd_project_batched(count, int(max_size), C.c_void_p(sizes.data_ptr()),
-                                       C.c_void_p(offsets.data_ptr()), C.c_void_p(inp.data_ptr()),
-                                       C.c_void_p(out.data_ptr()), dt, C.c_void_p(st)))
+    args = (count, int(max_size), C.c_void_p(sizes.data_ptr()), C.c_void_p(offsets.data_ptr()),
+            C.c_void_p(inp.data_ptr()), C.c_void_p(out.data_ptr()), dt, C.c_void_p(st))
+    if variant is None:
+        _check(lib.sdp_psd_project_batched(*args))
+    else:
+        _check(lib.sdp_psd_project_variant(int(variant), *args))
+
+
+def projection_variants(dtype: int):
+    """[(N, threads)] of the projection kernel variants for DTYPE_FP64/DTYPE_FP32."""
+    n = C.c_int32(0)
+    _check(lib.sdp_projection_variants(int(dtype), 0, None, None, C.byref(n)))
+    k = n.value
+    N, NT = (C.c_int32 * k)(), (C.c_int32 * k)()
+    _check(lib.sdp_projection_variants(int(dtype), k, N, NT, C.byref(n)))
+    return [(N[i], NT[i]) for i in range(k)]

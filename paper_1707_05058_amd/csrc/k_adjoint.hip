@@ -176,20 +176,22 @@ __global__ __launch_bounds__(256) void k_copy_user_rows(const double *src, doubl
 
 }  // namespace
 
-hipError_t launch_adj_projection(int precision, int bucket, const int32_t *list, int count,
+hipError_t launch_adj_projection(int precision, int N, const int32_t *list, int count,
                                  const AdjArgs &a, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   if (precision == 1) {
-    switch (bucket) {
+    switch (N) {
       case 16: hipLaunchKernelGGL((k_adj_proj<float, 16>), dim3(count), dim3(256), 0, st, a, list); break;
       case 32: hipLaunchKernelGGL((k_adj_proj<float, 32>), dim3(count), dim3(256), 0, st, a, list); break;
+      case 48: hipLaunchKernelGGL((k_adj_proj<float, 48>), dim3(count), dim3(256), 0, st, a, list); break;
       case 64: hipLaunchKernelGGL((k_adj_proj<float, 64>), dim3(count), dim3(256), 0, st, a, list); break;
       default: return hipErrorInvalidValue;
     }
   } else {
-    switch (bucket) {
+    switch (N) {
       case 16: hipLaunchKernelGGL((k_adj_proj<double, 16>), dim3(count), dim3(256), 0, st, a, list); break;
       case 32: hipLaunchKernelGGL((k_adj_proj<double, 32>), dim3(count), dim3(256), 0, st, a, list); break;
+      case 48: hipLaunchKernelGGL((k_adj_proj<double, 48>), dim3(count), dim3(256), 0, st, a, list); break;
       case 64: hipLaunchKernelGGL((k_adj_proj<double, 64>), dim3(count), dim3(256), 0, st, a, list); break;
       default: return hipErrorInvalidValue;
     }

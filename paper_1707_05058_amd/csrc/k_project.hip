@@ -341,72 +341,136 @@ hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t 
   return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t dispatch_f32(int bucket, int count, ProjArgs a, const int32_t *list,
-                        const int32_t *sizes, const int64_t *offsets, const float *in, float *out,
-                        double *lmin, int msw, double tol, hipStream_t st) {
-  switch (bucket) {
-    case 16: return launch_one<float, 16, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 32: return launch_one<float, 32, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 64: return launch_one<float, 64, 256, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 128: return launch_one<float, 128, 1024, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    default: return hipErrorInvalidValue;
+// Kernel variants: padded block size N and threads per workgroup NT.  Each
+// thread owns K*K/NT 2x2 blocks (K = N/2).  The autotuner picks, per clique
+// size, the variant that runs fastest; without it the smallest N and the
+// first NT listed for that N are used.
+struct Variant { int N, NT; };
+constexpr Variant kVar32[] = {{16, 64},  {32, 64},  {32, 128}, {32, 256}, {48, 192}, {64, 256},
+                              {64, 128}, {64, 512}, {96, 576}, {128, 1024}, {128, 512}};
+constexpr Variant kVar64[] = {{16, 64},  {32, 64},  {32, 128}, {32, 256}, {48, 192},
+                              {64, 256}, {64, 128}, {64, 512}, {96, 576}};
+constexpr int kNVar32 = sizeof(kVar32) / sizeof(kVar32[0]);
+constexpr int kNVar64 = sizeof(kVar64) / sizeof(kVar64[0]);
+
+template <typename T, int MODE>
+hipError_t dispatch(int N, int NT, int count, ProjArgs a, const int32_t *list,
+                    const int32_t *sizes, const int64_t *offsets, const T *in, T *out,
+                    double *lmin, int msw, double tol, hipStream_t st) {
+#define SDP_VARIANT(n, nt)                                                                     \
+  if (N == n && NT == nt)                                                                      \
+    return launch_one<T, n, nt, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
+  SDP_VARIANT(16, 64)
+  SDP_VARIANT(32, 64)
+  SDP_VARIANT(32, 128)
+  SDP_VARIANT(32, 256)
+  SDP_VARIANT(48, 192)
+  SDP_VARIANT(64, 128)
+  SDP_VARIANT(64, 256)
+  SDP_VARIANT(64, 512)
+  SDP_VARIANT(96, 576)
+  if constexpr (sizeof(T) == 4) {
+    SDP_VARIANT(128, 512)
+    SDP_VARIANT(128, 1024)
   }
+#undef SDP_VARIANT
+  return hipErrorInvalidValue;
 }
 
-template <int MODE>
-hipError_t dispatch_f64(int bucket, int count, ProjArgs a, const int32_t *list,
-                        const int32_t *sizes, const int64_t *offsets, const double *in,
-                        double *out, double *lmin, int msw, double tol, hipStream_t st) {
-  switch (bucket) {
-    case 16: return launch_one<double, 16, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 32: return launch_one<double, 32, 64, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 64: return launch_one<double, 64, 256, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    case 96: return launch_one<double, 96, 576, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-    default: return hipErrorInvalidValue;
-  }
+// Fills `count` symmetric s x s blocks (row-major, contiguous) with values in
+// (-1, 1) from a counter-based hash: synthetic inputs for the autotuner.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_blocks(T *out, int s, int count, uint32_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)count * s * s) return;
+  const int64_t blk = e / ((int64_t)s * s);
+  const int r = (int)(e % ((int64_t)s * s)) / s, c = (int)(e % ((int64_t)s * s)) % s;
+  const int i = r > c ? r : c, j = r > c ? c : r;
+  uint32_t x = seed ^ (uint32_t)(blk * 2654435761u) ^ (uint32_t)(i * 40503u + j * 2246822519u);
+  x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+  out[e] = (T)((double)x * (2.0 / 4294967296.0) - 1.0);
 }
 
 }  // namespace
 
-int projection_bucket(int precision, int s) {
+int projection_variant_count(int precision) { return precision == 1 ? kNVar32 : kNVar64; }
+
+void projection_variant_info(int precision, int v, int *N, int *NT) {
+  const Variant &x = precision == 1 ? kVar32[v] : kVar64[v];
+  *N = x.N;
+  *NT = x.NT;
+}
+
+int projection_default_variant(int precision, int s) {
   const int n = s + (s & 1);
-  if (n <= 16) return 16;
-  if (n <= 32) return 32;
-  if (n <= 64) return 64;
-  if (precision == 1) return n <= 128 ? 128 : 0;
-  return n <= 96 ? 96 : 0;
+  const int nv = projection_variant_count(precision);
+  int best = -1, bestN = 1 << 30;
+  for (int v = 0; v < nv; ++v) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (N >= n && N < bestN) {   // first listed NT of the smallest fitting N
+      best = v;
+      bestN = N;
+    }
+  }
+  return best;
+}
+
+hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
+                              hipStream_t st) {
+  const int64_t n = (int64_t)count * s * s;
+  const int nb = (int)((n + 255) / 256);
+  if (precision == 1)
+    hipLaunchKernelGGL(k_fill_blocks<float>, dim3(nb), dim3(256), 0, st, (float *)out, s, count, seed);
+  else
+    hipLaunchKernelGGL(k_fill_blocks<double>, dim3(nb), dim3(256), 0, st, (double *)out, s, count, seed);
+  return hipGetLastError();
+}
+
+
+int projection_bucket(int precision, int s) {
+  const int v = projection_default_variant(precision, s);
+  if (v < 0) return 0;
+  int N, NT;
+  projection_variant_info(precision, v, &N, &NT);
+  return N;
 }
 
 int projection_max_size(int precision) { return precision == 1 ? 128 : 96; }
 
-hipError_t launch_admm_projection(int precision, int bucket, const int32_t *list, int count,
+hipError_t launch_admm_projection(int precision, int variant, const int32_t *list, int count,
                                   const ProjArgs &a, hipStream_t st) {
+  int N, NT;
+  projection_variant_info(precision, variant, &N, &NT);
   if (precision == 1)
-    return dispatch_f32<MODE_ADMM>(bucket, count, a, list, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, a.max_sweeps, a.tol, st);
-  return dispatch_f64<MODE_ADMM>(bucket, count, a, list, nullptr, nullptr, nullptr, nullptr,
-                                 nullptr, a.max_sweeps, a.tol, st);
+    return dispatch<float, MODE_ADMM>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+                                      nullptr, a.max_sweeps, a.tol, st);
+  return dispatch<double, MODE_ADMM>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+                                     nullptr, a.max_sweeps, a.tol, st);
 }
 
-hipError_t launch_standalone_projection(int dtype, int bucket, int count, const int32_t *sizes,
+hipError_t launch_standalone_projection(int dtype, int variant, int count, const int32_t *sizes,
                                         const int64_t *offsets, const void *in, void *out,
                                         int max_sweeps, double tol, hipStream_t st) {
   ProjArgs a{};
+  int N, NT;
+  projection_variant_info(dtype, variant, &N, &NT);
   if (dtype == 1)
-    return dispatch_f32<MODE_STANDALONE>(bucket, count, a, nullptr, sizes, offsets,
-                                         (const float *)in, (float *)out, nullptr, max_sweeps,
-                                         tol, st);
-  return dispatch_f64<MODE_STANDALONE>(bucket, count, a, nullptr, sizes, offsets,
-                                       (const double *)in, (double *)out, nullptr, max_sweeps,
-                                       tol, st);
+    return dispatch<float, MODE_STANDALONE>(N, NT, count, a, nullptr, sizes, offsets,
+                                            (const float *)in, (float *)out, nullptr, max_sweeps,
+                                            tol, st);
+  return dispatch<double, MODE_STANDALONE>(N, NT, count, a, nullptr, sizes, offsets,
+                                           (const double *)in, (double *)out, nullptr,
+                                           max_sweeps, tol, st);
 }
 
-hipError_t launch_min_eig(int precision, int bucket, const int32_t *list, int count,
+hipError_t launch_min_eig(int precision, int variant, const int32_t *list, int count,
                           const ProjArgs &a, double *lmin_out, hipStream_t st) {
+  int N, NT;
+  projection_variant_info(precision, variant, &N, &NT);
   if (precision == 1)
-    return dispatch_f32<MODE_MINEIG>(bucket, count, a, list, nullptr, nullptr, nullptr, nullptr,
-                                     lmin_out, a.max_sweeps, a.tol, st);
-  return dispatch_f64<MODE_MINEIG>(bucket, count, a, list, nullptr, nullptr, nullptr, nullptr,
-                                   lmin_out, a.max_sweeps, a.tol, st);
+    return dispatch<float, MODE_MINEIG>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+                                        lmin_out, a.max_sweeps, a.tol, st);
+  return dispatch<double, MODE_MINEIG>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+                                       lmin_out, a.max_sweeps, a.tol, st);
 }

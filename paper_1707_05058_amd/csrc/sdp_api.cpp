@@ -11,8 +11,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 namespace {
@@ -163,6 +166,96 @@ T *dev_zeros(size_t count, std::vector<void *> &owned) {
   return p;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: for one clique size, time every kernel variant that fits on
+// synthetic symmetric blocks (min(count, 4096) of them, as many as the
+// projection will see) and keep the fastest.  Decisions are cached per
+// (precision, size, power-of-two count) for the life of the process.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol,
+                 hipStream_t st) {
+  const int n = s + (s & 1);
+  std::vector<int> cand;
+  for (int v = 0; v < projection_variant_count(precision); ++v) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (N >= n) cand.push_back(v);
+  }
+  if (cand.empty()) fail(SDP_ERR_UNSUPPORTED, "clique too large");
+  // variants beyond the next-larger block size are never faster
+  int nmin = 1 << 30;
+  for (int v : cand) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    nmin = std::min(nmin, N);
+  }
+  std::vector<int> keep;
+  for (int v : cand) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (N <= 2 * nmin) keep.push_back(v);
+  }
+  cand.swap(keep);
+  if (cand.size() == 1) return cand[0];
+  const int test = (int)std::min<int64_t>(count, 4096);
+  int lg = 0;
+  while ((1 << (lg + 1)) <= test) ++lg;
+  const auto key = std::make_tuple(precision, s, lg);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return it->second;
+  }
+  const size_t esz = precision == 1 ? sizeof(float) : sizeof(double);
+  std::vector<int32_t> sizes(test, s);
+  std::vector<int64_t> offs(test);
+  for (int i = 0; i < test; ++i) offs[i] = (int64_t)i * s * s;
+  std::vector<void *> tmp;
+  int best = cand[0];
+  try {
+    void *in = nullptr, *out = nullptr;
+    HIPCHK(hipMalloc(&in, esz * (size_t)test * s * s));
+    tmp.push_back(in);
+    HIPCHK(hipMalloc(&out, esz * (size_t)test * s * s));
+    tmp.push_back(out);
+    int32_t *d_sizes = dev_upload(sizes, tmp);
+    int64_t *d_offs = dev_upload(offs, tmp);
+    HIPCHK(fill_random_blocks(precision, in, s, test, 0x5eedu + (uint32_t)s, st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    for (int v : cand) {
+      HIPCHK(launch_standalone_projection(precision, v, test, d_sizes, d_offs, in, out, max_sweeps,
+                                          tol, st));
+      HIPCHK(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r)
+        HIPCHK(launch_standalone_projection(precision, v, test, d_sizes, d_offs, in, out,
+                                            max_sweeps, tol, st));
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  } catch (...) {
+    for (void *q : tmp) (void)hipFree(q);
+    throw;
+  }
+  for (void *q : tmp) (void)hipFree(q);
+  std::lock_guard<std::mutex> g(g_tune_mutex);
+  g_tune_cache[key] = best;
+  return best;
+}
+
 }  // namespace
 
 struct sdp_handle {
@@ -187,7 +280,9 @@ struct sdp_handle {
   double *h_obj = nullptr;               // pinned
   AffineArgs aff{};
   ProjArgs proj{};
-  std::vector<int> bucket_size;
+  std::vector<int> bucket_size;          // kernel variant of each launch list
+  std::vector<int> bucket_N;             // its padded block size
+  std::vector<int> clique_N;             // padded block size of every clique
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
   hipGraphExec_t graph = nullptr;
@@ -446,20 +541,39 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       }
       cl_first[batch] = k;
     }
-    // size buckets
+    // kernel variant per clique size (autotuned or default), one launch list
+    // per variant
     std::vector<std::vector<int32_t>> lists;
-    for (int64_t k = 0; k < cl; ++k) {
-      const int bs = projection_bucket(h->precision, cl_size[k]);
-      auto it = std::find(h->bucket_size.begin(), h->bucket_size.end(), bs);
-      size_t bi;
-      if (it == h->bucket_size.end()) {
-        h->bucket_size.push_back(bs);
-        lists.emplace_back();
-        bi = lists.size() - 1;
-      } else {
-        bi = it - h->bucket_size.begin();
+    {
+      std::map<int, int64_t> count_of_size;
+      for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
+      std::map<int, int> var_of_size;
+      for (auto &kv : count_of_size)
+        var_of_size[kv.first] = opt.autotune ? tune_variant(h->precision, kv.first, kv.second,
+                                                            h->max_sweeps, h->jac_tol, h->stream)
+                                             : projection_default_variant(h->precision, kv.first);
+      for (int64_t k = 0; k < cl; ++k) {
+        const int v = var_of_size[cl_size[k]];
+        auto it = std::find(h->bucket_size.begin(), h->bucket_size.end(), v);
+        size_t bi;
+        if (it == h->bucket_size.end()) {
+          h->bucket_size.push_back(v);
+          int N, NT;
+          projection_variant_info(h->precision, v, &N, &NT);
+          h->bucket_N.push_back(N);
+          lists.emplace_back();
+          bi = lists.size() - 1;
+        } else {
+          bi = it - h->bucket_size.begin();
+        }
+        lists[bi].push_back((int32_t)k);
       }
-      lists[bi].push_back((int32_t)k);
+      h->clique_N.resize(cl);
+      for (int64_t k = 0; k < cl; ++k) {
+        int N, NT;
+        projection_variant_info(h->precision, var_of_size[cl_size[k]], &N, &NT);
+        h->clique_N[k] = N;
+      }
     }
     // ---- row-space arrays ----
     std::vector<double> b(row, 0.0);
@@ -647,7 +761,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       int64_t eo = 0;
       h->adj_ready = true;
       for (int64_t k = 0; k < cl; ++k) {
-        const int nb = projection_bucket(h->precision, cl_size[k]);
+        const int nb = h->clique_N[k];
         if (nb > adjoint_max_bucket()) h->adj_ready = false;
         eoff[k] = eo;
         eo += (int64_t)cl_size[k] * nb + nb;
@@ -746,6 +860,7 @@ void sdp_default_options(sdp_options *opt) {
   opt->stream = nullptr;
   opt->jacobi_max_sweeps = 0;
   opt->jacobi_tol = 0.0;
+  opt->autotune = 1;
 }
 
 int sdp_setup(int32_t batch, const sdp_instance *inst, const sdp_options *opt, sdp_handle **out) {
@@ -801,22 +916,64 @@ int sdp_solve(sdp_handle *h, sdp_result *res) {
   });
 }
 
+namespace {
+int project_blocks(int variant, int32_t count, int32_t max_size, const int32_t *sizes,
+                   const int64_t *offsets, const void *in, void *out, int32_t dtype,
+                   void *stream) {
+  if (count < 0 || (count > 0 && (!sizes || !offsets || !in || !out)))
+    fail(SDP_ERR_ARG, "invalid arguments");
+  if (dtype != SDP_DTYPE_FP64 && dtype != SDP_DTYPE_FP32) fail(SDP_ERR_ARG, "invalid dtype");
+  const int prec = dtype == SDP_DTYPE_FP32 ? 1 : 0;
+  if (max_size <= 0 || max_size > projection_max_size(prec))
+    fail(SDP_ERR_UNSUPPORTED, "max_size out of range for this dtype");
+  if (variant < 0) {
+    variant = projection_default_variant(prec, max_size);
+  } else {
+    if (variant >= projection_variant_count(prec)) fail(SDP_ERR_ARG, "no such kernel variant");
+    int N, NT;
+    projection_variant_info(prec, variant, &N, &NT);
+    if (max_size > N) fail(SDP_ERR_ARG, "max_size exceeds the variant's block size");
+  }
+  if (count == 0) return SDP_OK;
+  const int msw = prec ? 30 : 40;
+  const double tol = prec ? 1e-6 : 1e-14;
+  HIPCHK(launch_standalone_projection(prec, variant, count, sizes, offsets, in, out, msw, tol,
+                                      (hipStream_t)stream));
+  return SDP_OK;
+}
+}  // namespace
+
 int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *sizes,
                             const int64_t *offsets, const void *in, void *out, int32_t dtype,
                             void *stream) {
   return guarded([&] {
-    if (count < 0 || (count > 0 && (!sizes || !offsets || !in || !out)))
-      fail(SDP_ERR_ARG, "invalid arguments");
+    return project_blocks(-1, count, max_size, sizes, offsets, in, out, dtype, stream);
+  });
+}
+
+int sdp_psd_project_variant(int32_t variant, int32_t count, int32_t max_size,
+                            const int32_t *sizes, const int64_t *offsets, const void *in,
+                            void *out, int32_t dtype, void *stream) {
+  return guarded([&] {
+    if (variant < 0) fail(SDP_ERR_ARG, "no such kernel variant");
+    return project_blocks(variant, count, max_size, sizes, offsets, in, out, dtype, stream);
+  });
+}
+
+int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_t *threads,
+                            int32_t *count) {
+  return guarded([&] {
     if (dtype != SDP_DTYPE_FP64 && dtype != SDP_DTYPE_FP32) fail(SDP_ERR_ARG, "invalid dtype");
+    if (cap < 0 || !count) fail(SDP_ERR_ARG, "invalid arguments");
     const int prec = dtype == SDP_DTYPE_FP32 ? 1 : 0;
-    if (max_size <= 0 || max_size > projection_max_size(prec))
-      fail(SDP_ERR_UNSUPPORTED, "max_size out of range for this dtype");
-    if (count == 0) return SDP_OK;
-    const int bucket = projection_bucket(prec, max_size);
-    const int msw = prec ? 30 : 40;
-    const double tol = prec ? 1e-6 : 1e-14;
-    HIPCHK(launch_standalone_projection(prec, bucket, count, sizes, offsets, in, out, msw, tol,
-                                        (hipStream_t)stream));
+    const int nv = projection_variant_count(prec);
+    for (int v = 0; v < nv && v < cap; ++v) {
+      int N, NT;
+      projection_variant_info(prec, v, &N, &NT);
+      if (block_n) block_n[v] = N;
+      if (threads) threads[v] = NT;
+    }
+    *count = nv;
     return SDP_OK;
   });
 }
@@ -913,6 +1070,23 @@ int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections) {
     }
     if (jacobi_sweeps) *jacobi_sweeps = sw;
     if (projections) *projections = pr;
+    return SDP_OK;
+  });
+}
+
+int sdp_projection_plan(sdp_handle *h, int32_t cap, int32_t *block_n, int32_t *threads,
+                        int32_t *cliques, int32_t *count) {
+  return guarded([&] {
+    if (!h || cap < 0 || !count) fail(SDP_ERR_ARG, "invalid arguments");
+    const int nl = (int)h->bucket_size.size();
+    for (int b = 0; b < nl && b < cap; ++b) {
+      int N, NT;
+      projection_variant_info(h->precision, h->bucket_size[b], &N, &NT);
+      if (block_n) block_n[b] = N;
+      if (threads) threads[b] = NT;
+      if (cliques) cliques[b] = h->bucket_count[b];
+    }
+    *count = nl;
     return SDP_OK;
   });
 }
@@ -1098,7 +1272,7 @@ int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, in
         g.eig = (const char *)h->d_eigbuf + esz * (size_t)(t - t0) * h->eig_total;
         g.seed = (t == T - 1) ? u_bar : nullptr;
         for (size_t b = 0; b < h->bucket_size.size(); ++b)
-          HIPCHK(launch_adj_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+          HIPCHK(launch_adj_projection(h->precision, h->bucket_N[b], h->bucket_list[b],
                                        h->bucket_count[b], g, h->stream));
         HIPCHK(launch_adj_scatter(g, h->stream));
         for (int stg = 1; stg <= 4; ++stg) HIPCHK(launch_affine_stage(ra, stg, h->stream));

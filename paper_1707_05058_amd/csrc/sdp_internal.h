@@ -75,22 +75,29 @@ struct ProjArgs {
   const int64_t *eig_off; // element offset of each clique's record in eig
 };
 
-// Launch the ADMM projection for the cliques in `list` (all of one size
-// bucket `bucket_size`).  precision: 0 = FP64, 1 = FP32.
-hipError_t launch_admm_projection(int precision, int bucket_size, const int32_t *list,
+// Kernel variants (padded size N, threads NT): ids are per precision.
+int projection_variant_count(int precision);
+void projection_variant_info(int precision, int variant, int *N, int *NT);
+int projection_default_variant(int precision, int s);   // -1 if s is too large
+hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
+                              hipStream_t st);
+
+// Launch the ADMM projection for the cliques in `list` (all handled by one
+// kernel variant).  precision: 0 = FP64, 1 = FP32.
+hipError_t launch_admm_projection(int precision, int variant, const int32_t *list,
                                   int count, const ProjArgs &a, hipStream_t st);
 
 // Standalone batched projection of full row-major blocks.
-hipError_t launch_standalone_projection(int dtype, int bucket_size, int count,
+hipError_t launch_standalone_projection(int dtype, int variant, int count,
                                         const int32_t *sizes, const int64_t *offsets,
                                         const void *in, void *out, int max_sweeps,
                                         double tol, hipStream_t st);
 
 // Minimum eigenvalue of each E_k U E_k^T (for eps_alpha); FP64.
-hipError_t launch_min_eig(int precision, int bucket_size, const int32_t *list, int count,
+hipError_t launch_min_eig(int precision, int variant, const int32_t *list, int count,
                           const ProjArgs &a, double *lmin_out, hipStream_t st);
 
-int projection_bucket(int precision, int s);   // 0 if unsupported
+int projection_bucket(int precision, int s);   // N of the default variant, 0 if unsupported
 int projection_max_size(int precision);
 
 // ----------------------------------------------------------------------------
@@ -208,7 +215,7 @@ struct AdjArgs {
   int batch;
 };
 
-hipError_t launch_adj_projection(int precision, int bucket, const int32_t *list, int count,
+hipError_t launch_adj_projection(int precision, int N, const int32_t *list, int count,
                                  const AdjArgs &a, hipStream_t st);
 hipError_t launch_adj_scatter(const AdjArgs &a, hipStream_t st);
 hipError_t launch_adj_coord_and_gather(const AdjArgs &a, hipStream_t st);

@@ -95,6 +95,18 @@ def test_projection_argument_checks(sdp):
     assert lib.sdp_psd_project_batched(0, 16, None, None, None, None, 5, None) == -1
     assert lib.sdp_psd_project_batched(0, 129, None, None, None, None, 1, None) == -7
     assert lib.sdp_psd_project_batched(0, 97, None, None, None, None, 0, None) == -7
+    # explicit variants: index range, block size that must hold max_size
+    v32 = sdp.projection_variants(sdp.DTYPE_FP32)
+    v64 = sdp.projection_variants(sdp.DTYPE_FP64)
+    assert max(n for n, _ in v32) == 128 and max(n for n, _ in v64) == 96
+    for n, nt in v32 + v64:
+        assert n % 16 == 0 and nt % 64 == 0 and (n // 2) ** 2 % nt == 0
+    assert lib.sdp_psd_project_variant(-1, 0, 16, None, None, None, None, 1, None) == -1
+    assert lib.sdp_psd_project_variant(len(v32), 0, 16, None, None, None, None, 1, None) == -1
+    small = [i for i, (n, _) in enumerate(v32) if n == 16][0]
+    assert lib.sdp_psd_project_variant(small, 0, 16, None, None, None, None, 1, None) == 0
+    assert lib.sdp_psd_project_variant(small, 0, 17, None, None, None, None, 1, None) == -1
+    assert lib.sdp_projection_variants(7, 0, None, None, None) == -1
 
 
 def test_null_handle_is_rejected(sdp):

@@ -230,3 +230,24 @@ def test_batched_workload_shapes_fixed_n_fp64(sdp, gpu, oracle_mod):
         log(f"  {inst.name}: {errs}")
         for k, v in errs.items():
             assert v <= 1e-8, (inst.name, k, v)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuned_plan_covers_every_clique_and_matches_default(sdp, gpu, precision):
+    """The launch plan (autotuned or default) holds every clique once, in a
+    block size that fits it; both plans give the same iterates up to rounding."""
+    insts = [sdpgen.uneven_block_arrow_instance(s, l_range=(2, 6), d_range=(3, 40),
+                                                h_range=(1, 8)) for s in range(4)]
+    sizes = np.concatenate([np.diff(i.clique_ptr) for i in insts])
+    res = {}
+    for tune in (0, 1):
+        with sdp.Solver(insts, tol=0.0, max_iter=1000, precision=precision,
+                        autotune=tune) as S:
+            plan = S.projection_plan()
+            log(f"autotune={tune} plan={plan}")
+            assert sum(c for _, _, c in plan) == len(sizes)
+            assert min(N for N, _, _ in plan) >= 16
+            S.step(12)
+            res[tune] = np.concatenate([S.solution(i)["u"] for i in range(len(insts))])
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert rel_err(res[1], res[0]) <= tol

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 TOL = {np.float64: 1e-11, np.float32: 3e-5}
 
 
-def run_gpu(sdp, blocks, dtype, max_size):
+def run_gpu(sdp, blocks, dtype, max_size, variant=None):
     import torch
     tdt = torch.float64 if dtype == np.float64 else torch.float32
     sizes = np.array([b.shape[0] for b in blocks], dtype=np.int32)
@@ -26,7 +26,7 @@ def run_gpu(sdp, blocks, dtype, max_size):
     t_in = torch.from_numpy(flat).to(dev)
     t_out = torch.full_like(t_in, float("nan"))
     sdp.psd_project_batched(torch.from_numpy(sizes).to(dev), torch.from_numpy(offs).to(dev),
-                            t_in, t_out, max_size)
+                            t_in, t_out, max_size, variant=variant)
     torch.cuda.synchronize()
     out = t_out.cpu().numpy().astype(np.float64)
     return [out[o:o + s * s].reshape(s, s) for o, s in zip(offs, sizes)]
@@ -61,6 +61,22 @@ def test_projection_matches_oracle_goe(sdp, gpu, oracle_mod, dtype, sizes, max_s
     blocks = sdpgen.goe_blocks(sizes, seed=max_size)
     outs = run_gpu(sdp, blocks, dtype, max_size)
     check(oracle_mod, blocks, outs, dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_every_kernel_variant_matches_oracle(sdp, gpu, oracle_mod, dtype):
+    """Each (block size N, threads) variant the autotuner may pick, on sizes
+    from the smallest that needs it to N, against the oracle."""
+    dt = sdp.DTYPE_FP32 if dtype == np.float32 else sdp.DTYPE_FP64
+    variants = sdp.projection_variants(dt)
+    Ns = sorted({n for n, _ in variants})
+    for v, (N, NT) in enumerate(variants):
+        lo = max([n for n in Ns if n < N], default=0) + 1
+        sizes = sorted({lo, (lo + N) // 2, N - 1, N}) + [1, 2]
+        print(f"variant {v}: N={N} NT={NT} sizes={sizes}", flush=True)
+        blocks = sdpgen.goe_blocks(sizes, seed=1000 + v)
+        outs = run_gpu(sdp, blocks, dtype, N, variant=v)
+        check(oracle_mod, blocks, outs, dtype)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
