@@ -94,6 +94,9 @@ typedef struct {
   int32_t autotune;             /* 1: time the projection kernel variants per clique size
                                    at setup and keep the fastest (cached per process);
                                    0: smallest fitting block size */
+  int32_t warm_start;           /* 1: each clique's eigen-solve starts from the eigenvector
+                                   basis it ended with in the previous iteration (kept
+                                   orthonormal on the device); 0: from the identity */
 } sdp_options;
 
 /* Per-instance result. */
@@ -109,7 +112,7 @@ typedef struct {
 
 /* Fills *opt with defaults: rho 1, tol 1e-4, max_iter 20000, SDP_FP64,
  * adaptive off, mu 2, nu 10, rho_period 1, graph_chunk 25, own stream,
- * autotune on. */
+ * autotune on, warm_start on. */
 void sdp_default_options(sdp_options *opt);
 
 /* Validates `batch` instances, copies them to the device, builds the clique

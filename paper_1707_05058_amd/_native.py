@@ -54,7 +54,7 @@ class sdp_options(C.Structure):
                 ("precision", C.c_int32), ("adaptive_rho", C.c_int32), ("mu", C.c_double),
                 ("nu", C.c_double), ("rho_period", C.c_int32), ("graph_chunk", C.c_int32),
                 ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("warm_start", C.c_int32)]
 
 
 class sdp_result(C.Structure):

@@ -162,6 +162,84 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
   const double thr = tol * tol * block_sum<NT>(f2, red);
 
+  // --- warm start: rotate W into the basis V0 the clique ended with last
+  // iteration, A = V0^T W V0 (symmetrised), and let the rotations accumulate
+  // onto V0.  The basis is orthonormal to rounding (re-orthonormalised when
+  // it is stored), so A has the eigenvalues of W and is nearly diagonal once
+  // the iteration settles: one or two sweeps instead of five or more. ---
+  T *vw = nullptr;
+  if (MODE == MODE_ADMM && a.vw) {
+    vw = reinterpret_cast<T *>(a.vw) + a.vw_off[cl];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = A[j][d][e];
+    }
+    for (int e = tid; e < N * N; e += NT) Vbuf[(e / N) * P + (e % N)] = vw[e];
+    __syncthreads();
+    // V regs <- W V0 (my blocks)
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int r0 = 2 * (a0 + AS * j);
+      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll 4
+      for (int k = 0; k < N; ++k) {
+        const T w0 = Abuf[r0 * P + k], w1 = Abuf[(r0 + 1) * P + k];
+        const T v0 = Vbuf[k * P + 2 * b], v1 = Vbuf[k * P + 2 * b + 1];
+        c00 += w0 * v0; c01 += w0 * v1; c10 += w1 * v0; c11 += w1 * v1;
+      }
+      V[j][0][0] = c00; V[j][0][1] = c01; V[j][1][0] = c10; V[j][1][1] = c11;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = V[j][d][e];
+    }
+    __syncthreads();
+    // A regs <- V0^T (W V0)
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int r0 = 2 * (a0 + AS * j);
+      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll 4
+      for (int k = 0; k < N; ++k) {
+        const T v0 = Vbuf[k * P + r0], v1 = Vbuf[k * P + r0 + 1];
+        const T t0 = Abuf[k * P + 2 * b], t1 = Abuf[k * P + 2 * b + 1];
+        c00 += v0 * t0; c01 += v0 * t1; c10 += v1 * t0; c11 += v1 * t1;
+      }
+      A[j][0][0] = c00; A[j][0][1] = c01; A[j][1][0] = c10; A[j][1][1] = c11;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = A[j][d][e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int r = 2 * aj + d, c = 2 * b + e;
+          A[j][d][e] = T(0.5) * (Abuf[r * P + c] + Abuf[c * P + r]);
+          V[j][d][e] = Vbuf[r * P + c];
+        }
+    }
+  }
+
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     double o2 = 0.0;
@@ -281,6 +359,48 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
   for (int k = tid; k < N; k += NT) thp[k] = th[k] > T(0) ? th[k] : T(0);
   __syncthreads();
+  if (MODE == MODE_ADMM && vw) {
+    // store the basis for the next iteration after one Newton-Schulz step,
+    // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int r0 = 2 * (a0 + AS * j);
+      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll 4
+      for (int k = 0; k < N; ++k) {
+        const T x0 = Vbuf[k * P + r0], x1 = Vbuf[k * P + r0 + 1];
+        const T y0 = Vbuf[k * P + 2 * b], y1 = Vbuf[k * P + 2 * b + 1];
+        c00 += x0 * y0; c01 += x0 * y1; c10 += x1 * y0; c11 += x1 * y1;
+      }
+      A[j][0][0] = c00; A[j][0][1] = c01; A[j][1][0] = c10; A[j][1][1] = c11;
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = A[j][d][e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int r0 = 2 * (a0 + AS * j);
+      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll 4
+      for (int k = 0; k < N; ++k) {
+        const T x0 = Vbuf[r0 * P + k], x1 = Vbuf[(r0 + 1) * P + k];
+        const T g0 = Abuf[k * P + 2 * b], g1 = Abuf[k * P + 2 * b + 1];
+        c00 += x0 * g0; c01 += x0 * g1; c10 += x1 * g0; c11 += x1 * g1;
+      }
+      T *row0 = vw + (int64_t)r0 * N + 2 * b;
+      T *row1 = row0 + N;
+      row0[0] = T(1.5) * V[j][0][0] - T(0.5) * c00;
+      row0[1] = T(1.5) * V[j][0][1] - T(0.5) * c01;
+      row1[0] = T(1.5) * V[j][1][0] - T(0.5) * c10;
+      row1[1] = T(1.5) * V[j][1][1] - T(0.5) * c11;
+    }
+  }
   if (MODE == MODE_ADMM && a.eig) {
     // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep
     T *eo = reinterpret_cast<T *>(a.eig) + a.eig_off[cl];
@@ -391,7 +511,28 @@ __global__ __launch_bounds__(256) void k_fill_blocks(T *out, int s, int count, u
   out[e] = (T)((double)x * (2.0 / 4294967296.0) - 1.0);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_identity_bases(T *vw, const int64_t *vw_off,
+                                                        const int32_t *cl_n, int64_t c0) {
+  const int64_t cl = c0 + blockIdx.x;
+  const int n = cl_n[cl];
+  T *v = vw + vw_off[cl];
+  for (int e = threadIdx.x; e < n * n; e += 256) v[e] = (e / n == e % n) ? T(1) : T(0);
+}
+
 }  // namespace
+
+hipError_t launch_identity_bases(int precision, void *vw, const int64_t *vw_off,
+                                 const int32_t *cl_n, int64_t c0, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_identity_bases<float>, dim3((unsigned)count), dim3(256), 0, st,
+                       (float *)vw, vw_off, cl_n, c0);
+  else
+    hipLaunchKernelGGL(k_identity_bases<double>, dim3((unsigned)count), dim3(256), 0, st,
+                       (double *)vw, vw_off, cl_n, c0);
+  return hipGetLastError();
+}
 
 int projection_variant_count(int precision) { return precision == 1 ? kNVar32 : kNVar64; }
 

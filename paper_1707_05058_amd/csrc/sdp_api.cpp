@@ -283,6 +283,10 @@ struct sdp_handle {
   std::vector<int> bucket_size;          // kernel variant of each launch list
   std::vector<int> bucket_N;             // its padded block size
   std::vector<int> clique_N;             // padded block size of every clique
+  std::vector<int64_t> cl_first;         // per instance, first global clique (B + 1)
+  int32_t *d_clique_N = nullptr;
+  int64_t *d_vw_off = nullptr;
+  void *d_vw = nullptr;                  // warm-start bases (precision of the eigen-solve)
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
   hipGraphExec_t graph = nullptr;
@@ -329,6 +333,7 @@ void enqueue_unrolled_iteration(sdp_handle *h, hipStream_t st, void *eig) {
   ProjArgs p = h->proj;
   p.eig = eig;
   p.eig_off = h->d_eig_off;
+  p.vw = nullptr;          // the reverse sweep recomputes segments: no cross-iteration state
   HIPCHK(launch_iteration_affine(a, st));
   for (size_t b = 0; b < h->bucket_size.size(); ++b)
     HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
@@ -409,6 +414,11 @@ void reset_state(sdp_handle *h) {
   HIPCHK(hipMemset(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
   HIPCHK(hipMemset(h->aff.u, 0, sizeof(double) * h->ncoord));
   HIPCHK(hipMemset(h->aff.y, 0, sizeof(double) * h->nrow));
+  if (h->d_vw) {
+    HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N, 0, h->ncl,
+                                 h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
   h->have_diag = false;
   h->iters_enqueued = 0;
 }
@@ -739,6 +749,22 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       h->bucket_list.push_back(dev_upload(l, own));
       h->bucket_count.push_back((int)l.size());
     }
+    h->cl_first = cl_first;
+    h->d_clique_N = dev_upload(h->clique_N, own);
+    if (opt.warm_start) {
+      std::vector<int64_t> voff(cl);
+      int64_t vo = 0;
+      for (int64_t k = 0; k < cl; ++k) {
+        voff[k] = vo;
+        vo += (int64_t)h->clique_N[k] * h->clique_N[k];
+      }
+      h->d_vw_off = dev_upload(voff, own);
+      const size_t esz = h->precision == SDP_FP32_EIG ? sizeof(float) : sizeof(double);
+      HIPCHK(hipMalloc(&h->d_vw, esz * (size_t)std::max<int64_t>(vo, 1)));
+      own.push_back(h->d_vw);
+      p.vw = h->d_vw;
+      p.vw_off = h->d_vw_off;
+    }
     h->d_diag = dev_zeros<double>((size_t)4 * batch, own);
     // caller layout of per-instance vectors, row -> instance map, and the
     // (V, theta) record offsets used by the reverse sweep
@@ -861,6 +887,7 @@ void sdp_default_options(sdp_options *opt) {
   opt->jacobi_max_sweeps = 0;
   opt->jacobi_tol = 0.0;
   opt->autotune = 1;
+  opt->warm_start = 1;
 }
 
 int sdp_setup(int32_t batch, const sdp_instance *inst, const sdp_options *opt, sdp_handle **out) {
@@ -1005,6 +1032,12 @@ int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *L
     const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
     if (Xk) HIPCHK(hipMemcpy(h->proj.X + o, Xk, sizeof(double) * n, hipMemcpyHostToDevice));
     if (Lk) HIPCHK(hipMemcpy(h->proj.Lam + o, Lk, sizeof(double) * n, hipMemcpyHostToDevice));
+    if (h->d_vw) {
+      HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N,
+                                   h->cl_first[inst], h->cl_first[inst + 1] - h->cl_first[inst],
+                                   h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
     pull_state(h);
     InstState s = h->h_state[inst];
     s.rho = rho;

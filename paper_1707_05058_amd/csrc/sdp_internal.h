@@ -73,6 +73,8 @@ struct ProjArgs {
   double tol;
   void *eig;              // optional: per clique V (s x N) then theta (N), precision T
   const int64_t *eig_off; // element offset of each clique's record in eig
+  void *vw;               // optional: per clique N x N eigenvector basis (warm start), T
+  const int64_t *vw_off;  // element offset of each clique's basis in vw
 };
 
 // Kernel variants (padded size N, threads NT): ids are per precision.
@@ -81,6 +83,9 @@ void projection_variant_info(int precision, int variant, int *N, int *NT);
 int projection_default_variant(int precision, int s);   // -1 if s is too large
 hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
                               hipStream_t st);
+// Sets the warm-start bases of cliques [c0, c0 + count) to the identity.
+hipError_t launch_identity_bases(int precision, void *vw, const int64_t *vw_off,
+                                 const int32_t *cl_n, int64_t c0, int64_t count, hipStream_t st);
 
 // Launch the ADMM projection for the cliques in `list` (all handled by one
 // kernel variant).  precision: 0 = FP64, 1 = FP32.

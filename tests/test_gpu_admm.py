@@ -251,3 +251,24 @@ def test_autotuned_plan_covers_every_clique_and_matches_default(sdp, gpu, precis
             res[tune] = np.concatenate([S.solution(i)["u"] for i in range(len(insts))])
     tol = 1e-9 if precision == "fp64" else 1e-4
     assert rel_err(res[1], res[0]) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_warm_started_eigensolves_match_cold_and_take_fewer_sweeps(sdp, gpu, oracle_mod,
+                                                                   precision, tol):
+    """Starting each clique's Jacobi from last iteration's basis computes the
+    same projection (fixed-N parity against the oracle) with fewer sweeps."""
+    inst = sdpgen.workload_small_blockarrow()
+    P = oracle_mod.Problem(inst)
+    P.run(60, tol=0.0)
+    sweeps = {}
+    for warm in (0, 1):
+        with sdp.Solver([inst], tol=0.0, max_iter=1000, precision=precision,
+                        warm_start=warm) as S:
+            S.step(60)
+            u = S.solution(0)["u"]
+            st = S.stats()
+            sweeps[warm] = st["jacobi_sweeps"] / st["projections"]
+        assert rel_err(u, P.u()) <= tol, (warm, rel_err(u, P.u()))
+    log(f"sweeps per projection: cold {sweeps[0]:.2f} warm {sweeps[1]:.2f}")
+    assert sweeps[1] < 0.8 * sweeps[0]
