@@ -6,6 +6,10 @@
 //   r    = A (w bhat / D) - b                                   (k_rowdot)
 //   y    = L^-T (L^-1 r)   with L^-1, L^-T cached               (k_trmv_wave)
 //   u    = (bhat - A^T y) / D                                   (k_coldot)
+// For dense A the forward substitution is folded into B = L^-1 A at setup:
+//   y1   = B (w bhat / D) - L^-1 b                              (k_rowdot)
+//   u    = (bhat - B^T y1) / D       (A^T y = A^T L^-T y1)      (k_coldot)
+// and y = L^-T y1 is formed only when the multiplier is asked for.
 // plus the per-instance residual reduction, stopping test and adaptive
 // penalty (k_residual_reduce).  Every kernel reads the instance's `done`
 // flag first, so a converged instance is frozen at its stopping iterate.
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
   if (!a.ignore_done && a.state[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int nrow = min(R, d.m - row0);
-  const double *mat = a.A + d.a_off + (int64_t)row0 * d.ld;
+  const double *mat = (a.Bm ? a.Bm : a.A) + d.a_off + (int64_t)row0 * d.ld;
   const double2 *v2 = reinterpret_cast<const double2 *>(a.v + d.coord_off);
   double acc[R];
 #pragma unroll
@@ -105,7 +109,9 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < ROW_NT / 64; ++i) s += red[i][r];
-    a.r[d.row_off + row0 + r] = s - a.b[d.row_off + row0 + r];
+    const int64_t g = d.row_off + row0 + r;
+    if (a.Bm) a.y1[g] = s - a.bp[g];
+    else a.r[g] = s - a.b[g];
   }
 }
 
@@ -124,10 +130,10 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
   const InstDesc d = a.inst[inst];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = col0 + 2 * l;
-  const double *vec = a.y + d.row_off;
+  const double *vec = (a.Bm ? a.y1 : a.y) + d.row_off;
   double ax = 0.0, ay = 0.0;
   if (col < d.ld) {
-    const double *base = a.A + d.a_off + col;
+    const double *base = (a.Bm ? a.Bm : a.A) + d.a_off + col;
 #pragma unroll 4
     for (int i = w; i < d.m; i += 4) {
       const double2 m2 = *reinterpret_cast<const double2 *>(base + (int64_t)i * d.ld);
@@ -166,8 +172,9 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
 template <int UPPER>
 __global__ __launch_bounds__(256) void k_trmv_wave(AffineArgs a) {
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wid >= a.n_t_rows) return;
-  const int inst = a.t_rows[2 * wid], row = a.t_rows[2 * wid + 1];
+  const int32_t *rows = UPPER ? a.t3_rows : a.t_rows;
+  if (wid >= (UPPER ? a.n_t3_rows : a.n_t_rows)) return;
+  const int inst = rows[2 * wid], row = rows[2 * wid + 1];
   if (!a.ignore_done && a.state[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int l = threadIdx.x & 63;
@@ -377,7 +384,9 @@ __global__ __launch_bounds__(256) void k_scaled_copy(const double *src, double *
 }  // namespace
 
 // Stages of the X-step, launched in this order every iteration:
-//   0 scatter (bhat, v)   1 A v - b   2 T r   3 T^T y1   4 (bhat - A^T y)/D
+//   0 scatter (bhat, v)   1 A v - b (B v - T b)   2 T r   3 T^T y1   4 (bhat - A^T y)/D
+// Stages 2 and 3 run over the rows in t_rows / t3_rows only (with B formed,
+// the rows of sparse instances; 3 over all rows when the multiplier is needed).
 hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
   switch (stage) {
     case 0: {
@@ -398,10 +407,12 @@ hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
         hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 2:
-      hipLaunchKernelGGL(k_trmv_wave<0>, dim3((a.n_t_rows + 3) / 4), dim3(256), 0, st, a);
+      if (a.n_t_rows > 0)
+        hipLaunchKernelGGL(k_trmv_wave<0>, dim3((a.n_t_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 3:
-      hipLaunchKernelGGL(k_trmv_wave<1>, dim3((a.n_t_rows + 3) / 4), dim3(256), 0, st, a);
+      if (a.n_t3_rows > 0)
+        hipLaunchKernelGGL(k_trmv_wave<1>, dim3((a.n_t3_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 4:
       if (a.n_col_tiles > 0)
@@ -441,6 +452,7 @@ hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const 
                               int64_t nrow, double *out, hipStream_t st) {
   AffineArgs a = a0;
   a.ignore_done = 1;
+  a.Bm = nullptr;             // residuals of the original data
   const int nb = (int)((a.ncoord + 255) / 256);
   hipLaunchKernelGGL(k_diag_coord, dim3(nb), dim3(256), 0, st, a, s);
   hipLaunchKernelGGL(k_diag_rows, dim3((nrow + 255) / 256), dim3(256), 0, st, a, s, nrow);

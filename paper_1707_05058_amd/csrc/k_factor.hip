@@ -5,6 +5,9 @@
 //                        applies y = T^T (T r), i.e. the forward and backward
 //                        substitutions with the cached factor, as two
 //                        bandwidth-bound triangular mat-vecs)
+//   B = T A             (dense A only: the forward substitution folded into
+//                        A, so the iteration needs y1 = B v - T b and
+//                        u = (bhat - B^T y1) / D: two passes, no substitution)
 // Every instance's M lives at t_off with pitch ldm (m rounded up to 64); the
 // padding is the identity, so all blocks are full 64 x 64 tiles.
 #include "sdp_internal.h"
@@ -327,6 +330,47 @@ hipError_t launch_syrk_csr(const FactorArgs &f, const int32_t *rows, int nrows, 
   if (nrows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_syrk_csr, dim3(nrows), dim3(64), (size_t)max_ldm * sizeof(double), st, f,
                      rows);
+  return hipGetLastError();
+}
+
+namespace {
+// B = T A for one 64 x 64 tile of one dense instance (rows < m are stored;
+// T is lower triangular, so the k-loop stops at the tile's last row).
+__global__ __launch_bounds__(256) void k_form_b(FactorArgs f, const int32_t *tiles) {
+  const int inst = tiles[3 * blockIdx.x], ti = tiles[3 * blockIdx.x + 1],
+            tj = tiles[3 * blockIdx.x + 2];
+  const InstDesc d = f.inst[inst];
+  const int i0 = ti * NB, j0 = tj * NB;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ double st[NB][LP], sa[NB][LP];
+  double acc[4][4] = {};
+  const double *T = f.T + d.t_off;
+  const double *A = f.A + d.a_off;
+  const int kend = min(i0 + NB, d.m);
+  for (int k0 = 0; k0 < kend; k0 += NB) {
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      st[r][c] = T[(int64_t)(i0 + r) * d.ldm + k0 + c];
+      sa[r][c] = (k0 + r < d.m) ? A[(int64_t)(k0 + r) * d.ld + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    mm_ab(st, sa, acc, tx, ty);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = i0 + ty * 4 + a;
+    if (row < d.m) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) f.Bout[d.a_off + (int64_t)row * d.ld + j0 + tx * 4 + b] = acc[a][b];
+    }
+  }
+}
+}  // namespace
+
+hipError_t launch_form_b(const FactorArgs &f, const int32_t *tiles, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_form_b, dim3(ntiles), dim3(256), 0, st, f, tiles);
   return hipGetLastError();
 }
 

@@ -287,6 +287,9 @@ struct sdp_handle {
   int32_t *d_clique_N = nullptr;
   int64_t *d_vw_off = nullptr;
   void *d_vw = nullptr;                  // warm-start bases (precision of the eigen-solve)
+  int32_t *d_t_rows_all = nullptr;       // (inst, row) over every row
+  int n_t_rows_all = 0;
+  double *d_ytmp = nullptr;              // row-space scratch for the scaled multiplier
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
   hipGraphExec_t graph = nullptr;
@@ -339,6 +342,27 @@ void enqueue_unrolled_iteration(sdp_handle *h, hipStream_t st, void *eig) {
     HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
                                   h->bucket_count[b], p, st));
   HIPCHK(launch_residual_reduce(a, st));
+}
+
+// y = L^-T y1 for every row (with B = L^-1 A formed, the iteration keeps only y1).
+void ensure_y(sdp_handle *h) {
+  AffineArgs a = h->aff;
+  a.t3_rows = h->d_t_rows_all;
+  a.n_t3_rows = h->n_t_rows_all;
+  a.ignore_done = 1;
+  HIPCHK(launch_affine_stage(a, 3, h->stream));
+}
+
+// bp = L^-1 b (needed with B = L^-1 A)
+void compute_bp(sdp_handle *h) {
+  if (!h->aff.Bm) return;
+  AffineArgs a = h->aff;
+  a.r = const_cast<double *>(h->aff.b);
+  a.y1 = const_cast<double *>(h->aff.bp);
+  a.t_rows = h->d_t_rows_all;
+  a.n_t_rows = h->n_t_rows_all;
+  a.ignore_done = 1;
+  HIPCHK(launch_affine_stage(a, 2, h->stream));
 }
 
 void build_graph(sdp_handle *h) {
@@ -602,10 +626,17 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     const int R = pick_r(dense_rows);
     const int CW = affine_col_tile_width();
     std::vector<int32_t> row_tiles, col_tiles, t_rows, csr_rows, csc_cols, syrk_tiles, syrk_rows;
+    std::vector<int32_t> t_rows_all, b_tiles;
     for (int i = 0; i < batch; ++i) {
       const HostInst &hi = H[i];
-      for (int r = 0; r < hi.m; ++r) { t_rows.push_back(i); t_rows.push_back(r); }
+      for (int r = 0; r < hi.m; ++r) { t_rows_all.push_back(i); t_rows_all.push_back(r); }
+      if (hi.fmt != SDP_A_DENSE)
+        for (int r = 0; r < hi.m; ++r) { t_rows.push_back(i); t_rows.push_back(r); }
       if (hi.fmt == SDP_A_DENSE) {
+        for (int ti = 0; ti < (hi.m + 63) / 64; ++ti)
+          for (int tj = 0; tj < hi.ld / 64; ++tj) {
+            b_tiles.push_back(i); b_tiles.push_back(ti); b_tiles.push_back(tj);
+          }
         for (int r = 0; r < hi.m; r += R) { row_tiles.push_back(i); row_tiles.push_back(r); }
         for (int cc = 0; cc < hi.ld; cc += CW) { col_tiles.push_back(i); col_tiles.push_back(cc); }
         for (int ti = 0; ti < hi.ldm / 64; ++ti)
@@ -721,6 +752,15 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     a.n_col_tiles = (int)(col_tiles.size() / 2);
     a.t_rows = dev_upload(t_rows, own);
     a.n_t_rows = (int)(t_rows.size() / 2);
+    a.t3_rows = a.t_rows;
+    a.n_t3_rows = a.n_t_rows;
+    h->d_t_rows_all = dev_upload(t_rows_all, own);
+    h->n_t_rows_all = (int)(t_rows_all.size() / 2);
+    h->d_ytmp = dev_zeros<double>(row, own);
+    if (d_A) {
+      a.Bm = dev_zeros<double>(aoff, own);
+      a.bp = dev_zeros<double>(row, own);
+    }
     a.csr_rows = dev_upload(csr_rows, own);
     a.n_csr_rows = (int)(csr_rows.size() / 2);
     a.csc_cols = dev_upload(csc_cols, own);
@@ -824,9 +864,13 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
                           ? launch_syrk_csr(f, d_syrk_rows, (int)(syrk_rows.size() / 2), max_ldm,
                                             h->stream)
                           : e1;
+      f.Bout = const_cast<double *>(a.Bm);
+      int32_t *d_b_tiles = dev_upload(b_tiles, tmp);
       hipError_t e3 = e2 == hipSuccess
                           ? launch_cholesky_and_inverse(f, max_ldm / 64, h->stream)
                           : e2;
+      if (e3 == hipSuccess && a.Bm)
+        e3 = launch_form_b(f, d_b_tiles, (int)(b_tiles.size() / 3), h->stream);
       hipError_t e4 = hipStreamSynchronize(h->stream);
       std::vector<int32_t> failed(batch, 0);
       hipError_t e5 = hipMemcpy(failed.data(), d_fail, sizeof(int32_t) * batch, hipMemcpyDeviceToHost);
@@ -842,6 +886,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
                                            ": A D^-1 A^T is not positive definite");
     }
     (void)wd;
+    compute_bp(h);
     reset_state(h);
     *out = h;
   } catch (...) {
@@ -1013,10 +1058,11 @@ int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual, dou
     HIPCHK(hipStreamSynchronize(h->stream));
     if (u) HIPCHK(hipMemcpy(u, h->aff.u + d.coord_off, sizeof(double) * d.nnz, hipMemcpyDeviceToHost));
     if (y_dual) {
-      HIPCHK(launch_scaled_copy(h->aff.y + d.row_off, h->aff.y1 + d.row_off, d.m, h->d_state, inst,
+      ensure_y(h);
+      HIPCHK(launch_scaled_copy(h->aff.y + d.row_off, h->d_ytmp + d.row_off, d.m, h->d_state, inst,
                                 h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
-      HIPCHK(hipMemcpy(y_dual, h->aff.y1 + d.row_off, sizeof(double) * d.m, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(y_dual, h->d_ytmp + d.row_off, sizeof(double) * d.m, hipMemcpyDeviceToHost));
     }
     const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
     if (Xk) HIPCHK(hipMemcpy(Xk, h->proj.X + o, sizeof(double) * n, hipMemcpyDeviceToHost));
@@ -1082,6 +1128,7 @@ int sdp_diagnostics(sdp_handle *h, sdp_result *res) {
     for (size_t b = 0; b < h->bucket_size.size(); ++b)
       HIPCHK(launch_min_eig(h->precision, h->bucket_size[b], h->bucket_list[b], h->bucket_count[b],
                             h->proj, h->dscr.lmin, h->stream));
+    ensure_y(h);
     HIPCHK(launch_diagnostics(h->aff, h->dscr, h->aff.inst_cl_first, h->nrow, h->d_diag,
                               h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1172,6 +1219,7 @@ int sdp_update_data(sdp_handle *h, const double *c, const double *b) {
     if (b)
       HIPCHK(launch_copy_user_rows(b, const_cast<double *>(h->aff.b), h->d_desc, h->d_row_inst,
                                    h->d_user_row_off, h->nrow, h->stream));
+    if (b) compute_bp(h);
     HIPCHK(hipStreamSynchronize(h->stream));
     h->have_diag = false;
     return SDP_OK;
@@ -1283,6 +1331,9 @@ int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, in
     AffineArgs ra = h->aff;
     ra.ignore_done = 1;
     ra.b = h->d_zero_rows;
+    ra.bp = h->d_zero_rows;
+    ra.t3_rows = h->d_t_rows_all;     // the multiplier cotangent is needed on every row
+    ra.n_t3_rows = h->n_t_rows_all;
     ra.bhat = h->d_bhat_bar;
     ra.v = h->d_v_bar;
     ra.r = h->d_r_bar;

@@ -129,10 +129,13 @@ struct AffineArgs {
   const int64_t *a_colptr; const int32_t *a_row; const double *a_cval;    // CSC (per instance blocks)
   const double *T;        // L^-1, lower, row-major (pitch ldm)
   const double *U;        // L^-T, upper, row-major (pitch ldm)
+  const double *Bm;       // B = L^-1 A for dense instances (layout of A), or NULL
+  const double *bp;       // L^-1 b (row space), used with Bm
   // tiles: (inst, start) pairs
   const int32_t *row_tiles; int n_row_tiles; int rows_per_tile;
   const int32_t *col_tiles; int n_col_tiles;
-  const int32_t *t_rows; int n_t_rows;      // (inst, row) per wave for the factor passes
+  const int32_t *t_rows; int n_t_rows;      // (inst, row) per wave for T r
+  const int32_t *t3_rows; int n_t3_rows;    // (inst, row) per wave for T^T y1
   const int32_t *csr_rows; int n_csr_rows;   // (inst, row) pairs for CSR instances
   const int32_t *csc_cols; int n_csc_cols;   // (inst, col-chunk) pairs for CSR instances
   // residual partials
@@ -179,6 +182,7 @@ struct FactorArgs {
   double *T;                     // out: L^-1 at t_off
   double *U;                     // out: L^-T at t_off
   int32_t *fail;                 // per instance: 1 if a pivot <= 0
+  double *Bout;                  // out: B = L^-1 A for dense instances (layout of A)
 };
 
 hipError_t launch_syrk_dense(const FactorArgs &f, const int32_t *tiles, int ntiles,
@@ -186,6 +190,8 @@ hipError_t launch_syrk_dense(const FactorArgs &f, const int32_t *tiles, int ntil
 hipError_t launch_syrk_csr(const FactorArgs &f, const int32_t *rows, int nrows, int max_ldm,
                            hipStream_t st);
 hipError_t launch_cholesky_and_inverse(const FactorArgs &f, int max_nblk, hipStream_t st);
+// tiles: (inst, row tile, column tile) triples over dense instances
+hipError_t launch_form_b(const FactorArgs &f, const int32_t *tiles, int ntiles, hipStream_t st);
 
 int affine_col_tile_width();
 int affine_max_rows_per_tile();
