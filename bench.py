@@ -13,8 +13,8 @@ FP32-eig form (eigensolves in FP32, affine step / multipliers / residuals in
 FP64) between HIP events on the solver's stream.  The same is done for the
 plain FP64 form, and both forms are also solved to max(eps_c, eps_lambda) <=
 1e-4 from a cold start (iterations and time to solution reported).  Per-stage
-times come from HIP events around every kernel stage (sdp_time_stages); the
-dominant stage is reported against its roofline.  The CPU oracle is timed on
+times come from HIP events around back-to-back launches of each kernel stage
+(sdp_time_stages); the dominant stage is reported against its roofline.  The CPU oracle is timed on
 a bounded sample of the same workload on the host cores.
 """
 import argparse
@@ -63,26 +63,35 @@ def make_instances(name, batch_count):
     raise SystemExit(f"unknown workload {name}")
 
 
-def stage_bytes_flops(insts, precision):
+def stage_bytes_flops(insts, precision, sweeps):
     """Algorithmic HBM bytes (or FLOPs) per launch of each stage, summed over
-    the instances of the batch."""
+    the instances of the batch.  Dense A is streamed as B = L^-1 A (same size)
+    and needs no triangular passes; sparse A is streamed as CSR (12 bytes per
+    nonzero) plus the two triangular factors.  The projection count, per
+    clique of size s with `sweeps` Jacobi sweeps on average: 6 s^3 per sweep
+    (each of the s(s-1)/2 rotations of a sweep updates two rows and columns of
+    the symmetric block and two columns of V), 4 s^3 for V0^T W V0 (warm
+    start), 4 s^3 for the Newton-Schulz step and s^3 for the rebuild."""
     import numpy as np
     tot = {k: 0 for k in ("scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "residual", "proj")}
     for inst in insts:
         m, nnz = inst.m, inst.nnz
         sizes = inst.clique_sizes().astype(np.int64)
         npk = int(np.sum(sizes * (sizes + 1) // 2))
-        abytes = 12 * int(inst.a_rowptr[-1]) if inst.a_format == 1 else 8 * m * nnz
-        tri = 8 * m * (m + 1) // 2
         tot["scatter"] += 8 * 2 * npk + 4 * npk + 8 * 5 * nnz
-        tot["A_v"] += abytes + 8 * nnz + 16 * m
-        tot["Linv_r"] += tri + 16 * m
-        tot["LinvT_y"] += tri + 16 * m
-        tot["AT_y"] += abytes + 8 * m + 24 * nnz
         tot["residual"] += 8 * 6 * inst.p
-        # model count for the projections: 10 s^3 per clique (symmetric eig
-        # with vectors ~9 s^3 plus the rebuild s^3)
-        tot["proj"] += int(np.sum(10 * sizes ** 3))
+        tot["proj"] += int(np.sum((6 * sweeps + 9) * sizes ** 3))
+        if inst.a_format == 1:
+            abytes = 12 * int(inst.a_rowptr[-1])
+            tri = 8 * m * (m + 1) // 2
+            tot["A_v"] += abytes + 8 * nnz + 16 * m
+            tot["Linv_r"] += tri + 16 * m
+            tot["LinvT_y"] += tri + 16 * m
+            tot["AT_y"] += abytes + 8 * m + 24 * nnz
+        else:
+            bbytes = 8 * m * nnz
+            tot["A_v"] += bbytes + 8 * nnz + 16 * m
+            tot["AT_y"] += bbytes + 8 * m + 24 * nnz
     d = {k: dict(bound="hbm", bytes=v) for k, v in tot.items() if k != "proj"}
     d["projection"] = dict(bound="alu", flops=tot["proj"],
                            peak_tflops=FP32_VECTOR_TFLOPS if precision == "fp32"
@@ -90,17 +99,20 @@ def stage_bytes_flops(insts, precision):
     return d
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("k_affine.hip", "k_project.hip"):
-        with open(os.path.join(ROOT, "paper_1707_05058_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+# source file of each stage's kernels (a summary is stale once that file changes)
+STAGE_SOURCE = {"scatter": "k_affine.hip", "A_v": "k_affine.hip", "Linv_r": "k_affine.hip",
+                "LinvT_y": "k_affine.hip", "AT_y": "k_affine.hip", "residual": "k_affine.hip",
+                "projection": "k_project.hip"}
+
+
+def source_hash(fname):
+    with open(os.path.join(ROOT, "paper_1707_05058_amd", "csrc", fname), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def load_traffic(workload, stage):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources."""
+    were taken on the current source of the stage's kernel."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -108,10 +120,116 @@ def load_traffic(workload, stage):
         data = json.load(open(path))
     except Exception:
         return None
-    if data.get("kernel_source_hash") != kernel_source_hash():
-        return None
     ent = data.get("stages", {}).get(stage)
-    return None if ent is None else ent.get("hbm_bytes_per_launch")
+    if ent is None or ent.get("source_hash") != source_hash(STAGE_SOURCE[stage]):
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+# kernels of each stage as rocprofv3 names them, (prefix, suffix) pairs; the
+# projection is the FP32-eig form's ADMM-mode kernel (template mode 0)
+STAGE_KERNELS = {"scatter": (("k_scatter", ""),), "A_v": (("k_rowdot<", ""), ("k_csr_rowdot", "")),
+                 "Linv_r": (("k_trmv_wave<0>", ""),), "LinvT_y": (("k_trmv_wave<1>", ""),),
+                 "AT_y": (("k_coldot<0>", ""), ("k_csc_coldot<0>", "")),
+                 "projection": (("k_project<float", ", 0>"),),
+                 "residual": (("k_residual_reduce", ""),)}
+COPY_CAL_BYTES = 512 << 20
+
+
+def _short_kernel(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0] if not name.startswith("__") else name
+
+
+def _csv_rows(root, suffix):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *{suffix} under {root}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def summarize_rocprof(workload, trace_dir, fetch_dir, write_dir, commands):
+    """Turns rocprofv3 CSV output (one --kernel-trace --stats run, one --pmc
+    FETCH_SIZE run, one --pmc WRITE_SIZE run of this script) into
+    profiles/kernel_trace_<workload>.md and profiles/traffic_<workload>.json.
+    The HBM counters are scaled by what they read for a plain copy of
+    COPY_CAL_BYTES (the --copy-calibration run), per launch of each stage."""
+    stats = _csv_rows(trace_dir, "kernel_stats.csv")
+    lines = [f"# Kernel trace and HBM traffic, {workload} workload ({WORKLOADS[workload]})", "",
+             "Commands (repository root, one MI355X; each rocprofv3 run in its own process):", "",
+             "```"] + commands + ["```", "",
+             "| kernel | calls | total (us) | average (us) | % |", "|---|---:|---:|---:|---:|"]
+    for r in stats[:25]:
+        lines.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['AverageNs']) / 1e3:.3f} | "
+                     f"{float(r['Percentage']):.1f} |")
+
+    def per_kernel(rows):
+        acc = {}
+        for r in rows:
+            name = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
+            val = float(r.get("Counter_Value") or r.get("Counter-Value") or 0.0)
+            acc.setdefault(name, []).append(val)
+        return acc
+
+    fetch = per_kernel(_csv_rows(fetch_dir, "counter_collection.csv"))
+    write = per_kernel(_csv_rows(write_dir, "counter_collection.csv"))
+
+    def copy_kib(acc):
+        vals = [v for n, vs in acc.items() if "copyBuffer" in n for v in vs]
+        return max(vals) if vals else None
+
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    if not cf or not cw:
+        raise SystemExit("no copy-calibration dispatch found (run with --copy-calibration)")
+    kib = COPY_CAL_BYTES / 1024.0
+    sf, sw = kib / cf, kib / cw
+    out = {"workload": workload,
+           "copy_calibration": {"bytes": COPY_CAL_BYTES, "fetch_kib": cf, "write_kib": cw,
+                                "fetch_scale": sf, "write_scale": sw},
+           "stages": {}}
+    lines += ["", f"HBM counters per launch (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, "
+              f"scaled by a {COPY_CAL_BYTES >> 20} MiB copy: fetch x{sf:.3f}, write x{sw:.3f}):", "",
+              "| stage | kernels | launches | fetch (MB) | write (MB) | HBM bytes per launch |",
+              "|---|---|---:|---:|---:|---:|"]
+    for stage, pats in STAGE_KERNELS.items():
+        f_names = [n for n in fetch
+                   if any(_short_kernel(n).startswith(p) and _short_kernel(n).endswith(q)
+                          for p, q in pats)]
+        if not f_names:
+            continue
+        fv = [v for n in f_names for v in fetch[n]]
+        wv = [v for n in f_names for v in write.get(n, [])]
+        if not fv or not wv:
+            continue
+        fb = sum(fv) / len(fv) * sf * 1024.0
+        wb = sum(wv) / len(wv) * sw * 1024.0
+        out["stages"][stage] = {"kernels": sorted({_short_kernel(n) for n in f_names}),
+                                "source": STAGE_SOURCE[stage],
+                                "source_hash": source_hash(STAGE_SOURCE[stage]),
+                                "launches": len(fv), "fetch_bytes_per_launch": fb,
+                                "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb}
+        lines.append(f"| {stage} | {', '.join('`%s`' % k for k in out['stages'][stage]['kernels'])} | "
+                     f"{len(fv)} | {fb / 1e6:.2f} | {wb / 1e6:.2f} | {fb + wb:.4g} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"kernel_trace_{workload}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("\n".join(lines))
+
+
+def copy_calibration(torch):
+    """A plain device-to-device copy of COPY_CAL_BYTES, for scaling the HBM
+    counters (rocprofv3 --pmc) of the same run."""
+    src = torch.ones(COPY_CAL_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, repeat_solve=True):
@@ -146,11 +264,12 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     out["projection_plan"] = [dict(N=n, threads=t, cliques=c) for n, t, c in S.projection_plan()]
     S.close()
     # --- the contract: W warm-up + exactly K timed iterations ---
-    S = sdp.Solver(insts, tol=0.0, max_iter=warmup + steps + stage_iters + 10,
-                   precision=precision, stream=stream.cuda_stream)
+    S = sdp.Solver(insts, tol=0.0, max_iter=10 ** 8, precision=precision,
+                   stream=stream.cuda_stream)
     with torch.cuda.stream(stream):
         S.step(warmup, results=False)
         torch.cuda.synchronize()
+        st0 = S.stats()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         S.step(steps, results=False)
@@ -162,6 +281,9 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     out["iter_per_s"] = steps / (ms / 1e3)
     out["projections_per_s"] = out["iter_per_s"] * p_total
     out["instance_iter_per_s"] = out["iter_per_s"] * len(insts)
+    st1 = S.stats()
+    out["timed_sweeps_per_projection"] = ((st1["jacobi_sweeps"] - st0["jacobi_sweeps"]) /
+                                          max(st1["projections"] - st0["projections"], 1))
     out["stages_ms"] = S.time_stages(stage_iters)
     S.close()
     return out
@@ -239,7 +361,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="instances of the batched workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="start with a plain 512 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
+                    help="write profiles/ summaries from rocprofv3 CSV output directories")
+    ap.add_argument("--commands-file", help="text file with the rocprofv3 commands (summaries)")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        cmds = open(args.commands_file).read().strip().splitlines() if args.commands_file else []
+        summarize_rocprof(args.workload, *args.summarize_rocprof, cmds)
+        return
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
               "(independent instances would shard across GPUs with no communication; "
@@ -250,6 +381,8 @@ def main():
     import paper_1707_05058_amd as sdp
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch)
     t0 = time.perf_counter()
     insts = make_instances(args.workload, args.batch_count)
     print(f"[bench] generated {len(insts)} instance(s) in {time.perf_counter() - t0:.1f} s",
@@ -267,8 +400,8 @@ def main():
         print(f"[bench] {args.workload} {precision}: {forms[precision]['iter_per_s']:.1f} iter/s",
               file=sys.stderr, flush=True)
     head = forms["fp32"]
-    model = stage_bytes_flops(insts, "fp32")
-    stages = head["stages_ms"]
+    model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"])
+    stages = {k: v for k, v in head["stages_ms"].items() if k in model}
     dom = max(stages, key=lambda k: stages[k])
     t_launch = stages[dom] / 1e3
     info = model[dom]

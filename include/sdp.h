@@ -197,12 +197,16 @@ int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
 int sdp_projection_plan(sdp_handle *h, int32_t cap, int32_t *block_n, int32_t *threads,
                         int32_t *cliques, int32_t *count);
 
-/* Runs n_iter iterations with plain launches, timing every stage with HIP
- * events recorded on the handle's stream, and writes the mean milliseconds
- * per iteration of each stage to ms[0..6]: 0 scatter (bhat), 1 A v - b,
- * 2 L^-1 r, 3 L^-T y1, 4 u = (bhat - A^T y)/D, 5 clique projections (all size
- * buckets), 6 residual reduction.  The iterations advance the state exactly
- * like sdp_admm_step.  Synchronises. */
+/* Times every stage of the iteration on its own: stage s is launched n_iter
+ * times back to back between two HIP events on the handle's stream (stages
+ * in iteration order), and ms[s] receives the mean milliseconds per launch:
+ * 0 scatter (bhat), 1 A v - b (B v - L^-1 b for dense A), 2 L^-1 r, 3 L^-T y1
+ * (2 and 3 only for sparse-A instances), 4 u = (bhat - A^T y)/D, 5 clique
+ * projections with the multiplier update (all launch lists), 6 residual
+ * reduction.  Stages 0-4 recompute the same outputs on every launch; stages 5
+ * and 6 advance X_k, Lambda_k and the iteration counters n_iter times, so afterwards the state is no longer
+ * an iterate of Algorithm 1 (sdp_reset or sdp_set_state before solving
+ * again).  Synchronises. */
 int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms);
 
 /* ---- differentiation of the unrolled iteration ---------------------------

@@ -35,37 +35,48 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// bhat and v = w * bhat / D (owner-computes: one thread per coordinate sums
-// its contributors in clique order; no atomics)
+// bhat and v = w * bhat / D (owner-computes, no atomics).  Four consecutive
+// lanes share a coordinate and split its contributors; their sums meet in a
+// fixed butterfly, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
+constexpr int SC_LANES = 4;
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b % 8).  Renumber them so that each XCD gets one contiguous range of the
+// logical index space: neighbouring coordinates share cache lines of X and
+// Lambda, and each XCD has its own L2.
+__device__ inline int xcd_contiguous(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
 __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= a.ncoord) return;
+  const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int64_t j = g / SC_LANES;
+  const int q = (int)(g % SC_LANES);
+  if (j >= a.ncoord) return;             // whole lane groups leave together
   const int inst = a.coord_inst[j];
   const InstState &st = a.state[inst];
   if (st.done) return;
   const double rho = st.rho;
-  // sum_k (x_k + lambda_k / rho) - c / rho = sum_k x_k + (sum_k lambda_k - c) / rho;
-  // the contributor loads are issued four at a time to overlap their latency
+  // sum_k (x_k + lambda_k / rho) - c / rho = sum_k x_k + (sum_k lambda_k - c) / rho
   double sx = 0.0, sl = 0.0;
-  int64_t t = a.contrib_ptr[j];
   const int64_t t1 = a.contrib_ptr[j + 1];
-  for (; t + 4 <= t1; t += 4) {
-    const int32_t e0 = a.contrib_idx[t], e1 = a.contrib_idx[t + 1];
-    const int32_t e2 = a.contrib_idx[t + 2], e3 = a.contrib_idx[t + 3];
-    const double x0 = a.X[e0], x1 = a.X[e1], x2 = a.X[e2], x3 = a.X[e3];
-    const double l0 = a.Lam[e0], l1 = a.Lam[e1], l2 = a.Lam[e2], l3 = a.Lam[e3];
-    sx += x0; sx += x1; sx += x2; sx += x3;
-    sl += l0; sl += l1; sl += l2; sl += l3;
-  }
-  for (; t < t1; ++t) {
+  for (int64_t t = a.contrib_ptr[j] + q; t < t1; t += SC_LANES) {
     const int32_t e = a.contrib_idx[t];
     sx += a.X[e];
     sl += a.Lam[e];
   }
-  const double bh = sx + (sl - a.c[j]) / rho;
-  a.bhat[j] = bh;
-  a.v[j] = a.w[j] * bh / a.D[j];
+#pragma unroll
+  for (int o = 1; o < SC_LANES; o <<= 1) {
+    sx += __shfl_xor(sx, o, 64);
+    sl += __shfl_xor(sl, o, 64);
+  }
+  if (q == 0) {
+    const double bh = sx + (sl - a.c[j]) / rho;
+    a.bhat[j] = bh;
+    a.v[j] = a.w[j] * bh / a.D[j];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -230,25 +241,30 @@ __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
 
 // ---------------------------------------------------------------------------
 // Residuals (PrimalConsensusResidual), stopping test and adaptive penalty.
-// One workgroup per instance sums its cliques' partials in a fixed order.
+// One workgroup per instance sums its cliques' partials (||X - Hx||^2,
+// ||X||^2, ||Hx||^2, ||X - X_prev||^2, ||Lambda||^2, sweeps) in a fixed
+// order.  The partial loads are issued before the `done` test so that the
+// two memory round trips overlap.
 // ---------------------------------------------------------------------------
 __device__ inline double ratio(double num, double den) {
   if (den > 0.0) return num / den;
   return num == 0.0 ? 0.0 : INFINITY;
 }
 
-__global__ __launch_bounds__(1024) void k_residual_reduce(AffineArgs a) {
+constexpr int RES_NT = 1024;
+
+__global__ __launch_bounds__(RES_NT) void k_residual_reduce(AffineArgs a) {
   const int inst = blockIdx.x;
   InstState &st = a.state[inst];
-  if (st.done) return;
   const int64_t c0 = a.inst_cl_first[inst], c1 = a.inst_cl_first[inst + 1];
   double s[NPART] = {0, 0, 0, 0, 0, 0};
-  for (int64_t k = c0 + threadIdx.x; k < c1; k += 1024) {
+  for (int64_t k = c0 + threadIdx.x; k < c1; k += RES_NT) {
     const double2 *pk = reinterpret_cast<const double2 *>(a.part + NPART * k);
     const double2 q0 = pk[0], q1 = pk[1], q2 = pk[2];
     s[0] += q0.x; s[1] += q0.y; s[2] += q1.x; s[3] += q1.y; s[4] += q2.x; s[5] += q2.y;
   }
-  __shared__ double red[16][NPART];
+  const int32_t done = st.done;
+  __shared__ double red[RES_NT / 64][NPART];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int t = 0; t < NPART; ++t) {
@@ -256,14 +272,12 @@ __global__ __launch_bounds__(1024) void k_residual_reduce(AffineArgs a) {
     if (l == 0) red[w][t] = v;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (w != 0 || done) return;
+  // wave 0 folds the 16 wave sums: lane i < 16 holds wave i's values
   double S[NPART];
 #pragma unroll
-  for (int t = 0; t < NPART; ++t) {
-    double acc = 0.0;
-    for (int i = 0; i < 16; ++i) acc += red[i][t];
-    S[t] = acc;
-  }
+  for (int t = 0; t < NPART; ++t) S[t] = wave_sum(l < RES_NT / 64 ? red[l][t] : 0.0);
+  if (l != 0) return;
   const double rho = st.rho;
   const double nx = sqrt(S[1]), nhx = sqrt(S[2]);
   const double eps_c = ratio(sqrt(S[0]), nx > nhx ? nx : nhx);
@@ -390,7 +404,7 @@ __global__ __launch_bounds__(256) void k_scaled_copy(const double *src, double *
 hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
   switch (stage) {
     case 0: {
-      const int nb = (int)((a.ncoord + 255) / 256);
+      const int nb = (int)((a.ncoord * SC_LANES + 255) / 256);
       hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a);
       break;
     }
@@ -435,7 +449,7 @@ hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_reduce, dim3(a.batch), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(k_residual_reduce, dim3(a.batch), dim3(RES_NT), 0, st, a);
   return hipGetLastError();
 }
 

@@ -120,9 +120,12 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     off = offsets[blockIdx.x];
     if (s <= 0 || s > N) return;   // sizes beyond max_size are left untouched
   } else {
-    cl = list[blockIdx.x];
+    // neighbouring cliques share coordinates of u: keep them on one XCD
+    // (workgroups are dealt to the 8 XCDs round-robin)
+    const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+    cl = list[x8 * q8 + min(x8, r8) + blockIdx.x / 8];
     const int inst = a.cl_inst[cl];
-    if (MODE == MODE_ADMM && a.state[inst].done) return;
+    if (MODE == MODE_ADMM && a.state[inst].done) return;   // uniform per workgroup
     s = a.cl_size[cl];
     off = a.cl_off[cl];
     rho = a.state[inst].rho;

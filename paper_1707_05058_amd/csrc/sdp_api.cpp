@@ -227,23 +227,32 @@ int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    float best_ms = 1e30f;
+    // best of three timings of three launches each; a variant replaces the
+    // default only when it is at least 5% faster (keeps the choice stable)
+    const int def = projection_default_variant(precision, s);
+    float def_ms = 1e30f, best_ms = 1e30f;
     for (int v : cand) {
       HIPCHK(launch_standalone_projection(precision, v, test, d_sizes, d_offs, in, out, max_sweeps,
                                           tol, st));
-      HIPCHK(hipEventRecord(e0, st));
-      for (int r = 0; r < 3; ++r)
-        HIPCHK(launch_standalone_projection(precision, v, test, d_sizes, d_offs, in, out,
-                                            max_sweeps, tol, st));
-      HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) {
-        best_ms = ms;
+      float vms = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r)
+          HIPCHK(launch_standalone_projection(precision, v, test, d_sizes, d_offs, in, out,
+                                              max_sweeps, tol, st));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        vms = std::min(vms, ms);
+      }
+      if (v == def) def_ms = vms;
+      if (vms < best_ms) {
+        best_ms = vms;
         best = v;
       }
     }
+    if (def_ms < 1e30f && best != def && best_ms > 0.95f * def_ms) best = def;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   } catch (...) {
@@ -783,6 +792,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     p.state = h->d_state;
     p.max_sweeps = h->max_sweeps;
     p.tol = h->jac_tol;
+
     a.X = p.X;
     a.Lam = p.Lam;
     for (auto &l : lists) {
@@ -1175,36 +1185,36 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
   return guarded([&] {
     if (!h || n_iter <= 0 || !ms) fail(SDP_ERR_ARG, "invalid arguments");
     constexpr int NS = 7;
-    hipEvent_t ev[NS + 1];
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-    double acc[NS] = {0, 0, 0, 0, 0, 0, 0};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
     try {
-      for (int it = 0; it < n_iter; ++it) {
-        HIPCHK(hipEventRecord(ev[0], h->stream));
-        for (int s = 0; s < 5; ++s) {
-          HIPCHK(launch_affine_stage(h->aff, s, h->stream));
-          HIPCHK(hipEventRecord(ev[s + 1], h->stream));
+      for (int s = 0; s < NS; ++s) {
+        HIPCHK(hipEventRecord(e0, h->stream));
+        for (int it = 0; it < n_iter; ++it) {
+          if (s < 5) {
+            HIPCHK(launch_affine_stage(h->aff, s, h->stream));
+          } else if (s == 5) {
+            for (size_t b = 0; b < h->bucket_size.size(); ++b)
+              HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+                                            h->bucket_count[b], h->proj, h->stream));
+          } else {
+            HIPCHK(launch_residual_reduce(h->aff, h->stream));
+          }
         }
-        for (size_t b = 0; b < h->bucket_size.size(); ++b)
-          HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                        h->bucket_count[b], h->proj, h->stream));
-        HIPCHK(hipEventRecord(ev[6], h->stream));
-        HIPCHK(launch_residual_reduce(h->aff, h->stream));
-        HIPCHK(hipEventRecord(ev[7], h->stream));
-        HIPCHK(hipEventSynchronize(ev[7]));
-        for (int s = 0; s < NS; ++s) {
-          float t = 0.f;
-          HIPCHK(hipEventElapsedTime(&t, ev[s], ev[s + 1]));
-          acc[s] += t;
-        }
+        HIPCHK(hipEventRecord(e1, h->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        ms[s] = (double)t / n_iter;
       }
     } catch (...) {
-      for (auto &e : ev) (void)hipEventDestroy(e);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       throw;
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
-    for (int s = 0; s < NS; ++s) ms[s] = acc[s] / n_iter;
-    h->iters_enqueued += n_iter;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     h->have_diag = false;
     return SDP_OK;
   });

@@ -163,8 +163,8 @@ hipError_t launch_scaled_copy(const double *src, double *dst, int64_t n, const I
                               int inst, hipStream_t st);
 
 hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st);
-hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st);
 hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st);
+hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st);
 hipError_t launch_objective(const AffineArgs &a, double *obj, hipStream_t st);
 
 // ----------------------------------------------------------------------------
