@@ -42,10 +42,13 @@ WORKLOADS = {
                "seeds 0..511, solved together",
     "adjoint": "64 block-arrow SDPs l=50 d=16 h=8 (n=808, 50 cliques of 24), m=400, seeds 0..63: "
                "200 unrolled iterations checkpointed every 20, forward + reverse sweep",
+    "projection": "standalone batched PSD projection (sdp_psd_project_batched): 4096 GOE blocks "
+                  "(symmetric N(0,1), about half the eigenvalues negative) per size "
+                  "s in {15, 16, 24, 32, 50, 64, 96, 128}, seed = s",
 }
 # precision forms each workload is timed in (FP64 blocks stop at 96 x 96)
 FORMS = {"banded": ("fp32", "fp64"), "small": ("fp32", "fp64"), "large": ("fp32",),
-         "batched": ("fp32", "fp64"), "adjoint": ("fp32", "fp64")}
+         "batched": ("fp32", "fp64"), "adjoint": ("fp32", "fp64"), "projection": ("fp32", "fp64")}
 
 
 def make_instances(name, batch_count):
@@ -383,6 +386,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(torch)
+    if args.workload == "projection":
+        run_projection(args, sdp, torch, torch.cuda.Stream())
+        return
     t0 = time.perf_counter()
     insts = make_instances(args.workload, args.batch_count)
     print(f"[bench] generated {len(insts)} instance(s) in {time.perf_counter() - t0:.1f} s",
@@ -454,6 +460,93 @@ def main():
         line["speedup_fp32_vs_fp64_time_to_tol"] = (f64["solve"]["time_to_tol_s"] /
                                                     f32["solve"]["time_to_tol_s"])
         line["objective_rel_diff_fp32_vs_fp64"] = float(np.max(np.abs(o32 - o64) / np.abs(o64)))
+    print(json.dumps(line), flush=True)
+
+
+PROJ_SIZES = (15, 16, 24, 32, 50, 64, 96, 128)
+
+
+def run_projection(args, sdp, torch, stream):
+    """Kernel-only rate of the batched projection: `count` blocks of one size
+    per launch, every kernel variant that fits (the default and the fastest
+    reported), timed with HIP events over `steps` launches after `warmup`."""
+    import numpy as np
+    import sdpgen
+    count = 4096
+    steps, warmup = max(3, min(args.steps, 20)), max(1, min(args.warmup, 3))
+    res = {}
+    for prec, npdt, tdt, dtc in (("fp32", np.float32, torch.float32, sdp.DTYPE_FP32),
+                                 ("fp64", np.float64, torch.float64, sdp.DTYPE_FP64)):
+        variants = sdp.projection_variants(dtc)
+        nmax = max(n for n, _ in variants)
+        peak = FP32_VECTOR_TFLOPS if prec == "fp32" else FP64_VECTOR_TFLOPS
+        for s in PROJ_SIZES:
+            if s > nmax:
+                continue
+            blocks = np.stack(sdpgen.goe_blocks([s] * count, seed=s, dtype=npdt))
+            dev = torch.device("cuda:0")
+            t_in = torch.from_numpy(blocks.reshape(-1)).to(dev)
+            t_out = torch.empty_like(t_in)
+            sizes = torch.full((count,), s, dtype=torch.int32, device=dev)
+            offs = torch.arange(count, dtype=torch.int64, device=dev) * (s * s)
+            n_fit = min(n for n, _ in variants if n >= s + (s & 1))
+            times = {}
+            for v, (N, NT) in enumerate(variants):
+                if N < s + (s & 1) or N > 2 * n_fit:
+                    continue
+                with torch.cuda.stream(stream):
+                    for _ in range(warmup):
+                        sdp.psd_project_batched(sizes, offs, t_in, t_out, s, stream=stream.cuda_stream,
+                                                variant=v)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(steps):
+                        sdp.psd_project_batched(sizes, offs, t_in, t_out, s, stream=stream.cuda_stream,
+                                                variant=v)
+                    e1.record(stream)
+                    e1.synchronize()
+                times[(N, NT)] = e0.elapsed_time(e1) / steps
+            (bn, bt), bms = min(times.items(), key=lambda kv: kv[1])
+            dn = [k for k in times if k[0] == n_fit][0]
+            model = 10.0 * s ** 3 * count
+            res[f"{prec}_s{s}"] = dict(
+                s=s, blocks=count, best_variant=dict(N=bn, threads=bt), ms_per_launch=bms,
+                projections_per_s=count / (bms / 1e3),
+                model_tflops=model / (bms / 1e3) / 1e12,
+                model_frac_of_peak=model / (bms / 1e3) / 1e12 / peak,
+                default_variant=dict(N=dn[0], threads=dn[1]), default_ms=times[dn],
+                all_variants_ms={f"{k[0]}x{k[1]}": t for k, t in sorted(times.items())})
+            print(f"[bench] projection {prec} s={s}: {count / (bms / 1e3):.3e} proj/s "
+                  f"({bn}x{bt}, {bms:.3f} ms)", file=sys.stderr, flush=True)
+            del t_in, t_out
+    head = res["fp32_s16"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        blocks = sdpgen.goe_blocks([16] * 256, seed=16)
+        t0, done = time.perf_counter(), 0
+        while time.perf_counter() - t0 < args.cpu_seconds and done < len(blocks):
+            oracle.psd_project(blocks[done])
+            done += 1
+        el = time.perf_counter() - t0
+        cpu = dict(value=done / el, unit="projections/s", cores=1, kind="oracle",
+                   sample=f"{done} GOE blocks of 16 projected one after another (FP64 cyclic "
+                          f"Jacobi) in {el:.1f} s")
+    line = {
+        "metric": "PSD clique projections/s (standalone batched kernel)",
+        "value": head["projections_per_s"], "unit": "projections/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": head["ms_per_launch"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["projection"], "headline": "FP32, s = 16"},
+        "sizes": res,
+        "roofline": {"kernel": "k_project (standalone)", "bound": "alu",
+                     "achieved": head["model_tflops"], "peak": FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": head["model_frac_of_peak"], "traffic": None,
+                     "model": "10 s^3 per block (symmetric eigensolve with vectors 9 s^3, "
+                              "rebuild s^3)"},
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(line), flush=True)
 
 

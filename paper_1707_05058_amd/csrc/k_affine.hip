@@ -220,23 +220,32 @@ __global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
   const int64_t t0 = a.a_rowptr[d.a_off + row], t1 = a.a_rowptr[d.a_off + row + 1];
   const double *v = a.v + d.coord_off;
   double acc = 0.0;
+#pragma unroll 4
   for (int64_t t = t0 + l; t < t1; t += 64) acc += a.a_val[t] * v[a.a_col[t]];
   acc = wave_sum(acc);
   if (l == 0) a.r[d.row_off + row] = acc - a.b[d.row_off + row];
 }
+
+// Transposed products with sparse A: CSC_G consecutive lanes share a column
+// and read its nonzeros contiguously; their sums meet in a fixed butterfly.
+constexpr int CSC_G = 8;
+constexpr int CSC_COLS = 256 / CSC_G;   // columns per workgroup
 
 template <int RAW>
 __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
   const int inst = a.csc_cols[2 * blockIdx.x], col0 = a.csc_cols[2 * blockIdx.x + 1];
   if (!a.ignore_done && a.state[inst].done) return;
   const InstDesc d = a.inst[inst];
-  const int col = col0 + threadIdx.x;
-  if (col >= d.ld) return;
+  const int col = col0 + (int)threadIdx.x / CSC_G, q = threadIdx.x % CSC_G;
+  if (col >= d.ld) return;                 // whole lane groups leave together
   const int64_t g = d.coord_off + col;
   const double *y = a.y + d.row_off;
   double acc = 0.0;
-  for (int64_t t = a.a_colptr[g]; t < a.a_colptr[g + 1]; ++t) acc += a.a_cval[t] * y[a.a_row[t]];
-  a.u[g] = RAW ? acc : (a.bhat[g] - acc) / a.D[g];
+  const int64_t t1 = a.a_colptr[g + 1];
+  for (int64_t t = a.a_colptr[g] + q; t < t1; t += CSC_G) acc += a.a_cval[t] * y[a.a_row[t]];
+#pragma unroll
+  for (int o = 1; o < CSC_G; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (q == 0) a.u[g] = RAW ? acc : (a.bhat[g] - acc) / a.D[g];
 }
 
 // ---------------------------------------------------------------------------
@@ -459,6 +468,7 @@ hipError_t launch_objective(const AffineArgs &a, double *obj, hipStream_t st) {
 }
 
 int affine_col_tile_width() { return COL_W; }
+int affine_csc_tile_width() { return CSC_COLS; }
 int affine_max_rows_per_tile() { return MAX_R; }
 
 // Diagnostics: needs the per-clique minimum eigenvalues in s.lmin already.

@@ -657,7 +657,10 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
           csr_rows.push_back(i); csr_rows.push_back(r);
           syrk_rows.push_back(i); syrk_rows.push_back(r);
         }
-        for (int cc = 0; cc < hi.ld; cc += 256) { csc_cols.push_back(i); csc_cols.push_back(cc); }
+        for (int cc = 0; cc < hi.ld; cc += affine_csc_tile_width()) {
+          csc_cols.push_back(i);
+          csc_cols.push_back(cc);
+        }
       }
     }
     if (max_ldm * sizeof(double) > 160 * 1024 && !syrk_rows.empty())

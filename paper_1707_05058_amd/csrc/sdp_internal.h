@@ -194,6 +194,7 @@ hipError_t launch_cholesky_and_inverse(const FactorArgs &f, int max_nblk, hipStr
 hipError_t launch_form_b(const FactorArgs &f, const int32_t *tiles, int ntiles, hipStream_t st);
 
 int affine_col_tile_width();
+int affine_csc_tile_width();   // columns per workgroup of the sparse transposed product
 int affine_max_rows_per_tile();
 
 // ----------------------------------------------------------------------------
