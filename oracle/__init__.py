@@ -54,6 +54,12 @@ def _load():
     lib.orc_run.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_double,
                             C.c_double, C.c_int, _ip, _dp, _dp, _dp]
     lib.orc_run.restype = C.c_int
+    lib.orc_run_dual.argtypes = lib.orc_run.argtypes
+    lib.orc_run_dual.restype = C.c_int
+    lib.orc_dual_objective.argtypes = [C.c_void_p]
+    lib.orc_dual_objective.restype = C.c_double
+    lib.orc_get_vd.argtypes = [C.c_void_p, _dp]
+    lib.orc_set_vd.argtypes = [C.c_void_p, _dp]
     lib.orc_jacobi_eig.argtypes = [C.c_int, _dp, _dp, _dp, C.c_int, C.c_double]
     lib.orc_jacobi_eig.restype = C.c_int
     lib.orc_psd_project.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.c_double]
@@ -228,13 +234,37 @@ class Problem:
         _load().orc_set_jacobi(self._h, max_sweeps, tol)
 
     def run(self, max_iter, tol=1e-4, adaptive=False, mu=2.0, nu=10.0, rho_period=1):
+        """Algorithm 1 (domain-space primal ADMM)."""
+        return self._run(_load().orc_run, max_iter, tol, adaptive, mu, nu, rho_period)
+
+    def run_dual(self, max_iter, tol=1e-4, adaptive=False, mu=2.0, nu=10.0, rho_period=1):
+        """Algorithm 2 (range-space dual ADMM): z_k in blocks()[0], lambda_k in
+        blocks()[1], x in u(), y in y()."""
+        return self._run(_load().orc_run_dual, max_iter, tol, adaptive, mu, nu, rho_period)
+
+    def dual_objective(self):
+        """b^T y of the current Algorithm 2 iterate."""
+        return float(_load().orc_dual_objective(self._h))
+
+    def v_blocks(self):
+        """The slack blocks v_k of Algorithm 2 (full s_k x s_k matrices)."""
+        n = int(_load().orc_nblk(self._h))
+        V = np.zeros(n)
+        _load().orc_get_vd(self._h, _d(V))
+        return self._split(V)
+
+    def set_v_blocks(self, Vs):
+        V = np.concatenate([np.asarray(v, dtype=np.float64).ravel() for v in Vs])
+        _load().orc_set_vd(self._h, _d(V))
+
+    def _run(self, fn, max_iter, tol, adaptive, mu, nu, rho_period):
         lib = _load()
         hc = np.zeros(max(max_iter, 1))
         hl = np.zeros(max(max_iter, 1))
         hr = np.zeros(max(max_iter, 1))
         it = C.c_int(0)
-        st = lib.orc_run(self._h, int(max_iter), float(tol), int(bool(adaptive)), float(mu),
-                         float(nu), int(rho_period), C.byref(it), _d(hc), _d(hl), _d(hr))
+        st = fn(self._h, int(max_iter), float(tol), int(bool(adaptive)), float(mu),
+                float(nu), int(rho_period), C.byref(it), _d(hc), _d(hl), _d(hr))
         k = it.value
         return RunResult(st, k, lib.orc_eps_c(self._h), lib.orc_eps_l(self._h),
                          lib.orc_rho(self._h), hc[:k], hl[:k], hr[:k])

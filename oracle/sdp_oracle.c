@@ -96,6 +96,7 @@ typedef struct orc_problem {
   /* ADMM state */
   double rho;
   double *X, *Lam, *Xprev;
+  double *Vd;         /* Algorithm 2: the slack blocks v_k (X holds z_k)      */
   double *u, *y, *bhat, *r, *tmp;
   int64_t nblk;       /* sum s_k^2 */
   int iters;
@@ -317,7 +318,7 @@ void orc_free(orc_problem *P) {
   free(P->pat_row); free(P->pat_col); free(P->cptr); free(P->cvert);
   free(P->blk_off); free(P->loc); free(P->D); free(P->w);
   free(P->a_rowptr); free(P->a_col); free(P->a_val); free(P->b); free(P->c);
-  free(P->L); free(P->X); free(P->Lam); free(P->Xprev);
+  free(P->L); free(P->X); free(P->Lam); free(P->Xprev); free(P->Vd);
   free(P->u); free(P->y); free(P->bhat); free(P->r); free(P->tmp);
   free(P);
 }
@@ -498,6 +499,7 @@ int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col
   P->X = (double *)calloc(P->nblk, sizeof(double));
   P->Lam = (double *)calloc(P->nblk, sizeof(double));
   P->Xprev = (double *)calloc(P->nblk, sizeof(double));
+  P->Vd = (double *)calloc(P->nblk, sizeof(double));
   P->u = (double *)calloc(nnz, sizeof(double));
   P->bhat = (double *)calloc(nnz, sizeof(double));
   P->tmp = (double *)calloc(nnz, sizeof(double));
@@ -515,6 +517,7 @@ void orc_reset(orc_problem *P, double rho0) {
   memset(P->X, 0, sizeof(double) * P->nblk);
   memset(P->Lam, 0, sizeof(double) * P->nblk);
   memset(P->Xprev, 0, sizeof(double) * P->nblk);
+  memset(P->Vd, 0, sizeof(double) * P->nblk);
   memset(P->u, 0, sizeof(double) * P->nnz);
   memset(P->y, 0, sizeof(double) * (P->m > 0 ? P->m : 1));
   P->rho = rho0;
@@ -640,6 +643,114 @@ int orc_run(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
   free(part); free(sweeps);
   return done ? ORC_OK : ORC_MAX_ITER;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 2: ADMM for the range-space decomposition of the dual-form SDP   */
+/* ------------------------------------------------------------------------- */
+
+/* Runs up to max_iter iterations of Algorithm 2 from the current state
+ * (z_k in X, lambda_k in Lam, v_k in Vd, x in u, y in y).  One iteration, in
+ * the order the algorithm lists its steps:
+ *   z_k = P+(v_k - lambda_k / rho)                                 (zkUpdate)
+ *   (x, y) from the KKT system with right-hand side
+ *     c - sum_k H_k^T (z_k + lambda_k / rho) and -b / rho     (OptCondMinYDual)
+ *   v_k = z_k + lambda_k / rho + H_k x                               (vkEqn)
+ *   lambda_k += rho (z_k - v_k)                              (MultUpdateDualSDP)
+ *   eps_c, eps_lambda as in DualConsensusResidual; stop, adaptive rho.
+ * On compact coordinates the KKT system reads D_j x_j + sum_i A_ij y_i = rhs_j
+ * and sum_j w_j A_ij x_j = -b_i / rho: the primal solve with other data.
+ * Same return values and history as orc_run. */
+int orc_run_dual(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
+                 double nu, int rho_period, int *iters_done, double *hist_eps_c,
+                 double *hist_eps_l, double *hist_rho) {
+  int p = P->p;
+  double *part = (double *)calloc((size_t)p * 5, sizeof(double));
+  int *sweeps = (int *)calloc(p, sizeof(int));
+  double *bvec = (double *)malloc(sizeof(double) * (P->m > 0 ? P->m : 1));
+  int done = 0, it;
+  for (it = 0; it < max_iter; ++it) {
+    double rho = P->rho;
+    /* z-update: independent projections */
+    memcpy(P->Xprev, P->X, sizeof(double) * P->nblk);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      double *Wk = (double *)malloc(sizeof(double) * s * s);
+      for (int e = 0; e < s * s; ++e) Wk[e] = P->Vd[o + e] - P->Lam[o + e] / rho;
+      sweeps[k] = orc_psd_project(s, Wk, P->X + o, NULL, NULL, P->jac_max_sweeps,
+                                  P->jac_tol);
+      free(Wk);
+    }
+    /* (x, y): right-hand side c - sum_k H_k^T (z_k + lambda_k / rho), summed
+       over the lower entries of the blocks in increasing k */
+    for (int64_t j = 0; j < P->nnz; ++j) P->bhat[j] = 0.0;
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      for (int a = 0; a < s; ++a)
+        for (int bb = 0; bb <= a; ++bb) {
+          int64_t e = o + (int64_t)a * s + bb;
+          P->bhat[P->loc[e]] += P->X[e] + P->Lam[e] / rho;
+        }
+    }
+    for (int64_t j = 0; j < P->nnz; ++j) P->bhat[j] = P->c[j] - P->bhat[j];
+    for (int i = 0; i < P->m; ++i) bvec[i] = -P->b[i] / rho;
+    orc_affine(P, P->bhat, bvec, P->u, P->y);
+    /* v and lambda updates, residual partial sums */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      double r_c = 0, n_z = 0, n_v = 0, r_d = 0, n_l = 0;
+      for (int e = 0; e < s * s; ++e) {
+        double zk = P->X[o + e];
+        double vk = zk + P->Lam[o + e] / rho + P->u[P->loc[o + e]];
+        double lk = P->Lam[o + e] + rho * (zk - vk);
+        P->Vd[o + e] = vk;
+        P->Lam[o + e] = lk;
+        double dc = zk - vk, dz = zk - P->Xprev[o + e];
+        r_c += dc * dc; n_z += zk * zk; n_v += vk * vk;
+        r_d += dz * dz; n_l += lk * lk;
+      }
+      part[5 * k + 0] = r_c; part[5 * k + 1] = n_z; part[5 * k + 2] = n_v;
+      part[5 * k + 3] = r_d; part[5 * k + 4] = n_l;
+    }
+    double S[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < p; ++k) {
+      for (int t = 0; t < 5; ++t) S[t] += part[5 * k + t];
+      P->total_sweeps += sweeps[k];
+      if (sweeps[k] > P->max_sweeps_seen) P->max_sweeps_seen = sweeps[k];
+    }
+    /* residuals (DualConsensusResidual) */
+    double den_c = sqrt(S[1]) > sqrt(S[2]) ? sqrt(S[1]) : sqrt(S[2]);
+    P->eps_c = ratio(sqrt(S[0]), den_c);
+    P->eps_l = ratio(rho * sqrt(S[3]), sqrt(S[4]));
+    if (hist_eps_c) hist_eps_c[it] = P->eps_c;
+    if (hist_eps_l) hist_eps_l[it] = P->eps_l;
+    if (hist_rho) hist_rho[it] = rho;
+    P->iters++;
+    double e = P->eps_c > P->eps_l ? P->eps_c : P->eps_l;
+    if (e <= tol) { done = 1; ++it; break; }
+    if (adaptive && rho_period > 0 && (P->iters % rho_period) == 0) {
+      if (P->eps_c >= nu * P->eps_l) P->rho = mu * rho;
+      else if (P->eps_l >= nu * P->eps_c) P->rho = rho / mu;
+    }
+  }
+  if (iters_done) *iters_done = it;
+  free(part); free(sweeps); free(bvec);
+  return done ? ORC_OK : ORC_MAX_ITER;
+}
+
+/* Dual objective b^T y of the current iterate of Algorithm 2. */
+double orc_dual_objective(const orc_problem *P) {
+  double acc = 0.0;
+  for (int i = 0; i < P->m; ++i) acc += P->b[i] * P->y[i];
+  return acc;
+}
+
+void orc_get_vd(const orc_problem *P, double *V) { memcpy(V, P->Vd, sizeof(double) * P->nblk); }
+void orc_set_vd(orc_problem *P, const double *V) { memcpy(P->Vd, V, sizeof(double) * P->nblk); }
 
 /* ------------------------------------------------------------------------- */
 /* Accessors and diagnostics                                                 */
