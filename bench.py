@@ -235,13 +235,14 @@ def copy_calibration(torch):
     del src, dst
 
 
-def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, repeat_solve=True):
+def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, repeat_solve=True,
+              algorithm="primal"):
     out = {}
     p_total = sum(i.p for i in insts)
     # --- solve to the 1e-4 residual from a cold start (second solve timed) ---
     t0 = time.perf_counter()
     S = sdp.Solver(insts, tol=1e-4, max_iter=20000, precision=precision,
-                   stream=stream.cuda_stream)
+                   stream=stream.cuda_stream, algorithm=algorithm)
     torch.cuda.synchronize()
     out["setup_s"] = time.perf_counter() - t0
     with torch.cuda.stream(stream):
@@ -268,7 +269,7 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     S.close()
     # --- the contract: W warm-up + exactly K timed iterations ---
     S = sdp.Solver(insts, tol=0.0, max_iter=10 ** 8, precision=precision,
-                   stream=stream.cuda_stream)
+                   stream=stream.cuda_stream, algorithm=algorithm)
     with torch.cuda.stream(stream):
         S.step(warmup, results=False)
         torch.cuda.synchronize()
@@ -325,7 +326,7 @@ def time_adjoint(sdp, torch, insts, precision, T, ckpt, stream):
     return out, cb.cpu().numpy(), bb.cpu().numpy()
 
 
-def cpu_baseline(insts, seconds):
+def cpu_baseline(insts, seconds, algorithm="primal"):
     """The oracle on a bounded sample: the first instances of the workload,
     a few iterations each; the per-iteration time of the whole batch is the
     sum over instances, extrapolated from the sampled ones."""
@@ -334,9 +335,10 @@ def cpu_baseline(insts, seconds):
     times, sampled, total_it = [], [], 0
     for inst in insts[:4]:
         P = oracle.Problem(inst)
+        step = P.run_dual if algorithm == "dual" else P.run
         done, t0 = 0, time.perf_counter()
         while True:
-            P.run(2, tol=0.0)
+            step(2, tol=0.0)
             done += 2
             el = time.perf_counter() - t0
             if el >= per_inst:
@@ -345,7 +347,8 @@ def cpu_baseline(insts, seconds):
         total_it += done
         sampled.append(inst.name)
     t_iter = sum(times) / len(times) * len(insts)
-    what = (f"first {total_it} iterations of Algorithm 1 from X_k = Lambda_k = 0 on "
+    what = (f"first {total_it} iterations of Algorithm {2 if algorithm == 'dual' else 1} from a "
+            f"zero state on "
             f"{len(sampled)} of {len(insts)} instance(s), FP64, setup excluded")
     if len(insts) > len(sampled):
         what += "; batch time per iteration extrapolated as mean x instance count"
@@ -364,6 +367,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="instances of the batched workload")
+    ap.add_argument("--algorithm", default="primal", choices=("primal", "dual"),
+                    help="Algorithm 1 (domain-space primal ADMM) or Algorithm 2 (range-space "
+                         "dual ADMM)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="start with a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
@@ -402,7 +408,8 @@ def main():
         print(f"[bench] {args.workload} {precision}: timing", file=sys.stderr, flush=True)
         forms[precision] = time_form(sdp, torch, insts, precision, args.steps, args.warmup,
                                      args.stage_iters, stream,
-                                     repeat_solve=args.workload not in ("batched", "large"))
+                                     repeat_solve=args.workload not in ("batched", "large"),
+                                     algorithm=args.algorithm)
         print(f"[bench] {args.workload} {precision}: {forms[precision]['iter_per_s']:.1f} iter/s",
               file=sys.stderr, flush=True)
     head = forms["fp32"]
@@ -426,7 +433,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(insts, args.cpu_seconds)
+        cpu = cpu_baseline(insts, args.cpu_seconds, args.algorithm)
 
     f32, f64 = forms["fp32"], forms.get("fp64")
     n_cl = sum(i.p for i in insts)
@@ -444,6 +451,8 @@ def main():
         "dtype": "fp32-eig/fp64-affine",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "precision": "fp32-eig/fp64-affine",
+                   "algorithm": {"primal": "Algorithm 1 (domain-space primal ADMM)",
+                                 "dual": "Algorithm 2 (range-space dual ADMM)"}[args.algorithm],
                    "tol": 1e-4, "rho": 1.0, "adaptive_rho": False, "instances": len(insts),
                    "n": [i.n for i in insts[:4]], "m": [i.m for i in insts[:4]],
                    "cliques": n_cl, "pattern_nnz": sum(i.nnz for i in insts)},

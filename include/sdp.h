@@ -55,6 +55,10 @@ enum { SDP_A_DENSE = 0, SDP_A_CSR = 1 };
  * multipliers and residuals are always FP64 */
 enum { SDP_FP64 = 0, SDP_FP32_EIG = 1 };
 enum { SDP_DTYPE_FP64 = 0, SDP_DTYPE_FP32 = 1 };
+/* which ADMM runs on the decomposed problem: Algorithm 1 (domain-space
+ * decomposition of the primal form, Section 4.1) or Algorithm 2 (range-space
+ * decomposition of the dual form, Section 4.2) */
+enum { SDP_ALG_PRIMAL = 0, SDP_ALG_DUAL = 1 };
 
 typedef struct sdp_handle sdp_handle;   /* opaque; owns every device buffer it allocates */
 
@@ -97,6 +101,11 @@ typedef struct {
   int32_t warm_start;           /* 1: each clique's eigen-solve starts from the eigenvector
                                    basis it ended with in the previous iteration (kept
                                    orthonormal on the device); 0: from the identity */
+  int32_t algorithm;            /* SDP_ALG_PRIMAL (Algorithm 1) or SDP_ALG_DUAL (Algorithm 2:
+                                   z_k = P+(v_k - lambda_k/rho), the KKT system with right-hand
+                                   sides c - sum H_k^T(z_k + lambda_k/rho) and -b/rho,
+                                   v_k = z_k + lambda_k/rho + H_k x, lambda_k += rho(z_k - v_k));
+                                   the same factor, kernels and stopping rule */
 } sdp_options;
 
 /* Per-instance result. */
@@ -104,7 +113,8 @@ typedef struct {
   int32_t iters;                /* iterations executed                        */
   int32_t status;               /* SDP_OK (converged) or SDP_MAX_ITER         */
   double eps_c, eps_lambda;     /* residuals of the last iteration            */
-  double objective;             /* <C, X> = sum_j w_j c_j u_j                  */
+  double objective;             /* Algorithm 1: <C, X> = sum_j w_j c_j u_j;
+                                   Algorithm 2: the dual objective b^T y       */
   double rho;                   /* penalty after the last iteration           */
   double eps_p, eps_d, eps_g;   /* primal/dual residuals and gap (NaN unless computed) */
   double eps_alpha;             /* PSD-completability violation (NaN unless computed) */
@@ -167,12 +177,15 @@ int sdp_psd_project_variant(int32_t variant, int32_t count, int32_t max_size,
 /* Copies instance `inst`'s iterate to host memory (any pointer may be NULL):
  * u[nnz_pattern] the lower values of X; y_dual[m] = -rho*y (the dual
  * multipliers of <A_i, X> = b_i); Xk/Lk the packed clique blocks of all p
- * cliques concatenated.  Synchronises. */
+ * cliques concatenated.  With SDP_ALG_DUAL: u = -rho x (the primal matrix
+ * estimate; x is the KKT variable of Algorithm 2), y_dual = y (the dual
+ * variable itself), Xk = z_k, Lk = lambda_k.  Synchronises. */
 int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual,
                      double *Xk_packed, double *Lk_packed);
 
 /* Overwrites instance `inst`'s clique blocks (packed, host memory) and its
- * penalty (rho > 0) -- a warm start.  Synchronises. */
+ * penalty (rho > 0) -- a warm start.  With SDP_ALG_DUAL the blocks are z_k
+ * and lambda_k, and the slack blocks v_k are set to z_k.  Synchronises. */
 int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk_packed,
                   const double *Lk_packed, double rho);
 
@@ -226,7 +239,8 @@ int sdp_update_data(sdp_handle *h, const double *c, const double *b);
 
 /* Runs the T unrolled iterations from the initial state, keeping X_k and
  * Lambda_k every ckpt_every iterations for the reverse sweep, and copies u_T
- * to u_out (DEVICE, concatenated layout; may be NULL).  Needs adaptive_rho = 0.
+ * to u_out (DEVICE, concatenated layout; may be NULL).  Needs adaptive_rho = 0
+ * and SDP_ALG_PRIMAL (SDP_ERR_UNSUPPORTED otherwise).
  * Leaves the handle at iterate T.  Synchronises. */
 int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u_out);
 

@@ -38,6 +38,7 @@ ERR_OOM = -9
 A_DENSE, A_CSR = 0, 1
 FP64, FP32_EIG = 0, 1
 DTYPE_FP64, DTYPE_FP32 = 0, 1
+ALG_PRIMAL, ALG_DUAL = 0, 1
 
 _p = C.c_void_p
 
@@ -54,7 +55,7 @@ class sdp_options(C.Structure):
                 ("precision", C.c_int32), ("adaptive_rho", C.c_int32), ("mu", C.c_double),
                 ("nu", C.c_double), ("rho_period", C.c_int32), ("graph_chunk", C.c_int32),
                 ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
-                ("autotune", C.c_int32), ("warm_start", C.c_int32)]
+                ("autotune", C.c_int32), ("warm_start", C.c_int32), ("algorithm", C.c_int32)]
 
 
 class sdp_result(C.Structure):
@@ -151,6 +152,8 @@ def make_options(**kw) -> sdp_options:
             v = None if v is None else C.c_void_p(int(v))
         elif k == "precision" and isinstance(v, str):
             v = {"fp64": FP64, "fp32": FP32_EIG, "fp32_eig": FP32_EIG}[v.lower()]
+        elif k == "algorithm" and isinstance(v, str):
+            v = {"primal": ALG_PRIMAL, "dual": ALG_DUAL}[v.lower()]
         setattr(o, k, v)
     return o
 

@@ -73,7 +73,9 @@ __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
     sl += __shfl_xor(sl, o, 64);
   }
   if (q == 0) {
-    const double bh = sx + (sl - a.c[j]) / rho;
+    // Algorithm 1: sum_k (x_k + lambda_k/rho) - c/rho; Algorithm 2 (x_k = z_k):
+    // c - sum_k (z_k + lambda_k/rho)
+    const double bh = a.dual ? a.c[j] - (sx + sl / rho) : sx + (sl - a.c[j]) / rho;
     a.bhat[j] = bh;
     a.v[j] = a.w[j] * bh / a.D[j];
   }
@@ -121,8 +123,10 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
 #pragma unroll
     for (int i = 0; i < ROW_NT / 64; ++i) s += red[i][r];
     const int64_t g = d.row_off + row0 + r;
-    if (a.Bm) a.y1[g] = s - a.bp[g];
-    else a.r[g] = s - a.b[g];
+    // Algorithm 2 solves with -b / rho in place of b
+    const double bs = a.dual ? -1.0 / a.state[inst].rho : 1.0;
+    if (a.Bm) a.y1[g] = s - bs * a.bp[g];
+    else a.r[g] = s - bs * a.b[g];
   }
 }
 
@@ -223,7 +227,8 @@ __global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
 #pragma unroll 4
   for (int64_t t = t0 + l; t < t1; t += 64) acc += a.a_val[t] * v[a.a_col[t]];
   acc = wave_sum(acc);
-  if (l == 0) a.r[d.row_off + row] = acc - a.b[d.row_off + row];
+  const double bs = a.dual ? -1.0 / a.state[inst].rho : 1.0;
+  if (l == 0) a.r[d.row_off + row] = acc - bs * a.b[d.row_off + row];
 }
 
 // Transposed products with sparse A: CSC_G consecutive lanes share a column
@@ -317,13 +322,18 @@ __global__ __launch_bounds__(RES_NT) void k_residual_reduce(AffineArgs a) {
 }
 
 // <C, X> = sum_j w_j c_j u_j per instance.
+// Algorithm 2: b^T y per instance (the dual objective).
 __global__ __launch_bounds__(256) void k_objective(AffineArgs a, double *obj) {
   const int inst = blockIdx.x;
   const InstDesc d = a.inst[inst];
   double s = 0.0;
-  for (int64_t j = threadIdx.x; j < d.ld; j += 256) {
-    const int64_t g = d.coord_off + j;
-    s += a.w[g] * a.c[g] * a.u[g];
+  if (a.dual) {
+    for (int64_t i = threadIdx.x; i < d.m; i += 256) s += a.b[d.row_off + i] * a.y[d.row_off + i];
+  } else {
+    for (int64_t j = threadIdx.x; j < d.ld; j += 256) {
+      const int64_t g = d.coord_off + j;
+      s += a.w[g] * a.c[g] * a.u[g];
+    }
   }
   __shared__ double red[4];
   s = wave_sum(s);
@@ -340,10 +350,14 @@ __global__ __launch_bounds__(256) void k_objective(AffineArgs a, double *obj) {
 __global__ __launch_bounds__(256) void k_diag_coord(AffineArgs a, DiagScratch s) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= a.ncoord) return;
+  // Algorithm 1: Z = sum_k H_k^T lambda_k and X = u;  Algorithm 2: Z = sum_k
+  // H_k^T z_k and the primal estimate X = -rho x
+  const double *zb = a.dual ? a.X : a.Lam;
   double z = 0.0;
-  for (int64_t t = a.contrib_ptr[j]; t < a.contrib_ptr[j + 1]; ++t) z += a.Lam[a.contrib_idx[t]];
+  for (int64_t t = a.contrib_ptr[j]; t < a.contrib_ptr[j + 1]; ++t) z += zb[a.contrib_idx[t]];
   s.z[j] = z;
-  s.wu[j] = a.w[j] * a.u[j];
+  const double xs = a.dual ? -a.state[a.coord_inst[j]].rho : 1.0;
+  s.wu[j] = a.w[j] * xs * a.u[j];
 }
 
 __global__ __launch_bounds__(256) void k_diag_rows(AffineArgs a, DiagScratch s, int64_t nrow) {
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(256) void k_diag_rows(AffineArgs a, DiagScratch s, 
   // instance of row i: rows are padded per instance, scan the descriptors
   int inst = 0;
   while (inst + 1 < a.batch && a.inst[inst + 1].row_off <= i) ++inst;
-  s.yd[i] = -a.state[inst].rho * a.y[i];
+  s.yd[i] = a.dual ? a.y[i] : -a.state[inst].rho * a.y[i];   // Algorithm 2: y itself
 }
 
 __global__ __launch_bounds__(256) void k_diag_reduce(AffineArgs a, DiagScratch s,
@@ -480,9 +494,10 @@ hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const 
   const int nb = (int)((a.ncoord + 255) / 256);
   hipLaunchKernelGGL(k_diag_coord, dim3(nb), dim3(256), 0, st, a, s);
   hipLaunchKernelGGL(k_diag_rows, dim3((nrow + 255) / 256), dim3(256), 0, st, a, s, nrow);
-  AffineArgs ar = a;          // A (w u) - b
+  AffineArgs ar = a;          // A (w u) - b with the problem's b
   ar.v = s.wu;
   ar.r = s.ax;
+  ar.dual = 0;
   if (ar.n_row_tiles > 0) {
     switch (ar.rows_per_tile) {
       case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;

@@ -153,8 +153,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
           } else {
             const int ii = i > k ? i : k, kk = i > k ? k : i;
             const int64_t g = off + (int64_t)ii * (ii + 1) / 2 + kk;
-            double wd = a.u[a.blk_loc[g]];
-            if (MODE == MODE_ADMM) wd -= a.Lam[g] / rho;
+            double wd;
+            if (MODE == MODE_ADMM && a.dual) {
+              wd = a.Vd[g] - a.Lam[g] / rho;                 // v_k - lambda_k / rho
+            } else {
+              wd = a.u[a.blk_loc[g]];
+              if (MODE == MODE_ADMM) wd -= a.Lam[g] / rho;   // H_k x - lambda_k / rho
+              if (MODE == MODE_MINEIG && a.dual) wd *= -rho; // primal estimate -rho x
+            }
             w = (T)wd;
           }
         }
@@ -423,6 +429,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     if (MODE == MODE_STANDALONE) {
       out[off + (int64_t)i * s + j] = acc;
       out[off + (int64_t)j * s + i] = acc;
+    } else if (a.dual) {
+      // Algorithm 2: z_k only; the multiplier and the other partials follow
+      // the affine step (launch_dual_update)
+      const int64_t g = off + e;
+      const double zo = a.X[g], zn = (double)acc;
+      a.X[g] = zn;
+      const double wt = (i == j) ? 1.0 : 2.0;
+      p3 += wt * (zn - zo) * (zn - zo);
     } else {
       const int64_t g = off + e;
       const double hu = a.u[a.blk_loc[g]];
@@ -448,9 +462,52 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     p4 = block_sum<NT>(p4, red);
     if (tid == 0) {
       double *pp = a.part + NPART * (int64_t)cl;
-      pp[0] = p0; pp[1] = p1; pp[2] = p2; pp[3] = p3; pp[4] = p4;
+      if (!a.dual) {
+        pp[0] = p0; pp[1] = p1; pp[2] = p2; pp[4] = p4;
+      }
+      pp[3] = p3;
       pp[5] = (double)sweep;
     }
+  }
+}
+
+// Algorithm 2, after the affine step: v_k and lambda_k on the packed lower
+// triangle of every clique, one workgroup per clique, with the partial sums
+// of DualConsensusResidual (full Frobenius norms: off-diagonal entries count
+// twice).
+__global__ __launch_bounds__(256) void k_dual_update(ProjArgs a) {
+  const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+  const int cl = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+  const int inst = a.cl_inst[cl];
+  if (a.state[inst].done) return;
+  const double rho = a.state[inst].rho;
+  const int s = a.cl_size[cl];
+  const int64_t off = a.cl_off[cl];
+  const int npk = s * (s + 1) / 2;
+  double p0 = 0, p1 = 0, p2 = 0, p4 = 0;
+  for (int e = threadIdx.x; e < npk; e += 256) {
+    int i, j;
+    tri_inv(e, i, j);
+    const int64_t g = off + e;
+    const double z = a.X[g], lo = a.Lam[g];
+    const double v = z + lo / rho + a.u[a.blk_loc[g]];
+    const double ln = lo + rho * (z - v);
+    a.Vd[g] = v;
+    a.Lam[g] = ln;
+    const double wt = (i == j) ? 1.0 : 2.0;
+    p0 += wt * (z - v) * (z - v);
+    p1 += wt * z * z;
+    p2 += wt * v * v;
+    p4 += wt * ln * ln;
+  }
+  __shared__ double red[4];
+  p0 = block_sum<256>(p0, red);
+  p1 = block_sum<256>(p1, red);
+  p2 = block_sum<256>(p2, red);
+  p4 = block_sum<256>(p4, red);
+  if (threadIdx.x == 0) {
+    double *pp = a.part + NPART * (int64_t)cl;
+    pp[0] = p0; pp[1] = p1; pp[2] = p2; pp[4] = p4;
   }
 }
 
@@ -524,6 +581,12 @@ __global__ __launch_bounds__(256) void k_identity_bases(T *vw, const int64_t *vw
 }
 
 }  // namespace
+
+hipError_t launch_dual_update(const ProjArgs &a, int64_t ncl, hipStream_t st) {
+  if (ncl <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dual_update, dim3((unsigned)ncl), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_identity_bases(int precision, void *vw, const int64_t *vw_off,
                                  const int32_t *cl_n, int64_t c0, int64_t count, hipStream_t st) {

@@ -299,6 +299,7 @@ struct sdp_handle {
   int32_t *d_t_rows_all = nullptr;       // (inst, row) over every row
   int n_t_rows_all = 0;
   double *d_ytmp = nullptr;              // row-space scratch for the scaled multiplier
+  double *d_utmp = nullptr;              // coordinate scratch (Algorithm 2: -rho x)
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
   hipGraphExec_t graph = nullptr;
@@ -329,11 +330,24 @@ struct sdp_handle {
 
 namespace {
 
-void enqueue_iteration(sdp_handle *h, hipStream_t st) {
-  HIPCHK(launch_iteration_affine(h->aff, st));
+void enqueue_projections(sdp_handle *h, const ProjArgs &p, hipStream_t st) {
   for (size_t b = 0; b < h->bucket_size.size(); ++b)
     HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                  h->bucket_count[b], h->proj, st));
+                                  h->bucket_count[b], p, st));
+}
+
+// Algorithm 1: x-update (affine), projections with the multiplier update,
+// residuals.  Algorithm 2: z-update (projections), (y, x) from the KKT
+// system, v and multiplier updates, residuals.
+void enqueue_iteration(sdp_handle *h, hipStream_t st) {
+  if (h->proj.dual) {
+    enqueue_projections(h, h->proj, st);
+    HIPCHK(launch_iteration_affine(h->aff, st));
+    HIPCHK(launch_dual_update(h->proj, h->ncl, st));
+  } else {
+    HIPCHK(launch_iteration_affine(h->aff, st));
+    enqueue_projections(h, h->proj, st);
+  }
   HIPCHK(launch_residual_reduce(h->aff, st));
 }
 
@@ -409,7 +423,10 @@ void pull_state(sdp_handle *h) {
   HIPCHK(hipStreamSynchronize(h->stream));
 }
 
+void ensure_y(sdp_handle *h);
+
 void fill_results(sdp_handle *h, sdp_result *res) {
+  if (h->aff.dual) ensure_y(h);   // the dual objective b^T y
   HIPCHK(launch_objective(h->aff, h->d_obj, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_obj, h->d_obj, sizeof(double) * h->B, hipMemcpyDeviceToHost,
                         h->stream));
@@ -447,6 +464,7 @@ void reset_state(sdp_handle *h) {
   HIPCHK(hipMemset(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
   HIPCHK(hipMemset(h->aff.u, 0, sizeof(double) * h->ncoord));
   HIPCHK(hipMemset(h->aff.y, 0, sizeof(double) * h->nrow));
+  if (h->proj.Vd) HIPCHK(hipMemset(h->proj.Vd, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
   if (h->d_vw) {
     HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N, 0, h->ncl,
                                  h->stream));
@@ -480,6 +498,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
   if (opt_in) opt = *opt_in;
   if (!(opt.rho > 0) || !(opt.tol >= 0) || opt.max_iter <= 0 ||
       (opt.precision != SDP_FP64 && opt.precision != SDP_FP32_EIG) ||
+      (opt.algorithm != SDP_ALG_PRIMAL && opt.algorithm != SDP_ALG_DUAL) ||
       (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
       opt.graph_chunk < 0)
     fail(SDP_ERR_ARG, "invalid options");
@@ -795,6 +814,11 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     p.state = h->d_state;
     p.max_sweeps = h->max_sweeps;
     p.tol = h->jac_tol;
+    p.dual = a.dual = opt.algorithm == SDP_ALG_DUAL ? 1 : 0;
+    if (p.dual) {
+      p.Vd = dev_zeros<double>(pk, own);
+      h->d_utmp = dev_zeros<double>(coord, own);
+    }
 
     a.X = p.X;
     a.Lam = p.Lam;
@@ -946,6 +970,7 @@ void sdp_default_options(sdp_options *opt) {
   opt->jacobi_tol = 0.0;
   opt->autotune = 1;
   opt->warm_start = 1;
+  opt->algorithm = SDP_ALG_PRIMAL;
 }
 
 int sdp_setup(int32_t batch, const sdp_instance *inst, const sdp_options *opt, sdp_handle **out) {
@@ -1068,14 +1093,27 @@ int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual, dou
   return guarded([&] {
     if (!h || inst < 0 || inst >= h->B) fail(SDP_ERR_ARG, "invalid handle or instance");
     const InstDesc &d = h->desc[inst];
+    const bool dual = h->aff.dual != 0;
     HIPCHK(hipStreamSynchronize(h->stream));
-    if (u) HIPCHK(hipMemcpy(u, h->aff.u + d.coord_off, sizeof(double) * d.nnz, hipMemcpyDeviceToHost));
+    if (u) {
+      const double *src = h->aff.u + d.coord_off;
+      if (dual) {   // the primal estimate -rho x
+        HIPCHK(launch_scaled_copy(src, h->d_utmp + d.coord_off, d.nnz, h->d_state, inst,
+                                  h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        src = h->d_utmp + d.coord_off;
+      }
+      HIPCHK(hipMemcpy(u, src, sizeof(double) * d.nnz, hipMemcpyDeviceToHost));
+    }
     if (y_dual) {
       ensure_y(h);
-      HIPCHK(launch_scaled_copy(h->aff.y + d.row_off, h->d_ytmp + d.row_off, d.m, h->d_state, inst,
-                                h->stream));
+      const double *src = h->aff.y + d.row_off;
+      if (!dual) {  // the multipliers of <A_i, X> = b_i: -rho y
+        HIPCHK(launch_scaled_copy(src, h->d_ytmp + d.row_off, d.m, h->d_state, inst, h->stream));
+        src = h->d_ytmp + d.row_off;
+      }
       HIPCHK(hipStreamSynchronize(h->stream));
-      HIPCHK(hipMemcpy(y_dual, h->d_ytmp + d.row_off, sizeof(double) * d.m, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(y_dual, src, sizeof(double) * d.m, hipMemcpyDeviceToHost));
     }
     const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
     if (Xk) HIPCHK(hipMemcpy(Xk, h->proj.X + o, sizeof(double) * n, hipMemcpyDeviceToHost));
@@ -1091,6 +1129,8 @@ int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *L
     const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
     if (Xk) HIPCHK(hipMemcpy(h->proj.X + o, Xk, sizeof(double) * n, hipMemcpyHostToDevice));
     if (Lk) HIPCHK(hipMemcpy(h->proj.Lam + o, Lk, sizeof(double) * n, hipMemcpyHostToDevice));
+    if (h->proj.Vd)   // Algorithm 2: the slack blocks start at consensus, v_k = z_k
+      HIPCHK(hipMemcpy(h->proj.Vd + o, h->proj.X + o, sizeof(double) * n, hipMemcpyDeviceToDevice));
     if (h->d_vw) {
       HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N,
                                    h->cl_first[inst], h->cl_first[inst + 1] - h->cl_first[inst],
@@ -1198,9 +1238,8 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
           if (s < 5) {
             HIPCHK(launch_affine_stage(h->aff, s, h->stream));
           } else if (s == 5) {
-            for (size_t b = 0; b < h->bucket_size.size(); ++b)
-              HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                            h->bucket_count[b], h->proj, h->stream));
+            enqueue_projections(h, h->proj, h->stream);
+            if (h->proj.dual) HIPCHK(launch_dual_update(h->proj, h->ncl, h->stream));
           } else {
             HIPCHK(launch_residual_reduce(h->aff, h->stream));
           }
@@ -1243,6 +1282,8 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
   return guarded([&] {
     if (!h || T <= 0 || ckpt_every <= 0) fail(SDP_ERR_ARG, "invalid arguments");
     if (h->opt.adaptive_rho) fail(SDP_ERR_ARG, "unrolled differentiation needs a fixed rho");
+    if (h->proj.dual)
+      fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
     const int nseg = (T + ckpt_every - 1) / ckpt_every;
     const int64_t need = (int64_t)nseg * 2 * std::max<int64_t>(h->npk, 1);
     if (need > h->ckpt_cap) {
@@ -1279,6 +1320,8 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
 int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, int32_t euclidean) {
   return guarded([&] {
     if (!h || !u_bar || !c_bar || !b_bar) fail(SDP_ERR_ARG, "invalid arguments");
+    if (h->proj.dual)
+      fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
     if (h->adj_T <= 0) fail(SDP_ERR_ARG, "run sdp_unrolled_forward first");
     if (!h->adj_ready)
       fail(SDP_ERR_UNSUPPORTED, "the projection adjoint supports cliques up to 64 vertices");

@@ -75,6 +75,11 @@ struct ProjArgs {
   const int64_t *eig_off; // element offset of each clique's record in eig
   void *vw;               // optional: per clique N x N eigenvector basis (warm start), T
   const int64_t *vw_off;  // element offset of each clique's basis in vw
+  // Algorithm 2 (range-space dual ADMM): X holds z_k, Lam holds lambda_k and
+  // Vd the slack blocks v_k (packed lower, like X); the projection input is
+  // v_k - lambda_k / rho and the multiplier update runs in launch_dual_update
+  int dual;
+  double *Vd;
 };
 
 // Kernel variants (padded size N, threads NT): ids are per precision.
@@ -98,7 +103,14 @@ hipError_t launch_standalone_projection(int dtype, int variant, int count,
                                         const void *in, void *out, int max_sweeps,
                                         double tol, hipStream_t st);
 
-// Minimum eigenvalue of each E_k U E_k^T (for eps_alpha); FP64.
+// Algorithm 2: v_k = z_k + lambda_k / rho + H_k x (vkEqn), lambda_k += rho
+// (z_k - v_k) (MultUpdateDualSDP) and the residual partials ||z - v||^2,
+// ||z||^2, ||v||^2, ||lambda||^2 of every clique (||z - z_prev||^2 and the
+// sweeps come from the projection).  x is a.u.
+hipError_t launch_dual_update(const ProjArgs &a, int64_t ncl, hipStream_t st);
+
+// Minimum eigenvalue of each E_k U E_k^T (for eps_alpha; with a.dual of
+// E_k (-rho x) E_k^T); FP64.
 hipError_t launch_min_eig(int precision, int variant, const int32_t *list, int count,
                           const ProjArgs &a, double *lmin_out, hipStream_t st);
 
@@ -144,6 +156,7 @@ struct AffineArgs {
   double *hist;                               // B x hist_cap x 3
   int batch;
   int ignore_done;                            // diagnostics: run on frozen instances too
+  int dual;                                   // Algorithm 2: right-hand sides c - sum(z + lambda/rho), -b/rho
 };
 
 // Scratch of the diagnostics pass (allocated on first use).
