@@ -60,6 +60,14 @@ def _load():
     lib.orc_dual_objective.restype = C.c_double
     lib.orc_get_vd.argtypes = [C.c_void_p, _dp]
     lib.orc_set_vd.argtypes = [C.c_void_p, _dp]
+    lib.orc_hsde_setup.argtypes = [C.c_void_p]
+    lib.orc_hsde_setup.restype = C.c_int
+    lib.orc_run_hsde.argtypes = [C.c_void_p, C.c_int, C.c_double, _ip, _dp, _dp]
+    lib.orc_run_hsde.restype = C.c_int
+    lib.orc_hsde_get.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_hsde_inner.argtypes = [C.c_void_p] + [_dp] * 8
+    lib.orc_hsde_set.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double]
+    lib.orc_hsde_raw.argtypes = [C.c_void_p, _dp, _dp]
     lib.orc_jacobi_eig.argtypes = [C.c_int, _dp, _dp, _dp, C.c_int, C.c_double]
     lib.orc_jacobi_eig.restype = C.c_int
     lib.orc_psd_project.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.c_double]
@@ -170,6 +178,11 @@ def chol_solve(L, r):
 # Whole-problem oracle
 # --------------------------------------------------------------------------
 
+class HsdeResult:
+    def __init__(self, status, iters, hist_e, hist_c):
+        self.status, self.iters, self.hist_e, self.hist_c = status, iters, hist_e, hist_c
+
+
 @dataclass
 class RunResult:
     status: int
@@ -252,6 +265,58 @@ class Problem:
         V = np.zeros(n)
         _load().orc_get_vd(self._h, _d(V))
         return self._split(V)
+
+    # ---- Algorithm 3 (HSDE) ----
+    def hsde_setup(self):
+        """Factor I + A W P^-1 A^T, form M^-1 zeta; u = v = (0, ..., 0, 1)."""
+        return int(_load().orc_hsde_setup(self._h))
+
+    def run_hsde(self, max_iter, tol=1e-4):
+        """Algorithm 3; status 0 solved, 1 iteration limit, 2 primal
+        infeasible, 3 dual infeasible; hist_e = max(eps_p, eps_d, eps_g),
+        hist_c = eps_c per iteration."""
+        lib = _load()
+        he = np.zeros(max(max_iter, 1))
+        hc = np.zeros(max(max_iter, 1))
+        it = C.c_int(0)
+        st = lib.orc_run_hsde(self._h, int(max_iter), float(tol), C.byref(it), _d(he), _d(hc))
+        k = it.value
+        return HsdeResult(st, k, he[:k], hc[:k])
+
+    def hsde_solution(self):
+        n = int(_load().orc_nblk(self._h))
+        x, y = np.zeros(self.nnz), np.zeros(max(self.m, 1))
+        S, Z, T, out = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(6)
+        _load().orc_hsde_get(self._h, _d(x), _d(y), _d(S), _d(Z), _d(T), _d(out))
+        return dict(x=x, y=y[:self.m], s=self._split(S), z=self._split(Z), t=self._split(T),
+                    tau=out[0], kappa=out[1], eps_p=out[2], eps_d=out[3], eps_g=out[4],
+                    eps_c=out[5])
+
+    def hsde_raw(self):
+        """u_x and u_y (not divided by tau)."""
+        x, y = np.zeros(self.nnz), np.zeros(max(self.m, 1))
+        _load().orc_hsde_raw(self._h, _d(x), _d(y))
+        return x, y[:self.m]
+
+    def hsde_set(self, ux, us, uy, ut, vz, tau, kappa):
+        cat = lambda bl: np.ascontiguousarray(np.concatenate([np.asarray(b, float).ravel()
+                                                              for b in bl]))
+        a = [np.ascontiguousarray(ux, float), cat(us), np.ascontiguousarray(uy, float),
+             cat(ut), cat(vz)]
+        _load().orc_hsde_set(self._h, *[_d(v) for v in a], float(tau), float(kappa))
+
+    def hsde_inner(self, nx, ns, ny, nt):
+        """sigma = M^-1 nu for the inner system of Section 5.2.2."""
+        n = int(_load().orc_nblk(self._h))
+        cat = lambda bl: np.ascontiguousarray(np.concatenate([np.asarray(b, float).ravel()
+                                                              for b in bl]))
+        nx, ny = np.ascontiguousarray(nx, float), np.ascontiguousarray(ny, float)
+        ns, nt = cat(ns), cat(nt)
+        sx, sy = np.zeros(self.nnz), np.zeros(max(self.m, 1))
+        ss, st = np.zeros(n), np.zeros(n)
+        _load().orc_hsde_inner(self._h, _d(nx), _d(ns), _d(ny), _d(nt), _d(sx), _d(ss), _d(sy),
+                               _d(st))
+        return sx, self._split(ss), sy[:self.m], self._split(st)
 
     def set_v_blocks(self, Vs):
         V = np.concatenate([np.asarray(v, dtype=np.float64).ravel() for v in Vs])

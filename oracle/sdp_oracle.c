@@ -97,6 +97,14 @@ typedef struct orc_problem {
   double rho;
   double *X, *Lam, *Xprev;
   double *Vd;         /* Algorithm 2: the slack blocks v_k (X holds z_k)      */
+  /* Algorithm 3 (HSDE): factor of I + A W P^-1 A^T with P = I + D/2, the
+   * iterates u = (x, s, y, t, tau), v = (0, z, 0, 0, kappa) and M^-1 zeta */
+  double *Lh, *hP;
+  double *ux, *us, *uy, *ut, *vz, utau, kappa;
+  double *mzx, *mzs, *mzy, *mzt, kz;
+  double *hx, *hs, *hy, *ht, *hx2, *hs2, *hy2, *ht2;   /* work */
+  double eps_p, eps_d, eps_g;
+  int hsde_status;
   double *u, *y, *bhat, *r, *tmp;
   int64_t nblk;       /* sum s_k^2 */
   int iters;
@@ -309,6 +317,50 @@ static void at_times(const orc_problem *P, const double *y, double *out) {
   }
 }
 
+/* M = A diag(wd) A^T (m x m, row-major, both triangles), summing over the
+ * compact coordinates j in increasing order. */
+static void assemble_gram(const orc_problem *P, const double *wd, double *M) {
+  const int m = P->m;
+  const int64_t nnz = P->nnz;
+  if (P->a_format == 0) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < m; ++i) {
+      const double *ri = P->a_val + (size_t)i * nnz;
+      for (int k = 0; k <= i; ++k) {
+        const double *rk = P->a_val + (size_t)k * nnz;
+        double acc = 0.0;
+        for (int64_t j = 0; j < nnz; ++j) acc += ri[j] * wd[j] * rk[j];
+        M[(size_t)i * m + k] = acc;
+        M[(size_t)k * m + i] = acc;
+      }
+    }
+    return;
+  }
+  /* the same sums skipping the zero terms */
+  const int64_t annz = P->a_rowptr[m];
+  int64_t *cptrA = (int64_t *)calloc(nnz + 1, sizeof(int64_t));
+  for (int64_t t = 0; t < annz; ++t) cptrA[P->a_col[t] + 1]++;
+  for (int64_t j = 0; j < nnz; ++j) cptrA[j + 1] += cptrA[j];
+  int *rowA = (int *)malloc(sizeof(int) * (annz > 0 ? annz : 1));
+  double *valA = (double *)malloc(sizeof(double) * (annz > 0 ? annz : 1));
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * nnz);
+  memcpy(fill, cptrA, sizeof(int64_t) * nnz);
+  for (int i = 0; i < m; ++i)
+    for (int64_t t = P->a_rowptr[i]; t < P->a_rowptr[i + 1]; ++t) {
+      int64_t pos = fill[P->a_col[t]]++;
+      rowA[pos] = i; valA[pos] = P->a_val[t];
+    }
+  for (int64_t j = 0; j < nnz; ++j)
+    for (int64_t s1 = cptrA[j]; s1 < cptrA[j + 1]; ++s1)
+      for (int64_t s2 = cptrA[j]; s2 <= s1; ++s2) {
+        int i = rowA[s1], k = rowA[s2];
+        M[(size_t)i * m + k] += valA[s1] * wd[j] * valA[s2];
+      }
+  for (int i = 0; i < m; ++i)
+    for (int k = 0; k < i; ++k) M[(size_t)k * m + i] = M[(size_t)i * m + k];
+  free(cptrA); free(rowA); free(valA); free(fill);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Set-up (Algorithm 1, data preprocessing)                                   */
 /* ------------------------------------------------------------------------- */
@@ -319,6 +371,10 @@ void orc_free(orc_problem *P) {
   free(P->blk_off); free(P->loc); free(P->D); free(P->w);
   free(P->a_rowptr); free(P->a_col); free(P->a_val); free(P->b); free(P->c);
   free(P->L); free(P->X); free(P->Lam); free(P->Xprev); free(P->Vd);
+  free(P->Lh); free(P->hP); free(P->ux); free(P->us); free(P->uy); free(P->ut); free(P->vz);
+  free(P->mzx); free(P->mzs); free(P->mzy); free(P->mzt);
+  free(P->hx); free(P->hs); free(P->hy); free(P->ht);
+  free(P->hx2); free(P->hs2); free(P->hy2); free(P->ht2);
   free(P->u); free(P->y); free(P->bhat); free(P->r); free(P->tmp);
   free(P);
 }
@@ -453,43 +509,11 @@ int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col
   /* M = A W D^-1 A^T (the matrix A D^-1 A^T of ADMMprimalFatorization on the
    * compact coordinates), then M = L L^T. */
   double *M = (double *)calloc((size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1), sizeof(double));
-  if (a_format == 0) {
-#pragma omp parallel for schedule(dynamic, 4)
-    for (int i = 0; i < m; ++i) {
-      const double *ri = P->a_val + (size_t)i * nnz;
-      for (int k = 0; k <= i; ++k) {
-        const double *rk = P->a_val + (size_t)k * nnz;
-        double acc = 0.0;
-        for (int64_t j = 0; j < nnz; ++j) acc += ri[j] * (P->w[j] / P->D[j]) * rk[j];
-        M[(size_t)i * m + k] = acc;
-        M[(size_t)k * m + i] = acc;
-      }
-    }
-  } else {
-    /* the same sum over j in increasing order, skipping the zero terms */
-    int64_t *cptrA = (int64_t *)calloc(nnz + 1, sizeof(int64_t));
-    for (int64_t t = 0; t < annz; ++t) cptrA[P->a_col[t] + 1]++;
-    for (int64_t j = 0; j < nnz; ++j) cptrA[j + 1] += cptrA[j];
-    int *rowA = (int *)malloc(sizeof(int) * (annz > 0 ? annz : 1));
-    double *valA = (double *)malloc(sizeof(double) * (annz > 0 ? annz : 1));
-    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * nnz);
-    memcpy(fill, cptrA, sizeof(int64_t) * nnz);
-    for (int i = 0; i < m; ++i)
-      for (int64_t t = P->a_rowptr[i]; t < P->a_rowptr[i + 1]; ++t) {
-        int64_t pos = fill[P->a_col[t]]++;
-        rowA[pos] = i; valA[pos] = P->a_val[t];
-      }
-    for (int64_t j = 0; j < nnz; ++j) {
-      double wd = P->w[j] / P->D[j];
-      for (int64_t s1 = cptrA[j]; s1 < cptrA[j + 1]; ++s1)
-        for (int64_t s2 = cptrA[j]; s2 <= s1; ++s2) {
-          int i = rowA[s1], k = rowA[s2];
-          M[(size_t)i * m + k] += valA[s1] * wd * valA[s2];
-        }
-    }
-    for (int i = 0; i < m; ++i)
-      for (int k = 0; k < i; ++k) M[(size_t)k * m + i] = M[(size_t)i * m + k];
-    free(cptrA); free(rowA); free(valA); free(fill);
+  {
+    double *wd = (double *)malloc(sizeof(double) * nnz);
+    for (int64_t j = 0; j < nnz; ++j) wd[j] = P->w[j] / P->D[j];
+    assemble_gram(P, wd, M);
+    free(wd);
   }
   P->L = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
   rc = orc_cholesky(m, M, P->L);
@@ -740,6 +764,301 @@ int orc_run_dual(orc_problem *P, int max_iter, double tol, int adaptive, double 
   if (iters_done) *iters_done = it;
   free(part); free(sweeps); free(bvec);
   return done ? ORC_OK : ORC_MAX_ITER;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 3: ADMM for the homogeneous self-dual embedding (Section 5)      */
+/* ------------------------------------------------------------------------- */
+/* Vectors over the pattern are compact lower coordinates: the paper's
+ * Euclidean products on vec(X) become sums weighted by w (1 on the diagonal,
+ * 2 off it), A x becomes A (w .* x), and the identity stays the identity.
+ * Clique blocks s, t, z are full s_k x s_k matrices (plain Frobenius
+ * products). */
+
+/* sum over the lower entries of every clique block into the coordinates:
+ * the compact form of H^T applied to blocks (increasing k) */
+static void h_transpose(const orc_problem *P, const double *blocks, double *out) {
+  for (int64_t j = 0; j < P->nnz; ++j) out[j] = 0.0;
+  for (int k = 0; k < P->p; ++k) {
+    int s = P->cptr[k + 1] - P->cptr[k];
+    int64_t o = P->blk_off[k];
+    for (int a = 0; a < s; ++a)
+      for (int bb = 0; bb <= a; ++bb) {
+        int64_t e = o + (int64_t)a * s + bb;
+        out[P->loc[e]] += blocks[e];
+      }
+  }
+}
+
+static double wdot(const orc_problem *P, const double *a, const double *b) {
+  double acc = 0.0;
+  for (int64_t j = 0; j < P->nnz; ++j) acc += P->w[j] * a[j] * b[j];
+  return acc;
+}
+
+/* The "inner" system M sigma = nu with M = [[I, -Ahat^T], [Ahat, I]],
+ * Ahat = [[A, 0], [H, -I]] (SecondBlockElimination), by the two block
+ * eliminations and the matrix inversion lemma of Section 5.2.2:
+ *   nu_x' = nu_x + H^T (nu_s + nu_t) / 2
+ *   g     = (I + A P^-1 A^T)^-1 (A P^-1 nu_x' - nu_y)
+ *   sigma_x = P^-1 (nu_x' - A^T g),  sigma_y = -g
+ *   sigma_s = (nu_s - nu_t + H sigma_x) / 2,  sigma_t = sigma_s - H sigma_x + nu_t */
+static void hsde_inner(orc_problem *P, const double *nx, const double *ns, const double *ny,
+                       const double *nt, double *sx, double *ss, double *sy, double *st) {
+  const int64_t nnz = P->nnz, nb = P->nblk;
+  double *sum = (double *)malloc(sizeof(double) * nb);
+  double *xp = (double *)malloc(sizeof(double) * nnz);
+  double *tmp = (double *)malloc(sizeof(double) * nnz);
+  double *r = (double *)malloc(sizeof(double) * (P->m > 0 ? P->m : 1));
+  for (int64_t e = 0; e < nb; ++e) sum[e] = 0.5 * (ns[e] + nt[e]);
+  h_transpose(P, sum, xp);
+  for (int64_t j = 0; j < nnz; ++j) xp[j] += nx[j];
+  for (int64_t j = 0; j < nnz; ++j) tmp[j] = P->w[j] * xp[j] / P->hP[j];
+  a_times(P, tmp, r);
+  for (int i = 0; i < P->m; ++i) r[i] -= ny[i];
+  orc_chol_solve(P->m, P->Lh, r, sy);            /* g, stored in sy for now */
+  at_times(P, sy, tmp);
+  for (int64_t j = 0; j < nnz; ++j) sx[j] = (xp[j] - tmp[j]) / P->hP[j];
+  for (int i = 0; i < P->m; ++i) sy[i] = -sy[i];
+  for (int k = 0; k < P->p; ++k) {
+    int s = P->cptr[k + 1] - P->cptr[k];
+    int64_t o = P->blk_off[k];
+    for (int e = 0; e < s * s; ++e) {
+      const double hx = sx[P->loc[o + e]];
+      ss[o + e] = 0.5 * (ns[o + e] - nt[o + e] + hx);
+      st[o + e] = ss[o + e] - hx + nt[o + e];
+    }
+  }
+  free(sum); free(xp); free(tmp); free(r);
+}
+
+/* zeta^T (x, s, y, t) with zeta = (c, 0, -b, 0) */
+static double zeta_dot(const orc_problem *P, const double *x, const double *y) {
+  double acc = wdot(P, P->c, x);
+  for (int i = 0; i < P->m; ++i) acc -= P->b[i] * y[i];
+  return acc;
+}
+
+/* Data preprocessing of Algorithm 3: factor I + A W P^-1 A^T
+ * (HSDEFactorizationFinal on compact coordinates), M^-1 zeta and
+ * 1 / (1 + zeta^T M^-1 zeta); u = (0, 0, 0, 0, 1), v = (0, 0, 0, 0, 1). */
+int orc_hsde_setup(orc_problem *P) {
+  const int m = P->m;
+  const int64_t nnz = P->nnz, nb = P->nblk;
+  if (!P->Lh) {
+    double *wd = (double *)malloc(sizeof(double) * nnz);
+    P->hP = (double *)malloc(sizeof(double) * nnz);
+    for (int64_t j = 0; j < nnz; ++j) {
+      P->hP[j] = 1.0 + 0.5 * P->D[j];
+      wd[j] = P->w[j] / P->hP[j];
+    }
+    double *M = (double *)calloc((size_t)m * m, sizeof(double));
+    assemble_gram(P, wd, M);
+    for (int i = 0; i < m; ++i) M[(size_t)i * m + i] += 1.0;
+    P->Lh = (double *)malloc(sizeof(double) * (size_t)m * m);
+    int rc = orc_cholesky(m, M, P->Lh);
+    free(M); free(wd);
+    if (rc != ORC_OK) return rc;
+    P->ux = (double *)calloc(nnz, sizeof(double)); P->us = (double *)calloc(nb, sizeof(double));
+    P->uy = (double *)calloc(m, sizeof(double));   P->ut = (double *)calloc(nb, sizeof(double));
+    P->vz = (double *)calloc(nb, sizeof(double));
+    P->mzx = (double *)calloc(nnz, sizeof(double)); P->mzs = (double *)calloc(nb, sizeof(double));
+    P->mzy = (double *)calloc(m, sizeof(double));   P->mzt = (double *)calloc(nb, sizeof(double));
+    P->hx = (double *)calloc(nnz, sizeof(double)); P->hs = (double *)calloc(nb, sizeof(double));
+    P->hy = (double *)calloc(m, sizeof(double));   P->ht = (double *)calloc(nb, sizeof(double));
+    P->hx2 = (double *)calloc(nnz, sizeof(double)); P->hs2 = (double *)calloc(nb, sizeof(double));
+    P->hy2 = (double *)calloc(m, sizeof(double));   P->ht2 = (double *)calloc(nb, sizeof(double));
+    /* M^-1 zeta: nu = (c, 0, -b, 0) */
+    double *zs = (double *)calloc(nb, sizeof(double));
+    double *zy = (double *)malloc(sizeof(double) * m);
+    for (int i = 0; i < m; ++i) zy[i] = -P->b[i];
+    hsde_inner(P, P->c, zs, zy, zs, P->mzx, P->mzs, P->mzy, P->mzt);
+    P->kz = 1.0 / (1.0 + zeta_dot(P, P->mzx, P->mzy));
+    free(zs); free(zy);
+  }
+  memset(P->ux, 0, sizeof(double) * nnz); memset(P->us, 0, sizeof(double) * nb);
+  memset(P->uy, 0, sizeof(double) * m);   memset(P->ut, 0, sizeof(double) * nb);
+  memset(P->vz, 0, sizeof(double) * nb);
+  P->utau = 1.0;
+  P->kappa = 1.0;
+  P->iters = 0;
+  P->eps_c = P->eps_l = P->eps_p = P->eps_d = P->eps_g = INFINITY;
+  P->hsde_status = ORC_MAX_ITER;
+  P->total_sweeps = 0;
+  P->max_sweeps_seen = 0;
+  return ORC_OK;
+}
+
+static double cratio(double num, double a, double b) {
+  double den = a > b ? a : b;
+  if (den > 0.0) return num / den;
+  return (num == 0.0) ? 0.0 : INFINITY;
+}
+
+/* Runs up to max_iter iterations of Algorithm 3 (after orc_hsde_setup):
+ *   u_hat = (I + Q)^-1 (u + v)       (HsdeStep1: LinearSystem, MatrixInverseResult,
+ *                                     FirstBlockElimination, hsde_inner)
+ *   u = P_K(u_hat - v)               (HsdeStep2: x, y, t free, s in the PSD cones
+ *                                     of the cliques, tau >= 0)
+ *   v = v - u_hat + u                (HsdeStep3; only z and kappa are nonzero)
+ * then, with tau > 0, the residuals HSDEerror and the consensus residual
+ * (the larger of PrimalConsensusResidual on (s, H x) and DualConsensusResidual
+ * on (z, t)); with tau = 0 the two infeasibility tests of Infeasibility.
+ * Returns ORC_OK (solved), 2 (primal infeasible), 3 (dual infeasible) or
+ * ORC_MAX_ITER.  Optional histories of max(eps_p, eps_d, eps_g) and eps_c. */
+int orc_run_hsde(orc_problem *P, int max_iter, double tol, int *iters_done, double *hist_e,
+                 double *hist_c) {
+  const int m = P->m, p = P->p;
+  const int64_t nnz = P->nnz, nb = P->nblk;
+  double nb2 = 0.0, nc2 = wdot(P, P->c, P->c);
+  for (int i = 0; i < m; ++i) nb2 += P->b[i] * P->b[i];
+  const double nrm_b = sqrt(nb2), nrm_c = sqrt(nc2);
+  double *hxs = (double *)malloc(sizeof(double) * nb);
+  double *ax = (double *)malloc(sizeof(double) * (m > 0 ? m : 1));
+  double *aty = (double *)malloc(sizeof(double) * nnz);
+  double *zc = (double *)malloc(sizeof(double) * nnz);
+  double *tmp = (double *)malloc(sizeof(double) * nnz);
+  int *sweeps = (int *)calloc(p, sizeof(int));
+  int status = ORC_MAX_ITER, it;
+  for (it = 0; it < max_iter; ++it) {
+    /* omega = u + v; nu = omega_1 - omega_2 zeta */
+    const double w2 = P->utau + P->kappa;
+    for (int64_t j = 0; j < nnz; ++j) P->hx[j] = P->ux[j] - w2 * P->c[j];
+    for (int64_t e = 0; e < nb; ++e) P->hs[e] = P->us[e] + P->vz[e];
+    for (int i = 0; i < m; ++i) P->hy[i] = P->uy[i] + w2 * P->b[i];
+    memcpy(P->ht, P->ut, sizeof(double) * nb);
+    /* sigma = M^-1 nu; u_hat_1 = sigma - M^-1 zeta (zeta^T sigma) / (1 + zeta^T M^-1 zeta) */
+    hsde_inner(P, P->hx, P->hs, P->hy, P->ht, P->hx2, P->hs2, P->hy2, P->ht2);
+    const double f = P->kz * zeta_dot(P, P->hx2, P->hy2);
+    for (int64_t j = 0; j < nnz; ++j) P->hx2[j] -= f * P->mzx[j];
+    for (int64_t e = 0; e < nb; ++e) { P->hs2[e] -= f * P->mzs[e]; P->ht2[e] -= f * P->mzt[e]; }
+    for (int i = 0; i < m; ++i) P->hy2[i] -= f * P->mzy[i];
+    const double uhat_tau = w2 + zeta_dot(P, P->hx2, P->hy2);
+    /* u = P_K(u_hat - v), v = v - u_hat + u */
+    memcpy(P->ux, P->hx2, sizeof(double) * nnz);
+    memcpy(P->uy, P->hy2, sizeof(double) * m);
+    memcpy(P->ut, P->ht2, sizeof(double) * nb);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < p; ++k) {
+      int s = P->cptr[k + 1] - P->cptr[k];
+      int64_t o = P->blk_off[k];
+      double *Wk = (double *)malloc(sizeof(double) * s * s);
+      for (int e = 0; e < s * s; ++e) Wk[e] = P->hs2[o + e] - P->vz[o + e];
+      sweeps[k] = orc_psd_project(s, Wk, P->us + o, NULL, NULL, P->jac_max_sweeps, P->jac_tol);
+      for (int e = 0; e < s * s; ++e) P->vz[o + e] += P->us[o + e] - P->hs2[o + e];
+      free(Wk);
+    }
+    const double tau_new = uhat_tau - P->kappa > 0.0 ? uhat_tau - P->kappa : 0.0;
+    P->kappa += tau_new - uhat_tau;
+    P->utau = tau_new;
+    for (int k = 0; k < p; ++k) {
+      P->total_sweeps += sweeps[k];
+      if (sweeps[k] > P->max_sweeps_seen) P->max_sweeps_seen = sweeps[k];
+    }
+    P->iters++;
+    /* stopping conditions */
+    double crit;
+    for (int64_t j = 0; j < nnz; ++j) tmp[j] = P->w[j] * P->ux[j];
+    a_times(P, tmp, ax);                       /* A u_x */
+    h_transpose(P, P->vz, zc);                 /* H^T v_z */
+    at_times(P, P->uy, aty);                   /* A^T u_y */
+    if (P->utau > 0.0) {
+      const double tau = P->utau;
+      double rp = 0.0, rd = 0.0;
+      for (int i = 0; i < m; ++i) { double d = ax[i] / tau - P->b[i]; rp += d * d; }
+      for (int64_t j = 0; j < nnz; ++j) {
+        double d = (aty[j] + zc[j]) / tau - P->c[j];
+        rd += P->w[j] * d * d;
+      }
+      const double ctx = wdot(P, P->c, P->ux) / tau;
+      double bty = 0.0;
+      for (int i = 0; i < m; ++i) bty += P->b[i] * P->uy[i];
+      bty /= tau;
+      P->eps_p = sqrt(rp) / (1.0 + nrm_b);
+      P->eps_d = sqrt(rd) / (1.0 + nrm_c);
+      P->eps_g = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
+      /* consensus residuals on (s, H x) and (z, t) */
+      double pc = 0, ns2 = 0, nh2 = 0, dc = 0, nz2 = 0, nt2 = 0;
+      for (int k = 0; k < p; ++k) {
+        int s = P->cptr[k + 1] - P->cptr[k];
+        int64_t o = P->blk_off[k];
+        for (int e = 0; e < s * s; ++e) {
+          const double hx = P->ux[P->loc[o + e]];
+          const double a1 = P->us[o + e] - hx, a2 = P->vz[o + e] - P->ut[o + e];
+          pc += a1 * a1; ns2 += P->us[o + e] * P->us[o + e]; nh2 += hx * hx;
+          dc += a2 * a2; nz2 += P->vz[o + e] * P->vz[o + e]; nt2 += P->ut[o + e] * P->ut[o + e];
+        }
+      }
+      const double c1 = cratio(sqrt(pc), sqrt(ns2), sqrt(nh2));
+      const double c2 = cratio(sqrt(dc), sqrt(nz2), sqrt(nt2));
+      P->eps_c = c1 > c2 ? c1 : c2;
+      crit = P->eps_p;
+      if (P->eps_d > crit) crit = P->eps_d;
+      if (P->eps_g > crit) crit = P->eps_g;
+      if (hist_e) hist_e[it] = crit;
+      if (hist_c) hist_c[it] = P->eps_c;
+      if (P->eps_c > crit) crit = P->eps_c;
+      if (crit <= tol) { status = ORC_OK; ++it; break; }
+    } else {
+      if (hist_e) hist_e[it] = INFINITY;
+      if (hist_c) hist_c[it] = INFINITY;
+      /* Infeasibility: ||A^T u_y + H^T v_z|| - (b^T u_y / ||b||) tol <= 0 certifies
+         primal infeasibility, ||A u_x|| + (c^T u_x / ||c||) tol <= 0 dual infeasibility */
+      double r1 = 0.0, r2 = 0.0, bty = 0.0;
+      for (int i = 0; i < m; ++i) { r1 += ax[i] * ax[i]; bty += P->b[i] * P->uy[i]; }
+      for (int64_t j = 0; j < nnz; ++j) {
+        double d = aty[j] + zc[j];
+        r2 += P->w[j] * d * d;
+      }
+      const double ctx = wdot(P, P->c, P->ux);
+      const double tp = sqrt(r2) - (nrm_b > 0 ? bty / nrm_b : 0.0) * tol;
+      const double td = sqrt(r1) + (nrm_c > 0 ? ctx / nrm_c : 0.0) * tol;
+      if (tp <= 0.0 && bty > 0.0) { status = 2; ++it; break; }
+      if (td <= 0.0 && ctx < 0.0) { status = 3; ++it; break; }
+    }
+  }
+  P->hsde_status = status;
+  if (iters_done) *iters_done = it;
+  free(hxs); free(ax); free(aty); free(zc); free(tmp); free(sweeps);
+  return status;
+}
+
+/* Accessors of the Algorithm 3 iterate: x = u_x / tau, y = u_y / tau (or the
+ * raw u_x, u_y when tau = 0), out = (tau, kappa, eps_p, eps_d, eps_g, eps_c). */
+void orc_hsde_get(const orc_problem *P, double *x, double *y, double *s_blocks,
+                  double *z_blocks, double *t_blocks, double *out) {
+  const double sc = P->utau > 0.0 ? 1.0 / P->utau : 1.0;
+  if (x) for (int64_t j = 0; j < P->nnz; ++j) x[j] = P->ux[j] * sc;
+  if (y) for (int i = 0; i < P->m; ++i) y[i] = P->uy[i] * sc;
+  if (s_blocks) memcpy(s_blocks, P->us, sizeof(double) * P->nblk);
+  if (z_blocks) memcpy(z_blocks, P->vz, sizeof(double) * P->nblk);
+  if (t_blocks) memcpy(t_blocks, P->ut, sizeof(double) * P->nblk);
+  if (out) {
+    out[0] = P->utau; out[1] = P->kappa; out[2] = P->eps_p; out[3] = P->eps_d;
+    out[4] = P->eps_g; out[5] = P->eps_c;
+  }
+}
+
+/* One-step access for tests: M^-1 zeta and the inner solve. */
+void orc_hsde_inner(orc_problem *P, const double *nx, const double *ns, const double *ny,
+                    const double *nt, double *sx, double *ss, double *sy, double *st) {
+  hsde_inner(P, nx, ns, ny, nt, sx, ss, sy, st);
+}
+
+void orc_hsde_set(orc_problem *P, const double *ux, const double *us, const double *uy,
+                  const double *ut, const double *vz, double utau, double kappa) {
+  memcpy(P->ux, ux, sizeof(double) * P->nnz);
+  memcpy(P->us, us, sizeof(double) * P->nblk);
+  memcpy(P->uy, uy, sizeof(double) * P->m);
+  memcpy(P->ut, ut, sizeof(double) * P->nblk);
+  memcpy(P->vz, vz, sizeof(double) * P->nblk);
+  P->utau = utau;
+  P->kappa = kappa;
+}
+
+void orc_hsde_raw(const orc_problem *P, double *ux, double *uy) {
+  if (ux) memcpy(ux, P->ux, sizeof(double) * P->nnz);
+  if (uy) memcpy(uy, P->uy, sizeof(double) * P->m);
 }
 
 /* Dual objective b^T y of the current iterate of Algorithm 2. */

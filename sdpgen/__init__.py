@@ -214,6 +214,36 @@ def uneven_block_arrow_instance(seed: int, l_range=(5, 50), d_range=(8, 40),
                            meta=dict(l=l, d=d, h=h))
 
 
+def primal_infeasible_instance(l, d, h, m, seed) -> Instance:
+    """A block-arrow instance with one more constraint <I, X> = -1, which no
+    PSD X satisfies (the other m rows are the usual random ones)."""
+    base = block_arrow_instance(l, d, h, m, seed)
+    diag = (base.pat_row == base.pat_col).astype(np.float64)
+    a = np.vstack([base.a_val, diag[None, :]])
+    b = np.concatenate([base.b, [-1.0]])
+    return Instance(n=base.n, m=m + 1, pat_row=base.pat_row, pat_col=base.pat_col,
+                    clique_ptr=base.clique_ptr, clique_vert=base.clique_vert, a_format=A_DENSE,
+                    a_val=a, b=b, c=base.c, name=f"primal_infeasible_l{l}_d{d}_h{h}_m{m}_s{seed}")
+
+
+def dual_infeasible_instance(l, d, h, m, seed) -> Instance:
+    """A block-arrow instance in which no constraint touches vertex 0 and
+    C_00 = -1: X = I stays feasible while X_00 can grow without bound, so the
+    primal is unbounded and no y makes C - sum y_i A_i PSD."""
+    base = block_arrow_instance(l, d, h, m, seed)
+    touch = (base.pat_row == 0) | (base.pat_col == 0)
+    a = base.a_val.copy()
+    a[:, touch] = 0.0
+    tr = (base.pat_row == base.pat_col).astype(np.float64)
+    b = a @ tr                                  # b_i = tr A_i: X = I is feasible
+    c = base.c.copy()
+    c[touch] = 0.0
+    c[(base.pat_row == 0) & (base.pat_col == 0)] = -1.0
+    return Instance(n=base.n, m=m, pat_row=base.pat_row, pat_col=base.pat_col,
+                    clique_ptr=base.clique_ptr, clique_vert=base.clique_vert, a_format=A_DENSE,
+                    a_val=a, b=b, c=c, name=f"dual_infeasible_l{l}_d{d}_h{h}_m{m}_s{seed}")
+
+
 # ----------------------------------------------------------------------------
 # The five named workloads
 # ----------------------------------------------------------------------------
