@@ -66,7 +66,7 @@ def make_instances(name, batch_count):
     raise SystemExit(f"unknown workload {name}")
 
 
-def stage_bytes_flops(insts, precision, sweeps):
+def stage_bytes_flops(insts, precision, sweeps, algorithm="primal"):
     """Algorithmic HBM bytes (or FLOPs) per launch of each stage, summed over
     the instances of the batch.  Dense A is streamed as B = L^-1 A (same size)
     and needs no triangular passes; sparse A is streamed as CSR (12 bytes per
@@ -84,8 +84,9 @@ def stage_bytes_flops(insts, precision, sweeps):
         tot["scatter"] += 8 * 2 * npk + 4 * npk + 8 * 5 * nnz
         tot["residual"] += 8 * 6 * inst.p
         tot["proj"] += int(np.sum((6 * sweeps + 9) * sizes ** 3))
-        if inst.a_format == 1:
-            abytes = 12 * int(inst.a_rowptr[-1])
+        if inst.a_format == 1 or algorithm == "hsde":
+            # sparse A, or the embedding (which keeps A and both triangular passes)
+            abytes = 12 * int(inst.a_rowptr[-1]) if inst.a_format == 1 else 8 * m * nnz
             tri = 8 * m * (m + 1) // 2
             tot["A_v"] += abytes + 8 * nnz + 16 * m
             tot["Linv_r"] += tri + 16 * m
@@ -335,7 +336,11 @@ def cpu_baseline(insts, seconds, algorithm="primal"):
     times, sampled, total_it = [], [], 0
     for inst in insts[:4]:
         P = oracle.Problem(inst)
-        step = P.run_dual if algorithm == "dual" else P.run
+        if algorithm == "hsde":
+            P.hsde_setup()
+            step = P.run_hsde
+        else:
+            step = P.run_dual if algorithm == "dual" else P.run
         done, t0 = 0, time.perf_counter()
         while True:
             step(2, tol=0.0)
@@ -347,7 +352,8 @@ def cpu_baseline(insts, seconds, algorithm="primal"):
         total_it += done
         sampled.append(inst.name)
     t_iter = sum(times) / len(times) * len(insts)
-    what = (f"first {total_it} iterations of Algorithm {2 if algorithm == 'dual' else 1} from a "
+    what = (f"first {total_it} iterations of Algorithm "
+            f"{dict(primal=1, dual=2, hsde=3)[algorithm]} from a "
             f"zero state on "
             f"{len(sampled)} of {len(insts)} instance(s), FP64, setup excluded")
     if len(insts) > len(sampled):
@@ -367,9 +373,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="instances of the batched workload")
-    ap.add_argument("--algorithm", default="primal", choices=("primal", "dual"),
-                    help="Algorithm 1 (domain-space primal ADMM) or Algorithm 2 (range-space "
-                         "dual ADMM)")
+    ap.add_argument("--algorithm", default="primal", choices=("primal", "dual", "hsde"),
+                    help="Algorithm 1 (domain-space primal ADMM), Algorithm 2 (range-space "
+                         "dual ADMM) or Algorithm 3 (ADMM on the homogeneous self-dual embedding)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="start with a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
@@ -413,7 +419,7 @@ def main():
         print(f"[bench] {args.workload} {precision}: {forms[precision]['iter_per_s']:.1f} iter/s",
               file=sys.stderr, flush=True)
     head = forms["fp32"]
-    model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"])
+    model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"], args.algorithm)
     stages = {k: v for k, v in head["stages_ms"].items() if k in model}
     dom = max(stages, key=lambda k: stages[k])
     t_launch = stages[dom] / 1e3
@@ -452,7 +458,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "precision": "fp32-eig/fp64-affine",
                    "algorithm": {"primal": "Algorithm 1 (domain-space primal ADMM)",
-                                 "dual": "Algorithm 2 (range-space dual ADMM)"}[args.algorithm],
+                                 "dual": "Algorithm 2 (range-space dual ADMM)",
+                                 "hsde": "Algorithm 3 (ADMM on the homogeneous self-dual "
+                                         "embedding)"}[args.algorithm],
                    "tol": 1e-4, "rho": 1.0, "adaptive_rho": False, "instances": len(insts),
                    "n": [i.n for i in insts[:4]], "m": [i.m for i in insts[:4]],
                    "cliques": n_cl, "pattern_nnz": sum(i.nnz for i in insts)},

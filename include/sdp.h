@@ -39,6 +39,8 @@ extern "C" {
 enum {
   SDP_OK = 0,
   SDP_MAX_ITER = 1,              /* iteration limit reached before tol      */
+  SDP_PRIMAL_INFEASIBLE = 2,     /* Algorithm 3: primal infeasibility certified */
+  SDP_DUAL_INFEASIBLE = 3,       /* Algorithm 3: dual infeasibility certified   */
   SDP_ERR_ARG = -1,              /* bad size/pointer/ordering of an input   */
   SDP_ERR_PATTERN_UNCOVERED = -2,/* a pattern entry lies in no clique (D_jj=0) */
   SDP_ERR_OFF_PATTERN = -3,      /* a clique holds a pair not in the pattern */
@@ -56,9 +58,10 @@ enum { SDP_A_DENSE = 0, SDP_A_CSR = 1 };
 enum { SDP_FP64 = 0, SDP_FP32_EIG = 1 };
 enum { SDP_DTYPE_FP64 = 0, SDP_DTYPE_FP32 = 1 };
 /* which ADMM runs on the decomposed problem: Algorithm 1 (domain-space
- * decomposition of the primal form, Section 4.1) or Algorithm 2 (range-space
- * decomposition of the dual form, Section 4.2) */
-enum { SDP_ALG_PRIMAL = 0, SDP_ALG_DUAL = 1 };
+ * decomposition of the primal form, Section 4.1), Algorithm 2 (range-space
+ * decomposition of the dual form, Section 4.2) or Algorithm 3 (the
+ * homogeneous self-dual embedding of the decomposed pair, Section 5) */
+enum { SDP_ALG_PRIMAL = 0, SDP_ALG_DUAL = 1, SDP_ALG_HSDE = 2 };
 
 typedef struct sdp_handle sdp_handle;   /* opaque; owns every device buffer it allocates */
 
@@ -105,18 +108,30 @@ typedef struct {
                                    z_k = P+(v_k - lambda_k/rho), the KKT system with right-hand
                                    sides c - sum H_k^T(z_k + lambda_k/rho) and -b/rho,
                                    v_k = z_k + lambda_k/rho + H_k x, lambda_k += rho(z_k - v_k));
-                                   the same factor, kernels and stopping rule */
+                                   the same factor, kernels and stopping rule) or
+                                   SDP_ALG_HSDE (Algorithm 3: u_hat = (I+Q)^-1(u+v) by block
+                                   elimination with the factor of I + A (I + D/2)^-1 A^T,
+                                   u = P_K(u_hat - v), v += u - u_hat; stops on
+                                   max(eps_p, eps_d, eps_g, eps_c) <= tol or on an
+                                   infeasibility certificate; no penalty, so adaptive_rho
+                                   must be 0) */
 } sdp_options;
 
 /* Per-instance result. */
 typedef struct {
   int32_t iters;                /* iterations executed                        */
-  int32_t status;               /* SDP_OK (converged) or SDP_MAX_ITER         */
-  double eps_c, eps_lambda;     /* residuals of the last iteration            */
+  int32_t status;               /* SDP_OK (converged), SDP_MAX_ITER, or with
+                                   Algorithm 3 SDP_PRIMAL_INFEASIBLE /
+                                   SDP_DUAL_INFEASIBLE                        */
+  double eps_c, eps_lambda;     /* residuals of the last iteration (Algorithm 3:
+                                   eps_c = consensus residual, eps_lambda =
+                                   max(eps_p, eps_d, eps_g))                   */
   double objective;             /* Algorithm 1: <C, X> = sum_j w_j c_j u_j;
-                                   Algorithm 2: the dual objective b^T y       */
-  double rho;                   /* penalty after the last iteration           */
-  double eps_p, eps_d, eps_g;   /* primal/dual residuals and gap (NaN unless computed) */
+                                   Algorithm 2: the dual objective b^T y;
+                                   Algorithm 3: <C, X> with X = u_x / tau     */
+  double rho;                   /* penalty after the last iteration (Algorithm 3: tau) */
+  double eps_p, eps_d, eps_g;   /* primal/dual residuals and gap (NaN unless computed;
+                                   Algorithm 3 computes them every iteration) */
   double eps_alpha;             /* PSD-completability violation (NaN unless computed) */
 } sdp_result;
 
@@ -146,8 +161,10 @@ int sdp_reset(sdp_handle *h);
  * returns without synchronising. */
 int sdp_admm_step(sdp_handle *h, int32_t n_steps, sdp_result *res);
 
-/* Iterates until every instance meets the tolerance or max_iter; fills res
- * (batch entries).  Returns SDP_OK if all converged, SDP_MAX_ITER otherwise. */
+/* Iterates until every instance meets the tolerance or max_iter (or, with
+ * Algorithm 3, certifies infeasibility); fills res (batch entries).  Returns
+ * SDP_MAX_ITER if an instance hit the limit, else the first infeasibility
+ * status, else SDP_OK. */
 int sdp_solve(sdp_handle *h, sdp_result *res);
 
 /* Standalone PSD projection of `count` symmetric blocks (XkUpdate):
@@ -179,7 +196,9 @@ int sdp_psd_project_variant(int32_t variant, int32_t count, int32_t max_size,
  * multipliers of <A_i, X> = b_i); Xk/Lk the packed clique blocks of all p
  * cliques concatenated.  With SDP_ALG_DUAL: u = -rho x (the primal matrix
  * estimate; x is the KKT variable of Algorithm 2), y_dual = y (the dual
- * variable itself), Xk = z_k, Lk = lambda_k.  Synchronises. */
+ * variable itself), Xk = z_k, Lk = lambda_k.  With SDP_ALG_HSDE: u = u_x / tau,
+ * y_dual = u_y / tau (u_x and u_y themselves -- the certificates up to scale --
+ * when tau = 0), Xk = u_s, Lk = v_z.  Synchronises. */
 int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual,
                      double *Xk_packed, double *Lk_packed);
 
@@ -190,8 +209,9 @@ int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk_packed,
                   const double *Lk_packed, double rho);
 
 /* Per-instance residual history of the iterations run since setup/reset:
- * eps_c, eps_lambda and the rho used, up to `cap` entries each (any pointer may
- * be NULL).  Returns the number of entries written through *count. */
+ * eps_c, eps_lambda and the rho used (Algorithm 3: eps_c, max(eps_p, eps_d,
+ * eps_g) and tau), up to `cap` entries each (any pointer may be NULL).
+ * Returns the number of entries written through *count. */
 int sdp_get_history(sdp_handle *h, int32_t inst, int32_t cap, double *eps_c,
                     double *eps_lambda, double *rho, int32_t *count);
 

@@ -5,7 +5,8 @@ Wynn, "Chordal decomposition in operator-splitting methods for sparse
 semidefinite programs") runs entirely in hand-written HIP kernels for gfx950
 behind the C ABI of include/sdp.h; this package is its thin Python binding.
 """
-from ._native import (A_CSR, A_DENSE, ALG_DUAL, ALG_PRIMAL, DTYPE_FP32, DTYPE_FP64, EXPORTS,
+from ._native import (A_CSR, A_DENSE, ALG_DUAL, ALG_HSDE, ALG_PRIMAL, DTYPE_FP32, DTYPE_FP64,
+                      DUAL_INFEASIBLE, EXPORTS, PRIMAL_INFEASIBLE,
                       FP32_EIG, FP64,
                       SdpError, Solver, default_options, lib, make_options, pack_blocks,
                       projection_variants, psd_project_batched, sdp_result, setup_status,
@@ -14,5 +15,6 @@ from ._native import (A_CSR, A_DENSE, ALG_DUAL, ALG_PRIMAL, DTYPE_FP32, DTYPE_FP
 __all__ = ["Solver", "SdpError", "psd_project_batched", "projection_variants", "setup_status",
            "make_options",
            "default_options", "pack_blocks", "unpack_blocks", "lib", "EXPORTS", "FP64",
-           "FP32_EIG", "DTYPE_FP32", "DTYPE_FP64", "A_DENSE", "A_CSR", "ALG_PRIMAL", "ALG_DUAL",
+           "FP32_EIG", "DTYPE_FP32", "DTYPE_FP64", "A_DENSE", "A_CSR", "ALG_PRIMAL", "ALG_DUAL", "ALG_HSDE",
+           "PRIMAL_INFEASIBLE", "DUAL_INFEASIBLE",
            "sdp_result"]

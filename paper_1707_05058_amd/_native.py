@@ -38,7 +38,8 @@ ERR_OOM = -9
 A_DENSE, A_CSR = 0, 1
 FP64, FP32_EIG = 0, 1
 DTYPE_FP64, DTYPE_FP32 = 0, 1
-ALG_PRIMAL, ALG_DUAL = 0, 1
+ALG_PRIMAL, ALG_DUAL, ALG_HSDE = 0, 1, 2
+PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 2, 3
 
 _p = C.c_void_p
 
@@ -153,7 +154,7 @@ def make_options(**kw) -> sdp_options:
         elif k == "precision" and isinstance(v, str):
             v = {"fp64": FP64, "fp32": FP32_EIG, "fp32_eig": FP32_EIG}[v.lower()]
         elif k == "algorithm" and isinstance(v, str):
-            v = {"primal": ALG_PRIMAL, "dual": ALG_DUAL}[v.lower()]
+            v = {"primal": ALG_PRIMAL, "dual": ALG_DUAL, "hsde": ALG_HSDE}[v.lower()]
         setattr(o, k, v)
     return o
 
@@ -237,7 +238,7 @@ class Solver:
 
     def solve(self):
         res = (sdp_result * self.batch)()
-        _check(lib.sdp_solve(self._h, res), ok=(OK, MAX_ITER))
+        _check(lib.sdp_solve(self._h, res), ok=(OK, MAX_ITER, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE))
         return [r.as_dict() for r in res]
 
     def diagnostics(self):

@@ -142,6 +142,8 @@ __global__ __launch_bounds__(64) void k_syrk_csr(FactorArgs f, const int32_t *ro
 __global__ __launch_bounds__(64) void k_pad_identity(FactorArgs f) {
   const InstDesc d = f.inst[blockIdx.x];
   for (int i = d.m + threadIdx.x; i < d.ldm; i += 64) f.M[d.t_off + (int64_t)i * d.ldm + i] = 1.0;
+  if (f.diag_shift != 0.0)   // I + A P^-1 A^T of the self-dual embedding
+    for (int i = threadIdx.x; i < d.m; i += 64) f.M[d.t_off + (int64_t)i * d.ldm + i] += f.diag_shift;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,367 @@
+// Algorithm 3 on gfx950: ADMM for the homogeneous self-dual embedding of the
+// decomposed primal-dual pair (Section 5).  One iteration:
+//   u_hat = (I + Q)^-1 (u + v)   (HsdeStep1) by the block eliminations of
+//            Section 5.2: the outer system (LinearSystem) with the matrix
+//            inversion lemma (MatrixInverseResult, FirstBlockElimination) and
+//            the inner system (SecondBlockElimination) reduced to the m x m
+//            factor of I + A P^-1 A^T, P = I + D/2 (HSDEFactorizationFinal)
+//   u = P_K(u_hat - v)           (HsdeStep2: x, y, t free, s in the cliques'
+//                                 PSD cones, tau >= 0)
+//   v = v - u_hat + u            (HsdeStep3: only z and kappa are nonzero)
+// then the residuals HSDEerror and the consensus residual, or the
+// infeasibility tests (Infeasibility) once tau = 0.
+//
+// Vectors over the pattern are compact lower coordinates with weights w (1 on
+// the diagonal, 2 off it): the paper's Euclidean products on vec(X) are the
+// w-weighted sums here, A x is A (w .* x), and I stays the identity.  The
+// inner solve, for nu = (nu_x, nu_s, nu_y, nu_t):
+//   x'      = nu_x + H^T (nu_s + nu_t) / 2                 (k_hsde_xprime)
+//   g       = (I + A W P^-1 A^T)^-1 (A W x'/P - nu_y)      (affine stages 1-3)
+//   sigma_x = (x' - A^T g) / P,  sigma_y = -g              (affine stage 4)
+//   sigma_s = (nu_s - nu_t + H sigma_x) / 2,  sigma_t = sigma_s - H sigma_x + nu_t
+// and u_hat_1 = sigma - f M^-1 zeta, f = (zeta^T sigma) / (1 + zeta^T M^-1 zeta),
+// u_hat_tau = omega_2 + f.  A u_x and A^T u_y for the residuals follow from
+// quantities of the solve (A W sigma_x = nu_y + g, A^T g = x' - P sigma_x) and
+// the set-up products A W M^-1 zeta_x, A^T M^-1 zeta_y: no extra pass over A.
+#include "sdp_internal.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int HS_LANES = 4;
+constexpr int HS_NT = 1024;    // per-instance reductions: one workgroup per instance
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup (HS_NT threads); every thread gets the total.
+__device__ inline double block_total(double v, double *red) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < HS_NT / 64; ++i) s += red[i];
+  return s;
+}
+
+__device__ inline double cratio(double num, double a, double b) {
+  const double den = a > b ? a : b;
+  if (den > 0.0) return num / den;
+  return num == 0.0 ? 0.0 : INFINITY;
+}
+
+// nu = omega_1 - omega_2 zeta with omega = u + v; in set-up mode nu = zeta
+// = (c, 0, -b, 0) (for M^-1 zeta).
+__global__ __launch_bounds__(256) void k_hsde_form_nu(HsdeArgs h, int setup) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < h.ncoord) {
+    const int inst = h.coord_inst[t];
+    if (setup) h.nx[t] = h.c[t];
+    else if (!h.state[inst].done) h.nx[t] = h.ux[t] - h.hs[inst].w2 * h.c[t];
+  }
+  if (t < h.npk) {
+    const int inst = h.coord_inst[h.blk_loc[t]];
+    if (setup) {
+      h.ns[t] = 0.0;
+      h.nt[t] = 0.0;
+    } else if (!h.state[inst].done) {
+      h.ns[t] = h.us[t] + h.vz[t];
+      h.nt[t] = h.ut[t];
+    }
+  }
+  if (t < h.nrow) {
+    const int inst = h.row_inst[t];
+    if (setup) h.ny[t] = -h.b[t];
+    else if (!h.state[inst].done) h.ny[t] = h.uy[t] + h.hs[inst].w2 * h.b[t];
+  }
+}
+
+// x' = nu_x + H^T (nu_s + nu_t) / 2 and v = w x' / P (four lanes per coordinate,
+// fixed butterfly; workgroups numbered contiguously per XCD).
+__global__ __launch_bounds__(256) void k_hsde_xprime(HsdeArgs h, const double *nx, const double *ns,
+                                                     const double *nt) {
+  const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+  const int64_t g = (int64_t)(x8 * q8 + min(x8, r8) + blockIdx.x / 8) * 256 + threadIdx.x;
+  const int64_t j = g / HS_LANES;
+  const int q = (int)(g % HS_LANES);
+  if (j >= h.ncoord) return;
+  const int inst = h.coord_inst[j];
+  if (!h.ignore_done && h.state[inst].done) return;
+  double acc = 0.0;
+  const int64_t t1 = h.contrib_ptr[j + 1];
+  for (int64_t t = h.contrib_ptr[j] + q; t < t1; t += HS_LANES) {
+    const int32_t e = h.contrib_idx[t];
+    acc += ns[e] + nt[e];
+  }
+#pragma unroll
+  for (int o = 1; o < HS_LANES; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (q == 0) {
+    const double x = nx[j] + 0.5 * acc;
+    h.xp[j] = x;
+    h.v[j] = h.w[j] * x / h.P[j];
+  }
+}
+
+// Set-up, after the inner solve of nu = zeta: the blocks of M^-1 zeta.
+__global__ __launch_bounds__(256) void k_hsde_zeta_blocks(HsdeArgs h) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= h.npk) return;
+  const double hx = h.sx[h.blk_loc[e]];
+  h.mzs[e] = 0.5 * hx;          // (0 - 0 + H sigma_x) / 2
+  h.mzt[e] = -0.5 * hx;         // sigma_s - H sigma_x + 0
+}
+
+// Set-up, one workgroup per instance: M^-1 zeta on coordinates and rows,
+// A W (M^-1 zeta)_x = -b + g, A^T (M^-1 zeta)_y = -(x' - P sigma_x), kz and
+// the norms of b and c; tau = kappa = 1.
+__global__ __launch_bounds__(HS_NT) void k_hsde_setup_finish(HsdeArgs h) {
+  const int inst = blockIdx.x;
+  const InstDesc d = h.inst[inst];
+  __shared__ double red[HS_NT / 64];
+  double zc = 0.0, nc2 = 0.0, zb = 0.0, nb2 = 0.0;
+  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT) {
+    const double sx = h.sx[j];
+    h.mzx[j] = sx;
+    h.atmz[j] = -(h.xp[j] - h.P[j] * sx);
+    zc += h.w[j] * h.c[j] * sx;
+    nc2 += h.w[j] * h.c[j] * h.c[j];
+  }
+  for (int64_t i = d.row_off + threadIdx.x; i < d.row_off + d.ldm; i += HS_NT) {
+    const double g = h.g[i];
+    h.mzy[i] = -g;
+    h.az[i] = g - h.b[i];
+    zb += h.b[i] * (-g);
+    nb2 += h.b[i] * h.b[i];
+  }
+  zc = block_total(zc, red);
+  nc2 = block_total(nc2, red);
+  zb = block_total(zb, red);
+  nb2 = block_total(nb2, red);
+  if (threadIdx.x == 0) {
+    HsdeState &s = h.hs[inst];
+    s.kz = 1.0 / (1.0 + zc - zb);   // zeta^T M^-1 zeta = c^T mz_x - b^T mz_y
+    s.nrm_b = sqrt(nb2);
+    s.nrm_c = sqrt(nc2);
+    s.tau = 1.0;
+    s.kappa = 1.0;
+    s.w2 = 2.0;
+    s.f = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hsde_reset(HsdeArgs h) {
+  const int inst = blockIdx.x * 256 + threadIdx.x;
+  if (inst >= h.batch) return;
+  HsdeState &s = h.hs[inst];
+  s.tau = 1.0;
+  s.kappa = 1.0;
+  s.w2 = 2.0;
+  s.f = 0.0;
+  s.rp2 = s.ax2 = s.bty = s.ctx = 0.0;
+  s.eps_p = s.eps_d = s.eps_g = INFINITY;
+}
+
+// One workgroup per instance, after the inner solve: f = kz zeta^T sigma,
+// u_hat_tau = omega_2 + f, tau = max(0, u_hat_tau - kappa), kappa -= u_hat_tau
+// - tau; u_x = sigma_x - f mz_x, u_y = -g - f mz_y; A W u_x = nu_y + g - f A W mz_x.
+__global__ __launch_bounds__(HS_NT) void k_hsde_update(HsdeArgs h) {
+  const int inst = blockIdx.x;
+  if (h.state[inst].done) return;
+  const InstDesc d = h.inst[inst];
+  __shared__ double red[HS_NT / 64];
+  double zs = 0.0;
+  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT)
+    zs += h.w[j] * h.c[j] * h.sx[j];
+  for (int64_t i = d.row_off + threadIdx.x; i < d.row_off + d.ldm; i += HS_NT)
+    zs += h.b[i] * h.g[i];            // -b^T sigma_y with sigma_y = -g
+  zs = block_total(zs, red);
+  HsdeState &s = h.hs[inst];
+  const double f = s.kz * zs;
+  const double uhat_tau = s.w2 + f;
+  const double kappa = s.kappa;
+  const double tau = uhat_tau - kappa > 0.0 ? uhat_tau - kappa : 0.0;
+  double ctx = 0.0, bty = 0.0, ax2 = 0.0, rp2 = 0.0;
+  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT) {
+    const double ux = h.sx[j] - f * h.mzx[j];
+    h.ux[j] = ux;
+    ctx += h.w[j] * h.c[j] * ux;
+  }
+  for (int64_t i = d.row_off + threadIdx.x; i < d.row_off + d.ldm; i += HS_NT) {
+    const double uy = -h.g[i] - f * h.mzy[i];
+    h.uy[i] = uy;
+    bty += h.b[i] * uy;
+    const double aux = h.ny[i] + h.g[i] - f * h.az[i];
+    ax2 += aux * aux;
+    const double rp = aux - tau * h.b[i];
+    rp2 += rp * rp;
+  }
+  ctx = block_total(ctx, red);
+  bty = block_total(bty, red);
+  ax2 = block_total(ax2, red);
+  rp2 = block_total(rp2, red);
+  if (threadIdx.x == 0) {
+    s.f = f;
+    s.tau = tau;
+    s.kappa = kappa - uhat_tau + tau;
+    s.w2 = s.tau + s.kappa;
+    s.ctx = ctx;
+    s.bty = bty;
+    s.ax2 = ax2;
+    s.rp2 = rp2;
+  }
+}
+
+// One workgroup per instance, after the projections: H^T v_z and A^T u_y on the
+// coordinates (dual residual), the clique partials (consensus residuals), the
+// stopping test or the infeasibility tests.
+__global__ __launch_bounds__(HS_NT) void k_hsde_finish(HsdeArgs h) {
+  const int inst = blockIdx.x;
+  InstState &st = h.state[inst];
+  if (st.done) return;
+  const InstDesc d = h.inst[inst];
+  HsdeState &s = h.hs[inst];
+  __shared__ double red[HS_NT / 64];
+  const double tau = s.tau, f = s.f;
+  double rd2 = 0.0, r2 = 0.0;
+  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT) {
+    double hz = 0.0;
+    for (int64_t t = h.contrib_ptr[j]; t < h.contrib_ptr[j + 1]; ++t) hz += h.vz[h.contrib_idx[t]];
+    const double aty = -(h.xp[j] - h.P[j] * h.sx[j]) - f * h.atmz[j];
+    const double q = aty + hz;
+    r2 += h.w[j] * q * q;
+    if (tau > 0.0) {
+      const double dd = q / tau - h.c[j];
+      rd2 += h.w[j] * dd * dd;
+    }
+  }
+  double S[7] = {0, 0, 0, 0, 0, 0, 0};
+  const int64_t c0 = h.inst_cl_first[inst], c1 = h.inst_cl_first[inst + 1];
+  for (int64_t k = c0 + threadIdx.x; k < c1; k += HS_NT) {
+    const double *pk = h.part + NPART * k;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) S[q] += pk[q];
+  }
+  rd2 = block_total(rd2, red);
+  r2 = block_total(r2, red);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) S[q] = block_total(S[q], red);
+  if (threadIdx.x != 0) return;
+  const SolverParams &P = h.params;
+  const int it = st.iter + 1;
+  double crit_e = INFINITY, eps_c = INFINITY;
+  if (tau > 0.0) {
+    const double ctx = s.ctx / tau, bty = s.bty / tau;
+    s.eps_p = sqrt(s.rp2) / tau / (1.0 + s.nrm_b);
+    s.eps_d = sqrt(rd2) / (1.0 + s.nrm_c);
+    s.eps_g = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
+    const double e1 = cratio(sqrt(S[0]), sqrt(S[1]), sqrt(S[2]));
+    const double e2 = cratio(sqrt(S[3]), sqrt(S[4]), sqrt(S[6]));
+    eps_c = e1 > e2 ? e1 : e2;
+    crit_e = s.eps_p;
+    if (s.eps_d > crit_e) crit_e = s.eps_d;
+    if (s.eps_g > crit_e) crit_e = s.eps_g;
+  }
+  if (h.hist && it - 1 < P.hist_cap) {
+    double *hh = h.hist + ((int64_t)inst * P.hist_cap + (it - 1)) * 3;
+    hh[0] = eps_c;
+    hh[1] = crit_e;
+    hh[2] = tau;
+  }
+  st.eps_c = eps_c;
+  st.eps_l = crit_e;
+  st.iter = it;
+  st.total_sweeps += S[5];
+  if (tau > 0.0) {
+    const double crit = crit_e > eps_c ? crit_e : eps_c;
+    if (crit <= P.tol) {
+      st.done = 1;
+      return;
+    }
+  } else {
+    const double tp = sqrt(r2) - (s.nrm_b > 0.0 ? s.bty / s.nrm_b : 0.0) * P.tol;
+    const double td = sqrt(s.ax2) + (s.nrm_c > 0.0 ? s.ctx / s.nrm_c : 0.0) * P.tol;
+    if (tp <= 0.0 && s.bty > 0.0) {
+      st.done = 3;
+      return;
+    }
+    if (td <= 0.0 && s.ctx < 0.0) {
+      st.done = 4;
+      return;
+    }
+  }
+  if (it >= P.max_iter) st.done = 2;
+}
+
+// x = u_x / tau and y = u_y / tau (the raw u_x, u_y when tau = 0).
+__global__ __launch_bounds__(256) void k_hsde_solution(HsdeArgs h, double *x_out, double *y_out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < h.ncoord) {
+    const double tau = h.hs[h.coord_inst[t]].tau;
+    x_out[t] = tau > 0.0 ? h.ux[t] / tau : h.ux[t];
+  }
+  if (t < h.nrow) {
+    const double tau = h.hs[h.row_inst[t]].tau;
+    y_out[t] = tau > 0.0 ? h.uy[t] / tau : h.uy[t];
+  }
+}
+
+int64_t max3(int64_t a, int64_t b, int64_t c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+}  // namespace
+
+hipError_t launch_hsde_form_nu(const HsdeArgs &h, hipStream_t st) {
+  const int64_t n = max3(h.ncoord, h.npk, h.nrow);
+  hipLaunchKernelGGL(k_hsde_form_nu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_xprime(const HsdeArgs &h, const double *nx, const double *ns,
+                              const double *nt, hipStream_t st) {
+  const int64_t n = h.ncoord * HS_LANES;
+  hipLaunchKernelGGL(k_hsde_xprime, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h, nx, ns,
+                     nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_setup_finish(const HsdeArgs &h, hipStream_t st) {
+  // the set-up inner solve runs between these two: form nu = zeta first
+  if (h.npk > 0)
+    hipLaunchKernelGGL(k_hsde_zeta_blocks, dim3((unsigned)((h.npk + 255) / 256)), dim3(256), 0, st,
+                       h);
+  hipLaunchKernelGGL(k_hsde_setup_finish, dim3(h.batch), dim3(HS_NT), 0, st, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_setup_nu(const HsdeArgs &h, hipStream_t st) {
+  const int64_t n = max3(h.ncoord, h.npk, h.nrow);
+  hipLaunchKernelGGL(k_hsde_form_nu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_update(const HsdeArgs &h, hipStream_t st) {
+  hipLaunchKernelGGL(k_hsde_update, dim3(h.batch), dim3(HS_NT), 0, st, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_finish(const HsdeArgs &h, hipStream_t st) {
+  hipLaunchKernelGGL(k_hsde_finish, dim3(h.batch), dim3(HS_NT), 0, st, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_reset(const HsdeArgs &h, hipStream_t st) {
+  hipLaunchKernelGGL(k_hsde_reset, dim3((h.batch + 255) / 256), dim3(256), 0, st, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsde_solution(const HsdeArgs &h, double *x_out, double *y_out, hipStream_t st) {
+  const int64_t n = h.ncoord > h.nrow ? h.ncoord : h.nrow;
+  hipLaunchKernelGGL(k_hsde_solution, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h, x_out,
+                     y_out);
+  return hipGetLastError();
+}

@@ -154,7 +154,12 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
             const int ii = i > k ? i : k, kk = i > k ? k : i;
             const int64_t g = off + (int64_t)ii * (ii + 1) / 2 + kk;
             double wd;
-            if (MODE == MODE_ADMM && a.dual) {
+            if (MODE == MODE_ADMM && a.hsde) {
+              // u_hat_s - v_z
+              const double hx = a.h_sx[a.blk_loc[g]];
+              const double ss = 0.5 * (a.h_ns[g] - a.h_nt[g] + hx);
+              wd = ss - a.hs[a.cl_inst[cl]].f * a.h_mzs[g] - a.Lam[g];
+            } else if (MODE == MODE_ADMM && a.dual) {
               wd = a.Vd[g] - a.Lam[g] / rho;                 // v_k - lambda_k / rho
             } else {
               wd = a.u[a.blk_loc[g]];
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 
   // --- rebuild X = V diag(theta+) V^T on the packed lower triangle ---
   const int npk = s * (s + 1) / 2;
-  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
+  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
   for (int e = tid; e < npk; e += NT) {
     int i, j;
     tri_inv(e, i, j);
@@ -429,6 +434,29 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     if (MODE == MODE_STANDALONE) {
       out[off + (int64_t)i * s + j] = acc;
       out[off + (int64_t)j * s + i] = acc;
+    } else if (a.hsde) {
+      // Algorithm 3: u_s = P+(u_hat_s - v_z), v_z += u_s - u_hat_s, u_t = u_hat_t;
+      // partials of the consensus residuals on (u_s, H u_x) and (v_z, u_t)
+      const int64_t g = off + e;
+      const double f = a.hs[a.cl_inst[cl]].f;
+      const int32_t loc = a.blk_loc[g];
+      const double hx = a.h_sx[loc], nt = a.h_nt[g];
+      const double ss = 0.5 * (a.h_ns[g] - nt + hx);
+      const double us_hat = ss - f * a.h_mzs[g];
+      const double ut = ss - hx + nt - f * a.h_mzt[g];
+      const double usn = (double)acc;
+      const double vzn = a.Lam[g] - us_hat + usn;
+      a.X[g] = usn;
+      a.Lam[g] = vzn;
+      a.h_ut[g] = ut;
+      const double hux = a.h_ux[loc];
+      const double wt = (i == j) ? 1.0 : 2.0;
+      p0 += wt * (usn - hux) * (usn - hux);
+      p1 += wt * usn * usn;
+      p2 += wt * hux * hux;
+      p3 += wt * (vzn - ut) * (vzn - ut);
+      p4 += wt * vzn * vzn;
+      p6 += wt * ut * ut;
     } else if (a.dual) {
       // Algorithm 2: z_k only; the multiplier and the other partials follow
       // the affine step (launch_dual_update)
@@ -460,6 +488,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     p2 = block_sum<NT>(p2, red);
     p3 = block_sum<NT>(p3, red);
     p4 = block_sum<NT>(p4, red);
+    if (a.hsde) p6 = block_sum<NT>(p6, red);
     if (tid == 0) {
       double *pp = a.part + NPART * (int64_t)cl;
       if (!a.dual) {
@@ -467,6 +496,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       }
       pp[3] = p3;
       pp[5] = (double)sweep;
+      pp[6] = p6;
     }
   }
 }

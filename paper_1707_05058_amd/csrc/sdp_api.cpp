@@ -300,6 +300,11 @@ struct sdp_handle {
   int n_t_rows_all = 0;
   double *d_ytmp = nullptr;              // row-space scratch for the scaled multiplier
   double *d_utmp = nullptr;              // coordinate scratch (Algorithm 2: -rho x)
+  // Algorithm 3
+  bool hsde = false;
+  HsdeArgs hsa{};
+  HsdeState *d_hs = nullptr;
+  std::vector<HsdeState> h_hs;
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
   hipGraphExec_t graph = nullptr;
@@ -339,7 +344,13 @@ void enqueue_projections(sdp_handle *h, const ProjArgs &p, hipStream_t st) {
 // Algorithm 1: x-update (affine), projections with the multiplier update,
 // residuals.  Algorithm 2: z-update (projections), (y, x) from the KKT
 // system, v and multiplier updates, residuals.
+void enqueue_hsde_iteration(sdp_handle *h, hipStream_t st);
+
 void enqueue_iteration(sdp_handle *h, hipStream_t st) {
+  if (h->hsde) {
+    enqueue_hsde_iteration(h, st);
+    return;
+  }
   if (h->proj.dual) {
     enqueue_projections(h, h->proj, st);
     HIPCHK(launch_iteration_affine(h->aff, st));
@@ -388,6 +399,94 @@ void compute_bp(sdp_handle *h) {
   HIPCHK(launch_affine_stage(a, 2, h->stream));
 }
 
+// Algorithm 3 set-up: buffers, then M^-1 zeta by one inner solve of nu = zeta
+// = (c, 0, -b, 0) through the same kernels as the iteration.
+void setup_hsde(sdp_handle *h, const std::vector<double> &D) {
+  auto &own = h->owned;
+  HsdeArgs &g = h->hsa;
+  AffineArgs &a = h->aff;
+  ProjArgs &p = h->proj;
+  h->hsde = true;
+  g.inst = h->d_desc;
+  g.state = h->d_state;
+  g.params = a.params;
+  g.batch = h->B;
+  g.ncoord = h->ncoord;
+  g.coord_inst = a.coord_inst;
+  g.c = a.c;
+  g.w = a.w;
+  std::vector<double> P(D.size());
+  for (size_t j = 0; j < D.size(); ++j) P[j] = 1.0 + 0.5 * D[j];
+  g.P = dev_upload(P, own);
+  g.contrib_ptr = a.contrib_ptr;
+  g.contrib_idx = a.contrib_idx;
+  g.ux = dev_zeros<double>(h->ncoord, own);
+  g.nx = dev_zeros<double>(h->ncoord, own);
+  g.xp = a.bhat;
+  g.v = a.v;
+  g.sx = a.u;
+  g.mzx = dev_zeros<double>(h->ncoord, own);
+  g.atmz = dev_zeros<double>(h->ncoord, own);
+  g.nrow = h->nrow;
+  g.row_inst = h->d_row_inst;
+  g.b = a.b;
+  g.uy = dev_zeros<double>(h->nrow, own);
+  g.ny = dev_zeros<double>(h->nrow, own);
+  g.g = a.y;
+  g.mzy = dev_zeros<double>(h->nrow, own);
+  g.az = dev_zeros<double>(h->nrow, own);
+  g.npk = h->npk;
+  g.blk_loc = p.blk_loc;
+  g.us = p.X;
+  g.vz = p.Lam;
+  const int64_t pk = std::max<int64_t>(h->npk, 1);
+  g.ut = dev_zeros<double>(pk, own);
+  g.ns = dev_zeros<double>(pk, own);
+  g.nt = dev_zeros<double>(pk, own);
+  g.mzs = dev_zeros<double>(pk, own);
+  g.mzt = dev_zeros<double>(pk, own);
+  g.part = p.part;
+  g.inst_cl_first = a.inst_cl_first;
+  g.hist = a.hist;
+  h->d_hs = dev_zeros<HsdeState>(h->B, own);
+  h->h_hs.assign(h->B, HsdeState{});
+  g.hs = h->d_hs;
+  // the affine stages of the inner solve: r = A (w x'/P) - nu_y, g = L^-T L^-1 r,
+  // sigma_x = (x' - A^T g) / P
+  a.b = g.ny;
+  a.D = g.P;
+  // the projection in embedding mode
+  p.hsde = 1;
+  p.hs = h->d_hs;
+  p.h_ns = g.ns;
+  p.h_nt = g.nt;
+  p.h_sx = g.sx;
+  p.h_ux = g.ux;
+  p.h_mzs = g.mzs;
+  p.h_mzt = g.mzt;
+  p.h_ut = g.ut;
+  // M^-1 zeta
+  g.ignore_done = 1;
+  AffineArgs as = a;
+  as.ignore_done = 1;
+  HIPCHK(launch_hsde_setup_nu(g, h->stream));
+  HIPCHK(launch_hsde_xprime(g, g.nx, g.ns, g.nt, h->stream));
+  for (int stg = 1; stg <= 4; ++stg) HIPCHK(launch_affine_stage(as, stg, h->stream));
+  HIPCHK(launch_hsde_setup_finish(g, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  g.ignore_done = 0;
+}
+
+void enqueue_hsde_iteration(sdp_handle *h, hipStream_t st) {
+  const HsdeArgs &g = h->hsa;
+  HIPCHK(launch_hsde_form_nu(g, st));
+  HIPCHK(launch_hsde_xprime(g, g.nx, g.ns, g.nt, st));
+  for (int stg = 1; stg <= 4; ++stg) HIPCHK(launch_affine_stage(h->aff, stg, st));
+  HIPCHK(launch_hsde_update(g, st));
+  enqueue_projections(h, h->proj, st);
+  HIPCHK(launch_hsde_finish(g, st));
+}
+
 void build_graph(sdp_handle *h) {
   if (h->graph || h->opt.graph_chunk <= 0) return;
   hipGraph_t g = nullptr;
@@ -426,6 +525,29 @@ void pull_state(sdp_handle *h) {
 void ensure_y(sdp_handle *h);
 
 void fill_results(sdp_handle *h, sdp_result *res) {
+  if (h->hsde) {
+    HIPCHK(hipMemcpyAsync(h->h_hs.data(), h->d_hs, sizeof(HsdeState) * h->B,
+                          hipMemcpyDeviceToHost, h->stream));
+    pull_state(h);
+    for (int i = 0; i < h->B; ++i) {
+      const InstState &s = h->h_state[i];
+      const HsdeState &q = h->h_hs[i];
+      sdp_result &r = res[i];
+      r.iters = s.iter;
+      r.status = s.done == 1 ? SDP_OK
+                 : s.done == 3 ? SDP_PRIMAL_INFEASIBLE
+                 : s.done == 4 ? SDP_DUAL_INFEASIBLE : SDP_MAX_ITER;
+      r.eps_c = s.eps_c;
+      r.eps_lambda = s.eps_l;
+      r.objective = q.tau > 0 ? q.ctx / q.tau : NAN;
+      r.rho = q.tau;
+      r.eps_p = q.eps_p;
+      r.eps_d = q.eps_d;
+      r.eps_g = q.eps_g;
+      r.eps_alpha = NAN;
+    }
+    return;
+  }
   if (h->aff.dual) ensure_y(h);   // the dual objective b^T y
   HIPCHK(launch_objective(h->aff, h->d_obj, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_obj, h->d_obj, sizeof(double) * h->B, hipMemcpyDeviceToHost,
@@ -465,6 +587,13 @@ void reset_state(sdp_handle *h) {
   HIPCHK(hipMemset(h->aff.u, 0, sizeof(double) * h->ncoord));
   HIPCHK(hipMemset(h->aff.y, 0, sizeof(double) * h->nrow));
   if (h->proj.Vd) HIPCHK(hipMemset(h->proj.Vd, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
+  if (h->hsde) {
+    HIPCHK(hipMemset(h->hsa.ux, 0, sizeof(double) * h->ncoord));
+    HIPCHK(hipMemset(h->hsa.uy, 0, sizeof(double) * h->nrow));
+    HIPCHK(hipMemset(h->hsa.ut, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
+    HIPCHK(launch_hsde_reset(h->hsa, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
   if (h->d_vw) {
     HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N, 0, h->ncl,
                                  h->stream));
@@ -498,7 +627,9 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
   if (opt_in) opt = *opt_in;
   if (!(opt.rho > 0) || !(opt.tol >= 0) || opt.max_iter <= 0 ||
       (opt.precision != SDP_FP64 && opt.precision != SDP_FP32_EIG) ||
-      (opt.algorithm != SDP_ALG_PRIMAL && opt.algorithm != SDP_ALG_DUAL) ||
+      (opt.algorithm != SDP_ALG_PRIMAL && opt.algorithm != SDP_ALG_DUAL &&
+       opt.algorithm != SDP_ALG_HSDE) ||
+      (opt.algorithm == SDP_ALG_HSDE && opt.adaptive_rho) ||
       (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
       opt.graph_chunk < 0)
     fail(SDP_ERR_ARG, "invalid options");
@@ -572,7 +703,8 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
         c[g] = inst[i].c[j];
         D[g] = (double)hi.D[j];
         w[g] = inst[i].pat_row[j] == inst[i].pat_col[j] ? 1.0 : 2.0;
-        wd[g] = w[g] / D[g];
+        // Algorithm 3 factors I + A W P^-1 A^T with P = I + D/2
+        wd[g] = opt.algorithm == SDP_ALG_HSDE ? w[g] / (1.0 + 0.5 * D[g]) : w[g] / D[g];
         cptr[g + 1] = hi.D[j];
       }
     }
@@ -788,7 +920,12 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     h->d_t_rows_all = dev_upload(t_rows_all, own);
     h->n_t_rows_all = (int)(t_rows_all.size() / 2);
     h->d_ytmp = dev_zeros<double>(row, own);
-    if (d_A) {
+    if (opt.algorithm == SDP_ALG_HSDE) {
+      // the embedding solves with right-hand sides that change every
+      // iteration on both sides of the factor: keep A and both triangular passes
+      a.t_rows = a.t3_rows = h->d_t_rows_all;
+      a.n_t_rows = a.n_t3_rows = h->n_t_rows_all;
+    } else if (d_A) {
       a.Bm = dev_zeros<double>(aoff, own);
       a.bp = dev_zeros<double>(row, own);
     }
@@ -890,6 +1027,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       f.a_rowptr = a.a_rowptr; f.a_col = a.a_col; f.a_val = a.a_val;
       f.a_colptr = a.a_colptr; f.a_row = a.a_row; f.a_cval = a.a_cval;
       f.wd = d_wd;
+      f.diag_shift = opt.algorithm == SDP_ALG_HSDE ? 1.0 : 0.0;
       f.M = d_M;
       f.T = d_T;
       f.U = d_U;
@@ -924,6 +1062,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     }
     (void)wd;
     compute_bp(h);
+    if (opt.algorithm == SDP_ALG_HSDE) setup_hsde(h, D);
     reset_state(h);
     *out = h;
   } catch (...) {
@@ -1021,7 +1160,8 @@ int sdp_solve(sdp_handle *h, sdp_result *res) {
     fill_results(h, res);
     int st = SDP_OK;
     for (int i = 0; i < h->B; ++i)
-      if (res[i].status != SDP_OK) st = SDP_MAX_ITER;
+      if (res[i].status == SDP_MAX_ITER) return (int)SDP_MAX_ITER;
+      else if (res[i].status != SDP_OK && st == SDP_OK) st = res[i].status;
     return st;
   });
 }
@@ -1095,6 +1235,17 @@ int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual, dou
     const InstDesc &d = h->desc[inst];
     const bool dual = h->aff.dual != 0;
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (h->hsde) {
+      if (!h->d_utmp) h->d_utmp = dev_zeros<double>(h->ncoord, h->owned);
+      HIPCHK(launch_hsde_solution(h->hsa, h->d_utmp, h->d_ytmp, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      if (u) HIPCHK(hipMemcpy(u, h->d_utmp + d.coord_off, sizeof(double) * d.nnz, hipMemcpyDeviceToHost));
+      if (y_dual) HIPCHK(hipMemcpy(y_dual, h->d_ytmp + d.row_off, sizeof(double) * d.m, hipMemcpyDeviceToHost));
+      const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
+      if (Xk) HIPCHK(hipMemcpy(Xk, h->proj.X + o, sizeof(double) * n, hipMemcpyDeviceToHost));
+      if (Lk) HIPCHK(hipMemcpy(Lk, h->proj.Lam + o, sizeof(double) * n, hipMemcpyDeviceToHost));
+      return SDP_OK;
+    }
     if (u) {
       const double *src = h->aff.u + d.coord_off;
       if (dual) {   // the primal estimate -rho x
@@ -1125,6 +1276,7 @@ int sdp_get_solution(sdp_handle *h, int32_t inst, double *u, double *y_dual, dou
 int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *Lk, double rho) {
   return guarded([&] {
     if (!h || inst < 0 || inst >= h->B || !(rho > 0)) fail(SDP_ERR_ARG, "invalid arguments");
+    if (h->hsde) fail(SDP_ERR_UNSUPPORTED, "warm starts are built for Algorithms 1 and 2");
     HIPCHK(hipStreamSynchronize(h->stream));
     const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
     if (Xk) HIPCHK(hipMemcpy(h->proj.X + o, Xk, sizeof(double) * n, hipMemcpyHostToDevice));
@@ -1170,6 +1322,10 @@ int sdp_get_history(sdp_handle *h, int32_t inst, int32_t cap, double *eps_c, dou
 int sdp_diagnostics(sdp_handle *h, sdp_result *res) {
   return guarded([&] {
     if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    if (h->hsde) {   // Algorithm 3 evaluates eps_p, eps_d, eps_g in every iteration
+      if (res) fill_results(h, res);
+      return SDP_OK;
+    }
     if (!h->dscr.wu) {
       h->dscr.wu = dev_zeros<double>(h->ncoord, h->owned);
       h->dscr.z = dev_zeros<double>(h->ncoord, h->owned);
@@ -1235,6 +1391,20 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
       for (int s = 0; s < NS; ++s) {
         HIPCHK(hipEventRecord(e0, h->stream));
         for (int it = 0; it < n_iter; ++it) {
+          if (h->hsde) {   // 0 nu and x', 1-4 the inner solve, 5 update + projections, 6 residuals
+            if (s == 0) {
+              HIPCHK(launch_hsde_form_nu(h->hsa, h->stream));
+              HIPCHK(launch_hsde_xprime(h->hsa, h->hsa.nx, h->hsa.ns, h->hsa.nt, h->stream));
+            } else if (s < 5) {
+              HIPCHK(launch_affine_stage(h->aff, s, h->stream));
+            } else if (s == 5) {
+              HIPCHK(launch_hsde_update(h->hsa, h->stream));
+              enqueue_projections(h, h->proj, h->stream);
+            } else {
+              HIPCHK(launch_hsde_finish(h->hsa, h->stream));
+            }
+            continue;
+          }
           if (s < 5) {
             HIPCHK(launch_affine_stage(h->aff, s, h->stream));
           } else if (s == 5) {
@@ -1265,6 +1435,7 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
 int sdp_update_data(sdp_handle *h, const double *c, const double *b) {
   return guarded([&] {
     if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    if (h->hsde) fail(SDP_ERR_UNSUPPORTED, "data updates are built for Algorithms 1 and 2");
     if (c)
       HIPCHK(launch_copy_user(c, const_cast<double *>(h->aff.c), h->d_desc, h->aff.coord_inst,
                               h->d_user_coord_off, h->ncoord, 0, h->stream));
@@ -1282,7 +1453,7 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
   return guarded([&] {
     if (!h || T <= 0 || ckpt_every <= 0) fail(SDP_ERR_ARG, "invalid arguments");
     if (h->opt.adaptive_rho) fail(SDP_ERR_ARG, "unrolled differentiation needs a fixed rho");
-    if (h->proj.dual)
+    if (h->proj.dual || h->hsde)
       fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
     const int nseg = (T + ckpt_every - 1) / ckpt_every;
     const int64_t need = (int64_t)nseg * 2 * std::max<int64_t>(h->npk, 1);
@@ -1320,7 +1491,7 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
 int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, int32_t euclidean) {
   return guarded([&] {
     if (!h || !u_bar || !c_bar || !b_bar) fail(SDP_ERR_ARG, "invalid arguments");
-    if (h->proj.dual)
+    if (h->proj.dual || h->hsde)
       fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
     if (h->adj_T <= 0) fail(SDP_ERR_ARG, "run sdp_unrolled_forward first");
     if (!h->adj_ready)

@@ -23,7 +23,7 @@
 #define SDP_WAVE 64
 // per-clique partial sums: ||X_k - H_k x||^2, ||X_k||^2, ||H_k x||^2,
 // ||X_k - X_k^prev||^2, ||Lambda_k||^2 (full Frobenius), Jacobi sweeps
-#define NPART 6
+#define NPART 8   // (Algorithm 3 uses seven: two consensus residuals need three norms each)
 
 struct InstDesc {
   int32_t n, m, p, a_format;
@@ -43,7 +43,19 @@ struct InstState {
   double eps_c, eps_l;
   double total_sweeps;
   int32_t iter;
-  int32_t done;        // 1: converged, 2: iteration limit reached
+  int32_t done;        // 1: converged, 2: iteration limit reached,
+                       // 3: primal infeasible, 4: dual infeasible (Algorithm 3)
+};
+
+// Algorithm 3 (homogeneous self-dual embedding): per-instance scalars.
+struct HsdeState {
+  double tau, kappa;   // u_tau and v_kappa
+  double w2;           // tau + kappa of the current iterate (omega_2)
+  double kz;           // 1 / (1 + zeta^T M^-1 zeta)
+  double f;            // kz * zeta^T sigma of the current iteration
+  double nrm_b, nrm_c; // ||b||, ||c|| (full-vector norms)
+  double rp2, ax2, bty, ctx;   // row-space pieces of the residuals (u, not divided by tau)
+  double eps_p, eps_d, eps_g;
 };
 
 struct SolverParams {
@@ -80,6 +92,13 @@ struct ProjArgs {
   // v_k - lambda_k / rho and the multiplier update runs in launch_dual_update
   int dual;
   double *Vd;
+  // Algorithm 3 (HSDE): X holds u_s, Lam holds v_z; the projection input is
+  // u_hat_s - v_z with u_hat_s = (nu_s - nu_t + H sigma_x) / 2 - f M^-1 zeta_s,
+  // and the epilogue also writes u_t = u_hat_t and the consensus partials
+  int hsde;
+  const HsdeState *hs;
+  const double *h_ns, *h_nt, *h_sx, *h_ux, *h_mzs, *h_mzt;
+  double *h_ut;
 };
 
 // Kernel variants (padded size N, threads NT): ids are per precision.
@@ -196,6 +215,7 @@ struct FactorArgs {
   double *U;                     // out: L^-T at t_off
   int32_t *fail;                 // per instance: 1 if a pivot <= 0
   double *Bout;                  // out: B = L^-1 A for dense instances (layout of A)
+  double diag_shift;             // added to the diagonal of M before the factorisation
 };
 
 hipError_t launch_syrk_dense(const FactorArgs &f, const int32_t *tiles, int ntiles,
@@ -205,6 +225,54 @@ hipError_t launch_syrk_csr(const FactorArgs &f, const int32_t *rows, int nrows, 
 hipError_t launch_cholesky_and_inverse(const FactorArgs &f, int max_nblk, hipStream_t st);
 // tiles: (inst, row tile, column tile) triples over dense instances
 hipError_t launch_form_b(const FactorArgs &f, const int32_t *tiles, int ntiles, hipStream_t st);
+
+// ----------------------------------------------------------------------------
+// Algorithm 3 (k_hsde.hip): the HSDE iteration around the shared kernels
+// ----------------------------------------------------------------------------
+struct HsdeArgs {
+  const InstDesc *inst;
+  InstState *state;
+  HsdeState *hs;
+  SolverParams params;
+  int batch;
+  int ignore_done;
+  // coordinate space (compact lower coordinates, weights w)
+  int64_t ncoord;
+  const int32_t *coord_inst;
+  const double *c, *w, *P;            // P = 1 + D/2
+  const int64_t *contrib_ptr;
+  const int32_t *contrib_idx;
+  double *ux, *nx, *xp, *v, *sx, *mzx, *atmz;
+  // row space
+  int64_t nrow;
+  const int32_t *row_inst;
+  const double *b;
+  double *uy, *ny, *g, *mzy, *az;
+  // packed clique blocks
+  int64_t npk;
+  const int32_t *blk_loc;
+  double *us, *vz, *ut, *ns, *nt, *mzs, *mzt;
+  // clique partials (NPART per clique) and history
+  const double *part;
+  const int64_t *inst_cl_first;
+  double *hist;
+};
+
+// nu = u + v - (u_tau + v_kappa) zeta on every space (coordinates, blocks, rows)
+hipError_t launch_hsde_form_nu(const HsdeArgs &h, hipStream_t st);
+// x' = nu_x + H^T (nu_s + nu_t) / 2 and v = w x' / P on the coordinates
+hipError_t launch_hsde_xprime(const HsdeArgs &h, const double *nx, const double *ns,
+                              const double *nt, hipStream_t st);
+// set-up: M^-1 zeta from the inner solve of nu = zeta, kz and the norms
+hipError_t launch_hsde_setup_finish(const HsdeArgs &h, hipStream_t st);
+hipError_t launch_hsde_setup_nu(const HsdeArgs &h, hipStream_t st);   // nu = zeta
+// tau, kappa, u_x, u_y and the row-space residual pieces
+hipError_t launch_hsde_update(const HsdeArgs &h, hipStream_t st);
+// H^T v_z, the dual residual, the clique partials: residuals, stopping,
+// infeasibility tests
+hipError_t launch_hsde_finish(const HsdeArgs &h, hipStream_t st);
+hipError_t launch_hsde_reset(const HsdeArgs &h, hipStream_t st);
+hipError_t launch_hsde_solution(const HsdeArgs &h, double *x_out, double *y_out, hipStream_t st);
 
 int affine_col_tile_width();
 int affine_csc_tile_width();   // columns per workgroup of the sparse transposed product
