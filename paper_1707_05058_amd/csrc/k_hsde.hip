@@ -38,7 +38,8 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// Sum over the workgroup (HS_NT threads); every thread gets the total.
+// Sum over the workgroup (NT threads); every thread gets the total.
+template <int NT>
 __device__ inline double block_total(double v, double *red) {
   v = wsum(v);
   __syncthreads();
@@ -46,7 +47,7 @@ __device__ inline double block_total(double v, double *red) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < HS_NT / 64; ++i) s += red[i];
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
   return s;
 }
 
@@ -139,10 +140,10 @@ __global__ __launch_bounds__(HS_NT) void k_hsde_setup_finish(HsdeArgs h) {
     zb += h.b[i] * (-g);
     nb2 += h.b[i] * h.b[i];
   }
-  zc = block_total(zc, red);
-  nc2 = block_total(nc2, red);
-  zb = block_total(zb, red);
-  nb2 = block_total(nb2, red);
+  zc = block_total<HS_NT>(zc, red);
+  nc2 = block_total<HS_NT>(nc2, red);
+  zb = block_total<HS_NT>(zb, red);
+  nb2 = block_total<HS_NT>(nb2, red);
   if (threadIdx.x == 0) {
     HsdeState &s = h.hs[inst];
     s.kz = 1.0 / (1.0 + zc - zb);   // zeta^T M^-1 zeta = c^T mz_x - b^T mz_y
@@ -167,99 +168,162 @@ __global__ __launch_bounds__(256) void k_hsde_reset(HsdeArgs h) {
   s.eps_p = s.eps_d = s.eps_g = INFINITY;
 }
 
-// One workgroup per instance, after the inner solve: f = kz zeta^T sigma,
-// u_hat_tau = omega_2 + f, tau = max(0, u_hat_tau - kappa), kappa -= u_hat_tau
-// - tau; u_x = sigma_x - f mz_x, u_y = -g - f mz_y; A W u_x = nu_y + g - f A W mz_x.
-__global__ __launch_bounds__(HS_NT) void k_hsde_update(HsdeArgs h) {
-  const int inst = blockIdx.x;
-  if (h.state[inst].done) return;
-  const InstDesc d = h.inst[inst];
-  __shared__ double red[HS_NT / 64];
-  double zs = 0.0;
-  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT)
-    zs += h.w[j] * h.c[j] * h.sx[j];
-  for (int64_t i = d.row_off + threadIdx.x; i < d.row_off + d.ldm; i += HS_NT)
-    zs += h.b[i] * h.g[i];            // -b^T sigma_y with sigma_y = -g
-  zs = block_total(zs, red);
-  HsdeState &s = h.hs[inst];
-  const double f = s.kz * zs;
-  const double uhat_tau = s.w2 + f;
-  const double kappa = s.kappa;
-  const double tau = uhat_tau - kappa > 0.0 ? uhat_tau - kappa : 0.0;
-  double ctx = 0.0, bty = 0.0, ax2 = 0.0, rp2 = 0.0;
-  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT) {
-    const double ux = h.sx[j] - f * h.mzx[j];
-    h.ux[j] = ux;
-    ctx += h.w[j] * h.c[j] * ux;
+// The per-instance sums of the iteration are formed in two steps: every wave
+// of 64 consecutive coordinates (or rows) -- never shared by two instances,
+// whose ranges are padded to multiples of 64 -- writes its partial sums, and
+// a per-instance pass adds them in a fixed order.
+//   coordinate-wave slots: 0 c^T W sigma_x, 1 c^T W u_x, 2 ||A^T u_y + H^T v_z||_W^2,
+//                          3 ||(A^T u_y + H^T v_z)/tau - c||_W^2
+//   row-wave slots:        0 b^T g, 1 b^T u_y, 2 ||A W u_x||^2, 3 ||A W u_x - tau b||^2
+constexpr int WSLOT = 4;
+
+__global__ __launch_bounds__(256) void k_hsde_zs_partials(HsdeArgs h) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  if (t < h.ncoord) {                                  // uniform per wave
+    const double v = wsum(h.w[t] * h.c[t] * h.sx[t]);
+    if (lane == 0) h.cw_part[(t >> 6) * WSLOT + 0] = v;
   }
-  for (int64_t i = d.row_off + threadIdx.x; i < d.row_off + d.ldm; i += HS_NT) {
-    const double uy = -h.g[i] - f * h.mzy[i];
-    h.uy[i] = uy;
-    bty += h.b[i] * uy;
-    const double aux = h.ny[i] + h.g[i] - f * h.az[i];
-    ax2 += aux * aux;
-    const double rp = aux - tau * h.b[i];
-    rp2 += rp * rp;
-  }
-  ctx = block_total(ctx, red);
-  bty = block_total(bty, red);
-  ax2 = block_total(ax2, red);
-  rp2 = block_total(rp2, red);
-  if (threadIdx.x == 0) {
-    s.f = f;
-    s.tau = tau;
-    s.kappa = kappa - uhat_tau + tau;
-    s.w2 = s.tau + s.kappa;
-    s.ctx = ctx;
-    s.bty = bty;
-    s.ax2 = ax2;
-    s.rp2 = rp2;
+  if (t < h.nrow) {
+    const double v = wsum(h.b[t] * h.g[t]);            // -b^T sigma_y
+    if (lane == 0) h.rw_part[(t >> 6) * WSLOT + 0] = v;
   }
 }
 
-// One workgroup per instance, after the projections: H^T v_z and A^T u_y on the
-// coordinates (dual residual), the clique partials (consensus residuals), the
-// stopping test or the infeasibility tests.
-__global__ __launch_bounds__(HS_NT) void k_hsde_finish(HsdeArgs h) {
+// One thread per instance: f = kz zeta^T sigma, u_hat_tau = omega_2 + f,
+// tau = max(0, u_hat_tau - kappa), kappa -= u_hat_tau - tau.
+__global__ __launch_bounds__(256) void k_hsde_scalars(HsdeArgs h) {
+  const int inst = blockIdx.x * 256 + threadIdx.x;
+  if (inst >= h.batch || h.state[inst].done) return;
+  const InstDesc d = h.inst[inst];
+  double zs = 0.0;
+  for (int64_t q = d.coord_off >> 6; q < (d.coord_off + d.ld) >> 6; ++q) zs += h.cw_part[q * WSLOT];
+  for (int64_t q = d.row_off >> 6; q < (d.row_off + d.ldm) >> 6; ++q) zs += h.rw_part[q * WSLOT];
+  HsdeState &s = h.hs[inst];
+  const double f = s.kz * zs;
+  const double uhat_tau = s.w2 + f;
+  const double tau = uhat_tau - s.kappa > 0.0 ? uhat_tau - s.kappa : 0.0;
+  s.f = f;
+  s.kappa = s.kappa - uhat_tau + tau;
+  s.tau = tau;
+  s.w2 = s.tau + s.kappa;
+}
+
+// u_x = sigma_x - f mz_x, u_y = -g - f mz_y, A W u_x = nu_y + g - f A W mz_x,
+// with their wave partial sums.
+__global__ __launch_bounds__(256) void k_hsde_apply(HsdeArgs h) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  if (t < h.ncoord) {
+    const int inst = h.coord_inst[t];
+    double ctx = 0.0;
+    if (!h.state[inst].done) {
+      const double ux = h.sx[t] - h.hs[inst].f * h.mzx[t];
+      h.ux[t] = ux;
+      ctx = h.w[t] * h.c[t] * ux;
+    }
+    ctx = wsum(ctx);
+    if (lane == 0) h.cw_part[(t >> 6) * WSLOT + 1] = ctx;
+  }
+  if (t < h.nrow) {
+    const int inst = h.row_inst[t];
+    double bty = 0.0, ax2 = 0.0, rp2 = 0.0;
+    if (!h.state[inst].done) {
+      const HsdeState &s = h.hs[inst];
+      const double uy = -h.g[t] - s.f * h.mzy[t];
+      h.uy[t] = uy;
+      bty = h.b[t] * uy;
+      const double aux = h.ny[t] + h.g[t] - s.f * h.az[t];
+      ax2 = aux * aux;
+      const double rp = aux - s.tau * h.b[t];
+      rp2 = rp * rp;
+    }
+    bty = wsum(bty);
+    ax2 = wsum(ax2);
+    rp2 = wsum(rp2);
+    if (lane == 0) {
+      double *q = h.rw_part + (t >> 6) * WSLOT;
+      q[1] = bty;
+      q[2] = ax2;
+      q[3] = rp2;
+    }
+  }
+}
+
+// After the projections: A^T u_y + H^T v_z on the coordinates (A^T g from the
+// inner solve as x' - P sigma_x) and the dual-residual wave sums.
+__global__ __launch_bounds__(256) void k_hsde_dual_partials(HsdeArgs h) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= h.ncoord) return;                           // uniform per wave
+  const int inst = h.coord_inst[j];
+  const HsdeState &s = h.hs[inst];
+  double hz = 0.0;
+  for (int64_t t = h.contrib_ptr[j]; t < h.contrib_ptr[j + 1]; ++t) hz += h.vz[h.contrib_idx[t]];
+  const double aty = -(h.xp[j] - h.P[j] * h.sx[j]) - s.f * h.atmz[j];
+  const double q = aty + hz;
+  double r2 = h.w[j] * q * q, rd2 = 0.0;
+  if (s.tau > 0.0) {
+    const double dd = q / s.tau - h.c[j];
+    rd2 = h.w[j] * dd * dd;
+  }
+  r2 = wsum(r2);
+  rd2 = wsum(rd2);
+  if ((threadIdx.x & 63) == 0) {
+    h.cw_part[(j >> 6) * WSLOT + 2] = r2;
+    h.cw_part[(j >> 6) * WSLOT + 3] = rd2;
+  }
+}
+
+// One workgroup per instance: the wave and clique partial sums in a fixed
+// order, the residuals HSDEerror and the consensus residual, the stopping
+// test, or the infeasibility tests when tau = 0.
+__global__ __launch_bounds__(256) void k_hsde_finish(HsdeArgs h) {
   const int inst = blockIdx.x;
   InstState &st = h.state[inst];
   if (st.done) return;
   const InstDesc d = h.inst[inst];
   HsdeState &s = h.hs[inst];
-  __shared__ double red[HS_NT / 64];
-  const double tau = s.tau, f = s.f;
-  double rd2 = 0.0, r2 = 0.0;
-  for (int64_t j = d.coord_off + threadIdx.x; j < d.coord_off + d.ld; j += HS_NT) {
-    double hz = 0.0;
-    for (int64_t t = h.contrib_ptr[j]; t < h.contrib_ptr[j + 1]; ++t) hz += h.vz[h.contrib_idx[t]];
-    const double aty = -(h.xp[j] - h.P[j] * h.sx[j]) - f * h.atmz[j];
-    const double q = aty + hz;
-    r2 += h.w[j] * q * q;
-    if (tau > 0.0) {
-      const double dd = q / tau - h.c[j];
-      rd2 += h.w[j] * dd * dd;
-    }
+  __shared__ double red[4];
+  double ctx = 0.0, r2 = 0.0, rd2 = 0.0, bty = 0.0, ax2 = 0.0, rp2 = 0.0;
+  for (int64_t q = (d.coord_off >> 6) + threadIdx.x; q < (d.coord_off + d.ld) >> 6; q += 256) {
+    const double *p = h.cw_part + q * WSLOT;
+    ctx += p[1];
+    r2 += p[2];
+    rd2 += p[3];
+  }
+  for (int64_t q = (d.row_off >> 6) + threadIdx.x; q < (d.row_off + d.ldm) >> 6; q += 256) {
+    const double *p = h.rw_part + q * WSLOT;
+    bty += p[1];
+    ax2 += p[2];
+    rp2 += p[3];
   }
   double S[7] = {0, 0, 0, 0, 0, 0, 0};
   const int64_t c0 = h.inst_cl_first[inst], c1 = h.inst_cl_first[inst + 1];
-  for (int64_t k = c0 + threadIdx.x; k < c1; k += HS_NT) {
+  for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {
     const double *pk = h.part + NPART * k;
 #pragma unroll
     for (int q = 0; q < 7; ++q) S[q] += pk[q];
   }
-  rd2 = block_total(rd2, red);
-  r2 = block_total(r2, red);
+  ctx = block_total<256>(ctx, red);
+  r2 = block_total<256>(r2, red);
+  rd2 = block_total<256>(rd2, red);
+  bty = block_total<256>(bty, red);
+  ax2 = block_total<256>(ax2, red);
+  rp2 = block_total<256>(rp2, red);
 #pragma unroll
-  for (int q = 0; q < 7; ++q) S[q] = block_total(S[q], red);
+  for (int q = 0; q < 7; ++q) S[q] = block_total<256>(S[q], red);
   if (threadIdx.x != 0) return;
+  s.ctx = ctx;
+  s.bty = bty;
   const SolverParams &P = h.params;
   const int it = st.iter + 1;
+  const double tau = s.tau;
   double crit_e = INFINITY, eps_c = INFINITY;
   if (tau > 0.0) {
-    const double ctx = s.ctx / tau, bty = s.bty / tau;
-    s.eps_p = sqrt(s.rp2) / tau / (1.0 + s.nrm_b);
+    const double cx = ctx / tau, by = bty / tau;
+    s.eps_p = sqrt(rp2) / tau / (1.0 + s.nrm_b);
     s.eps_d = sqrt(rd2) / (1.0 + s.nrm_c);
-    s.eps_g = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
+    s.eps_g = fabs(cx - by) / (1.0 + fabs(cx) + fabs(by));
     const double e1 = cratio(sqrt(S[0]), sqrt(S[1]), sqrt(S[2]));
     const double e2 = cratio(sqrt(S[3]), sqrt(S[4]), sqrt(S[6]));
     eps_c = e1 > e2 ? e1 : e2;
@@ -284,13 +348,13 @@ __global__ __launch_bounds__(HS_NT) void k_hsde_finish(HsdeArgs h) {
       return;
     }
   } else {
-    const double tp = sqrt(r2) - (s.nrm_b > 0.0 ? s.bty / s.nrm_b : 0.0) * P.tol;
-    const double td = sqrt(s.ax2) + (s.nrm_c > 0.0 ? s.ctx / s.nrm_c : 0.0) * P.tol;
-    if (tp <= 0.0 && s.bty > 0.0) {
+    const double tp = sqrt(r2) - (s.nrm_b > 0.0 ? bty / s.nrm_b : 0.0) * P.tol;
+    const double td = sqrt(ax2) + (s.nrm_c > 0.0 ? ctx / s.nrm_c : 0.0) * P.tol;
+    if (tp <= 0.0 && bty > 0.0) {
       st.done = 3;
       return;
     }
-    if (td <= 0.0 && s.ctx < 0.0) {
+    if (td <= 0.0 && ctx < 0.0) {
       st.done = 4;
       return;
     }
@@ -345,12 +409,18 @@ hipError_t launch_hsde_setup_nu(const HsdeArgs &h, hipStream_t st) {
 }
 
 hipError_t launch_hsde_update(const HsdeArgs &h, hipStream_t st) {
-  hipLaunchKernelGGL(k_hsde_update, dim3(h.batch), dim3(HS_NT), 0, st, h);
+  const int64_t n = h.ncoord > h.nrow ? h.ncoord : h.nrow;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_hsde_zs_partials, dim3(nb), dim3(256), 0, st, h);
+  hipLaunchKernelGGL(k_hsde_scalars, dim3((h.batch + 255) / 256), dim3(256), 0, st, h);
+  hipLaunchKernelGGL(k_hsde_apply, dim3(nb), dim3(256), 0, st, h);
   return hipGetLastError();
 }
 
 hipError_t launch_hsde_finish(const HsdeArgs &h, hipStream_t st) {
-  hipLaunchKernelGGL(k_hsde_finish, dim3(h.batch), dim3(HS_NT), 0, st, h);
+  hipLaunchKernelGGL(k_hsde_dual_partials, dim3((unsigned)((h.ncoord + 255) / 256)), dim3(256), 0,
+                     st, h);
+  hipLaunchKernelGGL(k_hsde_finish, dim3(h.batch), dim3(256), 0, st, h);
   return hipGetLastError();
 }
 

@@ -153,6 +153,9 @@ T *dev_upload(const std::vector<T> &v, std::vector<void *> &owned) {
   HIPCHK(hipMalloc((void **)&p, bytes));
   owned.push_back(p);
   if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  // the copy runs on the null stream, which does not order work on the
+  // handle's non-blocking stream: wait for it before anything can read p
+  HIPCHK(hipDeviceSynchronize());
   return p;
 }
 
@@ -163,6 +166,7 @@ T *dev_zeros(size_t count, std::vector<void *> &owned) {
   HIPCHK(hipMalloc((void **)&p, bytes));
   owned.push_back(p);
   HIPCHK(hipMemset(p, 0, bytes));
+  HIPCHK(hipDeviceSynchronize());   // null-stream fill: see dev_upload
   return p;
 }
 
@@ -445,6 +449,8 @@ void setup_hsde(sdp_handle *h, const std::vector<double> &D) {
   g.nt = dev_zeros<double>(pk, own);
   g.mzs = dev_zeros<double>(pk, own);
   g.mzt = dev_zeros<double>(pk, own);
+  g.cw_part = dev_zeros<double>((size_t)(h->ncoord / 64 + 1) * 4, own);
+  g.rw_part = dev_zeros<double>((size_t)(h->nrow / 64 + 1) * 4, own);
   g.part = p.part;
   g.inst_cl_first = a.inst_cl_first;
   g.hist = a.hist;
@@ -581,19 +587,23 @@ void reset_state(sdp_handle *h) {
     s.rho = h->opt.rho;
     s.eps_c = s.eps_l = INFINITY;
   }
-  HIPCHK(hipMemcpy(h->d_state, st.data(), sizeof(InstState) * h->B, hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(h->proj.X, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
-  HIPCHK(hipMemset(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
-  HIPCHK(hipMemset(h->aff.u, 0, sizeof(double) * h->ncoord));
-  HIPCHK(hipMemset(h->aff.y, 0, sizeof(double) * h->nrow));
-  if (h->proj.Vd) HIPCHK(hipMemset(h->proj.Vd, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
+  // every fill below is ordered on the handle's stream (a null-stream fill
+  // would not be ordered with the non-blocking stream's kernels)
+  HIPCHK(hipMemcpyAsync(h->d_state, st.data(), sizeof(InstState) * h->B, hipMemcpyHostToDevice,
+                        h->stream));
+  HIPCHK(hipMemsetAsync(h->proj.X, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
+  HIPCHK(hipMemsetAsync(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
+  HIPCHK(hipMemsetAsync(h->aff.u, 0, sizeof(double) * h->ncoord, h->stream));
+  HIPCHK(hipMemsetAsync(h->aff.y, 0, sizeof(double) * h->nrow, h->stream));
+  if (h->proj.Vd)
+    HIPCHK(hipMemsetAsync(h->proj.Vd, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
   if (h->hsde) {
-    HIPCHK(hipMemset(h->hsa.ux, 0, sizeof(double) * h->ncoord));
-    HIPCHK(hipMemset(h->hsa.uy, 0, sizeof(double) * h->nrow));
-    HIPCHK(hipMemset(h->hsa.ut, 0, sizeof(double) * std::max<int64_t>(h->npk, 1)));
+    HIPCHK(hipMemsetAsync(h->hsa.ux, 0, sizeof(double) * h->ncoord, h->stream));
+    HIPCHK(hipMemsetAsync(h->hsa.uy, 0, sizeof(double) * h->nrow, h->stream));
+    HIPCHK(hipMemsetAsync(h->hsa.ut, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
     HIPCHK(launch_hsde_reset(h->hsa, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
   }
+  HIPCHK(hipStreamSynchronize(h->stream));
   if (h->d_vw) {
     HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N, 0, h->ncl,
                                  h->stream));
@@ -1015,10 +1025,10 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     {
       double *d_M = nullptr;
       HIPCHK(hipMalloc((void **)&d_M, sizeof(double) * std::max<int64_t>(toff, 1)));
-      HIPCHK(hipMemset(d_M, 0, sizeof(double) * std::max<int64_t>(toff, 1)));
+      HIPCHK(hipMemsetAsync(d_M, 0, sizeof(double) * std::max<int64_t>(toff, 1), h->stream));
       int32_t *d_fail = nullptr;
       HIPCHK(hipMalloc((void **)&d_fail, sizeof(int32_t) * batch));
-      HIPCHK(hipMemset(d_fail, 0, sizeof(int32_t) * batch));
+      HIPCHK(hipMemsetAsync(d_fail, 0, sizeof(int32_t) * batch, h->stream));
       std::vector<void *> tmp;
       FactorArgs f{};
       f.inst = h->d_desc;
@@ -1279,10 +1289,14 @@ int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *L
     if (h->hsde) fail(SDP_ERR_UNSUPPORTED, "warm starts are built for Algorithms 1 and 2");
     HIPCHK(hipStreamSynchronize(h->stream));
     const int64_t o = h->npk_off[inst], n = h->inst_npk[inst];
-    if (Xk) HIPCHK(hipMemcpy(h->proj.X + o, Xk, sizeof(double) * n, hipMemcpyHostToDevice));
-    if (Lk) HIPCHK(hipMemcpy(h->proj.Lam + o, Lk, sizeof(double) * n, hipMemcpyHostToDevice));
+    if (Xk)
+      HIPCHK(hipMemcpyAsync(h->proj.X + o, Xk, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    if (Lk)
+      HIPCHK(hipMemcpyAsync(h->proj.Lam + o, Lk, sizeof(double) * n, hipMemcpyHostToDevice,
+                            h->stream));
     if (h->proj.Vd)   // Algorithm 2: the slack blocks start at consensus, v_k = z_k
-      HIPCHK(hipMemcpy(h->proj.Vd + o, h->proj.X + o, sizeof(double) * n, hipMemcpyDeviceToDevice));
+      HIPCHK(hipMemcpyAsync(h->proj.Vd + o, h->proj.X + o, sizeof(double) * n,
+                            hipMemcpyDeviceToDevice, h->stream));
     if (h->d_vw) {
       HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N,
                                    h->cl_first[inst], h->cl_first[inst + 1] - h->cl_first[inst],
@@ -1293,7 +1307,9 @@ int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *L
     InstState s = h->h_state[inst];
     s.rho = rho;
     s.done = 0;
-    HIPCHK(hipMemcpy(h->d_state + inst, &s, sizeof(InstState), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(h->d_state + inst, &s, sizeof(InstState), hipMemcpyHostToDevice,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     h->have_diag = false;
     return SDP_OK;
   });

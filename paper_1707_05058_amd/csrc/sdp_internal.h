@@ -252,7 +252,9 @@ struct HsdeArgs {
   int64_t npk;
   const int32_t *blk_loc;
   double *us, *vz, *ut, *ns, *nt, *mzs, *mzt;
-  // clique partials (NPART per clique) and history
+  // wave partial sums (4 per 64 coordinates / rows), clique partials
+  // (NPART per clique) and history
+  double *cw_part, *rw_part;
   const double *part;
   const int64_t *inst_cl_first;
   double *hist;
