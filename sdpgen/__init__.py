@@ -162,6 +162,10 @@ def random_instance(n: int, cliques: Sequence[np.ndarray], m: int, seed=None,
     if rng is None:
         rng = np.random.default_rng(seed)
     pat_row, pat_col = pattern_from_cliques(n, cliques)
+    return _instance_on(n, pat_row, pat_col, list(cliques), m, rng, seed, density, name, meta)
+
+
+def _instance_on(n, pat_row, pat_col, cliques, m, rng, seed, density, name, meta) -> Instance:
     nnz = pat_row.shape[0]
     if density is None:
         a_val = rng.standard_normal((m, nnz))
@@ -183,7 +187,7 @@ def random_instance(n: int, cliques: Sequence[np.ndarray], m: int, seed=None,
         a_val = np.concatenate(rows_v)
         fmt = A_CSR
     y0 = rng.standard_normal(m)
-    return _finish(n, m, pat_row, pat_col, list(cliques), fmt, a_val, a_rowptr,
+    return _finish(n, m, pat_row, pat_col, cliques, fmt, a_val, a_rowptr,
                    a_col, y0, name, dict(meta or {}, seed=seed))
 
 
@@ -242,6 +246,95 @@ def dual_infeasible_instance(l, d, h, m, seed) -> Instance:
     return Instance(n=base.n, m=m, pat_row=base.pat_row, pat_col=base.pat_col,
                     clique_ptr=base.clique_ptr, clique_vert=base.clique_vert, a_format=A_DENSE,
                     a_val=a, b=b, c=c, name=f"dual_infeasible_l{l}_d{d}_h{h}_m{m}_s{seed}")
+
+
+# ----------------------------------------------------------------------------
+# Nonchordal patterns (Section "Nonchordal SDPs": the cone's pattern is first
+# given a chordal extension).  These instances carry no cliques: the solver
+# takes them only after the extension step.
+# ----------------------------------------------------------------------------
+
+def _lower_sorted(n: int, edges) -> tuple:
+    """Lower coordinates of the edges plus every diagonal, sorted (col, row)."""
+    keys = [np.arange(n, dtype=np.int64) * (n + 1)]
+    if len(edges):
+        e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+        hi, lo = np.maximum(e[:, 0], e[:, 1]), np.minimum(e[:, 0], e[:, 1])
+        keys.append(lo * n + hi)
+    k = np.unique(np.concatenate(keys))
+    return (k % n).astype(np.int32), (k // n).astype(np.int32)
+
+
+def grid_pattern(rows: int, cols: int):
+    """4-neighbour grid graph on rows x cols vertices (vertex r*cols + c);
+    nonchordal for rows, cols >= 2 (every unit square is a chordless 4-cycle)."""
+    edges = []
+    for r in range(rows):
+        for c in range(cols):
+            v = r * cols + c
+            if c + 1 < cols:
+                edges.append((v, v + 1))
+            if r + 1 < rows:
+                edges.append((v, v + cols))
+    return _lower_sorted(rows * cols, edges)
+
+
+def cycle_pattern(n: int):
+    """The chordless cycle 0-1-...-(n-1)-0."""
+    return _lower_sorted(n, [(i, (i + 1) % n) for i in range(n)])
+
+
+def random_sparse_pattern(n: int, avg_degree: float, seed: int):
+    """A path through all vertices (so the graph is connected) plus uniformly
+    drawn extra edges up to the average degree."""
+    rng = np.random.default_rng(seed)
+    edges = [(i, i + 1) for i in range(n - 1)]
+    extra = max(0, int(round(avg_degree * n / 2)) - (n - 1))
+    a = rng.integers(0, n, size=extra)
+    b = rng.integers(0, n, size=extra)
+    edges += [(int(x), int(y)) for x, y in zip(a, b) if x != y]
+    return _lower_sorted(n, edges)
+
+
+def instance_on_pattern(n: int, pat_row, pat_col, m: int, seed: int, density=None,
+                        name: str = "") -> Instance:
+    """Random data (draw order as for every instance here) on an arbitrary
+    pattern; no cliques."""
+    rng = np.random.default_rng(seed)
+    return _instance_on(n, np.asarray(pat_row, np.int32), np.asarray(pat_col, np.int32), [], m,
+                        rng, seed, density, name or f"pattern_n{n}_m{m}_s{seed}", {})
+
+
+def workload_nonchordal(seed: int = 0, rows: int = 45, cols: int = 45, m: int = 200,
+                        density: float = 0.05) -> Instance:
+    """Stand-in for the nonchordal experiments (cone sizes about 2000-7500,
+    m = 200, sparse constraints): a 45 x 45 grid (n = 2025) with m = 200 sparse
+    random constraints on its pattern."""
+    pr, pc = grid_pattern(rows, cols)
+    return instance_on_pattern(rows * cols, pr, pc, m, seed, density=density,
+                               name=f"grid{rows}x{cols}_m{m}_s{seed}")
+
+
+def rescaled_instance(inst: Instance, seed: int, row_decades: float = 3.0,
+                      vertex_decades: float = 1.0, obj_factor: float = 100.0) -> Instance:
+    """An equivalent, badly scaled copy: A_i -> f_i T A_i T, b_i -> f_i b_i,
+    C -> g T C T with T = diag(t), log10 f ~ U(-row_decades, row_decades),
+    log10 t ~ U(-vertex_decades, vertex_decades), g = obj_factor.  X solves the
+    copy iff T X T solves the original; the optimal value is multiplied by g."""
+    rng = np.random.default_rng(seed)
+    f = 10.0 ** rng.uniform(-row_decades, row_decades, inst.m)
+    t = 10.0 ** rng.uniform(-vertex_decades, vertex_decades, inst.n)
+    tt = t[inst.pat_row] * t[inst.pat_col]
+    if inst.a_format == A_DENSE:
+        a = f[:, None] * inst.a_val * tt[None, :]
+    else:
+        rows = np.repeat(np.arange(inst.m), np.diff(inst.a_rowptr))
+        a = f[rows] * inst.a_val * tt[inst.a_col]
+    return Instance(n=inst.n, m=inst.m, pat_row=inst.pat_row, pat_col=inst.pat_col,
+                    clique_ptr=inst.clique_ptr, clique_vert=inst.clique_vert,
+                    a_format=inst.a_format, a_val=a, b=f * inst.b, c=obj_factor * tt * inst.c,
+                    a_rowptr=inst.a_rowptr, a_col=inst.a_col, name=inst.name + "_rescaled",
+                    meta=dict(inst.meta, f=f, t=t, g=obj_factor))
 
 
 # ----------------------------------------------------------------------------

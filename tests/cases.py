@@ -64,3 +64,28 @@ def singleton_clique_instance(seed=3):
     n = 3 * 4 + 2 + 1
     cl = cl + [np.array([n - 1], dtype=np.int32)]
     return sdpgen.random_instance(n, cl, 7, rng=rng, name="with_singleton")
+
+
+def oracle_extended(inst):
+    """The instance on the oracle's chordal extension of its pattern, with the
+    oracle's maximal cliques (A and C zero on the added coordinates)."""
+    from oracle import preprocess
+    pr, pc, cl = preprocess.chordal_extension(inst.n, inst.pat_row, inst.pat_col)
+    pos = {(int(r), int(c)): j for j, (r, c) in enumerate(zip(pr, pc))}
+    idx = np.array([pos[(int(r), int(c))] for r, c in zip(inst.pat_row, inst.pat_col)])
+    a = np.zeros((inst.m, pr.shape[0]))
+    a[:, idx] = inst.a_dense()
+    c = np.zeros(pr.shape[0])
+    c[idx] = inst.c
+    ptr, vert = sdpgen.cliques_to_csr([np.array(k, dtype=np.int32) for k in cl])
+    return sdpgen.Instance(n=inst.n, m=inst.m, pat_row=pr, pat_col=pc, clique_ptr=ptr,
+                           clique_vert=vert, a_format=sdpgen.A_DENSE, a_val=a, b=inst.b.copy(),
+                           c=c, name=inst.name + "_ext")
+
+
+def as_instance(d):
+    """An sdpgen.Instance with the fields of any instance-like object."""
+    return sdpgen.Instance(n=int(d.n), m=int(d.m), pat_row=d.pat_row, pat_col=d.pat_col,
+                           clique_ptr=d.clique_ptr, clique_vert=d.clique_vert,
+                           a_format=int(d.a_format), a_val=d.a_val, b=d.b, c=d.c,
+                           a_rowptr=d.a_rowptr, a_col=d.a_col, name=getattr(d, "name", ""))
