@@ -283,6 +283,82 @@ void sdp_destroy(sdp_handle *h);
 /* Thread-local message of the last non-zero status ("" if none). */
 const char *sdp_last_error(void);
 
+/* ---- generic sparsity patterns (host only, no device work) -------------- */
+/* A pattern that is not chordal is first replaced by a chordal extension
+ * whose maximal cliques define the decomposition (Theorem 1; Section 7.1.1
+ * describes this preprocessing).  The extension computed here is the filled
+ * graph of a symbolic Cholesky elimination under a greedy minimum-degree
+ * order (ties broken by the smaller vertex label); its maximal cliques are
+ * read off that perfect elimination order.  Both are deterministic. */
+typedef struct sdp_pattern sdp_pattern;   /* opaque; host memory only */
+
+/* Builds the chordal extension of the symmetric pattern on n vertices given
+ * by nnz coordinates (row[k], col[k]) in [0, n) (either triangle, duplicates
+ * and diagonal entries allowed; the diagonal is always part of the result).
+ * On success *out owns the result (release with sdp_pattern_destroy);
+ * SDP_ERR_ARG for n <= 0, nnz < 0, NULL arrays or coordinates out of range. */
+int sdp_pattern_create(int32_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                       sdp_pattern **out);
+
+/* Sizes of the result: *nnz_ext lower coordinates of the extended pattern,
+ * *p maximal cliques holding *clique_total vertices in all.  Any output
+ * pointer may be NULL. */
+int sdp_pattern_sizes(const sdp_pattern *pat, int64_t *nnz_ext, int32_t *p,
+                      int64_t *clique_total);
+
+/* Copies the result into caller arrays (each may be NULL to skip it):
+ * pat_row/pat_col [nnz_ext] the extended lower pattern in the order
+ * sdp_instance expects (sorted by column, then row, every diagonal present);
+ * clique_ptr [p + 1] and clique_vert [clique_total] the maximal cliques,
+ * vertices increasing, cliques in lexicographic order.  With index_out
+ * non-NULL, each of the nnz coordinates (row[k], col[k]) (either triangle)
+ * is mapped to its position in the extended pattern (always found for a
+ * coordinate of the original pattern; -1 if not in the extension). */
+int sdp_pattern_get(const sdp_pattern *pat, int32_t *pat_row, int32_t *pat_col,
+                    int32_t *clique_ptr, int32_t *clique_vert, int64_t nnz,
+                    const int32_t *row, const int32_t *col, int64_t *index_out);
+
+/* Releases the pattern (NULL is ignored). */
+void sdp_pattern_destroy(sdp_pattern *pat);
+
+/* ---- data scaling (host only, no device work) --------------------------- */
+/* Section 7.1.3: the problem is rescaled by positive diagonal matrices on the
+ * variable (preserving the cone) and on the equality constraints and by
+ * positive scalars on b and C, so that the rows of A and b have norms near one
+ * and the columns of A and c similar norms.  The variable scaling used here
+ * is a congruence X -> S X S by one positive diagonal S over the vertices,
+ * which keeps the pattern and every clique block's PSD cone:
+ *     A'_i = e_i S A_i S,   b'_i = rho_b e_i b_i,   C' = sigma_c S C S.
+ * The scaled instance has the same pattern, cliques and A layout, so the
+ * solver runs on it unchanged; its tolerance then applies to the scaled
+ * problem. */
+
+/* Computes e [m] (row_scale), s [n] (vertex_scale), rho_b and sigma_c: iters
+ * Ruiz iterations from e = s = 1, each taking ||A'_i||_F and the norm of
+ * vertex v's row over all A'_i on the current scaled A and dividing e_i and
+ * s_v by the square roots of those norms (zero norms leave the factor alone;
+ * factors clamped to [1e-4, 1e4]); then rho_b = mean row norm / ||E b||_2 and
+ * sigma_c = mean vertex norm / ||S C S||_F (denominators at least 1e-4, results
+ * clamped to [1e-4, 1e4]).  The instance's cliques are not read.
+ * SDP_ERR_ARG / SDP_ERR_NONFINITE on invalid data. */
+int sdp_scale_compute(const sdp_instance *inst, int32_t iters, double *row_scale,
+                      double *vertex_scale, double *rho_b, double *sigma_c);
+
+/* Writes the scaled data: a_val_out in the instance's own A layout (dense
+ * m x nnz_pattern, or the CSR values in a_col order), b_out [m], c_out
+ * [nnz_pattern]; each may be NULL.  The scalings are the caller's (from
+ * sdp_scale_compute or any positive values). */
+int sdp_scale_apply(const sdp_instance *inst, const double *row_scale, const double *vertex_scale,
+                    double rho_b, double sigma_c, double *a_val_out, double *b_out,
+                    double *c_out);
+
+/* Maps a solution of the scaled problem back, in place: x [nnz_pattern] (the
+ * lower pattern values of X) to S X S / rho_b, y [m] to E y / sigma_c and
+ * z [nnz_pattern] (of Z = C - sum y_i A_i) to S^-1 Z S^-1 / sigma_c; each may
+ * be NULL.  Only n, m and the pattern of inst are read. */
+int sdp_scale_recover(const sdp_instance *inst, const double *row_scale, const double *vertex_scale,
+                      double rho_b, double sigma_c, double *x, double *y, double *z);
+
 #ifdef __cplusplus
 }
 #endif

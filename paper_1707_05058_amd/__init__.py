@@ -11,10 +11,13 @@ from ._native import (A_CSR, A_DENSE, ALG_DUAL, ALG_HSDE, ALG_PRIMAL, DTYPE_FP32
                       SdpError, Solver, default_options, lib, make_options, pack_blocks,
                       projection_variants, psd_project_batched, sdp_result, setup_status,
                       unpack_blocks)
+from .preprocess import (ChordalPattern, InstanceData, Scaling, chordal_extension,
+                         extend_instance, scale_instance)
 
 __all__ = ["Solver", "SdpError", "psd_project_batched", "projection_variants", "setup_status",
            "make_options",
            "default_options", "pack_blocks", "unpack_blocks", "lib", "EXPORTS", "FP64",
            "FP32_EIG", "DTYPE_FP32", "DTYPE_FP64", "A_DENSE", "A_CSR", "ALG_PRIMAL", "ALG_DUAL", "ALG_HSDE",
            "PRIMAL_INFEASIBLE", "DUAL_INFEASIBLE",
-           "sdp_result"]
+           "sdp_result", "ChordalPattern", "InstanceData", "Scaling", "chordal_extension",
+           "extend_instance", "scale_instance"]

@@ -73,7 +73,9 @@ EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sd
            "sdp_psd_project_batched", "sdp_projection_variants", "sdp_psd_project_variant",
            "sdp_get_solution", "sdp_set_state", "sdp_get_history",
            "sdp_diagnostics", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
-           "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_destroy", "sdp_last_error"]
+           "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_destroy", "sdp_last_error",
+           "sdp_pattern_create", "sdp_pattern_sizes", "sdp_pattern_get", "sdp_pattern_destroy",
+           "sdp_scale_compute", "sdp_scale_apply", "sdp_scale_recover"]
 
 STAGES = ["scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "projection", "residual"]
 
@@ -112,6 +114,8 @@ def _load():
     lib.sdp_last_error.argtypes = []
     lib.sdp_last_error.restype = C.c_char_p
     for name in EXPORTS:
+        if name.startswith(("sdp_pattern_", "sdp_scale_")):
+            continue                      # typed in preprocess.py
         if name not in ("sdp_default_options", "sdp_destroy", "sdp_last_error"):
             getattr(lib, name).restype = C.c_int
     return lib

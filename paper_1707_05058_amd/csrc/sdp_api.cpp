@@ -1617,3 +1617,7 @@ void sdp_destroy(sdp_handle *h) { destroy_handle(h); }
 const char *sdp_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+// Lets the pattern routines (a separate translation unit) report errors
+// through the same thread-local message.
+void sdp_set_last_error(const std::string &msg) { g_last_error = msg; }
