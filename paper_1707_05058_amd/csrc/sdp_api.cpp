@@ -311,6 +311,14 @@ struct sdp_handle {
   std::vector<HsdeState> h_hs;
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
+  // Buckets of different block sizes run concurrently: bucket_order[0] (the
+  // largest block size, the longest per-clique latency) is enqueued first on
+  // an auxiliary stream forked from the iteration's stream, the others after
+  // it, the last on the iteration's stream itself; then everything joins.
+  std::vector<int> bucket_order;
+  std::vector<hipStream_t> aux_stream;   // bucket_order.size() - 1 of them
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   int hist_cap = 0;
@@ -340,9 +348,27 @@ struct sdp_handle {
 namespace {
 
 void enqueue_projections(sdp_handle *h, const ProjArgs &p, hipStream_t st) {
-  for (size_t b = 0; b < h->bucket_size.size(); ++b)
+  const size_t nb = h->bucket_order.size();
+  if (nb <= 1 || h->aux_stream.size() + 1 != nb) {
+    for (size_t b = 0; b < h->bucket_size.size(); ++b)
+      HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
+                                    h->bucket_count[b], p, st));
+    return;
+  }
+  // fork: every bucket but the last on its own stream, ordered after st
+  HIPCHK(hipEventRecord(h->ev_fork, st));
+  for (size_t i = 0; i + 1 < nb; ++i) {
+    const int b = h->bucket_order[i];
+    HIPCHK(hipStreamWaitEvent(h->aux_stream[i], h->ev_fork, 0));
     HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                  h->bucket_count[b], p, st));
+                                  h->bucket_count[b], p, h->aux_stream[i]));
+    HIPCHK(hipEventRecord(h->ev_join[i], h->aux_stream[i]));
+  }
+  const int last = h->bucket_order[nb - 1];
+  HIPCHK(launch_admm_projection(h->precision, h->bucket_size[last], h->bucket_list[last],
+                                h->bucket_count[last], p, st));
+  // join: st continues only after every bucket
+  for (size_t i = 0; i + 1 < nb; ++i) HIPCHK(hipStreamWaitEvent(st, h->ev_join[i], 0));
 }
 
 // Algorithm 1: x-update (affine), projections with the multiplier update,
@@ -622,6 +648,10 @@ void destroy_handle(sdp_handle *h) {
   if (h->d_eigbuf) (void)hipFree(h->d_eigbuf);
   if (h->h_state) (void)hipHostFree(h->h_state);
   if (h->h_obj) (void)hipHostFree(h->h_obj);
+  for (hipStream_t a : h->aux_stream) (void)hipStreamSynchronize(a);
+  for (hipStream_t a : h->aux_stream) (void)hipStreamDestroy(a);
+  for (hipEvent_t e : h->ev_join) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
@@ -972,6 +1002,21 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     for (auto &l : lists) {
       h->bucket_list.push_back(dev_upload(l, own));
       h->bucket_count.push_back((int)l.size());
+    }
+    h->bucket_order.resize(lists.size());
+    for (size_t b = 0; b < lists.size(); ++b) h->bucket_order[b] = (int)b;
+    std::stable_sort(h->bucket_order.begin(), h->bucket_order.end(),
+                     [&](int x, int y) { return h->bucket_N[x] > h->bucket_N[y]; });
+    if (lists.size() > 1) {
+      HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      for (size_t i = 0; i + 1 < lists.size(); ++i) {
+        hipStream_t a = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+        h->aux_stream.push_back(a);
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->ev_join.push_back(e);
+      }
     }
     h->cl_first = cl_first;
     h->d_clique_N = dev_upload(h->clique_N, own);
