@@ -56,6 +56,12 @@ def _load():
     lib.orc_run.restype = C.c_int
     lib.orc_run_dual.argtypes = lib.orc_run.argtypes
     lib.orc_run_dual.restype = C.c_int
+    lib.orc_set_affine_cg.argtypes = [C.c_void_p, C.c_int, C.c_double]
+    lib.orc_set_affine_cg.restype = C.c_int
+    lib.orc_pcg.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_double, _dp]
+    lib.orc_pcg.restype = C.c_int
+    lib.orc_cg_steps.argtypes = [C.c_void_p]
+    lib.orc_cg_steps.restype = C.c_int64
     lib.orc_dual_objective.argtypes = [C.c_void_p]
     lib.orc_dual_objective.restype = C.c_double
     lib.orc_get_vd.argtypes = [C.c_void_p, _dp]
@@ -364,6 +370,26 @@ class Problem:
 
     def y_dual(self):
         return -self.rho * self.y()
+
+    # conjugate-gradient affine step ----------------------------------------
+    def set_affine_cg(self, max_iter: int, tol: float = 0.0):
+        """Algorithm 1's affine step by preconditioned CG (max_iter > 0) or by
+        the cached factor (max_iter = 0)."""
+        rc = _load().orc_set_affine_cg(self._h, int(max_iter), float(tol))
+        if rc != OK:
+            raise OracleError(rc)
+
+    def pcg(self, rhs, y0, max_iter: int, tol_abs: float = 0.0):
+        """Standalone PCG on (A W D^-1 A^T) y = rhs from y0 (after
+        set_affine_cg): (y, residual norms ||r_j||_2 for j = 0..steps)."""
+        y = np.array(y0, dtype=np.float64)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        hist = np.zeros(max_iter + 1)
+        k = _load().orc_pcg(self._h, _d(rhs), _d(y), int(max_iter), float(tol_abs), _d(hist))
+        return y, hist[:k + 1]
+
+    def cg_steps(self) -> int:
+        return int(_load().orc_cg_steps(self._h))
 
     def D(self):
         out = np.zeros(self.nnz)

@@ -22,6 +22,9 @@
  *     multiplier update (LambdakUpdate), then the stopping test on
  *     eps_c and eps_lambda (PrimalConsensusResidual).
  *   - Optional adaptive penalty of the Section "Adaptive penalty strategy".
+ *   - Optional affine step by preconditioned conjugate gradients, the
+ *     iterative alternative to the factorisation that Section 4.1.1 names
+ *     (Jacobi preconditioner, warm start from the previous multiplier).
  *   - Diagnostics eps_p, eps_d, eps_g (HSDEerror) and eps_alpha
  *     (PSD-violation), as the paper reports them for its primal solver.
  *
@@ -106,6 +109,14 @@ typedef struct orc_problem {
   double eps_p, eps_d, eps_g;
   int hsde_status;
   double *u, *y, *bhat, *r, *tmp;
+  /* Affine step by preconditioned conjugate gradients instead of the cached
+   * factor (the iterative alternative of Section 4.1.1): at most cg_max_iter
+   * steps, stop when ||r||_2 <= cg_tol (1 + ||b||_2), Jacobi preconditioner
+   * diag(A W D^-1 A^T), warm start from the previous y. */
+  int cg_max_iter;    /* 0: Cholesky */
+  double cg_tol;
+  double *cg_diag, *cg_r, *cg_z, *cg_p, *cg_Mp, *cg_t;
+  int64_t cg_steps;   /* conjugate-gradient steps taken so far */
   int64_t nblk;       /* sum s_k^2 */
   int iters;
   double eps_c, eps_l;
@@ -376,6 +387,7 @@ void orc_free(orc_problem *P) {
   free(P->hx); free(P->hs); free(P->hy); free(P->ht);
   free(P->hx2); free(P->hs2); free(P->hy2); free(P->ht2);
   free(P->u); free(P->y); free(P->bhat); free(P->r); free(P->tmp);
+  free(P->cg_diag); free(P->cg_r); free(P->cg_z); free(P->cg_p); free(P->cg_Mp); free(P->cg_t);
   free(P);
 }
 
@@ -549,6 +561,7 @@ void orc_reset(orc_problem *P, double rho0) {
   P->eps_c = P->eps_l = INFINITY;
   P->total_sweeps = 0;
   P->max_sweeps_seen = 0;
+  P->cg_steps = 0;
 }
 
 void orc_set_jacobi(orc_problem *P, int max_sweeps, double tol) {
@@ -577,6 +590,84 @@ void orc_form_bhat(const orc_problem *P, const double *X, const double *Lam,
   for (int64_t j = 0; j < P->nnz; ++j) bhat[j] -= P->c[j] / rho;
 }
 
+/* out = A W D^-1 A^T v, without forming the matrix. */
+static void gram_times(orc_problem *P, const double *v, double *out) {
+  at_times(P, v, P->cg_t);
+  for (int64_t j = 0; j < P->nnz; ++j) P->cg_t[j] *= P->w[j] / P->D[j];
+  a_times(P, P->cg_t, out);
+}
+
+static double dot_m(int m, const double *a, const double *b) {
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) s += a[i] * b[i];
+  return s;
+}
+
+/* Switches the affine step to preconditioned conjugate gradients (max_iter
+ * > 0) or back to the cached factor (max_iter = 0).  The preconditioner is
+ * the diagonal of A W D^-1 A^T: sum_j A_ij^2 w_j / D_j. */
+int orc_set_affine_cg(orc_problem *P, int max_iter, double tol) {
+  if (max_iter < 0 || !(tol >= 0)) return ORC_ERR_ARG;
+  P->cg_max_iter = max_iter;
+  P->cg_tol = tol;
+  if (max_iter == 0 || P->cg_diag) return ORC_OK;
+  int m = P->m > 0 ? P->m : 1;
+  P->cg_diag = (double *)calloc(m, sizeof(double));
+  P->cg_r = (double *)calloc(m, sizeof(double));
+  P->cg_z = (double *)calloc(m, sizeof(double));
+  P->cg_p = (double *)calloc(m, sizeof(double));
+  P->cg_Mp = (double *)calloc(m, sizeof(double));
+  P->cg_t = (double *)calloc(P->nnz, sizeof(double));
+  for (int i = 0; i < P->m; ++i) {
+    double s = 0.0;
+    if (P->a_format == 0) {
+      for (int64_t j = 0; j < P->nnz; ++j) {
+        double a = P->a_val[(size_t)i * P->nnz + j];
+        s += a * a * P->w[j] / P->D[j];
+      }
+    } else {
+      for (int64_t t = P->a_rowptr[i]; t < P->a_rowptr[i + 1]; ++t)
+        s += P->a_val[t] * P->a_val[t] * P->w[P->a_col[t]] / P->D[P->a_col[t]];
+    }
+    P->cg_diag[i] = s;
+  }
+  return ORC_OK;
+}
+
+/* Preconditioned conjugate gradients (Saad, Iterative Methods for Sparse
+ * Linear Systems, the preconditioned CG algorithm with a left/split Jacobi
+ * preconditioner) on (A W D^-1 A^T) y = rhs from the y passed in.  Before
+ * every step the residual is tested: ||r||_2 <= tol_abs stops.  Optional
+ * history of ||r_j||_2 (j = 0..steps).  Returns the steps taken. */
+int orc_pcg(orc_problem *P, const double *rhs, double *y, int max_iter, double tol_abs,
+            double *hist_rnorm) {
+  const int m = P->m;
+  double *r = P->cg_r, *z = P->cg_z, *p = P->cg_p, *Mp = P->cg_Mp;
+  gram_times(P, y, Mp);
+  for (int i = 0; i < m; ++i) r[i] = rhs[i] - Mp[i];
+  for (int i = 0; i < m; ++i) z[i] = r[i] / P->cg_diag[i];
+  for (int i = 0; i < m; ++i) p[i] = z[i];
+  double rz = dot_m(m, r, z);
+  double rn = sqrt(dot_m(m, r, r));
+  if (hist_rnorm) hist_rnorm[0] = rn;
+  int j = 0;
+  while (j < max_iter && !(rn <= tol_abs)) {
+    gram_times(P, p, Mp);
+    const double alpha = rz / dot_m(m, p, Mp);
+    for (int i = 0; i < m; ++i) y[i] += alpha * p[i];
+    for (int i = 0; i < m; ++i) r[i] -= alpha * Mp[i];
+    for (int i = 0; i < m; ++i) z[i] = r[i] / P->cg_diag[i];
+    const double rz_new = dot_m(m, r, z);
+    const double beta = rz_new / rz;
+    for (int i = 0; i < m; ++i) p[i] = z[i] + beta * p[i];
+    rz = rz_new;
+    rn = sqrt(dot_m(m, r, r));
+    ++j;
+    if (hist_rnorm) hist_rnorm[j] = rn;
+  }
+  return j;
+}
+
 /* Solve the KKT system (OptCondMinYPrimal) for given bhat by block
  * elimination (KKTflops): L L^T y = A W D^-1 bhat - b, u = D^-1(bhat - A^T y). */
 void orc_affine(orc_problem *P, const double *bhat, const double *bvec,
@@ -588,6 +679,21 @@ void orc_affine(orc_problem *P, const double *bhat, const double *bvec,
   at_times(P, y, P->tmp);
   for (int64_t j = 0; j < P->nnz; ++j) u[j] = (bhat[j] - P->tmp[j]) / P->D[j];
 }
+
+/* The same elimination with y from orc_pcg, started at the y of the previous
+ * iteration (Algorithm 1 in conjugate-gradient mode). */
+static void affine_cg(orc_problem *P, const double *bhat, const double *bvec, double *u,
+                      double *y) {
+  for (int64_t j = 0; j < P->nnz; ++j) P->tmp[j] = P->w[j] * bhat[j] / P->D[j];
+  a_times(P, P->tmp, P->r);
+  for (int i = 0; i < P->m; ++i) P->r[i] -= bvec[i];
+  const double tol_abs = P->cg_tol * (1.0 + sqrt(dot_m(P->m, bvec, bvec)));
+  P->cg_steps += orc_pcg(P, P->r, y, P->cg_max_iter, tol_abs, NULL);
+  at_times(P, y, P->tmp);
+  for (int64_t j = 0; j < P->nnz; ++j) u[j] = (bhat[j] - P->tmp[j]) / P->D[j];
+}
+
+int64_t orc_cg_steps(const orc_problem *P) { return P->cg_steps; }
 
 /* E_k U E_k^T as a full s x s block. */
 static void gather_block(const orc_problem *P, int k, const double *u, double *Uk) {
@@ -616,7 +722,8 @@ int orc_run(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
     double rho = P->rho;
     /* x-update */
     orc_form_bhat(P, P->X, P->Lam, rho, P->bhat);
-    orc_affine(P, P->bhat, P->b, P->u, P->y);
+    if (P->cg_max_iter > 0) affine_cg(P, P->bhat, P->b, P->u, P->y);
+    else orc_affine(P, P->bhat, P->b, P->u, P->y);
     memcpy(P->Xprev, P->X, sizeof(double) * P->nblk);
     /* clique projections and multiplier updates (independent over k) */
 #pragma omp parallel for schedule(dynamic, 1)
