@@ -42,6 +42,9 @@ WORKLOADS = {
                "seeds 0..511, solved together",
     "adjoint": "64 block-arrow SDPs l=50 d=16 h=8 (n=808, 50 cliques of 24), m=400, seeds 0..63: "
                "200 unrolled iterations checkpointed every 20, forward + reverse sweep",
+    "large_m": "banded n=20000, half-bandwidth 15 (19985 cliques of 16), m=40000 sparse "
+               "constraints of 64 N(0,1) coordinates each, seed 0; affine step by Jacobi-"
+               "preconditioned conjugate gradients, 3 steps per iteration (no m x m factor)",
     "nonchordal": "45 x 45 grid graph pattern (n=2025, nonchordal), m=200 sparse (5%) N(0,1) "
                   "constraints, seed 0, solved on its chordal extension (minimum-degree "
                   "elimination fill: 1540 maximal cliques of 3..76 vertices)",
@@ -49,9 +52,12 @@ WORKLOADS = {
                   "(symmetric N(0,1), about half the eigenvalues negative) per size "
                   "s in {15, 16, 24, 32, 50, 64, 96, 128}, seed = s",
 }
+# solver options of workloads that need more than the defaults
+EXTRA_OPTIONS = {"large_m": dict(cg_max_iter=3, cg_tol=0.0)}
 # precision forms each workload is timed in (FP64 blocks stop at 96 x 96)
 FORMS = {"banded": ("fp32", "fp64"), "small": ("fp32", "fp64"), "large": ("fp32",),
-         "batched": ("fp32", "fp64"), "nonchordal": ("fp32", "fp64"), "adjoint": ("fp32", "fp64"), "projection": ("fp32", "fp64")}
+         "batched": ("fp32", "fp64"), "nonchordal": ("fp32", "fp64"), "large_m": ("fp32", "fp64"),
+         "adjoint": ("fp32", "fp64"), "projection": ("fp32", "fp64")}
 
 
 def make_instances(name, batch_count):
@@ -68,10 +74,12 @@ def make_instances(name, batch_count):
         return sdpgen.workload_adjoint(range(min(batch_count, 64)))
     if name == "nonchordal":
         return [sdpgen.workload_nonchordal()]
+    if name == "large_m":
+        return [sdpgen.workload_large_m()]
     raise SystemExit(f"unknown workload {name}")
 
 
-def stage_bytes_flops(insts, precision, sweeps, algorithm="primal"):
+def stage_bytes_flops(insts, precision, sweeps, algorithm="primal", cg_steps=0):
     """Algorithmic HBM bytes (or FLOPs) per launch of each stage, summed over
     the instances of the batch.  Dense A is streamed as B = L^-1 A (same size)
     and needs no triangular passes; sparse A is streamed as CSR (12 bytes per
@@ -79,9 +87,14 @@ def stage_bytes_flops(insts, precision, sweeps, algorithm="primal"):
     clique of size s with `sweeps` Jacobi sweeps on average: 6 s^3 per sweep
     (each of the s(s-1)/2 rotations of a sweep updates two rows and columns of
     the symmetric block and two columns of V), 4 s^3 for V0^T W V0 (warm
-    start), 4 s^3 for the Newton-Schulz step and s^3 for the rebuild."""
+    start), 4 s^3 for the Newton-Schulz step and s^3 for the rebuild.
+    With the conjugate-gradient affine step (cg_steps per iteration) A is
+    streamed as itself; each step is one column pass (A^T p, written as
+    W D^-1 A^T p), one row pass (A v) and the per-instance row-vector update
+    (11 row vectors of 8 bytes); the start reads r and diag and writes z, p."""
     import numpy as np
-    tot = {k: 0 for k in ("scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "residual", "proj")}
+    tot = {k: 0 for k in ("scatter", "A_v", "Linv_r", "LinvT_y", "AT_y", "residual", "proj",
+                          "cg_solve")}
     for inst in insts:
         m, nnz = inst.m, inst.nnz
         sizes = inst.clique_sizes().astype(np.int64)
@@ -89,7 +102,13 @@ def stage_bytes_flops(insts, precision, sweeps, algorithm="primal"):
         tot["scatter"] += 8 * 2 * npk + 4 * npk + 8 * 5 * nnz
         tot["residual"] += 8 * 6 * inst.p
         tot["proj"] += int(np.sum((6 * sweeps + 9) * sizes ** 3))
-        if inst.a_format == 1 or algorithm == "hsde":
+        if cg_steps > 0:
+            abytes = 12 * int(inst.a_rowptr[-1]) if inst.a_format == 1 else 8 * m * nnz
+            tot["scatter"] += 8 * nnz                      # A^T y of the last solve
+            tot["A_v"] += abytes + 8 * nnz + 16 * m
+            tot["cg_solve"] += 32 * m + cg_steps * (2 * abytes + 32 * nnz + 104 * m)
+            tot["AT_y"] += abytes + 8 * m + 32 * nnz
+        elif inst.a_format == 1 or algorithm == "hsde":
             # sparse A, or the embedding (which keeps A and both triangular passes)
             abytes = 12 * int(inst.a_rowptr[-1]) if inst.a_format == 1 else 8 * m * nnz
             tri = 8 * m * (m + 1) // 2
@@ -101,7 +120,7 @@ def stage_bytes_flops(insts, precision, sweeps, algorithm="primal"):
             bbytes = 8 * m * nnz
             tot["A_v"] += bbytes + 8 * nnz + 16 * m
             tot["AT_y"] += bbytes + 8 * m + 24 * nnz
-    d = {k: dict(bound="hbm", bytes=v) for k, v in tot.items() if k != "proj"}
+    d = {k: dict(bound="hbm", bytes=v) for k, v in tot.items() if k != "proj" and v > 0}
     d["projection"] = dict(bound="alu", flops=tot["proj"],
                            peak_tflops=FP32_VECTOR_TFLOPS if precision == "fp32"
                            else FP64_VECTOR_TFLOPS)
@@ -110,6 +129,7 @@ def stage_bytes_flops(insts, precision, sweeps, algorithm="primal"):
 
 # source file of each stage's kernels (a summary is stale once that file changes)
 STAGE_SOURCE = {"scatter": "k_affine.hip", "A_v": "k_affine.hip", "Linv_r": "k_affine.hip",
+                "cg_solve": "k_affine.hip",
                 "LinvT_y": "k_affine.hip", "AT_y": "k_affine.hip", "residual": "k_affine.hip",
                 "projection": "k_project.hip"}
 
@@ -242,13 +262,14 @@ def copy_calibration(torch):
 
 
 def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, repeat_solve=True,
-              algorithm="primal"):
+              algorithm="primal", extra=None):
     out = {}
+    extra = dict(extra or {})
     p_total = sum(i.p for i in insts)
     # --- solve to the 1e-4 residual from a cold start (second solve timed) ---
     t0 = time.perf_counter()
     S = sdp.Solver(insts, tol=1e-4, max_iter=20000, precision=precision,
-                   stream=stream.cuda_stream, algorithm=algorithm)
+                   stream=stream.cuda_stream, algorithm=algorithm, **extra)
     torch.cuda.synchronize()
     out["setup_s"] = time.perf_counter() - t0
     with torch.cuda.stream(stream):
@@ -272,10 +293,12 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     out["jacobi_sweeps_per_projection"] = (S.stats()["jacobi_sweeps"] /
                                            max(S.stats()["projections"], 1))
     out["projection_plan"] = [dict(N=n, threads=t, cliques=c) for n, t, c in S.projection_plan()]
+    if extra.get("cg_max_iter"):
+        out["solve"]["cg_steps_per_iteration"] = S.cg_steps() / max(sum(its), 1)
     S.close()
     # --- the contract: W warm-up + exactly K timed iterations ---
     S = sdp.Solver(insts, tol=0.0, max_iter=10 ** 8, precision=precision,
-                   stream=stream.cuda_stream, algorithm=algorithm)
+                   stream=stream.cuda_stream, algorithm=algorithm, **extra)
     with torch.cuda.stream(stream):
         S.step(warmup, results=False)
         torch.cuda.synchronize()
@@ -294,7 +317,12 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     st1 = S.stats()
     out["timed_sweeps_per_projection"] = ((st1["jacobi_sweeps"] - st0["jacobi_sweeps"]) /
                                           max(st1["projections"] - st0["projections"], 1))
-    out["stages_ms"] = S.time_stages(stage_iters)
+    stages = S.time_stages(stage_iters)
+    if extra.get("cg_max_iter"):
+        # the solve sits in the slot of the first substitution; there is no second
+        stages = {("cg_solve" if k == "Linv_r" else k): v for k, v in stages.items()
+                  if k != "LinvT_y"}
+    out["stages_ms"] = stages
     S.close()
     return out
 
@@ -332,15 +360,18 @@ def time_adjoint(sdp, torch, insts, precision, T, ckpt, stream):
     return out, cb.cpu().numpy(), bb.cpu().numpy()
 
 
-def cpu_baseline(insts, seconds, algorithm="primal"):
+def cpu_baseline(insts, seconds, algorithm="primal", extra=None):
     """The oracle on a bounded sample: the first instances of the workload,
     a few iterations each; the per-iteration time of the whole batch is the
     sum over instances, extrapolated from the sampled ones."""
     import oracle
     per_inst = seconds / min(len(insts), 4)
     times, sampled, total_it = [], [], 0
+    cg = (extra or {}).get("cg_max_iter", 0)
     for inst in insts[:4]:
-        P = oracle.Problem(inst)
+        P = oracle.Problem(inst, factor=not cg)
+        if cg:
+            P.set_affine_cg(cg, (extra or {}).get("cg_tol", 0.0))
         if algorithm == "hsde":
             P.hsde_setup()
             step = P.run_hsde
@@ -361,6 +392,8 @@ def cpu_baseline(insts, seconds, algorithm="primal"):
             f"{dict(primal=1, dual=2, hsde=3)[algorithm]} from a "
             f"zero state on "
             f"{len(sampled)} of {len(insts)} instance(s), FP64, setup excluded")
+    if cg:
+        what += f"; affine step by {cg} conjugate-gradient steps per iteration, as on the GPU"
     if len(insts) > len(sampled):
         what += "; batch time per iteration extrapolated as mean x instance count"
     return dict(value=1.0 / t_iter, unit="iter/s", cores=oracle.max_threads(), kind="oracle",
@@ -448,11 +481,14 @@ def main():
         forms[precision] = time_form(sdp, torch, insts, precision, args.steps, args.warmup,
                                      args.stage_iters, stream,
                                      repeat_solve=args.workload not in ("batched", "large"),
-                                     algorithm=args.algorithm)
+                                     algorithm=args.algorithm,
+                                     extra=EXTRA_OPTIONS.get(args.workload))
         print(f"[bench] {args.workload} {precision}: {forms[precision]['iter_per_s']:.1f} iter/s",
               file=sys.stderr, flush=True)
     head = forms["fp32"]
-    model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"], args.algorithm)
+    extra = EXTRA_OPTIONS.get(args.workload, {})
+    model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"], args.algorithm,
+                              cg_steps=extra.get("cg_max_iter", 0))
     stages = {k: v for k, v in head["stages_ms"].items() if k in model}
     dom = max(stages, key=lambda k: stages[k])
     t_launch = stages[dom] / 1e3
@@ -472,7 +508,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(insts, args.cpu_seconds, args.algorithm)
+        cpu = cpu_baseline(insts, args.cpu_seconds, args.algorithm, extra)
 
     f32, f64 = forms["fp32"], forms.get("fp64")
     n_cl = sum(i.p for i in insts)
@@ -495,6 +531,8 @@ def main():
                                  "hsde": "Algorithm 3 (ADMM on the homogeneous self-dual "
                                          "embedding)"}[args.algorithm],
                    "tol": 1e-4, "rho": 1.0, "adaptive_rho": False, "instances": len(insts),
+                   "affine_step": (f"PCG, {extra['cg_max_iter']} steps per iteration"
+                                   if extra.get("cg_max_iter") else "cached Cholesky factor"),
                    "n": [i.n for i in insts[:4]], "m": [i.m for i in insts[:4]],
                    "cliques": n_cl, "pattern_nnz": sum(i.nnz for i in insts)},
         "projections_per_s": head["projections_per_s"],

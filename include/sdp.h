@@ -115,6 +115,16 @@ typedef struct {
                                    max(eps_p, eps_d, eps_g, eps_c) <= tol or on an
                                    infeasibility certificate; no penalty, so adaptive_rho
                                    must be 0) */
+  int32_t cg_max_iter;          /* 0: the affine step solves with the cached Cholesky factor
+                                   of A D^-1 A^T.  > 0 (Algorithm 1 only): no factor is
+                                   formed; each iteration solves (A W D^-1 A^T) y = rhs by
+                                   conjugate gradients with the Jacobi preconditioner
+                                   diag(A W D^-1 A^T), started from the previous iteration's
+                                   y, at most cg_max_iter steps (the iterative alternative of
+                                   Section 4.1.1, for m where the m x m factor is too large;
+                                   also lifts the m <= 20480 limit of sparse A) */
+  double cg_tol;                /* the solve also stops once ||r||_2 <= cg_tol (1 + ||b||_2);
+                                   0: always cg_max_iter steps */
 } sdp_options;
 
 /* Per-instance result. */
@@ -276,6 +286,10 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
  * sdp_reset before solving again).  Synchronises. */
 int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar,
             int32_t euclidean);
+
+/* Conjugate-gradient steps taken over all instances since the last reset
+ * (0 when the handle uses the factor).  Synchronises. */
+int sdp_cg_steps(sdp_handle *h, int64_t *steps);
 
 /* Releases every device buffer of the handle. */
 void sdp_destroy(sdp_handle *h);

@@ -48,6 +48,8 @@ def _load():
     lib.orc_create.argtypes = [C.c_int, C.c_int, C.c_int64, _ip, _ip, C.c_int, _ip, _ip,
                                C.c_int, _lp, _ip, _dp, _dp, _dp, C.POINTER(C.c_void_p)]
     lib.orc_create.restype = C.c_int
+    lib.orc_create_ex.argtypes = lib.orc_create.argtypes[:-1] + [C.c_int, C.POINTER(C.c_void_p)]
+    lib.orc_create_ex.restype = C.c_int
     lib.orc_free.argtypes = [C.c_void_p]
     lib.orc_reset.argtypes = [C.c_void_p, C.c_double]
     lib.orc_set_jacobi.argtypes = [C.c_void_p, C.c_int, C.c_double]
@@ -210,7 +212,9 @@ class OracleError(RuntimeError):
 class Problem:
     """Algorithm 1 on one SDP instance (an ``sdpgen.Instance``)."""
 
-    def __init__(self, inst, rho0: float = 1.0):
+    def __init__(self, inst, rho0: float = 1.0, factor: bool = True):
+        """factor=False skips the Cholesky factor of A W D^-1 A^T (for large m):
+        the problem then runs Algorithm 1 only after set_affine_cg."""
         lib = _load()
         self.inst = inst
         self._keep = []
@@ -228,9 +232,9 @@ class Problem:
         else:
             arp, acp = None, None
         h = C.c_void_p()
-        rc = lib.orc_create(int(inst.n), int(inst.m), int(pr.shape[0]), _i(pr), _i(pc),
-                            int(cp.shape[0] - 1), _i(cp), _i(cv), int(inst.a_format),
-                            arp, acp, _d(av), _d(b), _d(c), C.byref(h))
+        rc = lib.orc_create_ex(int(inst.n), int(inst.m), int(pr.shape[0]), _i(pr), _i(pc),
+                               int(cp.shape[0] - 1), _i(cp), _i(cv), int(inst.a_format),
+                               arp, acp, _d(av), _d(b), _d(c), int(bool(factor)), C.byref(h))
         if rc != OK:
             raise OracleError(rc)
         self._h = h

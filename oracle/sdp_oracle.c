@@ -398,11 +398,13 @@ static int finite_all(const double *v, int64_t n) {
 
 /* Validate the data, build the clique index maps, D, w, and factor
  * M = A W D^-1 A^T.  All input arrays are copied. */
-int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col,
-               int p, const int *clique_ptr, const int *clique_vert,
-               int a_format, const int64_t *a_rowptr, const int *a_col,
-               const double *a_val, const double *b, const double *c,
-               orc_problem **out) {
+/* factor = 0 skips the Cholesky factor: such a problem runs Algorithm 1 only
+ * with the conjugate-gradient affine step (orc_set_affine_cg first). */
+int orc_create_ex(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col,
+                  int p, const int *clique_ptr, const int *clique_vert,
+                  int a_format, const int64_t *a_rowptr, const int *a_col,
+                  const double *a_val, const double *b, const double *c, int factor,
+                  orc_problem **out) {
   *out = NULL;
   if (n <= 0 || m < 1 || nnz <= 0 || p <= 0 || !pat_row || !pat_col ||
       !clique_ptr || !clique_vert || !a_val || !b || !c ||
@@ -520,17 +522,19 @@ int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col
 
   /* M = A W D^-1 A^T (the matrix A D^-1 A^T of ADMMprimalFatorization on the
    * compact coordinates), then M = L L^T. */
-  double *M = (double *)calloc((size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1), sizeof(double));
-  {
-    double *wd = (double *)malloc(sizeof(double) * nnz);
-    for (int64_t j = 0; j < nnz; ++j) wd[j] = P->w[j] / P->D[j];
-    assemble_gram(P, wd, M);
-    free(wd);
+  if (factor) {
+    double *M = (double *)calloc((size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1), sizeof(double));
+    {
+      double *wd = (double *)malloc(sizeof(double) * nnz);
+      for (int64_t j = 0; j < nnz; ++j) wd[j] = P->w[j] / P->D[j];
+      assemble_gram(P, wd, M);
+      free(wd);
+    }
+    P->L = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
+    rc = orc_cholesky(m, M, P->L);
+    free(M);
+    if (rc != ORC_OK) { orc_free(P); return rc; }
   }
-  P->L = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
-  rc = orc_cholesky(m, M, P->L);
-  free(M);
-  if (rc != ORC_OK) { orc_free(P); return rc; }
 
   P->X = (double *)calloc(P->nblk, sizeof(double));
   P->Lam = (double *)calloc(P->nblk, sizeof(double));
@@ -546,6 +550,15 @@ int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col
   P->jac_tol = 1e-14;
   *out = P;
   return ORC_OK;
+}
+
+int orc_create(int n, int m, int64_t nnz, const int *pat_row, const int *pat_col,
+               int p, const int *clique_ptr, const int *clique_vert,
+               int a_format, const int64_t *a_rowptr, const int *a_col,
+               const double *a_val, const double *b, const double *c,
+               orc_problem **out) {
+  return orc_create_ex(n, m, nnz, pat_row, pat_col, p, clique_ptr, clique_vert, a_format,
+                       a_rowptr, a_col, a_val, b, c, 1, out);
 }
 
 /* Initial guesses X_k = Lambda_k = 0 and penalty rho0. */
@@ -714,6 +727,7 @@ static double ratio(double num, double den) {
 int orc_run(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
             double nu, int rho_period, int *iters_done, double *hist_eps_c,
             double *hist_eps_l, double *hist_rho) {
+  if (!P->L && P->cg_max_iter <= 0) return ORC_ERR_ARG;   /* no factor: CG mode only */
   int p = P->p;
   double *part = (double *)calloc((size_t)p * 5, sizeof(double));
   int *sweeps = (int *)calloc(p, sizeof(int));
@@ -794,6 +808,7 @@ int orc_run(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
 int orc_run_dual(orc_problem *P, int max_iter, double tol, int adaptive, double mu,
                  double nu, int rho_period, int *iters_done, double *hist_eps_c,
                  double *hist_eps_l, double *hist_rho) {
+  if (!P->L) return ORC_ERR_ARG;
   int p = P->p;
   double *part = (double *)calloc((size_t)p * 5, sizeof(double));
   int *sweeps = (int *)calloc(p, sizeof(int));

@@ -56,7 +56,8 @@ class sdp_options(C.Structure):
                 ("precision", C.c_int32), ("adaptive_rho", C.c_int32), ("mu", C.c_double),
                 ("nu", C.c_double), ("rho_period", C.c_int32), ("graph_chunk", C.c_int32),
                 ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
-                ("autotune", C.c_int32), ("warm_start", C.c_int32), ("algorithm", C.c_int32)]
+                ("autotune", C.c_int32), ("warm_start", C.c_int32), ("algorithm", C.c_int32),
+                ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double)]
 
 
 class sdp_result(C.Structure):
@@ -73,7 +74,8 @@ EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sd
            "sdp_psd_project_batched", "sdp_projection_variants", "sdp_psd_project_variant",
            "sdp_get_solution", "sdp_set_state", "sdp_get_history",
            "sdp_diagnostics", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
-           "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_destroy", "sdp_last_error",
+           "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_cg_steps", "sdp_destroy",
+           "sdp_last_error",
            "sdp_pattern_create", "sdp_pattern_sizes", "sdp_pattern_get", "sdp_pattern_destroy",
            "sdp_scale_compute", "sdp_scale_apply", "sdp_scale_recover"]
 
@@ -109,6 +111,7 @@ def _load():
     lib.sdp_update_data.argtypes = [_p, _p, _p]
     lib.sdp_unrolled_forward.argtypes = [_p, C.c_int32, C.c_int32, _p]
     lib.sdp_vjp.argtypes = [_p, _p, _p, _p, C.c_int32]
+    lib.sdp_cg_steps.argtypes = [_p, C.POINTER(C.c_int64)]
     lib.sdp_destroy.argtypes = [_p]
     lib.sdp_destroy.restype = None
     lib.sdp_last_error.argtypes = []
@@ -316,6 +319,12 @@ class Solver:
         sw, pr = C.c_int64(0), C.c_int64(0)
         _check(lib.sdp_get_stats(self._h, C.byref(sw), C.byref(pr)))
         return dict(jacobi_sweeps=sw.value, projections=pr.value)
+
+    def cg_steps(self) -> int:
+        """Conjugate-gradient steps over all instances since the last reset."""
+        n = C.c_int64(0)
+        _check(lib.sdp_cg_steps(self._h, C.byref(n)))
+        return n.value
 
     def projection_plan(self):
         """[(N, threads, cliques)] of the projection launch lists."""

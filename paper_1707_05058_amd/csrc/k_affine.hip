@@ -77,7 +77,9 @@ __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
     // c - sum_k (z_k + lambda_k/rho)
     const double bh = a.dual ? a.c[j] - (sx + sl / rho) : sx + (sl - a.c[j]) / rho;
     a.bhat[j] = bh;
-    a.v[j] = a.w[j] * bh / a.D[j];
+    // with conjugate gradients: W D^-1 (bhat - A^T y_prev), so that the row
+    // products give the solve's initial residual r0 = rhs - M y_prev
+    a.v[j] = a.w[j] * (a.cg_g ? bh - a.cg_g[j] : bh) / a.D[j];
   }
 }
 
@@ -91,6 +93,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
   const int inst = a.row_tiles[2 * blockIdx.x];
   const int row0 = a.row_tiles[2 * blockIdx.x + 1];
   if (!a.ignore_done && a.state[inst].done) return;
+  if (a.cg_loop && a.cg[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int nrow = min(R, d.m - row0);
   const double *mat = (a.Bm ? a.Bm : a.A) + d.a_off + (int64_t)row0 * d.ld;
@@ -125,7 +128,8 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
     const int64_t g = d.row_off + row0 + r;
     // Algorithm 2 solves with -b / rho in place of b
     const double bs = a.dual ? -1.0 / a.state[inst].rho : 1.0;
-    if (a.Bm) a.y1[g] = s - bs * a.bp[g];
+    if (a.no_b) a.r[g] = s;
+    else if (a.Bm) a.y1[g] = s - bs * a.bp[g];
     else a.r[g] = s - bs * a.b[g];
   }
 }
@@ -133,7 +137,9 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
 // ---------------------------------------------------------------------------
 // Column-oriented (transposed) products over dense A.
 //   RAW = 0:  u[j] = (bhat[j] - sum_i A[i][j] y[i]) / D[j]
+//             (with conjugate gradients also cg_g[j] = sum_i A[i][j] y[i])
 //   RAW = 1:  u[j] = sum_i A[i][j] y[i]            (diagnostics: A^T y)
+//   RAW = 2:  u[j] = w[j] sum_i A[i][j] y[i] / D[j] (inside the CG solve)
 // One tile = 128 columns of one instance; lane l owns columns 2l, 2l+1 and
 // the 4 waves split the rows, so each wave reads contiguous 1 KiB segments.
 // ---------------------------------------------------------------------------
@@ -142,6 +148,7 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
   const int inst = a.col_tiles[2 * blockIdx.x];
   const int col0 = a.col_tiles[2 * blockIdx.x + 1];
   if (!a.ignore_done && a.state[inst].done) return;
+  if (a.cg_loop && a.cg[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = col0 + 2 * l;
@@ -168,12 +175,19 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
       sy += red[k][l].y;
     }
     const int64_t g = d.coord_off + col;
-    if (RAW) {
+    if (RAW == 1) {
       a.u[g] = sx;
       a.u[g + 1] = sy;
+    } else if (RAW == 2) {
+      a.u[g] = a.w[g] * sx / a.D[g];
+      a.u[g + 1] = a.w[g + 1] * sy / a.D[g + 1];
     } else {
       a.u[g] = (a.bhat[g] - sx) / a.D[g];
       a.u[g + 1] = (a.bhat[g + 1] - sy) / a.D[g + 1];
+      if (a.cg_g) {
+        a.cg_g[g] = sx;
+        a.cg_g[g + 1] = sy;
+      }
     }
   }
 }
@@ -219,6 +233,7 @@ __global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
   if (wid >= a.n_csr_rows) return;
   const int inst = a.csr_rows[2 * wid], row = a.csr_rows[2 * wid + 1];
   if (!a.ignore_done && a.state[inst].done) return;
+  if (a.cg_loop && a.cg[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int l = threadIdx.x & 63;
   const int64_t t0 = a.a_rowptr[d.a_off + row], t1 = a.a_rowptr[d.a_off + row + 1];
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
   for (int64_t t = t0 + l; t < t1; t += 64) acc += a.a_val[t] * v[a.a_col[t]];
   acc = wave_sum(acc);
   const double bs = a.dual ? -1.0 / a.state[inst].rho : 1.0;
-  if (l == 0) a.r[d.row_off + row] = acc - bs * a.b[d.row_off + row];
+  if (l == 0) a.r[d.row_off + row] = a.no_b ? acc : acc - bs * a.b[d.row_off + row];
 }
 
 // Transposed products with sparse A: CSC_G consecutive lanes share a column
@@ -240,6 +255,7 @@ template <int RAW>
 __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
   const int inst = a.csc_cols[2 * blockIdx.x], col0 = a.csc_cols[2 * blockIdx.x + 1];
   if (!a.ignore_done && a.state[inst].done) return;
+  if (a.cg_loop && a.cg[inst].done) return;
   const InstDesc d = a.inst[inst];
   const int col = col0 + (int)threadIdx.x / CSC_G, q = threadIdx.x % CSC_G;
   if (col >= d.ld) return;                 // whole lane groups leave together
@@ -250,7 +266,16 @@ __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
   for (int64_t t = a.a_colptr[g] + q; t < t1; t += CSC_G) acc += a.a_cval[t] * y[a.a_row[t]];
 #pragma unroll
   for (int o = 1; o < CSC_G; o <<= 1) acc += __shfl_xor(acc, o, 64);
-  if (q == 0) a.u[g] = RAW ? acc : (a.bhat[g] - acc) / a.D[g];
+  if (q == 0) {
+    if (RAW == 1) {
+      a.u[g] = acc;
+    } else if (RAW == 2) {
+      a.u[g] = a.w[g] * acc / a.D[g];
+    } else {
+      a.u[g] = (a.bhat[g] - acc) / a.D[g];
+      if (a.cg_g) a.cg_g[g] = acc;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -418,6 +443,146 @@ __global__ __launch_bounds__(256) void k_scaled_copy(const double *src, double *
   if (i < n) dst[i] = -state[inst].rho * src[i];
 }
 
+// ---------------------------------------------------------------------------
+// Affine step by preconditioned conjugate gradients (the iterative
+// alternative to the factor, Section 4.1.1): M y = rhs with M = A W D^-1 A^T,
+// Jacobi preconditioner diag(M), started from the previous iteration's y.
+// The row products r0 = A W D^-1 (bhat - A^T y_prev) - b and M p =
+// A (W D^-1 A^T p) reuse the row/column kernels above; the per-instance
+// scalars (alpha, beta, the stopping test) live in one workgroup per
+// instance; y, r, z and p are updated tile by tile over the instance's rows.
+// ---------------------------------------------------------------------------
+// Row vectors are split into tiles of CG_ROWS rows of one instance; the
+// scalars of a step come from per-tile partial sums, which every consumer
+// adds in tile order (fixed order: reproducible results).
+constexpr int CG_NT = 256;
+constexpr int CG_ROWS = 1024;
+
+__device__ inline double cg_block_sum(double x, double *red) {
+  x = wave_sum(x);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = x;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < CG_NT / 64; ++i) s += red[i];
+  return s;
+}
+
+// sum of one partial over the tiles of an instance, in tile order
+__device__ inline double cg_tiles_sum(const double *part, int t0, int t1) {
+  double s = 0.0;
+  for (int t = t0; t < t1; ++t) s += part[t];
+  return s;
+}
+
+// MODE 0 (start): z = r / diag, p = z; partials r^T z, ||r||^2.
+// MODE 1: partial p^T M p.
+// MODE 2: alpha = r^T z / p^T M p; y += alpha p, r -= alpha M p, z = r / diag;
+//         partials r^T z, ||r||^2.
+// MODE 3: beta = r'^T z' / r^T z; p = z + beta p.
+template <int MODE>
+__global__ __launch_bounds__(CG_NT) void k_cg_rows(AffineArgs a) {
+  const int inst = a.cg_tiles[2 * blockIdx.x], row0 = a.cg_tiles[2 * blockIdx.x + 1];
+  if (!a.ignore_done && a.state[inst].done) return;
+  const CgState c = a.cg[inst];
+  if (MODE != 0 && c.done) return;
+  const InstDesc d = a.inst[inst];
+  const int row1 = min(d.m, row0 + CG_ROWS);
+  const int t0 = a.cg_tile_first[inst], t1 = a.cg_tile_first[inst + 1];
+  __shared__ double red[CG_NT / 64];
+  double s0 = 0.0, s1 = 0.0;
+  if (MODE == 0) {
+    for (int i = row0 + threadIdx.x; i < row1; i += CG_NT) {
+      const int64_t g = d.row_off + i;
+      const double r = a.r[g], z = r / a.cg_diag[g];
+      a.cg_z[g] = z;
+      a.cg_p[g] = z;
+      s0 += r * z;
+      s1 += r * r;
+    }
+  } else if (MODE == 1) {
+    for (int i = row0 + threadIdx.x; i < row1; i += CG_NT) {
+      const int64_t g = d.row_off + i;
+      s0 += a.cg_p[g] * a.cg_Mp[g];
+    }
+  } else if (MODE == 2) {
+    const double alpha = c.rz / cg_tiles_sum(a.cg_part, t0, t1);
+    for (int i = row0 + threadIdx.x; i < row1; i += CG_NT) {
+      const int64_t g = d.row_off + i;
+      a.y[g] += alpha * a.cg_p[g];
+      const double r = a.r[g] - alpha * a.cg_Mp[g];
+      const double z = r / a.cg_diag[g];
+      a.r[g] = r;
+      a.cg_z[g] = z;
+      s0 += r * z;
+      s1 += r * r;
+    }
+  } else {
+    const double beta = cg_tiles_sum(a.cg_part + a.cg_ntiles, t0, t1) / c.rz;
+    for (int i = row0 + threadIdx.x; i < row1; i += CG_NT) {
+      const int64_t g = d.row_off + i;
+      a.cg_p[g] = a.cg_z[g] + beta * a.cg_p[g];
+    }
+  }
+  if (MODE == 3) return;
+  s0 = cg_block_sum(s0, red);
+  if (MODE != 1) s1 = cg_block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    // MODE 1 writes slot 0 (p^T M p); MODES 0, 2 write slots 1, 2 (r^T z, ||r||^2)
+    if (MODE == 1) {
+      a.cg_part[blockIdx.x] = s0;
+    } else {
+      a.cg_part[a.cg_ntiles + blockIdx.x] = s0;
+      a.cg_part[2 * a.cg_ntiles + blockIdx.x] = s1;
+    }
+  }
+}
+
+// Per instance, after MODE 0 (start = 1) or MODE 3 (start = 0): r^T z and
+// ||r||^2 from the partials, step count and the stopping test.
+__global__ __launch_bounds__(256) void k_cg_scalars(AffineArgs a, int start) {
+  const int inst = blockIdx.x * 256 + threadIdx.x;
+  if (inst >= a.batch) return;
+  if (!a.ignore_done && a.state[inst].done) return;
+  CgState c = a.cg[inst];
+  if (!start && c.done) return;
+  const int t0 = a.cg_tile_first[inst], t1 = a.cg_tile_first[inst + 1];
+  c.rz = cg_tiles_sum(a.cg_part + a.cg_ntiles, t0, t1);
+  c.rn2 = cg_tiles_sum(a.cg_part + 2 * a.cg_ntiles, t0, t1);
+  if (start) {
+    c.steps = 0;
+    c.done = (a.cg_max_iter <= 0 || c.rn2 <= a.cg_tol2[inst]) ? 1 : 0;
+  } else {
+    c.steps += 1;
+    c.total += 1;
+    c.done = (c.steps >= a.cg_max_iter || c.rn2 <= a.cg_tol2[inst]) ? 1 : 0;
+  }
+  a.cg[inst] = c;
+}
+
+// diag(A W D^-1 A^T)_i = sum_j A_ij^2 w_j / D_j, one wave per row.
+__global__ __launch_bounds__(256) void k_cg_diag(AffineArgs a, const double *wd,
+                                                 const int32_t *rows, int nrows, double *out) {
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= nrows) return;
+  const int inst = rows[2 * wid], row = rows[2 * wid + 1];
+  const InstDesc d = a.inst[inst];
+  const int l = threadIdx.x & 63;
+  double acc = 0.0;
+  if (d.a_format == 0) {                 // dense rows (SDP_A_DENSE)
+    const double *arow = a.A + d.a_off + (int64_t)row * d.ld;
+    for (int j = l; j < d.nnz; j += 64) acc += arow[j] * arow[j] * wd[d.coord_off + j];
+  } else {
+    const int64_t t0 = a.a_rowptr[d.a_off + row], t1 = a.a_rowptr[d.a_off + row + 1];
+    for (int64_t t = t0 + l; t < t1; t += 64)
+      acc += a.a_val[t] * a.a_val[t] * wd[d.coord_off + a.a_col[t]];
+  }
+  acc = wave_sum(acc);
+  if (l == 0) out[d.row_off + row] = acc;
+}
+
 }  // namespace
 
 // Stages of the X-step, launched in this order every iteration:
@@ -482,6 +647,7 @@ hipError_t launch_objective(const AffineArgs &a, double *obj, hipStream_t st) {
 }
 
 int affine_col_tile_width() { return COL_W; }
+int affine_cg_tile_rows() { return CG_ROWS; }
 int affine_csc_tile_width() { return CSC_COLS; }
 int affine_max_rows_per_tile() { return MAX_R; }
 
@@ -524,5 +690,69 @@ hipError_t launch_scaled_copy(const double *src, double *dst, int64_t n, const I
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scaled_copy, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, state,
                      inst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The affine step with conjugate gradients.  Every launch is issued for every
+// step up to cg_max_iter, so the sequence can be captured in a graph; the
+// kernels of an instance whose solve has stopped return at once.
+// ---------------------------------------------------------------------------
+namespace {
+
+void launch_rowdots(const AffineArgs &a, hipStream_t st) {
+  if (a.n_row_tiles > 0) {
+    switch (a.rows_per_tile) {
+      case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((k_rowdot<2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+      case 4: hipLaunchKernelGGL((k_rowdot<4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_rowdot<MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
+    }
+  }
+  if (a.n_csr_rows > 0)
+    hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
+}
+
+}  // namespace
+
+hipError_t launch_cg_stage(const AffineArgs &a, int stage, hipStream_t st) {
+  if (stage != 2) return launch_affine_stage(a, stage, st);
+  const dim3 tg(a.cg_ntiles), sg((a.batch + 255) / 256);
+  hipLaunchKernelGGL(k_cg_rows<0>, tg, dim3(CG_NT), 0, st, a);
+  hipLaunchKernelGGL(k_cg_scalars, sg, dim3(256), 0, st, a, 1);
+  AffineArgs at = a;        // v = W D^-1 A^T p
+  at.y = a.cg_p;
+  at.u = a.v;
+  at.cg_loop = 1;
+  AffineArgs ar = a;        // M p = A v
+  ar.r = a.cg_Mp;
+  ar.no_b = 1;
+  ar.cg_loop = 1;
+  for (int k = 0; k < a.cg_max_iter; ++k) {
+    if (at.n_col_tiles > 0)
+      hipLaunchKernelGGL(k_coldot<2>, dim3(at.n_col_tiles), dim3(COL_NT), 0, st, at);
+    if (at.n_csc_cols > 0)
+      hipLaunchKernelGGL(k_csc_coldot<2>, dim3(at.n_csc_cols), dim3(256), 0, st, at);
+    launch_rowdots(ar, st);
+    hipLaunchKernelGGL(k_cg_rows<1>, tg, dim3(CG_NT), 0, st, a);
+    hipLaunchKernelGGL(k_cg_rows<2>, tg, dim3(CG_NT), 0, st, a);
+    hipLaunchKernelGGL(k_cg_rows<3>, tg, dim3(CG_NT), 0, st, a);
+    hipLaunchKernelGGL(k_cg_scalars, sg, dim3(256), 0, st, a, 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_affine(const AffineArgs &a, hipStream_t st) {
+  for (int stage : {0, 1, 2, 4}) {
+    const hipError_t e = launch_cg_stage(a, stage, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cg_diag(const AffineArgs &a, const double *wd, const int32_t *rows, int nrows,
+                          double *out, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_diag, dim3((nrows + 3) / 4), dim3(256), 0, st, a, wd, rows, nrows, out);
   return hipGetLastError();
 }

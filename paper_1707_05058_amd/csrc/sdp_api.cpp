@@ -304,6 +304,9 @@ struct sdp_handle {
   int n_t_rows_all = 0;
   double *d_ytmp = nullptr;              // row-space scratch for the scaled multiplier
   double *d_utmp = nullptr;              // coordinate scratch (Algorithm 2: -rho x)
+  // affine step by conjugate gradients (no factor)
+  bool cg = false;
+  std::vector<double> cg_tol2;           // per instance (cg_tol (1 + ||b||))^2
   // Algorithm 3
   bool hsde = false;
   HsdeArgs hsa{};
@@ -386,7 +389,8 @@ void enqueue_iteration(sdp_handle *h, hipStream_t st) {
     HIPCHK(launch_iteration_affine(h->aff, st));
     HIPCHK(launch_dual_update(h->proj, h->ncl, st));
   } else {
-    HIPCHK(launch_iteration_affine(h->aff, st));
+    if (h->cg) HIPCHK(launch_cg_affine(h->aff, st));
+    else HIPCHK(launch_iteration_affine(h->aff, st));
     enqueue_projections(h, h->proj, st);
   }
   HIPCHK(launch_residual_reduce(h->aff, st));
@@ -410,6 +414,7 @@ void enqueue_unrolled_iteration(sdp_handle *h, hipStream_t st, void *eig) {
 
 // y = L^-T y1 for every row (with B = L^-1 A formed, the iteration keeps only y1).
 void ensure_y(sdp_handle *h) {
+  if (h->cg) return;          // the solve keeps y itself
   AffineArgs a = h->aff;
   a.t3_rows = h->d_t_rows_all;
   a.n_t3_rows = h->n_t_rows_all;
@@ -621,6 +626,10 @@ void reset_state(sdp_handle *h) {
   HIPCHK(hipMemsetAsync(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
   HIPCHK(hipMemsetAsync(h->aff.u, 0, sizeof(double) * h->ncoord, h->stream));
   HIPCHK(hipMemsetAsync(h->aff.y, 0, sizeof(double) * h->nrow, h->stream));
+  if (h->cg) {
+    HIPCHK(hipMemsetAsync(h->aff.cg_g, 0, sizeof(double) * h->ncoord, h->stream));
+    HIPCHK(hipMemsetAsync(h->aff.cg, 0, sizeof(CgState) * h->B, h->stream));
+  }
   if (h->proj.Vd)
     HIPCHK(hipMemsetAsync(h->proj.Vd, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
   if (h->hsde) {
@@ -671,8 +680,10 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
        opt.algorithm != SDP_ALG_HSDE) ||
       (opt.algorithm == SDP_ALG_HSDE && opt.adaptive_rho) ||
       (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
-      opt.graph_chunk < 0)
+      opt.graph_chunk < 0 || opt.cg_max_iter < 0 || !(opt.cg_tol >= 0))
     fail(SDP_ERR_ARG, "invalid options");
+  if (opt.cg_max_iter > 0 && opt.algorithm != SDP_ALG_PRIMAL)
+    fail(SDP_ERR_UNSUPPORTED, "the conjugate-gradient affine step is built for Algorithm 1 only");
 
   // ---- validation and host indices (nothing touches the GPU before this) ----
   std::vector<HostInst> H(batch);
@@ -854,8 +865,9 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
         }
       }
     }
-    if (max_ldm * sizeof(double) > 160 * 1024 && !syrk_rows.empty())
-      fail(SDP_ERR_UNSUPPORTED, "sparse A with m > 20480 is not supported");
+    const bool cg = opt.cg_max_iter > 0;
+    if (!cg && max_ldm * sizeof(double) > 160 * 1024 && !syrk_rows.empty())
+      fail(SDP_ERR_UNSUPPORTED, "sparse A with m > 20480 needs the conjugate-gradient affine step");
 
     // ---- CSR and CSC of sparse A ----
     std::vector<int64_t> a_rowptr, a_colptr;
@@ -908,8 +920,9 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
                            hipMemcpyHostToDevice));
       }
     }
-    double *d_T = dev_zeros<double>(toff, own);
-    double *d_U = dev_zeros<double>(toff, own);
+    // the factor's inverse triangles (none with conjugate gradients)
+    double *d_T = cg ? nullptr : dev_zeros<double>(toff, own);
+    double *d_U = cg ? nullptr : dev_zeros<double>(toff, own);
     double *d_wd = dev_upload(wd, own);
 
     AffineArgs &a = h->aff;
@@ -965,7 +978,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       // iteration on both sides of the factor: keep A and both triangular passes
       a.t_rows = a.t3_rows = h->d_t_rows_all;
       a.n_t_rows = a.n_t3_rows = h->n_t_rows_all;
-    } else if (d_A) {
+    } else if (d_A && !cg) {
       a.Bm = dev_zeros<double>(aoff, own);
       a.bp = dev_zeros<double>(row, own);
     }
@@ -1067,7 +1080,49 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     h->diag.assign(4 * batch, NAN);
 
     // ---- one-time factorisation: M = A W D^-1 A^T = L L^T, T = L^-1 ----
-    {
+    // (with conjugate gradients: only diag(M) for the preconditioner)
+    if (cg) {
+      h->cg = true;
+      a.cg_max_iter = opt.cg_max_iter;
+      a.cg = dev_zeros<CgState>(batch, own);
+      a.cg_g = dev_zeros<double>(coord, own);
+      a.cg_z = dev_zeros<double>(row, own);
+      a.cg_p = dev_zeros<double>(row, own);
+      a.cg_Mp = dev_zeros<double>(row, own);
+      std::vector<int32_t> tiles, tile_first(batch + 1, 0);
+      for (int i = 0; i < batch; ++i) {
+        tile_first[i] = (int32_t)(tiles.size() / 2);
+        for (int r = 0; r < H[i].m; r += affine_cg_tile_rows()) {
+          tiles.push_back(i);
+          tiles.push_back(r);
+        }
+      }
+      tile_first[batch] = (int32_t)(tiles.size() / 2);
+      a.cg_tiles = dev_upload(tiles, own);
+      a.cg_ntiles = tile_first[batch];
+      a.cg_tile_first = dev_upload(tile_first, own);
+      a.cg_part = dev_zeros<double>((size_t)3 * a.cg_ntiles, own);
+      double *d_diagm = dev_zeros<double>(row, own);
+      a.cg_diag = d_diagm;
+      h->cg_tol2.resize(batch);
+      for (int i = 0; i < batch; ++i) {
+        double nb2 = 0.0;
+        for (int r = 0; r < H[i].m; ++r) nb2 += inst[i].b[r] * inst[i].b[r];
+        const double t = opt.cg_tol * (1.0 + std::sqrt(nb2));
+        h->cg_tol2[i] = t * t;
+      }
+      a.cg_tol2 = dev_upload(h->cg_tol2, own);
+      HIPCHK(launch_cg_diag(a, d_wd, h->d_t_rows_all, h->n_t_rows_all, d_diagm, h->stream));
+      std::vector<double> dm(row);
+      HIPCHK(hipMemcpyAsync(dm.data(), d_diagm, sizeof(double) * row, hipMemcpyDeviceToHost,
+                            h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      for (int i = 0; i < batch; ++i)
+        for (int r = 0; r < H[i].m; ++r)
+          if (!(dm[h->desc[i].row_off + r] > 0))
+            fail(SDP_ERR_RANK_DEFICIENT, "instance " + std::to_string(i) + ": row " +
+                                             std::to_string(r) + " of A is zero");
+    } else {
       double *d_M = nullptr;
       HIPCHK(hipMalloc((void **)&d_M, sizeof(double) * std::max<int64_t>(toff, 1)));
       HIPCHK(hipMemsetAsync(d_M, 0, sizeof(double) * std::max<int64_t>(toff, 1), h->stream));
@@ -1424,6 +1479,20 @@ int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections) {
   });
 }
 
+int sdp_cg_steps(sdp_handle *h, int64_t *steps) {
+  return guarded([&] {
+    if (!h || !steps) fail(SDP_ERR_ARG, "invalid arguments");
+    *steps = 0;
+    if (!h->cg) return SDP_OK;
+    std::vector<CgState> cs(h->B);
+    HIPCHK(hipMemcpyAsync(cs.data(), h->aff.cg, sizeof(CgState) * h->B, hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (const CgState &c : cs) *steps += c.total;
+    return SDP_OK;
+  });
+}
+
 int sdp_projection_plan(sdp_handle *h, int32_t cap, int32_t *block_n, int32_t *threads,
                         int32_t *cliques, int32_t *count) {
   return guarded([&] {
@@ -1467,7 +1536,8 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
             continue;
           }
           if (s < 5) {
-            HIPCHK(launch_affine_stage(h->aff, s, h->stream));
+            if (!h->cg) HIPCHK(launch_affine_stage(h->aff, s, h->stream));
+            else if (s != 3) HIPCHK(launch_cg_stage(h->aff, s, h->stream));
           } else if (s == 5) {
             enqueue_projections(h, h->proj, h->stream);
             if (h->proj.dual) HIPCHK(launch_dual_update(h->proj, h->ncl, h->stream));
@@ -1504,6 +1574,18 @@ int sdp_update_data(sdp_handle *h, const double *c, const double *b) {
       HIPCHK(launch_copy_user_rows(b, const_cast<double *>(h->aff.b), h->d_desc, h->d_row_inst,
                                    h->d_user_row_off, h->nrow, h->stream));
     if (b) compute_bp(h);
+    if (b && h->cg) {
+      int64_t o = 0;
+      for (int i = 0; i < h->B; ++i) {
+        double nb2 = 0.0;
+        for (int r = 0; r < h->desc[i].m; ++r) nb2 += b[o + r] * b[o + r];
+        o += h->desc[i].m;
+        const double t = h->opt.cg_tol * (1.0 + std::sqrt(nb2));
+        h->cg_tol2[i] = t * t;
+      }
+      HIPCHK(hipMemcpyAsync(const_cast<double *>(h->aff.cg_tol2), h->cg_tol2.data(),
+                            sizeof(double) * h->B, hipMemcpyHostToDevice, h->stream));
+    }
     HIPCHK(hipStreamSynchronize(h->stream));
     h->have_diag = false;
     return SDP_OK;
@@ -1516,6 +1598,7 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
     if (h->opt.adaptive_rho) fail(SDP_ERR_ARG, "unrolled differentiation needs a fixed rho");
     if (h->proj.dual || h->hsde)
       fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
+    if (h->cg) fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation needs the factored affine step");
     const int nseg = (T + ckpt_every - 1) / ckpt_every;
     const int64_t need = (int64_t)nseg * 2 * std::max<int64_t>(h->npk, 1);
     if (need > h->ckpt_cap) {
@@ -1554,6 +1637,7 @@ int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, in
     if (!h || !u_bar || !c_bar || !b_bar) fail(SDP_ERR_ARG, "invalid arguments");
     if (h->proj.dual || h->hsde)
       fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
+    if (h->cg) fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation needs the factored affine step");
     if (h->adj_T <= 0) fail(SDP_ERR_ARG, "run sdp_unrolled_forward first");
     if (!h->adj_ready)
       fail(SDP_ERR_UNSUPPORTED, "the projection adjoint supports cliques up to 64 vertices");

@@ -47,6 +47,16 @@ struct InstState {
                        // 3: primal infeasible, 4: dual infeasible (Algorithm 3)
 };
 
+// Affine step by preconditioned conjugate gradients: per-instance scalars
+// of the current solve.
+struct CgState {
+  double rz;           // r^T z (z = r / diag(A W D^-1 A^T))
+  double rn2;          // ||r||^2
+  int32_t steps;       // steps taken in this iteration's solve
+  int32_t done;        // 1: this iteration's solve has stopped
+  int64_t total;       // steps since the last reset
+};
+
 // Algorithm 3 (homogeneous self-dual embedding): per-instance scalars.
 struct HsdeState {
   double tau, kappa;   // u_tau and v_kappa
@@ -176,6 +186,18 @@ struct AffineArgs {
   int batch;
   int ignore_done;                            // diagnostics: run on frozen instances too
   int dual;                                   // Algorithm 2: right-hand sides c - sum(z + lambda/rho), -b/rho
+  // affine step by preconditioned conjugate gradients (cg_max_iter > 0)
+  int cg_max_iter;
+  CgState *cg;                                // [batch]
+  const double *cg_tol2;                      // [batch] (cg_tol (1 + ||b||))^2
+  const double *cg_diag;                      // rows: diag(A W D^-1 A^T)
+  double *cg_g;                               // coordinates: A^T y of the last solve
+  double *cg_z, *cg_p, *cg_Mp;                // rows (the residual lives in r)
+  const int32_t *cg_tiles; int cg_ntiles;     // (inst, first row) per tile of rows
+  const int32_t *cg_tile_first;               // [batch + 1]: an instance's tiles
+  double *cg_part;                            // [3][cg_ntiles]: p^T M p, r^T z, ||r||^2
+  int cg_loop;                                // products inside the solve: skip stopped instances
+  int no_b;                                   // row products without the -b term
 };
 
 // Scratch of the diagnostics pass (allocated on first use).
@@ -195,6 +217,15 @@ hipError_t launch_scaled_copy(const double *src, double *dst, int64_t n, const I
                               int inst, hipStream_t st);
 
 hipError_t launch_iteration_affine(const AffineArgs &a, hipStream_t st);
+// The affine step with conjugate gradients: scatter, r0, the solve, u.
+hipError_t launch_cg_affine(const AffineArgs &a, hipStream_t st);
+// Stages of that step for timing: 0 scatter, 1 r0, 2 the solve, 4 u.
+hipError_t launch_cg_stage(const AffineArgs &a, int stage, hipStream_t st);
+// rows of one conjugate-gradient tile
+int affine_cg_tile_rows();
+// diag(A W D^-1 A^T) into out (wd = w / D; rows: (inst, row) pairs)
+hipError_t launch_cg_diag(const AffineArgs &a, const double *wd, const int32_t *rows, int nrows,
+                          double *out, hipStream_t st);
 hipError_t launch_residual_reduce(const AffineArgs &a, hipStream_t st);
 hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st);
 hipError_t launch_objective(const AffineArgs &a, double *obj, hipStream_t st);

@@ -305,6 +305,43 @@ def instance_on_pattern(n: int, pat_row, pat_col, m: int, seed: int, density=Non
                         rng, seed, density, name or f"pattern_n{n}_m{m}_s{seed}", {})
 
 
+def sparse_rows_instance(n: int, cliques: Sequence[np.ndarray], m: int, nnz_per_row: int,
+                         seed: int, name: str = "") -> Instance:
+    """Random primal SDP whose constraints each touch nnz_per_row pattern
+    coordinates (CSR A).  Draw order: for each row, 2 * nnz_per_row uniform
+    coordinate indices (distinct ones kept, first nnz_per_row in draw order,
+    then sorted), then nnz_per_row normals; finally y0 ~ N(0,1)^m."""
+    rng = np.random.default_rng(seed)
+    pat_row, pat_col = pattern_from_cliques(n, cliques)
+    nnz = pat_row.shape[0]
+    k = min(nnz_per_row, nnz)
+    rows_c, rows_v = [], []
+    for _ in range(m):
+        while True:
+            cand = rng.integers(0, nnz, size=2 * k)
+            _, first = np.unique(cand, return_index=True)
+            if first.shape[0] >= k:
+                break
+        cols = np.sort(cand[np.sort(first)[:k]]).astype(np.int32)
+        rows_c.append(cols)
+        rows_v.append(rng.standard_normal(k))
+    a_rowptr = np.arange(m + 1, dtype=np.int64) * k
+    a_col = np.concatenate(rows_c)
+    a_val = np.concatenate(rows_v)
+    y0 = rng.standard_normal(m)
+    return _finish(n, m, pat_row, pat_col, list(cliques), A_CSR, a_val, a_rowptr, a_col, y0,
+                   name or f"sparse_rows_n{n}_m{m}_k{k}_s{seed}", dict(seed=seed))
+
+
+def workload_large_m(seed: int = 0, n: int = 20000, w: int = 15, m: int = 40000,
+                     nnz_per_row: int = 64) -> Instance:
+    """Banded n = 20000, half-bandwidth 15 (19985 cliques of 16) with m = 40000
+    sparse constraints of 64 coordinates each: the m x m factor would take
+    12.8 GB per triangle, the case the conjugate-gradient affine step is for."""
+    return sparse_rows_instance(n, banded_cliques(n, w), m, nnz_per_row, seed,
+                                name=f"banded_n{n}_w{w}_m{m}_k{nnz_per_row}_s{seed}")
+
+
 def workload_nonchordal(seed: int = 0, rows: int = 45, cols: int = 45, m: int = 200,
                         density: float = 0.05) -> Instance:
     """Stand-in for the nonchordal experiments (cone sizes about 2000-7500,

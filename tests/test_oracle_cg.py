@@ -126,3 +126,18 @@ def test_invalid_cg_settings(oracle_mod):
         P.set_affine_cg(-1, 0.0)
     with pytest.raises(Exception):
         P.set_affine_cg(3, -1.0)
+
+
+def test_factorless_problem_runs_the_same_cg_iterates(oracle_mod):
+    """A problem created without the factor (the large-m case) runs Algorithm 1
+    in conjugate-gradient mode exactly as a factored one does, and refuses
+    the factor-based iteration."""
+    inst = sdpgen.block_arrow_instance(4, 5, 2, 12, seed=3, density=0.3)
+    Pa, Pb = oracle_mod.Problem(inst), oracle_mod.Problem(inst, factor=False)
+    Pa.set_affine_cg(3, 0.0)
+    Pb.set_affine_cg(3, 0.0)
+    Pa.run(20, tol=0.0)
+    Pb.run(20, tol=0.0)
+    assert np.array_equal(Pa.u(), Pb.u())
+    Pc = oracle_mod.Problem(inst, factor=False)
+    assert Pc.run(5, tol=0.0).status == oracle_mod.ERR_ARG
