@@ -91,6 +91,76 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
+// Dense N x N products on the matrix cores: C = sum_k a(i, k) b(k, j) by
+// 16 x 16 tiles, one wave per tile (tiles dealt round-robin to the waves),
+// 16x16x4 MFMA steps over k.  Operands come from LDS through the functors;
+// store(i, j, c) receives every result after a barrier, so a product may
+// overwrite its own inputs.  Lane layouts (verified on gfx950): operand a
+// lane l holds a(l % 16, k0 + l / 16), operand b lane l holds
+// b(k0 + l / 16, l % 16); result register r of lane l is C(i, l % 16) with
+// i = 4 (l / 16) + r (FP32) or i = l / 16 + 4 r (FP64).  LOWER = true
+// computes only the tiles on or below the diagonal.
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+template <typename T, int N, int NT, bool LOWER, typename FA, typename FB, typename FS>
+__device__ inline void tile_product(FA fa, FB fb, FS store) {
+  constexpr int TN = N / 16;
+  constexpr int NW = NT / 64;
+  constexpr int TILES = LOWER ? TN * (TN + 1) / 2 : TN * TN;
+  constexpr int TPW = (TILES + NW - 1) / NW;
+  static_assert(N % 16 == 0 && NT % 64 == 0, "tiles of 16, whole waves");
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  typename Mma<T>::v4 acc[TPW];
+  int ti[TPW], tj[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = w + t * NW;         // uniform over the wave
+    int I = 0, J = 0;
+    if (LOWER) {
+      I = 0;
+      while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+      J = tile - I * (I + 1) / 2;
+    } else {
+      I = tile / TN;
+      J = tile % TN;
+    }
+    ti[t] = I;
+    tj[t] = J;
+    acc[t] = typename Mma<T>::v4{0, 0, 0, 0};
+    if (tile < TILES) {
+      const int ia = 16 * I + (l & 15), jb = 16 * J + (l & 15);
+#pragma unroll 4
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int k = k0 + (l >> 4);
+        acc[t] = Mma<T>::step(fa(ia, k), fb(k, jb), acc[t]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    if (w + t * NW < TILES) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        store(16 * ti[t] + Mma<T>::row(l, r), 16 * tj[t] + (l & 15), acc[t][r]);
+    }
+  }
+}
+
 template <typename T, int N, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__restrict__ list,
                                                 const int32_t *__restrict__ sizes,
@@ -194,51 +264,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     }
     for (int e = tid; e < N * N; e += NT) Vbuf[(e / N) * P + (e % N)] = vw[e];
     __syncthreads();
-    // V regs <- W V0 (my blocks)
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int r0 = 2 * (a0 + AS * j);
-      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-#pragma unroll 4
-      for (int k = 0; k < N; ++k) {
-        const T w0 = Abuf[r0 * P + k], w1 = Abuf[(r0 + 1) * P + k];
-        const T v0 = Vbuf[k * P + 2 * b], v1 = Vbuf[k * P + 2 * b + 1];
-        c00 += w0 * v0; c01 += w0 * v1; c10 += w1 * v0; c11 += w1 * v1;
-      }
-      V[j][0][0] = c00; V[j][0][1] = c01; V[j][1][0] = c10; V[j][1][1] = c11;
-    }
+    // W V0 (W is symmetric: a(i, k) = W(k, i)), then V0^T (W V0), both into Abuf
+    tile_product<T, N, NT, false>([&](int i, int k) { return Abuf[k * P + i]; },
+                                  [&](int k, int j) { return Vbuf[k * P + j]; },
+                                  [&](int i, int j, T v) { Abuf[i * P + j] = v; });
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int aj = a0 + AS * j;
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = V[j][d][e];
-    }
-    __syncthreads();
-    // A regs <- V0^T (W V0)
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int r0 = 2 * (a0 + AS * j);
-      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-#pragma unroll 4
-      for (int k = 0; k < N; ++k) {
-        const T v0 = Vbuf[k * P + r0], v1 = Vbuf[k * P + r0 + 1];
-        const T t0 = Abuf[k * P + 2 * b], t1 = Abuf[k * P + 2 * b + 1];
-        c00 += v0 * t0; c01 += v0 * t1; c10 += v1 * t0; c11 += v1 * t1;
-      }
-      A[j][0][0] = c00; A[j][0][1] = c01; A[j][1][0] = c10; A[j][1][1] = c11;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int aj = a0 + AS * j;
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = A[j][d][e];
-    }
+    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[k * P + i]; },
+                                  [&](int k, int j) { return Abuf[k * P + j]; },
+                                  [&](int i, int j, T v) { Abuf[i * P + j] = v; });
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -376,44 +409,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   if (MODE == MODE_ADMM && vw) {
     // store the basis for the next iteration after one Newton-Schulz step,
     // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int r0 = 2 * (a0 + AS * j);
-      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-#pragma unroll 4
-      for (int k = 0; k < N; ++k) {
-        const T x0 = Vbuf[k * P + r0], x1 = Vbuf[k * P + r0 + 1];
-        const T y0 = Vbuf[k * P + 2 * b], y1 = Vbuf[k * P + 2 * b + 1];
-        c00 += x0 * y0; c01 += x0 * y1; c10 += x1 * y0; c11 += x1 * y1;
-      }
-      A[j][0][0] = c00; A[j][0][1] = c01; A[j][1][0] = c10; A[j][1][1] = c11;
-    }
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int aj = a0 + AS * j;
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = A[j][d][e];
-    }
+    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[k * P + i]; },
+                                  [&](int k, int j) { return Vbuf[k * P + j]; },
+                                  [&](int i, int j, T v) { Abuf[i * P + j] = v; });
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int r0 = 2 * (a0 + AS * j);
-      T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-#pragma unroll 4
-      for (int k = 0; k < N; ++k) {
-        const T x0 = Vbuf[r0 * P + k], x1 = Vbuf[(r0 + 1) * P + k];
-        const T g0 = Abuf[k * P + 2 * b], g1 = Abuf[k * P + 2 * b + 1];
-        c00 += x0 * g0; c01 += x0 * g1; c10 += x1 * g0; c11 += x1 * g1;
-      }
-      T *row0 = vw + (int64_t)r0 * N + 2 * b;
-      T *row1 = row0 + N;
-      row0[0] = T(1.5) * V[j][0][0] - T(0.5) * c00;
-      row0[1] = T(1.5) * V[j][0][1] - T(0.5) * c01;
-      row1[0] = T(1.5) * V[j][1][0] - T(0.5) * c10;
-      row1[1] = T(1.5) * V[j][1][1] - T(0.5) * c11;
-    }
+    tile_product<T, N, NT, false>(
+        [&](int i, int k) { return Vbuf[i * P + k]; },
+        [&](int k, int j) { return Abuf[k * P + j]; },
+        [&](int i, int j, T v) { vw[(int64_t)i * N + j] = T(1.5) * Vbuf[i * P + j] - T(0.5) * v; });
   }
   if (MODE == MODE_ADMM && a.eig) {
     // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep
@@ -422,15 +425,18 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     for (int k = tid; k < N; k += NT) eo[s * N + k] = th[k];
   }
 
-  // --- rebuild X = V diag(theta+) V^T on the packed lower triangle ---
+  // --- rebuild X = V diag(theta+) V^T (lower tiles into Abuf), then the
+  // epilogue over the packed lower triangle ---
+  tile_product<T, N, NT, true>([&](int i, int k) { return Vbuf[i * P + k] * thp[k]; },
+                               [&](int k, int j) { return Vbuf[j * P + k]; },
+                               [&](int i, int j, T v) { Abuf[i * P + j] = v; });
+  __syncthreads();
   const int npk = s * (s + 1) / 2;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
   for (int e = tid; e < npk; e += NT) {
     int i, j;
     tri_inv(e, i, j);
-    T acc = T(0);
-#pragma unroll 8
-    for (int k = 0; k < N; ++k) acc += Vbuf[i * P + k] * thp[k] * Vbuf[j * P + k];
+    const T acc = Abuf[i * P + j];
     if (MODE == MODE_STANDALONE) {
       out[off + (int64_t)i * s + j] = acc;
       out[off + (int64_t)j * s + i] = acc;
