@@ -91,6 +91,21 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
+// Column layout of the LDS blocks: de-interleaved (even slots, then odd)
+// for N <= 48, where the Jacobi rounds dominate and many row groups share a
+// wave; plain for larger blocks, whose matrix-core operand reads (16 rows x
+// 4 columns per wave) conflict on banks when the two halves of a row sit a
+// multiple of 32 words apart.
+__host__ __device__ constexpr bool lds_split(int N) { return N <= 48; }
+
+template <typename T>
+__host__ __device__ constexpr int lds_pitch(int N) {
+  if (sizeof(T) == 8 || !lds_split(N)) return N + 1;
+  int p = N;
+  while (p % 32 != (N / 4) % 32) ++p;
+  return p;
+}
+
 // Dense N x N products on the matrix cores: C = sum_k a(i, k) b(k, j) by
 // 16 x 16 tiles, one wave per tile (tiles dealt round-robin to the waves),
 // 16x16x4 MFMA steps over k.  Operands come from LDS through the functors;
@@ -172,7 +187,18 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   static_assert(NT % K == 0 && (K * K) % NT == 0, "block ownership must tile the matrix");
   constexpr int BPT = K * K / NT;     // 2x2 blocks per thread
   constexpr int AS = NT / K;          // row-pair stride between a thread's blocks
-  constexpr int P = N + 1;            // LDS pitch
+  // LDS layout: row r at r * P.  Split layout (small N): column c at
+  // (c & 1) * K + c / 2 (even slots first, then odd), so the K lanes that
+  // read a row's column pairs, and the lanes that write the advancing even /
+  // retreating odd slots, touch consecutive words; the FP32 pitch
+  // P = K/2 (mod 32) puts the row pairs of the 64 / K row groups of a wave on
+  // disjoint banks (FP64 keeps an odd pitch: its blocks must fit the LDS).
+  // Plain layout (large N): column c at c, odd pitch.
+  constexpr int P = lds_pitch<T>(N);
+  constexpr bool SPLIT = lds_split(N);
+  const auto ix = [](int r, int c) {
+    return SPLIT ? r * P + (c & 1) * (N / 2) + (c >> 1) : r * P + c;
+  };
   constexpr bool WANT_V = MODE != MODE_MINEIG;
 
   __shared__ T Abuf[N * P];
@@ -260,18 +286,18 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
       for (int d = 0; d < 2; ++d)
 #pragma unroll
-        for (int e = 0; e < 2; ++e) Abuf[(2 * aj + d) * P + 2 * b + e] = A[j][d][e];
+        for (int e = 0; e < 2; ++e) Abuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e];
     }
-    for (int e = tid; e < N * N; e += NT) Vbuf[(e / N) * P + (e % N)] = vw[e];
+    for (int e = tid; e < N * N; e += NT) Vbuf[ix(e / N, e % N)] = vw[e];
     __syncthreads();
     // W V0 (W is symmetric: a(i, k) = W(k, i)), then V0^T (W V0), both into Abuf
-    tile_product<T, N, NT, false>([&](int i, int k) { return Abuf[k * P + i]; },
-                                  [&](int k, int j) { return Vbuf[k * P + j]; },
-                                  [&](int i, int j, T v) { Abuf[i * P + j] = v; });
+    tile_product<T, N, NT, false>([&](int i, int k) { return Abuf[ix(k, i)]; },
+                                  [&](int k, int j) { return Vbuf[ix(k, j)]; },
+                                  [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
     __syncthreads();
-    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[k * P + i]; },
-                                  [&](int k, int j) { return Abuf[k * P + j]; },
-                                  [&](int i, int j, T v) { Abuf[i * P + j] = v; });
+    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[ix(k, i)]; },
+                                  [&](int k, int j) { return Abuf[ix(k, j)]; },
+                                  [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -281,8 +307,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int r = 2 * aj + d, c = 2 * b + e;
-          A[j][d][e] = T(0.5) * (Abuf[r * P + c] + Abuf[c * P + r]);
-          V[j][d][e] = Vbuf[r * P + c];
+          A[j][d][e] = T(0.5) * (Abuf[ix(r, c)] + Abuf[ix(c, r)]);
+          V[j][d][e] = Vbuf[ix(r, c)];
         }
     }
   }
@@ -352,15 +378,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       for (int j = 0; j < BPT; ++j) {
         const int aj = a0 + AS * j;
         const int sa0 = sigma_slot(2 * aj, N), sa1 = sigma_slot(2 * aj + 1, N);
-        An[sa0 * P + sb0] = A[j][0][0];
-        An[sa0 * P + sb1] = A[j][0][1];
-        An[sa1 * P + sb0] = A[j][1][0];
-        An[sa1 * P + sb1] = A[j][1][1];
+        An[ix(sa0, sb0)] = A[j][0][0];
+        An[ix(sa0, sb1)] = A[j][0][1];
+        An[ix(sa1, sb0)] = A[j][1][0];
+        An[ix(sa1, sb1)] = A[j][1][1];
         if (WANT_V) {
-          Vn[(2 * aj) * P + sb0] = V[j][0][0];
-          Vn[(2 * aj) * P + sb1] = V[j][0][1];
-          Vn[(2 * aj + 1) * P + sb0] = V[j][1][0];
-          Vn[(2 * aj + 1) * P + sb1] = V[j][1][1];
+          Vn[ix(2 * aj, sb0)] = V[j][0][0];
+          Vn[ix(2 * aj, sb1)] = V[j][0][1];
+          Vn[ix(2 * aj + 1, sb0)] = V[j][1][0];
+          Vn[ix(2 * aj + 1, sb1)] = V[j][1][1];
         }
       }
       __syncthreads();
@@ -371,8 +397,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
         for (int d = 0; d < 2; ++d)
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
-            A[j][d][e] = An[(2 * aj + d) * P + 2 * b + e];
-            if (WANT_V) V[j][d][e] = Vn[(2 * aj + d) * P + 2 * b + e];
+            A[j][d][e] = An[ix(2 * aj + d, 2 * b + e)];
+            if (WANT_V) V[j][d][e] = Vn[ix(2 * aj + d, 2 * b + e)];
           }
       }
     }
@@ -402,41 +428,41 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
     for (int d = 0; d < 2; ++d)
 #pragma unroll
-      for (int e = 0; e < 2; ++e) Vbuf[(2 * aj + d) * P + 2 * b + e] = V[j][d][e];
+      for (int e = 0; e < 2; ++e) Vbuf[ix(2 * aj + d, 2 * b + e)] = V[j][d][e];
   }
   for (int k = tid; k < N; k += NT) thp[k] = th[k] > T(0) ? th[k] : T(0);
   __syncthreads();
   if (MODE == MODE_ADMM && vw) {
     // store the basis for the next iteration after one Newton-Schulz step,
     // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality
-    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[k * P + i]; },
-                                  [&](int k, int j) { return Vbuf[k * P + j]; },
-                                  [&](int i, int j, T v) { Abuf[i * P + j] = v; });
+    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[ix(k, i)]; },
+                                  [&](int k, int j) { return Vbuf[ix(k, j)]; },
+                                  [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
     __syncthreads();
     tile_product<T, N, NT, false>(
-        [&](int i, int k) { return Vbuf[i * P + k]; },
-        [&](int k, int j) { return Abuf[k * P + j]; },
-        [&](int i, int j, T v) { vw[(int64_t)i * N + j] = T(1.5) * Vbuf[i * P + j] - T(0.5) * v; });
+        [&](int i, int k) { return Vbuf[ix(i, k)]; },
+        [&](int k, int j) { return Abuf[ix(k, j)]; },
+        [&](int i, int j, T v) { vw[(int64_t)i * N + j] = T(1.5) * Vbuf[ix(i, j)] - T(0.5) * v; });
   }
   if (MODE == MODE_ADMM && a.eig) {
     // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep
     T *eo = reinterpret_cast<T *>(a.eig) + a.eig_off[cl];
-    for (int e = tid; e < s * N; e += NT) eo[e] = Vbuf[(e / N) * P + (e % N)];
+    for (int e = tid; e < s * N; e += NT) eo[e] = Vbuf[ix(e / N, e % N)];
     for (int k = tid; k < N; k += NT) eo[s * N + k] = th[k];
   }
 
   // --- rebuild X = V diag(theta+) V^T (lower tiles into Abuf), then the
   // epilogue over the packed lower triangle ---
-  tile_product<T, N, NT, true>([&](int i, int k) { return Vbuf[i * P + k] * thp[k]; },
-                               [&](int k, int j) { return Vbuf[j * P + k]; },
-                               [&](int i, int j, T v) { Abuf[i * P + j] = v; });
+  tile_product<T, N, NT, true>([&](int i, int k) { return Vbuf[ix(i, k)] * thp[k]; },
+                               [&](int k, int j) { return Vbuf[ix(j, k)]; },
+                               [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
   __syncthreads();
   const int npk = s * (s + 1) / 2;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
   for (int e = tid; e < npk; e += NT) {
     int i, j;
     tri_inv(e, i, j);
-    const T acc = Abuf[i * P + j];
+    const T acc = Abuf[ix(i, j)];
     if (MODE == MODE_STANDALONE) {
       out[off + (int64_t)i * s + j] = acc;
       out[off + (int64_t)j * s + i] = acc;
