@@ -91,30 +91,32 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
-// Column layout of the LDS blocks: de-interleaved (even slots, then odd)
-// for N <= 48, where the Jacobi rounds dominate and many row groups share a
-// wave; plain for larger blocks, whose matrix-core operand reads (16 rows x
-// 4 columns per wave) conflict on banks when the two halves of a row sit a
-// multiple of 32 words apart.
-__host__ __device__ constexpr bool lds_split(int N) { return N <= 48; }
-
+// Row pitch of the LDS blocks (in elements).  FP32, N <= 48: P = N/4
+// (mod 32), so the row pairs that the 64 / K row groups of a wave read in a
+// Jacobi round sit on disjoint banks.  FP32, N >= 64 (one or two row groups
+// per wave): P = 16 (mod 32), so the matrix-core operand reads (4 rows x 16
+// consecutive stored columns per wave) are free of bank conflicts.  FP64:
+// an odd pitch (its blocks must fit the LDS).
 template <typename T>
 __host__ __device__ constexpr int lds_pitch(int N) {
-  if (sizeof(T) == 8 || !lds_split(N)) return N + 1;
+  if (sizeof(T) == 8) return N + 1;
+  const int target = N <= 48 ? (N / 4) % 32 : 16;
   int p = N;
-  while (p % 32 != (N / 4) % 32) ++p;
+  while (p % 32 != target) ++p;
   return p;
 }
 
-// Dense N x N products on the matrix cores: C = sum_k a(i, k) b(k, j) by
-// 16 x 16 tiles, one wave per tile (tiles dealt round-robin to the waves),
-// 16x16x4 MFMA steps over k.  Operands come from LDS through the functors;
-// store(i, j, c) receives every result after a barrier, so a product may
-// overwrite its own inputs.  Lane layouts (verified on gfx950): operand a
-// lane l holds a(l % 16, k0 + l / 16), operand b lane l holds
-// b(k0 + l / 16, l % 16); result register r of lane l is C(i, l % 16) with
+// Dense N x N products on the matrix cores, C(i, j) = sum_k x(k, i) y(k, j),
+// by 16 x 16 tiles, one wave per tile (tiles dealt round-robin to the waves),
+// 16x16x4 MFMA steps over k.  Tiles run over stored column positions (the
+// LDS blocks keep slot c at position (c & 1) N/2 + c/2), so each operand read
+// x(k, q), y(k, q) takes row k at 16 consecutive positions q; store(qi, qj, c)
+// gets the result for the slots at positions qi, qj after a barrier, so a
+// product may overwrite its own inputs.  Lane layouts (verified on gfx950):
+// operand a lane l holds A(l % 16, k0 + l / 16), operand b lane l holds
+// B(k0 + l / 16, l % 16); result register r of lane l is C(i, l % 16) with
 // i = 4 (l / 16) + r (FP32) or i = l / 16 + 4 r (FP64).  LOWER = true
-// computes only the tiles on or below the diagonal.
+// computes only the tiles on or below the diagonal (in position order).
 template <typename T> struct Mma;
 template <> struct Mma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
@@ -131,8 +133,8 @@ template <> struct Mma<double> {
   __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-template <typename T, int N, int NT, bool LOWER, typename FA, typename FB, typename FS>
-__device__ inline void tile_product(FA fa, FB fb, FS store) {
+template <typename T, int N, int NT, bool LOWER, typename FX, typename FY, typename FS>
+__device__ inline void tile_product(FX fx, FY fy, FS store) {
   constexpr int TN = N / 16;
   constexpr int NW = NT / 64;
   constexpr int TILES = LOWER ? TN * (TN + 1) / 2 : TN * TN;
@@ -157,11 +159,11 @@ __device__ inline void tile_product(FA fa, FB fb, FS store) {
     tj[t] = J;
     acc[t] = typename Mma<T>::v4{0, 0, 0, 0};
     if (tile < TILES) {
-      const int ia = 16 * I + (l & 15), jb = 16 * J + (l & 15);
+      const int qa = 16 * I + (l & 15), qb = 16 * J + (l & 15);
 #pragma unroll 4
       for (int k0 = 0; k0 < N; k0 += 4) {
         const int k = k0 + (l >> 4);
-        acc[t] = Mma<T>::step(fa(ia, k), fb(k, jb), acc[t]);
+        acc[t] = Mma<T>::step(fx(k, qa), fy(k, qb), acc[t]);
       }
     }
   }
@@ -187,18 +189,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   static_assert(NT % K == 0 && (K * K) % NT == 0, "block ownership must tile the matrix");
   constexpr int BPT = K * K / NT;     // 2x2 blocks per thread
   constexpr int AS = NT / K;          // row-pair stride between a thread's blocks
-  // LDS layout: row r at r * P.  Split layout (small N): column c at
-  // (c & 1) * K + c / 2 (even slots first, then odd), so the K lanes that
-  // read a row's column pairs, and the lanes that write the advancing even /
-  // retreating odd slots, touch consecutive words; the FP32 pitch
-  // P = K/2 (mod 32) puts the row pairs of the 64 / K row groups of a wave on
-  // disjoint banks (FP64 keeps an odd pitch: its blocks must fit the LDS).
-  // Plain layout (large N): column c at c, odd pitch.
+  // LDS layout: row r at r * P, column (slot) c at position
+  // (c & 1) * K + c / 2 (even slots first, then odd), so the K lanes that read
+  // a row's column pairs, and the lanes that write the advancing even /
+  // retreating odd slots, touch consecutive words.  slot(q) inverts the
+  // position map.
   constexpr int P = lds_pitch<T>(N);
-  constexpr bool SPLIT = lds_split(N);
-  const auto ix = [](int r, int c) {
-    return SPLIT ? r * P + (c & 1) * (N / 2) + (c >> 1) : r * P + c;
-  };
+  const auto ix = [](int r, int c) { return r * P + (c & 1) * K + (c >> 1); };
+  const auto slot = [](int q) { return q < K ? 2 * q : 2 * (q - K) + 1; };
   constexpr bool WANT_V = MODE != MODE_MINEIG;
 
   __shared__ T Abuf[N * P];
@@ -290,14 +288,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     }
     for (int e = tid; e < N * N; e += NT) Vbuf[ix(e / N, e % N)] = vw[e];
     __syncthreads();
-    // W V0 (W is symmetric: a(i, k) = W(k, i)), then V0^T (W V0), both into Abuf
-    tile_product<T, N, NT, false>([&](int i, int k) { return Abuf[ix(k, i)]; },
-                                  [&](int k, int j) { return Vbuf[ix(k, j)]; },
-                                  [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
+    // W V0 (W is symmetric: W(i, k) = W(k, i)), then V0^T (W V0), both into Abuf
+    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
     __syncthreads();
-    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[ix(k, i)]; },
-                                  [&](int k, int j) { return Abuf[ix(k, j)]; },
-                                  [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
+    tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -432,30 +430,49 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
   for (int k = tid; k < N; k += NT) thp[k] = th[k] > T(0) ? th[k] : T(0);
   __syncthreads();
+  // the Gram matrix V^T V of the Newton-Schulz step reads V by rows; the
+  // products after it read V^T, written over V from the registers
+  if (MODE == MODE_ADMM && vw) {
+    tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
+  }
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int aj = a0 + AS * j;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) Vbuf[ix(2 * b + e, 2 * aj + d)] = V[j][d][e];
+  }
+  __syncthreads();
   if (MODE == MODE_ADMM && vw) {
     // store the basis for the next iteration after one Newton-Schulz step,
-    // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality
-    tile_product<T, N, NT, false>([&](int i, int k) { return Vbuf[ix(k, i)]; },
-                                  [&](int k, int j) { return Vbuf[ix(k, j)]; },
-                                  [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
-    __syncthreads();
+    // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality:
+    // (V G)(i, j) = sum_k V^T(k, i) G(k, j), V(i, j) = V^T(j, i)
     tile_product<T, N, NT, false>(
-        [&](int i, int k) { return Vbuf[ix(i, k)]; },
-        [&](int k, int j) { return Abuf[ix(k, j)]; },
-        [&](int i, int j, T v) { vw[(int64_t)i * N + j] = T(1.5) * Vbuf[ix(i, j)] - T(0.5) * v; });
+        [&](int k, int q) { return Vbuf[k * P + q]; },
+        [&](int k, int q) { return Abuf[k * P + q]; },
+        [&](int qi, int qj, T v) {
+          vw[(int64_t)slot(qi) * N + slot(qj)] = T(1.5) * Vbuf[slot(qj) * P + qi] - T(0.5) * v;
+        });
   }
   if (MODE == MODE_ADMM && a.eig) {
     // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep
     T *eo = reinterpret_cast<T *>(a.eig) + a.eig_off[cl];
-    for (int e = tid; e < s * N; e += NT) eo[e] = Vbuf[ix(e / N, e % N)];
+    for (int e = tid; e < s * N; e += NT) eo[e] = Vbuf[ix(e % N, e / N)];
     for (int k = tid; k < N; k += NT) eo[s * N + k] = th[k];
   }
 
-  // --- rebuild X = V diag(theta+) V^T (lower tiles into Abuf), then the
-  // epilogue over the packed lower triangle ---
-  tile_product<T, N, NT, true>([&](int i, int k) { return Vbuf[ix(i, k)] * thp[k]; },
-                               [&](int k, int j) { return Vbuf[ix(j, k)]; },
-                               [&](int i, int j, T v) { Abuf[ix(i, j)] = v; });
+  // --- rebuild X = V diag(theta+) V^T = sum_k V^T(k, i) theta+_k V^T(k, j):
+  // tiles on or below the diagonal, each result stored at (i, j) and (j, i);
+  // then the epilogue over the packed lower triangle ---
+  tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q] * thp[k]; },
+                               [&](int k, int q) { return Vbuf[k * P + q]; },
+                               [&](int qi, int qj, T v) {
+                                 Abuf[slot(qi) * P + qj] = v;
+                                 Abuf[slot(qj) * P + qi] = v;
+                               });
   __syncthreads();
   const int npk = s * (s + 1) / 2;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
