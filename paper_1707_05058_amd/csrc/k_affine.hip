@@ -28,6 +28,15 @@ constexpr int COL_NT = 256;   // threads of a column-dot workgroup (4 waves)
 constexpr int COL_W = 128;    // columns per column-dot tile (2 per lane)
 constexpr int MAX_R = 8;      // max rows per row-dot tile
 
+// Rows of dense A (or B) are read as pairs; for matrices larger than the
+// 256 MB last-level cache (stream_nt) by the kernel instances with non-
+// temporal loads (+10% on a 31.8 GB batch), otherwise with plain loads, which
+// let a matrix that fits be served partly from that cache (non-temporal loads
+// cost 25% on a 256 MB one).  The choice is a template parameter: a runtime
+// select between the two loads of one address may be merged into one plain
+// load.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -88,7 +97,7 @@ __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
 // consecutive rows of one instance; lanes stride the columns with 16-byte
 // loads, so every wave reads contiguous 1 KiB segments of A.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool NTL>
 __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
   const int inst = a.row_tiles[2 * blockIdx.x];
   const int row0 = a.row_tiles[2 * blockIdx.x + 1];
@@ -107,7 +116,10 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (r < nrow) {
-        const double2 m2 = reinterpret_cast<const double2 *>(mat + (int64_t)r * d.ld)[c];
+        const dvec2 *pm = reinterpret_cast<const dvec2 *>(mat + (int64_t)r * d.ld) + c;
+        dvec2 m2;
+        if constexpr (NTL) m2 = __builtin_nontemporal_load(pm);
+        else m2 = *pm;
         acc[r] += m2.x * x.x + m2.y * x.y;
       }
     }
@@ -143,7 +155,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
 // One tile = 128 columns of one instance; lane l owns columns 2l, 2l+1 and
 // the 4 waves split the rows, so each wave reads contiguous 1 KiB segments.
 // ---------------------------------------------------------------------------
-template <int RAW>
+template <int RAW, bool NTL>
 __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
   const int inst = a.col_tiles[2 * blockIdx.x];
   const int col0 = a.col_tiles[2 * blockIdx.x + 1];
@@ -158,7 +170,10 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
     const double *base = (a.Bm ? a.Bm : a.A) + d.a_off + col;
 #pragma unroll 4
     for (int i = w; i < d.m; i += 4) {
-      const double2 m2 = *reinterpret_cast<const double2 *>(base + (int64_t)i * d.ld);
+      const dvec2 *pm = reinterpret_cast<const dvec2 *>(base + (int64_t)i * d.ld);
+      dvec2 m2;
+      if constexpr (NTL) m2 = __builtin_nontemporal_load(pm);
+      else m2 = *pm;
       const double yi = vec[i];
       ax += m2.x * yi;
       ay += m2.y * yi;
@@ -583,6 +598,33 @@ __global__ __launch_bounds__(256) void k_cg_diag(AffineArgs a, const double *wd,
   if (l == 0) out[d.row_off + row] = acc;
 }
 
+// Dense row and column passes with the tile height and load kind of `a`.
+template <bool NTL>
+void rowdot_tiles(const AffineArgs &a, hipStream_t st) {
+  const dim3 g(a.n_row_tiles), b(ROW_NT);
+  switch (a.rows_per_tile) {
+    case 1: hipLaunchKernelGGL((k_rowdot<1, NTL>), g, b, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_rowdot<2, NTL>), g, b, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_rowdot<4, NTL>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_rowdot<MAX_R, NTL>), g, b, 0, st, a); break;
+  }
+}
+
+void launch_dense_rowdot(const AffineArgs &a, hipStream_t st) {
+  if (a.n_row_tiles <= 0) return;
+  if (a.stream_nt) rowdot_tiles<true>(a, st);
+  else rowdot_tiles<false>(a, st);
+}
+
+template <int RAW>
+void launch_dense_coldot(const AffineArgs &a, hipStream_t st) {
+  if (a.n_col_tiles <= 0) return;
+  if (a.stream_nt)
+    hipLaunchKernelGGL((k_coldot<RAW, true>), dim3(a.n_col_tiles), dim3(COL_NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_coldot<RAW, false>), dim3(a.n_col_tiles), dim3(COL_NT), 0, st, a);
+}
+
 }  // namespace
 
 // Stages of the X-step, launched in this order every iteration:
@@ -597,14 +639,7 @@ hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
       break;
     }
     case 1:
-      if (a.n_row_tiles > 0) {
-        switch (a.rows_per_tile) {
-          case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-          case 2: hipLaunchKernelGGL((k_rowdot<2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-          case 4: hipLaunchKernelGGL((k_rowdot<4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-          default: hipLaunchKernelGGL((k_rowdot<MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-        }
-      }
+      launch_dense_rowdot(a, st);
       if (a.n_csr_rows > 0)
         hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
       break;
@@ -617,8 +652,7 @@ hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
         hipLaunchKernelGGL(k_trmv_wave<1>, dim3((a.n_t3_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 4:
-      if (a.n_col_tiles > 0)
-        hipLaunchKernelGGL(k_coldot<0>, dim3(a.n_col_tiles), dim3(COL_NT), 0, st, a);
+      launch_dense_coldot<0>(a, st);
       if (a.n_csc_cols > 0)
         hipLaunchKernelGGL(k_csc_coldot<0>, dim3(a.n_csc_cols), dim3(256), 0, st, a);
       break;
@@ -664,21 +698,13 @@ hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const 
   ar.v = s.wu;
   ar.r = s.ax;
   ar.dual = 0;
-  if (ar.n_row_tiles > 0) {
-    switch (ar.rows_per_tile) {
-      case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-      case 2: hipLaunchKernelGGL((k_rowdot<2>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-      case 4: hipLaunchKernelGGL((k_rowdot<4>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-      default: hipLaunchKernelGGL((k_rowdot<MAX_R>), dim3(ar.n_row_tiles), dim3(ROW_NT), 0, st, ar); break;
-    }
-  }
+  launch_dense_rowdot(ar, st);
   if (ar.n_csr_rows > 0)
     hipLaunchKernelGGL(k_csr_rowdot, dim3((ar.n_csr_rows + 3) / 4), dim3(256), 0, st, ar);
   AffineArgs at = a;          // A^T y_dual
   at.y = s.yd;
   at.u = s.aty;
-  if (at.n_col_tiles > 0)
-    hipLaunchKernelGGL(k_coldot<1>, dim3(at.n_col_tiles), dim3(COL_NT), 0, st, at);
+  launch_dense_coldot<1>(at, st);
   if (at.n_csc_cols > 0)
     hipLaunchKernelGGL(k_csc_coldot<1>, dim3(at.n_csc_cols), dim3(256), 0, st, at);
   hipLaunchKernelGGL(k_diag_reduce, dim3(a.batch), dim3(256), 0, st, a, s, cl_first, out);
@@ -701,14 +727,7 @@ hipError_t launch_scaled_copy(const double *src, double *dst, int64_t n, const I
 namespace {
 
 void launch_rowdots(const AffineArgs &a, hipStream_t st) {
-  if (a.n_row_tiles > 0) {
-    switch (a.rows_per_tile) {
-      case 1: hipLaunchKernelGGL((k_rowdot<1>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-      case 2: hipLaunchKernelGGL((k_rowdot<2>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-      case 4: hipLaunchKernelGGL((k_rowdot<4>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-      default: hipLaunchKernelGGL((k_rowdot<MAX_R>), dim3(a.n_row_tiles), dim3(ROW_NT), 0, st, a); break;
-    }
-  }
+  launch_dense_rowdot(a, st);
   if (a.n_csr_rows > 0)
     hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
 }
@@ -729,8 +748,7 @@ hipError_t launch_cg_stage(const AffineArgs &a, int stage, hipStream_t st) {
   ar.no_b = 1;
   ar.cg_loop = 1;
   for (int k = 0; k < a.cg_max_iter; ++k) {
-    if (at.n_col_tiles > 0)
-      hipLaunchKernelGGL(k_coldot<2>, dim3(at.n_col_tiles), dim3(COL_NT), 0, st, at);
+    launch_dense_coldot<2>(at, st);
     if (at.n_csc_cols > 0)
       hipLaunchKernelGGL(k_csc_coldot<2>, dim3(at.n_csc_cols), dim3(256), 0, st, at);
     launch_rowdots(ar, st);

@@ -951,6 +951,9 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     a.y1 = dev_zeros<double>(row, own);
     a.y = dev_zeros<double>(row, own);
     a.A = d_A;
+    // dense matrices beyond the 256 MB last-level cache stream with
+    // non-temporal loads (each pass reads them once)
+    a.stream_nt = (double)aoff * sizeof(double) > 256.0 * 1024 * 1024 ? 1 : 0;
     if (any_csr) {
       a.a_rowptr = dev_upload(a_rowptr, own);
       a.a_col = dev_upload(a_col, own);

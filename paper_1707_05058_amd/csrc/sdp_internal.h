@@ -197,6 +197,7 @@ struct AffineArgs {
   const int32_t *cg_tile_first;               // [batch + 1]: an instance's tiles
   double *cg_part;                            // [3][cg_ntiles]: p^T M p, r^T z, ||r||^2
   int cg_loop;                                // products inside the solve: skip stopped instances
+  int stream_nt;                              // dense passes with non-temporal loads
   int no_b;                                   // row products without the -b term
 };
 
