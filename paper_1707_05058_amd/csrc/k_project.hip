@@ -605,10 +605,11 @@ hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t 
 // size, the variant that runs fastest; without it the smallest N and the
 // first NT listed for that N are used.
 struct Variant { int N, NT; };
-constexpr Variant kVar32[] = {{16, 64},  {32, 64},  {32, 128}, {32, 256}, {48, 192}, {64, 256},
-                              {64, 128}, {64, 512}, {96, 576}, {128, 1024}, {128, 512}};
+constexpr Variant kVar32[] = {{16, 64},  {32, 64},  {32, 128},  {32, 256},  {48, 192},
+                              {64, 256}, {64, 128}, {64, 512},  {80, 320},  {96, 576},
+                              {112, 448}, {128, 1024}, {128, 512}};
 constexpr Variant kVar64[] = {{16, 64},  {32, 64},  {32, 128}, {32, 256}, {48, 192},
-                              {64, 256}, {64, 128}, {64, 512}, {96, 576}};
+                              {64, 256}, {64, 128}, {64, 512}, {80, 320}, {96, 576}};
 constexpr int kNVar32 = sizeof(kVar32) / sizeof(kVar32[0]);
 constexpr int kNVar64 = sizeof(kVar64) / sizeof(kVar64[0]);
 
@@ -627,8 +628,10 @@ hipError_t dispatch(int N, int NT, int count, ProjArgs a, const int32_t *list,
   SDP_VARIANT(64, 128)
   SDP_VARIANT(64, 256)
   SDP_VARIANT(64, 512)
+  SDP_VARIANT(80, 320)
   SDP_VARIANT(96, 576)
   if constexpr (sizeof(T) == 4) {
+    SDP_VARIANT(112, 448)
     SDP_VARIANT(128, 512)
     SDP_VARIANT(128, 1024)
   }
