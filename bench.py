@@ -292,7 +292,10 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     out["objectives"] = [r["objective"] for r in rs]
     out["jacobi_sweeps_per_projection"] = (S.stats()["jacobi_sweeps"] /
                                            max(S.stats()["projections"], 1))
-    out["projection_plan"] = [dict(N=n, threads=t, cliques=c) for n, t, c in S.projection_plan()]
+    two = [sdp.projection_variant_two_level(sdp.DTYPE_FP32 if precision == "fp32" else sdp.DTYPE_FP64, v)
+           for v in S.projection_plan_variants()]
+    out["projection_plan"] = [dict(N=n, threads=t, cliques=c, two_level=tl)
+                              for (n, t, c), tl in zip(S.projection_plan(), two)]
     if extra.get("cg_max_iter"):
         out["solve"]["cg_steps_per_iteration"] = S.cg_steps() / max(sum(its), 1)
     S.close()

@@ -193,6 +193,12 @@ int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *size
 int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_t *threads,
                             int32_t *count);
 
+/* Whether kernel variant `variant` of `dtype` runs the two-level (block)
+ * Jacobi method (*two_level = 1: groups of 8 indices paired round-robin, each
+ * pair's 16 x 16 problem diagonalised by one wave and applied to the block on
+ * the matrix cores) or the scalar parallel-order one (0).  Host only. */
+int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *two_level);
+
 /* sdp_psd_project_batched with an explicit kernel variant (an index into the
  * list of sdp_projection_variants); max_size must not exceed that variant's
  * N.  The result is the same projection; the variants differ in how the work
@@ -239,6 +245,10 @@ int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
  * is 0) and the number of lists through *count. */
 int sdp_projection_plan(sdp_handle *h, int32_t cap, int32_t *block_n, int32_t *threads,
                         int32_t *cliques, int32_t *count);
+
+/* The kernel variant (index into sdp_projection_variants for the handle's
+ * precision) of each launch list of sdp_projection_plan, same order. */
+int sdp_projection_plan_variants(sdp_handle *h, int32_t cap, int32_t *variant, int32_t *count);
 
 /* Times every stage of the iteration on its own: stage s is launched n_iter
  * times back to back between two HIP events on the handle's stream (stages

@@ -75,6 +75,7 @@ EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sd
            "sdp_get_solution", "sdp_set_state", "sdp_get_history",
            "sdp_diagnostics", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
            "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_cg_steps", "sdp_destroy",
+           "sdp_projection_variant_kind", "sdp_projection_plan_variants",
            "sdp_last_error",
            "sdp_pattern_create", "sdp_pattern_sizes", "sdp_pattern_get", "sdp_pattern_destroy",
            "sdp_scale_compute", "sdp_scale_apply", "sdp_scale_recover"]
@@ -112,6 +113,8 @@ def _load():
     lib.sdp_unrolled_forward.argtypes = [_p, C.c_int32, C.c_int32, _p]
     lib.sdp_vjp.argtypes = [_p, _p, _p, _p, C.c_int32]
     lib.sdp_cg_steps.argtypes = [_p, C.POINTER(C.c_int64)]
+    lib.sdp_projection_variant_kind.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    lib.sdp_projection_plan_variants.argtypes = [_p, C.c_int32, ip, C.POINTER(C.c_int32)]
     lib.sdp_destroy.argtypes = [_p]
     lib.sdp_destroy.restype = None
     lib.sdp_last_error.argtypes = []
@@ -335,6 +338,15 @@ class Solver:
         _check(lib.sdp_projection_plan(self._h, k, N, NT, cnt, C.byref(n)))
         return [(N[i], NT[i], cnt[i]) for i in range(k)]
 
+    def projection_plan_variants(self):
+        """Kernel variant index of each projection launch list."""
+        n = C.c_int32(0)
+        _check(lib.sdp_projection_plan_variants(self._h, 0, None, C.byref(n)))
+        k = n.value
+        v = (C.c_int32 * k)()
+        _check(lib.sdp_projection_plan_variants(self._h, k, v, C.byref(n)))
+        return list(v)
+
 
 def _check_tensor(t, n):
     import torch as _t
@@ -397,6 +409,13 @@ def psd_project_batched(sizes, offsets, inp, out, max_size: int, stream=None,
         _check(lib.sdp_psd_project_batched(*args))
     else:
         _check(lib.sdp_psd_project_variant(int(variant), *args))
+
+
+def projection_variant_two_level(dtype: int, variant: int) -> bool:
+    """Whether the variant runs the two-level (block) Jacobi method."""
+    t = C.c_int32(0)
+    _check(lib.sdp_projection_variant_kind(int(dtype), int(variant), C.byref(t)))
+    return bool(t.value)
 
 
 def projection_variants(dtype: int):

@@ -98,8 +98,8 @@ __device__ inline double block_sum(double v, double *red) {
 // consecutive stored columns per wave) are free of bank conflicts.  FP64:
 // an odd pitch (its blocks must fit the LDS).
 template <typename T>
-__host__ __device__ constexpr int lds_pitch(int N) {
-  if (sizeof(T) == 8) return N + 1;
+__host__ __device__ constexpr int lds_pitch(int N, bool two_level) {
+  if (sizeof(T) == 8 || two_level) return N + 1;
   const int target = N <= 48 ? (N / 4) % 32 : 16;
   int p = N;
   while (p % 32 != target) ++p;
@@ -178,7 +178,231 @@ __device__ inline void tile_product(FX fx, FY fy, FS store) {
   }
 }
 
-template <typename T, int N, int NT, int MODE>
+// ---------------------------------------------------------------------------
+// Two-level (block) Jacobi for large blocks.  The N indices form N/8 groups of
+// 8; in each round of a sweep the groups are paired by the circle method (N/8
+// - 1 rounds meet every pair of groups once).  Each pair's 16 x 16 principal
+// submatrix S is diagonalised by one wave (the parallel-order Jacobi above on
+// 16 indices, its exchanges in wave-private LDS), giving S = Q diag(lambda)
+// Q^T; then every 16 x 16 submatrix A[P1, P2] of two pairs becomes
+// Q1^T A[P1, P2] Q2 (lambda on the pair's own diagonal block) and every 16-row
+// panel of V[:, P] becomes V[:, P] Q, both on the matrix cores.  A and V stay
+// in place in LDS (row-major, pitch N + 1); only 16 x 16 submatrices move.
+// ---------------------------------------------------------------------------
+constexpr int QP = 17;                        // pitch of the per-wave 16 x 16 scratch
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// orders this wave's LDS accesses: what a lane wrote is visible to every lane
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);         // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// groups of pair w in round r (nb groups, circle method)
+__device__ inline void round_pair(int r, int w, int nb, int &gi, int &gj) {
+  const int m = nb - 1;
+  if (w == 0) {
+    gi = nb - 1;
+    gj = r % m;
+  } else {
+    gi = (r + w) % m;
+    gj = (r - w + m) % m;
+  }
+}
+
+// index of entry k (0..15) of a pair made of groups gi, gj
+__device__ inline int pair_index(int gi, int gj, int k) { return k < 8 ? 8 * gi + k : 8 * gj + k - 8; }
+
+// One wave: diagonalise S = A[idx, idx] (idx from groups gi, gj) by the
+// parallel-order Jacobi; Q (16 x 16, row-major, pitch QP: entry (i, slot k))
+// into q, the eigenvalues (by slot) into lam.  sa is scratch of 16 x QP, prm
+// of 16.
+template <typename T, int P>
+__device__ void pair_eig16(const T *Abuf, int gi, int gj, T *sa, T *q, T *prm, T *lam,
+                           double tol, int max_sweeps) {
+  const int l = threadIdx.x & 63, a0 = l >> 3, b = l & 7;   // 2x2 block (a0, b) of 8x8
+  T A[2][2], V[2][2];
+  double f2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = pair_index(gi, gj, 2 * a0 + d), k = pair_index(gi, gj, 2 * b + e);
+      A[d][e] = Abuf[i * P + k];
+      V[d][e] = (2 * a0 + d == 2 * b + e) ? T(1) : T(0);
+      f2 += (double)A[d][e] * (double)A[d][e];
+    }
+  const bool diag = a0 == b;
+  const double thr = tol * tol * wave_sum(f2);
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double o2 = (double)A[0][1] * A[0][1] + (double)A[1][0] * A[1][0];
+    if (!diag) o2 += (double)A[0][0] * A[0][0] + (double)A[1][1] * A[1][1];
+    if (!(wave_sum(o2) > thr)) break;
+    for (int r = 0; r < 15; ++r) {
+      if (diag) {
+        T c, sn, t;
+        const T apq = A[0][1];
+        sym_rotation<T>(A[0][0], A[1][1], apq, c, sn, t);
+        A[0][0] -= t * apq;
+        A[1][1] += t * apq;
+        A[0][1] = T(0);
+        A[1][0] = T(0);
+        prm[b] = c;
+        prm[8 + b] = sn;
+      }
+      wave_lds_sync();
+      const T cb = prm[b], sb = prm[8 + b];
+      if (!diag) {
+        const T ca = prm[a0], s_a = prm[8 + a0];
+        const T b00 = A[0][0], b01 = A[0][1], b10 = A[1][0], b11 = A[1][1];
+        const T c00 = cb * b00 - sb * b01, c01 = sb * b00 + cb * b01;
+        const T c10 = cb * b10 - sb * b11, c11 = sb * b10 + cb * b11;
+        A[0][0] = ca * c00 - s_a * c10;
+        A[0][1] = ca * c01 - s_a * c11;
+        A[1][0] = s_a * c00 + ca * c10;
+        A[1][1] = s_a * c01 + ca * c11;
+      }
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T vp = V[d][0], vq = V[d][1];
+        V[d][0] = cb * vp - sb * vq;
+        V[d][1] = sb * vp + cb * vq;
+      }
+      const int sa0 = sigma_slot(2 * a0, 16), sa1 = sigma_slot(2 * a0 + 1, 16);
+      const int sb0 = sigma_slot(2 * b, 16), sb1 = sigma_slot(2 * b + 1, 16);
+      sa[sa0 * QP + sb0] = A[0][0];
+      sa[sa0 * QP + sb1] = A[0][1];
+      sa[sa1 * QP + sb0] = A[1][0];
+      sa[sa1 * QP + sb1] = A[1][1];
+      q[(2 * a0) * QP + sb0] = V[0][0];
+      q[(2 * a0) * QP + sb1] = V[0][1];
+      q[(2 * a0 + 1) * QP + sb0] = V[1][0];
+      q[(2 * a0 + 1) * QP + sb1] = V[1][1];
+      wave_lds_sync();
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          A[d][e] = sa[(2 * a0 + d) * QP + 2 * b + e];
+          V[d][e] = q[(2 * a0 + d) * QP + 2 * b + e];
+        }
+      wave_lds_sync();
+    }
+  }
+  if (diag) {
+    lam[2 * b] = A[0][0];
+    lam[2 * b + 1] = A[1][1];
+  }
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) q[(2 * a0 + d) * QP + 2 * b + e] = V[d][e];
+  wave_lds_sync();
+}
+
+// Sweeps of the two-level Jacobi over A and V in LDS (row-major, pitch P).
+// ws holds per-wave scratch: 16 x QP for S / intermediate products, 16 x QP
+// for Q, 16 rotation parameters, 16 eigenvalues.  Returns the sweeps done.
+template <typename T, int N, int NT, int P, bool WANT_V>
+__device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr, double tol,
+                                int max_sweeps) {
+  constexpr int NG = N / 8;                   // groups of 8
+  constexpr int NP = N / 16;                  // pairs per round
+  constexpr int NW = NT / 64;
+  constexpr int WS = 2 * 16 * QP + 32;        // scratch per wave
+  static_assert(NW >= NP, "one wave per pair");
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  T *sa = ws + w * WS, *q = sa + 16 * QP, *prm = q + 16 * QP, *lam = prm + 16;
+  const auto wsq = [&](int pw) { return ws + pw * WS + 16 * QP; };        // Q of pair pw
+  const auto wsl = [&](int pw) { return ws + pw * WS + 2 * 16 * QP + 16; }; // lambda of pair pw
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    double o2 = 0.0;
+    for (int e = tid; e < N * N; e += NT) {
+      const int i = e / N, k = e % N;
+      if (i != k) o2 += (double)Abuf[i * P + k] * (double)Abuf[i * P + k];
+    }
+    o2 = block_sum<NT>(o2, red);
+    if (!(o2 > thr)) break;
+    for (int r = 0; r < NG - 1; ++r) {
+      if (w < NP) {
+        int gi, gj;
+        round_pair(r, w, NG, gi, gj);
+        pair_eig16<T, P>(Abuf, gi, gj, sa, q, prm, lam, tol, max_sweeps);
+      }
+      __syncthreads();
+      // A[P1, P2] <- Q1^T A[P1, P2] Q2: tiles (p1, p2) dealt to the waves
+      for (int t = w; t < NP * NP; t += NW) {
+        const int p1 = t / NP, p2 = t % NP;
+        int g1i, g1j, g2i, g2j;
+        round_pair(r, p1, NG, g1i, g1j);
+        round_pair(r, p2, NG, g2i, g2j);
+        if (p1 == p2) {
+          const T *lm = wsl(p1);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = Mma<T>::row(l, rr), k = l & 15;
+            Abuf[pair_index(g1i, g1j, i) * P + pair_index(g1i, g1j, k)] = (i == k) ? lm[i] : T(0);
+          }
+          continue;
+        }
+        const T *q1 = wsq(p1), *q2 = wsq(p2);
+        // T = A[P1, P2] Q2 into this wave's sa
+        typename Mma<T>::v4 acc = {0, 0, 0, 0};
+        const int ia = pair_index(g1i, g1j, l & 15);
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const int k = k0 + (l >> 4);
+          acc = Mma<T>::step(Abuf[ia * P + pair_index(g2i, g2j, k)], q2[k * QP + (l & 15)], acc);
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) sa[Mma<T>::row(l, rr) * QP + (l & 15)] = acc[rr];
+        wave_lds_sync();
+        // Q1^T T back into A[P1, P2]
+        typename Mma<T>::v4 acc2 = {0, 0, 0, 0};
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const int k = k0 + (l >> 4);
+          acc2 = Mma<T>::step(q1[k * QP + (l & 15)], sa[k * QP + (l & 15)], acc2);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          Abuf[pair_index(g1i, g1j, Mma<T>::row(l, rr)) * P + pair_index(g2i, g2j, l & 15)] =
+              acc2[rr];
+      }
+      if (WANT_V) {
+        // V[:, P] <- V[:, P] Q: 16-row panels x pairs
+        for (int t = w; t < NP * (N / 16); t += NW) {
+          const int pc = t % NP, rt = t / NP;
+          int gi, gj;
+          round_pair(r, pc, NG, gi, gj);
+          const T *qc = wsq(pc);
+          typename Mma<T>::v4 acc = {0, 0, 0, 0};
+          const int row = 16 * rt + (l & 15);
+#pragma unroll
+          for (int k0 = 0; k0 < 16; k0 += 4) {
+            const int k = k0 + (l >> 4);
+            acc = Mma<T>::step(Vbuf[row * P + pair_index(gi, gj, k)], qc[k * QP + (l & 15)], acc);
+          }
+          wave_lds_sync();
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            Vbuf[(16 * rt + Mma<T>::row(l, rr)) * P + pair_index(gi, gj, l & 15)] = acc[rr];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return sweep;
+}
+
+template <typename T, int N, int NT, int MODE, bool BLK>
 __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__restrict__ list,
                                                 const int32_t *__restrict__ sizes,
                                                 const int64_t *__restrict__ offsets,
@@ -194,9 +418,10 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   // a row's column pairs, and the lanes that write the advancing even /
   // retreating odd slots, touch consecutive words.  slot(q) inverts the
   // position map.
-  constexpr int P = lds_pitch<T>(N);
-  const auto ix = [](int r, int c) { return r * P + (c & 1) * K + (c >> 1); };
-  const auto slot = [](int q) { return q < K ? 2 * q : 2 * (q - K) + 1; };
+  // (two-level mode: plain row-major, pitch N + 1)
+  constexpr int P = lds_pitch<T>(N, BLK);
+  const auto ix = [](int r, int c) { return BLK ? r * P + c : r * P + (c & 1) * K + (c >> 1); };
+  const auto slot = [](int q) { return BLK ? q : (q < K ? 2 * q : 2 * (q - K) + 1); };
   constexpr bool WANT_V = MODE != MODE_MINEIG;
 
   __shared__ T Abuf[N * P];
@@ -204,6 +429,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   __shared__ T prm_c[K], prm_s[K];
   __shared__ T th[N], thp[N];
   __shared__ double red[NT / 64];
+  __shared__ T ws[BLK ? (NT / 64) * (2 * 16 * QP + 32) : 1];
 
   const int tid = threadIdx.x;
   int s, cl = 0;
@@ -312,7 +538,32 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
 
   int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
+  if constexpr (BLK) {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          Abuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e];
+          if (WANT_V) Vbuf[ix(2 * aj + d, 2 * b + e)] = V[j][d][e];
+        }
+    }
+    __syncthreads();
+    sweep = two_level_sweeps<T, N, NT, P, WANT_V>(Abuf, Vbuf, ws, red, thr, tol, max_sweeps);
+    for (int k = tid; k < N; k += NT) th[k] = Abuf[k * P + k];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          if (WANT_V) V[j][d][e] = Vbuf[ix(2 * aj + d, 2 * b + e)];
+    }
+  }
+  for (; !BLK && sweep < max_sweeps; ++sweep) {
     double o2 = 0.0;
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -405,7 +656,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   // eigenvalues sit on the diagonal slots
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
-    if (a0 + AS * j == b) {
+    if (!BLK && a0 + AS * j == b) {
       th[2 * b] = A[j][0][0];
       th[2 * b + 1] = A[j][1][1];
     }
@@ -590,13 +841,13 @@ __global__ __launch_bounds__(256) void k_dual_update(ProjArgs a) {
   }
 }
 
-template <typename T, int N, int NT, int MODE>
+template <typename T, int N, int NT, int MODE, bool BLK>
 hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t *sizes,
                       const int64_t *offsets, const T *in, T *out, double *lmin, int msw,
                       double tol, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_project<T, N, NT, MODE>), dim3(count), dim3(NT), 0, st, a, list, sizes,
-                     offsets, in, out, lmin, msw, tol);
+  hipLaunchKernelGGL((k_project<T, N, NT, MODE, BLK>), dim3(count), dim3(NT), 0, st, a, list,
+                     sizes, offsets, in, out, lmin, msw, tol);
   return hipGetLastError();
 }
 
@@ -604,45 +855,57 @@ hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t 
 // thread owns K*K/NT 2x2 blocks (K = N/2).  The autotuner picks, per clique
 // size, the variant that runs fastest; without it the smallest N and the
 // first NT listed for that N are used.
-struct Variant { int N, NT; };
-constexpr Variant kVar32[] = {{16, 64},  {32, 64},  {32, 128},  {32, 256},  {48, 192},
-                              {64, 256}, {64, 128}, {64, 512},  {80, 320},  {96, 576},
-                              {112, 448}, {128, 1024}, {128, 512}};
-constexpr Variant kVar64[] = {{16, 64},  {32, 64},  {32, 128}, {32, 256}, {48, 192},
-                              {64, 256}, {64, 128}, {64, 512}, {80, 320}, {96, 576}};
+struct Variant { int N, NT, two_level; };
+constexpr Variant kVar32[] = {
+    {16, 64, 0},   {32, 64, 0},    {32, 128, 0},  {32, 256, 0}, {48, 192, 0},
+    {64, 256, 0},  {64, 128, 0},   {64, 512, 0},  {80, 320, 0}, {96, 576, 0},
+    {112, 448, 0}, {128, 1024, 0}, {128, 512, 0}, {64, 256, 1}, {80, 320, 1},
+    {96, 384, 1},  {112, 448, 1},  {128, 512, 1}};
+constexpr Variant kVar64[] = {{16, 64, 0},  {32, 64, 0},  {32, 128, 0}, {32, 256, 0},
+                              {48, 192, 0}, {64, 256, 0}, {64, 128, 0}, {64, 512, 0},
+                              {80, 320, 0}, {96, 576, 0}, {64, 256, 1}, {80, 320, 1}};
 constexpr int kNVar32 = sizeof(kVar32) / sizeof(kVar32[0]);
 constexpr int kNVar64 = sizeof(kVar64) / sizeof(kVar64[0]);
 
 template <typename T, int MODE>
-hipError_t dispatch(int N, int NT, int count, ProjArgs a, const int32_t *list,
+hipError_t dispatch(int N, int NT, int blk, int count, ProjArgs a, const int32_t *list,
                     const int32_t *sizes, const int64_t *offsets, const T *in, T *out,
                     double *lmin, int msw, double tol, hipStream_t st) {
-#define SDP_VARIANT(n, nt)                                                                     \
-  if (N == n && NT == nt)                                                                      \
-    return launch_one<T, n, nt, MODE>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
-  SDP_VARIANT(16, 64)
-  SDP_VARIANT(32, 64)
-  SDP_VARIANT(32, 128)
-  SDP_VARIANT(32, 256)
-  SDP_VARIANT(48, 192)
-  SDP_VARIANT(64, 128)
-  SDP_VARIANT(64, 256)
-  SDP_VARIANT(64, 512)
-  SDP_VARIANT(80, 320)
-  SDP_VARIANT(96, 576)
+#define SDP_VARIANT(n, nt, bl)                                                                 \
+  if (N == n && NT == nt && blk == bl)                                                         \
+    return launch_one<T, n, nt, MODE, bl>(count, a, list, sizes, offsets, in, out, lmin, msw,  \
+                                          tol, st);
+  SDP_VARIANT(16, 64, 0)
+  SDP_VARIANT(32, 64, 0)
+  SDP_VARIANT(32, 128, 0)
+  SDP_VARIANT(32, 256, 0)
+  SDP_VARIANT(48, 192, 0)
+  SDP_VARIANT(64, 128, 0)
+  SDP_VARIANT(64, 256, 0)
+  SDP_VARIANT(64, 512, 0)
+  SDP_VARIANT(80, 320, 0)
+  SDP_VARIANT(96, 576, 0)
+  SDP_VARIANT(64, 256, 1)
+  SDP_VARIANT(80, 320, 1)
   if constexpr (sizeof(T) == 4) {
-    SDP_VARIANT(112, 448)
-    SDP_VARIANT(128, 512)
-    SDP_VARIANT(128, 1024)
+    SDP_VARIANT(112, 448, 0)
+    SDP_VARIANT(128, 512, 0)
+    SDP_VARIANT(128, 1024, 0)
+    SDP_VARIANT(96, 384, 1)
+    SDP_VARIANT(112, 448, 1)
+    SDP_VARIANT(128, 512, 1)
   }
 #undef SDP_VARIANT
   return hipErrorInvalidValue;
 }
 
 // Fills `count` symmetric s x s blocks (row-major, contiguous) with values in
-// (-1, 1) from a counter-based hash: synthetic inputs for the autotuner.
+// (-1, 1) from a counter-based hash, the off-diagonal ones scaled by offdiag:
+// synthetic inputs for the autotuner (offdiag = 1: a cold eigensolve;
+// offdiag << 1: the nearly diagonal matrix a warm-started one sees).
 template <typename T>
-__global__ __launch_bounds__(256) void k_fill_blocks(T *out, int s, int count, uint32_t seed) {
+__global__ __launch_bounds__(256) void k_fill_blocks(T *out, int s, int count, uint32_t seed,
+                                                     double offdiag) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)count * s * s) return;
   const int64_t blk = e / ((int64_t)s * s);
@@ -650,7 +913,8 @@ __global__ __launch_bounds__(256) void k_fill_blocks(T *out, int s, int count, u
   const int i = r > c ? r : c, j = r > c ? c : r;
   uint32_t x = seed ^ (uint32_t)(blk * 2654435761u) ^ (uint32_t)(i * 40503u + j * 2246822519u);
   x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
-  out[e] = (T)((double)x * (2.0 / 4294967296.0) - 1.0);
+  const double v = (double)x * (2.0 / 4294967296.0) - 1.0;
+  out[e] = (T)(i == j ? v : offdiag * v);
 }
 
 template <typename T>
@@ -690,6 +954,10 @@ void projection_variant_info(int precision, int v, int *N, int *NT) {
   *NT = x.NT;
 }
 
+int projection_variant_two_level(int precision, int v) {
+  return (precision == 1 ? kVar32[v] : kVar64[v]).two_level;
+}
+
 int projection_default_variant(int precision, int s) {
   const int n = s + (s & 1);
   const int nv = projection_variant_count(precision);
@@ -706,13 +974,15 @@ int projection_default_variant(int precision, int s) {
 }
 
 hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
-                              hipStream_t st) {
+                              double offdiag, hipStream_t st) {
   const int64_t n = (int64_t)count * s * s;
   const int nb = (int)((n + 255) / 256);
   if (precision == 1)
-    hipLaunchKernelGGL(k_fill_blocks<float>, dim3(nb), dim3(256), 0, st, (float *)out, s, count, seed);
+    hipLaunchKernelGGL(k_fill_blocks<float>, dim3(nb), dim3(256), 0, st, (float *)out, s, count,
+                       seed, offdiag);
   else
-    hipLaunchKernelGGL(k_fill_blocks<double>, dim3(nb), dim3(256), 0, st, (double *)out, s, count, seed);
+    hipLaunchKernelGGL(k_fill_blocks<double>, dim3(nb), dim3(256), 0, st, (double *)out, s,
+                       count, seed, offdiag);
   return hipGetLastError();
 }
 
@@ -731,10 +1001,11 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
                                   const ProjArgs &a, hipStream_t st) {
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
+  const int blk = projection_variant_two_level(precision, variant);
   if (precision == 1)
-    return dispatch<float, MODE_ADMM>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+    return dispatch<float, MODE_ADMM>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr, nullptr,
                                       nullptr, a.max_sweeps, a.tol, st);
-  return dispatch<double, MODE_ADMM>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+  return dispatch<double, MODE_ADMM>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr, nullptr,
                                      nullptr, a.max_sweeps, a.tol, st);
 }
 
@@ -744,11 +1015,12 @@ hipError_t launch_standalone_projection(int dtype, int variant, int count, const
   ProjArgs a{};
   int N, NT;
   projection_variant_info(dtype, variant, &N, &NT);
+  const int blk = projection_variant_two_level(dtype, variant);
   if (dtype == 1)
-    return dispatch<float, MODE_STANDALONE>(N, NT, count, a, nullptr, sizes, offsets,
+    return dispatch<float, MODE_STANDALONE>(N, NT, blk, count, a, nullptr, sizes, offsets,
                                             (const float *)in, (float *)out, nullptr, max_sweeps,
                                             tol, st);
-  return dispatch<double, MODE_STANDALONE>(N, NT, count, a, nullptr, sizes, offsets,
+  return dispatch<double, MODE_STANDALONE>(N, NT, blk, count, a, nullptr, sizes, offsets,
                                            (const double *)in, (double *)out, nullptr,
                                            max_sweeps, tol, st);
 }
@@ -757,9 +1029,10 @@ hipError_t launch_min_eig(int precision, int variant, const int32_t *list, int c
                           const ProjArgs &a, double *lmin_out, hipStream_t st) {
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
+  const int blk = projection_variant_two_level(precision, variant);
   if (precision == 1)
-    return dispatch<float, MODE_MINEIG>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+    return dispatch<float, MODE_MINEIG>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr, nullptr,
                                         lmin_out, a.max_sweeps, a.tol, st);
-  return dispatch<double, MODE_MINEIG>(N, NT, count, a, list, nullptr, nullptr, nullptr, nullptr,
+  return dispatch<double, MODE_MINEIG>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr, nullptr,
                                        lmin_out, a.max_sweeps, a.tol, st);
 }

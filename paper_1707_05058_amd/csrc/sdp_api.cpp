@@ -177,9 +177,12 @@ T *dev_zeros(size_t count, std::vector<void *> &owned) {
 // (precision, size, power-of-two count) for the life of the process.
 // ---------------------------------------------------------------------------
 std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int>, int> g_tune_cache;
+std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
 
-int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol,
+// Times the candidate variants on synthetic blocks: nearly diagonal ones
+// (off-diagonal entries scaled by 1e-3) when the solves are warm-started,
+// which is the matrix such a solve diagonalises, else cold random ones.
+int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol, bool warm,
                  hipStream_t st) {
   const int n = s + (s & 1);
   std::vector<int> cand;
@@ -207,7 +210,7 @@ int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol
   const int test = (int)std::min<int64_t>(count, 4096);
   int lg = 0;
   while ((1 << (lg + 1)) <= test) ++lg;
-  const auto key = std::make_tuple(precision, s, lg);
+  const auto key = std::make_tuple(precision, s, lg, warm ? 1 : 0);
   {
     std::lock_guard<std::mutex> g(g_tune_mutex);
     auto it = g_tune_cache.find(key);
@@ -227,7 +230,8 @@ int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol
     tmp.push_back(out);
     int32_t *d_sizes = dev_upload(sizes, tmp);
     int64_t *d_offs = dev_upload(offs, tmp);
-    HIPCHK(fill_random_blocks(precision, in, s, test, 0x5eedu + (uint32_t)s, st));
+    HIPCHK(fill_random_blocks(precision, in, s, test, 0x5eedu + (uint32_t)s, warm ? 1e-3 : 1.0,
+                              st));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -795,7 +799,8 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       std::map<int, int> var_of_size;
       for (auto &kv : count_of_size)
         var_of_size[kv.first] = opt.autotune ? tune_variant(h->precision, kv.first, kv.second,
-                                                            h->max_sweeps, h->jac_tol, h->stream)
+                                                            h->max_sweeps, h->jac_tol,
+                                                            opt.warm_start != 0, h->stream)
                                              : projection_default_variant(h->precision, kv.first);
       for (int64_t k = 0; k < cl; ++k) {
         const int v = var_of_size[cl_size[k]];
@@ -1337,6 +1342,28 @@ int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_
       if (threads) threads[v] = NT;
     }
     *count = nv;
+    return SDP_OK;
+  });
+}
+
+int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *two_level) {
+  return guarded([&] {
+    if (dtype != SDP_DTYPE_FP64 && dtype != SDP_DTYPE_FP32) fail(SDP_ERR_ARG, "invalid dtype");
+    const int prec = dtype == SDP_DTYPE_FP32 ? 1 : 0;
+    if (!two_level || variant < 0 || variant >= projection_variant_count(prec))
+      fail(SDP_ERR_ARG, "invalid arguments");
+    *two_level = projection_variant_two_level(prec, variant);
+    return SDP_OK;
+  });
+}
+
+int sdp_projection_plan_variants(sdp_handle *h, int32_t cap, int32_t *variant, int32_t *count) {
+  return guarded([&] {
+    if (!h || cap < 0 || !count) fail(SDP_ERR_ARG, "invalid arguments");
+    const int nl = (int)h->bucket_size.size();
+    for (int b = 0; b < nl && b < cap; ++b)
+      if (variant) variant[b] = h->bucket_size[b];
+    *count = nl;
     return SDP_OK;
   });
 }

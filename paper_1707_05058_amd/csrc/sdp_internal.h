@@ -114,9 +114,11 @@ struct ProjArgs {
 // Kernel variants (padded size N, threads NT): ids are per precision.
 int projection_variant_count(int precision);
 void projection_variant_info(int precision, int variant, int *N, int *NT);
+// 1: two-level (block) Jacobi with 16 x 16 pair problems; 0: scalar rounds
+int projection_variant_two_level(int precision, int variant);
 int projection_default_variant(int precision, int s);   // -1 if s is too large
 hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
-                              hipStream_t st);
+                              double offdiag, hipStream_t st);
 // Sets the warm-start bases of cliques [c0, c0 + count) to the identity.
 hipError_t launch_identity_bases(int precision, void *vw, const int64_t *vw_off,
                                  const int32_t *cl_n, int64_t c0, int64_t count, hipStream_t st);

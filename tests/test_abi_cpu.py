@@ -113,3 +113,21 @@ def test_null_handle_is_rejected(sdp):
     assert sdp.lib.sdp_reset(None) == -1
     assert sdp.lib.sdp_admm_step(None, 1, None) == -1
     assert sdp.lib.sdp_get_stats(None, None, None) == -1
+
+
+def test_projection_variant_kinds(sdp):
+    """Every listed variant reports its method; the two-level ones have
+    blocks of at least 64 (16 x 16 pair problems of groups of 8)."""
+    for dt in (sdp.DTYPE_FP32, sdp.DTYPE_FP64):
+        vs = sdp.projection_variants(dt)
+        kinds = [sdp.projection_variant_two_level(dt, v) for v in range(len(vs))]
+        assert any(kinds) and not all(kinds)
+        for (N, NT), k in zip(vs, kinds):
+            if k:
+                assert N >= 64 and N % 16 == 0 and NT >= 64 * (N // 16)
+    import ctypes as C
+    t = C.c_int32(0)
+    assert sdp.lib.sdp_projection_variant_kind(sdp.DTYPE_FP32, -1, C.byref(t)) == -1
+    assert sdp.lib.sdp_projection_variant_kind(sdp.DTYPE_FP32, len(sdp.projection_variants(sdp.DTYPE_FP32)),
+                                               C.byref(t)) == -1
+    assert sdp.lib.sdp_projection_variant_kind(7, 0, C.byref(t)) == -1
