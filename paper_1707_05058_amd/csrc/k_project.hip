@@ -218,10 +218,10 @@ __device__ inline void round_pair(int r, int w, int nb, int &gi, int &gj) {
 // index of entry k (0..15) of a pair made of groups gi, gj
 __device__ inline int pair_index(int gi, int gj, int k) { return k < 8 ? 8 * gi + k : 8 * gj + k - 8; }
 
-// One wave: diagonalise S = A[idx, idx] (idx from groups gi, gj) by the
-// parallel-order Jacobi; Q (16 x 16, row-major, pitch QP: entry (i, slot k))
-// into q, the eigenvalues (by slot) into lam.  sa is scratch of 16 x QP, prm
-// of 16.
+// One wave: diagonalise S = A[idx, idx] (idx from groups gi, gj) by at most
+// max_sweeps sweeps of the parallel-order Jacobi; Q (16 x 16, row-major,
+// pitch QP: entry (i, slot k)) into q, Q^T S Q into sa (16 x QP, also the
+// exchange scratch), its diagonal into lam; prm is scratch of 16.
 template <typename T, int P>
 __device__ void pair_eig16(const T *Abuf, int gi, int gj, T *sa, T *q, T *prm, T *lam,
                            double tol, int max_sweeps) {
@@ -298,10 +298,14 @@ __device__ void pair_eig16(const T *Abuf, int gi, int gj, T *sa, T *q, T *prm, T
     lam[2 * b] = A[0][0];
     lam[2 * b + 1] = A[1][1];
   }
+  // Q, and Q^T S Q itself (diagonal only to the inner tolerance)
 #pragma unroll
   for (int d = 0; d < 2; ++d)
 #pragma unroll
-    for (int e = 0; e < 2; ++e) q[(2 * a0 + d) * QP + 2 * b + e] = V[d][e];
+    for (int e = 0; e < 2; ++e) {
+      q[(2 * a0 + d) * QP + 2 * b + e] = V[d][e];
+      sa[(2 * a0 + d) * QP + 2 * b + e] = A[d][e];
+    }
   wave_lds_sync();
 }
 
@@ -319,7 +323,7 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   T *sa = ws + w * WS, *q = sa + 16 * QP, *prm = q + 16 * QP, *lam = prm + 16;
   const auto wsq = [&](int pw) { return ws + pw * WS + 16 * QP; };        // Q of pair pw
-  const auto wsl = [&](int pw) { return ws + pw * WS + 2 * 16 * QP + 16; }; // lambda of pair pw
+  const auto wss = [&](int pw) { return ws + pw * WS; };                   // Q^T S Q of pair pw
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     double o2 = 0.0;
@@ -343,16 +347,16 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
         round_pair(r, p1, NG, g1i, g1j);
         round_pair(r, p2, NG, g2i, g2j);
         if (p1 == p2) {
-          const T *lm = wsl(p1);
+          const T *sd = wss(p1);
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
             const int i = Mma<T>::row(l, rr), k = l & 15;
-            Abuf[pair_index(g1i, g1j, i) * P + pair_index(g1i, g1j, k)] = (i == k) ? lm[i] : T(0);
+            Abuf[pair_index(g1i, g1j, i) * P + pair_index(g1i, g1j, k)] = sd[i * QP + k];
           }
           continue;
         }
         const T *q1 = wsq(p1), *q2 = wsq(p2);
-        // T = A[P1, P2] Q2 into this wave's sa
+        // T = A[P1, P2] Q2 (in registers: T(row(l, r), l % 16) in acc[r])
         typename Mma<T>::v4 acc = {0, 0, 0, 0};
         const int ia = pair_index(g1i, g1j, l & 15);
 #pragma unroll
@@ -360,17 +364,12 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
           const int k = k0 + (l >> 4);
           acc = Mma<T>::step(Abuf[ia * P + pair_index(g2i, g2j, k)], q2[k * QP + (l & 15)], acc);
         }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) sa[Mma<T>::row(l, rr) * QP + (l & 15)] = acc[rr];
-        wave_lds_sync();
-        // Q1^T T back into A[P1, P2]
+        // Q1^T T straight from those registers: step r sums over the rows
+        // k = row(l, r) that lane l holds, so the b operand is acc[r]
         typename Mma<T>::v4 acc2 = {0, 0, 0, 0};
 #pragma unroll
-        for (int k0 = 0; k0 < 16; k0 += 4) {
-          const int k = k0 + (l >> 4);
-          acc2 = Mma<T>::step(q1[k * QP + (l & 15)], sa[k * QP + (l & 15)], acc2);
-        }
-        wave_lds_sync();
+        for (int r = 0; r < 4; ++r)
+          acc2 = Mma<T>::step(q1[Mma<T>::row(l, r) * QP + (l & 15)], acc[r], acc2);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr)
           Abuf[pair_index(g1i, g1j, Mma<T>::row(l, rr)) * P + pair_index(g2i, g2j, l & 15)] =
@@ -390,7 +389,6 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
             const int k = k0 + (l >> 4);
             acc = Mma<T>::step(Vbuf[row * P + pair_index(gi, gj, k)], qc[k * QP + (l & 15)], acc);
           }
-          wave_lds_sync();
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr)
             Vbuf[(16 * rt + Mma<T>::row(l, rr)) * P + pair_index(gi, gj, l & 15)] = acc[rr];
