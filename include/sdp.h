@@ -125,6 +125,11 @@ typedef struct {
                                    also lifts the m <= 20480 limit of sparse A) */
   double cg_tol;                /* the solve also stops once ||r||_2 <= cg_tol (1 + ||b||_2);
                                    0: always cg_max_iter steps */
+  int32_t projection_method;    /* eigensolver of the clique projections: 0 the autotuner (or,
+                                   with autotune = 0, the default variant) chooses; 1 scalar
+                                   parallel-order Jacobi only; 2 the two-level (block) Jacobi
+                                   wherever a variant for the clique size exists (blocks of
+                                   64 and more), scalar elsewhere */
 } sdp_options;
 
 /* Per-instance result. */

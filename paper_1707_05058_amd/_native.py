@@ -57,7 +57,8 @@ class sdp_options(C.Structure):
                 ("nu", C.c_double), ("rho_period", C.c_int32), ("graph_chunk", C.c_int32),
                 ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
                 ("autotune", C.c_int32), ("warm_start", C.c_int32), ("algorithm", C.c_int32),
-                ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double)]
+                ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
+                ("projection_method", C.c_int32)]
 
 
 class sdp_result(C.Structure):
@@ -165,6 +166,8 @@ def make_options(**kw) -> sdp_options:
             v = {"fp64": FP64, "fp32": FP32_EIG, "fp32_eig": FP32_EIG}[v.lower()]
         elif k == "algorithm" and isinstance(v, str):
             v = {"primal": ALG_PRIMAL, "dual": ALG_DUAL, "hsde": ALG_HSDE}[v.lower()]
+        elif k == "projection_method" and isinstance(v, str):
+            v = {"auto": 0, "scalar": 1, "two_level": 2}[v.lower()]
         setattr(o, k, v)
     return o
 

@@ -182,15 +182,42 @@ std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
 // Times the candidate variants on synthetic blocks: nearly diagonal ones
 // (off-diagonal entries scaled by 1e-3) when the solves are warm-started,
 // which is the matrix such a solve diagonalises, else cold random ones.
-int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol, bool warm,
-                 hipStream_t st) {
+// Variants that hold cliques of size s under projection method `method` (0
+// any, 1 scalar only, 2 two-level when one fits, else scalar).
+std::vector<int> fitting_variants(int precision, int s, int method) {
   const int n = s + (s & 1);
-  std::vector<int> cand;
+  std::vector<int> any, scalar, two;
   for (int v = 0; v < projection_variant_count(precision); ++v) {
     int N, NT;
     projection_variant_info(precision, v, &N, &NT);
-    if (N >= n) cand.push_back(v);
+    if (N < n) continue;
+    any.push_back(v);
+    (projection_variant_two_level(precision, v) ? two : scalar).push_back(v);
   }
+  if (method == 1) return scalar;
+  if (method == 2 && !two.empty()) return two;
+  if (method == 2) return scalar;
+  return any;
+}
+
+// The untuned choice: the first listed variant of the smallest fitting N.
+int default_variant(int precision, int s, int method) {
+  const std::vector<int> c = fitting_variants(precision, s, method);
+  int best = -1, bestN = 1 << 30;
+  for (int v : c) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (N < bestN) {
+      best = v;
+      bestN = N;
+    }
+  }
+  return best;
+}
+
+int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol, bool warm,
+                 int method, hipStream_t st) {
+  std::vector<int> cand = fitting_variants(precision, s, method);
   if (cand.empty()) fail(SDP_ERR_UNSUPPORTED, "clique too large");
   // variants beyond the next-larger block size are never faster
   int nmin = 1 << 30;
@@ -210,7 +237,7 @@ int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol
   const int test = (int)std::min<int64_t>(count, 4096);
   int lg = 0;
   while ((1 << (lg + 1)) <= test) ++lg;
-  const auto key = std::make_tuple(precision, s, lg, warm ? 1 : 0);
+  const auto key = std::make_tuple(precision, s, lg, (warm ? 1 : 0) + 2 * method);
   {
     std::lock_guard<std::mutex> g(g_tune_mutex);
     auto it = g_tune_cache.find(key);
@@ -237,7 +264,7 @@ int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol
     HIPCHK(hipEventCreate(&e1));
     // best of three timings of three launches each; a variant replaces the
     // default only when it is at least 5% faster (keeps the choice stable)
-    const int def = projection_default_variant(precision, s);
+    const int def = default_variant(precision, s, method);
     float def_ms = 1e30f, best_ms = 1e30f;
     for (int v : cand) {
       HIPCHK(launch_standalone_projection(precision, v, test, d_sizes, d_offs, in, out, max_sweeps,
@@ -684,7 +711,8 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
        opt.algorithm != SDP_ALG_HSDE) ||
       (opt.algorithm == SDP_ALG_HSDE && opt.adaptive_rho) ||
       (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
-      opt.graph_chunk < 0 || opt.cg_max_iter < 0 || !(opt.cg_tol >= 0))
+      opt.graph_chunk < 0 || opt.cg_max_iter < 0 || !(opt.cg_tol >= 0) ||
+      opt.projection_method < 0 || opt.projection_method > 2)
     fail(SDP_ERR_ARG, "invalid options");
   if (opt.cg_max_iter > 0 && opt.algorithm != SDP_ALG_PRIMAL)
     fail(SDP_ERR_UNSUPPORTED, "the conjugate-gradient affine step is built for Algorithm 1 only");
@@ -798,10 +826,11 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
       std::map<int, int> var_of_size;
       for (auto &kv : count_of_size)
-        var_of_size[kv.first] = opt.autotune ? tune_variant(h->precision, kv.first, kv.second,
-                                                            h->max_sweeps, h->jac_tol,
-                                                            opt.warm_start != 0, h->stream)
-                                             : projection_default_variant(h->precision, kv.first);
+        var_of_size[kv.first] =
+            opt.autotune ? tune_variant(h->precision, kv.first, kv.second, h->max_sweeps,
+                                        h->jac_tol, opt.warm_start != 0, opt.projection_method,
+                                        h->stream)
+                         : default_variant(h->precision, kv.first, opt.projection_method);
       for (int64_t k = 0; k < cl; ++k) {
         const int v = var_of_size[cl_size[k]];
         auto it = std::find(h->bucket_size.begin(), h->bucket_size.end(), v);
