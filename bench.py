@@ -159,8 +159,8 @@ def load_traffic(workload, stage):
 # projection is the FP32-eig form's ADMM-mode kernel (template mode 0)
 STAGE_KERNELS = {"scatter": (("k_scatter", ""),), "A_v": (("k_rowdot<", ""), ("k_csr_rowdot", "")),
                  "Linv_r": (("k_trmv_wave<0>", ""),), "LinvT_y": (("k_trmv_wave<1>", ""),),
-                 "AT_y": (("k_coldot<0>", ""), ("k_csc_coldot<0>", "")),
-                 "projection": (("k_project<float", ", 0>"),),
+                 "AT_y": (("k_coldot<0,", ""), ("k_csc_coldot<0>", "")),
+                 "projection": (("k_project<float", ", 0, false>"), ("k_project<float", ", 0, true>")),
                  "residual": (("k_residual_reduce", ""),)}
 COPY_CAL_BYTES = 512 << 20
 
