@@ -59,8 +59,19 @@ __device__ inline int xcd_contiguous(int b, int nb) {
   return x * q + min(x, r) + b / 8;
 }
 
+__device__ void residual_block(const AffineArgs &a, int inst);
+
 __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
-  const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if ((int)blockIdx.x < a.res_blocks) {
+    // the previous iteration's residuals, stopping test (fixed penalty);
+    // the `done` read below may see this iteration's update or not: either
+    // way the scatter's outputs are only read by kernels that test it again
+    if ((int)blockIdx.x < a.batch) residual_block(a, blockIdx.x);
+    return;
+  }
+  // res_blocks is a multiple of 8: the XCD of a workgroup is unchanged
+  const int64_t g = (int64_t)xcd_contiguous(blockIdx.x - a.res_blocks, gridDim.x - a.res_blocks) * 256 +
+                    threadIdx.x;
   const int64_t j = g / SC_LANES;
   const int q = (int)(g % SC_LANES);
   if (j >= a.ncoord) return;             // whole lane groups leave together
@@ -298,20 +309,23 @@ __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
 // One workgroup per instance sums its cliques' partials (||X - Hx||^2,
 // ||X||^2, ||Hx||^2, ||X - X_prev||^2, ||Lambda||^2, sweeps) in a fixed
 // order.  The partial loads are issued before the `done` test so that the
-// two memory round trips overlap.
+// two memory round trips overlap.  With a fixed penalty the next iteration's
+// scatter kernel runs these workgroups ahead of its own (k_scatter,
+// res_blocks): the scatter needs only the penalty, and its outputs are
+// scratch that the later kernels of an iteration that has stopped ignore.
 // ---------------------------------------------------------------------------
 __device__ inline double ratio(double num, double den) {
   if (den > 0.0) return num / den;
   return num == 0.0 ? 0.0 : INFINITY;
 }
 
-constexpr int RES_NT = 1024;
+constexpr int RES_NT = 256;
 
-__global__ __launch_bounds__(RES_NT) void k_residual_reduce(AffineArgs a) {
-  const int inst = blockIdx.x;
+__device__ void residual_block(const AffineArgs &a, int inst) {
   InstState &st = a.state[inst];
   const int64_t c0 = a.inst_cl_first[inst], c1 = a.inst_cl_first[inst + 1];
   double s[NPART] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 4
   for (int64_t k = c0 + threadIdx.x; k < c1; k += RES_NT) {
     const double2 *pk = reinterpret_cast<const double2 *>(a.part + NPART * k);
     const double2 q0 = pk[0], q1 = pk[1], q2 = pk[2];
@@ -326,12 +340,14 @@ __global__ __launch_bounds__(RES_NT) void k_residual_reduce(AffineArgs a) {
     if (l == 0) red[w][t] = v;
   }
   __syncthreads();
-  if (w != 0 || done) return;
-  // wave 0 folds the 16 wave sums: lane i < 16 holds wave i's values
+  if (threadIdx.x != 0 || done) return;
   double S[NPART];
 #pragma unroll
-  for (int t = 0; t < NPART; ++t) S[t] = wave_sum(l < RES_NT / 64 ? red[l][t] : 0.0);
-  if (l != 0) return;
+  for (int t = 0; t < NPART; ++t) {
+    S[t] = 0.0;
+#pragma unroll
+    for (int i = 0; i < RES_NT / 64; ++i) S[t] += red[i][t];
+  }
   const double rho = st.rho;
   const double nx = sqrt(S[1]), nhx = sqrt(S[2]);
   const double eps_c = ratio(sqrt(S[0]), nx > nhx ? nx : nhx);
@@ -359,6 +375,10 @@ __global__ __launch_bounds__(RES_NT) void k_residual_reduce(AffineArgs a) {
     else if (eps_l >= P.nu * eps_c) st.rho = rho / P.mu;
   }
   if (it >= P.max_iter) st.done = 2;
+}
+
+__global__ __launch_bounds__(RES_NT) void k_residual_reduce(AffineArgs a) {
+  residual_block(a, blockIdx.x);
 }
 
 // <C, X> = sum_j w_j c_j u_j per instance.
@@ -634,7 +654,7 @@ void launch_dense_coldot(const AffineArgs &a, hipStream_t st) {
 hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
   switch (stage) {
     case 0: {
-      const int nb = (int)((a.ncoord * SC_LANES + 255) / 256);
+      const int nb = (int)((a.ncoord * SC_LANES + 255) / 256) + a.res_blocks;
       hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a);
       break;
     }

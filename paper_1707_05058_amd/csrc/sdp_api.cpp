@@ -410,7 +410,18 @@ void enqueue_projections(sdp_handle *h, const ProjArgs &p, hipStream_t st) {
 // system, v and multiplier updates, residuals.
 void enqueue_hsde_iteration(sdp_handle *h, hipStream_t st);
 
-void enqueue_iteration(sdp_handle *h, hipStream_t st) {
+// Algorithm 1 with a fixed penalty: the scatter kernel of an iteration can
+// also finish the previous one (the penalty it reads cannot change).
+bool can_fold_residual(const sdp_handle *h) {
+  return !h->hsde && !h->proj.dual && !h->opt.adaptive_rho;
+}
+
+// fold_prev: this iteration's scatter kernel also finishes the previous
+// iteration (whose residual kernel was left out); defer: leave this
+// iteration's residual kernel out (the next iteration folds it).  A sequence
+// of iterations is enqueued with fold_prev = (not first), defer = (not last),
+// so the state is complete after it.
+void enqueue_iteration(sdp_handle *h, hipStream_t st, bool fold_prev = false, bool defer = false) {
   if (h->hsde) {
     enqueue_hsde_iteration(h, st);
     return;
@@ -420,11 +431,19 @@ void enqueue_iteration(sdp_handle *h, hipStream_t st) {
     HIPCHK(launch_iteration_affine(h->aff, st));
     HIPCHK(launch_dual_update(h->proj, h->ncl, st));
   } else {
-    if (h->cg) HIPCHK(launch_cg_affine(h->aff, st));
-    else HIPCHK(launch_iteration_affine(h->aff, st));
+    AffineArgs a = h->aff;
+    if (fold_prev) a.res_blocks = (h->B + 7) / 8 * 8;
+    if (h->cg) HIPCHK(launch_cg_affine(a, st));
+    else HIPCHK(launch_iteration_affine(a, st));
     enqueue_projections(h, h->proj, st);
   }
-  HIPCHK(launch_residual_reduce(h->aff, st));
+  if (!defer) HIPCHK(launch_residual_reduce(h->aff, st));
+}
+
+// n iterations, the residual kernels folded into the next scatter where allowed
+void enqueue_sequence(sdp_handle *h, hipStream_t st, int64_t n) {
+  const bool fold = can_fold_residual(h);
+  for (int64_t i = 0; i < n; ++i) enqueue_iteration(h, st, fold && i > 0, fold && i + 1 < n);
 }
 
 // One unrolled iteration (no stopping test); optionally stores (V, theta).
@@ -560,7 +579,7 @@ void build_graph(sdp_handle *h) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   try {
-    for (int i = 0; i < h->opt.graph_chunk; ++i) enqueue_iteration(h, h->cap_stream);
+    enqueue_sequence(h, h->cap_stream, h->opt.graph_chunk);
   } catch (...) {
     hipGraph_t dummy;
     (void)hipStreamEndCapture(h->cap_stream, &dummy);
@@ -581,7 +600,7 @@ void enqueue_steps(sdp_handle *h, int64_t n) {
       n -= h->graph_iters;
     }
   }
-  for (int64_t i = 0; i < n; ++i) enqueue_iteration(h, h->stream);
+  enqueue_sequence(h, h->stream, n);
 }
 
 void pull_state(sdp_handle *h) {

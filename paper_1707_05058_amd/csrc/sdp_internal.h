@@ -185,6 +185,9 @@ struct AffineArgs {
   const double *part;
   const int64_t *inst_cl_first;               // [B+1]
   double *hist;                               // B x hist_cap x 3
+  // k_scatter: number of leading workgroups (a multiple of 8, >= batch, or
+  // 0) that first finish the previous iteration (residuals, stopping test)
+  int32_t res_blocks;
   int batch;
   int ignore_done;                            // diagnostics: run on frozen instances too
   int dual;                                   // Algorithm 2: right-hand sides c - sum(z + lambda/rho), -b/rho

@@ -272,3 +272,40 @@ def test_warm_started_eigensolves_match_cold_and_take_fewer_sweeps(sdp, gpu, ora
         assert rel_err(u, P.u()) <= tol, (warm, rel_err(u, P.u()))
     log(f"sweeps per projection: cold {sweeps[0]:.2f} warm {sweeps[1]:.2f}")
     assert sweeps[1] < 0.8 * sweeps[0]
+
+
+def run_batch(sdp, insts, n, single_steps, **opts):
+    with sdp.Solver(insts, tol=1e-3, max_iter=100000, **opts) as S:
+        if single_steps:
+            for _ in range(n):
+                res = S.step(1)
+        else:
+            res = S.step(n)
+        out = []
+        for i in range(len(insts)):
+            sol = S.solution(i)
+            out.append((res[i]["iters"], res[i]["status"], sol["u"], sol["X_packed"],
+                        sol["L_packed"], np.asarray(S.history(i)[0]), np.asarray(S.history(i)[1])))
+    return out
+
+
+@pytest.mark.parametrize("opts", [dict(graph_chunk=25), dict(graph_chunk=0),
+                                  dict(graph_chunk=25, cg_max_iter=3)])
+def test_folded_residuals_equal_single_steps(sdp, gpu, opts):
+    """With a fixed penalty the scatter kernel of an iteration also finishes
+    the previous one; a sequence of n iterations must equal n separate calls
+    (each a sequence of one, no folding) bit for bit, including instances of
+    a batch that stop at different iterations inside the sequence."""
+    insts = [sdpgen.block_arrow_instance(3, 5, 2, 12, seed=1),
+             sdpgen.block_arrow_instance(5, 8, 3, 40, seed=2),
+             sdpgen.workload_small_blockarrow()]
+    n = 130
+    a = run_batch(sdp, insts, n, False, **opts)
+    b = run_batch(sdp, insts, n, True, **opts)
+    iters = [x[0] for x in a]
+    log(f"folded vs single steps {opts}: iterations {iters}, status {[x[1] for x in a]}")
+    assert len(set(iters)) > 1 and min(iters) < n, "instances should stop at different iterations"
+    for x, y in zip(a, b):
+        assert x[0] == y[0] and x[1] == y[1]
+        for p, q in zip(x[2:], y[2:]):
+            assert np.array_equal(p, q)
