@@ -363,6 +363,14 @@ def time_adjoint(sdp, torch, insts, precision, T, ckpt, stream):
     return out, cb.cpu().numpy(), bb.cpu().numpy()
 
 
+def solver_options(args):
+    """Per-workload solver options plus the command line's."""
+    extra = dict(EXTRA_OPTIONS.get(args.workload, {}))
+    if args.decouple is not None:
+        extra["decouple"] = args.decouple
+    return extra
+
+
 def cpu_baseline(insts, seconds, algorithm="primal", extra=None):
     """The oracle on a bounded sample: the first instances of the workload,
     a few iterations each; the per-iteration time of the whole batch is the
@@ -447,6 +455,9 @@ def main():
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 CSV output directories")
     ap.add_argument("--commands-file", help="text file with the rocprofv3 commands (summaries)")
+    ap.add_argument("--decouple", type=int, choices=(0, 1), default=None,
+                    help="positive/negative decoupling of warm-started projections "
+                         "(default: the library's default)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         cmds = open(args.commands_file).read().strip().splitlines() if args.commands_file else []
@@ -485,11 +496,11 @@ def main():
                                      args.stage_iters, stream,
                                      repeat_solve=args.workload not in ("batched", "large"),
                                      algorithm=args.algorithm,
-                                     extra=EXTRA_OPTIONS.get(args.workload))
+                                     extra=solver_options(args))
         print(f"[bench] {args.workload} {precision}: {forms[precision]['iter_per_s']:.1f} iter/s",
               file=sys.stderr, flush=True)
     head = forms["fp32"]
-    extra = EXTRA_OPTIONS.get(args.workload, {})
+    extra = solver_options(args)
     model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"], args.algorithm,
                               cg_steps=extra.get("cg_max_iter", 0))
     stages = {k: v for k, v in head["stages_ms"].items() if k in model}
@@ -537,7 +548,8 @@ def main():
                    "affine_step": (f"PCG, {extra['cg_max_iter']} steps per iteration"
                                    if extra.get("cg_max_iter") else "cached Cholesky factor"),
                    "n": [i.n for i in insts[:4]], "m": [i.m for i in insts[:4]],
-                   "cliques": n_cl, "pattern_nnz": sum(i.nnz for i in insts)},
+                   "cliques": n_cl, "pattern_nnz": sum(i.nnz for i in insts),
+                   "projection_decoupling": bool(extra.get("decouple", 1))},
         "projections_per_s": head["projections_per_s"],
         "fp32_eig": {k: v for k, v in f32.items() if k != "objectives"},
         "fp64": None if f64 is None else {k: v for k, v in f64.items() if k != "objectives"},

@@ -130,6 +130,21 @@ typedef struct {
                                    parallel-order Jacobi only; 2 the two-level (block) Jacobi
                                    wherever a variant for the clique size exists (blocks of
                                    64 and more), scalar elsewhere */
+  int32_t decouple;             /* 1 (SDP_FP32_EIG with warm_start = 1; blocks padded to 64
+                                   and more; Algorithms 1-3 outside the unrolled iterations):
+                                   a warm-started projection first separates the eigenspaces
+                                   of the positive and the non-positive eigenvalues:
+                                   simultaneous Jacobi rotations of the opposite-sign pairs of
+                                   V^T W V, at most 2 refinements on the matrix cores; when
+                                   the remaining opposite-sign mass is below the sweep
+                                   tolerance and Gershgorin bounds certify both diagonal
+                                   blocks, X is rebuilt from the positive block with no sweep;
+                                   otherwise the Jacobi sweeps continue from the refined basis
+                                   (and the clique skips the attempt for 4 iterations).  The
+                                   result is P+(W) to the sweep tolerance either way.  With
+                                   projection_method = 0 those blocks then take the scalar
+                                   variants (which carry the decoupling).  Ignored for FP64
+                                   and smaller blocks.  0: sweeps only.  Default 1 */
 } sdp_options;
 
 /* Per-instance result. */

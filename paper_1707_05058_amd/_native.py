@@ -58,7 +58,7 @@ class sdp_options(C.Structure):
                 ("stream", _p), ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
                 ("autotune", C.c_int32), ("warm_start", C.c_int32), ("algorithm", C.c_int32),
                 ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
-                ("projection_method", C.c_int32)]
+                ("projection_method", C.c_int32), ("decouple", C.c_int32)]
 
 
 class sdp_result(C.Structure):

@@ -26,7 +26,13 @@
 
 namespace {
 
-enum Mode { MODE_ADMM = 0, MODE_STANDALONE = 1, MODE_MINEIG = 2 };
+// MODE_ADMM_DEC: MODE_ADMM with the positive/negative decoupling compiled in
+// (FP32 scalar variants with N >= DEC_MIN_N; separate instances keep the
+// register use of the others).  For smaller blocks a sweep costs less than
+// the refinements, and FP64's tolerance leaves one Newton-Schulz step too
+// little room (||T||_F <= 3.4e-4).
+enum Mode { MODE_ADMM = 0, MODE_STANDALONE = 1, MODE_MINEIG = 2, MODE_ADMM_DEC = 3 };
+constexpr int DEC_MIN_N = 64;
 
 template <typename T> struct Num;
 template <> struct Num<float> {
@@ -400,6 +406,171 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
   return sweep;
 }
 
+// ---------------------------------------------------------------------------
+// Positive/negative decoupling of a warm-started block (scalar-round
+// variants).  P_+(W) depends only on the split of R^N into the invariant
+// subspaces of the positive and of the non-positive eigenvalues, not on a
+// full diagonalisation.  In the warm-started basis A = V^T W V is nearly
+// diagonal; with P = {i : a_ii > 0} and N the rest, one refinement applies
+// the Jacobi rotations of all opposite-sign pairs (p, q) at once:
+// T(p, q) = tan of the angle that zeroes a_pq in its own 2x2 problem (T skew,
+// |T(p, q)| <= 1; the same-sign pairs are left alone), Q = (I + T)(I - T^T T
+// / 2) (one Newton-Schulz step towards the orthogonal polar factor of I + T),
+// A <- Q^T A Q, V <- V Q, five products on the matrix cores.  Near the
+// decoupled state the opposite-sign mass falls quadratically.  The block is
+// accepted when
+//   * sum over opposite-sign pairs of a_pq^2 <= thr (= tol^2 ||W||_F^2), and
+//   * Gershgorin certifies A_PP >= -eps and A_NN <= eps (eps = sqrt(thr)):
+//     |a_ii| - sum_{j != i, same sign} |a_ij| >= -eps for every i,
+// and then P_+(W) = V [A_PP 0; 0 0] V^T up to O(eps) (P_+ is 1-Lipschitz, so
+// the dropped coupling costs at most sqrt(2) sqrt(thr); the certified blocks
+// add at most eps per eigenvalue).  The refinement is only taken while
+// ||T||_F <= tmax, so that the Newton-Schulz step leaves Q orthogonal to
+// O(||T||^4) below the tolerance.  Returns true when accepted; otherwise A, V
+// are still V^T W V and an orthonormal basis and the sweeps continue.
+// Layout as in k_project's scalar path: A and V in registers (2x2 blocks),
+// LDS blocks with de-interleaved slot columns; Abuf, Vbuf are scratch here.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NT, int P>
+__device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
+                                T (&V)[(N / 2) * (N / 2) / NT][2][2], T *Abuf, T *Vbuf, T *th,
+                                double *red, double thr, double tmax2, int max_ref) {
+  constexpr int K = N / 2;
+  constexpr int BPT = K * K / NT;
+  constexpr int AS = NT / K;
+  const auto ix = [](int r, int c) { return r * P + (c & 1) * K + (c >> 1); };
+  const auto slot = [](int q) { return q < K ? 2 * q : 2 * (q - K) + 1; };
+  const int tid = threadIdx.x, b = tid % K, a0 = tid / K;
+  const double eps = sqrt(thr);
+  for (int ref = 0;; ++ref) {
+    // diagonal (its signs define P and N)
+#pragma unroll
+    for (int j = 0; j < BPT; ++j)
+      if (a0 + AS * j == b) {
+        th[2 * b] = A[j][0][0];
+        th[2 * b + 1] = A[j][1][1];
+      }
+    __syncthreads();
+    // opposite-sign mass; same-sign absolute row sums, per thread into Abuf
+    double o2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int r = 2 * aj + d;
+        const bool pr = th[r] > T(0);
+        double rs = 0.0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int c = 2 * b + e;
+          const double v = (double)A[j][d][e];
+          if (r == c) continue;
+          if (pr != (th[c] > T(0))) o2 += v * v;
+          else rs += fabs(v);
+        }
+        Abuf[r * P + b] = (T)rs;
+      }
+    }
+    o2 = block_sum<NT>(o2, red);   // (its barriers also order the row sums)
+    __syncthreads();
+    double bad = 0.0;
+    for (int r = tid; r < N; r += NT) {
+      double rs = 0.0;
+      for (int k = 0; k < K; ++k) rs += (double)Abuf[r * P + k];
+      if (fabs((double)th[r]) - rs < -eps) bad += 1.0;
+    }
+    bad = block_sum<NT>(bad, red);
+    if (o2 <= thr && bad == 0.0) return true;
+    if (ref >= max_ref) return false;
+    // generator T of the opposite-sign rotations (skew), into Abuf
+    double t2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int r = 2 * aj + d, c = 2 * b + e;
+          T t = T(0);
+          if (r != c && ((th[r] > T(0)) != (th[c] > T(0)))) {
+            T cs, sn;
+            sym_rotation<T>(th[r], th[c], A[j][d][e], cs, sn, t);
+          }
+          t2 += (double)t * (double)t;
+          Abuf[ix(r, c)] = t;
+        }
+    }
+    t2 = block_sum<NT>(t2, red);
+    if (!(t2 <= tmax2)) return false;
+    __syncthreads();
+    // Z = T^T T
+    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
+    __syncthreads();
+    // Q = (I + T)(I - Z / 2): x(k, i) = (I + T)(i, k) = (I - T)(k, i)
+    tile_product<T, N, NT, false>(
+        [&](int k, int q) { return (k == slot(q) ? T(1) : T(0)) - Abuf[k * P + q]; },
+        [&](int k, int q) { return (k == slot(q) ? T(1) : T(0)) - T(0.5) * Vbuf[k * P + q]; },
+        [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
+    // A into Vbuf, then A Q and Q^T (A Q)
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Vbuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e];
+    }
+    __syncthreads();
+    tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
+    __syncthreads();
+    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int r = 2 * aj + d, c = 2 * b + e;
+          A[j][d][e] = T(0.5) * (Vbuf[ix(r, c)] + Vbuf[ix(c, r)]);
+        }
+    }
+    __syncthreads();
+    // V <- V Q: x(k, i) = V(i, k) from V^T in Vbuf
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Vbuf[ix(2 * b + e, 2 * aj + d)] = V[j][d][e];
+    }
+    __syncthreads();
+    tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) V[j][d][e] = Vbuf[ix(2 * aj + d, 2 * b + e)];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int N, int NT, int MODE, bool BLK>
 __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__restrict__ list,
                                                 const int32_t *__restrict__ sizes,
@@ -421,6 +592,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   const auto ix = [](int r, int c) { return BLK ? r * P + c : r * P + (c & 1) * K + (c >> 1); };
   const auto slot = [](int q) { return BLK ? q : (q < K ? 2 * q : 2 * (q - K) + 1); };
   constexpr bool WANT_V = MODE != MODE_MINEIG;
+  constexpr bool ADMM = MODE == MODE_ADMM || MODE == MODE_ADMM_DEC;
+  constexpr bool DEC = MODE == MODE_ADMM_DEC && !BLK;
 
   __shared__ T Abuf[N * P];
   __shared__ T Vbuf[WANT_V ? N * P : 1];
@@ -443,7 +616,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
     cl = list[x8 * q8 + min(x8, r8) + blockIdx.x / 8];
     const int inst = a.cl_inst[cl];
-    if (MODE == MODE_ADMM && a.state[inst].done) return;   // uniform per workgroup
+    if (ADMM && a.state[inst].done) return;   // uniform per workgroup
     s = a.cl_size[cl];
     off = a.cl_off[cl];
     rho = a.state[inst].rho;
@@ -453,6 +626,9 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   const int a0 = tid / K;
   T A[BPT][2][2];
   T V[BPT][2][2];
+  // decoupling: iterations this clique still skips it (loaded early)
+  double dec_skip_left = 0.0;
+  if constexpr (DEC) dec_skip_left = a.part[NPART * (int64_t)cl + 7];
 
   // --- gather W_k = E_k U E_k^T - Lambda_k / rho (or the caller's block) ---
   double f2 = 0.0;
@@ -472,16 +648,16 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
             const int ii = i > k ? i : k, kk = i > k ? k : i;
             const int64_t g = off + (int64_t)ii * (ii + 1) / 2 + kk;
             double wd;
-            if (MODE == MODE_ADMM && a.hsde) {
+            if (ADMM && a.hsde) {
               // u_hat_s - v_z
               const double hx = a.h_sx[a.blk_loc[g]];
               const double ss = 0.5 * (a.h_ns[g] - a.h_nt[g] + hx);
               wd = ss - a.hs[a.cl_inst[cl]].f * a.h_mzs[g] - a.Lam[g];
-            } else if (MODE == MODE_ADMM && a.dual) {
+            } else if (ADMM && a.dual) {
               wd = a.Vd[g] - a.Lam[g] / rho;                 // v_k - lambda_k / rho
             } else {
               wd = a.u[a.blk_loc[g]];
-              if (MODE == MODE_ADMM) wd -= a.Lam[g] / rho;   // H_k x - lambda_k / rho
+              if (ADMM) wd -= a.Lam[g] / rho;   // H_k x - lambda_k / rho
               if (MODE == MODE_MINEIG && a.dual) wd *= -rho; // primal estimate -rho x
             }
             w = (T)wd;
@@ -500,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   // it is stored), so A has the eigenvalues of W and is nearly diagonal once
   // the iteration settles: one or two sweeps instead of five or more. ---
   T *vw = nullptr;
-  if (MODE == MODE_ADMM && a.vw) {
+  if (ADMM && a.vw) {
     vw = reinterpret_cast<T *>(a.vw) + a.vw_off[cl];
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -535,6 +711,25 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     }
   }
 
+  // positive/negative decoupling instead of sweeps (warm-started ADMM blocks
+  // whose eigenvectors are not recorded); after a failed attempt the clique
+  // skips it for dec_skip iterations (counter in its partial-sum slot 7)
+  bool dec = false;
+  if constexpr (DEC) {
+    if (vw && !a.eig) {
+      double *flag = a.part + NPART * (int64_t)cl + 7;
+      const double skip = dec_skip_left;
+      __syncthreads();   // every thread has read the counter before it changes
+      if (skip > 0.0) {
+        if (tid == 0) *flag = skip - 1.0;
+      } else {
+        dec = decouple_blocks<T, N, NT, P>(A, V, Abuf, Vbuf, th, red, thr, a.dec_tmax2,
+                                           a.dec_max_ref);
+        if (tid == 0) *flag = dec ? 0.0 : (double)a.dec_skip;
+      }
+    }
+  }
+
   int sweep = 0;
   if constexpr (BLK) {
 #pragma unroll
@@ -561,7 +756,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
           if (WANT_V) V[j][d][e] = Vbuf[ix(2 * aj + d, 2 * b + e)];
     }
   }
-  for (; !BLK && sweep < max_sweeps; ++sweep) {
+  for (; !BLK && !dec && sweep < max_sweeps; ++sweep) {
     double o2 = 0.0;
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -681,7 +876,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   __syncthreads();
   // the Gram matrix V^T V of the Newton-Schulz step reads V by rows; the
   // products after it read V^T, written over V from the registers
-  if (MODE == MODE_ADMM && vw) {
+  if (ADMM && vw) {
     tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
                                   [&](int k, int q) { return Vbuf[k * P + q]; },
                                   [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
@@ -695,7 +890,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       for (int e = 0; e < 2; ++e) Vbuf[ix(2 * b + e, 2 * aj + d)] = V[j][d][e];
   }
   __syncthreads();
-  if (MODE == MODE_ADMM && vw) {
+  if (ADMM && vw) {
     // store the basis for the next iteration after one Newton-Schulz step,
     // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality:
     // (V G)(i, j) = sum_k V^T(k, i) G(k, j), V(i, j) = V^T(j, i)
@@ -706,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
           vw[(int64_t)slot(qi) * N + slot(qj)] = T(1.5) * Vbuf[slot(qj) * P + qi] - T(0.5) * v;
         });
   }
-  if (MODE == MODE_ADMM && a.eig) {
+  if (ADMM && a.eig) {
     // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep
     T *eo = reinterpret_cast<T *>(a.eig) + a.eig_off[cl];
     for (int e = tid; e < s * N; e += NT) eo[e] = Vbuf[ix(e % N, e / N)];
@@ -715,13 +910,40 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 
   // --- rebuild X = V diag(theta+) V^T = sum_k V^T(k, i) theta+_k V^T(k, j):
   // tiles on or below the diagonal, each result stored at (i, j) and (j, i);
-  // then the epilogue over the packed lower triangle ---
-  tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q] * thp[k]; },
-                               [&](int k, int q) { return Vbuf[k * P + q]; },
-                               [&](int qi, int qj, T v) {
-                                 Abuf[slot(qi) * P + qj] = v;
-                                 Abuf[slot(qj) * P + qi] = v;
-                               });
+  // after a decoupling X = V M V^T with M = A on the positive slots, zero
+  // elsewhere (Y = M V^T first; Abuf is free once the Newton-Schulz product
+  // has passed its barrier); then the epilogue over the packed lower triangle ---
+  if (!BLK && dec) {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int r = 2 * aj + d, c = 2 * b + e;
+          Abuf[ix(r, c)] = (th[r] > T(0) && th[c] > T(0)) ? A[j][d][e] : T(0);
+        }
+    }
+    __syncthreads();
+    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
+                                  [&](int k, int q) { return Vbuf[k * P + q]; },
+                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
+    __syncthreads();
+    tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                 [&](int k, int q) { return Abuf[k * P + q]; },
+                                 [&](int qi, int qj, T v) {
+                                   Abuf[slot(qi) * P + qj] = v;
+                                   Abuf[slot(qj) * P + qi] = v;
+                                 });
+  } else {
+    tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q] * thp[k]; },
+                                 [&](int k, int q) { return Vbuf[k * P + q]; },
+                                 [&](int qi, int qj, T v) {
+                                   Abuf[slot(qi) * P + qj] = v;
+                                   Abuf[slot(qj) * P + qi] = v;
+                                 });
+  }
   __syncthreads();
   const int npk = s * (s + 1) / 2;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
@@ -780,7 +1002,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       p4 += wt * ln * ln;
     }
   }
-  if (MODE == MODE_ADMM) {
+  if (ADMM) {
     p0 = block_sum<NT>(p0, red);
     p1 = block_sum<NT>(p1, red);
     p2 = block_sum<NT>(p2, red);
@@ -871,8 +1093,11 @@ hipError_t dispatch(int N, int NT, int blk, int count, ProjArgs a, const int32_t
                     double *lmin, int msw, double tol, hipStream_t st) {
 #define SDP_VARIANT(n, nt, bl)                                                                 \
   if (N == n && NT == nt && blk == bl)                                                         \
-    return launch_one<T, n, nt, MODE, bl>(count, a, list, sizes, offsets, in, out, lmin, msw,  \
-                                          tol, st);
+    return launch_one<T, n, nt,                                                                \
+                      (MODE == MODE_ADMM_DEC && (bl || n < DEC_MIN_N || sizeof(T) == 8))       \
+                          ? MODE_ADMM                                                          \
+                          : MODE,                                                              \
+                      bl>(count, a, list, sizes, offsets, in, out, lmin, msw, tol, st);
   SDP_VARIANT(16, 64, 0)
   SDP_VARIANT(32, 64, 0)
   SDP_VARIANT(32, 128, 0)
@@ -1000,6 +1225,13 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
   const int blk = projection_variant_two_level(precision, variant);
+  if (a.decouple && a.vw && !a.eig) {
+    if (precision == 1)
+      return dispatch<float, MODE_ADMM_DEC>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr,
+                                            nullptr, nullptr, a.max_sweeps, a.tol, st);
+    return dispatch<double, MODE_ADMM_DEC>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr,
+                                           nullptr, nullptr, a.max_sweeps, a.tol, st);
+  }
   if (precision == 1)
     return dispatch<float, MODE_ADMM>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr, nullptr,
                                       nullptr, a.max_sweeps, a.tol, st);

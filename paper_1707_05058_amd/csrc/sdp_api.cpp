@@ -731,7 +731,8 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       (opt.algorithm == SDP_ALG_HSDE && opt.adaptive_rho) ||
       (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
       opt.graph_chunk < 0 || opt.cg_max_iter < 0 || !(opt.cg_tol >= 0) ||
-      opt.projection_method < 0 || opt.projection_method > 2)
+      opt.projection_method < 0 || opt.projection_method > 2 || opt.decouple < 0 ||
+      opt.decouple > 1)
     fail(SDP_ERR_ARG, "invalid options");
   if (opt.cg_max_iter > 0 && opt.algorithm != SDP_ALG_PRIMAL)
     fail(SDP_ERR_UNSUPPORTED, "the conjugate-gradient affine step is built for Algorithm 1 only");
@@ -844,12 +845,17 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       std::map<int, int64_t> count_of_size;
       for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
       std::map<int, int> var_of_size;
+      // with the decoupling (FP32, warm start) the large blocks take the
+      // scalar variants, which carry it
+      const int method = (opt.decouple && opt.warm_start && h->precision == SDP_FP32_EIG &&
+                          opt.projection_method == 0)
+                             ? 1
+                             : opt.projection_method;
       for (auto &kv : count_of_size)
         var_of_size[kv.first] =
             opt.autotune ? tune_variant(h->precision, kv.first, kv.second, h->max_sweeps,
-                                        h->jac_tol, opt.warm_start != 0, opt.projection_method,
-                                        h->stream)
-                         : default_variant(h->precision, kv.first, opt.projection_method);
+                                        h->jac_tol, opt.warm_start != 0, method, h->stream)
+                         : default_variant(h->precision, kv.first, method);
       for (int64_t k = 0; k < cl; ++k) {
         const int v = var_of_size[cl_size[k]];
         auto it = std::find(h->bucket_size.begin(), h->bucket_size.end(), v);
@@ -1060,6 +1066,12 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     p.state = h->d_state;
     p.max_sweeps = h->max_sweeps;
     p.tol = h->jac_tol;
+    p.decouple = opt.decouple && h->precision == SDP_FP32_EIG;
+    p.dec_max_ref = h->precision == SDP_FP32_EIG ? 2 : 3;
+    p.dec_skip = 4;
+    // one Newton-Schulz step leaves Q^T Q - I = -(3/4) Z^2 + Z^3 / 4 with
+    // ||Z||_F <= ||T||_F^2: keep that below the sweep tolerance
+    p.dec_tmax2 = std::sqrt(h->jac_tol / 0.75);
     p.dual = a.dual = opt.algorithm == SDP_ALG_DUAL ? 1 : 0;
     if (p.dual) {
       p.Vd = dev_zeros<double>(pk, own);
@@ -1276,6 +1288,7 @@ void sdp_default_options(sdp_options *opt) {
   opt->autotune = 1;
   opt->warm_start = 1;
   opt->algorithm = SDP_ALG_PRIMAL;
+  opt->decouple = 1;
 }
 
 int sdp_setup(int32_t batch, const sdp_instance *inst, const sdp_options *opt, sdp_handle **out) {

@@ -93,6 +93,11 @@ struct ProjArgs {
   const InstState *state;
   int max_sweeps;
   double tol;
+  // positive/negative decoupling of warm-started blocks: on/off, refinements
+  // per attempt, iterations a clique skips it after a failed attempt, bound
+  // on ||T||_F^2 for one Newton-Schulz step
+  int decouple, dec_max_ref, dec_skip;
+  double dec_tmax2;
   void *eig;              // optional: per clique V (s x N) then theta (N), precision T
   const int64_t *eig_off; // element offset of each clique's record in eig
   void *vw;               // optional: per clique N x N eigenvector basis (warm start), T
