@@ -622,6 +622,37 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     rho = a.state[inst].rho;
   }
 
+  // small variants: the loads of the warm-start basis and of the epilogue's
+  // old X, Lambda and H_k x are issued here, so that their latency overlaps
+  // the gather and the sweeps instead of adding to the chain after them
+  constexpr int VPT = N * N / NT;                       // basis entries per thread
+  constexpr int EPT = (N * (N + 1) / 2 + NT - 1) / NT;  // packed entries per thread
+  constexpr bool PRE = ADMM && VPT <= 4 && EPT <= 4;
+  static_assert(!PRE || (N * N) % NT == 0, "whole basis rows per thread");
+  T pre_v[PRE ? VPT : 1];
+  double pre_x[PRE ? EPT : 1], pre_l[PRE ? EPT : 1], pre_u[PRE ? EPT : 1];
+  if constexpr (PRE) {
+    if (a.vw) {
+      const T *vp = reinterpret_cast<const T *>(a.vw) + a.vw_off[cl];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) pre_v[i] = vp[tid + NT * i];
+    }
+    if (!a.hsde && !a.dual) {
+      const int npk0 = s * (s + 1) / 2;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + NT * i;
+        pre_x[i] = pre_l[i] = pre_u[i] = 0.0;
+        if (e < npk0) {
+          const int64_t g = off + e;
+          pre_x[i] = a.X[g];
+          pre_l[i] = a.Lam[g];
+          pre_u[i] = a.u[a.blk_loc[g]];
+        }
+      }
+    }
+  }
+
   const int b = tid % K;
   const int a0 = tid / K;
   T A[BPT][2][2];
@@ -686,7 +717,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
         for (int e = 0; e < 2; ++e) Abuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e];
     }
-    for (int e = tid; e < N * N; e += NT) Vbuf[ix(e / N, e % N)] = vw[e];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int e = tid + NT * i;
+        Vbuf[ix(e / N, e % N)] = pre_v[i];
+      }
+    } else {
+      for (int e = tid; e < N * N; e += NT) Vbuf[ix(e / N, e % N)] = vw[e];
+    }
     __syncthreads();
     // W V0 (W is symmetric: W(i, k) = W(k, i)), then V0^T (W V0), both into Abuf
     tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
@@ -947,7 +986,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   __syncthreads();
   const int npk = s * (s + 1) / 2;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
-  for (int e = tid; e < npk; e += NT) {
+  // packed entry e (the it-th of this thread)
+  auto epilogue = [&](int e, int it) {
     int i, j;
     tri_inv(e, i, j);
     const T acc = Abuf[ix(i, j)];
@@ -987,8 +1027,16 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       p3 += wt * (zn - zo) * (zn - zo);
     } else {
       const int64_t g = off + e;
-      const double hu = a.u[a.blk_loc[g]];
-      const double xo = a.X[g], lo = a.Lam[g];
+      double hu, xo, lo;
+      if constexpr (PRE) {
+        hu = pre_u[it];
+        xo = pre_x[it];
+        lo = pre_l[it];
+      } else {
+        hu = a.u[a.blk_loc[g]];
+        xo = a.X[g];
+        lo = a.Lam[g];
+      }
       const double xn = (double)acc;
       const double ln = lo + rho * (xn - hu);
       a.X[g] = xn;
@@ -1001,6 +1049,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       p3 += wt * dx * dx;
       p4 += wt * ln * ln;
     }
+  };
+  if constexpr (PRE) {
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+      const int e = tid + NT * it;
+      if (e < npk) epilogue(e, it);
+    }
+  } else {
+    for (int e = tid; e < npk; e += NT) epilogue(e, 0);
   }
   if (ADMM) {
     p0 = block_sum<NT>(p0, red);
