@@ -20,6 +20,7 @@ a bounded sample of the same workload on the host cores.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -571,6 +572,18 @@ def main():
 PROJ_SIZES = (15, 16, 24, 32, 50, 64, 96, 128)
 
 
+def sign_products(prec, N):
+    """Matrix-core flops of one sign-function projection of a padded N x N
+    block: k1 = ceil(log(1/tol) / log 3) steps of three products, k2 of two,
+    one final product; each product computes the TN (TN + 1) / 2 tiles on or
+    below the diagonal, 2 N 16^2 flops per tile."""
+    tol = 1e-6 if prec == "fp32" else 1e-14
+    k1 = max(4, math.ceil(math.log(1.0 / tol) / math.log(3.0)))
+    k2 = 3 if prec == "fp32" else 4
+    tn = N // 16
+    return (3 * k1 + 2 * k2 + 1) * tn * (tn + 1) // 2 * 2 * N * 16 * 16
+
+
 def run_projection(args, sdp, torch, stream):
     """Kernel-only rate of the batched projection: `count` blocks of one size
     per launch, every kernel variant that fits (the default and the fastest
@@ -595,6 +608,7 @@ def run_projection(args, sdp, torch, stream):
             sizes = torch.full((count,), s, dtype=torch.int32, device=dev)
             offs = torch.arange(count, dtype=torch.int64, device=dev) * (s * s)
             n_fit = min(n for n, _ in variants if n >= s + (s & 1))
+            kinds = [sdp.projection_variant_kind(dtc, v) for v in range(len(variants))]
             times = {}
             for v, (N, NT) in enumerate(variants):
                 if N < s + (s & 1) or N > 2 * n_fit:
@@ -610,19 +624,35 @@ def run_projection(args, sdp, torch, stream):
                                                 variant=v)
                     e1.record(stream)
                     e1.synchronize()
-                times[(N, NT)] = e0.elapsed_time(e1) / steps
-            (bn, bt), bms = min(times.items(), key=lambda kv: kv[1])
-            dn = [k for k in times if k[0] == n_fit][0]
+                times[v] = e0.elapsed_time(e1) / steps
+            kind_name = {0: "jacobi", 1: "two-level", 2: "sign"}
+
+            def vname(v):
+                return f"{variants[v][0]}x{variants[v][1]}-{kind_name[kinds[v]]}"
+            bv, bms = min(times.items(), key=lambda kv: kv[1])
+            # the library's default: the first listed sign-function variant of the
+            # smallest N (else the first Jacobi one)
+            dv = ([v for v in times if variants[v][0] == n_fit and kinds[v] == 2]
+                  or [v for v in times if variants[v][0] == n_fit and kinds[v] == 0])[0]
             model = 10.0 * s ** 3 * count
+            executed = None
+            if kinds[bv] == 2:
+                executed = sign_products(prec, variants[bv][0]) * count / (bms / 1e3) / 1e12
             res[f"{prec}_s{s}"] = dict(
-                s=s, blocks=count, best_variant=dict(N=bn, threads=bt), ms_per_launch=bms,
-                projections_per_s=count / (bms / 1e3),
+                s=s, blocks=count,
+                best_variant=dict(N=variants[bv][0], threads=variants[bv][1],
+                                  method=kind_name[kinds[bv]]),
+                ms_per_launch=bms, projections_per_s=count / (bms / 1e3),
                 model_tflops=model / (bms / 1e3) / 1e12,
                 model_frac_of_peak=model / (bms / 1e3) / 1e12 / peak,
-                default_variant=dict(N=dn[0], threads=dn[1]), default_ms=times[dn],
-                all_variants_ms={f"{k[0]}x{k[1]}": t for k, t in sorted(times.items())})
+                default_variant=dict(N=variants[dv][0], threads=variants[dv][1],
+                                     method=kind_name[kinds[dv]]),
+                default_ms=times[dv],
+                executed_matrix_tflops=executed,
+                executed_frac_of_peak=None if executed is None else executed / peak,
+                all_variants_ms={vname(v): t for v, t in sorted(times.items())})
             print(f"[bench] projection {prec} s={s}: {count / (bms / 1e3):.3e} proj/s "
-                  f"({bn}x{bt}, {bms:.3f} ms)", file=sys.stderr, flush=True)
+                  f"({vname(bv)}, {bms:.3f} ms)", file=sys.stderr, flush=True)
             del t_in, t_out
     head = res["fp32_s16"]
     cpu = None
@@ -645,11 +675,20 @@ def run_projection(args, sdp, torch, stream):
         "data": "synthetic",
         "config": {"workload": WORKLOADS["projection"], "headline": "FP32, s = 16"},
         "sizes": res,
-        "roofline": {"kernel": "k_project (standalone)", "bound": "alu",
+        "roofline": {"kernel": ("k_project_sign" if head["best_variant"]["method"] == "sign"
+                                else "k_project") + f" (N = {head['best_variant']['N']}, "
+                               f"{head['best_variant']['threads']} threads, standalone)",
+                     "bound": "mfma" if head["best_variant"]["method"] == "sign" else "alu",
                      "achieved": head["model_tflops"], "peak": FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": head["model_frac_of_peak"], "traffic": None,
                      "model": "10 s^3 per block (symmetric eigensolve with vectors 9 s^3, "
-                              "rebuild s^3)"},
+                              "rebuild s^3)",
+                     "executed": head["executed_matrix_tflops"],
+                     "executed_frac": head["executed_frac_of_peak"],
+                     "executed_model": "sign method: (3 k1 + 2 k2 + 1) products of the padded "
+                                       "N x N block, tiles on or below the diagonal only "
+                                       "(TN (TN + 1) / 2 of TN^2 16 x 16 tiles, TN = N / 16), "
+                                       "2 N 16^2 flops per tile; FP32 matrix peak"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

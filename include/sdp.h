@@ -202,7 +202,11 @@ int sdp_solve(sdp_handle *h, sdp_result *res);
  * sizes (int32[count]) and offsets (int64[count], element offsets of each
  * full s x s row-major block) are DEVICE pointers; in/out are device buffers
  * of `dtype`; every size must be <= max_size <= 128 (96 for FP64).  Blocks
- * must not overlap between in and out.  Asynchronous on `stream`. */
+ * must not overlap between in and out.  Asynchronous on `stream`.  Runs the
+ * sign-function variant (sdp_projection_variant_kind = 2) of the smallest
+ * block size that holds max_size: the same projection to the tolerance of
+ * the Jacobi variants (1e-6 ||W||_F in FP32, 1e-14 in FP64), which
+ * sdp_psd_project_variant still selects. */
 int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *sizes,
                             const int64_t *offsets, const void *in, void *out,
                             int32_t dtype, void *stream);
@@ -213,16 +217,24 @@ int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *size
 int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_t *threads,
                             int32_t *count);
 
-/* Whether kernel variant `variant` of `dtype` runs the two-level (block)
- * Jacobi method (*two_level = 1: groups of 8 indices paired round-robin, each
- * pair's 16 x 16 problem diagonalised by one wave and applied to the block on
- * the matrix cores) or the scalar parallel-order one (0).  Host only. */
-int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *two_level);
+/* The method of kernel variant `variant` of `dtype` (host only):
+ *   *kind = 0  scalar parallel-order Jacobi;
+ *   *kind = 1  two-level (block) Jacobi: groups of 8 indices paired
+ *              round-robin, each pair's 16 x 16 problem diagonalised by one
+ *              wave and applied to the block on the matrix cores;
+ *   *kind = 2  matrix sign function, P+(W) = (W + W sign(W)) / 2, sign(W) by
+ *              polynomial Newton-Schulz iterations on the matrix cores
+ *              (ceil(log(1/tol) / log 3) steps of X (3I - 3.2X^2 + 1.2X^4), then
+ *              3 (FP32) or 4 (FP64) of X (3I - X^2) / 2).  It yields no
+ *              eigenvectors, so only sdp_psd_project_variant runs it; the
+ *              solver's plans hold kinds 0 and 1 only. */
+int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *kind);
 
 /* sdp_psd_project_batched with an explicit kernel variant (an index into the
  * list of sdp_projection_variants); max_size must not exceed that variant's
- * N.  The result is the same projection; the variants differ in how the work
- * is spread over the workgroup. */
+ * N.  The result is the same projection (to the tolerance); the variants
+ * differ in the method (sdp_projection_variant_kind) and in how the work is
+ * spread over the workgroup. */
 int sdp_psd_project_variant(int32_t variant, int32_t count, int32_t max_size,
                             const int32_t *sizes, const int64_t *offsets, const void *in,
                             void *out, int32_t dtype, void *stream);

@@ -414,11 +414,16 @@ def psd_project_batched(sizes, offsets, inp, out, max_size: int, stream=None,
         _check(lib.sdp_psd_project_variant(int(variant), *args))
 
 
-def projection_variant_two_level(dtype: int, variant: int) -> bool:
-    """Whether the variant runs the two-level (block) Jacobi method."""
+def projection_variant_kind(dtype: int, variant: int) -> int:
+    """0 scalar Jacobi, 1 two-level Jacobi, 2 sign function (standalone only)."""
     t = C.c_int32(0)
     _check(lib.sdp_projection_variant_kind(int(dtype), int(variant), C.byref(t)))
-    return bool(t.value)
+    return t.value
+
+
+def projection_variant_two_level(dtype: int, variant: int) -> bool:
+    """Whether the variant runs the two-level (block) Jacobi method."""
+    return projection_variant_kind(dtype, variant) == 1
 
 
 def projection_variants(dtype: int):

@@ -24,6 +24,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <cmath>
+
 namespace {
 
 // MODE_ADMM_DEC: MODE_ADMM with the positive/negative decoupling compiled in
@@ -1078,6 +1081,125 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Standalone projection by the matrix sign function (no eigenvectors):
+// P+(W) = (W + W sign(W)) / 2.  sign(W) is the limit of polynomial
+// iterations on X0 = W / ||W||_F (all eigenvalues in [-1, 1]):
+//   k1 steps  X <- X (3 I - 3.2 X^2 + 1.2 X^4)  (p(x) = 3x - 3.2x^3 + 1.2x^5:
+//             slope 3 at 0, fixed point 1 with |p'(1)| = 0.6, p([0,1]) within
+//             [0, 1.21], inside the basin of the next phase)
+//   k2 steps  X <- X (3 I - X^2) / 2            (quadratic convergence to +-1)
+// An eigenvalue with |lambda| >= 3^-k1 ||W||_F reaches +-1; a smaller one
+// contributes at most |lambda| to P+ either way, so k1 = ceil(log(1/tol) /
+// log 3) keeps the result within the tolerance of the Jacobi variants.  Each
+// product is a polynomial in W, symmetric in exact arithmetic: only the tiles
+// on or below the diagonal are computed, and only the lanes on or below the
+// diagonal store (both triangles), so every iterate is exactly symmetric.
+// The products run on the matrix cores from two N x N LDS buffers (natural
+// layout, pitch 16 mod 32 for FP32 and N + 1 for FP64).
+// ---------------------------------------------------------------------------
+template <typename T>
+__host__ __device__ constexpr int sign_pitch(int N) {
+  if (sizeof(T) == 8) return N + 1;
+  int p = N;
+  while (p % 32 != 16) ++p;
+  return p;
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_project_sign(const int32_t *__restrict__ sizes,
+                                                     const int64_t *__restrict__ offsets,
+                                                     const T *__restrict__ in, T *__restrict__ out,
+                                                     int k1, int k2) {
+  constexpr int P = sign_pitch<T>(N);
+  constexpr int VPT = N * N / NT;
+  static_assert((N * N) % NT == 0, "whole entries per thread");
+  __shared__ T X[N * P];
+  __shared__ T Y[N * P];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int s = sizes[blockIdx.x];
+  const int64_t off = offsets[blockIdx.x];
+  if (s <= 0 || s > N) return;   // sizes beyond max_size are left untouched
+  // W (symmetrised, zero-padded): entry e = tid + NT i is (e / N, e % N)
+  T w[VPT];
+  double f2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int e = tid + NT * i, r = e / N, c = e % N;
+    T v = T(0);
+    if (r < s && c < s) v = T(0.5) * (in[off + (int64_t)r * s + c] + in[off + (int64_t)c * s + r]);
+    w[i] = v;
+    f2 += (double)v * (double)v;
+  }
+  f2 = block_sum<NT>(f2, red);
+  if (!(f2 > 0.0)) {   // W = 0
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int e = tid + NT * i, r = e / N, c = e % N;
+      if (r < s && c < s) out[off + (int64_t)r * s + c] = T(0);
+    }
+    return;
+  }
+  const T scale = (T)(1.0 / sqrt(f2));
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int e = tid + NT * i;
+    X[(e / N) * P + e % N] = w[i] * scale;
+  }
+  __syncthreads();
+  const auto eye = [](int k, int q) { return k == q ? T(1) : T(0); };
+  const auto sym_x = [&](int qi, int qj, T v) {
+    if (qi >= qj) {
+      X[qi * P + qj] = v;
+      X[qj * P + qi] = v;
+    }
+  };
+  const auto sym_y = [&](int qi, int qj, T v) {
+    if (qi >= qj) {
+      Y[qi * P + qj] = v;
+      Y[qj * P + qi] = v;
+    }
+  };
+  for (int it = 0; it < k1 + k2; ++it) {
+    // Y = X^2
+    tile_product<T, N, NT, true>([&](int k, int q) { return X[k * P + q]; },
+                                 [&](int k, int q) { return X[k * P + q]; }, sym_y);
+    __syncthreads();
+    if (it < k1) {
+      // Y = X^2 (-3.2 I + 1.2 X^2), then X = X (3 I + Y)
+      tile_product<T, N, NT, true>(
+          [&](int k, int q) { return Y[k * P + q]; },
+          [&](int k, int q) { return T(-3.2) * eye(k, q) + T(1.2) * Y[k * P + q]; }, sym_y);
+      __syncthreads();
+      tile_product<T, N, NT, true>([&](int k, int q) { return X[k * P + q]; },
+                                   [&](int k, int q) { return T(3) * eye(k, q) + Y[k * P + q]; },
+                                   sym_x);
+    } else {
+      // X = X (1.5 I - 0.5 X^2)
+      tile_product<T, N, NT, true>(
+          [&](int k, int q) { return X[k * P + q]; },
+          [&](int k, int q) { return T(1.5) * eye(k, q) - T(0.5) * Y[k * P + q]; }, sym_x);
+    }
+    __syncthreads();
+  }
+  // C = W S (W into Y), then P+(W) = (W + C) / 2
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int e = tid + NT * i;
+    Y[(e / N) * P + e % N] = w[i];
+  }
+  __syncthreads();
+  tile_product<T, N, NT, true>([&](int k, int q) { return Y[k * P + q]; },
+                               [&](int k, int q) { return X[k * P + q]; }, sym_x);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int e = tid + NT * i, r = e / N, c = e % N;
+    if (r < s && c < s) out[off + (int64_t)r * s + c] = T(0.5) * (w[i] + X[r * P + c]);
+  }
+}
+
 // Algorithm 2, after the affine step: v_k and lambda_k on the packed lower
 // triangle of every clique, one workgroup per clique, with the partial sums
 // of DualConsensusResidual (full Frobenius norms: off-diagonal entries count
@@ -1128,19 +1250,25 @@ hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t 
   return hipGetLastError();
 }
 
-// Kernel variants: padded block size N and threads per workgroup NT.  Each
-// thread owns K*K/NT 2x2 blocks (K = N/2).  The autotuner picks, per clique
-// size, the variant that runs fastest; without it the smallest N and the
-// first NT listed for that N are used.
-struct Variant { int N, NT, two_level; };
+// Kernel variants: padded block size N, threads per workgroup NT and kind
+// (0 scalar Jacobi: each thread owns K*K/NT 2x2 blocks, K = N/2; 1 two-level
+// Jacobi; 2 sign function, standalone projections only: it yields no
+// eigenvectors).  The autotuner picks, per clique size, the Jacobi variant
+// that runs fastest; without it the smallest N and the first NT listed for
+// that N are used.
+struct Variant { int N, NT, kind; };
 constexpr Variant kVar32[] = {
     {16, 64, 0},   {32, 64, 0},    {32, 128, 0},  {32, 256, 0}, {48, 192, 0},
     {64, 256, 0},  {64, 128, 0},   {64, 512, 0},  {80, 320, 0}, {96, 576, 0},
     {112, 448, 0}, {128, 1024, 0}, {128, 512, 0}, {64, 256, 1}, {80, 320, 1},
-    {96, 384, 1},  {112, 448, 1},  {128, 512, 1}};
+    {96, 384, 1},  {112, 448, 1},  {128, 512, 1}, {16, 64, 2},  {32, 256, 2},
+    {32, 64, 2},   {48, 192, 2},   {64, 256, 2},  {80, 320, 2}, {96, 384, 2},
+    {112, 448, 2}, {128, 512, 2}};
 constexpr Variant kVar64[] = {{16, 64, 0},  {32, 64, 0},  {32, 128, 0}, {32, 256, 0},
                               {48, 192, 0}, {64, 256, 0}, {64, 128, 0}, {64, 512, 0},
-                              {80, 320, 0}, {96, 576, 0}, {64, 256, 1}, {80, 320, 1}};
+                              {80, 320, 0}, {96, 576, 0}, {64, 256, 1}, {80, 320, 1},
+                              {16, 64, 2},  {32, 64, 2},  {48, 192, 2}, {64, 256, 2},
+                              {80, 320, 2}, {96, 384, 2}};
 constexpr int kNVar32 = sizeof(kVar32) / sizeof(kVar32[0]);
 constexpr int kNVar64 = sizeof(kVar64) / sizeof(kVar64[0]);
 
@@ -1234,8 +1362,12 @@ void projection_variant_info(int precision, int v, int *N, int *NT) {
   *NT = x.NT;
 }
 
+int projection_variant_kind(int precision, int v) {
+  return (precision == 1 ? kVar32[v] : kVar64[v]).kind;
+}
+
 int projection_variant_two_level(int precision, int v) {
-  return (precision == 1 ? kVar32[v] : kVar64[v]).two_level;
+  return projection_variant_kind(precision, v) == 1;
 }
 
 int projection_default_variant(int precision, int s) {
@@ -1245,12 +1377,29 @@ int projection_default_variant(int precision, int s) {
   for (int v = 0; v < nv; ++v) {
     int N, NT;
     projection_variant_info(precision, v, &N, &NT);
+    if (projection_variant_kind(precision, v) == 2) continue;
     if (N >= n && N < bestN) {   // first listed NT of the smallest fitting N
       best = v;
       bestN = N;
     }
   }
   return best;
+}
+
+// Standalone projections: the first listed sign-function variant of the
+// smallest fitting N (fastest at every size measured), else the Jacobi default.
+int projection_standalone_variant(int precision, int s) {
+  const int n = s + (s & 1);
+  int best = -1, bestN = 1 << 30;
+  for (int v = 0; v < projection_variant_count(precision); ++v) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (projection_variant_kind(precision, v) == 2 && N >= n && N < bestN) {
+      best = v;
+      bestN = N;
+    }
+  }
+  return best >= 0 ? best : projection_default_variant(precision, s);
 }
 
 hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
@@ -1277,6 +1426,41 @@ int projection_bucket(int precision, int s) {
 
 int projection_max_size(int precision) { return precision == 1 ? 128 : 96; }
 
+template <typename T, int N, int NT>
+hipError_t launch_sign(int count, const int32_t *sizes, const int64_t *offsets, const void *in,
+                       void *out, int k1, int k2, hipStream_t st) {
+  hipLaunchKernelGGL((k_project_sign<T, N, NT>), dim3(count), dim3(NT), 0, st, sizes, offsets,
+                     (const T *)in, (T *)out, k1, k2);
+  return hipGetLastError();
+}
+
+hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *sizes,
+                         const int64_t *offsets, const void *in, void *out, int k1, int k2,
+                         hipStream_t st) {
+#define SDP_SIGN(T, n, nt)                                                                     \
+  if (N == n && NT == nt) return launch_sign<T, n, nt>(count, sizes, offsets, in, out, k1, k2, st);
+  if (dtype == 1) {
+    SDP_SIGN(float, 16, 64)
+    SDP_SIGN(float, 32, 64)
+    SDP_SIGN(float, 32, 256)
+    SDP_SIGN(float, 48, 192)
+    SDP_SIGN(float, 64, 256)
+    SDP_SIGN(float, 80, 320)
+    SDP_SIGN(float, 96, 384)
+    SDP_SIGN(float, 112, 448)
+    SDP_SIGN(float, 128, 512)
+  } else {
+    SDP_SIGN(double, 16, 64)
+    SDP_SIGN(double, 32, 64)
+    SDP_SIGN(double, 48, 192)
+    SDP_SIGN(double, 64, 256)
+    SDP_SIGN(double, 80, 320)
+    SDP_SIGN(double, 96, 384)
+  }
+#undef SDP_SIGN
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_admm_projection(int precision, int variant, const int32_t *list, int count,
                                   const ProjArgs &a, hipStream_t st) {
   int N, NT;
@@ -1302,6 +1486,13 @@ hipError_t launch_standalone_projection(int dtype, int variant, int count, const
   ProjArgs a{};
   int N, NT;
   projection_variant_info(dtype, variant, &N, &NT);
+  if (projection_variant_kind(dtype, variant) == 2) {
+    if (count <= 0) return hipSuccess;
+    // sign iteration: k1 fast steps resolve eigenvalues down to 3^-k1 ||W||_F
+    const int k1 = std::max(4, (int)std::ceil(std::log(1.0 / tol) / std::log(3.0)));
+    const int k2 = dtype == 1 ? 3 : 4;
+    return dispatch_sign(dtype, N, NT, count, sizes, offsets, in, out, k1, k2, st);
+  }
   const int blk = projection_variant_two_level(dtype, variant);
   if (dtype == 1)
     return dispatch<float, MODE_STANDALONE>(N, NT, blk, count, a, nullptr, sizes, offsets,

@@ -191,6 +191,7 @@ std::vector<int> fitting_variants(int precision, int s, int method) {
     int N, NT;
     projection_variant_info(precision, v, &N, &NT);
     if (N < n) continue;
+    if (projection_variant_kind(precision, v) == 2) continue;   // no eigenvectors
     any.push_back(v);
     (projection_variant_two_level(precision, v) ? two : scalar).push_back(v);
   }
@@ -1356,7 +1357,7 @@ int project_blocks(int variant, int32_t count, int32_t max_size, const int32_t *
   if (max_size <= 0 || max_size > projection_max_size(prec))
     fail(SDP_ERR_UNSUPPORTED, "max_size out of range for this dtype");
   if (variant < 0) {
-    variant = projection_default_variant(prec, max_size);
+    variant = projection_standalone_variant(prec, max_size);
   } else {
     if (variant >= projection_variant_count(prec)) fail(SDP_ERR_ARG, "no such kernel variant");
     int N, NT;
@@ -1407,13 +1408,13 @@ int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_
   });
 }
 
-int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *two_level) {
+int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *kind) {
   return guarded([&] {
     if (dtype != SDP_DTYPE_FP64 && dtype != SDP_DTYPE_FP32) fail(SDP_ERR_ARG, "invalid dtype");
     const int prec = dtype == SDP_DTYPE_FP32 ? 1 : 0;
-    if (!two_level || variant < 0 || variant >= projection_variant_count(prec))
+    if (!kind || variant < 0 || variant >= projection_variant_count(prec))
       fail(SDP_ERR_ARG, "invalid arguments");
-    *two_level = projection_variant_two_level(prec, variant);
+    *kind = projection_variant_kind(prec, variant);
     return SDP_OK;
   });
 }

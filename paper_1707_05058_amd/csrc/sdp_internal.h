@@ -121,7 +121,10 @@ int projection_variant_count(int precision);
 void projection_variant_info(int precision, int variant, int *N, int *NT);
 // 1: two-level (block) Jacobi with 16 x 16 pair problems; 0: scalar rounds
 int projection_variant_two_level(int precision, int variant);
-int projection_default_variant(int precision, int s);   // -1 if s is too large
+// 0 scalar Jacobi, 1 two-level Jacobi, 2 sign function (standalone only)
+int projection_variant_kind(int precision, int variant);
+int projection_default_variant(int precision, int s);   // -1 if s is too large (Jacobi)
+int projection_standalone_variant(int precision, int s);  // sign function where built
 hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
                               double offdiag, hipStream_t st);
 // Sets the warm-start bases of cliques [c0, c0 + count) to the identity.

@@ -118,3 +118,32 @@ def test_projection_empty_call(sdp, gpu):
     f = torch.zeros(0, dtype=torch.float32, device=dev)
     sdp.psd_project_batched(z32, z64, f, f.clone(), 16)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_sign_variants_degenerate_and_clustered_spectra(sdp, gpu, oracle_mod, dtype):
+    """The sign-function variants (no eigenvectors) on zero, PSD, NSD,
+    repeated and zero eigenvalues, and on spectra whose magnitudes spread
+    log-uniformly down to 1e-9 (eigenvalues below the resolution contribute
+    at most their size)."""
+    dt = sdp.DTYPE_FP32 if dtype == np.float32 else sdp.DTYPE_FP64
+    variants = sdp.projection_variants(dt)
+    sign = [v for v in range(len(variants)) if sdp.projection_variant_kind(dt, v) == 2]
+    assert sign, "no sign-function variants"
+    rng = np.random.default_rng(9)
+    for v in sign:
+        N = variants[v][0]
+        s = N - 3 if N > 16 else 12
+        Q, _ = np.linalg.qr(rng.standard_normal((s, s)))
+        G = rng.standard_normal((s, s))
+        mags = 10 ** rng.uniform(-9, 0, s) * rng.choice([-1.0, 1.0], s)
+        blocks = [np.zeros((s, s)), G @ G.T, -(G @ G.T),
+                  (Q * np.array([2.0] * (s // 2) + [-1.0] * (s - s // 2))) @ Q.T,
+                  (Q * np.concatenate([np.zeros(s // 3), 3.0 * np.ones(s // 3),
+                                       -3.0 * np.ones(s - 2 * (s // 3))])) @ Q.T,
+                  (Q * mags) @ Q.T, np.eye(s) * 7.0]
+        blocks = [0.5 * (b + b.T) for b in blocks]
+        print(f"sign variant {v}: N={N} s={s}", flush=True)
+        outs = run_gpu(sdp, blocks, dtype, N, variant=v)
+        check(oracle_mod, blocks, outs, dtype)
+        assert np.all(outs[0] == 0.0)
