@@ -1096,14 +1096,11 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 // on or below the diagonal are computed, and only the lanes on or below the
 // diagonal store (both triangles), so every iterate is exactly symmetric.
 // The products run on the matrix cores from two N x N LDS buffers (natural
-// layout, pitch 16 mod 32 for FP32 and N + 1 for FP64).
+// layout, odd pitch N + 1: the mirrored stores run down columns).
 // ---------------------------------------------------------------------------
 template <typename T>
 __host__ __device__ constexpr int sign_pitch(int N) {
-  if (sizeof(T) == 8) return N + 1;
-  int p = N;
-  while (p % 32 != 16) ++p;
-  return p;
+  return N + 1;
 }
 
 template <typename T, int N, int NT>
