@@ -508,10 +508,15 @@ __device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
     t2 = block_sum<NT>(t2, red);
     if (!(t2 <= tmax2)) return false;
     __syncthreads();
-    // Z = T^T T
-    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
-                                  [&](int k, int q) { return Abuf[k * P + q]; },
-                                  [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
+    // Z = T^T T (symmetric: tiles on or below the diagonal, mirrored)
+    tile_product<T, N, NT, true>([&](int k, int q) { return Abuf[k * P + q]; },
+                                 [&](int k, int q) { return Abuf[k * P + q]; },
+                                 [&](int qi, int qj, T v) {
+                                   if (qi >= qj) {
+                                     Vbuf[slot(qi) * P + qj] = v;
+                                     Vbuf[slot(qj) * P + qi] = v;
+                                   }
+                                 });
     __syncthreads();
     // Q = (I + T)(I - Z / 2): x(k, i) = (I + T)(i, k) = (I - T)(k, i)
     tile_product<T, N, NT, false>(
@@ -532,9 +537,15 @@ __device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
                                   [&](int k, int q) { return Abuf[k * P + q]; },
                                   [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
     __syncthreads();
-    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
-                                  [&](int k, int q) { return Vbuf[k * P + q]; },
-                                  [&](int qi, int qj, T v) { Vbuf[slot(qi) * P + qj] = v; });
+    // Q^T (A Q), symmetric
+    tile_product<T, N, NT, true>([&](int k, int q) { return Abuf[k * P + q]; },
+                                 [&](int k, int q) { return Vbuf[k * P + q]; },
+                                 [&](int qi, int qj, T v) {
+                                   if (qi >= qj) {
+                                     Vbuf[slot(qi) * P + qj] = v;
+                                     Vbuf[slot(qj) * P + qi] = v;
+                                   }
+                                 });
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -735,9 +746,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
                                   [&](int k, int q) { return Vbuf[k * P + q]; },
                                   [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
     __syncthreads();
-    tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
-                                  [&](int k, int q) { return Abuf[k * P + q]; },
-                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
+    // (symmetric: tiles on or below the diagonal, mirrored)
+    tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                 [&](int k, int q) { return Abuf[k * P + q]; },
+                                 [&](int qi, int qj, T v) {
+                                   if (qi >= qj) {
+                                     Abuf[slot(qi) * P + qj] = v;
+                                     Abuf[slot(qj) * P + qi] = v;
+                                   }
+                                 });
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -919,9 +936,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   // the Gram matrix V^T V of the Newton-Schulz step reads V by rows; the
   // products after it read V^T, written over V from the registers
   if (ADMM && vw) {
-    tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },
-                                  [&](int k, int q) { return Vbuf[k * P + q]; },
-                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
+    // (symmetric: tiles on or below the diagonal, mirrored)
+    tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                 [&](int k, int q) { return Vbuf[k * P + q]; },
+                                 [&](int qi, int qj, T v) {
+                                   if (qi >= qj) {
+                                     Abuf[slot(qi) * P + qj] = v;
+                                     Abuf[slot(qj) * P + qi] = v;
+                                   }
+                                 });
   }
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
