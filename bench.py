@@ -331,6 +331,35 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     return out
 
 
+def time_loop(sdp, torch, insts, precision, steps, warmup, stream, total):
+    """The batch as a loop of per-instance solves: one handle per instance
+    (each with its own captured graph), stepped one after another on the same
+    stream.  `insts` is a sample of the batch; the time of one iteration of
+    every sampled instance is extrapolated linearly to `total` instances."""
+    handles = [sdp.Solver([i], tol=0.0, max_iter=10 ** 8, precision=precision,
+                          stream=stream.cuda_stream) for i in insts]
+    try:
+        with torch.cuda.stream(stream):
+            for S in handles:
+                S.step(warmup, results=False)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for S in handles:
+                S.step(steps, results=False)
+            e1.record(stream)
+            e1.synchronize()
+        ms_round = e0.elapsed_time(e1) / steps          # one iteration of each sampled instance
+    finally:
+        for S in handles:
+            S.close()
+    ms_all = ms_round * total / len(insts)
+    return dict(precision=precision, instances_timed=len(insts), steps=steps,
+                ms_per_iteration_of_all=ms_all, instance_iter_per_s=total / (ms_all / 1e3),
+                sample=f"instances 0..{len(insts) - 1} of {total}, each its own handle, "
+                       f"{steps} iterations each; extrapolated linearly to {total}")
+
+
 def time_adjoint(sdp, torch, insts, precision, T, ckpt, stream):
     """Unrolled forward (T iterations, checkpoints every ckpt) and the reverse
     sweep of <C, X_T>, timed with HIP events on the solver's stream."""
@@ -566,6 +595,17 @@ def main():
         line["speedup_fp32_vs_fp64_time_to_tol"] = (f64["solve"]["time_to_tol_s"] /
                                                     f32["solve"]["time_to_tol_s"])
         line["objective_rel_diff_fp32_vs_fp64"] = float(np.max(np.abs(o32 - o64) / np.abs(o64)))
+    if args.workload == "batched":
+        # the batched handle against a loop of per-instance plain FP64 solves
+        print("[bench] batched: loop of per-instance FP64 solves", file=sys.stderr, flush=True)
+        loop = time_loop(sdp, torch, insts[:32], "fp64", min(args.steps, 100), 10, stream,
+                         len(insts))
+        line["loop_fp64"] = loop
+        line["speedup_batched_fp32_vs_loop_fp64"] = (f32["instance_iter_per_s"] /
+                                                     loop["instance_iter_per_s"])
+        if f64 is not None:
+            line["speedup_batched_fp64_vs_loop_fp64"] = (f64["instance_iter_per_s"] /
+                                                         loop["instance_iter_per_s"])
     print(json.dumps(line), flush=True)
 
 
