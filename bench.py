@@ -157,11 +157,13 @@ def load_traffic(workload, stage):
 
 
 # kernels of each stage as rocprofv3 names them, (prefix, suffix) pairs; the
-# projection is the FP32-eig form's ADMM-mode kernel (template mode 0)
+# projection is the FP32-eig form's ADMM-mode kernel (template mode 0, or 3 with the
+# positive/negative decoupling compiled in)
 STAGE_KERNELS = {"scatter": (("k_scatter", ""),), "A_v": (("k_rowdot<", ""), ("k_csr_rowdot", "")),
                  "Linv_r": (("k_trmv_wave<0>", ""),), "LinvT_y": (("k_trmv_wave<1>", ""),),
                  "AT_y": (("k_coldot<0,", ""), ("k_csc_coldot<0>", "")),
-                 "projection": (("k_project<float", ", 0, false>"), ("k_project<float", ", 0, true>")),
+                 "projection": (("k_project<float", ", 0, false>"), ("k_project<float", ", 0, true>"),
+                                ("k_project<float", ", 3, false>")),
                  "residual": (("k_residual_reduce", ""),)}
 COPY_CAL_BYTES = 512 << 20
 
@@ -393,6 +395,27 @@ def time_adjoint(sdp, torch, insts, precision, T, ckpt, stream):
     return out, cb.cpu().numpy(), bb.cpu().numpy()
 
 
+def roofline_of(insts, stages_ms, sweeps, algorithm, extra, workload):
+    """Roofline of the longest stage: algorithmic bytes (or flops) per launch
+    over its mean launch time, with the counter traffic of the workload's
+    profile when one is committed for the current kernel source."""
+    model = stage_bytes_flops(insts, "fp32", sweeps, algorithm,
+                              cg_steps=extra.get("cg_max_iter", 0))
+    stages = {k: v for k, v in stages_ms.items() if k in model}
+    dom = max(stages, key=lambda k: stages[k])
+    t_launch = stages[dom] / 1e3
+    info = model[dom]
+    if info["bound"] == "hbm":
+        achieved = info["bytes"] / t_launch / 1e9
+        return dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(workload, dom),
+                    algorithmic_bytes_per_launch=info["bytes"], launch_ms=stages[dom])
+    achieved = info["flops"] / t_launch / 1e12
+    return dict(kernel=dom, bound="alu", achieved=achieved, peak=info["peak_tflops"],
+                unit="TFLOP/s", frac=achieved / info["peak_tflops"], traffic=None,
+                model_flops_per_launch=info["flops"], launch_ms=stages[dom])
+
+
 def solver_options(args):
     """Per-workload solver options plus the command line's."""
     extra = dict(EXTRA_OPTIONS.get(args.workload, {}))
@@ -531,23 +554,8 @@ def main():
               file=sys.stderr, flush=True)
     head = forms["fp32"]
     extra = solver_options(args)
-    model = stage_bytes_flops(insts, "fp32", head["timed_sweeps_per_projection"], args.algorithm,
-                              cg_steps=extra.get("cg_max_iter", 0))
-    stages = {k: v for k, v in head["stages_ms"].items() if k in model}
-    dom = max(stages, key=lambda k: stages[k])
-    t_launch = stages[dom] / 1e3
-    info = model[dom]
-    if info["bound"] == "hbm":
-        achieved = info["bytes"] / t_launch / 1e9
-        traffic = load_traffic(args.workload, dom)
-        roof = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                    algorithmic_bytes_per_launch=info["bytes"], launch_ms=stages[dom])
-    else:
-        achieved = info["flops"] / t_launch / 1e12
-        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=info["peak_tflops"],
-                    unit="TFLOP/s", frac=achieved / info["peak_tflops"], traffic=None,
-                    model_flops_per_launch=info["flops"], launch_ms=stages[dom])
+    roof = roofline_of(insts, head["stages_ms"], head["timed_sweeps_per_projection"],
+                       args.algorithm, extra, args.workload)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -743,6 +751,21 @@ def run_adjoint(args, sdp, torch, insts, stream):
         grads[precision] = (cb, bb)
     (c32, b32), (c64, b64) = grads["fp32"], grads["fp64"]
     head = res["fp32"]
+    # the forward iterations are the solver's: stage timing of a handle over
+    # the same instances (FP32-eig, fixed penalty, warm-started)
+    with torch.cuda.stream(stream):
+        S = sdp.Solver(insts, tol=0.0, max_iter=10 ** 8, precision="fp32",
+                       stream=stream.cuda_stream)
+        S.step(20, results=False)
+        st0 = S.stats()
+        S.step(20, results=False)
+        st1 = S.stats()
+        sweeps = ((st1["jacobi_sweeps"] - st0["jacobi_sweeps"]) /
+                  max(st1["projections"] - st0["projections"], 1))
+        stages = S.time_stages(20)
+        S.close()
+    roof = roofline_of(insts, stages, sweeps, "primal", {}, "adjoint")
+    roof["note"] = "longest stage of the forward iteration (the reverse sweep reuses the same passes)"
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -765,7 +788,7 @@ def run_adjoint(args, sdp, torch, insts, stream):
         "grad_rel_diff_fp32_vs_fp64": {
             "c": float(np.abs(c32 - c64).max() / np.abs(c64).max()),
             "b": float(np.abs(b32 - b64).max() / np.abs(b64).max())},
-        "roofline": None, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
