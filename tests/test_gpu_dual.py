@@ -123,3 +123,10 @@ def test_dual_rejects_unrolled_differentiation(sdp, gpu):
         with pytest.raises(sdp.SdpError) as e:
             S.unrolled_forward(5, 5, u)
         assert e.value.code == -7
+
+
+def test_dual_fixed_n_fp32_blocks_of_64_with_decoupling(sdp, gpu, oracle_mod):
+    """Algorithm 2 in the FP32-eig form on cliques of 64: the warm-started
+    projections take the positive/negative decoupling (on by default)."""
+    inst = sdpgen.block_arrow_instance(3, 58, 6, 40, seed=5)
+    compare_fixed_n_dual(sdp, oracle_mod, [inst], 40, precision="fp32", tol_rel=2e-4)

@@ -141,3 +141,10 @@ def test_hsde_certificates_on_gpu(sdp, gpu, oracle_mod):
     assert np.linalg.eigvalsh(Sm).min() >= -1e-4 * max(1.0, np.abs(Sm).max())
     x = -sols[2]["u"] / np.sum(w * insts[2].c * sols[2]["u"])
     assert np.linalg.norm(insts[2].a_val @ (w * x)) <= 1e-4
+
+
+def test_hsde_fixed_n_fp32_blocks_of_64_with_decoupling(sdp, gpu, oracle_mod):
+    """Algorithm 3 in the FP32-eig form on cliques of 64: the warm-started
+    projections take the positive/negative decoupling (on by default)."""
+    inst = sdpgen.block_arrow_instance(3, 58, 6, 40, seed=5)
+    compare_fixed_n_hsde(sdp, oracle_mod, [inst], 40, precision="fp32", tol_rel=2e-4)
