@@ -206,7 +206,8 @@ int sdp_solve(sdp_handle *h, sdp_result *res);
  * sign-function variant (sdp_projection_variant_kind = 2) of the smallest
  * block size that holds max_size: the same projection to the tolerance of
  * the Jacobi variants (1e-6 ||W||_F in FP32, 1e-14 in FP64), which
- * sdp_psd_project_variant still selects. */
+ * sdp_psd_project_variant still selects.  A block with a NaN or infinite
+ * entry comes out all NaN (every variant). */
 int sdp_psd_project_batched(int32_t count, int32_t max_size, const int32_t *sizes,
                             const int64_t *offsets, const void *in, void *out,
                             int32_t dtype, void *stream);

@@ -714,6 +714,11 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       }
   }
   const double thr = tol * tol * block_sum<NT>(f2, red);
+  if (MODE == MODE_STANDALONE && !(thr < INFINITY)) {
+    // a NaN or infinite entry: NaN throughout, never a finite result
+    for (int e = tid; e < s * s; e += NT) out[off + e] = T(NAN);
+    return;
+  }
 
   // --- warm start: rotate W into the basis V0 the clique ended with last
   // iteration, A = V0^T W V0 (symmetrised), and let the rotations accumulate
@@ -1153,11 +1158,14 @@ __global__ __launch_bounds__(NT) void k_project_sign(const int32_t *__restrict__
     f2 += (double)v * (double)v;
   }
   f2 = block_sum<NT>(f2, red);
-  if (!(f2 > 0.0)) {   // W = 0
+  if (!(f2 > 0.0 && f2 < INFINITY)) {
+    // W = 0: P+(W) = 0; a NaN or infinite entry: NaN throughout (as the
+    // Jacobi variants give), never a finite result
+    const T fill = f2 == 0.0 ? T(0) : T(NAN);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int e = tid + NT * i, r = e / N, c = e % N;
-      if (r < s && c < s) out[off + (int64_t)r * s + c] = T(0);
+      if (r < s && c < s) out[off + (int64_t)r * s + c] = fill;
     }
     return;
   }

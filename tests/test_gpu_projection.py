@@ -147,3 +147,23 @@ def test_sign_variants_degenerate_and_clustered_spectra(sdp, gpu, oracle_mod, dt
         outs = run_gpu(sdp, blocks, dtype, N, variant=v)
         check(oracle_mod, blocks, outs, dtype)
         assert np.all(outs[0] == 0.0)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_nonfinite_blocks_give_nan_not_a_finite_result(sdp, gpu, dtype):
+    """A block with a NaN or an infinite entry comes out all NaN from every
+    variant (never zeros or a finite matrix); the other blocks of the batch
+    are unaffected."""
+    dt = sdp.DTYPE_FP32 if dtype == np.float32 else sdp.DTYPE_FP64
+    variants = sdp.projection_variants(dt)
+    rng = np.random.default_rng(2)
+    good = 0.5 * (lambda G: G + G.T)(rng.standard_normal((10, 10)))
+    bad_nan, bad_inf = good.copy(), good.copy()
+    bad_nan[3, 4] = bad_nan[4, 3] = np.nan
+    bad_inf[1, 1] = np.inf
+    for v in [v for v in range(len(variants)) if variants[v][0] == 16]:
+        outs = run_gpu(sdp, [good, bad_nan, bad_inf], dtype, 16, variant=v)
+        print(f"variant {v} kind {sdp.projection_variant_kind(dt, v)}", flush=True)
+        assert np.all(np.isfinite(outs[0]))
+        assert np.all(np.isnan(outs[1])), outs[1]
+        assert not np.any(np.isfinite(outs[2])), outs[2]
