@@ -1454,6 +1454,110 @@ int projection_bucket(int precision, int s) {
 
 int projection_max_size(int precision) { return precision == 1 ? 128 : 96; }
 
+// The sign iteration for blocks of 16, one wave per block, entirely in
+// registers.  A 16 x 16 x 16 product is four 16x16x4 matrix-core steps; the
+// sum over k may be split over the steps in any order as long as both
+// operands agree, and step j takes k = R(g, j) from lane group g = l / 16,
+// where R(g, r) is the row of result register r (4g + r for FP32, g + 4r for
+// FP64).  Lane l then keeps X(R(g, r), l mod 16) in register r, and that is
+// exactly its operand of step r of the next product: the left operand
+// X(l mod 16, k) = X(k, l mod 16) by symmetry, the right one M(k, l mod 16).
+// So every product is four back-to-back steps on registers.  Using the
+// transposed element for the left operand makes each product X^T M, equal
+// to X M only while X is symmetric: without a correction the antisymmetric
+// rounding grows through the iteration (errors near 1e-2 in a lane-exact
+// simulation), so after every step X <- (X + X^T) / 2 through LDS (5e-8
+// then), and once more for the result.
+template <typename T>
+__device__ inline int sign16_row(int g, int r) {
+  return sizeof(T) == 4 ? 4 * g + r : g + 4 * r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_project_sign16(const int32_t *__restrict__ sizes,
+                                                      const int64_t *__restrict__ offsets,
+                                                      const T *__restrict__ in,
+                                                      T *__restrict__ out, int k1, int k2) {
+  typedef typename Mma<T>::v4 v4;
+  __shared__ T C[16 * 17];
+  const int l = threadIdx.x, g = l >> 4, col = l & 15;
+  const int s = sizes[blockIdx.x];
+  const int64_t off = offsets[blockIdx.x];
+  if (s <= 0 || s > 16) return;   // sizes beyond max_size are left untouched
+  T w[4];
+  double f2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = sign16_row<T>(g, r);
+    T v = T(0);
+    if (row < s && col < s)
+      v = T(0.5) * (in[off + (int64_t)row * s + col] + in[off + (int64_t)col * s + row]);
+    w[r] = v;
+    f2 += (double)v * (double)v;
+  }
+  f2 = wave_sum(f2);
+  if (!(f2 > 0.0 && f2 < INFINITY)) {
+    const T fill = f2 == 0.0 ? T(0) : T(NAN);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = sign16_row<T>(g, r);
+      if (row < s && col < s) out[off + (int64_t)row * s + col] = fill;
+    }
+    return;
+  }
+  const T scale = (T)(1.0 / sqrt(f2));
+  T x[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) x[r] = w[r] * scale;
+  // identity in the register layout
+  T id[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) id[r] = sign16_row<T>(g, r) == col ? T(1) : T(0);
+  const auto prod = [](const T (&a)[4], const T (&b)[4], T (&c)[4]) {
+    v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc = Mma<T>::step(a[j], b[j], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c[r] = acc[r];
+  };
+  for (int it = 0; it < k1 + k2; ++it) {
+    T y[4], m[4];
+    prod(x, x, y);                                              // Y = X^2
+    if (it < k1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) m[r] = T(-3.2) * id[r] + T(1.2) * y[r];
+      T t[4];
+      prod(y, m, t);                                            // T = Y (-3.2 I + 1.2 Y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) m[r] = T(3) * id[r] + t[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) m[r] = T(1.5) * id[r] - T(0.5) * y[r];
+    }
+    T xn[4];
+    prod(x, m, xn);                                             // X <- X M
+    // X <- (X + X^T) / 2 (both triangles from the same two values)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[sign16_row<T>(g, r) * 17 + col] = xn[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = T(0.5) * (xn[r] + C[col * 17 + sign16_row<T>(g, r)]);
+    __syncthreads();
+  }
+  // W S, symmetrised through LDS: P+(W) = (W + (W S + S W) / 2) / 2
+  T c[4];
+  prod(w, x, c);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) C[sign16_row<T>(g, r) * 17 + col] = c[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = sign16_row<T>(g, r);
+    if (row < s && col < s)
+      out[off + (int64_t)row * s + col] = T(0.5) * (w[r] + T(0.5) * (c[r] + C[col * 17 + row]));
+  }
+}
+
 template <typename T, int N, int NT>
 hipError_t launch_sign(int count, const int32_t *sizes, const int64_t *offsets, const void *in,
                        void *out, int k1, int k2, hipStream_t st) {
@@ -1467,8 +1571,16 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
                          hipStream_t st) {
 #define SDP_SIGN(T, n, nt)                                                                     \
   if (N == n && NT == nt) return launch_sign<T, n, nt>(count, sizes, offsets, in, out, k1, k2, st);
+  if (N == 16 && NT == 64) {   // blocks of 16: the register-resident kernel
+    if (dtype == 1)
+      hipLaunchKernelGGL(k_project_sign16<float>, dim3(count), dim3(64), 0, st, sizes, offsets,
+                         (const float *)in, (float *)out, k1, k2);
+    else
+      hipLaunchKernelGGL(k_project_sign16<double>, dim3(count), dim3(64), 0, st, sizes, offsets,
+                         (const double *)in, (double *)out, k1, k2);
+    return hipGetLastError();
+  }
   if (dtype == 1) {
-    SDP_SIGN(float, 16, 64)
     SDP_SIGN(float, 32, 64)
     SDP_SIGN(float, 32, 256)
     SDP_SIGN(float, 48, 192)
@@ -1478,7 +1590,6 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
     SDP_SIGN(float, 112, 448)
     SDP_SIGN(float, 128, 512)
   } else {
-    SDP_SIGN(double, 16, 64)
     SDP_SIGN(double, 32, 64)
     SDP_SIGN(double, 48, 192)
     SDP_SIGN(double, 64, 256)
