@@ -723,7 +723,9 @@ def run_projection(args, sdp, torch, stream):
         "data": "synthetic",
         "config": {"workload": WORKLOADS["projection"], "headline": "FP32, s = 16"},
         "sizes": res,
-        "roofline": {"kernel": ("k_project_sign" if head["best_variant"]["method"] == "sign"
+        "roofline": {"kernel": (("k_project_sign16" if head["best_variant"]["N"] == 16
+                                 else "k_project_sign")
+                                if head["best_variant"]["method"] == "sign"
                                 else "k_project") + f" (N = {head['best_variant']['N']}, "
                                f"{head['best_variant']['threads']} threads, standalone)",
                      "bound": "mfma" if head["best_variant"]["method"] == "sign" else "alu",
