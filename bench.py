@@ -187,16 +187,25 @@ def summarize_rocprof(workload, trace_dir, fetch_dir, write_dir, commands):
     FETCH_SIZE run, one --pmc WRITE_SIZE run of this script) into
     profiles/kernel_trace_<workload>.md and profiles/traffic_<workload>.json.
     The HBM counters are scaled by what they read for a plain copy of
-    COPY_CAL_BYTES (the --copy-calibration run), per launch of each stage."""
+    COPY_CAL_BYTES (the --copy-calibration run), per launch of each stage.
+    With "-" for both counter directories it writes the kernel trace only."""
     stats = _csv_rows(trace_dir, "kernel_stats.csv")
-    lines = [f"# Kernel trace and HBM traffic, {workload} workload ({WORKLOADS[workload]})", "",
+    trace_only = fetch_dir == "-" and write_dir == "-"
+    lines = [f"# Kernel trace{'' if trace_only else ' and HBM traffic'}, {workload} workload "
+             f"({WORKLOADS[workload]})", "",
              "Commands (repository root, one MI355X; each rocprofv3 run in its own process):", "",
              "```"] + commands + ["```", "",
              "| kernel | calls | total (us) | average (us) | % |", "|---|---:|---:|---:|---:|"]
-    for r in stats[:25]:
+    for r in (stats if trace_only else stats[:25]):
         lines.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | "
                      f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['AverageNs']) / 1e3:.3f} | "
                      f"{float(r['Percentage']):.1f} |")
+    if trace_only:
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        with open(os.path.join(ROOT, "profiles", f"kernel_trace_{workload}.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
 
     def per_kernel(rows):
         acc = {}

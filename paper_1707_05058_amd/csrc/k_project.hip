@@ -149,7 +149,12 @@ __device__ inline void tile_product(FX fx, FY fy, FS store) {
   constexpr int TILES = LOWER ? TN * (TN + 1) / 2 : TN * TN;
   constexpr int TPW = (TILES + NW - 1) / NW;
   static_assert(N % 16 == 0 && NT % 64 == 0, "tiles of 16, whole waves");
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the lane index passes through an empty asm statement, so the addresses
+  // derived from it are computed in each product rather than hoisted out of
+  // the caller's loops and kept live (spilled) across them
+  int lt = threadIdx.x & 63;
+  asm volatile("" : "+v"(lt));
+  const int l = lt, w = threadIdx.x >> 6;
   typename Mma<T>::v4 acc[TPW];
   int ti[TPW], tj[TPW];
 #pragma unroll
@@ -417,9 +422,10 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
 // diagonal; with P = {i : a_ii > 0} and N the rest, one refinement applies
 // the Jacobi rotations of all opposite-sign pairs (p, q) at once:
 // T(p, q) = tan of the angle that zeroes a_pq in its own 2x2 problem (T skew,
-// |T(p, q)| <= 1; the same-sign pairs are left alone), Q = (I + T)(I - T^T T
-// / 2) (one Newton-Schulz step towards the orthogonal polar factor of I + T),
-// A <- Q^T A Q, V <- V Q, five products on the matrix cores.  Near the
+// |T(p, q)| <= 1; the same-sign pairs are left alone), Q = I + T - T^T T / 2
+// (= I + T + T^2 / 2 for skew T, the exponential of T to second order; then
+// Q^T Q = I + T^4 / 4 exactly), A <- Q^T A Q, V <- V Q: four products on the
+// matrix cores (T^T T, A Q, Q^T (A Q), V Q).  Near the
 // decoupled state the opposite-sign mass falls quadratically.  The block is
 // accepted when
 //   * sum over opposite-sign pairs of a_pq^2 <= thr (= tol^2 ||W||_F^2), and
@@ -428,7 +434,7 @@ __device__ int two_level_sweeps(T *Abuf, T *Vbuf, T *ws, double *red, double thr
 // and then P_+(W) = V [A_PP 0; 0 0] V^T up to O(eps) (P_+ is 1-Lipschitz, so
 // the dropped coupling costs at most sqrt(2) sqrt(thr); the certified blocks
 // add at most eps per eigenvalue).  The refinement is only taken while
-// ||T||_F <= tmax, so that the Newton-Schulz step leaves Q orthogonal to
+// ||T||_F <= tmax, so that Q is orthogonal to
 // O(||T||^4) below the tolerance.  Returns true when accepted; otherwise A, V
 // are still V^T W V and an orthonormal basis and the sweeps continue.
 // Layout as in k_project's scalar path: A and V in registers (2x2 blocks),
@@ -443,9 +449,13 @@ __device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
   constexpr int AS = NT / K;
   const auto ix = [](int r, int c) { return r * P + (c & 1) * K + (c >> 1); };
   const auto slot = [](int q) { return q < K ? 2 * q : 2 * (q - K) + 1; };
-  const int tid = threadIdx.x, b = tid % K, a0 = tid / K;
   const double eps = sqrt(thr);
   for (int ref = 0;; ++ref) {
+    // thread coordinates through an empty asm statement: the addresses of
+    // this pass are computed in it, not kept live across the refinements
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int b = tid % K, a0 = tid / K;
     // diagonal (its signs define P and N)
 #pragma unroll
     for (int j = 0; j < BPT; ++j)
@@ -518,19 +528,19 @@ __device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
                                    }
                                  });
     __syncthreads();
-    // Q = (I + T)(I - Z / 2): x(k, i) = (I + T)(i, k) = (I - T)(k, i)
-    tile_product<T, N, NT, false>(
-        [&](int k, int q) { return (k == slot(q) ? T(1) : T(0)) - Abuf[k * P + q]; },
-        [&](int k, int q) { return (k == slot(q) ? T(1) : T(0)) - T(0.5) * Vbuf[k * P + q]; },
-        [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
-    // A into Vbuf, then A Q and Q^T (A Q)
+    // Q = I + T - Z / 2 over T in Abuf, and A over Z in Vbuf: each thread
+    // reads and writes only its own entries; then A Q and Q^T (A Q)
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
       const int aj = a0 + AS * j;
 #pragma unroll
       for (int d = 0; d < 2; ++d)
 #pragma unroll
-        for (int e = 0; e < 2; ++e) Vbuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e];
+        for (int e = 0; e < 2; ++e) {
+          const int r = 2 * aj + d, c = 2 * b + e, x = ix(r, c);
+          Abuf[x] = (r == c ? T(1) : T(0)) + Abuf[x] - T(0.5) * Vbuf[x];
+          Vbuf[x] = A[j][d][e];
+        }
     }
     __syncthreads();
     tile_product<T, N, NT, false>([&](int k, int q) { return Vbuf[k * P + q]; },

@@ -1070,8 +1070,10 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     p.decouple = opt.decouple && h->precision == SDP_FP32_EIG;
     p.dec_max_ref = h->precision == SDP_FP32_EIG ? 2 : 3;
     p.dec_skip = 4;
-    // one Newton-Schulz step leaves Q^T Q - I = -(3/4) Z^2 + Z^3 / 4 with
-    // ||Z||_F <= ||T||_F^2: keep that below the sweep tolerance
+    // the rotation Q = I + T + T^2 / 2 has Q^T Q - I = T^4 / 4, at most
+    // ||T||_F^4 / 4: with ||T||_F^2 <= sqrt(tol / 0.75) that stays below a
+    // third of the sweep tolerance (the bound limits the refinements to
+    // nearly decoupled blocks, where they converge quadratically)
     p.dec_tmax2 = std::sqrt(h->jac_tol / 0.75);
     p.dual = a.dual = opt.algorithm == SDP_ALG_DUAL ? 1 : 0;
     if (p.dual) {
