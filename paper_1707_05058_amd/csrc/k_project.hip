@@ -192,6 +192,54 @@ __device__ inline void tile_product(FX fx, FY fy, FS store) {
   }
 }
 
+// The same product with a depth known only at run time: k runs over
+// [0, kend) (kend a multiple of 4; fx and fy return 0 past the true depth),
+// and without LOWER only the first ceil(rows / 16) rows of tiles are formed.
+template <typename T, int N, int NT, bool LOWER, typename FX, typename FY, typename FS>
+__device__ inline void tile_product_part(int rows, int kend, FX fx, FY fy, FS store) {
+  constexpr int TN = N / 16;
+  constexpr int NW = NT / 64;
+  constexpr int TILES = LOWER ? TN * (TN + 1) / 2 : TN * TN;
+  constexpr int TPW = (TILES + NW - 1) / NW;
+  int lt = threadIdx.x & 63;
+  asm volatile("" : "+v"(lt));
+  const int l = lt, w = threadIdx.x >> 6;
+  const int tiles = LOWER ? TILES : ((rows + 15) / 16) * TN;
+  typename Mma<T>::v4 acc[TPW];
+  int ti[TPW], tj[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = w + t * NW;
+    int I = 0, J = 0;
+    if (LOWER) {
+      while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+      J = tile - I * (I + 1) / 2;
+    } else {
+      I = tile / TN;
+      J = tile % TN;
+    }
+    ti[t] = I;
+    tj[t] = J;
+    acc[t] = typename Mma<T>::v4{0, 0, 0, 0};
+    if (tile < tiles) {
+      const int qa = 16 * I + (l & 15), qb = 16 * J + (l & 15);
+      for (int k0 = 0; k0 < kend; k0 += 4) {
+        const int k = k0 + (l >> 4);
+        acc[t] = Mma<T>::step(fx(k, qa), fy(k, qb), acc[t]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    if (w + t * NW < tiles) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        store(16 * ti[t] + Mma<T>::row(l, r), 16 * tj[t] + (l & 15), acc[t][r]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Two-level (block) Jacobi for large blocks.  The N indices form N/8 groups of
 // 8; in each round of a sweep the groups are paired by the circle method (N/8
@@ -618,8 +666,12 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   constexpr bool WANT_V = MODE != MODE_MINEIG;
   constexpr bool ADMM = MODE == MODE_ADMM || MODE == MODE_ADMM_DEC;
   constexpr bool DEC = MODE == MODE_ADMM_DEC && !BLK;
+  // the rebuild of larger blocks sums over the positive slots only (listed)
+  constexpr bool COMPACT = WANT_V && N >= 64 && NT >= N;
 
   __shared__ T Abuf[N * P];
+  __shared__ int plist[COMPACT ? N : 1];
+  __shared__ int pwc[COMPACT ? (N + 63) / 64 : 1];
   __shared__ T Vbuf[WANT_V ? N * P : 1];
   __shared__ T prm_c[K], prm_s[K];
   __shared__ T th[N], thp[N];
@@ -947,6 +999,23 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       for (int e = 0; e < 2; ++e) Vbuf[ix(2 * aj + d, 2 * b + e)] = V[j][d][e];
   }
   for (int k = tid; k < N; k += NT) thp[k] = th[k] > T(0) ? th[k] : T(0);
+  // the positive slots in increasing order, plist[0 .. npos): wave ballots
+  int npos = N;
+  if constexpr (COMPACT) {
+    const bool ispos = tid < N && th[tid] > T(0);
+    const unsigned long long bal = __ballot(ispos);
+    if ((tid & 63) == 0 && tid < N) pwc[tid >> 6] = __popcll(bal);
+    __syncthreads();
+    int base = 0;
+    npos = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < (N + 63) / 64; ++w2) {
+      const int c = pwc[w2];
+      if (w2 < (tid >> 6)) base += c;
+      npos += c;
+    }
+    if (ispos) plist[base + __popcll(bal & ((1ull << (tid & 63)) - 1ull))] = tid;
+  }
   __syncthreads();
   // the Gram matrix V^T V of the Newton-Schulz step reads V by rows; the
   // products after it read V^T, written over V from the registers
@@ -992,7 +1061,15 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   // tiles on or below the diagonal, each result stored at (i, j) and (j, i);
   // after a decoupling X = V M V^T with M = A on the positive slots, zero
   // elsewhere (Y = M V^T first; Abuf is free once the Newton-Schulz product
-  // has passed its barrier); then the epilogue over the packed lower triangle ---
+  // has passed its barrier).  Blocks of 64 and more sum over the npos
+  // positive slots p_a = plist[a] only (X has rank npos): after a decoupling
+  // Y(a, j) = sum_b A(p_a, p_b) V(j, p_b) for a < npos, then
+  // X = sum_a V(i, p_a) Y(a, j); otherwise X = sum_a V(i, p_a) theta_{p_a} V(j, p_a).
+  // Then the epilogue over the packed lower triangle ---
+  const auto mirror = [&](int qi, int qj, T v) {
+    Abuf[slot(qi) * P + qj] = v;
+    Abuf[slot(qj) * P + qi] = v;
+  };
   if (!BLK && dec) {
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -1006,23 +1083,41 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
         }
     }
     __syncthreads();
-    tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
-                                  [&](int k, int q) { return Vbuf[k * P + q]; },
-                                  [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
-    __syncthreads();
-    tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
-                                 [&](int k, int q) { return Abuf[k * P + q]; },
-                                 [&](int qi, int qj, T v) {
-                                   Abuf[slot(qi) * P + qj] = v;
-                                   Abuf[slot(qj) * P + qi] = v;
-                                 });
+    if constexpr (COMPACT) {
+      const int kend = (npos + 3) & ~3;
+      tile_product_part<T, N, NT, false>(
+          npos, kend,
+          [&](int k, int q) {
+            return (k < npos && q < npos) ? Abuf[plist[k] * P + ix(0, plist[q])] : T(0);
+          },
+          [&](int k, int q) { return k < npos ? Vbuf[plist[k] * P + q] : T(0); },
+          [&](int qi, int qj, T v) {
+            if (qi < npos) Abuf[qi * P + qj] = v;
+          });
+      __syncthreads();
+      tile_product_part<T, N, NT, true>(
+          N, kend, [&](int k, int q) { return k < npos ? Vbuf[plist[k] * P + q] : T(0); },
+          [&](int k, int q) { return k < npos ? Abuf[k * P + q] : T(0); }, mirror);
+    } else {
+      tile_product<T, N, NT, false>([&](int k, int q) { return Abuf[k * P + q]; },
+                                    [&](int k, int q) { return Vbuf[k * P + q]; },
+                                    [&](int qi, int qj, T v) { Abuf[slot(qi) * P + qj] = v; });
+      __syncthreads();
+      tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
+                                   [&](int k, int q) { return Abuf[k * P + q]; }, mirror);
+    }
+  } else if constexpr (COMPACT) {
+    tile_product_part<T, N, NT, true>(
+        N, (npos + 3) & ~3,
+        [&](int k, int q) {
+          if (k >= npos) return T(0);
+          const int pk = plist[k];
+          return Vbuf[pk * P + q] * thp[pk];
+        },
+        [&](int k, int q) { return k < npos ? Vbuf[plist[k] * P + q] : T(0); }, mirror);
   } else {
     tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q] * thp[k]; },
-                                 [&](int k, int q) { return Vbuf[k * P + q]; },
-                                 [&](int qi, int qj, T v) {
-                                   Abuf[slot(qi) * P + qj] = v;
-                                   Abuf[slot(qj) * P + qi] = v;
-                                 });
+                                 [&](int k, int q) { return Vbuf[k * P + q]; }, mirror);
   }
   __syncthreads();
   const int npk = s * (s + 1) / 2;

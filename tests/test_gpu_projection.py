@@ -167,3 +167,35 @@ def test_nonfinite_blocks_give_nan_not_a_finite_result(sdp, gpu, dtype):
         assert np.all(np.isfinite(outs[0]))
         assert np.all(np.isnan(outs[1])), outs[1]
         assert not np.any(np.isfinite(outs[2])), outs[2]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_jacobi_variants_low_rank_and_definite_blocks(sdp, gpu, oracle_mod, dtype):
+    """The eigenvector variants of blocks of 64 and more rebuild X from the
+    positive eigenpairs only (a list of the positive slots): no positive
+    eigenvalue (zero and negative definite blocks: X = 0), all of them
+    (positive definite at the full size: X = W), rank 1, and rank 17 (the
+    list crosses a 16-row tile), at s = N and s = N - 3."""
+    dt = sdp.DTYPE_FP32 if dtype == np.float32 else sdp.DTYPE_FP64
+    variants = sdp.projection_variants(dt)
+    eig = [v for v in range(len(variants))
+           if sdp.projection_variant_kind(dt, v) != 2 and variants[v][0] >= 64]
+    assert eig, "no eigenvector variants of blocks of 64 and more"
+    rng = np.random.default_rng(21)
+    for v in eig:
+        N = variants[v][0]
+        for s in (N, N - 3):
+            Q, _ = np.linalg.qr(rng.standard_normal((s, s)))
+            G = rng.standard_normal((s, s))
+            lam1 = -rng.uniform(0.5, 2.0, s)
+            lam1[0] = 3.0
+            lam17 = rng.uniform(-2.0, -0.1, s)
+            lam17[rng.choice(s, 17, replace=False)] = rng.uniform(0.1, 2.0, 17)
+            blocks = [np.zeros((s, s)), G @ G.T + s * np.eye(s), -(G @ G.T),
+                      (Q * lam1) @ Q.T, (Q * lam17) @ Q.T]
+            blocks = [0.5 * (b + b.T) for b in blocks]
+            print(f"eigenvector variant {v}: N={N} NT={variants[v][1]} s={s}", flush=True)
+            outs = run_gpu(sdp, blocks, dtype, N, variant=v)
+            check(oracle_mod, blocks, outs, dtype)
+            assert np.all(outs[0] == 0.0)
+            assert np.all(np.abs(outs[2]) <= TOL[dtype] * np.linalg.norm(blocks[2]))
