@@ -613,7 +613,9 @@ __device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int r = 2 * aj + d, c = 2 * b + e;
-          A[j][d][e] = T(0.5) * (Vbuf[ix(r, c)] + Vbuf[ix(c, r)]);
+          // exactly symmetric: the lower-tile product stored both
+          // triangles from one value (no transposed, bank-conflicted read)
+          A[j][d][e] = Vbuf[ix(r, c)];
         }
     }
     __syncthreads();
@@ -831,7 +833,9 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int r = 2 * aj + d, c = 2 * b + e;
-          A[j][d][e] = T(0.5) * (Abuf[ix(r, c)] + Abuf[ix(c, r)]);
+          // exactly symmetric: the lower-tile product stored both
+          // triangles from one value (no transposed, bank-conflicted read)
+          A[j][d][e] = Abuf[ix(r, c)];
           V[j][d][e] = Vbuf[ix(r, c)];
         }
     }
