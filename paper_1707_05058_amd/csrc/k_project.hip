@@ -100,6 +100,30 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
+// NV block sums at once (one pair of barriers); each value is summed in the
+// order block_sum uses, so the results are the same bit for bit.
+template <int NT, int NV>
+__device__ inline void block_sum_n(double (&v)[NV], double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int n = 0; n < NV; ++n) v[n] += __shfl_xor(v[n], o, 64);
+  if (NT == 64) return;
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int n = 0; n < NV; ++n) red[n * (NT / 64) + w] = v[n];
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < NV; ++n) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[n * (NT / 64) + i];
+    v[n] = s;
+  }
+}
+
 // Row pitch of the LDS blocks (in elements).  FP32, N <= 48: P = N/4
 // (mod 32), so the row pairs that the 64 / K row groups of a wave read in a
 // Jacobi round sit on disjoint banks.  FP32, N >= 64 (one or two row groups
@@ -678,6 +702,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   __shared__ T prm_c[K], prm_s[K];
   __shared__ T th[N], thp[N];
   __shared__ double red[NT / 64];
+  __shared__ double red6[ADMM ? 6 * (NT / 64) : 1];
   __shared__ T ws[BLK ? (NT / 64) * (2 * 16 * QP + 32) : 1];
 
   const int tid = threadIdx.x;
@@ -741,6 +766,45 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 
   // --- gather W_k = E_k U E_k^T - Lambda_k / rho (or the caller's block) ---
   double f2 = 0.0;
+  // Algorithm 1 (the uniform common case): every entry's index and
+  // multiplier loads are issued before any is used, then the loads of u
+  // they index, so the thread waits for two memory latencies rather than
+  // two per entry (entries outside the clique load its first entry and
+  // are masked)
+  const bool primal = ADMM && !a.hsde && !a.dual;
+  if (primal) {
+    int32_t loc[BPT][2][2];
+    double lam[BPT][2][2];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int i = 2 * aj + d, k = 2 * b + e;
+          const int ii = i > k ? i : k, kk = i > k ? k : i;
+          const int64_t g = (i < s && k < s) ? off + (int64_t)ii * (ii + 1) / 2 + kk : off;
+          loc[j][d][e] = a.blk_loc[g];
+          lam[j][d][e] = a.Lam[g];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int aj = a0 + AS * j;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int i = 2 * aj + d, k = 2 * b + e;
+          const double wd = a.u[loc[j][d][e]] - lam[j][d][e] / rho;
+          const T w = (i < s && k < s) ? (T)wd : T(0);
+          A[j][d][e] = w;
+          V[j][d][e] = (i == k) ? T(1) : T(0);
+          f2 += (double)w * (double)w;
+        }
+    }
+  } else {
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int aj = a0 + AS * j;
@@ -776,6 +840,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
         V[j][d][e] = (i == k) ? T(1) : T(0);
         f2 += (double)w * (double)w;
       }
+  }
   }
   const double thr = tol * tol * block_sum<NT>(f2, red);
   if (MODE == MODE_STANDALONE && !(thr < INFINITY)) {
@@ -1126,6 +1191,24 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   __syncthreads();
   const int npk = s * (s + 1) / 2;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
+  // Algorithm 1 at packed entry e, given H_k x (hu) and the old X (xo) and
+  // Lambda (lo) there: X, Lambda and the residual partials
+  auto primal_step = [&](int e, double hu, double xo, double lo) {
+    int i, j;
+    tri_inv(e, i, j);
+    const int64_t g = off + e;
+    const double xn = (double)Abuf[ix(i, j)];
+    const double ln = lo + rho * (xn - hu);
+    a.X[g] = xn;
+    a.Lam[g] = ln;
+    const double wt = (i == j) ? 1.0 : 2.0;
+    const double dc = xn - hu, dx = xn - xo;
+    p0 += wt * dc * dc;
+    p1 += wt * xn * xn;
+    p2 += wt * hu * hu;
+    p3 += wt * dx * dx;
+    p4 += wt * ln * ln;
+  };
   // packed entry e (the it-th of this thread)
   auto epilogue = [&](int e, int it) {
     int i, j;
@@ -1167,27 +1250,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       p3 += wt * (zn - zo) * (zn - zo);
     } else {
       const int64_t g = off + e;
-      double hu, xo, lo;
-      if constexpr (PRE) {
-        hu = pre_u[it];
-        xo = pre_x[it];
-        lo = pre_l[it];
-      } else {
-        hu = a.u[a.blk_loc[g]];
-        xo = a.X[g];
-        lo = a.Lam[g];
-      }
-      const double xn = (double)acc;
-      const double ln = lo + rho * (xn - hu);
-      a.X[g] = xn;
-      a.Lam[g] = ln;
-      const double wt = (i == j) ? 1.0 : 2.0;
-      const double dc = xn - hu, dx = xn - xo;
-      p0 += wt * dc * dc;
-      p1 += wt * xn * xn;
-      p2 += wt * hu * hu;
-      p3 += wt * dx * dx;
-      p4 += wt * ln * ln;
+      if constexpr (PRE) primal_step(e, pre_u[it], pre_x[it], pre_l[it]);
+      else primal_step(e, a.u[a.blk_loc[g]], a.X[g], a.Lam[g]);
     }
   };
   if constexpr (PRE) {
@@ -1196,16 +1260,42 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       const int e = tid + NT * it;
       if (e < npk) epilogue(e, it);
     }
+  } else if (primal) {
+    // chunks of CH entries: all their loads are issued before any is used
+    // (entries past the end load the first entry and are skipped)
+    constexpr int CH = 8;
+    for (int e0 = tid; e0 < npk; e0 += CH * NT) {
+      int32_t lc[CH];
+      double cx[CH], cm[CH], cu[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int e = e0 + c * NT;
+        const int64_t g = off + (e < npk ? e : 0);
+        lc[c] = a.blk_loc[g];
+        cx[c] = a.X[g];
+        cm[c] = a.Lam[g];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) cu[c] = a.u[lc[c]];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int e = e0 + c * NT;
+        if (e < npk) primal_step(e, cu[c], cx[c], cm[c]);
+      }
+    }
   } else {
     for (int e = tid; e < npk; e += NT) epilogue(e, 0);
   }
   if (ADMM) {
-    p0 = block_sum<NT>(p0, red);
-    p1 = block_sum<NT>(p1, red);
-    p2 = block_sum<NT>(p2, red);
-    p3 = block_sum<NT>(p3, red);
-    p4 = block_sum<NT>(p4, red);
-    if (a.hsde) p6 = block_sum<NT>(p6, red);
+    if (a.hsde) {
+      double pv[6] = {p0, p1, p2, p3, p4, p6};
+      block_sum_n<NT, 6>(pv, red6);
+      p0 = pv[0]; p1 = pv[1]; p2 = pv[2]; p3 = pv[3]; p4 = pv[4]; p6 = pv[5];
+    } else {
+      double pv[5] = {p0, p1, p2, p3, p4};
+      block_sum_n<NT, 5>(pv, red6);
+      p0 = pv[0]; p1 = pv[1]; p2 = pv[2]; p3 = pv[3]; p4 = pv[4];
+    }
     if (tid == 0) {
       double *pp = a.part + NPART * (int64_t)cl;
       if (!a.dual) {
