@@ -166,6 +166,7 @@ STAGE_KERNELS = {"scatter": (("k_scatter", ""),), "A_v": (("k_rowdot<", ""), ("k
                                 ("k_project<float", ", 3, false>")),
                  "residual": (("k_residual_reduce", ""),)}
 COPY_CAL_BYTES = 512 << 20
+COMPUTE_UNITS = 256
 
 
 def _short_kernel(name):
@@ -420,9 +421,15 @@ def roofline_of(insts, stages_ms, sweeps, algorithm, extra, workload):
                     frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(workload, dom),
                     algorithmic_bytes_per_launch=info["bytes"], launch_ms=stages[dom])
     achieved = info["flops"] / t_launch / 1e12
+    # one workgroup per clique: a launch of fewer cliques than compute units
+    # leaves the rest idle, so the fraction of the occupied units is given too
+    wgs = sum(len(inst.clique_sizes()) for inst in insts)
+    occupied = min(wgs, COMPUTE_UNITS) / COMPUTE_UNITS
     return dict(kernel=dom, bound="alu", achieved=achieved, peak=info["peak_tflops"],
-                unit="TFLOP/s", frac=achieved / info["peak_tflops"], traffic=None,
-                model_flops_per_launch=info["flops"], launch_ms=stages[dom])
+                unit="TFLOP/s", frac=achieved / info["peak_tflops"],
+                traffic=load_traffic(workload, dom),
+                model_flops_per_launch=info["flops"], launch_ms=stages[dom],
+                workgroups=wgs, frac_of_occupied_units=achieved / (info["peak_tflops"] * occupied))
 
 
 def solver_options(args):
