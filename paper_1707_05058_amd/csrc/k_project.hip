@@ -707,6 +707,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 
   const int tid = threadIdx.x;
   int s, cl = 0;
+  bool inst_done = false;
   int64_t off;
   double rho = 1.0;
   if (MODE == MODE_STANDALONE) {
@@ -719,9 +720,12 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
     cl = list[x8 * q8 + min(x8, r8) + blockIdx.x / 8];
     const int inst = a.cl_inst[cl];
-    if (ADMM && a.state[inst].done) return;   // uniform per workgroup
+    // the clique record is loaded beside the instance index, and the
+    // instance's done flag is tested only after the gather (below) has its
+    // loads in flight: two memory latencies fewer before the first use of u
     s = a.cl_size[cl];
     off = a.cl_off[cl];
+    if (ADMM) inst_done = a.state[inst].done != 0;
     rho = a.state[inst].rho;
   }
 
@@ -842,6 +846,9 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       }
   }
   }
+  // a finished instance writes nothing (uniform per workgroup; the gather's
+  // loads feed f2, so they are issued before this test)
+  if (ADMM && inst_done) return;
   const double thr = tol * tol * block_sum<NT>(f2, red);
   if (MODE == MODE_STANDALONE && !(thr < INFINITY)) {
     // a NaN or infinite entry: NaN throughout, never a finite result
