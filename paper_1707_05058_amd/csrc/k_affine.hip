@@ -75,14 +75,16 @@ __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
   const int64_t j = g / SC_LANES;
   const int q = (int)(g % SC_LANES);
   if (j >= a.ncoord) return;             // whole lane groups leave together
+  // the contributor range loads beside the instance index, and the done
+  // test waits until the sums are formed (nothing is stored before it):
+  // three dependent loads before the sums instead of five
   const int inst = a.coord_inst[j];
+  const int64_t t0 = a.contrib_ptr[j], t1 = a.contrib_ptr[j + 1];
   const InstState &st = a.state[inst];
-  if (st.done) return;
-  const double rho = st.rho;
+  const bool done = st.done != 0;
   // sum_k (x_k + lambda_k / rho) - c / rho = sum_k x_k + (sum_k lambda_k - c) / rho
   double sx = 0.0, sl = 0.0;
-  const int64_t t1 = a.contrib_ptr[j + 1];
-  for (int64_t t = a.contrib_ptr[j] + q; t < t1; t += SC_LANES) {
+  for (int64_t t = t0 + q; t < t1; t += SC_LANES) {
     const int32_t e = a.contrib_idx[t];
     sx += a.X[e];
     sl += a.Lam[e];
@@ -92,6 +94,8 @@ __global__ __launch_bounds__(256) void k_scatter(AffineArgs a) {
     sx += __shfl_xor(sx, o, 64);
     sl += __shfl_xor(sl, o, 64);
   }
+  if (done) return;                      // uniform per lane group (one coordinate)
+  const double rho = st.rho;
   if (q == 0) {
     // Algorithm 1: sum_k (x_k + lambda_k/rho) - c/rho; Algorithm 2 (x_k = z_k):
     // c - sum_k (z_k + lambda_k/rho)
@@ -112,9 +116,15 @@ template <int R, bool NTL>
 __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
   const int inst = a.row_tiles[2 * blockIdx.x];
   const int row0 = a.row_tiles[2 * blockIdx.x + 1];
-  if (!a.ignore_done && a.state[inst].done) return;
-  if (a.cg_loop && a.cg[inst].done) return;
+  // the descriptor loads beside the done flag (one latency fewer before the
+  // stream starts); the empty asm takes its fields as inputs so that the
+  // compiler keeps those loads ahead of the test instead of sinking them
   const InstDesc d = a.inst[inst];
+  const int32_t done = a.state[inst].done;
+  asm volatile("" ::"s"(d.m), "s"(d.ld), "s"(d.a_off), "s"(d.coord_off), "s"(d.row_off),
+               "s"(done));
+  if (!a.ignore_done && done) return;
+  if (a.cg_loop && a.cg[inst].done) return;
   const int nrow = min(R, d.m - row0);
   const double *mat = (a.Bm ? a.Bm : a.A) + d.a_off + (int64_t)row0 * d.ld;
   const double2 *v2 = reinterpret_cast<const double2 *>(a.v + d.coord_off);
@@ -170,9 +180,15 @@ template <int RAW, bool NTL>
 __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
   const int inst = a.col_tiles[2 * blockIdx.x];
   const int col0 = a.col_tiles[2 * blockIdx.x + 1];
-  if (!a.ignore_done && a.state[inst].done) return;
-  if (a.cg_loop && a.cg[inst].done) return;
+  // the descriptor loads beside the done flag (one latency fewer before the
+  // stream starts); the empty asm takes its fields as inputs so that the
+  // compiler keeps those loads ahead of the test instead of sinking them
   const InstDesc d = a.inst[inst];
+  const int32_t done = a.state[inst].done;
+  asm volatile("" ::"s"(d.m), "s"(d.ld), "s"(d.a_off), "s"(d.coord_off), "s"(d.row_off),
+               "s"(done));
+  if (!a.ignore_done && done) return;
+  if (a.cg_loop && a.cg[inst].done) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = col0 + 2 * l;
   const double *vec = (a.Bm ? a.y1 : a.y) + d.row_off;
