@@ -1672,8 +1672,10 @@ int projection_max_size(int precision) { return precision == 1 ? 128 : 96; }
 // transposed element for the left operand makes each product X^T M, equal
 // to X M only while X is symmetric: without a correction the antisymmetric
 // rounding grows through the iteration (errors near 1e-2 in a lane-exact
-// simulation), so after every step X <- (X + X^T) / 2 through LDS (5e-8
-// then), and once more for the result.
+// simulation: the antisymmetric part changes sign and is scaled by up to 3
+// at every step), so X <- (X + X^T) / 2 through LDS after every second step
+// and after the last (the part then stays within 9 steps' rounding), and
+// once more for the result.
 template <typename T>
 __device__ inline int sign16_row(int g, int r) {
   return sizeof(T) == 4 ? 4 * g + r : g + 4 * r;
@@ -1742,13 +1744,18 @@ __global__ __launch_bounds__(64) void k_project_sign16(const int32_t *__restrict
     }
     T xn[4];
     prod(x, m, xn);                                             // X <- X M
-    // X <- (X + X^T) / 2 (both triangles from the same two values)
+    if ((it & 1) || it == k1 + k2 - 1) {
+      // X <- (X + X^T) / 2 (both triangles from the same two values)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) C[sign16_row<T>(g, r) * 17 + col] = xn[r];
-    __syncthreads();
+      for (int r = 0; r < 4; ++r) C[sign16_row<T>(g, r) * 17 + col] = xn[r];
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) x[r] = T(0.5) * (xn[r] + C[col * 17 + sign16_row<T>(g, r)]);
-    __syncthreads();
+      for (int r = 0; r < 4; ++r) x[r] = T(0.5) * (xn[r] + C[col * 17 + sign16_row<T>(g, r)]);
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[r] = xn[r];
+    }
   }
   // W S, symmetrised through LDS: P+(W) = (W + (W S + S W) / 2) / 2
   T c[4];
