@@ -636,16 +636,19 @@ def main():
 PROJ_SIZES = (15, 16, 24, 32, 50, 64, 96, 128)
 
 
-def sign_products(prec, N):
+def sign_products(prec, N, threads):
     """Matrix-core flops of one sign-function projection of a padded N x N
     block: k1 = ceil(log(1/tol) / log 3) steps of three products, k2 of two,
-    one final product; each product computes the TN (TN + 1) / 2 tiles on or
-    below the diagonal, 2 N 16^2 flops per tile."""
+    one final product, 2 N 16^2 flops per 16 x 16 tile; the LDS kernels form
+    the TN (TN + 1) / 2 tiles on or below the diagonal, the one-wave
+    register kernels for N = 32 all TN^2 (each off-diagonal tile is the
+    other's operand)."""
     tol = 1e-6 if prec == "fp32" else 1e-14
     k1 = max(4, math.ceil(math.log(1.0 / tol) / math.log(3.0)))
     k2 = 3 if prec == "fp32" else 4
     tn = N // 16
-    return (3 * k1 + 2 * k2 + 1) * tn * (tn + 1) // 2 * 2 * N * 16 * 16
+    tiles = tn * tn if (N == 32 and threads == 64) else tn * (tn + 1) // 2
+    return (3 * k1 + 2 * k2 + 1) * tiles * 2 * N * 16 * 16
 
 
 def run_projection(args, sdp, torch, stream):
@@ -701,7 +704,7 @@ def run_projection(args, sdp, torch, stream):
             model = 10.0 * s ** 3 * count
             executed = None
             if kinds[bv] == 2:
-                executed = sign_products(prec, variants[bv][0]) * count / (bms / 1e3) / 1e12
+                executed = sign_products(prec, variants[bv][0], variants[bv][1]) * count / (bms / 1e3) / 1e12
             res[f"{prec}_s{s}"] = dict(
                 s=s, blocks=count,
                 best_variant=dict(N=variants[bv][0], threads=variants[bv][1],
@@ -752,9 +755,10 @@ def run_projection(args, sdp, torch, stream):
                      "executed": head["executed_matrix_tflops"],
                      "executed_frac": head["executed_frac_of_peak"],
                      "executed_model": "sign method: (3 k1 + 2 k2 + 1) products of the padded "
-                                       "N x N block, tiles on or below the diagonal only "
-                                       "(TN (TN + 1) / 2 of TN^2 16 x 16 tiles, TN = N / 16), "
-                                       "2 N 16^2 flops per tile; FP32 matrix peak"},
+                                       "N x N block, 2 N 16^2 flops per 16 x 16 tile; the LDS "
+                                       "kernels form the TN (TN + 1) / 2 tiles on or below the "
+                                       "diagonal (TN = N / 16), the one-wave register kernel "
+                                       "for N = 32 all TN^2; FP32 matrix peak"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

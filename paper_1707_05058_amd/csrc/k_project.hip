@@ -1771,6 +1771,130 @@ __global__ __launch_bounds__(64) void k_project_sign16(const int32_t *__restrict
   }
 }
 
+// The same for blocks of 32, one wave per block: X is held as 2 x 2 tiles
+// of 16 (tile t = 2 I + J in registers 4t .. 4t + 3, rows 16 I + R(g, r),
+// column 16 J + l mod 16).  Tile (I, J) of a product sums over the depth
+// tiles K: its left operand X(16 I + i, 16 K + k) is, by symmetry, register
+// j of tile (K, I), its right operand register j of tile (K, J), so each
+// product is 32 matrix-core steps on registers (all four tiles are formed,
+// both off-diagonal ones included, since each is the other's operand).
+template <typename T>
+__global__ __launch_bounds__(64) void k_project_sign32(const int32_t *__restrict__ sizes,
+                                                      const int64_t *__restrict__ offsets,
+                                                      const T *__restrict__ in,
+                                                      T *__restrict__ out, int k1, int k2) {
+  typedef typename Mma<T>::v4 v4;
+  __shared__ T C[32 * 33];
+  const int l = threadIdx.x, g = l >> 4, col = l & 15;
+  const int s = sizes[blockIdx.x];
+  const int64_t off = offsets[blockIdx.x];
+  if (s <= 0 || s > 32) return;   // sizes beyond max_size are left untouched
+  const auto rowof = [&](int t, int r) { return 16 * (t >> 1) + sign16_row<T>(g, r); };
+  const auto colof = [&](int t) { return 16 * (t & 1) + col; };
+  T w[4][4];
+  double f2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = rowof(t, r), cc = colof(t);
+      T v = T(0);
+      if (row < s && cc < s)
+        v = T(0.5) * (in[off + (int64_t)row * s + cc] + in[off + (int64_t)cc * s + row]);
+      w[t][r] = v;
+      f2 += (double)v * (double)v;
+    }
+  f2 = wave_sum(f2);
+  if (!(f2 > 0.0 && f2 < INFINITY)) {
+    const T fill = f2 == 0.0 ? T(0) : T(NAN);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rowof(t, r), cc = colof(t);
+        if (row < s && cc < s) out[off + (int64_t)row * s + cc] = fill;
+      }
+    return;
+  }
+  const T scale = (T)(1.0 / sqrt(f2));
+  T x[4][4], id[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      x[t][r] = w[t][r] * scale;
+      id[t][r] = rowof(t, r) == colof(t) ? T(1) : T(0);
+    }
+  const auto prod = [](const T (&a)[4][4], const T (&b)[4][4], T (&c)[4][4]) {
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int K = 0; K < 2; ++K)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc = Mma<T>::step(a[2 * K + I][j], b[2 * K + J][j], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[2 * I + J][r] = acc[r];
+      }
+  };
+  const auto symmetrise = [&](const T (&v)[4][4], T (&dst)[4][4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) C[rowof(t, r) * 33 + colof(t)] = v[t][r];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[t][r] = T(0.5) * (v[t][r] + C[colof(t) * 33 + rowof(t, r)]);
+    __syncthreads();
+  };
+  for (int it = 0; it < k1 + k2; ++it) {
+    T y[4][4], m[4][4];
+    prod(x, x, y);                                              // Y = X^2
+    if (it < k1) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[t][r] = T(-3.2) * id[t][r] + T(1.2) * y[t][r];
+      T u[4][4];
+      prod(y, m, u);                                            // U = Y (-3.2 I + 1.2 Y)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[t][r] = T(3) * id[t][r] + u[t][r];
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[t][r] = T(1.5) * id[t][r] - T(0.5) * y[t][r];
+    }
+    T xn[4][4];
+    prod(x, m, xn);                                             // X <- X M
+    if ((it & 1) || it == k1 + k2 - 1) {
+      symmetrise(xn, x);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[t][r] = xn[t][r];
+    }
+  }
+  // W S, symmetrised: P+(W) = (W + (W S + S W) / 2) / 2
+  T c[4][4], cs[4][4];
+  prod(w, x, c);
+  symmetrise(c, cs);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = rowof(t, r), cc = colof(t);
+      if (row < s && cc < s) out[off + (int64_t)row * s + cc] = T(0.5) * (w[t][r] + cs[t][r]);
+    }
+}
+
 template <typename T, int N, int NT>
 hipError_t launch_sign(int count, const int32_t *sizes, const int64_t *offsets, const void *in,
                        void *out, int k1, int k2, hipStream_t st) {
@@ -1793,8 +1917,16 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
                          (const double *)in, (double *)out, k1, k2);
     return hipGetLastError();
   }
+  if (N == 32 && NT == 64) {   // blocks of 32: the register-resident kernel
+    if (dtype == 1)
+      hipLaunchKernelGGL(k_project_sign32<float>, dim3(count), dim3(64), 0, st, sizes, offsets,
+                         (const float *)in, (float *)out, k1, k2);
+    else
+      hipLaunchKernelGGL(k_project_sign32<double>, dim3(count), dim3(64), 0, st, sizes, offsets,
+                         (const double *)in, (double *)out, k1, k2);
+    return hipGetLastError();
+  }
   if (dtype == 1) {
-    SDP_SIGN(float, 32, 64)
     SDP_SIGN(float, 32, 256)
     SDP_SIGN(float, 48, 192)
     SDP_SIGN(float, 64, 256)
@@ -1803,7 +1935,6 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
     SDP_SIGN(float, 112, 448)
     SDP_SIGN(float, 128, 512)
   } else {
-    SDP_SIGN(double, 32, 64)
     SDP_SIGN(double, 48, 192)
     SDP_SIGN(double, 64, 256)
     SDP_SIGN(double, 80, 320)
