@@ -914,20 +914,25 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   }
 
   // positive/negative decoupling instead of sweeps (warm-started ADMM blocks
-  // whose eigenvectors are not recorded); after a failed attempt the clique
-  // skips it for dec_skip iterations (counter in its partial-sum slot 7)
+  // whose eigenvectors are not recorded).  After a failed attempt the clique
+  // skips it for a while, doubling the wait with every further failure in a
+  // row: dec_skip, 2 dec_skip, ... 16 dec_skip iterations (blocks whose two
+  // eigenvalue groups both reach zero fail the certificate every time); a
+  // success starts over.  Its partial-sum slot 7 keeps 256 level + wait.
   bool dec = false;
   if constexpr (DEC) {
     if (vw && !a.eig) {
       double *flag = a.part + NPART * (int64_t)cl + 7;
-      const double skip = dec_skip_left;
+      const double v = dec_skip_left;
+      const int level = (int)(v * (1.0 / 256.0));
       __syncthreads();   // every thread has read the counter before it changes
-      if (skip > 0.0) {
-        if (tid == 0) *flag = skip - 1.0;
+      if (v - 256.0 * level > 0.0) {
+        if (tid == 0) *flag = v - 1.0;
       } else {
         dec = decouple_blocks<T, N, NT, P>(A, V, Abuf, Vbuf, th, red, thr, a.dec_tmax2,
                                            a.dec_max_ref);
-        if (tid == 0) *flag = dec ? 0.0 : (double)a.dec_skip;
+        const int nl = level < 5 ? level + 1 : 5;
+        if (tid == 0) *flag = dec ? 0.0 : 256.0 * nl + (double)(a.dec_skip << (nl - 1));
       }
     }
   }
