@@ -118,3 +118,25 @@ def test_decouple_plans_scalar_variants_for_large_blocks(sdp, gpu):
                  for v in S.projection_plan_variants()]
     log(f"decouple on: two-level per bucket {kinds}")
     assert not any(kinds)
+
+
+def test_decouple_with_failing_certificates_reaches_oracle_optimum(sdp, gpu, oracle_mod):
+    """The nonchordal workload's extension in the FP32-eig form: its cliques
+    of 64 to 76 vertices fail the decoupling certificate near convergence
+    (both eigenvalue groups reach zero), so the attempts back off and the
+    sweeps carry the projection.  The solve to 1e-4 still stops within a few
+    iterations of the FP64 oracle and reaches its objective to 1e-4."""
+    from cases import as_instance
+    ext = as_instance(sdp.extend_instance(sdpgen.workload_nonchordal()))
+    P = oracle_mod.Problem(ext)
+    r = P.run(20000, tol=1e-4)
+    assert r.status == 0
+    with sdp.Solver([ext], tol=1e-4, max_iter=20000, precision="fp32", decouple=1) as S:
+        g = S.solve()[0]
+        st = S.stats()
+    log(f"nonchordal fp32: gpu {g['iters']} it obj {g['objective']:.10g} "
+        f"(sweeps per projection {st['jacobi_sweeps'] / max(st['projections'], 1):.3f}); "
+        f"oracle {r.iters} it obj {P.objective():.10g}")
+    assert g["status"] == 0
+    assert abs(g["iters"] - r.iters) <= max(3, 0.01 * r.iters)
+    assert abs(g["objective"] - P.objective()) <= 1e-4 * abs(P.objective())
