@@ -669,6 +669,100 @@ __device__ bool decouple_blocks(T (&A)[(N / 2) * (N / 2) / NT][2][2],
   }
 }
 
+// P+(A) for a block held in registers (the scalar variants' 2 x 2 layout),
+// by the matrix sign function on the matrix cores: X0 = A / ||A||_F, k1
+// steps X <- X (3 I - 3.2 X^2 + 1.2 X^4), k2 steps X <- X (3 I - X^2) / 2,
+// then P+(A) = (A + A sign(A)) / 2, which replaces A in the registers.  The
+// products are the lower-tile ones (every iterate exactly symmetric); Abuf
+// and Vbuf are scratch.  For blocks whose eigenvalue groups both reach zero,
+// where the decoupling's certificate fails and the sweeps would need several
+// passes of N - 1 rounds.
+template <typename T, int N, int NT, int P>
+__device__ void sign_project_regs(T (&A)[(N / 2) * (N / 2) / NT][2][2], T *Abuf, T *Vbuf,
+                                  double *red, int k1, int k2) {
+  constexpr int K = N / 2;
+  constexpr int BPT = K * K / NT;
+  constexpr int AS = NT / K;
+  const auto ix = [](int r, int c) { return r * P + (c & 1) * K + (c >> 1); };
+  const auto slot = [](int q) { return q < K ? 2 * q : 2 * (q - K) + 1; };
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int b = tid % K, a0 = tid / K;
+  double f2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j)
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) f2 += (double)A[j][d][e] * (double)A[j][d][e];
+  f2 = block_sum<NT>(f2, red);
+  const T scale = f2 > 0.0 ? (T)(1.0 / sqrt(f2)) : T(0);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int aj = a0 + AS * j;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) Abuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e] * scale;
+  }
+  __syncthreads();
+  const auto mirror_to = [&](T *buf) {
+    return [=](int qi, int qj, T v) {
+      if (qi >= qj) {
+        buf[slot(qi) * P + qj] = v;
+        buf[slot(qj) * P + qi] = v;
+      }
+    };
+  };
+  for (int it = 0; it < k1 + k2; ++it) {
+    // Y = X^2 into Vbuf
+    tile_product<T, N, NT, true>([&](int k, int q) { return Abuf[k * P + q]; },
+                                 [&](int k, int q) { return Abuf[k * P + q]; }, mirror_to(Vbuf));
+    __syncthreads();
+    if (it < k1) {
+      // Y (-3.2 I + 1.2 Y) over Y, then X (3 I + that) over X
+      tile_product<T, N, NT, true>(
+          [&](int k, int q) { return Vbuf[k * P + q]; },
+          [&](int k, int q) { return (k == slot(q) ? T(-3.2) : T(0)) + T(1.2) * Vbuf[k * P + q]; },
+          mirror_to(Vbuf));
+      __syncthreads();
+      tile_product<T, N, NT, true>(
+          [&](int k, int q) { return Abuf[k * P + q]; },
+          [&](int k, int q) { return (k == slot(q) ? T(3) : T(0)) + Vbuf[k * P + q]; },
+          mirror_to(Abuf));
+    } else {
+      tile_product<T, N, NT, true>(
+          [&](int k, int q) { return Abuf[k * P + q]; },
+          [&](int k, int q) { return (k == slot(q) ? T(1.5) : T(0)) - T(0.5) * Vbuf[k * P + q]; },
+          mirror_to(Abuf));
+    }
+    __syncthreads();
+  }
+  // A sign(A) with A into Vbuf, then P+(A) = (A + A sign(A)) / 2
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int aj = a0 + AS * j;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) Vbuf[ix(2 * aj + d, 2 * b + e)] = A[j][d][e];
+  }
+  __syncthreads();
+  tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
+                               [&](int k, int q) { return Abuf[k * P + q]; }, mirror_to(Abuf));
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int aj = a0 + AS * j;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        A[j][d][e] = T(0.5) * (A[j][d][e] + Abuf[ix(2 * aj + d, 2 * b + e)]);
+  }
+  __syncthreads();
+}
+
 template <typename T, int N, int NT, int MODE, bool BLK>
 __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__restrict__ list,
                                                 const int32_t *__restrict__ sizes,
@@ -919,7 +1013,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   // row: dec_skip, 2 dec_skip, ... 16 dec_skip iterations (blocks whose two
   // eigenvalue groups both reach zero fail the certificate every time); a
   // success starts over.  Its partial-sum slot 7 keeps 256 level + wait.
-  bool dec = false;
+  bool dec = false, sgn = false;
   if constexpr (DEC) {
     if (vw && !a.eig) {
       double *flag = a.part + NPART * (int64_t)cl + 7;
@@ -928,6 +1022,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       __syncthreads();   // every thread has read the counter before it changes
       if (v - 256.0 * level > 0.0) {
         if (tid == 0) *flag = v - 1.0;
+        // blocks of up to 96 with two or more failures in a row: the sign
+        // function instead of sweeps (for larger blocks its ~46 products
+        // cost more than the sweeps from the refined basis, which are few
+        // where failures are rare, as on the large workload's blocks of 128)
+        if (N <= 96 && level >= 2) {
+          sign_project_regs<T, N, NT, P>(A, Abuf, Vbuf, red, a.sign_k1, a.sign_k2);
+          sgn = true;
+        }
       } else {
         dec = decouple_blocks<T, N, NT, P>(A, V, Abuf, Vbuf, th, red, thr, a.dec_tmax2,
                                            a.dec_max_ref);
@@ -963,7 +1065,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
           if (WANT_V) V[j][d][e] = Vbuf[ix(2 * aj + d, 2 * b + e)];
     }
   }
-  for (; !BLK && !dec && sweep < max_sweeps; ++sweep) {
+  for (; !BLK && !dec && !sgn && sweep < max_sweeps; ++sweep) {
     double o2 = 0.0;
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -1151,7 +1253,8 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     Abuf[slot(qi) * P + qj] = v;
     Abuf[slot(qj) * P + qi] = v;
   };
-  if (!BLK && dec) {
+  if (!BLK && (dec || sgn)) {
+    // (after the sign function M is P+(A) itself, a full matrix)
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
       const int aj = a0 + AS * j;
@@ -1160,11 +1263,11 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int r = 2 * aj + d, c = 2 * b + e;
-          Abuf[ix(r, c)] = (th[r] > T(0) && th[c] > T(0)) ? A[j][d][e] : T(0);
+          Abuf[ix(r, c)] = (sgn || (th[r] > T(0) && th[c] > T(0))) ? A[j][d][e] : T(0);
         }
     }
     __syncthreads();
-    if constexpr (COMPACT) {
+    if (COMPACT && !sgn) {
       const int kend = (npos + 3) & ~3;
       tile_product_part<T, N, NT, false>(
           npos, kend,

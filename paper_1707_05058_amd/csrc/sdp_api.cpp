@@ -1070,6 +1070,10 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     p.decouple = opt.decouple && h->precision == SDP_FP32_EIG;
     p.dec_max_ref = h->precision == SDP_FP32_EIG ? 2 : 3;
     p.dec_skip = 4;
+    // the sign-function fallback of cliques whose certificate keeps failing:
+    // eigenvalues above the sweep tolerance (relative to ||W||_F) reach +-1
+    p.sign_k1 = std::max(4, (int)std::ceil(std::log(1.0 / h->jac_tol) / std::log(3.0)));
+    p.sign_k2 = 3;
     // the rotation Q = I + T + T^2 / 2 has Q^T Q - I = T^4 / 4, at most
     // ||T||_F^4 / 4: with ||T||_F^2 <= sqrt(tol / 0.75) that stays below a
     // third of the sweep tolerance (the bound limits the refinements to

@@ -97,6 +97,7 @@ struct ProjArgs {
   // per attempt, iterations a clique skips it after a failed attempt, bound
   // on ||T||_F^2 for one Newton-Schulz step
   int decouple, dec_max_ref, dec_skip;
+  int sign_k1, sign_k2;   // sign-function steps for cliques whose decoupling keeps failing
   double dec_tmax2;
   void *eig;              // optional: per clique V (s x N) then theta (N), precision T
   const int64_t *eig_off; // element offset of each clique's record in eig
