@@ -141,7 +141,10 @@ typedef struct {
                                    blocks, X is rebuilt from the positive block with no sweep;
                                    otherwise the Jacobi sweeps continue from the refined basis
                                    (and the clique skips the attempt for 4 iterations,
-                                   doubling after each further failure in a row, up to 64).  The
+                                   doubling after each further failure in a row, up to 64;
+                                   blocks of up to 96 with two or more failures in a row
+                                   use the matrix sign function instead of sweeps while
+                                   they wait).  The
                                    result is P+(W) to the sweep tolerance either way.  With
                                    projection_method = 0 those blocks then take the scalar
                                    variants (which carry the decoupling).  Ignored for FP64
