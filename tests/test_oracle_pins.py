@@ -412,3 +412,100 @@ def test_oracle_validation_codes(oracle_mod, case):
 
 def test_oracle_rank_deficient(oracle_mod):
     assert oracle_mod.create_status(rank_deficient_instance()) == oracle_mod.ERR_RANK_DEFICIENT
+
+
+# ----------------------------------------------------------------------------
+# Diagnostics: HSDEerror (relative primal/dual residuals and gap, Section 5.2.3)
+# and the PSD-violation bound eps_alpha (Section 7.2)
+# ----------------------------------------------------------------------------
+
+def _full_diagnostics(inst, u, y_dual, lam_blocks, b):
+    """eps_p, eps_d, eps_g and eps_alpha from explicit n x n matrices: X, C and
+    every A_i built on both triangles, Z = sum_k E_k^T Lambda_k E_k with the
+    selector matrices, Frobenius norms of the full matrices (no compact
+    weights anywhere)."""
+    n, m = inst.n, inst.m
+    X = full_sym_from_lower(inst, u)
+    C = full_sym_from_lower(inst, inst.c)
+    A = [full_sym_from_lower(inst, row) for row in inst.a_dense()]
+    Z = np.zeros((n, n))
+    cliques = [inst.clique_vert[inst.clique_ptr[k]:inst.clique_ptr[k + 1]]
+               for k in range(len(inst.clique_ptr) - 1)]
+    lmin = []
+    for k, cl in enumerate(cliques):
+        E = selector(cl, n)
+        Z += E.T @ lam_blocks[k] @ E
+        lmin.append(np.linalg.eigvalsh(E @ X @ E.T).min())
+    ax = np.array([np.sum(Ai * X) for Ai in A])
+    eps_p = np.linalg.norm(ax - b) / (1.0 + np.linalg.norm(b))
+    dres = sum(y_dual[i] * A[i] for i in range(m)) + Z - C
+    eps_d = np.linalg.norm(dres) / (1.0 + np.linalg.norm(C))
+    ctx, bty = np.sum(C * X), b @ y_dual
+    eps_g = abs(ctx - bty) / (1.0 + abs(ctx) + abs(bty))
+    alpha = -min(0.0, min(lmin))
+    eps_alpha = alpha / (1.0 + np.linalg.norm(X))
+    return dict(eps_p=eps_p, eps_d=eps_d, eps_g=eps_g, eps_alpha=eps_alpha,
+                objective=ctx, dual_objective=bty), alpha, X, cliques
+
+
+@pytest.mark.parametrize("iters,seed", [(2, 11), (5, 12), (9, 13)])
+def test_diagnostics_follow_their_definitions(oracle_mod, iters, seed):
+    """The oracle's eps_p, eps_d, eps_g (HSDEerror) and eps_alpha (PSD-violation)
+    on a non-converged iterate, against the definitions evaluated on explicit
+    full matrices.  b is replaced after the iteration, so that A x != b and the
+    primal residual's normalisation 1 + ||b|| is exercised (the x-update alone
+    keeps A x = b to rounding); the early iterate has clique blocks with
+    negative eigenvalues and large dual residuals, so a lambda_max for
+    lambda_min, a missing off-diagonal weight in ||X||_F or ||C||_F, or a
+    dropped 1 + in any denominator changes the result."""
+    inst = sdpgen.block_arrow_instance(4, 5, 3, 12, seed=seed)
+    P = oracle_mod.Problem(inst, rho0=0.7)
+    P.run(iters, tol=0.0)
+    rng = np.random.default_rng(seed)
+    b2 = inst.b + rng.standard_normal(inst.m)
+    P.set_cb(b=b2)
+    got = P.diagnostics()
+    _, Ls = P.blocks()
+    ref, alpha, X, cliques = _full_diagnostics(inst, P.u(), -P.rho * P.y(), Ls, b2)
+    assert alpha > 1e-3, "the test needs a clique block with a negative eigenvalue"
+    assert ref["eps_p"] > 1e-2 and ref["eps_d"] > 1e-3
+    for key in ("eps_p", "eps_d", "eps_g", "eps_alpha", "objective", "dual_objective"):
+        assert np.isclose(got[key], ref[key], rtol=1e-10, atol=1e-14), key
+
+
+def test_eps_alpha_is_the_smallest_completable_shift(oracle_mod):
+    """Section 7.2: alpha is the smallest non-negative shift with X + alpha I
+    PSD-completable; by the chordal completion theorem that means every clique
+    block of X + alpha I is PSD.  Checked with dense eigh on the blocks: alpha
+    makes them all PSD, 0.99 alpha leaves one indefinite; the normalisation
+    uses the full Frobenius norm of the partial matrix X."""
+    inst = sdpgen.banded_instance(30, 4, 15, seed=5)
+    P = oracle_mod.Problem(inst)
+    P.run(3, tol=0.0)
+    X = full_sym_from_lower(inst, P.u())
+    alpha = P.diagnostics()["eps_alpha"] * (1.0 + np.linalg.norm(X))
+    assert alpha > 1e-3
+    n = inst.n
+    cl = [inst.clique_vert[inst.clique_ptr[k]:inst.clique_ptr[k + 1]]
+          for k in range(len(inst.clique_ptr) - 1)]
+    mins = [np.linalg.eigvalsh(selector(c, n) @ (X + alpha * np.eye(n)) @ selector(c, n).T).min()
+            for c in cl]
+    assert min(mins) >= -1e-10 * alpha
+    mins99 = [np.linalg.eigvalsh(selector(c, n) @ (X + 0.99 * alpha * np.eye(n)) @ selector(c, n).T).min()
+              for c in cl]
+    assert min(mins99) < 0
+
+
+def test_eps_alpha_zero_for_psd_blocks(oracle_mod):
+    """With every clique block of X positive definite the bound is exactly 0:
+    after convergence of a MaxCut relaxation on a tree (optimum attained by a
+    rank-one +-1 matrix, blocks [[1, +-1], [+-1, 1]] shifted by the iterate's
+    rounding) alpha vanishes up to the 1e-10 residual."""
+    inst = sdpgen.maxcut_tree(12, 3)
+    P = oracle_mod.Problem(inst)
+    P.run(200000, tol=1e-11, adaptive=True)
+    d = P.diagnostics()
+    _, Ls = P.blocks()
+    ref, alpha, _, _ = _full_diagnostics(inst, P.u(), P.y_dual(), Ls, inst.b)
+    assert d["eps_alpha"] <= 1e-8
+    assert np.isclose(d["eps_alpha"], ref["eps_alpha"], rtol=1e-6, atol=1e-14)
