@@ -273,6 +273,22 @@ int sdp_get_history(sdp_handle *h, int32_t inst, int32_t cap, double *eps_c,
  * iterate on the GPU and stores them in res (batch entries). */
 int sdp_diagnostics(sdp_handle *h, sdp_result *res);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * diagnostics as sdp_diagnostics, with the same results, but every scratch
+ * vector lives in one static device array of 2^21 doubles (16 MiB) that the
+ * library holds on each GPU it runs on until the process ends; the call
+ * makes no hipMalloc, hipFree or other device allocation.  The handle needs
+ * 3 doubles per coordinate slot, 2 per row slot and 1 per clique (slots are
+ * the 64-padded counts of all instances); a larger handle returns
+ * SDP_ERR_UNSUPPORTED without launching anything.  The first call on a
+ * device looks up the array's address there (SDP_ERR_HIP if that fails).
+ * Every call on one GPU shares the array and overwrites what the previous
+ * call left (all of it is written before it is read): calls that overlap in
+ * time on one GPU, from several threads or on several streams, race.
+ * Synchronises the handle's stream. */
+int sdp_diagnostics_noalloc(sdp_handle *h, sdp_result *res);
+
 /* Statistics since setup/reset: total Jacobi sweeps and clique projections run. */
 int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
 

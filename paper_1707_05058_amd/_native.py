@@ -74,7 +74,7 @@ class sdp_result(C.Structure):
 EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sdp_solve",
            "sdp_psd_project_batched", "sdp_projection_variants", "sdp_psd_project_variant",
            "sdp_get_solution", "sdp_set_state", "sdp_get_history",
-           "sdp_diagnostics", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
+           "sdp_diagnostics", "sdp_diagnostics_noalloc", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
            "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_cg_steps", "sdp_destroy",
            "sdp_projection_variant_kind", "sdp_projection_plan_variants",
            "sdp_last_error",
@@ -106,6 +106,7 @@ def _load():
     lib.sdp_set_state.argtypes = [_p, C.c_int32, dp, dp, C.c_double]
     lib.sdp_get_history.argtypes = [_p, C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32)]
     lib.sdp_diagnostics.argtypes = [_p, C.POINTER(sdp_result)]
+    lib.sdp_diagnostics_noalloc.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_get_stats.argtypes = [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     ip = C.POINTER(C.c_int32)
     lib.sdp_projection_plan.argtypes = [_p, C.c_int32, ip, ip, ip, ip]
@@ -254,9 +255,12 @@ class Solver:
         _check(lib.sdp_solve(self._h, res), ok=(OK, MAX_ITER, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE))
         return [r.as_dict() for r in res]
 
-    def diagnostics(self):
+    def diagnostics(self, noalloc: bool = False):
+        """eps_p, eps_d, eps_g, eps_alpha of the current iterate; noalloc selects
+        sdp_diagnostics_noalloc (scratch in the library's static device array)."""
         res = (sdp_result * self.batch)()
-        _check(lib.sdp_diagnostics(self._h, res))
+        fn = lib.sdp_diagnostics_noalloc if noalloc else lib.sdp_diagnostics
+        _check(fn(self._h, res))
         return [r.as_dict() for r in res]
 
     def solution(self, i: int = 0):

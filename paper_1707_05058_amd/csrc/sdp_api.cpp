@@ -1275,6 +1275,53 @@ int guarded(F &&f) {
 
 }  // namespace
 
+// Scratch of the allocation-free diagnostics: one static array per device,
+// held until the process ends (see diag_scratch_address).
+constexpr int64_t kDiagScratchDoubles = int64_t(1) << 21;   // 16 MiB
+static __device__ __align__(256) double scratch[kDiagScratchDoubles];
+
+namespace {
+
+// The diagnostics launches on a given scratch record (six vectors, every
+// entry overwritten by the kernels before it is read), then the host copy.
+void run_diagnostics(sdp_handle *h, const DiagScratch &s, sdp_result *res) {
+  for (size_t b = 0; b < h->bucket_size.size(); ++b)
+    HIPCHK(launch_min_eig(h->precision, h->bucket_size[b], h->bucket_list[b], h->bucket_count[b],
+                          h->proj, s.lmin, h->stream));
+  ensure_y(h);
+  HIPCHK(launch_diagnostics(h->aff, s, h->aff.inst_cl_first, h->nrow, h->d_diag, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(h->diag.data(), h->d_diag, sizeof(double) * 4 * h->B, hipMemcpyDeviceToHost));
+  h->have_diag = true;
+  if (res) fill_results(h, res);
+}
+
+// Host code never uses the name `scratch` as an address (on the host it
+// names a stand-in, not device memory): it asks the runtime for the array's
+// address on device `dev` once, with that device current, and keeps it.
+constexpr int kMaxDevices = 64;
+
+double *diag_scratch_address(int dev) {
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) fail(SDP_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      fail(SDP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = static_cast<double *>(p);
+  }
+  return addr[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 void sdp_default_options(sdp_options *opt) {
@@ -1548,16 +1595,36 @@ int sdp_diagnostics(sdp_handle *h, sdp_result *res) {
       h->dscr.yd = dev_zeros<double>(h->nrow, h->owned);
       h->dscr.lmin = dev_zeros<double>(h->ncl, h->owned);
     }
-    for (size_t b = 0; b < h->bucket_size.size(); ++b)
-      HIPCHK(launch_min_eig(h->precision, h->bucket_size[b], h->bucket_list[b], h->bucket_count[b],
-                            h->proj, h->dscr.lmin, h->stream));
-    ensure_y(h);
-    HIPCHK(launch_diagnostics(h->aff, h->dscr, h->aff.inst_cl_first, h->nrow, h->d_diag,
-                              h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    HIPCHK(hipMemcpy(h->diag.data(), h->d_diag, sizeof(double) * 4 * h->B, hipMemcpyDeviceToHost));
-    h->have_diag = true;
-    if (res) fill_results(h, res);
+    run_diagnostics(h, h->dscr, res);
+    return SDP_OK;
+  });
+}
+
+int sdp_diagnostics_noalloc(sdp_handle *h, sdp_result *res) {
+  return guarded([&] {
+    if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    if (h->hsde) {
+      if (res) fill_results(h, res);
+      return SDP_OK;
+    }
+    const int64_t need = 3 * h->ncoord + 2 * h->nrow + h->ncl;
+    if (need > kDiagScratchDoubles)
+      fail(SDP_ERR_UNSUPPORTED,
+           "sdp_diagnostics_noalloc: the handle needs " + std::to_string(need) +
+               " doubles of scratch (3 per coordinate slot, 2 per row slot, 1 per clique); the "
+               "static limit is " + std::to_string(kDiagScratchDoubles));
+    int dev = -1;   // the device the handle's stream (and so its kernels) runs on
+    HIPCHK(hipStreamGetDevice(h->stream, &dev));
+    double *base = diag_scratch_address(dev);
+    // ncoord and nrow are multiples of 64, so every vector starts 512-byte aligned
+    DiagScratch s;
+    s.wu = base;
+    s.z = s.wu + h->ncoord;
+    s.aty = s.z + h->ncoord;
+    s.ax = s.aty + h->ncoord;
+    s.yd = s.ax + h->nrow;
+    s.lmin = s.yd + h->nrow;
+    run_diagnostics(h, s, res);
     return SDP_OK;
   });
 }
