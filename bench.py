@@ -274,8 +274,32 @@ def copy_calibration(torch):
     del src, dst
 
 
+def graph_chunk_for(steps, warmup, cap=50):
+    """Iterations per captured graph for the timed run: the largest divisor of
+    gcd(K, W) up to `cap` (of K alone without warm-up), so that W warm-up
+    iterations build the graph and K timed ones are whole graph launches."""
+    g = math.gcd(steps, warmup) if warmup > 0 else steps
+    return max(d for d in range(1, min(g, cap) + 1) if g % d == 0)
+
+
+def timed_steps(S, torch, stream, steps, warmup):
+    """W untimed iterations, then exactly K between HIP events on the solver's
+    stream; returns (milliseconds, stats before, stats after)."""
+    with torch.cuda.stream(stream):
+        S.step(warmup, results=False)
+        torch.cuda.synchronize()
+        st0 = S.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.step(steps, results=False)
+        e1.record(stream)
+        e1.synchronize()
+        torch.cuda.synchronize()
+    return e0.elapsed_time(e1), st0, S.stats()
+
+
 def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, repeat_solve=True,
-              algorithm="primal", extra=None):
+              algorithm="primal", extra=None, eager=True):
     out = {}
     extra = dict(extra or {})
     p_total = sum(i.p for i in insts)
@@ -312,27 +336,29 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     if extra.get("cg_max_iter"):
         out["solve"]["cg_steps_per_iteration"] = S.cg_steps() / max(sum(its), 1)
     S.close()
-    # --- the contract: W warm-up + exactly K timed iterations ---
+    # --- the contract: W warm-up + exactly K timed iterations, through the
+    # captured-graph path a solve takes: the graph holds a number of iterations
+    # that divides both W and K, so the warm-up captures and instantiates it
+    # and the timed K iterations are graph launches only ---
+    chunk = graph_chunk_for(steps, warmup)
+    out["graph_chunk"] = chunk
     S = sdp.Solver(insts, tol=0.0, max_iter=10 ** 8, precision=precision,
-                   stream=stream.cuda_stream, algorithm=algorithm, **extra)
-    with torch.cuda.stream(stream):
-        S.step(warmup, results=False)
-        torch.cuda.synchronize()
-        st0 = S.stats()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        S.step(steps, results=False)
-        e1.record(stream)
-        e1.synchronize()
-        torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+                   stream=stream.cuda_stream, algorithm=algorithm, graph_chunk=chunk, **extra)
+    ms, st0, st1 = timed_steps(S, torch, stream, steps, warmup)
     out["ms_per_step"] = ms / steps
     out["iter_per_s"] = steps / (ms / 1e3)
     out["projections_per_s"] = out["iter_per_s"] * p_total
     out["instance_iter_per_s"] = out["iter_per_s"] * len(insts)
-    st1 = S.stats()
     out["timed_sweeps_per_projection"] = ((st1["jacobi_sweeps"] - st0["jacobi_sweeps"]) /
                                           max(st1["projections"] - st0["projections"], 1))
+    if eager:
+        # the same W + K with plain launches (no graph), for comparison
+        E = sdp.Solver(insts, tol=0.0, max_iter=10 ** 8, precision=precision,
+                       stream=stream.cuda_stream, algorithm=algorithm, graph_chunk=0, **extra)
+        ms_e, _, _ = timed_steps(E, torch, stream, steps, warmup)
+        E.close()
+        out["eager_ms_per_step"] = ms_e / steps
+        out["eager_iter_per_s"] = steps / (ms_e / 1e3)
     stages = S.time_stages(stage_iters)
     if extra.get("cg_max_iter"):
         # the solve sits in the slot of the first substitution; there is no second
@@ -437,6 +463,8 @@ def solver_options(args):
     extra = dict(EXTRA_OPTIONS.get(args.workload, {}))
     if args.decouple is not None:
         extra["decouple"] = args.decouple
+    if args.projection_method is not None:
+        extra["projection_method"] = args.projection_method
     return extra
 
 
@@ -527,6 +555,9 @@ def main():
     ap.add_argument("--decouple", type=int, choices=(0, 1), default=None,
                     help="positive/negative decoupling of warm-started projections "
                          "(default: the library's default)")
+    ap.add_argument("--projection-method", default=None,
+                    choices=("auto", "scalar", "two_level", "sign"),
+                    help="eigensolver of the clique projections (default: the library's)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         cmds = open(args.commands_file).read().strip().splitlines() if args.commands_file else []
