@@ -33,12 +33,12 @@ def rel_err(a, b):
 
 
 def compare_fixed_n(sdp, oracle_mod, inst, n_iter, precision="fp64", rho=1.0, tol_rel=1e-8,
-                    graph_chunk=25):
-    log(f"fixed-N parity {inst.name} N={n_iter} precision={precision}")
+                    graph_chunk=25, **opts):
+    log(f"fixed-N parity {inst.name} N={n_iter} precision={precision} {opts}")
     P = oracle_mod.Problem(inst, rho0=rho)
     r = P.run(n_iter, tol=0.0)
     with sdp.Solver([inst], rho=rho, tol=0.0, max_iter=100000, precision=precision,
-                    graph_chunk=graph_chunk) as S:
+                    graph_chunk=graph_chunk, **opts) as S:
         S.step(n_iter)
         sol = S.solution(0)
         hc, hl, hr = S.history(0)
