@@ -129,7 +129,10 @@ typedef struct {
                                    with autotune = 0, the default variant) chooses; 1 scalar
                                    parallel-order Jacobi only; 2 the two-level (block) Jacobi
                                    wherever a variant for the clique size exists (blocks of
-                                   64 and more), scalar elsewhere */
+                                   64 and more), scalar elsewhere; 3 (Algorithm 1) cliques of
+                                   up to 32 vertices take the matrix sign function in one
+                                   wave's registers (X_k = (W + W sign(W)) / 2, no
+                                   eigenvectors, no warm start), larger ones as with 0 */
   int32_t decouple;             /* 1 (SDP_FP32_EIG with warm_start = 1; blocks padded to 64
                                    and more; Algorithms 1-3 outside the unrolled iterations):
                                    a warm-started projection first separates the eigenspaces
@@ -231,9 +234,19 @@ int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_
  *              polynomial Newton-Schulz iterations on the matrix cores
  *              (ceil(log(1/tol) / log 3) steps of X (3I - 3.2X^2 + 1.2X^4), then
  *              3 (FP32) or 4 (FP64) of X (3I - X^2) / 2).  It yields no
- *              eigenvectors, so only sdp_psd_project_variant runs it; the
- *              solver's plans hold kinds 0 and 1 only. */
+ *              eigenvectors: the standalone projections run it, and the
+ *              solver's plans hold it only for Algorithm 1's cliques of up
+ *              to 32 vertices with projection_method = 3 (the one-wave
+ *              variants of 16 and 32), where the projection needs no
+ *              eigenvectors; everything else in the solver is kind 0 or 1. */
 int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *kind);
+
+/* The variant sdp_psd_project_batched runs for blocks of up to max_size
+ * (host only): the sign-function variant of the smallest block size that
+ * holds max_size, the one-wave register kernel where there are several
+ * (blocks of 16 and 32).  SDP_ERR_UNSUPPORTED if max_size is out of range
+ * for dtype. */
+int sdp_projection_default_variant(int32_t dtype, int32_t max_size, int32_t *variant);
 
 /* sdp_psd_project_batched with an explicit kernel variant (an index into the
  * list of sdp_projection_variants); max_size must not exceed that variant's
@@ -291,6 +304,13 @@ int sdp_diagnostics_noalloc(sdp_handle *h, sdp_result *res);
 
 /* Statistics since setup/reset: total Jacobi sweeps and clique projections run. */
 int sdp_get_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections);
+
+/* The same statistics plus the number of projections since setup/reset that
+ * took the matrix sign function as the fallback of a clique whose
+ * decoupling certificate failed twice or more in a row (option decouple).
+ * Any pointer may be NULL. */
+int sdp_get_projection_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections,
+                             int64_t *sign_fallbacks);
 
 /* The projection launch plan chosen at setup: one entry per launch list, with
  * the padded block size N, the threads per workgroup NT and the number of

@@ -74,9 +74,11 @@ class sdp_result(C.Structure):
 EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sdp_solve",
            "sdp_psd_project_batched", "sdp_projection_variants", "sdp_psd_project_variant",
            "sdp_get_solution", "sdp_set_state", "sdp_get_history",
-           "sdp_diagnostics", "sdp_diagnostics_noalloc", "sdp_get_stats", "sdp_projection_plan", "sdp_time_stages",
+           "sdp_diagnostics", "sdp_diagnostics_noalloc", "sdp_get_stats",
+           "sdp_get_projection_stats", "sdp_projection_plan", "sdp_time_stages",
            "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_cg_steps", "sdp_destroy",
            "sdp_projection_variant_kind", "sdp_projection_plan_variants",
+           "sdp_projection_default_variant",
            "sdp_last_error",
            "sdp_pattern_create", "sdp_pattern_sizes", "sdp_pattern_get", "sdp_pattern_destroy",
            "sdp_scale_compute", "sdp_scale_apply", "sdp_scale_recover"]
@@ -108,6 +110,7 @@ def _load():
     lib.sdp_diagnostics.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_diagnostics_noalloc.argtypes = [_p, C.POINTER(sdp_result)]
     lib.sdp_get_stats.argtypes = [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.sdp_get_projection_stats.argtypes = [_p] + [C.POINTER(C.c_int64)] * 3
     ip = C.POINTER(C.c_int32)
     lib.sdp_projection_plan.argtypes = [_p, C.c_int32, ip, ip, ip, ip]
     lib.sdp_time_stages.argtypes = [_p, C.c_int32, dp]
@@ -116,6 +119,7 @@ def _load():
     lib.sdp_vjp.argtypes = [_p, _p, _p, _p, C.c_int32]
     lib.sdp_cg_steps.argtypes = [_p, C.POINTER(C.c_int64)]
     lib.sdp_projection_variant_kind.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    lib.sdp_projection_default_variant.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     lib.sdp_projection_plan_variants.argtypes = [_p, C.c_int32, ip, C.POINTER(C.c_int32)]
     lib.sdp_destroy.argtypes = [_p]
     lib.sdp_destroy.restype = None
@@ -168,7 +172,7 @@ def make_options(**kw) -> sdp_options:
         elif k == "algorithm" and isinstance(v, str):
             v = {"primal": ALG_PRIMAL, "dual": ALG_DUAL, "hsde": ALG_HSDE}[v.lower()]
         elif k == "projection_method" and isinstance(v, str):
-            v = {"auto": 0, "scalar": 1, "two_level": 2}[v.lower()]
+            v = {"auto": 0, "scalar": 1, "two_level": 2, "sign": 3}[v.lower()]
         setattr(o, k, v)
     return o
 
@@ -326,9 +330,9 @@ class Solver:
                            C.c_void_p(b_bar.data_ptr()), int(bool(euclidean))))
 
     def stats(self):
-        sw, pr = C.c_int64(0), C.c_int64(0)
-        _check(lib.sdp_get_stats(self._h, C.byref(sw), C.byref(pr)))
-        return dict(jacobi_sweeps=sw.value, projections=pr.value)
+        sw, pr, sg = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        _check(lib.sdp_get_projection_stats(self._h, C.byref(sw), C.byref(pr), C.byref(sg)))
+        return dict(jacobi_sweeps=sw.value, projections=pr.value, sign_fallbacks=sg.value)
 
     def cg_steps(self) -> int:
         """Conjugate-gradient steps over all instances since the last reset."""
@@ -419,9 +423,17 @@ def psd_project_batched(sizes, offsets, inp, out, max_size: int, stream=None,
 
 
 def projection_variant_kind(dtype: int, variant: int) -> int:
-    """0 scalar Jacobi, 1 two-level Jacobi, 2 sign function (standalone only)."""
+    """0 scalar Jacobi, 1 two-level Jacobi, 2 sign function (no eigenvectors)."""
     t = C.c_int32(0)
     _check(lib.sdp_projection_variant_kind(int(dtype), int(variant), C.byref(t)))
+    return t.value
+
+
+def projection_default_variant(dtype: int, max_size: int) -> int:
+    """The variant psd_project_batched runs (no explicit variant) for blocks of
+    up to max_size."""
+    t = C.c_int32(0)
+    _check(lib.sdp_projection_default_variant(int(dtype), int(max_size), C.byref(t)))
     return t.value
 
 

@@ -340,12 +340,14 @@ constexpr int RES_NT = 256;
 __device__ void residual_block(const AffineArgs &a, int inst) {
   InstState &st = a.state[inst];
   const int64_t c0 = a.inst_cl_first[inst], c1 = a.inst_cl_first[inst + 1];
-  double s[NPART] = {0, 0, 0, 0, 0, 0};
+  double s[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 4
   for (int64_t k = c0 + threadIdx.x; k < c1; k += RES_NT) {
     const double2 *pk = reinterpret_cast<const double2 *>(a.part + NPART * k);
     const double2 q0 = pk[0], q1 = pk[1], q2 = pk[2];
+    const double q6 = a.part[NPART * k + 6];   // sign-function fallback taken (0 or 1)
     s[0] += q0.x; s[1] += q0.y; s[2] += q1.x; s[3] += q1.y; s[4] += q2.x; s[5] += q2.y;
+    s[6] += q6;
   }
   const int32_t done = st.done;
   __shared__ double red[RES_NT / 64][NPART];
@@ -380,6 +382,7 @@ __device__ void residual_block(const AffineArgs &a, int inst) {
   st.eps_l = eps_l;
   st.iter = it;
   st.total_sweeps += S[5];
+  st.total_sign += S[6];
   if (P.no_stop) return;
   const double e = eps_c > eps_l ? eps_c : eps_l;
   if (e <= P.tol) {

@@ -1418,7 +1418,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       }
       pp[3] = p3;
       pp[5] = (double)sweep;
-      pp[6] = p6;
+      pp[6] = a.hsde ? p6 : (sgn ? 1.0 : 0.0);   // Algorithms 1, 2: sign fallback taken
     }
   }
 }
@@ -1728,17 +1728,20 @@ int projection_default_variant(int precision, int s) {
   return best;
 }
 
-// Standalone projections: the first listed sign-function variant of the
-// smallest fitting N (fastest at every size measured), else the Jacobi default.
+// Standalone projections: the sign-function variant of the smallest fitting
+// N with the fewest threads (fastest at every size measured: for N = 32 the
+// one-wave register kernel beats the LDS one by 1.6x), else the Jacobi default.
 int projection_standalone_variant(int precision, int s) {
   const int n = s + (s & 1);
-  int best = -1, bestN = 1 << 30;
+  int best = -1, bestN = 1 << 30, bestNT = 1 << 30;
   for (int v = 0; v < projection_variant_count(precision); ++v) {
     int N, NT;
     projection_variant_info(precision, v, &N, &NT);
-    if (projection_variant_kind(precision, v) == 2 && N >= n && N < bestN) {
+    if (projection_variant_kind(precision, v) != 2 || N < n) continue;
+    if (N < bestN || (N == bestN && NT < bestNT)) {
       best = v;
       bestN = N;
+      bestNT = NT;
     }
   }
   return best >= 0 ? best : projection_default_variant(precision, s);
@@ -2003,6 +2006,205 @@ __global__ __launch_bounds__(64) void k_project_sign32(const int32_t *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 1's clique step for blocks of up to 16 TB vertices (TB = 1, 2) in
+// one wave's registers, with no eigenvectors: X_k = P+(W_k) by the sign
+// iteration of k_project_sign16/32 on W_k = H_k x - Lambda_k / rho, then the
+// multiplier update Lambda_k += rho (X_k - H_k x) (XkUpdate, LambdakUpdate)
+// and the five residual partials of k_project's ADMM epilogue.  The register
+// layout is the sign kernels': tile t = TB I + J holds rows 16 I + R(g, r) at
+// column 16 J + l mod 16.  W_k(i, k) and W_k(k, i) come from the same packed
+// entry, so W_k is exactly symmetric.
+// ---------------------------------------------------------------------------
+template <typename T, int TB>
+__global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__restrict__ list,
+                                                  int k1, int k2) {
+  constexpr int NTL = TB * TB, NB = 16 * TB, CP = NB + 1;
+  typedef typename Mma<T>::v4 v4;
+  __shared__ T C[NB * CP];
+  const int l = threadIdx.x, g = l >> 4, col = l & 15;
+  // neighbouring cliques share coordinates of u: keep them on one XCD
+  const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+  const int cl = list[x8 * q8 + min(x8, r8) + blockIdx.x / 8];
+  const int inst = a.cl_inst[cl];
+  const int s = a.cl_size[cl];
+  const int64_t off = a.cl_off[cl];
+  const bool inst_done = a.state[inst].done != 0;
+  const double rho = a.state[inst].rho;
+  const auto rowof = [&](int t, int r) { return 16 * (t / TB) + sign16_row<T>(g, r); };
+  const auto colof = [&](int t) { return 16 * (t % TB) + col; };
+
+  // gather: every index, multiplier and old-X load is issued before any is
+  // used, then the loads of u they index (entries outside the clique read
+  // its first entry and are masked).  Blocks of 16 keep the FP64 values for
+  // the epilogue in registers; blocks of 32 (16 entries per lane) load them
+  // again there, from the cache, so that the sign iteration keeps two waves
+  // per SIMD.
+  constexpr bool KEEP = TB == 1;
+  constexpr int KT = KEEP ? NTL : 1;
+  int32_t loc[NTL][4];
+  double lam[NTL][4], xo[KT][4], hu[KT][4];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rowof(t, r), k = colof(t);
+      const int ii = i > k ? i : k, kk = i > k ? k : i;
+      const int64_t e = (i < s && k < s) ? off + (int64_t)ii * (ii + 1) / 2 + kk : off;
+      loc[t][r] = a.blk_loc[e];
+      lam[t][r] = a.Lam[e];
+      if constexpr (KEEP) xo[t][r] = a.X[e];
+    }
+  T w[NTL][4];
+  double f2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rowof(t, r), k = colof(t);
+      const double h = a.u[loc[t][r]];
+      if constexpr (KEEP) hu[t][r] = h;
+      const T v = (i < s && k < s) ? (T)(h - lam[t][r] / rho) : T(0);
+      w[t][r] = v;
+      f2 += (double)v * (double)v;
+    }
+  f2 = wave_sum(f2);
+  // a finished instance writes nothing (uniform per workgroup)
+  if (inst_done) return;
+
+  // sign(W) from X0 = W / ||W||_F (W = 0 gives X = 0 and P+(W) = 0)
+  const T scale = f2 > 0.0 ? (T)(1.0 / sqrt(f2)) : T(0);
+  T x[NTL][4], id[NTL][4];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      x[t][r] = w[t][r] * scale;
+      id[t][r] = rowof(t, r) == colof(t) ? T(1) : T(0);
+    }
+  const auto prod = [](const T (&p)[NTL][4], const T (&q)[NTL][4], T (&z)[NTL][4]) {
+#pragma unroll
+    for (int I = 0; I < TB; ++I)
+#pragma unroll
+      for (int J = 0; J < TB; ++J) {
+        v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int K = 0; K < TB; ++K)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc = Mma<T>::step(p[TB * K + I][j], q[TB * K + J][j], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[TB * I + J][r] = acc[r];
+      }
+  };
+  const auto symmetrise = [&](const T (&v)[NTL][4], T (&dst)[NTL][4]) {
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) C[rowof(t, r) * CP + colof(t)] = v[t][r];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[t][r] = T(0.5) * (v[t][r] + C[colof(t) * CP + rowof(t, r)]);
+    __syncthreads();
+  };
+  for (int it = 0; it < k1 + k2; ++it) {
+    T y[NTL][4], m[NTL][4];
+    prod(x, x, y);                                              // Y = X^2
+    if (it < k1) {
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[t][r] = T(-3.2) * id[t][r] + T(1.2) * y[t][r];
+      T z[NTL][4];
+      prod(y, m, z);                                            // Z = Y (-3.2 I + 1.2 Y)
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[t][r] = T(3) * id[t][r] + z[t][r];
+    } else {
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[t][r] = T(1.5) * id[t][r] - T(0.5) * y[t][r];
+    }
+    T xn[NTL][4];
+    prod(x, m, xn);                                             // X <- X M
+    if ((it & 1) || it == k1 + k2 - 1) {
+      symmetrise(xn, x);
+    } else {
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[t][r] = xn[t][r];
+    }
+  }
+  // X_k = P+(W) = (W + (W S + S W) / 2) / 2
+  T c[NTL][4], cs[NTL][4];
+  prod(w, x, c);
+  symmetrise(c, cs);
+
+  // epilogue on the lower entries: X_k, Lambda_k and the residual partials
+  // (||X - Hx||^2, ||X||^2, ||Hx||^2, ||X - X_prev||^2, ||Lambda||^2, full
+  // Frobenius norms: off-diagonal entries count twice)
+  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
+  double lo[NTL][4], xp[NTL][4], hp[NTL][4];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rowof(t, r), k = colof(t);
+      const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
+      const bool lower = i < s && k <= i;
+      if constexpr (KEEP) {
+        lo[t][r] = lam[t][r];
+        xp[t][r] = xo[t][r];
+        hp[t][r] = hu[t][r];
+      } else {
+        lo[t][r] = lower ? a.Lam[e] : 0.0;
+        xp[t][r] = lower ? a.X[e] : 0.0;
+        hp[t][r] = lower ? a.u[loc[t][r]] : 0.0;
+      }
+    }
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rowof(t, r), k = colof(t);
+      if (i < s && k <= i) {
+        const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
+        const double xn = (double)(T(0.5) * (w[t][r] + cs[t][r]));
+        const double hx = hp[t][r];
+        const double ln = lo[t][r] + rho * (xn - hx);
+        a.X[e] = xn;
+        a.Lam[e] = ln;
+        const double wt = (i == k) ? 1.0 : 2.0;
+        const double dc = xn - hx, dx = xn - xp[t][r];
+        p0 += wt * dc * dc;
+        p1 += wt * xn * xn;
+        p2 += wt * hx * hx;
+        p3 += wt * dx * dx;
+        p4 += wt * ln * ln;
+      }
+    }
+  p0 = wave_sum(p0);
+  p1 = wave_sum(p1);
+  p2 = wave_sum(p2);
+  p3 = wave_sum(p3);
+  p4 = wave_sum(p4);
+  if (l == 0) {
+    double *pp = a.part + NPART * (int64_t)cl;
+    pp[0] = p0;
+    pp[1] = p1;
+    pp[2] = p2;
+    pp[3] = p3;
+    pp[4] = p4;
+    pp[5] = 0.0;   // no Jacobi sweeps
+    pp[6] = 0.0;
+  }
+}
+
 template <typename T, int N, int NT>
 hipError_t launch_sign(int count, const int32_t *sizes, const int64_t *offsets, const void *in,
                        void *out, int k1, int k2, hipStream_t st) {
@@ -2056,6 +2258,30 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
                                   const ProjArgs &a, hipStream_t st) {
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
+  if (projection_variant_kind(precision, variant) == 2) {
+    // sign-function lists: Algorithm 1's register kernels; a caller that
+    // needs eigenvectors (the unrolled forward records V, theta) or another
+    // algorithm gets the Jacobi default of the same block size
+    if (!a.eig && !a.dual && !a.hsde && NT == 64 && (N == 16 || N == 32)) {
+      if (count <= 0) return hipSuccess;
+      const int k1 = std::max(4, (int)std::ceil(std::log(1.0 / a.tol) / std::log(3.0)));
+      const int k2 = precision == 1 ? 3 : 4;
+      if (precision == 1) {
+        if (N == 16)
+          hipLaunchKernelGGL((k_admm_sign<float, 1>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
+        else
+          hipLaunchKernelGGL((k_admm_sign<float, 2>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
+      } else {
+        if (N == 16)
+          hipLaunchKernelGGL((k_admm_sign<double, 1>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
+        else
+          hipLaunchKernelGGL((k_admm_sign<double, 2>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
+      }
+      return hipGetLastError();
+    }
+    variant = projection_default_variant(precision, N);
+    projection_variant_info(precision, variant, &N, &NT);
+  }
   const int blk = projection_variant_two_level(precision, variant);
   if (a.decouple && a.vw && !a.eig) {
     if (precision == 1)
@@ -2098,6 +2324,10 @@ hipError_t launch_min_eig(int precision, int variant, const int32_t *list, int c
                           const ProjArgs &a, double *lmin_out, hipStream_t st) {
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
+  if (projection_variant_kind(precision, variant) == 2) {   // eigenvalues: Jacobi
+    variant = projection_default_variant(precision, N);
+    projection_variant_info(precision, variant, &N, &NT);
+  }
   const int blk = projection_variant_two_level(precision, variant);
   if (precision == 1)
     return dispatch<float, MODE_MINEIG>(N, NT, blk, count, a, list, nullptr, nullptr, nullptr, nullptr,

@@ -216,6 +216,23 @@ int default_variant(int precision, int s, int method) {
   return best;
 }
 
+// The register-resident sign-function variant (one wave, N = 16 or 32) for
+// cliques of s vertices, -1 if s > 32.
+int sign_variant(int precision, int s) {
+  if (s > 32) return -1;
+  const int want = s <= 16 ? 16 : 32;
+  for (int v = 0; v < projection_variant_count(precision); ++v) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (projection_variant_kind(precision, v) == 2 && N == want && NT == 64) return v;
+  }
+  return -1;
+}
+
+// Whether projection_method 0 takes the sign-function variants for
+// Algorithm 1's cliques of up to 32 vertices.
+bool sign_by_default(int precision) { return false; }
+
 int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol, bool warm,
                  int method, hipStream_t st) {
   std::vector<int> cand = fitting_variants(precision, s, method);
@@ -675,6 +692,10 @@ void reset_state(sdp_handle *h) {
                         h->stream));
   HIPCHK(hipMemsetAsync(h->proj.X, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
   HIPCHK(hipMemsetAsync(h->proj.Lam, 0, sizeof(double) * std::max<int64_t>(h->npk, 1), h->stream));
+  // the per-clique partial-sum records, including the decoupling's back-off
+  // counter (slot 7), start from zero as in a fresh handle
+  HIPCHK(hipMemsetAsync(h->proj.part, 0, sizeof(double) * NPART * std::max<int64_t>(h->ncl, 1),
+                        h->stream));
   HIPCHK(hipMemsetAsync(h->aff.u, 0, sizeof(double) * h->ncoord, h->stream));
   HIPCHK(hipMemsetAsync(h->aff.y, 0, sizeof(double) * h->nrow, h->stream));
   if (h->cg) {
@@ -732,7 +753,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       (opt.algorithm == SDP_ALG_HSDE && opt.adaptive_rho) ||
       (opt.adaptive_rho && (!(opt.mu >= 1) || !(opt.nu >= 1) || opt.rho_period <= 0)) ||
       opt.graph_chunk < 0 || opt.cg_max_iter < 0 || !(opt.cg_tol >= 0) ||
-      opt.projection_method < 0 || opt.projection_method > 2 || opt.decouple < 0 ||
+      opt.projection_method < 0 || opt.projection_method > 3 || opt.decouple < 0 ||
       opt.decouple > 1)
     fail(SDP_ERR_ARG, "invalid options");
   if (opt.cg_max_iter > 0 && opt.algorithm != SDP_ALG_PRIMAL)
@@ -846,17 +867,26 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       std::map<int, int64_t> count_of_size;
       for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
       std::map<int, int> var_of_size;
+      // Algorithm 1's cliques of up to 32 vertices: the sign-function
+      // variants (one wave's registers, no eigenvectors) where selected
+      const bool sign_lists = opt.algorithm == SDP_ALG_PRIMAL &&
+                              (opt.projection_method == 3 ||
+                               (opt.projection_method == 0 && sign_by_default(h->precision)));
       // with the decoupling (FP32, warm start) the large blocks take the
       // scalar variants, which carry it
+      const int pm = opt.projection_method == 3 ? 0 : opt.projection_method;
       const int method = (opt.decouple && opt.warm_start && h->precision == SDP_FP32_EIG &&
-                          opt.projection_method == 0)
+                          pm == 0)
                              ? 1
-                             : opt.projection_method;
-      for (auto &kv : count_of_size)
+                             : pm;
+      for (auto &kv : count_of_size) {
+        const int sv = sign_lists ? sign_variant(h->precision, kv.first) : -1;
         var_of_size[kv.first] =
-            opt.autotune ? tune_variant(h->precision, kv.first, kv.second, h->max_sweeps,
-                                        h->jac_tol, opt.warm_start != 0, method, h->stream)
-                         : default_variant(h->precision, kv.first, method);
+            sv >= 0 ? sv
+            : opt.autotune ? tune_variant(h->precision, kv.first, kv.second, h->max_sweeps,
+                                          h->jac_tol, opt.warm_start != 0, method, h->stream)
+                           : default_variant(h->precision, kv.first, method);
+      }
       for (int64_t k = 0; k < cl; ++k) {
         const int v = var_of_size[cl_size[k]];
         auto it = std::find(h->bucket_size.begin(), h->bucket_size.end(), v);
@@ -1472,6 +1502,18 @@ int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *kind) {
   });
 }
 
+int sdp_projection_default_variant(int32_t dtype, int32_t max_size, int32_t *variant) {
+  return guarded([&] {
+    if (dtype != SDP_DTYPE_FP64 && dtype != SDP_DTYPE_FP32) fail(SDP_ERR_ARG, "invalid dtype");
+    if (!variant) fail(SDP_ERR_ARG, "invalid arguments");
+    const int prec = dtype == SDP_DTYPE_FP32 ? 1 : 0;
+    if (max_size <= 0 || max_size > projection_max_size(prec))
+      fail(SDP_ERR_UNSUPPORTED, "max_size out of range for this dtype");
+    *variant = projection_standalone_variant(prec, max_size);
+    return SDP_OK;
+  });
+}
+
 int sdp_projection_plan_variants(sdp_handle *h, int32_t cap, int32_t *variant, int32_t *count) {
   return guarded([&] {
     if (!h || cap < 0 || !count) fail(SDP_ERR_ARG, "invalid arguments");
@@ -1542,6 +1584,12 @@ int sdp_set_state(sdp_handle *h, int32_t inst, const double *Xk, const double *L
     if (h->proj.Vd)   // Algorithm 2: the slack blocks start at consensus, v_k = z_k
       HIPCHK(hipMemcpyAsync(h->proj.Vd + o, h->proj.X + o, sizeof(double) * n,
                             hipMemcpyDeviceToDevice, h->stream));
+    {   // the instance's cliques start their decoupling back-off afresh (slot 7)
+      const int64_t c0 = h->cl_first[inst], c1 = h->cl_first[inst + 1];
+      if (c1 > c0)
+        HIPCHK(hipMemsetAsync(h->proj.part + NPART * c0, 0, sizeof(double) * NPART * (c1 - c0),
+                              h->stream));
+    }
     if (h->d_vw) {
       HIPCHK(launch_identity_bases(h->precision, h->d_vw, h->d_vw_off, h->d_clique_N,
                                    h->cl_first[inst], h->cl_first[inst + 1] - h->cl_first[inst],
@@ -1625,6 +1673,24 @@ int sdp_diagnostics_noalloc(sdp_handle *h, sdp_result *res) {
     s.yd = s.ax + h->nrow;
     s.lmin = s.yd + h->nrow;
     run_diagnostics(h, s, res);
+    return SDP_OK;
+  });
+}
+
+int sdp_get_projection_stats(sdp_handle *h, int64_t *jacobi_sweeps, int64_t *projections,
+                             int64_t *sign_fallbacks) {
+  return guarded([&] {
+    if (!h) fail(SDP_ERR_ARG, "NULL handle");
+    pull_state(h);
+    int64_t sw = 0, pr = 0, sg = 0;
+    for (int i = 0; i < h->B; ++i) {
+      sw += (int64_t)h->h_state[i].total_sweeps;
+      pr += (int64_t)h->h_state[i].iter * h->inst_p[i];
+      sg += (int64_t)h->h_state[i].total_sign;
+    }
+    if (jacobi_sweeps) *jacobi_sweeps = sw;
+    if (projections) *projections = pr;
+    if (sign_fallbacks) *sign_fallbacks = sg;
     return SDP_OK;
   });
 }

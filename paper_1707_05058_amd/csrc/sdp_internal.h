@@ -42,6 +42,7 @@ struct InstState {
   double rho;
   double eps_c, eps_l;
   double total_sweeps;
+  double total_sign;   // projections that took the sign-function fallback
   int32_t iter;
   int32_t done;        // 1: converged, 2: iteration limit reached,
                        // 3: primal infeasible, 4: dual infeasible (Algorithm 3)

@@ -123,9 +123,11 @@ def test_decouple_plans_scalar_variants_for_large_blocks(sdp, gpu):
 def test_decouple_with_failing_certificates_reaches_oracle_optimum(sdp, gpu, oracle_mod):
     """The nonchordal workload's extension in the FP32-eig form: its cliques
     of 64 to 76 vertices fail the decoupling certificate near convergence
-    (both eigenvalue groups reach zero), so the attempts back off and the
-    sweeps carry the projection.  The solve to 1e-4 still stops within a few
-    iterations of the FP64 oracle and reaches its objective to 1e-4."""
+    (both eigenvalue groups reach zero), so the attempts back off, and after
+    two failures in a row the matrix sign function carries those cliques
+    (blocks of up to 96) while they wait.  The solve to 1e-4 still stops
+    within a few iterations of the FP64 oracle and reaches its objective to
+    1e-4."""
     from cases import as_instance
     ext = as_instance(sdp.extend_instance(sdpgen.workload_nonchordal()))
     P = oracle_mod.Problem(ext)
@@ -135,8 +137,56 @@ def test_decouple_with_failing_certificates_reaches_oracle_optimum(sdp, gpu, ora
         g = S.solve()[0]
         st = S.stats()
     log(f"nonchordal fp32: gpu {g['iters']} it obj {g['objective']:.10g} "
-        f"(sweeps per projection {st['jacobi_sweeps'] / max(st['projections'], 1):.3f}); "
+        f"(sweeps per projection {st['jacobi_sweeps'] / max(st['projections'], 1):.3f}, "
+        f"{st['sign_fallbacks']} sign-function fallbacks); "
         f"oracle {r.iters} it obj {P.objective():.10g}")
+    assert st["sign_fallbacks"] > 0
     assert g["status"] == 0
     assert abs(g["iters"] - r.iters) <= max(3, 0.01 * r.iters)
     assert abs(g["objective"] - P.objective()) <= 1e-4 * abs(P.objective())
+
+
+def _nonchordal_extension(sdp):
+    from cases import as_instance
+    return as_instance(sdp.extend_instance(sdpgen.workload_nonchordal()))
+
+
+def test_sign_fallback_fixed_n_matches_oracle(sdp, gpu, oracle_mod):
+    """Fixed-N parity through the sign-function fallback: 1400 FP32-eig
+    iterations of the nonchordal extension, long enough for its cliques of
+    65 to 76 vertices (padded to 80) to fail the certificate twice in a row
+    and take the fallback (counted in the stats); X, Lambda, u and the
+    residual history then match the FP64 oracle.  Bar: each FP32 projection
+    is accurate to ~1e-6 ||W||_F (sweep tolerance, sign iteration resolving
+    eigenvalues down to 3^-13 ||W||_F) and the ADMM map is nonexpansive, so
+    N iterations differ by at most ~N * 1e-6 relative: 1.5e-6 N."""
+    ext = _nonchordal_extension(sdp)
+    n_iter = 1400
+    st = parity(sdp, oracle_mod, [ext], n_iter, "fp32", 1.5e-6 * n_iter)
+    log(f"  sign-function fallbacks: {st['sign_fallbacks']}")
+    assert st["sign_fallbacks"] > 0
+
+
+def test_reset_restores_decoupling_back_off_bitwise(sdp, gpu):
+    """sdp_reset returns every clique's decoupling back-off to its initial
+    state: after a run long enough for certificate failures (and sign-function
+    fallbacks), a reset and the same run again reproduce a fresh handle's
+    iterates bit for bit; so does sdp_set_state with the zero state."""
+    ext = _nonchordal_extension(sdp)
+    n = 1400
+    with sdp.Solver([ext], tol=0.0, max_iter=100000, precision="fp32", decouple=1) as S:
+        S.step(n)
+        first = S.solution(0)
+        st1 = S.stats()
+        S.reset()
+        S.step(n)
+        second = S.solution(0)
+        st2 = S.stats()
+        S.set_state(0, np.zeros(S.npk[0]), np.zeros(S.npk[0]), 1.0)
+        S.step(n)
+        third = S.solution(0)
+    log(f"  fallbacks: first run {st1['sign_fallbacks']}, after reset {st2['sign_fallbacks']}")
+    assert st1["sign_fallbacks"] > 0 and st2["sign_fallbacks"] == st1["sign_fallbacks"]
+    for key in ("u", "X_packed", "L_packed", "y_dual"):
+        assert np.array_equal(first[key], second[key]), key
+        assert np.array_equal(first[key], third[key]), key
