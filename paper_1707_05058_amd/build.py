@@ -15,6 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdp.so")
 SOURCES = ["k_project.hip", "k_affine.hip", "k_factor.hip", "k_adjoint.hip", "k_hsde.hip", "sdp_api.cpp",
+           "sdp_validate.cpp",
            "sdp_pattern.cpp", "sdp_scale.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SDP_OFFLOAD_ARCH", "gfx950")
