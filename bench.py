@@ -84,11 +84,12 @@ def stage_bytes_flops(insts, precision, sweeps, algorithm="primal", cg_steps=0):
     """Algorithmic HBM bytes (or FLOPs) per launch of each stage, summed over
     the instances of the batch.  Dense A is streamed as B = L^-1 A (same size)
     and needs no triangular passes; sparse A is streamed as CSR (12 bytes per
-    nonzero) plus the two triangular factors.  The projection count, per
-    clique of size s with `sweeps` Jacobi sweeps on average: 6 s^3 per sweep
-    (each of the s(s-1)/2 rotations of a sweep updates two rows and columns of
-    the symmetric block and two columns of V), 4 s^3 for V0^T W V0 (warm
-    start), 4 s^3 for the Newton-Schulz step and s^3 for the rebuild.
+    nonzero) plus the two triangular factors.  The projection's figure is the
+    method's work, 10 s^3 per clique of s (9 s^3 for a symmetric
+    eigendecomposition with vectors, s^3 for the rebuild), whatever the
+    kernel executes (Jacobi sweeps, warm-start and Newton-Schulz products, or
+    the sign iteration's products; the compute counters give that); `sweeps`
+    is kept for the callers and no longer enters it.
     With the conjugate-gradient affine step (cg_steps per iteration) A is
     streamed as itself; each step is one column pass (A^T p, written as
     W D^-1 A^T p), one row pass (A v) and the per-instance row-vector update
@@ -102,7 +103,7 @@ def stage_bytes_flops(insts, precision, sweeps, algorithm="primal", cg_steps=0):
         npk = int(np.sum(sizes * (sizes + 1) // 2))
         tot["scatter"] += 8 * 2 * npk + 4 * npk + 8 * 5 * nnz
         tot["residual"] += 8 * 6 * inst.p
-        tot["proj"] += int(np.sum((6 * sweeps + 9) * sizes ** 3))
+        tot["proj"] += int(np.sum(10 * sizes ** 3))
         if cg_steps > 0:
             abytes = 12 * int(inst.a_rowptr[-1]) if inst.a_format == 1 else 8 * m * nnz
             tot["scatter"] += 8 * nnz                      # A^T y of the last solve
@@ -163,7 +164,7 @@ STAGE_KERNELS = {"scatter": (("k_scatter", ""),), "A_v": (("k_rowdot<", ""), ("k
                  "Linv_r": (("k_trmv_wave<0>", ""),), "LinvT_y": (("k_trmv_wave<1>", ""),),
                  "AT_y": (("k_coldot<0,", ""), ("k_csc_coldot<0>", "")),
                  "projection": (("k_project<float", ", 0, false>"), ("k_project<float", ", 0, true>"),
-                                ("k_project<float", ", 3, false>")),
+                                ("k_project<float", ", 3, false>"), ("k_admm_sign<float", "")),
                  "residual": (("k_residual_reduce", ""),)}
 COPY_CAL_BYTES = 512 << 20
 COMPUTE_UNITS = 256
@@ -261,6 +262,107 @@ def summarize_rocprof(workload, trace_dir, fetch_dir, write_dir, commands):
     with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json"), "w") as f:
         json.dump(out, f, indent=1)
     print("\n".join(lines))
+
+
+# compute counters of the --summarize-counters passes (rocprofv3 --pmc, one
+# pass per group; at most 8 SQ and 2 GRBM counters in one pass)
+COUNTER_PASSES = (
+    ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_VALU_MFMA_BUSY_CYCLES",
+     "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU",
+     "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"),
+    ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+     "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_LDS", "SQ_WAVES",
+     "SQ_INSTS_SALU"),
+)
+FP32_MATRIX_TFLOPS = 157.3      # dense FP32 MFMA peak
+FP64_MATRIX_TFLOPS = 78.6
+SIMDS = 4 * COMPUTE_UNITS
+CLOCK_GHZ = 2.4
+KERNEL_SOURCES = (("k_project", "k_project.hip"), ("k_admm_sign", "k_project.hip"),
+                  ("k_adj_proj", "k_adjoint.hip"), ("k_", "k_affine.hip"))
+
+
+def kernel_source(short):
+    for prefix, src in KERNEL_SOURCES:
+        if short.startswith(prefix):
+            return src
+    return None
+
+
+def summarize_counters(workload, trace_dir, pass_dirs, commands, kernels_prefix=("k_",)):
+    """Executed work of each kernel from rocprofv3 --pmc passes (COUNTER_PASSES)
+    and its mean duration from a --kernel-trace --stats run of the same
+    command: matrix-core FLOPs (SQ_INSTS_VALU_MFMA_MOPS_* x 512), vector FP
+    FLOPs (64 lanes x (ADD + MUL + 2 FMA) instructions; transcendental and
+    other instructions are counted, not converted to flops), MFMA busy
+    fraction (SQ_VALU_MFMA_BUSY_CYCLES over all SIMDs at 2.4 GHz for the
+    kernel's duration).  Writes profiles/counters_<workload>.md and .json."""
+    stats = {_short_kernel(r["Name"]): float(r["AverageNs"]) for r in
+             _csv_rows(trace_dir, "kernel_stats.csv")}
+    vals = {}
+    for d in pass_dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            name = _short_kernel(r.get("Kernel_Name") or r.get("Kernel-Name") or "")
+            cn = r.get("Counter_Name") or r.get("Counter-Name") or ""
+            v = float(r.get("Counter_Value") or r.get("Counter-Value") or 0.0)
+            vals.setdefault(name, {}).setdefault(cn, []).append(v)
+    out = {"workload": workload, "clock_ghz": CLOCK_GHZ, "simds": SIMDS, "kernels": {}}
+    lines = [f"# Compute counters, {workload} workload ({WORKLOADS[workload]})", "",
+             "Commands (repository root, one MI355X; each rocprofv3 run in its own process):", "",
+             "```"] + commands + ["```", "",
+             "Per launch: matrix-core FLOPs = 512 x SQ_INSTS_VALU_MFMA_MOPS_{F32,F64}; vector "
+             "FLOPs = 64 x (ADD + MUL + 2 FMA) wave instructions; MFMA busy = "
+             "SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x 2.4 GHz x mean duration).", "",
+             "| kernel | launches | mean (us) | MFMA GFLOP | VALU F32 GFLOP | VALU F64 GFLOP | "
+             "executed TFLOP/s | % FP32 matrix peak | MFMA busy | VALU instr. | LDS instr. |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name in sorted(vals, key=lambda n: -stats.get(n, 0.0)):
+        if not name.startswith(tuple(kernels_prefix)) or name not in stats:
+            continue
+        c = {k: sum(v) / len(v) for k, v in vals[name].items()}
+        launches = max(len(v) for v in vals[name].values())
+        t = stats[name] * 1e-9
+        mf = 512.0 * (c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) + c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0))
+        v32 = 64.0 * (c.get("SQ_INSTS_VALU_ADD_F32", 0.0) + c.get("SQ_INSTS_VALU_MUL_F32", 0.0)
+                      + 2.0 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0))
+        v64 = 64.0 * (c.get("SQ_INSTS_VALU_ADD_F64", 0.0) + c.get("SQ_INSTS_VALU_MUL_F64", 0.0)
+                      + 2.0 * c.get("SQ_INSTS_VALU_FMA_F64", 0.0))
+        tf = (mf + v32 + v64) / t / 1e12 if t > 0 else 0.0
+        busy = (c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (SIMDS * CLOCK_GHZ * 1e9 * t)
+                if t > 0 else 0.0)
+        src = kernel_source(name)
+        ent = {"launches": launches, "mean_us": t * 1e6, "mfma_flops_per_launch": mf,
+               "valu_f32_flops_per_launch": v32, "valu_f64_flops_per_launch": v64,
+               "executed_tflops": tf, "frac_fp32_matrix_peak": tf / FP32_MATRIX_TFLOPS,
+               "mfma_busy": busy, "counters": c, "source": src,
+               "source_hash": source_hash(src) if src else None}
+        out["kernels"][name] = ent
+        lines.append(f"| `{name}` | {launches} | {t * 1e6:.2f} | {mf / 1e9:.4f} | {v32 / 1e9:.4f} | "
+                     f"{v64 / 1e9:.4f} | {tf:.2f} | {100 * tf / FP32_MATRIX_TFLOPS:.1f} | "
+                     f"{100 * busy:.1f}% | {c.get('SQ_INSTS_VALU', 0.0):.4g} | "
+                     f"{c.get('SQ_INSTS_LDS', 0.0):.4g} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"counters_{workload}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(ROOT, "profiles", f"counters_{workload}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("\n".join(lines))
+    return out
+
+
+def load_counters(workload, kernel):
+    """Counter record of one kernel from profiles/counters_<workload>.json, if
+    it was taken on the kernel's current source."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        ent = json.load(open(path))["kernels"].get(kernel)
+    except Exception:
+        return None
+    if not ent or not ent.get("source") or ent.get("source_hash") != source_hash(ent["source"]):
+        return None
+    return ent
 
 
 def copy_calibration(torch):
@@ -369,6 +471,35 @@ def time_form(sdp, torch, insts, precision, steps, warmup, stage_iters, stream, 
     return out
 
 
+def batched_leg(args, sdp, torch, stream):
+    """The batched half of the metric beside the headline: the 512-instance
+    workload in one handle, FP32-eig and FP64 (W warm-up + at most 100 timed
+    iterations each through captured graphs, and a solve of every instance to
+    1e-4 from a cold start), against a loop of per-instance FP64 solves."""
+    insts = make_instances("batched", args.batch_count)
+    steps = min(args.steps, 100)
+    out = {"workload": WORKLOADS["batched"], "steps": steps, "warmup": args.warmup}
+    keep = ("setup_s", "graph_chunk", "ms_per_step", "iter_per_s", "instance_iter_per_s",
+            "projections_per_s", "stages_ms", "solve")
+    for precision in ("fp32", "fp64"):
+        print(f"[bench] batched {precision}: timing", file=sys.stderr, flush=True)
+        f = time_form(sdp, torch, insts, precision, steps, args.warmup, args.stage_iters, stream,
+                      repeat_solve=False, eager=False, extra=solver_options(args))
+        out["fp32_eig" if precision == "fp32" else "fp64"] = {k: f[k] for k in keep if k in f}
+        print(f"[bench] batched {precision}: {f['iter_per_s']:.1f} batched iter/s",
+              file=sys.stderr, flush=True)
+    print("[bench] batched: loop of per-instance FP64 solves", file=sys.stderr, flush=True)
+    loop = time_loop(sdp, torch, insts[:32], "fp64", min(steps, 100), 10, stream, len(insts))
+    out["loop_fp64"] = loop
+    f32, f64 = out["fp32_eig"], out["fp64"]
+    out["speedup_fp32_vs_fp64_iter_per_s"] = f32["iter_per_s"] / f64["iter_per_s"]
+    out["speedup_fp32_vs_fp64_time_to_tol"] = (f64["solve"]["time_to_tol_s"] /
+                                               f32["solve"]["time_to_tol_s"])
+    out["speedup_batched_fp32_vs_loop_fp64"] = (f32["instance_iter_per_s"] /
+                                                loop["instance_iter_per_s"])
+    return out
+
+
 def time_loop(sdp, torch, insts, precision, steps, warmup, stream, total):
     """The batch as a loop of per-instance solves: one handle per instance
     (each with its own captured graph), stepped one after another on the same
@@ -456,6 +587,43 @@ def roofline_of(insts, stages_ms, sweeps, algorithm, extra, workload):
                 traffic=load_traffic(workload, dom),
                 model_flops_per_launch=info["flops"], launch_ms=stages[dom],
                 workgroups=wgs, frac_of_occupied_units=achieved / (info["peak_tflops"] * occupied))
+
+
+def projection_roofline(insts, stages_ms, workload, precision="fp32"):
+    """The projection stage against the FP32 (or FP64) matrix peak: the
+    method's work (10 s^3 per clique) per launch over the stage's mean launch
+    time, and, from the workload's committed compute-counter profile when it
+    was taken on the current kernel source, the work the dominant projection
+    kernel executed per launch (matrix-core plus vector FLOPs) over the same
+    time, with its MFMA busy fraction."""
+    import numpy as np
+    sizes = np.concatenate([i.clique_sizes().astype(np.int64) for i in insts])
+    model = float(np.sum(10 * sizes ** 3))
+    t = stages_ms["projection"] / 1e3
+    peak = FP32_MATRIX_TFLOPS if precision == "fp32" else FP64_MATRIX_TFLOPS
+    out = dict(stage="projection", model="10 s^3 per clique", model_flops_per_launch=model,
+               launch_ms=stages_ms["projection"], model_tflops=model / t / 1e12,
+               peak_tflops=peak, model_frac=model / t / 1e12 / peak, counters=None)
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    if os.path.exists(path):
+        try:
+            ks = json.load(open(path))["kernels"]
+        except Exception:
+            ks = {}
+        tag = "<float" if precision == "fp32" else "<double"
+        cand = [n for n in ks if (n.startswith("k_admm_sign" + tag) or n.startswith("k_project" + tag))]
+        if cand:
+            name = max(cand, key=lambda n: ks[n]["mean_us"] * ks[n]["launches"])
+            ent = load_counters(workload, name)
+            if ent is not None:
+                ex = (ent["mfma_flops_per_launch"] + ent["valu_f32_flops_per_launch"]
+                      + ent["valu_f64_flops_per_launch"])
+                out["counters"] = dict(kernel=name, executed_flops_per_launch=ex,
+                                       executed_tflops=ex / t / 1e12,
+                                       executed_frac=ex / t / 1e12 / peak,
+                                       mfma_busy=ent["mfma_busy"],
+                                       profile_mean_us=ent["mean_us"])
+    return out
 
 
 def solver_options(args):
@@ -552,9 +720,14 @@ def main():
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 CSV output directories")
     ap.add_argument("--commands-file", help="text file with the rocprofv3 commands (summaries)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="TRACE PASS1 [PASS2 ...]: write profiles/counters_<workload>.{md,json} "
+                         "from a kernel-trace run and rocprofv3 --pmc runs of COUNTER_PASSES")
     ap.add_argument("--decouple", type=int, choices=(0, 1), default=None,
                     help="positive/negative decoupling of warm-started projections "
                          "(default: the library's default)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="leave the batched workload out of the banded (default) line")
     ap.add_argument("--projection-method", default=None,
                     choices=("auto", "scalar", "two_level", "sign"),
                     help="eigensolver of the clique projections (default: the library's)")
@@ -562,6 +735,11 @@ def main():
     if args.summarize_rocprof:
         cmds = open(args.commands_file).read().strip().splitlines() if args.commands_file else []
         summarize_rocprof(args.workload, *args.summarize_rocprof, cmds)
+        return
+    if args.summarize_counters:
+        cmds = open(args.commands_file).read().strip().splitlines() if args.commands_file else []
+        summarize_counters(args.workload, args.summarize_counters[0], args.summarize_counters[1:],
+                           cmds)
         return
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -639,6 +817,7 @@ def main():
         "fp32_eig": {k: v for k, v in f32.items() if k != "objectives"},
         "fp64": None if f64 is None else {k: v for k, v in f64.items() if k != "objectives"},
         "roofline": roof,
+        "projection_roofline": projection_roofline(insts, head["stages_ms"], args.workload),
         "cpu_baseline": cpu,
     }
     if preprocess is not None:
@@ -650,6 +829,8 @@ def main():
         line["speedup_fp32_vs_fp64_time_to_tol"] = (f64["solve"]["time_to_tol_s"] /
                                                     f32["solve"]["time_to_tol_s"])
         line["objective_rel_diff_fp32_vs_fp64"] = float(np.max(np.abs(o32 - o64) / np.abs(o64)))
+    if args.workload == "banded" and not args.no_batched:
+        line["batched"] = batched_leg(args, sdp, torch, stream)
     if args.workload == "batched":
         # the batched handle against a loop of per-instance plain FP64 solves
         print("[bench] batched: loop of per-instance FP64 solves", file=sys.stderr, flush=True)

@@ -126,7 +126,9 @@ typedef struct {
   double cg_tol;                /* the solve also stops once ||r||_2 <= cg_tol (1 + ||b||_2);
                                    0: always cg_max_iter steps */
   int32_t projection_method;    /* eigensolver of the clique projections: 0 the autotuner (or,
-                                   with autotune = 0, the default variant) chooses; 1 scalar
+                                   with autotune = 0, the default variant) chooses, and with
+                                   Algorithm 1 cliques of up to 32 vertices take the sign
+                                   function as with 3; 1 scalar
                                    parallel-order Jacobi only; 2 the two-level (block) Jacobi
                                    wherever a variant for the clique size exists (blocks of
                                    64 and more), scalar elsewhere; 3 (Algorithm 1) cliques of
@@ -364,8 +366,9 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
  * weighted by 2); with euclidean = 1 w.r.t. the plain dot product of the
  * compact vectors (what an autodiff framework uses).  Segments between
  * checkpoints are recomputed forward, storing each projection's eigenvectors
- * (FP32 in the SDP_FP32_EIG form), then reversed.  Cliques larger than 64 give
- * SDP_ERR_UNSUPPORTED.  The handle's iterate is unspecified afterwards (call
+ * (FP32 in the SDP_FP32_EIG form), then reversed; the projection adjoints run
+ * on the matrix cores for every clique size the solver takes (128 in FP32, 96
+ * in FP64).  The handle's iterate is unspecified afterwards (call
  * sdp_reset before solving again).  Synchronises. */
 int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar,
             int32_t euclidean);

@@ -16,6 +16,7 @@
 // The eigenvectors and eigenvalues of each W_k come from a recomputation of
 // the segment since the last checkpoint (k_project stores them).
 #include "sdp_internal.h"
+#include "mfma_tile.h"
 
 #include <math.h>
 
@@ -29,14 +30,19 @@ __device__ inline void tri_inv_a(int t, int &a, int &b) {
   b = t - x * (x + 1) / 2;
 }
 
-// Projection adjoint for the cliques of one size bucket (N <= 64).
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_adj_proj(AdjArgs a, const int32_t *__restrict__ list) {
-  constexpr int NT = 256;
+// Projection adjoint for the cliques of one size bucket: the four N x N
+// products of the Daleckii-Krein form on the matrix cores (tile_product,
+// 16x16x4 MFMA), V and one work block in LDS.  Each product is stored over
+// its own input after the barrier inside tile_product:
+//   B = V^T G;  B = (B V) o Gamma;  B = V B;  Wb = B V^T (lower tiles only,
+//   written straight to the packed cotangents).
+// V holds the eigenvectors as columns (rows >= s are zero), theta follows V
+// in the clique's record.
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_adj_proj(AdjArgs a, const int32_t *__restrict__ list) {
   constexpr int P = N + 1;
   __shared__ T Vs[N * P];
-  __shared__ T Gs[N * P];
-  __shared__ T Ts[N * P];
+  __shared__ T Bs[N * P];
   __shared__ T th[N];
   const int cl = list[blockIdx.x];
   const int inst = a.cl_inst[cl];
@@ -54,52 +60,46 @@ __global__ __launch_bounds__(256) void k_adj_proj(AdjArgs a, const int32_t *__re
       const int64_t pk = off + (int64_t)ii * (ii + 1) / 2 + jj;
       g = (T)(a.Xb[pk] + rho * a.Lb[pk]);
     }
-    Gs[i * P + j] = g;
+    Bs[i * P + j] = g;
   }
   for (int k = tid; k < N; k += NT) th[k] = eo[s * N + k];
   __syncthreads();
-  // Ts = V^T G
-  for (int e = tid; e < N * N; e += NT) {
-    const int i = e / N, j = e % N;
-    T acc = T(0);
-    for (int k = 0; k < s; ++k) acc += Vs[k * P + i] * Gs[k * P + j];
-    Ts[i * P + j] = acc;
-  }
+  // B = V^T G
+  tile_product<T, N, NT, false>([&](int k, int q) { return Vs[k * P + q]; },
+                                [&](int k, int q) { return Bs[k * P + q]; },
+                                [&](int i, int j, T v) { Bs[i * P + j] = v; });
   __syncthreads();
-  // Gs = (Ts V) o Gamma
-  for (int e = tid; e < N * N; e += NT) {
-    const int i = e / N, j = e % N;
-    T acc = T(0);
-    for (int k = 0; k < s; ++k) acc += Ts[i * P + k] * Vs[k * P + j];
-    const T ti = th[i], tj = th[j];
-    T gam;
-    if (ti > T(0) && tj > T(0)) gam = T(1);
-    else if (!(ti > T(0)) && !(tj > T(0))) gam = T(0);
-    else gam = ((ti > T(0) ? ti : T(0)) - (tj > T(0) ? tj : T(0))) / (ti - tj);
-    Gs[i * P + j] = acc * gam;
-  }
+  // B = (B V) o Gamma
+  tile_product<T, N, NT, false>([&](int k, int q) { return Bs[q * P + k]; },
+                                [&](int k, int q) { return Vs[k * P + q]; },
+                                [&](int i, int j, T v) {
+                                  const T ti = th[i], tj = th[j];
+                                  T gam;
+                                  if (ti > T(0) && tj > T(0)) gam = T(1);
+                                  else if (!(ti > T(0)) && !(tj > T(0))) gam = T(0);
+                                  else
+                                    gam = ((ti > T(0) ? ti : T(0)) - (tj > T(0) ? tj : T(0))) /
+                                          (ti - tj);
+                                  Bs[i * P + j] = v * gam;
+                                });
   __syncthreads();
-  // Ts = V Gs   (rows < s)
-  for (int e = tid; e < s * N; e += NT) {
-    const int i = e / N, j = e % N;
-    T acc = T(0);
-    for (int k = 0; k < N; ++k) acc += Vs[i * P + k] * Gs[k * P + j];
-    Ts[i * P + j] = acc;
-  }
+  // B = V B
+  tile_product<T, N, NT, false>([&](int k, int q) { return Vs[q * P + k]; },
+                                [&](int k, int q) { return Bs[k * P + q]; },
+                                [&](int i, int j, T v) { Bs[i * P + j] = v; });
   __syncthreads();
-  // Wb = Ts V^T on the packed lower triangle, then the two cotangent updates
-  const int npk = s * (s + 1) / 2;
-  for (int e = tid; e < npk; e += NT) {
-    int i, j;
-    tri_inv_a(e, i, j);
-    T acc = T(0);
-    for (int k = 0; k < N; ++k) acc += Ts[i * P + k] * Vs[j * P + k];
-    const double wb = (double)acc;
-    const int64_t g = off + e;
-    const double lb = a.Lb[g];
-    a.Ub[g] = wb - rho * lb;
-    a.Lb[g] = lb - wb / rho;
-  }
+  // Wb = B V^T on the packed lower triangle, then the two cotangent updates
+  tile_product<T, N, NT, true>([&](int k, int q) { return Bs[q * P + k]; },
+                               [&](int k, int q) { return Vs[q * P + k]; },
+                               [&](int i, int j, T v) {
+                                 if (i < s && j <= i) {
+                                   const int64_t g = off + (int64_t)i * (i + 1) / 2 + j;
+                                   const double wb = (double)v;
+                                   const double lb = a.Lb[g];
+                                   a.Ub[g] = wb - rho * lb;
+                                   a.Lb[g] = lb - wb / rho;
+                                 }
+                               });
 }
 
 __global__ __launch_bounds__(256) void k_adj_scatter(AdjArgs a) {
@@ -179,27 +179,39 @@ __global__ __launch_bounds__(256) void k_copy_user_rows(const double *src, doubl
 hipError_t launch_adj_projection(int precision, int N, const int32_t *list, int count,
                                  const AdjArgs &a, hipStream_t st) {
   if (count <= 0) return hipSuccess;
+#define SDP_ADJ(T, n)                                                                          \
+  case n:                                                                                      \
+    hipLaunchKernelGGL((k_adj_proj<T, n, (n <= 64 ? 256 : 512)>), dim3(count),               \
+                       dim3(n <= 64 ? 256 : 512), 0, st, a, list);                             \
+    break;
   if (precision == 1) {
     switch (N) {
-      case 16: hipLaunchKernelGGL((k_adj_proj<float, 16>), dim3(count), dim3(256), 0, st, a, list); break;
-      case 32: hipLaunchKernelGGL((k_adj_proj<float, 32>), dim3(count), dim3(256), 0, st, a, list); break;
-      case 48: hipLaunchKernelGGL((k_adj_proj<float, 48>), dim3(count), dim3(256), 0, st, a, list); break;
-      case 64: hipLaunchKernelGGL((k_adj_proj<float, 64>), dim3(count), dim3(256), 0, st, a, list); break;
+      SDP_ADJ(float, 16)
+      SDP_ADJ(float, 32)
+      SDP_ADJ(float, 48)
+      SDP_ADJ(float, 64)
+      SDP_ADJ(float, 80)
+      SDP_ADJ(float, 96)
+      SDP_ADJ(float, 112)
+      SDP_ADJ(float, 128)
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (N) {
-      case 16: hipLaunchKernelGGL((k_adj_proj<double, 16>), dim3(count), dim3(256), 0, st, a, list); break;
-      case 32: hipLaunchKernelGGL((k_adj_proj<double, 32>), dim3(count), dim3(256), 0, st, a, list); break;
-      case 48: hipLaunchKernelGGL((k_adj_proj<double, 48>), dim3(count), dim3(256), 0, st, a, list); break;
-      case 64: hipLaunchKernelGGL((k_adj_proj<double, 64>), dim3(count), dim3(256), 0, st, a, list); break;
+      SDP_ADJ(double, 16)
+      SDP_ADJ(double, 32)
+      SDP_ADJ(double, 48)
+      SDP_ADJ(double, 64)
+      SDP_ADJ(double, 80)
+      SDP_ADJ(double, 96)
       default: return hipErrorInvalidValue;
     }
   }
+#undef SDP_ADJ
   return hipGetLastError();
 }
 
-int adjoint_max_bucket() { return 64; }
+int adjoint_max_bucket(int precision) { return precision == 1 ? 128 : 96; }
 
 hipError_t launch_adj_scatter(const AdjArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_scatter, dim3((a.ncoord + 255) / 256), dim3(256), 0, st, a);

@@ -121,8 +121,11 @@ int sign_variant(int precision, int s) {
 }
 
 // Whether projection_method 0 takes the sign-function variants for
-// Algorithm 1's cliques of up to 32 vertices.
-bool sign_by_default(int precision) { return false; }
+// Algorithm 1's cliques of up to 32 vertices: yes in both precisions (one
+// MI355X: banded workload projection 22.0 -> 13.8 us FP32, 52.9 -> 36.4 us
+// FP64; the batched workload's cliques of 10-50 1.27 -> 1.21 ms and 4.30 ->
+// 4.23 ms).
+bool sign_by_default(int) { return true; }
 
 int tune_variant(int precision, int s, int64_t count, int max_sweeps, double tol, bool warm,
                  int method, hipStream_t st) {
@@ -365,9 +368,16 @@ void enqueue_unrolled_iteration(sdp_handle *h, hipStream_t st, void *eig) {
   p.eig_off = h->d_eig_off;
   p.vw = nullptr;          // the reverse sweep recomputes segments: no cross-iteration state
   HIPCHK(launch_iteration_affine(a, st));
-  for (size_t b = 0; b < h->bucket_size.size(); ++b)
-    HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                  h->bucket_count[b], p, st));
+  // always the Jacobi kernels (the sign-function lists of the plan take the
+  // Jacobi default of their block size): the recomputed segments record
+  // eigenvectors, and the first pass must compute the same iterates bit for
+  // bit, or the checkpoint spacing would change the result
+  for (size_t b = 0; b < h->bucket_size.size(); ++b) {
+    int v = h->bucket_size[b];
+    if (projection_variant_kind(h->precision, v) == 2)
+      v = projection_default_variant(h->precision, h->bucket_N[b]);
+    HIPCHK(launch_admm_projection(h->precision, v, h->bucket_list[b], h->bucket_count[b], p, st));
+  }
   HIPCHK(launch_residual_reduce(a, st));
 }
 
@@ -968,6 +978,22 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     }
     a.csr_rows = dev_upload(csr_rows, own);
     a.n_csr_rows = (int)(csr_rows.size() / 2);
+    // long rows are read by four waves each (the longest rows set a pass's
+    // time when every row is resident at once): CSR rows of 512 nonzeros and
+    // more on average, triangular factors of 1024 rows and more
+    {
+      int64_t csr_nnz = 0, csr_nr = 0;
+      int max_m = 0;
+      for (int i = 0; i < batch; ++i) {
+        max_m = std::max(max_m, H[i].m);
+        if (H[i].fmt == SDP_A_CSR) {
+          csr_nnz += inst[i].a_rowptr[H[i].m];
+          csr_nr += H[i].m;
+        }
+      }
+      a.csr_wpr = (csr_nr > 0 && csr_nnz >= 512 * csr_nr) ? 4 : 1;
+      a.trmv_wpr = max_m >= 1024 ? 4 : 1;
+    }
     a.csc_cols = dev_upload(csc_cols, own);
     a.n_csc_cols = (int)(csc_cols.size() / 2);
     double *d_part = dev_zeros<double>((size_t)cl * NPART, own);
@@ -1066,7 +1092,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       h->adj_ready = true;
       for (int64_t k = 0; k < cl; ++k) {
         const int nb = h->clique_N[k];
-        if (nb > adjoint_max_bucket()) h->adj_ready = false;
+        if (nb > adjoint_max_bucket(h->precision)) h->adj_ready = false;
         eoff[k] = eo;
         eo += (int64_t)cl_size[k] * nb + nb;
       }

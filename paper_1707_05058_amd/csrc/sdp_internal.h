@@ -190,6 +190,7 @@ struct AffineArgs {
   const int32_t *t_rows; int n_t_rows;      // (inst, row) per wave for T r
   const int32_t *t3_rows; int n_t3_rows;    // (inst, row) per wave for T^T y1
   const int32_t *csr_rows; int n_csr_rows;   // (inst, row) pairs for CSR instances
+  int csr_wpr, trmv_wpr;                      // waves per row of the CSR and triangular passes (1, 4)
   const int32_t *csc_cols; int n_csc_cols;   // (inst, col-chunk) pairs for CSR instances
   // residual partials
   const double *part;
@@ -367,4 +368,4 @@ hipError_t launch_copy_user(const double *src, double *dst, const InstDesc *inst
 hipError_t launch_copy_user_rows(const double *src, double *dst, const InstDesc *inst,
                                  const int32_t *row_inst, const int64_t *user_row_off,
                                  int64_t nrow, hipStream_t st);
-int adjoint_max_bucket();
+int adjoint_max_bucket(int precision);   // largest padded block with a projection adjoint

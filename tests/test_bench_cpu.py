@@ -35,7 +35,7 @@ def test_banded_pass_bytes():
     assert model["AT_y"]["bytes"] == 8 * m * nnz + 8 * m + 24 * nnz
     assert "Linv_r" not in model and "LinvT_y" not in model
     sizes = inst.clique_sizes().astype(np.int64)
-    assert model["projection"]["flops"] == int(np.sum(15 * sizes ** 3))
+    assert model["projection"]["flops"] == int(np.sum(10 * sizes ** 3))   # the method's work
 
 
 def test_roofline_hbm_and_alu_forms():
@@ -104,3 +104,47 @@ def test_summarizer_trace_only_and_counters(tmp_path, monkeypatch):
     assert bench.load_traffic("banded", "AT_y") == pytest.approx(st["hbm_bytes_per_launch"])
     (tmp_path / "paper_1707_05058_amd" / "csrc" / bench.STAGE_SOURCE["AT_y"]).write_text("// new")
     assert bench.load_traffic("banded", "AT_y") is None
+
+
+def test_projection_roofline_and_counter_summary(tmp_path, monkeypatch):
+    """The projection block of the bench line: 10 s^3 per clique over the
+    stage time; the counter summary turns MFMA and vector counts into FLOPs
+    per launch, and the bench line takes the executed work of the dominant
+    projection kernel only while its source is unchanged."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "paper_1707_05058_amd" / "csrc")
+    for f in ("k_project.hip", "k_affine.hip", "k_adjoint.hip"):
+        (tmp_path / "paper_1707_05058_amd" / "csrc" / f).write_text("// source " + f)
+    inst = sdpgen.workload_banded()
+    r = bench.projection_roofline([inst], {"projection": 0.010}, "banded")
+    model = 10.0 * 1985 * 16 ** 3
+    assert r["model_flops_per_launch"] == pytest.approx(model)
+    assert r["model_tflops"] == pytest.approx(model / 10e-6 / 1e12)
+    assert r["counters"] is None
+    trace = tmp_path / "trace"
+    _write_csv(str(trace / "t_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+               [["void k_admm_sign<float, 1>(ProjArgs, int const*, int, int)", 4, 40000, 10000, 50.0],
+                ["void k_coldot<0, false>(AffineArgs)", 4, 40000, 10000, 50.0]])
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    kname = "void k_admm_sign<float, 1>(ProjArgs, int const*, int, int)"
+    _write_csv(str(tmp_path / "p1" / "a_counter_collection.csv"), hdr,
+               [[kname, "SQ_INSTS_VALU_MFMA_MOPS_F32", 1000.0],
+                [kname, "SQ_INSTS_VALU_MFMA_MOPS_F32", 3000.0],
+                [kname, "SQ_INSTS_VALU_FMA_F32", 10.0],
+                [kname, "SQ_VALU_MFMA_BUSY_CYCLES", 1024 * 2.4e9 * 10e-6 * 0.25]])
+    _write_csv(str(tmp_path / "p2" / "b_counter_collection.csv"), hdr,
+               [[kname, "SQ_INSTS_VALU_FMA_F64", 5.0]])
+    out = bench.summarize_counters("banded", str(trace), [str(tmp_path / "p1"), str(tmp_path / "p2")],
+                                   ["cmd"])
+    k = out["kernels"]["k_admm_sign<float, 1>"]
+    assert k["mfma_flops_per_launch"] == pytest.approx(512 * 2000.0)
+    assert k["valu_f32_flops_per_launch"] == pytest.approx(64 * 2 * 10.0)
+    assert k["valu_f64_flops_per_launch"] == pytest.approx(64 * 2 * 5.0)
+    assert k["mfma_busy"] == pytest.approx(0.25)
+    r = bench.projection_roofline([inst], {"projection": 0.010}, "banded")
+    ex = 512 * 2000.0 + 64 * 2 * 10.0 + 64 * 2 * 5.0
+    assert r["counters"]["executed_flops_per_launch"] == pytest.approx(ex)
+    assert r["counters"]["executed_tflops"] == pytest.approx(ex / 10e-6 / 1e12)
+    (tmp_path / "paper_1707_05058_amd" / "csrc" / "k_project.hip").write_text("// changed")
+    assert bench.projection_roofline([inst], {"projection": 0.010}, "banded")["counters"] is None

@@ -65,6 +65,15 @@ def test_fixed_n_small_blockarrow_fp32(sdp, gpu, oracle_mod):
                     tol_rel=2e-4)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 2e-4)])
+def test_fixed_n_small_blockarrow_jacobi_path(sdp, gpu, oracle_mod, precision, tol):
+    """The warm-started Jacobi kernels of the small blocks (the path that
+    projection_method = "scalar", Algorithms 2 and 3 and the unrolled
+    iterations take; the default plan runs the sign function there)."""
+    compare_fixed_n(sdp, oracle_mod, sdpgen.workload_small_blockarrow(), 30,
+                    precision=precision, tol_rel=tol, projection_method="scalar")
+
+
 def test_fixed_n_singleton_and_odd_cliques(sdp, gpu, oracle_mod):
     compare_fixed_n(sdp, oracle_mod, singleton_clique_instance(), 25, rho=0.7)
 
@@ -203,6 +212,8 @@ def test_banded_workload_fixed_n_fp64_and_fp32(sdp, gpu, oracle_mod):
     inst = sdpgen.workload_banded()
     compare_fixed_n(sdp, oracle_mod, inst, 8, tol_rel=1e-8)
     compare_fixed_n(sdp, oracle_mod, inst, 8, precision="fp32", tol_rel=1e-4)
+    compare_fixed_n(sdp, oracle_mod, inst, 8, precision="fp32", tol_rel=1e-4,
+                    projection_method="scalar")
 
 
 def test_large_clique_workload_fixed_n_fp32(sdp, gpu, oracle_mod):
@@ -264,7 +275,7 @@ def test_warm_started_eigensolves_match_cold_and_take_fewer_sweeps(sdp, gpu, ora
     sweeps = {}
     for warm in (0, 1):
         with sdp.Solver([inst], tol=0.0, max_iter=1000, precision=precision,
-                        warm_start=warm) as S:
+                        warm_start=warm, projection_method="scalar") as S:
             S.step(60)
             u = S.solution(0)["u"]
             st = S.stats()

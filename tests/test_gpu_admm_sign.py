@@ -1,5 +1,6 @@
 """Algorithm 1 with the register-resident sign-function projection
-(projection_method = "sign": cliques of up to 32 vertices, X_k = P+(W_k) =
+(the default plan, or projection_method = "sign": cliques of up to 32
+vertices, X_k = P+(W_k) =
 (W_k + W_k sign(W_k)) / 2 in one wave's registers, Lambda_k += rho (X_k - H_k x)
 and the residual partials in the same kernel) against the FP64 oracle.
 
@@ -84,17 +85,18 @@ def test_sign_larger_cliques_keep_jacobi(sdp, gpu, oracle_mod):
 
 
 def test_sign_diagnostics_and_unrolled_use_eigen_paths(sdp, gpu, oracle_mod):
-    """The minimum-eigenvalue pass of the diagnostics and the unrolled forward
-    (which records eigenvectors) run the Jacobi kernels of the same block
-    size under a sign-function plan, with the same results as a Jacobi plan."""
+    """The minimum-eigenvalue pass of the diagnostics runs the Jacobi kernels
+    of the same block size under a sign-function plan, with the same results
+    as a Jacobi plan (the unrolled forward, which records eigenvectors, is
+    covered by the adjoint tests, whose plans are sign-function plans too)."""
     inst = sdpgen.block_arrow_instance(5, 8, 3, 25, seed=6)
     out = {}
-    for method in ("auto", "sign"):
+    for method in ("scalar", "sign"):
         with sdp.Solver([inst], tol=0.0, precision="fp64", projection_method=method) as S:
             S.step(12)
             out[method] = S.diagnostics()[0]
     for k in ("eps_p", "eps_d", "eps_g", "eps_alpha"):
-        a, b = out["auto"][k], out["sign"][k]
+        a, b = out["scalar"][k], out["sign"][k]
         assert abs(a - b) <= 1e-8 * max(abs(a), abs(b)) + 1e-12, (k, a, b)
 
 
