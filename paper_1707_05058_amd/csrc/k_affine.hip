@@ -240,32 +240,10 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
 //   UPPER = 0:  y1[i] = sum_{k<=i} T[i][k] r[k]      (T = L^-1)
 //   UPPER = 1:  y[i]  = sum_{k>=i} U[i][k] y1[k]     (U = L^-T)
 // ---------------------------------------------------------------------------
-// WPR waves share a row (1 or 4, the whole workgroup): each takes every
-// WPR-th 128-entry chunk of it, and the WPR partial sums meet in LDS in a
-// fixed order.  With 4 the longest rows, which set the time of a pass when
-// every row is resident at once, are read by four waves.
-template <int WPR>
-__device__ inline double rows_sum(double acc, int part, int l) {
-  acc = wave_sum(acc);
-  if constexpr (WPR == 1) {
-    return acc;
-  } else {
-    __shared__ double red[4];
-    if (l == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < WPR; ++k) s += red[(threadIdx.x >> 6) - part + k];
-    return s;
-  }
-}
-
-template <int UPPER, int WPR>
+template <int UPPER>
 __global__ __launch_bounds__(256) void k_trmv_wave(AffineArgs a) {
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int wid = wave / WPR, part = wave % WPR;
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int32_t *rows = UPPER ? a.t3_rows : a.t_rows;
-  // (with WPR = 4 a workgroup is one row: the tests below are uniform over it)
   if (wid >= (UPPER ? a.n_t3_rows : a.n_t_rows)) return;
   const int inst = rows[2 * wid], row = rows[2 * wid + 1];
   if (!a.ignore_done && a.state[inst].done) return;
@@ -276,31 +254,24 @@ __global__ __launch_bounds__(256) void k_trmv_wave(AffineArgs a) {
   // the matrix is zero outside [begin, end); both ends are even
   const int begin = UPPER ? (row & ~1) : 0;
   const int end = UPPER ? ((d.m + 1) & ~1) : ((row + 2) & ~1);
-  const dvec2 *m2 = reinterpret_cast<const dvec2 *>(mat);
+  const double2 *m2 = reinterpret_cast<const double2 *>(mat);
   const double2 *v2 = reinterpret_cast<const double2 *>(vec);
   double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll 8
-  for (int c = begin / 2 + 64 * part + l; c < end / 2; c += 64 * WPR) {
-    // the factor is read once per pass: non-temporal, so that it does not
-    // displace the vector from the cache
-    const dvec2 x = __builtin_nontemporal_load(m2 + c);
-    const double2 y = v2[c];
+  for (int c = begin / 2 + l; c < end / 2; c += 64) {
+    const double2 x = m2[c], y = v2[c];
     acc0 += x.x * y.x;
     acc1 += x.y * y.y;
   }
-  const double sum = rows_sum<WPR>(acc0 + acc1, part, l);
-  if (l == 0 && part == 0) (UPPER ? a.y : a.y1)[d.row_off + row] = sum;
+  const double sum = wave_sum(acc0 + acc1);
+  if (l == 0) (UPPER ? a.y : a.y1)[d.row_off + row] = sum;
 }
 
 // ---------------------------------------------------------------------------
-// Sparse A (CSR rows, CSC columns) for instances stored in SDP_A_CSR.  The
-// values and indices of A are read once per pass (non-temporal loads keep
-// the gathered vector in the cache); WPR waves share a row as above.
+// Sparse A (CSR rows, CSC columns) for instances stored in SDP_A_CSR.
 // ---------------------------------------------------------------------------
-template <int WPR>
 __global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int wid = wave / WPR, part = wave % WPR;
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= a.n_csr_rows) return;
   const int inst = a.csr_rows[2 * wid], row = a.csr_rows[2 * wid + 1];
   if (!a.ignore_done && a.state[inst].done) return;
@@ -311,11 +282,10 @@ __global__ __launch_bounds__(256) void k_csr_rowdot(AffineArgs a) {
   const double *v = a.v + d.coord_off;
   double acc = 0.0;
 #pragma unroll 4
-  for (int64_t t = t0 + 64 * part + l; t < t1; t += 64 * WPR)
-    acc += __builtin_nontemporal_load(a.a_val + t) * v[__builtin_nontemporal_load(a.a_col + t)];
-  acc = rows_sum<WPR>(acc, part, l);
+  for (int64_t t = t0 + l; t < t1; t += 64) acc += a.a_val[t] * v[a.a_col[t]];
+  acc = wave_sum(acc);
   const double bs = a.dual ? -1.0 / a.state[inst].rho : 1.0;
-  if (l == 0 && part == 0) a.r[d.row_off + row] = a.no_b ? acc : acc - bs * a.b[d.row_off + row];
+  if (l == 0) a.r[d.row_off + row] = a.no_b ? acc : acc - bs * a.b[d.row_off + row];
 }
 
 // Transposed products with sparse A: CSC_G consecutive lanes share a column
@@ -335,8 +305,7 @@ __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
   const double *y = a.y + d.row_off;
   double acc = 0.0;
   const int64_t t1 = a.a_colptr[g + 1];
-  for (int64_t t = a.a_colptr[g] + q; t < t1; t += CSC_G)
-    acc += __builtin_nontemporal_load(a.a_cval + t) * y[__builtin_nontemporal_load(a.a_row + t)];
+  for (int64_t t = a.a_colptr[g] + q; t < t1; t += CSC_G) acc += a.a_cval[t] * y[a.a_row[t]];
 #pragma unroll
   for (int o = 1; o < CSC_G; o <<= 1) acc += __shfl_xor(acc, o, 64);
   if (q == 0) {
@@ -349,25 +318,6 @@ __global__ __launch_bounds__(256) void k_csc_coldot(AffineArgs a) {
       if (a.cg_g) a.cg_g[g] = acc;
     }
   }
-}
-
-// Launches of the row passes with the handle's waves per row (1 or 4).
-void launch_csr_rows(const AffineArgs &a, hipStream_t st) {
-  if (a.n_csr_rows <= 0) return;
-  if (a.csr_wpr == 4)
-    hipLaunchKernelGGL(k_csr_rowdot<4>, dim3(a.n_csr_rows), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_csr_rowdot<1>, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
-}
-
-template <int UPPER>
-void launch_trmv(const AffineArgs &a, hipStream_t st) {
-  const int n = UPPER ? a.n_t3_rows : a.n_t_rows;
-  if (n <= 0) return;
-  if (a.trmv_wpr == 4)
-    hipLaunchKernelGGL((k_trmv_wave<UPPER, 4>), dim3(n), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_trmv_wave<UPPER, 1>), dim3((n + 3) / 4), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -730,15 +680,15 @@ hipError_t launch_affine_stage(const AffineArgs &a, int stage, hipStream_t st) {
     case 1:
       launch_dense_rowdot(a, st);
       if (a.n_csr_rows > 0)
-        launch_csr_rows(a, st);
+        hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 2:
       if (a.n_t_rows > 0)
-        launch_trmv<0>(a, st);
+        hipLaunchKernelGGL(k_trmv_wave<0>, dim3((a.n_t_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 3:
       if (a.n_t3_rows > 0)
-        launch_trmv<1>(a, st);
+        hipLaunchKernelGGL(k_trmv_wave<1>, dim3((a.n_t3_rows + 3) / 4), dim3(256), 0, st, a);
       break;
     case 4:
       launch_dense_coldot<0>(a, st);
@@ -789,7 +739,7 @@ hipError_t launch_diagnostics(const AffineArgs &a0, const DiagScratch &s, const 
   ar.dual = 0;
   launch_dense_rowdot(ar, st);
   if (ar.n_csr_rows > 0)
-    launch_csr_rows(ar, st);
+    hipLaunchKernelGGL(k_csr_rowdot, dim3((ar.n_csr_rows + 3) / 4), dim3(256), 0, st, ar);
   AffineArgs at = a;          // A^T y_dual
   at.y = s.yd;
   at.u = s.aty;
@@ -818,7 +768,7 @@ namespace {
 void launch_rowdots(const AffineArgs &a, hipStream_t st) {
   launch_dense_rowdot(a, st);
   if (a.n_csr_rows > 0)
-    launch_csr_rows(a, st);
+    hipLaunchKernelGGL(k_csr_rowdot, dim3((a.n_csr_rows + 3) / 4), dim3(256), 0, st, a);
 }
 
 }  // namespace

@@ -681,6 +681,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
   bool inst_done = false;
   int64_t off;
   double rho = 1.0;
+  int iter = 0;
   if (MODE == MODE_STANDALONE) {
     s = sizes[blockIdx.x];
     off = offsets[blockIdx.x];
@@ -698,6 +699,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     off = a.cl_off[cl];
     if (ADMM) inst_done = a.state[inst].done != 0;
     rho = a.state[inst].rho;
+    if (ADMM) iter = a.state[inst].iter;
   }
 
   // small variants: the loads of the warm-start basis and of the epilogue's
@@ -1077,9 +1079,14 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
     if (ispos) plist[base + __popcll(bal & ((1ull << (tid & 63)) - 1ull))] = tid;
   }
   __syncthreads();
+  // the basis is re-orthonormalised by a Newton-Schulz step on every
+  // ns_period-th iteration of the instance: it departs from orthonormality
+  // by rounding only (about N eps per iteration), and one step squares the
+  // departure, so every second iteration keeps it at the level of a few eps
+  const bool ns = ADMM && vw && (a.ns_period <= 1 || (iter + a.ns_shift) % a.ns_period == 0);
   // the Gram matrix V^T V of the Newton-Schulz step reads V by rows; the
   // products after it read V^T, written over V from the registers
-  if (ADMM && vw) {
+  if (ns) {
     // (symmetric: tiles on or below the diagonal, mirrored)
     tile_product<T, N, NT, true>([&](int k, int q) { return Vbuf[k * P + q]; },
                                  [&](int k, int q) { return Vbuf[k * P + q]; },
@@ -1099,7 +1106,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
       for (int e = 0; e < 2; ++e) Vbuf[ix(2 * b + e, 2 * aj + d)] = V[j][d][e];
   }
   __syncthreads();
-  if (ADMM && vw) {
+  if (ns) {
     // store the basis for the next iteration after one Newton-Schulz step,
     // V <- V (3I - V^T V) / 2, which squares its departure from orthonormality:
     // (V G)(i, j) = sum_k V^T(k, i) G(k, j), V(i, j) = V^T(j, i)
@@ -1109,6 +1116,12 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
         [&](int qi, int qj, T v) {
           vw[(int64_t)slot(qi) * N + slot(qj)] = T(1.5) * Vbuf[slot(qj) * P + qi] - T(0.5) * v;
         });
+  } else if (ADMM && vw) {
+    // store the basis as it is
+    for (int e = tid; e < N * N; e += NT) {
+      const int qi = e / N, qj = e % N;
+      vw[(int64_t)slot(qi) * N + slot(qj)] = Vbuf[slot(qj) * P + qi];
+    }
   }
   if (ADMM && a.eig) {
     // keep V (rows < s, all N slots) and the eigenvalues for the reverse sweep

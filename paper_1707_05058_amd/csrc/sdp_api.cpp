@@ -978,22 +978,6 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     }
     a.csr_rows = dev_upload(csr_rows, own);
     a.n_csr_rows = (int)(csr_rows.size() / 2);
-    // long rows are read by four waves each (the longest rows set a pass's
-    // time when every row is resident at once): CSR rows of 512 nonzeros and
-    // more on average, triangular factors of 1024 rows and more
-    {
-      int64_t csr_nnz = 0, csr_nr = 0;
-      int max_m = 0;
-      for (int i = 0; i < batch; ++i) {
-        max_m = std::max(max_m, H[i].m);
-        if (H[i].fmt == SDP_A_CSR) {
-          csr_nnz += inst[i].a_rowptr[H[i].m];
-          csr_nr += H[i].m;
-        }
-      }
-      a.csr_wpr = (csr_nr > 0 && csr_nnz >= 512 * csr_nr) ? 4 : 1;
-      a.trmv_wpr = max_m >= 1024 ? 4 : 1;
-    }
     a.csc_cols = dev_upload(csc_cols, own);
     a.n_csc_cols = (int)(csc_cols.size() / 2);
     double *d_part = dev_zeros<double>((size_t)cl * NPART, own);
@@ -1067,6 +1051,8 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       HIPCHK(hipMalloc(&h->d_vw, esz * (size_t)std::max<int64_t>(vo, 1)));
       own.push_back(h->d_vw);
       p.vw = h->d_vw;
+      p.ns_period = 2;
+      p.ns_shift = 0;
       p.vw_off = h->d_vw_off;
     }
     h->d_diag = dev_zeros<double>((size_t)4 * batch, own);
@@ -1687,7 +1673,11 @@ int sdp_time_stages(sdp_handle *h, int32_t n_iter, double *ms) {
             if (!h->cg) HIPCHK(launch_affine_stage(h->aff, s, h->stream));
             else if (s != 3) HIPCHK(launch_cg_stage(h->aff, s, h->stream));
           } else if (s == 5) {
-            enqueue_projections(h, h->proj, h->stream);
+            // (the launches step through the re-orthonormalisation period as
+            // the iterations do; the iteration counter itself does not move)
+            ProjArgs p = h->proj;
+            p.ns_shift = it;
+            enqueue_projections(h, p, h->stream);
             if (h->proj.dual) HIPCHK(launch_dual_update(h->proj, h->ncl, h->stream));
           } else {
             HIPCHK(launch_residual_reduce(h->aff, h->stream));

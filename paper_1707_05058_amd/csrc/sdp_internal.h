@@ -103,6 +103,8 @@ struct ProjArgs {
   void *eig;              // optional: per clique V (s x N) then theta (N), precision T
   const int64_t *eig_off; // element offset of each clique's record in eig
   void *vw;               // optional: per clique N x N eigenvector basis (warm start), T
+  int ns_period;          // the basis is re-orthonormalised every ns_period-th iteration
+  int ns_shift;           // (of iteration + ns_shift; 0 except in the stage timing)
   const int64_t *vw_off;  // element offset of each clique's basis in vw
   // Algorithm 2 (range-space dual ADMM): X holds z_k, Lam holds lambda_k and
   // Vd the slack blocks v_k (packed lower, like X); the projection input is
@@ -190,7 +192,6 @@ struct AffineArgs {
   const int32_t *t_rows; int n_t_rows;      // (inst, row) per wave for T r
   const int32_t *t3_rows; int n_t3_rows;    // (inst, row) per wave for T^T y1
   const int32_t *csr_rows; int n_csr_rows;   // (inst, row) pairs for CSR instances
-  int csr_wpr, trmv_wpr;                      // waves per row of the CSR and triangular passes (1, 4)
   const int32_t *csc_cols; int n_csc_cols;   // (inst, col-chunk) pairs for CSR instances
   // residual partials
   const double *part;
