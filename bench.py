@@ -633,6 +633,8 @@ def solver_options(args):
         extra["decouple"] = args.decouple
     if args.projection_method is not None:
         extra["projection_method"] = args.projection_method
+    if args.autotune is not None:
+        extra["autotune"] = args.autotune
     return extra
 
 
@@ -726,6 +728,8 @@ def main():
     ap.add_argument("--decouple", type=int, choices=(0, 1), default=None,
                     help="positive/negative decoupling of warm-started projections "
                          "(default: the library's default)")
+    ap.add_argument("--autotune", type=int, choices=(0, 1), default=None,
+                    help="time the kernel variants at setup (default: the library's, on)")
     ap.add_argument("--no-batched", action="store_true",
                     help="leave the batched workload out of the banded (default) line")
     ap.add_argument("--projection-method", default=None,
