@@ -913,10 +913,8 @@ def run_projection(args, sdp, torch, stream):
             def vname(v):
                 return f"{variants[v][0]}x{variants[v][1]}-{kind_name[kinds[v]]}"
             bv, bms = min(times.items(), key=lambda kv: kv[1])
-            # the library's default: the first listed sign-function variant of the
-            # smallest N (else the first Jacobi one)
-            dv = ([v for v in times if variants[v][0] == n_fit and kinds[v] == 2]
-                  or [v for v in times if variants[v][0] == n_fit and kinds[v] == 0])[0]
+            # the variant the library runs without an explicit choice
+            dv = sdp.projection_default_variant(dtc, s)
             model = 10.0 * s ** 3 * count
             executed = None
             if kinds[bv] == 2:
