@@ -127,13 +127,13 @@ typedef struct {
                                    0: always cg_max_iter steps */
   int32_t projection_method;    /* eigensolver of the clique projections: 0 the autotuner (or,
                                    with autotune = 0, the default variant) chooses, and with
-                                   Algorithm 1 cliques of up to 32 vertices take the sign
-                                   function as with 3; 1 scalar
+                                   Algorithms 1 and 2 cliques of up to 32 vertices take the
+                                   sign function as with 3; 1 scalar
                                    parallel-order Jacobi only; 2 the two-level (block) Jacobi
                                    wherever a variant for the clique size exists (blocks of
-                                   64 and more), scalar elsewhere; 3 (Algorithm 1) cliques of
-                                   up to 32 vertices take the matrix sign function in one
-                                   wave's registers (X_k = (W + W sign(W)) / 2, no
+                                   64 and more), scalar elsewhere; 3 (Algorithms 1 and 2)
+                                   cliques of up to 32 vertices take the matrix sign function
+                                   in one wave's registers (X_k = (W + W sign(W)) / 2, no
                                    eigenvectors, no warm start), larger ones as with 0 */
   int32_t decouple;             /* 1 (SDP_FP32_EIG with warm_start = 1; blocks padded to 64
                                    and more; Algorithms 1-3 outside the unrolled iterations):

@@ -1901,12 +1901,14 @@ __global__ __launch_bounds__(64) void k_project_sign32(const int32_t *__restrict
 // one wave's registers, with no eigenvectors: X_k = P+(W_k) by the sign
 // iteration of k_project_sign16/32 on W_k = H_k x - Lambda_k / rho, then the
 // multiplier update Lambda_k += rho (X_k - H_k x) (XkUpdate, LambdakUpdate)
-// and the five residual partials of k_project's ADMM epilogue.  The register
-// layout is the sign kernels': tile t = TB I + J holds rows 16 I + R(g, r) at
-// column 16 J + l mod 16.  W_k(i, k) and W_k(k, i) come from the same packed
-// entry, so W_k is exactly symmetric.
+// and the five residual partials of k_project's ADMM epilogue.  With DUAL,
+// Algorithm 2's z-update instead: z_k = P+(v_k - lambda_k / rho) (zkUpdate)
+// and ||z_k - z_k_prev||^2, the rest following the affine step as with the
+// Jacobi kernels.  The register layout is the sign kernels': tile t = TB I + J
+// holds rows 16 I + R(g, r) at column 16 J + l mod 16.  W_k(i, k) and
+// W_k(k, i) come from the same packed entry, so W_k is exactly symmetric.
 // ---------------------------------------------------------------------------
-template <typename T, int TB>
+template <typename T, int TB, bool DUAL>
 __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__restrict__ list,
                                                   int k1, int k2) {
   constexpr int NTL = TB * TB, NB = 16 * TB, CP = NB + 1;
@@ -1932,8 +1934,8 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   // per SIMD.
   constexpr bool KEEP = TB == 1;
   constexpr int KT = KEEP ? NTL : 1;
-  int32_t loc[NTL][4];
-  double lam[NTL][4], xo[KT][4], hu[KT][4];
+  int32_t loc[DUAL ? 1 : NTL][4];
+  double lam[NTL][4], xo[KT][4], hu[DUAL ? 1 : KT][4], vd[DUAL ? NTL : 1][4];
 #pragma unroll
   for (int t = 0; t < NTL; ++t)
 #pragma unroll
@@ -1941,9 +1943,10 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
       const int i = rowof(t, r), k = colof(t);
       const int ii = i > k ? i : k, kk = i > k ? k : i;
       const int64_t e = (i < s && k < s) ? off + (int64_t)ii * (ii + 1) / 2 + kk : off;
-      loc[t][r] = a.blk_loc[e];
+      if constexpr (!DUAL) loc[t][r] = a.blk_loc[e];
       lam[t][r] = a.Lam[e];
       if constexpr (KEEP) xo[t][r] = a.X[e];
+      if constexpr (DUAL) vd[t][r] = a.Vd[e];   // the slack block v_k
     }
   T w[NTL][4];
   double f2 = 0.0;
@@ -1952,8 +1955,13 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = rowof(t, r), k = colof(t);
-      const double h = a.u[loc[t][r]];
-      if constexpr (KEEP) hu[t][r] = h;
+      double h;
+      if constexpr (DUAL) {
+        h = vd[t][r];
+      } else {
+        h = a.u[loc[t][r]];
+        if constexpr (KEEP) hu[t][r] = h;
+      }
       const T v = (i < s && k < s) ? (T)(h - lam[t][r] / rho) : T(0);
       w[t][r] = v;
       f2 += (double)v * (double)v;
@@ -2047,7 +2055,11 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
       const int i = rowof(t, r), k = colof(t);
       const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
       const bool lower = i < s && k <= i;
-      if constexpr (KEEP) {
+      if constexpr (DUAL) {
+        lo[t][r] = hp[t][r] = 0.0;
+        if constexpr (KEEP) xp[t][r] = xo[t][r];
+        else xp[t][r] = lower ? a.X[e] : 0.0;
+      } else if constexpr (KEEP) {
         lo[t][r] = lam[t][r];
         xp[t][r] = xo[t][r];
         hp[t][r] = hu[t][r];
@@ -2062,7 +2074,15 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = rowof(t, r), k = colof(t);
-      if (i < s && k <= i) {
+      if (DUAL && i < s && k <= i) {
+        // Algorithm 2: z_k and ||z_k - z_k_prev||^2 only
+        const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
+        const double zn = (double)(T(0.5) * (w[t][r] + cs[t][r]));
+        a.X[e] = zn;
+        const double wt = (i == k) ? 1.0 : 2.0;
+        const double dz = zn - xp[t][r];
+        p3 += wt * dz * dz;
+      } else if (!DUAL && i < s && k <= i) {
         const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
         const double xn = (double)(T(0.5) * (w[t][r] + cs[t][r]));
         const double hx = hp[t][r];
@@ -2085,11 +2105,13 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   p4 = wave_sum(p4);
   if (l == 0) {
     double *pp = a.part + NPART * (int64_t)cl;
-    pp[0] = p0;
-    pp[1] = p1;
-    pp[2] = p2;
+    if (!DUAL) {   // (Algorithm 2: the multiplier update writes these)
+      pp[0] = p0;
+      pp[1] = p1;
+      pp[2] = p2;
+      pp[4] = p4;
+    }
     pp[3] = p3;
-    pp[4] = p4;
     pp[5] = 0.0;   // no Jacobi sweeps
     pp[6] = 0.0;
   }
@@ -2149,24 +2171,33 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
   if (projection_variant_kind(precision, variant) == 2) {
-    // sign-function lists: Algorithm 1's register kernels; a caller that
-    // needs eigenvectors (the unrolled forward records V, theta) or another
-    // algorithm gets the Jacobi default of the same block size
-    if (!a.eig && !a.dual && !a.hsde && NT == 64 && (N == 16 || N == 32)) {
+    // sign-function lists: the register kernels of Algorithms 1 and 2; a
+    // caller that needs eigenvectors (the unrolled forward records V, theta)
+    // or Algorithm 3 gets the Jacobi default of the same block size
+    if (!a.eig && !a.hsde && NT == 64 && (N == 16 || N == 32)) {
       if (count <= 0) return hipSuccess;
       const int k1 = std::max(4, (int)std::ceil(std::log(1.0 / a.tol) / std::log(3.0)));
       const int k2 = precision == 1 ? 3 : 4;
+#define SDP_ADMM_SIGN(T, tb, dual)                                                              \
+  hipLaunchKernelGGL((k_admm_sign<T, tb, dual>), dim3(count), dim3(64), 0, st, a, list, k1, k2)
       if (precision == 1) {
-        if (N == 16)
-          hipLaunchKernelGGL((k_admm_sign<float, 1>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
-        else
-          hipLaunchKernelGGL((k_admm_sign<float, 2>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
+        if (N == 16) {
+          if (a.dual) SDP_ADMM_SIGN(float, 1, true);
+          else SDP_ADMM_SIGN(float, 1, false);
+        } else {
+          if (a.dual) SDP_ADMM_SIGN(float, 2, true);
+          else SDP_ADMM_SIGN(float, 2, false);
+        }
       } else {
-        if (N == 16)
-          hipLaunchKernelGGL((k_admm_sign<double, 1>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
-        else
-          hipLaunchKernelGGL((k_admm_sign<double, 2>), dim3(count), dim3(64), 0, st, a, list, k1, k2);
+        if (N == 16) {
+          if (a.dual) SDP_ADMM_SIGN(double, 1, true);
+          else SDP_ADMM_SIGN(double, 1, false);
+        } else {
+          if (a.dual) SDP_ADMM_SIGN(double, 2, true);
+          else SDP_ADMM_SIGN(double, 2, false);
+        }
       }
+#undef SDP_ADMM_SIGN
       return hipGetLastError();
     }
     variant = projection_default_variant(precision, N);

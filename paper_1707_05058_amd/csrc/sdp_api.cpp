@@ -768,9 +768,9 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       std::map<int, int64_t> count_of_size;
       for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
       std::map<int, int> var_of_size;
-      // Algorithm 1's cliques of up to 32 vertices: the sign-function
+      // Algorithm 1's and 2's cliques of up to 32 vertices: the sign-function
       // variants (one wave's registers, no eigenvectors) where selected
-      const bool sign_lists = opt.algorithm == SDP_ALG_PRIMAL &&
+      const bool sign_lists = opt.algorithm != SDP_ALG_HSDE &&
                               (opt.projection_method == 3 ||
                                (opt.projection_method == 0 && sign_by_default(h->precision)));
       // with the decoupling (FP32, warm start) the large blocks take the

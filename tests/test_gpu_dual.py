@@ -30,10 +30,10 @@ def weights(inst):
 
 
 def compare_fixed_n_dual(sdp, oracle_mod, insts, n_iter, precision="fp64", rho=1.0,
-                         tol_rel=1e-8):
-    log(f"dual fixed-N {[i.name for i in insts]} N={n_iter} {precision}")
+                         tol_rel=1e-8, **opts):
+    log(f"dual fixed-N {[i.name for i in insts]} N={n_iter} {precision} {opts}")
     with sdp.Solver(insts, rho=rho, tol=0.0, max_iter=100000, precision=precision,
-                    algorithm="dual") as S:
+                    algorithm="dual", **opts) as S:
         S.step(n_iter)
         sols = [S.solution(i) for i in range(len(insts))]
         hists = [S.history(i) for i in range(len(insts))]
@@ -64,6 +64,22 @@ def test_dual_fixed_n_sparse_a_singleton_cliques_and_batch(sdp, gpu, oracle_mod)
              sdpgen.block_arrow_instance(4, 6, 3, 30, seed=2, density=0.2),
              sdpgen.block_arrow_instance(6, 9, 4, 150, seed=3)]
     compare_fixed_n_dual(sdp, oracle_mod, insts, 20, rho=0.7)
+
+
+@pytest.mark.parametrize("method", ["scalar", "sign"])
+def test_dual_fixed_n_both_projection_paths(sdp, gpu, oracle_mod, method):
+    """The z-update on the warm-started Jacobi kernels and on the register
+    sign-function kernels (cliques of 8, 13, 24 and 31: both block sizes),
+    FP64 at 1e-8 and FP32-eig at 2e-4."""
+    from test_gpu_admm_sign import arrow_with_blocks
+    inst = arrow_with_blocks([4, 9, 20, 27], 4, 40, seed=11)
+    with sdp.Solver([inst], algorithm="dual", projection_method=method) as S:
+        dt = sdp.DTYPE_FP64
+        kinds = {sdp.projection_variant_kind(dt, v) for v in S.projection_plan_variants()}
+    assert kinds == ({2} if method == "sign" else {0})
+    compare_fixed_n_dual(sdp, oracle_mod, [inst], 30, rho=0.9, projection_method=method)
+    compare_fixed_n_dual(sdp, oracle_mod, [inst], 30, rho=0.9, precision="fp32", tol_rel=2e-4,
+                         projection_method=method)
 
 
 def test_dual_banded_workload_fixed_n(sdp, gpu, oracle_mod):
