@@ -852,16 +852,15 @@ def main():
 PROJ_SIZES = (15, 16, 24, 32, 50, 64, 96, 128)
 
 
-def sign_products(prec, N, threads):
+def sign_products(sdp, prec, N, threads):
     """Matrix-core flops of one sign-function projection of a padded N x N
-    block: k1 = ceil(log(1/tol) / log 3) steps of three products, k2 of two,
-    one final product, 2 N 16^2 flops per 16 x 16 tile; the LDS kernels form
-    the TN (TN + 1) / 2 tiles on or below the diagonal, the one-wave
-    register kernels for N = 32 all TN^2 (each off-diagonal tile is the
-    other's operand)."""
+    block: the library's schedule (sdp.sign_schedule) of k1 fast steps of
+    three products, k2 Newton-Schulz steps of two, one final product, at
+    2 N 16^2 flops per 16 x 16 tile; the LDS kernels form the TN (TN + 1) / 2
+    tiles on or below the diagonal, the one-wave register kernels for N = 32
+    all TN^2 (each off-diagonal tile is the other's operand)."""
     tol = 1e-6 if prec == "fp32" else 1e-14
-    k1 = max(4, math.ceil(math.log(1.0 / tol) / math.log(3.0)))
-    k2 = 3 if prec == "fp32" else 4
+    k1, k2 = sdp.sign_schedule(tol, N)
     tn = N // 16
     tiles = tn * tn if (N == 32 and threads == 64) else tn * (tn + 1) // 2
     return (3 * k1 + 2 * k2 + 1) * tiles * 2 * N * 16 * 16
@@ -918,7 +917,7 @@ def run_projection(args, sdp, torch, stream):
             model = 10.0 * s ** 3 * count
             executed = None
             if kinds[bv] == 2:
-                executed = sign_products(prec, variants[bv][0], variants[bv][1]) * count / (bms / 1e3) / 1e12
+                executed = sign_products(sdp, prec, variants[bv][0], variants[bv][1]) * count / (bms / 1e3) / 1e12
             res[f"{prec}_s{s}"] = dict(
                 s=s, blocks=count,
                 best_variant=dict(N=variants[bv][0], threads=variants[bv][1],

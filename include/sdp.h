@@ -233,15 +233,28 @@ int sdp_projection_variants(int32_t dtype, int32_t cap, int32_t *block_n, int32_
  *              round-robin, each pair's 16 x 16 problem diagonalised by one
  *              wave and applied to the block on the matrix cores;
  *   *kind = 2  matrix sign function, P+(W) = (W + W sign(W)) / 2, sign(W) by
- *              polynomial Newton-Schulz iterations on the matrix cores
- *              (ceil(log(1/tol) / log 3) steps of X (3I - 3.2X^2 + 1.2X^4), then
- *              3 (FP32) or 4 (FP64) of X (3I - X^2) / 2).  It yields no
- *              eigenvectors: the standalone projections run it, and the
- *              solver's plans hold it only for Algorithm 1's cliques of up
- *              to 32 vertices with projection_method = 3 (the one-wave
- *              variants of 16 and 32), where the projection needs no
- *              eigenvectors; everything else in the solver is kind 0 or 1. */
+ *              polynomial iterations on the matrix cores (k1 steps of
+ *              X (3I - 3.2X^2 + 1.2X^4), then k2 of X (3I - X^2) / 2, as
+ *              sdp_sign_schedule gives them).  It yields no eigenvectors: the
+ *              standalone projections run it, and the solver's plans hold it
+ *              only for the cliques of up to 32 vertices of Algorithms 1 and
+ *              2 (projection_method 0 or 3; the one-wave variants of 16 and
+ *              32), where the projection needs no eigenvectors; everything
+ *              else in the solver is kind 0 or 1. */
 int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *kind);
+
+/* The steps of the sign iteration for blocks of n vertices and a tolerance
+ * tol relative to ||W||_F (host only): *k1 fast steps
+ * X <- X (3I - 3.2X^2 + 1.2X^4) (three matrix products each) from
+ * X0 = W / ||W||_F, then *k2 >= 2 Newton-Schulz steps X <- X (3I - X^2) / 2
+ * (two products each), and one product for W sign(W).  The schedule is the
+ * fewest products for which the error of P+(W) = (W + W sign(W)) / 2, in exact
+ * arithmetic, stays within tol ||W||_F / 2 in the Frobenius norm (each
+ * eigenvalue follows the scalar maps; the bound takes n - 1 eigenvalues at
+ * the worst point of a fine grid).  FP32-eig's default tolerance 1e-6 gives
+ * (12, 2) for n = 16; FP64's 1e-14 gives (29, 2).  Tolerances below 1e-16
+ * are taken as 1e-16.  SDP_ERR_ARG if n < 1 or a pointer is NULL. */
+int sdp_sign_schedule(double tol, int32_t n, int32_t *k1, int32_t *k2);
 
 /* The variant sdp_psd_project_batched runs for blocks of up to max_size
  * (host only): the sign-function variant of the smallest block size that

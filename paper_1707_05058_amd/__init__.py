@@ -11,13 +11,13 @@ from ._native import (A_CSR, A_DENSE, ALG_DUAL, ALG_HSDE, ALG_PRIMAL, DTYPE_FP32
                       SdpError, Solver, default_options, lib, make_options, pack_blocks,
                       projection_default_variant, projection_variant_kind, projection_variant_two_level,
                       projection_variants, psd_project_batched,
-                      sdp_result, setup_status,
+                      sdp_result, setup_status, sign_schedule,
                       unpack_blocks)
 from .preprocess import (ChordalPattern, InstanceData, Scaling, chordal_extension,
                          extend_instance, scale_instance)
 
 __all__ = ["Solver", "SdpError", "psd_project_batched", "projection_variants",
-           "projection_default_variant",
+           "projection_default_variant", "sign_schedule",
            "projection_variant_kind", "projection_variant_two_level", "setup_status",
            "make_options",
            "default_options", "pack_blocks", "unpack_blocks", "lib", "EXPORTS", "FP64",

@@ -78,7 +78,7 @@ EXPORTS = ["sdp_default_options", "sdp_setup", "sdp_reset", "sdp_admm_step", "sd
            "sdp_get_projection_stats", "sdp_projection_plan", "sdp_time_stages",
            "sdp_update_data", "sdp_unrolled_forward", "sdp_vjp", "sdp_cg_steps", "sdp_destroy",
            "sdp_projection_variant_kind", "sdp_projection_plan_variants",
-           "sdp_projection_default_variant",
+           "sdp_projection_default_variant", "sdp_sign_schedule",
            "sdp_last_error",
            "sdp_pattern_create", "sdp_pattern_sizes", "sdp_pattern_get", "sdp_pattern_destroy",
            "sdp_scale_compute", "sdp_scale_apply", "sdp_scale_recover"]
@@ -120,6 +120,8 @@ def _load():
     lib.sdp_cg_steps.argtypes = [_p, C.POINTER(C.c_int64)]
     lib.sdp_projection_variant_kind.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     lib.sdp_projection_default_variant.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    lib.sdp_sign_schedule.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
     lib.sdp_projection_plan_variants.argtypes = [_p, C.c_int32, ip, C.POINTER(C.c_int32)]
     lib.sdp_destroy.argtypes = [_p]
     lib.sdp_destroy.restype = None
@@ -427,6 +429,14 @@ def projection_variant_kind(dtype: int, variant: int) -> int:
     t = C.c_int32(0)
     _check(lib.sdp_projection_variant_kind(int(dtype), int(variant), C.byref(t)))
     return t.value
+
+
+def sign_schedule(tol: float, n: int):
+    """(k1, k2): fast and Newton-Schulz steps of the sign iteration for blocks
+    of n vertices at tolerance tol (relative to ||W||_F)."""
+    k1, k2 = C.c_int32(0), C.c_int32(0)
+    _check(lib.sdp_sign_schedule(float(tol), int(n), C.byref(k1), C.byref(k2)))
+    return k1.value, k2.value
 
 
 def projection_default_variant(dtype: int, max_size: int) -> int:

@@ -24,7 +24,8 @@
 namespace {
 
 constexpr int ROW_NT = 256;   // threads of a row-dot workgroup
-constexpr int COL_NT = 256;   // threads of a column-dot workgroup (4 waves)
+constexpr int COL_NT = 512;   // threads of a column-dot workgroup
+constexpr int COL_WAVES = COL_NT / 64;   // waves splitting the rows of a tile
 constexpr int COL_W = 128;    // columns per column-dot tile (2 per lane)
 constexpr int MAX_R = 8;      // max rows per row-dot tile
 
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(ROW_NT) void k_rowdot(AffineArgs a) {
 //   RAW = 1:  u[j] = sum_i A[i][j] y[i]            (diagnostics: A^T y)
 //   RAW = 2:  u[j] = w[j] sum_i A[i][j] y[i] / D[j] (inside the CG solve)
 // One tile = 128 columns of one instance; lane l owns columns 2l, 2l+1 and
-// the 4 waves split the rows, so each wave reads contiguous 1 KiB segments.
+// the COL_WAVES waves split the rows, so each wave reads contiguous 1 KiB
+// segments.
 // ---------------------------------------------------------------------------
 template <int RAW, bool NTL>
 __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
   if (col < d.ld) {
     const double *base = (a.Bm ? a.Bm : a.A) + d.a_off + col;
 #pragma unroll 4
-    for (int i = w; i < d.m; i += 4) {
+    for (int i = w; i < d.m; i += COL_WAVES) {
       const dvec2 *pm = reinterpret_cast<const dvec2 *>(base + (int64_t)i * d.ld);
       dvec2 m2;
       if constexpr (NTL) m2 = __builtin_nontemporal_load(pm);
@@ -206,13 +208,13 @@ __global__ __launch_bounds__(COL_NT) void k_coldot(AffineArgs a) {
       ay += m2.y * yi;
     }
   }
-  __shared__ double2 red[4][64];
+  __shared__ double2 red[COL_WAVES][64];
   red[w][l] = make_double2(ax, ay);
   __syncthreads();
   if (w == 0 && col < d.ld) {
     double sx = 0.0, sy = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < COL_WAVES; ++k) {
       sx += red[k][l].x;
       sy += red[k][l].y;
     }

@@ -26,7 +26,12 @@
 #include <math.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 namespace {
 
@@ -1321,9 +1326,10 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a, const int32_t *__res
 //             slope 3 at 0, fixed point 1 with |p'(1)| = 0.6, p([0,1]) within
 //             [0, 1.21], inside the basin of the next phase)
 //   k2 steps  X <- X (3 I - X^2) / 2            (quadratic convergence to +-1)
-// An eigenvalue with |lambda| >= 3^-k1 ||W||_F reaches +-1; a smaller one
-// contributes at most |lambda| to P+ either way, so k1 = ceil(log(1/tol) /
-// log 3) keeps the result within the tolerance of the Jacobi variants.  Each
+// Small eigenvalues triple in each fast step; one that stays below 1 adds at
+// most |lambda| (1 - s(lambda)) / 2 to the error of P+.  (k1, k2) come from
+// sign_schedule: the fewest products that keep the Frobenius error below
+// the tolerance (relative to ||W||_F) of the Jacobi variants.  Each
 // product is a polynomial in W, symmetric in exact arithmetic: only the tiles
 // on or below the diagonal are computed, and only the lanes on or below the
 // diagonal store (both triangles), so every iterate is exactly symmetric.
@@ -1567,6 +1573,59 @@ __global__ __launch_bounds__(256) void k_identity_bases(T *vw, const int64_t *vw
 }
 
 }  // namespace
+
+// The sign iteration's schedule.  X0 = W / ||W||_F has eigenvalues delta_i
+// with sum delta_i^2 = 1; the fast map p(x) = 3x - 3.2x^3 + 1.2x^5 (three
+// products) and the Newton-Schulz map x(3 - x^2)/2 (two) are odd and act on
+// each eigenvalue alone, so P+ = (W + W s(X0)) / 2 is off by
+// e(delta) = |delta| |1 - s(|delta|)| / 2 (in units of ||W||_F) along
+// eigenvector i.  Every eigenvalue but the largest (|delta| >= 1/sqrt(n)) may
+// sit at the worst delta, so the Frobenius error is at most
+// sqrt(n - 1) max e.  The schedule takes the fewest products, with at least
+// two Newton-Schulz steps, for which 2 sqrt(n - 1) max e <= tol on a grid
+// of delta: 256 points per decade down to where delta / 2 alone meets the
+// bound, and 1024 uniform points on (0, 1] (e is smooth; the factor 2 covers
+// the grid and rounding).  Tolerances below 1e-16, beyond what FP64 products
+// resolve, are taken as 1e-16.
+void sign_schedule(double tol, int n, int *k1_out, int *k2_out) {
+  static std::mutex mu;
+  static std::map<std::pair<double, int>, std::pair<int, int>> cache;
+  const double t = tol >= 1e-16 ? tol : 1e-16;   // (also a NaN tolerance)
+  std::lock_guard<std::mutex> lock(mu);
+  const std::pair<double, int> key(t, n);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    const double target = t / (2.0 * std::sqrt((double)std::max(n - 1, 1)));
+    const int dec = std::max(1, (int)std::ceil(-std::log10(2.0 * target)));
+    std::vector<double> d;
+    for (int j = 0; j <= 256 * dec; ++j) d.push_back(std::pow(10.0, -dec + j / 256.0));
+    for (int j = 1; j <= 1024; ++j) d.push_back(j / 1024.0);
+    std::vector<double> x(d), y(d.size());
+    constexpr int K1_MAX = 200, K2_MAX = 8;
+    int best = INT_MAX, b1 = K1_MAX, b2 = 4;
+    for (int k1 = 0; k1 <= K1_MAX && 3 * k1 + 4 < best; ++k1) {
+      if (k1 > 0)
+        for (double &v : x) v = v * (3.0 - 3.2 * v * v + 1.2 * v * v * v * v);
+      y = x;
+      for (int k2 = 1; k2 <= K2_MAX && 3 * k1 + 2 * k2 < best; ++k2) {
+        double e = 0.0;
+        for (size_t j = 0; j < d.size(); ++j) {
+          y[j] = y[j] * (3.0 - y[j] * y[j]) / 2.0;
+          e = std::max(e, d[j] * std::fabs(1.0 - y[j]) / 2.0);
+        }
+        if (k2 >= 2 && e <= target) {
+          best = 3 * k1 + 2 * k2;
+          b1 = k1;
+          b2 = k2;
+          break;
+        }
+      }
+    }
+    it = cache.emplace(key, std::make_pair(b1, b2)).first;
+  }
+  *k1_out = it->second.first;
+  *k2_out = it->second.second;
+}
 
 hipError_t launch_dual_update(const ProjArgs &a, int64_t ncl, hipStream_t st) {
   if (ncl <= 0) return hipSuccess;
@@ -2176,8 +2235,8 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
     // or Algorithm 3 gets the Jacobi default of the same block size
     if (!a.eig && !a.hsde && NT == 64 && (N == 16 || N == 32)) {
       if (count <= 0) return hipSuccess;
-      const int k1 = std::max(4, (int)std::ceil(std::log(1.0 / a.tol) / std::log(3.0)));
-      const int k2 = precision == 1 ? 3 : 4;
+      int k1, k2;
+      sign_schedule(a.tol, N, &k1, &k2);
 #define SDP_ADMM_SIGN(T, tb, dual)                                                              \
   hipLaunchKernelGGL((k_admm_sign<T, tb, dual>), dim3(count), dim3(64), 0, st, a, list, k1, k2)
       if (precision == 1) {
@@ -2226,9 +2285,8 @@ hipError_t launch_standalone_projection(int dtype, int variant, int count, const
   projection_variant_info(dtype, variant, &N, &NT);
   if (projection_variant_kind(dtype, variant) == 2) {
     if (count <= 0) return hipSuccess;
-    // sign iteration: k1 fast steps resolve eigenvalues down to 3^-k1 ||W||_F
-    const int k1 = std::max(4, (int)std::ceil(std::log(1.0 / tol) / std::log(3.0)));
-    const int k2 = dtype == 1 ? 3 : 4;
+    int k1, k2;
+    sign_schedule(tol, N, &k1, &k2);
     return dispatch_sign(dtype, N, NT, count, sizes, offsets, in, out, k1, k2, st);
   }
   const int blk = projection_variant_two_level(dtype, variant);

@@ -624,13 +624,13 @@ void reset_state(sdp_handle *h) {
 void destroy_handle(sdp_handle *h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (hipStream_t a : h->aux_stream) (void)hipStreamSynchronize(a);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   for (void *p : h->owned) (void)hipFree(p);
   if (h->d_ckpt) (void)hipFree(h->d_ckpt);
   if (h->d_eigbuf) (void)hipFree(h->d_eigbuf);
   if (h->h_state) (void)hipHostFree(h->h_state);
   if (h->h_obj) (void)hipHostFree(h->h_obj);
-  for (hipStream_t a : h->aux_stream) (void)hipStreamSynchronize(a);
   for (hipStream_t a : h->aux_stream) (void)hipStreamDestroy(a);
   for (hipEvent_t e : h->ev_join) (void)hipEventDestroy(e);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -1001,10 +1001,9 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     p.decouple = opt.decouple && h->precision == SDP_FP32_EIG;
     p.dec_max_ref = h->precision == SDP_FP32_EIG ? 2 : 3;
     p.dec_skip = 4;
-    // the sign-function fallback of cliques whose certificate keeps failing:
-    // eigenvalues above the sweep tolerance (relative to ||W||_F) reach +-1
-    p.sign_k1 = std::max(4, (int)std::ceil(std::log(1.0 / h->jac_tol) / std::log(3.0)));
-    p.sign_k2 = 3;
+    // the sign-function fallback of cliques (of up to 96 vertices) whose
+    // certificate keeps failing: P+ to the sweep tolerance
+    sign_schedule(h->jac_tol, 96, &p.sign_k1, &p.sign_k2);
     // the rotation Q = I + T + T^2 / 2 has Q^T Q - I = T^4 / 4, at most
     // ||T||_F^4 / 4: with ||T||_F^2 <= sqrt(tol / 0.75) that stays below a
     // third of the sweep tolerance (the bound limits the refinements to
@@ -1401,6 +1400,17 @@ int sdp_projection_variant_kind(int32_t dtype, int32_t variant, int32_t *kind) {
     if (!kind || variant < 0 || variant >= projection_variant_count(prec))
       fail(SDP_ERR_ARG, "invalid arguments");
     *kind = projection_variant_kind(prec, variant);
+    return SDP_OK;
+  });
+}
+
+int sdp_sign_schedule(double tol, int32_t n, int32_t *k1, int32_t *k2) {
+  return guarded([&] {
+    if (!k1 || !k2 || n < 1) fail(SDP_ERR_ARG, "invalid arguments");
+    int a = 0, b = 0;
+    sign_schedule(tol, n, &a, &b);
+    *k1 = a;
+    *k2 = b;
     return SDP_OK;
   });
 }

@@ -128,6 +128,10 @@ int projection_variant_two_level(int precision, int variant);
 // 0 scalar Jacobi, 1 two-level Jacobi, 2 sign function (standalone only)
 int projection_variant_kind(int precision, int variant);
 int projection_default_variant(int precision, int s);   // -1 if s is too large (Jacobi)
+// Steps of the sign iteration for blocks of n vertices and a tolerance
+// relative to ||W||_F: k1 fast steps, k2 Newton-Schulz steps (cached per
+// (tol, n); thread-safe)
+void sign_schedule(double tol, int n, int *k1, int *k2);
 int projection_standalone_variant(int precision, int s);  // sign function where built
 hipError_t fill_random_blocks(int precision, void *out, int s, int count, uint32_t seed,
                               double offdiag, hipStream_t st);
