@@ -55,8 +55,8 @@ WORKLOADS = {
 }
 # solver options of workloads that need more than the defaults
 EXTRA_OPTIONS = {"large_m": dict(cg_max_iter=3, cg_tol=0.0)}
-# precision forms each workload is timed in (FP64 blocks stop at 96 x 96)
-FORMS = {"banded": ("fp32", "fp64"), "small": ("fp32", "fp64"), "large": ("fp32",),
+# precision forms each workload is timed in
+FORMS = {"banded": ("fp32", "fp64"), "small": ("fp32", "fp64"), "large": ("fp32", "fp64"),
          "batched": ("fp32", "fp64"), "nonchordal": ("fp32", "fp64"), "large_m": ("fp32", "fp64"),
          "adjoint": ("fp32", "fp64"), "projection": ("fp32", "fp64")}
 

@@ -1490,10 +1490,11 @@ hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t 
 
 // Kernel variants: padded block size N, threads per workgroup NT and kind
 // (0 scalar Jacobi: each thread owns K*K/NT 2x2 blocks, K = N/2; 1 two-level
-// Jacobi; 2 sign function, standalone projections only: it yields no
-// eigenvectors).  The autotuner picks, per clique size, the Jacobi variant
-// that runs fastest; without it the smallest N and the first NT listed for
-// that N are used.
+// Jacobi; 2 sign function: it yields no eigenvectors).  The autotuner picks,
+// per clique size, the Jacobi variant that runs fastest; without it the
+// smallest N and the first NT listed for that N are used.  FP64 blocks of
+// 97-128 have the sign function only (k_sign128: two FP64 blocks of 128 do
+// not fit in LDS, which every Jacobi variant with eigenvectors needs).
 struct Variant { int N, NT, kind; };
 constexpr Variant kVar32[] = {
     {16, 64, 0},   {32, 64, 0},    {32, 128, 0},  {32, 256, 0}, {48, 192, 0},
@@ -1506,7 +1507,7 @@ constexpr Variant kVar64[] = {{16, 64, 0},  {32, 64, 0},  {32, 128, 0}, {32, 256
                               {48, 192, 0}, {64, 256, 0}, {64, 128, 0}, {64, 512, 0},
                               {80, 320, 0}, {96, 576, 0}, {64, 256, 1}, {80, 320, 1},
                               {16, 64, 2},  {32, 64, 2},  {48, 192, 2}, {64, 256, 2},
-                              {80, 320, 2}, {96, 384, 2}};
+                              {80, 320, 2}, {96, 384, 2}, {128, 512, 2}};
 constexpr int kNVar32 = sizeof(kVar32) / sizeof(kVar32[0]);
 constexpr int kNVar64 = sizeof(kVar64) / sizeof(kVar64[0]);
 
@@ -1718,7 +1719,7 @@ int projection_bucket(int precision, int s) {
   return N;
 }
 
-int projection_max_size(int precision) { return precision == 1 ? 128 : 96; }
+int projection_max_size(int precision) { return 128; }
 
 // The sign iteration for blocks of 16, one wave per block, entirely in
 // registers.  A 16 x 16 x 16 product is four 16x16x4 matrix-core steps; the
@@ -2176,6 +2177,233 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   }
 }
 
+// FP64 blocks of up to 128 by the sign iteration with one N x N matrix in
+// LDS (the LDS kernels above hold two, 264 KB at this size).  Eight waves;
+// wave w owns column block J (16 columns: J = w for w < 4, 11 - w after, so
+// that the two waves that share a SIMD hold 9 of the 36 tiles on or below
+// the diagonal between them) and the lower tiles (I, J), I >= J, in it.  A
+// product C = L M takes its left operand from the matrix L in LDS and its
+// right operand M from registers: the wave's column block of M in the matrix
+// cores' result layout (register r of lane l in row block K holds
+// M(16K + g + 4r, 16J + c), g = l / 16, c = l % 16), which is exactly the
+// right operand of step (K, r) of a product.  (Z = Y (-3.2 I + 1.2 Y) reads
+// both operands from LDS.)  The lower tiles of a result go to LDS on both
+// sides of the diagonal, so every iterate is exactly symmetric, and a wave
+// reloads its column block of X from there after each step.  All factors
+// are polynomials in W and commute, so the fast step X (3 I + Z) is formed as
+// (3 I + Z) X with X the register operand, and the result as S W.
+// MODE: 0 standalone (row-major s x s blocks in `in` / `out`), 1 Algorithm
+// 1's clique step (X_k, Lambda_k and the five residual partials, as
+// k_admm_sign), 2 Algorithm 2's z-update (z_k and ||z_k - z_k_prev||^2).
+template <int MODE>
+__global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ sizes,
+                                                 const int64_t *__restrict__ offsets,
+                                                 const double *__restrict__ in,
+                                                 double *__restrict__ out, int k1, int k2) {
+  constexpr int N = 128, P = N + 1, TN = N / 16, NT = 512;
+  typedef Mma<double>::v4 v4;
+  __shared__ double L[N * P];
+  __shared__ double red[5 * (NT / 64)];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  const int J = w < 4 ? w : 11 - w, nt = TN - J, jc = 16 * J + c;
+
+  int s, cl = 0;
+  int64_t off;
+  bool inst_done = false;
+  double rho = 1.0;
+  if (MODE == 0) {
+    s = sizes[blockIdx.x];
+    off = offsets[blockIdx.x];
+    if (s <= 0 || s > N) return;   // sizes beyond max_size are left untouched
+  } else {
+    // neighbouring cliques share coordinates of u: keep them on one XCD
+    const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+    cl = list[x8 * q8 + min(x8, r8) + blockIdx.x / 8];
+    const int inst = a.cl_inst[cl];
+    s = a.cl_size[cl];
+    off = a.cl_off[cl];
+    inst_done = a.state[inst].done != 0;
+    rho = a.state[inst].rho;
+  }
+  // packed position of (i, j) in the clique's lower triangle (i, j < s)
+  const auto packed = [&](int i, int j) {
+    const int ii = i > j ? i : j, jj = i > j ? j : i;
+    return off + (int64_t)ii * (ii + 1) / 2 + jj;
+  };
+  // W(i, j) inside the clique, the same arithmetic at every call
+  const auto w_entry = [&](int i, int j, double lam, double h) {
+    return MODE == 0 ? 0.5 * (in[off + (int64_t)i * s + j] + in[off + (int64_t)j * s + i])
+                     : h - lam / rho;
+  };
+  // the wave's column block of W (zero outside the clique) into x; returns
+  // its sum of squares
+  double x[TN][4];
+  const auto gather_w = [&]() {
+    int32_t loc[TN][4];
+    double lam[TN][4];
+#pragma unroll
+    for (int K = 0; K < TN; ++K)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * K + g + 4 * r;
+        const int64_t e = (i < s && jc < s) ? packed(i, jc) : off;
+        if (MODE != 0) {
+          lam[K][r] = a.Lam[e];
+          if (MODE == 1) loc[K][r] = a.blk_loc[e];
+          else x[K][r] = a.Vd[e];   // the slack block v_k
+        }
+      }
+    double f2 = 0.0;
+#pragma unroll
+    for (int K = 0; K < TN; ++K)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * K + g + 4 * r;
+        double v = 0.0;
+        if (i < s && jc < s) {
+          if (MODE == 0) v = w_entry(i, jc, 0.0, 0.0);
+          else v = w_entry(i, jc, lam[K][r], MODE == 1 ? a.u[loc[K][r]] : x[K][r]);
+        }
+        x[K][r] = v;
+        f2 += v * v;
+      }
+    return f2;
+  };
+  double f2 = block_sum<NT>(gather_w(), red);
+  if (inst_done) return;   // a finished instance writes nothing (uniform)
+  if (MODE == 0 && !(f2 > 0.0 && f2 < INFINITY)) {
+    // W = 0: P+(W) = 0; a NaN or infinite entry: NaN throughout
+    const double fill = f2 == 0.0 ? 0.0 : NAN;
+#pragma unroll
+    for (int K = 0; K < TN; ++K)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * K + g + 4 * r;
+        if (i < s && jc < s) out[off + (int64_t)i * s + jc] = fill;
+      }
+    return;
+  }
+  // X0 = W / ||W||_F into L (the column blocks partition the matrix) and x
+  const double scale = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
+#pragma unroll
+  for (int K = 0; K < TN; ++K)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      x[K][r] *= scale;
+      L[(16 * K + g + 4 * r) * P + jc] = x[K][r];
+    }
+  __syncthreads();
+
+  // one product over the wave's lower tiles: acc(t) = sum_k L(k, :)^T M(k, J)
+  // for row block J + t; M from x, or (from_l) alpha [k == j] + beta L(k, j)
+  v4 acc[TN];
+  const auto product = [&](bool from_l, double alpha, double beta) {
+#pragma unroll
+    for (int t = 0; t < TN; ++t) acc[t] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int K = 0; K < TN; ++K)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * K + 4 * r + g;
+        const double b = from_l ? (k == jc ? alpha : 0.0) + beta * L[k * P + jc] : x[K][r];
+        const double *row = L + k * P + 16 * J + c;
+#pragma unroll
+        for (int t = 0; t < TN; ++t)
+          if (t < nt) acc[t] = Mma<double>::step(row[16 * t], b, acc[t]);
+      }
+  };
+  // the lower tiles of acc (transformed: alpha [i == j] + beta v) to L on
+  // both sides of the diagonal, between barriers
+  const auto store = [&](double alpha, double beta) {
+    __syncthreads();   // every wave has read L
+#pragma unroll
+    for (int t = 0; t < TN; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * (J + t) + g + 4 * r;
+        if (t < nt && i >= jc) {
+          const double v = (i == jc ? alpha : 0.0) + beta * acc[t][r];
+          L[i * P + jc] = v;
+          L[jc * P + i] = v;
+        }
+      }
+    __syncthreads();
+  };
+  // the products of the k1 fast steps (Y = X X; L = Y; Z = Y (-3.2 I +
+  // 1.2 Y); L = 3 I + Z; X <- L X; L = X) and of the k2 Newton-Schulz steps
+  // (Y = X X; L = 1.5 I - 0.5 Y; X <- L X; L = X), one product per pass (one
+  // copy of the product code keeps the register use within a wave's share)
+  const int nprod = 3 * k1 + 2 * k2;
+  for (int q = 0; q < nprod; ++q) {
+    const bool fast = q < 3 * k1;
+    const int ph = fast ? q % 3 : ((q - 3 * k1) % 2 == 0 ? 0 : 2);   // Y, Z, X
+    product(ph == 1, -3.2, 1.2);
+    double al = 0.0, be = 1.0;
+    if (ph == 1) al = 3.0;
+    if (!fast && ph == 0) {
+      al = 1.5;
+      be = -0.5;
+    }
+    store(al, be);
+    if (ph == 2) {
+#pragma unroll
+      for (int K = 0; K < TN; ++K)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[K][r] = L[(16 * K + g + 4 * r) * P + jc];
+    }
+  }
+  // C = S W (S in L, W again in x), then P+(W) = (W + C) / 2 on the lower tiles
+  gather_w();
+  product(false, 0.0, 0.0);
+
+  double pv[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int t = 0; t < TN; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * (J + t) + g + 4 * r;
+      if (t >= nt || i < jc || i >= s) continue;
+      if (MODE == 0) {
+        const double xn = 0.5 * (w_entry(i, jc, 0.0, 0.0) + acc[t][r]);
+        out[off + (int64_t)i * s + jc] = xn;
+        out[off + (int64_t)jc * s + i] = xn;
+        continue;
+      }
+      const int64_t e = packed(i, jc);
+      const double lam = a.Lam[e], xo = a.X[e];
+      const double h = MODE == 1 ? a.u[a.blk_loc[e]] : a.Vd[e];
+      const double xn = 0.5 * (w_entry(i, jc, lam, h) + acc[t][r]);
+      const double wt = (i == jc) ? 1.0 : 2.0;
+      a.X[e] = xn;
+      const double dx = xn - xo;
+      pv[3] += wt * dx * dx;
+      if (MODE == 1) {
+        const double ln = lam + rho * (xn - h);
+        a.Lam[e] = ln;
+        const double dc = xn - h;
+        pv[0] += wt * dc * dc;
+        pv[1] += wt * xn * xn;
+        pv[2] += wt * h * h;
+        pv[4] += wt * ln * ln;
+      }
+    }
+  if (MODE == 0) return;
+  block_sum_n<NT, 5>(pv, red);
+  if (tid == 0) {
+    double *pp = a.part + NPART * (int64_t)cl;
+    if (MODE == 1) {   // (Algorithm 2: the multiplier update writes these)
+      pp[0] = pv[0];
+      pp[1] = pv[1];
+      pp[2] = pv[2];
+      pp[4] = pv[4];
+    }
+    pp[3] = pv[3];
+    pp[5] = 0.0;   // no Jacobi sweeps
+    pp[6] = 0.0;
+  }
+}
+
 template <typename T, int N, int NT>
 hipError_t launch_sign(int count, const int32_t *sizes, const int64_t *offsets, const void *in,
                        void *out, int k1, int k2, hipStream_t st) {
@@ -2220,6 +2448,11 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
     SDP_SIGN(double, 64, 256)
     SDP_SIGN(double, 80, 320)
     SDP_SIGN(double, 96, 384)
+    if (N == 128 && NT == 512) {
+      hipLaunchKernelGGL(k_sign128<0>, dim3(count), dim3(512), 0, st, ProjArgs{}, nullptr, sizes,
+                         offsets, (const double *)in, (double *)out, k1, k2);
+      return hipGetLastError();
+    }
   }
 #undef SDP_SIGN
   return hipErrorInvalidValue;
@@ -2257,6 +2490,21 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
         }
       }
 #undef SDP_ADMM_SIGN
+      return hipGetLastError();
+    }
+    if (precision == 0 && N == 128 && NT == 512) {
+      // FP64 blocks of 97-128: no variant with eigenvectors exists (the
+      // plan refuses Algorithm 3 and the unrolled iterations for them)
+      if (a.eig || a.hsde) return hipErrorInvalidValue;
+      if (count <= 0) return hipSuccess;
+      int k1, k2;
+      sign_schedule(a.tol, N, &k1, &k2);
+      if (a.dual)
+        hipLaunchKernelGGL(k_sign128<2>, dim3(count), dim3(512), 0, st, a, list, nullptr, nullptr,
+                           nullptr, nullptr, k1, k2);
+      else
+        hipLaunchKernelGGL(k_sign128<1>, dim3(count), dim3(512), 0, st, a, list, nullptr, nullptr,
+                           nullptr, nullptr, k1, k2);
       return hipGetLastError();
     }
     variant = projection_default_variant(precision, N);
@@ -2304,6 +2552,11 @@ hipError_t launch_min_eig(int precision, int variant, const int32_t *list, int c
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
   if (projection_variant_kind(precision, variant) == 2) {   // eigenvalues: Jacobi
+    if (precision == 0 && N == 128)
+      // eigenvalues only: the scalar Jacobi of FP64 blocks of 128 needs one
+      // block in LDS (no eigenvectors), which fits
+      return launch_one<double, 128, 1024, MODE_MINEIG, false>(
+          count, a, list, nullptr, nullptr, nullptr, nullptr, lmin_out, a.max_sweeps, a.tol, st);
     variant = projection_default_variant(precision, N);
     projection_variant_info(precision, variant, &N, &NT);
   }

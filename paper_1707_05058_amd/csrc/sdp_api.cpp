@@ -120,6 +120,19 @@ int sign_variant(int precision, int s) {
   return -1;
 }
 
+// The sign-function variant that Algorithms 1 and 2 take for cliques of s
+// vertices that no Jacobi variant holds (FP64, 97-128), -1 if none.
+int big_sign_variant(int precision, int s) {
+  for (int v = 0; v < projection_variant_count(precision); ++v) {
+    int N, NT;
+    projection_variant_info(precision, v, &N, &NT);
+    if (projection_variant_kind(precision, v) == 2 && precision == 0 && N == 128 && NT == 512 &&
+        s <= N)
+      return v;
+  }
+  return -1;
+}
+
 // Whether projection_method 0 takes the sign-function variants for
 // Algorithm 1's cliques of up to 32 vertices: yes in both precisions (one
 // MI355X: banded workload projection 22.0 -> 13.8 us FP32, 52.9 -> 36.4 us
@@ -376,6 +389,7 @@ void enqueue_unrolled_iteration(sdp_handle *h, hipStream_t st, void *eig) {
     int v = h->bucket_size[b];
     if (projection_variant_kind(h->precision, v) == 2)
       v = projection_default_variant(h->precision, h->bucket_N[b]);
+    if (v < 0) fail(SDP_ERR_UNSUPPORTED, "no eigenvector kernel for this block size");
     HIPCHK(launch_admm_projection(h->precision, v, h->bucket_list[b], h->bucket_count[b], p, st));
   }
   HIPCHK(launch_residual_reduce(a, st));
@@ -670,6 +684,15 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     }
   }
 
+  // Algorithm 3 needs eigenvectors, which no FP64 kernel keeps for blocks of
+  // more than 96 (two such blocks do not fit in LDS)
+  if (opt.algorithm == SDP_ALG_HSDE && opt.precision == SDP_FP64)
+    for (int i = 0; i < batch; ++i)
+      for (int q = 0; q < H[i].p; ++q)
+        if (inst[i].clique_ptr[q + 1] - inst[i].clique_ptr[q] > 96)
+          fail(SDP_ERR_UNSUPPORTED, "instance " + std::to_string(i) +
+                                        ": Algorithm 3 in FP64 takes cliques of up to 96 vertices");
+
   sdp_handle *h = new sdp_handle();
   try {
     h->B = batch;
@@ -781,7 +804,13 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
                              ? 1
                              : pm;
       for (auto &kv : count_of_size) {
-        const int sv = sign_lists ? sign_variant(h->precision, kv.first) : -1;
+        int sv = sign_lists ? sign_variant(h->precision, kv.first) : -1;
+        if (fitting_variants(h->precision, kv.first, 0).empty()) {
+          // FP64 cliques of 97-128 (Algorithms 1 and 2; Algorithm 3 was
+          // refused above): the sign-function kernel is the only one
+          sv = big_sign_variant(h->precision, kv.first);
+          if (sv < 0) fail(SDP_ERR_UNSUPPORTED, "clique too large");
+        }
         var_of_size[kv.first] =
             sv >= 0 ? sv
             : opt.autotune ? tune_variant(h->precision, kv.first, kv.second, h->max_sweeps,
@@ -1747,6 +1776,10 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
     if (h->proj.dual || h->hsde)
       fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation is built for Algorithm 1 only");
     if (h->cg) fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation needs the factored affine step");
+    // the forward records every clique's eigenvectors for the adjoint
+    if (!h->adj_ready)
+      fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation takes cliques of up to 128 vertices in "
+                                "FP32 and 96 in FP64");
     const int nseg = (T + ckpt_every - 1) / ckpt_every;
     const int64_t need = (int64_t)nseg * 2 * std::max<int64_t>(h->npk, 1);
     if (need > h->ckpt_cap) {
@@ -1788,7 +1821,8 @@ int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar, in
     if (h->cg) fail(SDP_ERR_UNSUPPORTED, "unrolled differentiation needs the factored affine step");
     if (h->adj_T <= 0) fail(SDP_ERR_ARG, "run sdp_unrolled_forward first");
     if (!h->adj_ready)
-      fail(SDP_ERR_UNSUPPORTED, "the projection adjoint supports cliques up to 64 vertices");
+      fail(SDP_ERR_UNSUPPORTED, "the projection adjoint supports cliques of up to 128 vertices in "
+                                     "FP32 and 96 in FP64");
     auto &own = h->owned;
     if (!h->d_Xb) {
       h->d_Xb = dev_zeros<double>(h->npk, own);

@@ -74,10 +74,15 @@ def test_invalid_options_rejected(sdp):
     assert sdp.setup_status([inst], precision=7) == -1
 
 
-def test_fp64_projection_size_limit(sdp):
-    """The FP64 projection keeps the block and V in LDS up to 96 x 96."""
-    inst = sdpgen.lovasz_theta_odd_cycle(97)
-    assert sdp.setup_status([inst], precision=sdp.FP64) == -7
+def test_projection_size_limits(sdp):
+    """Blocks of up to 128 in both precisions; Algorithm 3 needs eigenvectors,
+    which FP64 keeps for blocks of up to 96 only (host checks, before any
+    device work)."""
+    assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(129)], precision=sdp.FP64) == -7
+    assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(129)], precision=sdp.FP32_EIG) == -7
+    assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(97)], precision=sdp.FP64,
+                            algorithm="hsde") == -7
+    assert "96" in sdp.lib.sdp_last_error().decode()
 
 
 def test_batch_error_names_instance(sdp):
@@ -94,11 +99,12 @@ def test_projection_argument_checks(sdp):
     assert lib.sdp_psd_project_batched(-1, 16, None, None, None, None, 0, None) == -1
     assert lib.sdp_psd_project_batched(0, 16, None, None, None, None, 5, None) == -1
     assert lib.sdp_psd_project_batched(0, 129, None, None, None, None, 1, None) == -7
-    assert lib.sdp_psd_project_batched(0, 97, None, None, None, None, 0, None) == -7
+    assert lib.sdp_psd_project_batched(0, 129, None, None, None, None, 0, None) == -7
+    assert lib.sdp_psd_project_batched(0, 128, None, None, None, None, 0, None) == 0
     # explicit variants: index range, block size that must hold max_size
     v32 = sdp.projection_variants(sdp.DTYPE_FP32)
     v64 = sdp.projection_variants(sdp.DTYPE_FP64)
-    assert max(n for n, _ in v32) == 128 and max(n for n, _ in v64) == 96
+    assert max(n for n, _ in v32) == 128 and max(n for n, _ in v64) == 128
     for n, nt in v32 + v64:
         assert n % 16 == 0 and nt % 64 == 0 and (n // 2) ** 2 % nt == 0
     assert lib.sdp_psd_project_variant(-1, 0, 16, None, None, None, None, 1, None) == -1

@@ -1,0 +1,153 @@
+"""FP64 cliques of 97-128 vertices: the sign-function kernel with one block in
+LDS (k_sign128), against the oracle (FP64 eigendecompositions).
+
+* fixed-N parity of Algorithm 1 (u, y, X_k, Lambda_k, residual history to
+  1e-8 relative to the largest entry) on cliques of 128, alone and beside
+  smaller cliques (several launch lists), with and without graphs;
+* fixed-N parity of Algorithm 2's z-update on cliques of 128;
+* a solve to 1e-4: the oracle's stopping iteration (+-1) and objective to
+  1e-6 relative, and the diagnostics (eps_alpha through the eigenvalue-only
+  Jacobi kernel of FP64 blocks of 128) against the oracle's;
+* the standalone projection of FP64 blocks of 97-128 (the default variant)
+  against the oracle to 1e-11 ||W||_F.
+"""
+import numpy as np
+import pytest
+
+import sdpgen
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def fixed_n(sdp, oracle_mod, inst, n_iter, tol_rel=1e-8, **opts):
+    log(f"FP64 large-clique fixed-N {inst.name} N={n_iter} {opts}")
+    P = oracle_mod.Problem(inst)
+    r = P.run(n_iter, tol=0.0)
+    with sdp.Solver([inst], tol=0.0, max_iter=100000, precision="fp64", **opts) as S:
+        plan = S.projection_plan()
+        S.step(n_iter)
+        sol = S.solution(0)
+        hc, hl, _ = S.history(0)
+    log(f"  plan {plan}")
+    assert any(n == 128 for n, _, _ in plan)
+    X, L = P.blocks()
+    errs = dict(u=rel_err(sol["u"], P.u()), y=rel_err(sol["y_dual"], P.y_dual()),
+                X=rel_err(sol["X_packed"], sdp.pack_blocks(X)),
+                L=rel_err(sol["L_packed"], sdp.pack_blocks(L)),
+                eps_c=rel_err(hc, r.hist_eps_c), eps_l=rel_err(hl, r.hist_eps_l))
+    log(f"  errors {errs}")
+    for k, v in errs.items():
+        assert v <= tol_rel, (k, v)
+
+
+def test_fixed_n_cliques_of_128(sdp, gpu, oracle_mod):
+    fixed_n(sdp, oracle_mod, sdpgen.block_arrow_instance(3, 120, 8, 200, seed=21), 12)
+
+
+def test_fixed_n_cliques_of_97_to_128_eager(sdp, gpu, oracle_mod):
+    fixed_n(sdp, oracle_mod, sdpgen.block_arrow_instance(2, 95, 2, 150, seed=22), 6,
+            graph_chunk=0)
+
+
+def test_fixed_n_mixed_with_small_cliques(sdp, gpu, oracle_mod):
+    # cliques of 128, 100 and 24 in one instance: three launch lists
+    n1, n2, n3 = 120, 92, 16
+    h = 8
+    n = n1 + n2 + n3 + h
+    arrow = np.arange(n - h, n, dtype=np.int32)
+    cliques, start = [], 0
+    for d in (n1, n2, n3):
+        cliques.append(np.concatenate([np.arange(start, start + d, dtype=np.int32), arrow]))
+        start += d
+    inst = sdpgen.random_instance(n, cliques, 180, seed=23, name="mixed_128_100_24")
+    fixed_n(sdp, oracle_mod, inst, 10)
+
+
+def test_dual_fixed_n_cliques_of_128(sdp, gpu, oracle_mod):
+    inst = sdpgen.block_arrow_instance(3, 120, 8, 200, seed=24)
+    n_iter = 10
+    P = oracle_mod.Problem(inst)
+    r = P.run_dual(n_iter, tol=0.0)
+    with sdp.Solver([inst], tol=0.0, max_iter=100000, precision="fp64",
+                    algorithm="dual") as S:
+        S.step(n_iter)
+        sol = S.solution(0)
+        hc, hl, _ = S.history(0)
+    Z, L = P.blocks()
+    errs = dict(u=rel_err(sol["u"], -P.rho * P.u()), y=rel_err(sol["y_dual"], P.y()),
+                Z=rel_err(sol["X_packed"], sdp.pack_blocks(Z)),
+                L=rel_err(sol["L_packed"], sdp.pack_blocks(L)),
+                eps_c=rel_err(hc, r.hist_eps_c), eps_l=rel_err(hl, r.hist_eps_l))
+    log(f"dual FP64 cliques of 128: {errs}")
+    for k, v in errs.items():
+        assert v <= 1e-8, (k, v)
+
+
+def test_solve_and_diagnostics_cliques_of_128(sdp, gpu, oracle_mod):
+    inst = sdpgen.block_arrow_instance(2, 120, 8, 150, seed=25)
+    P = oracle_mod.Problem(inst)
+    ref = P.run(20000, tol=1e-4)
+    do = P.diagnostics()
+    with sdp.Solver([inst], tol=1e-4, max_iter=20000, precision="fp64") as S:
+        g = S.solve()[0]
+        dg = S.diagnostics()[0]
+    log(f"solve: gpu {g['iters']} iterations obj {g['objective']:.12g}; oracle {ref.iters} "
+        f"obj {P.objective():.12g}")
+    assert g["status"] == 0 and ref.status == 0
+    assert abs(g["iters"] - ref.iters) <= 1
+    assert abs(g["objective"] - P.objective()) <= 1e-6 * max(1.0, abs(P.objective()))
+    # eps_g is the normalised difference of two objectives of ~124 that agree
+    # to ~1e-6 relative: each carries the iterates' relative error (the 1e-8
+    # fixed-N bar), which the cancellation leaves as an absolute error of up
+    # to ~1e-8 |obj| / (1 + 2 |obj|)
+    for k, absbar in (("eps_d", 1e-12), ("eps_g", 1e-8), ("eps_alpha", 1e-12)):
+        log(f"  {k}: gpu {dg[k]:.6e} oracle {do[k]:.6e}")
+        assert abs(dg[k] - do[k]) <= 1e-6 * max(do[k], 1e-12) + absbar, k
+
+
+def test_hsde_refuses_fp64_cliques_above_96(sdp, gpu):
+    inst = sdpgen.block_arrow_instance(2, 95, 2, 150, seed=26)
+    assert sdp.setup_status([inst], precision=sdp.FP64, algorithm="hsde") == -7   # unsupported
+    assert sdp.setup_status([inst], precision=sdp.FP32_EIG, algorithm="hsde") == 0
+
+
+def test_unrolled_refuses_fp64_cliques_above_96(sdp, gpu):
+    inst = sdpgen.block_arrow_instance(2, 95, 2, 150, seed=27)
+    with sdp.Solver([inst], precision="fp64") as S:
+        with pytest.raises(sdp.SdpError) as e:
+            S.unrolled_forward(3, 1)
+    assert e.value.code == -7   # unsupported
+
+
+def test_standalone_fp64_97_to_128(sdp, gpu, oracle_mod):
+    import torch
+    sizes = [97, 100, 113, 127, 128, 1, 5]
+    blocks = sdpgen.goe_blocks(sizes, seed=28)
+    v = sdp.projection_default_variant(sdp.DTYPE_FP64, 128)
+    assert sdp.projection_variant_kind(sdp.DTYPE_FP64, v) == 2
+    s = np.array(sizes, dtype=np.int32)
+    offs = np.concatenate([[0], np.cumsum(s.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+    flat = np.concatenate([b.ravel() for b in blocks])
+    dev = torch.device("cuda:0")
+    t_in = torch.from_numpy(flat).to(dev)
+    t_out = torch.full_like(t_in, float("nan"))
+    sdp.psd_project_batched(torch.from_numpy(s).to(dev), torch.from_numpy(offs).to(dev),
+                            t_in, t_out, 128)
+    torch.cuda.synchronize()
+    out = t_out.cpu().numpy()
+    for W, o, n in zip(blocks, offs, sizes):
+        X = out[o:o + n * n].reshape(n, n)
+        ref = oracle_mod.psd_project(0.5 * (W + W.T))
+        err = np.abs(X - ref).max() / max(np.linalg.norm(W), 1e-300)
+        log(f"  standalone FP64 s={n}: {err:.2e}")
+        assert err <= 1e-11
+        assert np.array_equal(X, X.T)
