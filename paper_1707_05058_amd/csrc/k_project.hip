@@ -2177,6 +2177,66 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   }
 }
 
+// One pass of k_sign128 for a wave with NTL lower tiles in column block J:
+// the product acc(t) = sum_k L(k, 16 (J + t) + c')^T M(k, J), M from x or
+// (from_l) alpha [k == j] + beta L(k, j); then, between barriers, the lower
+// tiles transformed to sa [i == j] + sb v into L on both sides of the
+// diagonal.  The tile count is a template parameter, so each step's loads
+// and matrix-core steps form one straight block (a run-time bound puts every
+// load and step under a branch of its own), and the accumulators live only
+// inside the pass.  The loads of step s + 1 are issued before the steps of
+// s; the scheduling barrier keeps the compiler from hoisting all of them,
+// which would need more registers than a wave has.
+template <int NTL>
+__device__ __forceinline__ void sb_pass(double *L, const double (&x)[8][4], bool from_l,
+                                        double alpha, double beta, double sa, double sb, int J,
+                                        int g, int c) {
+  constexpr int P = 129;
+  typedef Mma<double>::v4 v4;
+  const int jc = 16 * J + c;
+  const auto bval = [&](int K, int r) {
+    const int k = 16 * K + 4 * r + g;
+    return from_l ? (k == jc ? alpha : 0.0) + beta * L[k * P + jc] : x[K][r];
+  };
+  v4 acc[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) acc[t] = v4{0, 0, 0, 0};
+  double av[NTL], b = bval(0, 0);
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) av[t] = L[g * P + jc + 16 * t];
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    double an[NTL], bn = 0.0;
+    if (st + 1 < 32) {
+      const int K = (st + 1) >> 2, r = (st + 1) & 3, k = 16 * K + 4 * r + g;
+      bn = bval(K, r);
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) an[t] = L[k * P + jc + 16 * t];
+    }
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) acc[t] = Mma<double>::step(av[t], b, acc[t]);
+    __builtin_amdgcn_sched_barrier(0);
+    if (st + 1 < 32) {
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) av[t] = an[t];
+      b = bn;
+    }
+  }
+  __syncthreads();   // every wave has read L
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * (J + t) + g + 4 * r;
+      if (i >= jc) {
+        const double v = (i == jc ? sa : 0.0) + sb * acc[t][r];
+        L[i * P + jc] = v;
+        L[jc * P + i] = v;
+      }
+    }
+  __syncthreads();
+}
+
 // FP64 blocks of up to 128 by the sign iteration with one N x N matrix in
 // LDS (the LDS kernels above hold two, 264 KB at this size).  Eight waves;
 // wave w owns column block J (16 columns: J = w for w < 4, 11 - w after, so
@@ -2191,7 +2251,8 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
 // sides of the diagonal, so every iterate is exactly symmetric, and a wave
 // reloads its column block of X from there after each step.  All factors
 // are polynomials in W and commute, so the fast step X (3 I + Z) is formed as
-// (3 I + Z) X with X the register operand, and the result as S W.
+// (3 I + Z) X with X the register operand, and the result as S W, which also
+// goes to LDS for the epilogue.
 // MODE: 0 standalone (row-major s x s blocks in `in` / `out`), 1 Algorithm
 // 1's clique step (X_k, Lambda_k and the five residual partials, as
 // k_admm_sign), 2 Algorithm 2's z-update (z_k and ||z_k - z_k_prev||^2).
@@ -2202,7 +2263,6 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
                                                  const double *__restrict__ in,
                                                  double *__restrict__ out, int k1, int k2) {
   constexpr int N = 128, P = N + 1, TN = N / 16, NT = 512;
-  typedef Mma<double>::v4 v4;
   __shared__ double L[N * P];
   __shared__ double red[5 * (NT / 64)];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
@@ -2240,13 +2300,18 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
   // its sum of squares
   double x[TN][4];
   const auto gather_w = [&]() {
+    // the lane index passes through an empty asm statement, so that the
+    // addresses are formed at each call rather than hoisted out of the
+    // iteration loop and kept live across it
+    int gl = g;
+    asm volatile("" : "+v"(gl));
     int32_t loc[TN][4];
     double lam[TN][4];
 #pragma unroll
     for (int K = 0; K < TN; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * K + g + 4 * r;
+        const int i = 16 * K + gl + 4 * r;
         const int64_t e = (i < s && jc < s) ? packed(i, jc) : off;
         if (MODE != 0) {
           lam[K][r] = a.Lam[e];
@@ -2259,7 +2324,7 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
     for (int K = 0; K < TN; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * K + g + 4 * r;
+        const int i = 16 * K + gl + 4 * r;
         double v = 0.0;
         if (i < s && jc < s) {
           if (MODE == 0) v = w_entry(i, jc, 0.0, 0.0);
@@ -2295,77 +2360,61 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
     }
   __syncthreads();
 
-  // one product over the wave's lower tiles: acc(t) = sum_k L(k, :)^T M(k, J)
-  // for row block J + t; M from x, or (from_l) alpha [k == j] + beta L(k, j)
-  v4 acc[TN];
-  const auto product = [&](bool from_l, double alpha, double beta) {
-#pragma unroll
-    for (int t = 0; t < TN; ++t) acc[t] = v4{0, 0, 0, 0};
-#pragma unroll
-    for (int K = 0; K < TN; ++K)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * K + 4 * r + g;
-        const double b = from_l ? (k == jc ? alpha : 0.0) + beta * L[k * P + jc] : x[K][r];
-        const double *row = L + k * P + 16 * J + c;
-#pragma unroll
-        for (int t = 0; t < TN; ++t)
-          if (t < nt) acc[t] = Mma<double>::step(row[16 * t], b, acc[t]);
-      }
+  const int ntu = __builtin_amdgcn_readfirstlane(nt);   // uniform per wave
+  // one pass: L <- sa I + sb (L M), M from x or alpha I + beta L (from_l)
+  const auto pass = [&](bool from_l, double alpha, double beta, double sa, double sb, int gq,
+                        int cq) {
+    switch (ntu) {
+      case 8: sb_pass<8>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 7: sb_pass<7>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 6: sb_pass<6>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 5: sb_pass<5>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 4: sb_pass<4>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 3: sb_pass<3>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 2: sb_pass<2>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      default: sb_pass<1>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+    }
   };
-  // the lower tiles of acc (transformed: alpha [i == j] + beta v) to L on
-  // both sides of the diagonal, between barriers
-  const auto store = [&](double alpha, double beta) {
-    __syncthreads();   // every wave has read L
-#pragma unroll
-    for (int t = 0; t < TN; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * (J + t) + g + 4 * r;
-        if (t < nt && i >= jc) {
-          const double v = (i == jc ? alpha : 0.0) + beta * acc[t][r];
-          L[i * P + jc] = v;
-          L[jc * P + i] = v;
-        }
-      }
-    __syncthreads();
-  };
-  // the products of the k1 fast steps (Y = X X; L = Y; Z = Y (-3.2 I +
-  // 1.2 Y); L = 3 I + Z; X <- L X; L = X) and of the k2 Newton-Schulz steps
-  // (Y = X X; L = 1.5 I - 0.5 Y; X <- L X; L = X), one product per pass (one
-  // copy of the product code keeps the register use within a wave's share)
+  // The passes of the k1 fast steps (L = X X; L = 3 I + L (-3.2 I + 1.2 L);
+  // L = L X, then x = L) and of the k2 Newton-Schulz steps (L = 1.5 I -
+  // 0.5 X X; L = L X, then x = L), and a last one, L = S W with W again in
+  // x.  (The lane index passes through an empty asm statement at each pass,
+  // so that the LDS addresses derived from it are formed in the pass instead
+  // of hoisted out of the loop and kept live, which spills.)
   const int nprod = 3 * k1 + 2 * k2;
-  for (int q = 0; q < nprod; ++q) {
+  for (int q = 0; q <= nprod; ++q) {
+    int lq = l;
+    asm volatile("" : "+v"(lq));
+    const int gq = lq >> 4, cq = lq & 15;
     const bool fast = q < 3 * k1;
     const int ph = fast ? q % 3 : ((q - 3 * k1) % 2 == 0 ? 0 : 2);   // Y, Z, X
-    product(ph == 1, -3.2, 1.2);
-    double al = 0.0, be = 1.0;
-    if (ph == 1) al = 3.0;
-    if (!fast && ph == 0) {
-      al = 1.5;
-      be = -0.5;
+    if (q == nprod) gather_w();
+    double sa = 0.0, sb = 1.0;
+    if (q < nprod && ph == 1) sa = 3.0;
+    if (q < nprod && !fast && ph == 0) {
+      sa = 1.5;
+      sb = -0.5;
     }
-    store(al, be);
-    if (ph == 2) {
+    pass(q < nprod && ph == 1, -3.2, 1.2, sa, sb, gq, cq);
+    if (q < nprod && ph == 2) {
 #pragma unroll
       for (int K = 0; K < TN; ++K)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) x[K][r] = L[(16 * K + g + 4 * r) * P + jc];
+        for (int r = 0; r < 4; ++r) x[K][r] = L[(16 * K + gq + 4 * r) * P + 16 * J + cq];
     }
   }
-  // C = S W (S in L, W again in x), then P+(W) = (W + C) / 2 on the lower tiles
-  gather_w();
-  product(false, 0.0, 0.0);
 
+  // P+(W) = (W + C) / 2 on the lower entries of the wave's column block
   double pv[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t < TN; ++t)
+  for (int K = 0; K < TN; ++K)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * (J + t) + g + 4 * r;
-      if (t >= nt || i < jc || i >= s) continue;
+      const int i = 16 * K + g + 4 * r;
+      if (i < jc || i >= s) continue;
+      const double cv = L[i * P + jc];
       if (MODE == 0) {
-        const double xn = 0.5 * (w_entry(i, jc, 0.0, 0.0) + acc[t][r]);
+        const double xn = 0.5 * (w_entry(i, jc, 0.0, 0.0) + cv);
         out[off + (int64_t)i * s + jc] = xn;
         out[off + (int64_t)jc * s + i] = xn;
         continue;
@@ -2373,7 +2422,7 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
       const int64_t e = packed(i, jc);
       const double lam = a.Lam[e], xo = a.X[e];
       const double h = MODE == 1 ? a.u[a.blk_loc[e]] : a.Vd[e];
-      const double xn = 0.5 * (w_entry(i, jc, lam, h) + acc[t][r]);
+      const double xn = 0.5 * (w_entry(i, jc, lam, h) + cv);
       const double wt = (i == jc) ? 1.0 : 2.0;
       a.X[e] = xn;
       const double dx = xn - xo;
