@@ -233,9 +233,10 @@ def summarize_rocprof(workload, trace_dir, fetch_dir, write_dir, commands):
            "copy_calibration": {"bytes": COPY_CAL_BYTES, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_scale": sf, "write_scale": sw},
            "stages": {}}
-    lines += ["", f"HBM counters per launch (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, "
+    lines += ["", f"HBM counters per launch (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, mean over "
+              f"the launches within 10% of the largest, "
               f"scaled by a {COPY_CAL_BYTES >> 20} MiB copy: fetch x{sf:.3f}, write x{sw:.3f}):", "",
-              "| stage | kernels | launches | fetch (MB) | write (MB) | HBM bytes per launch |",
+              "| stage | kernels | full launches | fetch (MB) | write (MB) | HBM bytes per launch |",
               "|---|---|---:|---:|---:|---:|"]
     for stage, pats in STAGE_KERNELS.items():
         f_names = [n for n in fetch
@@ -247,6 +248,12 @@ def summarize_rocprof(workload, trace_dir, fetch_dir, write_dir, commands):
         wv = [v for n in f_names for v in write.get(n, [])]
         if not fv or not wv:
             continue
+        # launches with every instance active: in a batch solved to
+        # tolerance, finished instances skip their work, so the launches of
+        # the late iterations move fewer bytes; those within 10% of the
+        # largest dispatch are the full ones
+        fv = [v for v in fv if v >= 0.9 * max(fv)]
+        wv = [v for v in wv if v >= 0.9 * max(wv)]
         fb = sum(fv) / len(fv) * sf * 1024.0
         wb = sum(wv) / len(wv) * sw * 1024.0
         out["stages"][stage] = {"kernels": sorted({_short_kernel(n) for n in f_names}),
@@ -486,6 +493,11 @@ def batched_leg(args, sdp, torch, stream):
         f = time_form(sdp, torch, insts, precision, steps, args.warmup, args.stage_iters, stream,
                       repeat_solve=False, eager=False, extra=solver_options(args))
         out["fp32_eig" if precision == "fp32" else "fp64"] = {k: f[k] for k in keep if k in f}
+        if precision == "fp32":
+            # the longest stage of the batched FP32 iteration, with the counter
+            # traffic of profiles/traffic_batched.json when it is current
+            out["roofline"] = roofline_of(insts, f["stages_ms"], f["timed_sweeps_per_projection"],
+                                          "primal", solver_options(args), "batched")
         print(f"[bench] batched {precision}: {f['iter_per_s']:.1f} batched iter/s",
               file=sys.stderr, flush=True)
     print("[bench] batched: loop of per-instance FP64 solves", file=sys.stderr, flush=True)
