@@ -85,10 +85,12 @@ def test_summarizer_trace_only_and_counters(tmp_path, monkeypatch):
     hdr = ["Kernel_Name", "Counter_Value"]
     _write_csv(str(tmp_path / "fetch" / "f_counter_collection.csv"), hdr,
                [["__amd_rocclr_copyBuffer", kib / 2],
-                ["void k_coldot<0, false>(AffineArgs)", 1000.0],
+                ["void k_coldot<0, false>(AffineArgs)", 2900.0],
+                ["void k_coldot<0, false>(AffineArgs)", 1000.0],   # instances finished
                 ["void k_coldot<0, false>(AffineArgs)", 3000.0]])
     _write_csv(str(tmp_path / "write" / "w_counter_collection.csv"), hdr,
                [["__amd_rocclr_copyBuffer", kib],
+                ["void k_coldot<0, false>(AffineArgs)", 29.0],
                 ["void k_coldot<0, false>(AffineArgs)", 10.0],
                 ["void k_coldot<0, false>(AffineArgs)", 30.0]])
     bench.summarize_rocprof("banded", str(trace), str(tmp_path / "fetch"),
@@ -97,9 +99,10 @@ def test_summarizer_trace_only_and_counters(tmp_path, monkeypatch):
     assert t["copy_calibration"]["fetch_scale"] == pytest.approx(2.0)
     assert t["copy_calibration"]["write_scale"] == pytest.approx(1.0)
     st = t["stages"]["AT_y"]
+    # the mean over the full launches (within 10% of the largest dispatch)
     assert st["launches"] == 2
-    assert st["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 2 * 1024)
-    assert st["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
+    assert st["fetch_bytes_per_launch"] == pytest.approx(2950.0 * 2 * 1024)
+    assert st["write_bytes_per_launch"] == pytest.approx(29.5 * 1024)
     # the stage is tied to its source: the traffic goes stale when it changes
     assert bench.load_traffic("banded", "AT_y") == pytest.approx(st["hbm_bytes_per_launch"])
     (tmp_path / "paper_1707_05058_amd" / "csrc" / bench.STAGE_SOURCE["AT_y"]).write_text("// new")
