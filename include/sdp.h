@@ -19,7 +19,9 @@
  *    entry (i, i) is present.  The pattern must equal the union of all clique
  *    pairs (a chordal graph or a chordal extension).
  *  - Cliques are 0-based vertex lists in strictly increasing order, at most
- *    128 vertices each (96 for the SDP_FP64 projection).
+ *    128 vertices each.  In SDP_FP64, cliques of more than 96 vertices are
+ *    projected by the matrix sign function (no eigenvectors), so Algorithm 3
+ *    and the unrolled iterations refuse them (SDP_ERR_UNSUPPORTED).
  *  - A clique block X_k (s x s) is stored "packed": lower triangle row by
  *    row, entry (i, j), i >= j, at i*(i+1)/2 + j.
  *  - All functions return an int status: 0 = SDP_OK, >0 informational,
@@ -114,7 +116,7 @@ typedef struct {
                                    u = P_K(u_hat - v), v += u - u_hat; stops on
                                    max(eps_p, eps_d, eps_g, eps_c) <= tol or on an
                                    infeasibility certificate; no penalty, so adaptive_rho
-                                   must be 0) */
+                                   must be 0; in SDP_FP64 cliques of up to 96 vertices) */
   int32_t cg_max_iter;          /* 0: the affine step solves with the cached Cholesky factor
                                    of A D^-1 A^T.  > 0 (Algorithm 1 only): no factor is
                                    formed; each iteration solves (A W D^-1 A^T) y = rhs by
@@ -210,7 +212,7 @@ int sdp_solve(sdp_handle *h, sdp_result *res);
  * out_k = V diag(max(theta, 0)) V^T for in_k = V diag(theta) V^T.
  * sizes (int32[count]) and offsets (int64[count], element offsets of each
  * full s x s row-major block) are DEVICE pointers; in/out are device buffers
- * of `dtype`; every size must be <= max_size <= 128 (96 for FP64).  Blocks
+ * of `dtype`; every size must be <= max_size <= 128.  Blocks
  * must not overlap between in and out.  Asynchronous on `stream`.  Runs the
  * sign-function variant (sdp_projection_variant_kind = 2) of the smallest
  * block size that holds max_size: the same projection to the tolerance of
@@ -367,8 +369,9 @@ int sdp_update_data(sdp_handle *h, const double *c, const double *b);
 
 /* Runs the T unrolled iterations from the initial state, keeping X_k and
  * Lambda_k every ckpt_every iterations for the reverse sweep, and copies u_T
- * to u_out (DEVICE, concatenated layout; may be NULL).  Needs adaptive_rho = 0
- * and SDP_ALG_PRIMAL (SDP_ERR_UNSUPPORTED otherwise).
+ * to u_out (DEVICE, concatenated layout; may be NULL).  Needs adaptive_rho = 0,
+ * SDP_ALG_PRIMAL, the cached factor and cliques of up to 128 vertices in
+ * SDP_FP32_EIG or 96 in SDP_FP64 (SDP_ERR_UNSUPPORTED otherwise).
  * Leaves the handle at iterate T.  Synchronises. */
 int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u_out);
 
@@ -380,8 +383,9 @@ int sdp_unrolled_forward(sdp_handle *h, int32_t T, int32_t ckpt_every, double *u
  * compact vectors (what an autodiff framework uses).  Segments between
  * checkpoints are recomputed forward, storing each projection's eigenvectors
  * (FP32 in the SDP_FP32_EIG form), then reversed; the projection adjoints run
- * on the matrix cores for every clique size the solver takes (128 in FP32, 96
- * in FP64).  The handle's iterate is unspecified afterwards (call
+ * on the matrix cores for cliques of up to 128 vertices in FP32 and 96 in
+ * FP64 (larger ones: sdp_unrolled_forward returns SDP_ERR_UNSUPPORTED).  The
+ * handle's iterate is unspecified afterwards (call
  * sdp_reset before solving again).  Synchronises. */
 int sdp_vjp(sdp_handle *h, const double *u_bar, double *c_bar, double *b_bar,
             int32_t euclidean);
