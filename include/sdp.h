@@ -129,14 +129,16 @@ typedef struct {
                                    0: always cg_max_iter steps */
   int32_t projection_method;    /* eigensolver of the clique projections: 0 the autotuner (or,
                                    with autotune = 0, the default variant) chooses, and with
-                                   Algorithms 1 and 2 cliques of up to 32 vertices take the
-                                   sign function as with 3; 1 scalar
-                                   parallel-order Jacobi only; 2 the two-level (block) Jacobi
-                                   wherever a variant for the clique size exists (blocks of
-                                   64 and more), scalar elsewhere; 3 (Algorithms 1 and 2)
-                                   cliques of up to 32 vertices take the matrix sign function
-                                   in one wave's registers (X_k = (W + W sign(W)) / 2, no
-                                   eigenvectors, no warm start), larger ones as with 0 */
+                                   Algorithms 1 and 2 the cliques listed under 3 take the
+                                   sign function; 1 scalar parallel-order Jacobi only (FP64
+                                   cliques of 97-128 still take the sign function, the only
+                                   kernel for them); 2 the two-level (block) Jacobi wherever a
+                                   variant for the clique size exists (blocks of 64 and more),
+                                   scalar elsewhere; 3 (Algorithms 1 and 2) the matrix sign
+                                   function, X_k = (W + W sign(W)) / 2 (no eigenvectors, no
+                                   warm start), for cliques of up to 32 vertices (in one
+                                   wave's registers) and in SDP_FP64 for all cliques (larger
+                                   ones with one block in LDS); the rest as with 0 */
   int32_t decouple;             /* 1 (SDP_FP32_EIG with warm_start = 1; blocks padded to 64
                                    and more; Algorithms 1-3 outside the unrolled iterations):
                                    a warm-started projection first separates the eigenspaces

@@ -1493,7 +1493,7 @@ hipError_t launch_one(int count, ProjArgs a, const int32_t *list, const int32_t 
 // Jacobi; 2 sign function: it yields no eigenvectors).  The autotuner picks,
 // per clique size, the Jacobi variant that runs fastest; without it the
 // smallest N and the first NT listed for that N are used.  FP64 blocks of
-// 97-128 have the sign function only (k_sign128: two FP64 blocks of 128 do
+// 97-128 have the sign function only (k_sign_big: two FP64 blocks of 128 do
 // not fit in LDS, which every Jacobi variant with eigenvectors needs).
 struct Variant { int N, NT, kind; };
 constexpr Variant kVar32[] = {
@@ -2177,46 +2177,52 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   }
 }
 
-// One pass of k_sign128 for a wave with NTL lower tiles in column block J:
+// One pass of k_sign_big for a wave with NTL lower tiles in column block J:
 // the product acc(t) = sum_k L(k, 16 (J + t) + c')^T M(k, J), M from x or
 // (from_l) alpha [k == j] + beta L(k, j); then, between barriers, the lower
 // tiles transformed to sa [i == j] + sb v into L on both sides of the
-// diagonal.  The tile count is a template parameter, so each step's loads
-// and matrix-core steps form one straight block (a run-time bound puts every
-// load and step under a branch of its own), and the accumulators live only
-// inside the pass.  The loads of step s + 1 are issued before the steps of
-// s; the scheduling barrier keeps the compiler from hoisting all of them,
-// which would need more registers than a wave has.
-template <int NTL>
-__device__ __forceinline__ void sb_pass(double *L, const double (&x)[8][4], bool from_l,
-                                        double alpha, double beta, double sa, double sb, int J,
-                                        int g, int c) {
-  constexpr int P = 129;
-  typedef Mma<double>::v4 v4;
+// diagonal.  Step (K, r) of the product takes k = 16 K + R(g, r) from lane
+// group g (R the result-row map of the matrix cores: g + 4 r in FP64,
+// 4 g + r in FP32), which is where register r of tile K holds row k.  The
+// tile count is a template parameter, so each step's loads and matrix-core
+// steps form one straight block (a run-time bound puts every load and step
+// under a branch of its own), and the accumulators live only inside the
+// pass.  The loads of step s + 1 are issued before the steps of s; the
+// scheduling barrier keeps the compiler from hoisting all of them, which
+// would need more registers than a wave has.
+template <typename T, int N, int NTL>
+__device__ __forceinline__ void sb_pass(T *L, const T (&x)[N / 16][4], bool from_l, T alpha,
+                                        T beta, T sa, T sb, int J, int g, int c) {
+  constexpr int P = N + 1, STEPS = N / 4;
+  typedef typename Mma<T>::v4 v4;
   const int jc = 16 * J + c;
+  const auto krow = [&](int K, int r) { return 16 * K + sign16_row<T>(g, r); };
   const auto bval = [&](int K, int r) {
-    const int k = 16 * K + 4 * r + g;
-    return from_l ? (k == jc ? alpha : 0.0) + beta * L[k * P + jc] : x[K][r];
+    const int k = krow(K, r);
+    return from_l ? (k == jc ? alpha : T(0)) + beta * L[k * P + jc] : x[K][r];
   };
   v4 acc[NTL];
 #pragma unroll
   for (int t = 0; t < NTL; ++t) acc[t] = v4{0, 0, 0, 0};
-  double av[NTL], b = bval(0, 0);
+  T av[NTL], b = bval(0, 0);
+  {
+    const int k = krow(0, 0);
 #pragma unroll
-  for (int t = 0; t < NTL; ++t) av[t] = L[g * P + jc + 16 * t];
+    for (int t = 0; t < NTL; ++t) av[t] = L[k * P + jc + 16 * t];
+  }
 #pragma unroll
-  for (int st = 0; st < 32; ++st) {
-    double an[NTL], bn = 0.0;
-    if (st + 1 < 32) {
-      const int K = (st + 1) >> 2, r = (st + 1) & 3, k = 16 * K + 4 * r + g;
+  for (int st = 0; st < STEPS; ++st) {
+    T an[NTL], bn = T(0);
+    if (st + 1 < STEPS) {
+      const int K = (st + 1) >> 2, r = (st + 1) & 3, k = krow(K, r);
       bn = bval(K, r);
 #pragma unroll
       for (int t = 0; t < NTL; ++t) an[t] = L[k * P + jc + 16 * t];
     }
 #pragma unroll
-    for (int t = 0; t < NTL; ++t) acc[t] = Mma<double>::step(av[t], b, acc[t]);
+    for (int t = 0; t < NTL; ++t) acc[t] = Mma<T>::step(av[t], b, acc[t]);
     __builtin_amdgcn_sched_barrier(0);
-    if (st + 1 < 32) {
+    if (st + 1 < STEPS) {
 #pragma unroll
       for (int t = 0; t < NTL; ++t) av[t] = an[t];
       b = bn;
@@ -2227,9 +2233,9 @@ __device__ __forceinline__ void sb_pass(double *L, const double (&x)[8][4], bool
   for (int t = 0; t < NTL; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * (J + t) + g + 4 * r;
+      const int i = 16 * (J + t) + sign16_row<T>(g, r);
       if (i >= jc) {
-        const double v = (i == jc ? sa : 0.0) + sb * acc[t][r];
+        const T v = (i == jc ? sa : T(0)) + sb * acc[t][r];
         L[i * P + jc] = v;
         L[jc * P + i] = v;
       }
@@ -2237,36 +2243,37 @@ __device__ __forceinline__ void sb_pass(double *L, const double (&x)[8][4], bool
   __syncthreads();
 }
 
-// FP64 blocks of up to 128 by the sign iteration with one N x N matrix in
-// LDS (the LDS kernels above hold two, 264 KB at this size).  Eight waves;
-// wave w owns column block J (16 columns: J = w for w < 4, 11 - w after, so
-// that the two waves that share a SIMD hold 9 of the 36 tiles on or below
-// the diagonal between them) and the lower tiles (I, J), I >= J, in it.  A
-// product C = L M takes its left operand from the matrix L in LDS and its
-// right operand M from registers: the wave's column block of M in the matrix
-// cores' result layout (register r of lane l in row block K holds
-// M(16K + g + 4r, 16J + c), g = l / 16, c = l % 16), which is exactly the
-// right operand of step (K, r) of a product.  (Z = Y (-3.2 I + 1.2 Y) reads
-// both operands from LDS.)  The lower tiles of a result go to LDS on both
-// sides of the diagonal, so every iterate is exactly symmetric, and a wave
-// reloads its column block of X from there after each step.  All factors
-// are polynomials in W and commute, so the fast step X (3 I + Z) is formed as
-// (3 I + Z) X with X the register operand, and the result as S W, which also
-// goes to LDS for the epilogue.
+// Blocks of N = 48..128 by the sign iteration with one N x N matrix in LDS
+// (the LDS kernels above hold two: 264 KB for FP64 blocks of 128).  One wave
+// per column block of 16 (NT = 4 N); wave w owns column block J (J = w; for
+// N = 128, 11 - w for w >= 4, so that the two waves that share a SIMD hold 9
+// of the 36 tiles on or below the diagonal between them) and the lower tiles
+// (I, J), I >= J, in it.  A product C = L M takes its left operand from the
+// matrix L in LDS and its right operand M from registers: the wave's column
+// block of M in the matrix cores' result layout (register r of lane l in row
+// block K holds M(16K + R(g, r), 16J + c), g = l / 16, c = l % 16), which is
+// exactly the right operand of step (K, r) of a product.  (Z = Y (-3.2 I +
+// 1.2 Y) reads both operands from LDS.)  The lower tiles of a result go to
+// LDS on both sides of the diagonal, so every iterate is exactly symmetric,
+// and a wave reloads its column block of X from there after each step.  All
+// factors are polynomials in W and commute, so the fast step X (3 I + Z) is
+// formed as (3 I + Z) X with X the register operand, and the result as S W,
+// which also goes to LDS for the epilogue.
 // MODE: 0 standalone (row-major s x s blocks in `in` / `out`), 1 Algorithm
 // 1's clique step (X_k, Lambda_k and the five residual partials, as
 // k_admm_sign), 2 Algorithm 2's z-update (z_k and ||z_k - z_k_prev||^2).
-template <int MODE>
-__global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__restrict__ list,
-                                                 const int32_t *__restrict__ sizes,
-                                                 const int64_t *__restrict__ offsets,
-                                                 const double *__restrict__ in,
-                                                 double *__restrict__ out, int k1, int k2) {
-  constexpr int N = 128, P = N + 1, TN = N / 16, NT = 512;
-  __shared__ double L[N * P];
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *__restrict__ list,
+                                                    const int32_t *__restrict__ sizes,
+                                                    const int64_t *__restrict__ offsets,
+                                                    const T *__restrict__ in, T *__restrict__ out,
+                                                    int k1, int k2) {
+  constexpr int P = N + 1, TN = N / 16, NT = 4 * N;
+  static_assert(N % 16 == 0 && N >= 48 && N <= 128, "column blocks of 16");
+  __shared__ T L[N * P];
   __shared__ double red[5 * (NT / 64)];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
-  const int J = w < 4 ? w : 11 - w, nt = TN - J, jc = 16 * J + c;
+  const int J = (TN == 8 && w >= 4) ? 11 - w : w, nt = TN - J, jc = 16 * J + c;
 
   int s, cl = 0;
   int64_t off;
@@ -2291,14 +2298,15 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
     const int ii = i > j ? i : j, jj = i > j ? j : i;
     return off + (int64_t)ii * (ii + 1) / 2 + jj;
   };
-  // W(i, j) inside the clique, the same arithmetic at every call
+  // W(i, j) inside the clique in the block's precision, the same arithmetic
+  // at every call
   const auto w_entry = [&](int i, int j, double lam, double h) {
-    return MODE == 0 ? 0.5 * (in[off + (int64_t)i * s + j] + in[off + (int64_t)j * s + i])
-                     : h - lam / rho;
+    return MODE == 0 ? T(0.5) * (in[off + (int64_t)i * s + j] + in[off + (int64_t)j * s + i])
+                     : (T)(h - lam / rho);
   };
   // the wave's column block of W (zero outside the clique) into x; returns
   // its sum of squares
-  double x[TN][4];
+  T x[TN][4];
   const auto gather_w = [&]() {
     // the lane index passes through an empty asm statement, so that the
     // addresses are formed at each call rather than hoisted out of the
@@ -2306,17 +2314,17 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
     int gl = g;
     asm volatile("" : "+v"(gl));
     int32_t loc[TN][4];
-    double lam[TN][4];
+    double lam[TN][4], hv[TN][4];
 #pragma unroll
     for (int K = 0; K < TN; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * K + gl + 4 * r;
+        const int i = 16 * K + sign16_row<T>(gl, r);
         const int64_t e = (i < s && jc < s) ? packed(i, jc) : off;
         if (MODE != 0) {
           lam[K][r] = a.Lam[e];
           if (MODE == 1) loc[K][r] = a.blk_loc[e];
-          else x[K][r] = a.Vd[e];   // the slack block v_k
+          else hv[K][r] = a.Vd[e];   // the slack block v_k
         }
       }
     double f2 = 0.0;
@@ -2324,14 +2332,14 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
     for (int K = 0; K < TN; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * K + gl + 4 * r;
-        double v = 0.0;
+        const int i = 16 * K + sign16_row<T>(gl, r);
+        T v = T(0);
         if (i < s && jc < s) {
           if (MODE == 0) v = w_entry(i, jc, 0.0, 0.0);
-          else v = w_entry(i, jc, lam[K][r], MODE == 1 ? a.u[loc[K][r]] : x[K][r]);
+          else v = w_entry(i, jc, lam[K][r], MODE == 1 ? a.u[loc[K][r]] : hv[K][r]);
         }
         x[K][r] = v;
-        f2 += v * v;
+        f2 += (double)v * (double)v;
       }
     return f2;
   };
@@ -2339,40 +2347,39 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
   if (inst_done) return;   // a finished instance writes nothing (uniform)
   if (MODE == 0 && !(f2 > 0.0 && f2 < INFINITY)) {
     // W = 0: P+(W) = 0; a NaN or infinite entry: NaN throughout
-    const double fill = f2 == 0.0 ? 0.0 : NAN;
+    const T fill = f2 == 0.0 ? T(0) : T(NAN);
 #pragma unroll
     for (int K = 0; K < TN; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * K + g + 4 * r;
+        const int i = 16 * K + sign16_row<T>(g, r);
         if (i < s && jc < s) out[off + (int64_t)i * s + jc] = fill;
       }
     return;
   }
   // X0 = W / ||W||_F into L (the column blocks partition the matrix) and x
-  const double scale = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
+  const T scale = f2 > 0.0 ? (T)(1.0 / sqrt(f2)) : T(0);
 #pragma unroll
   for (int K = 0; K < TN; ++K)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       x[K][r] *= scale;
-      L[(16 * K + g + 4 * r) * P + jc] = x[K][r];
+      L[(16 * K + sign16_row<T>(g, r)) * P + jc] = x[K][r];
     }
   __syncthreads();
 
   const int ntu = __builtin_amdgcn_readfirstlane(nt);   // uniform per wave
   // one pass: L <- sa I + sb (L M), M from x or alpha I + beta L (from_l)
-  const auto pass = [&](bool from_l, double alpha, double beta, double sa, double sb, int gq,
-                        int cq) {
+  const auto pass = [&](bool from_l, T alpha, T beta, T sa, T sb, int gq, int cq) {
     switch (ntu) {
-      case 8: sb_pass<8>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      case 7: sb_pass<7>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      case 6: sb_pass<6>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      case 5: sb_pass<5>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      case 4: sb_pass<4>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      case 3: sb_pass<3>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      case 2: sb_pass<2>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
-      default: sb_pass<1>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 8: if constexpr (TN >= 8) sb_pass<T, N, 8>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 7: if constexpr (TN >= 7) sb_pass<T, N, 7>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 6: if constexpr (TN >= 6) sb_pass<T, N, 6>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 5: if constexpr (TN >= 5) sb_pass<T, N, 5>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 4: if constexpr (TN >= 4) sb_pass<T, N, 4>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 3: sb_pass<T, N, 3>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      case 2: sb_pass<T, N, 2>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
+      default: sb_pass<T, N, 1>(L, x, from_l, alpha, beta, sa, sb, J, gq, cq); break;
     }
   };
   // The passes of the k1 fast steps (L = X X; L = 3 I + L (-3.2 I + 1.2 L);
@@ -2389,18 +2396,19 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
     const bool fast = q < 3 * k1;
     const int ph = fast ? q % 3 : ((q - 3 * k1) % 2 == 0 ? 0 : 2);   // Y, Z, X
     if (q == nprod) gather_w();
-    double sa = 0.0, sb = 1.0;
-    if (q < nprod && ph == 1) sa = 3.0;
+    T sa = T(0), sb = T(1);
+    if (q < nprod && ph == 1) sa = T(3);
     if (q < nprod && !fast && ph == 0) {
-      sa = 1.5;
-      sb = -0.5;
+      sa = T(1.5);
+      sb = T(-0.5);
     }
-    pass(q < nprod && ph == 1, -3.2, 1.2, sa, sb, gq, cq);
+    pass(q < nprod && ph == 1, T(-3.2), T(1.2), sa, sb, gq, cq);
     if (q < nprod && ph == 2) {
 #pragma unroll
       for (int K = 0; K < TN; ++K)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) x[K][r] = L[(16 * K + gq + 4 * r) * P + 16 * J + cq];
+        for (int r = 0; r < 4; ++r)
+          x[K][r] = L[(16 * K + sign16_row<T>(gq, r)) * P + 16 * J + cq];
     }
   }
 
@@ -2410,11 +2418,11 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
   for (int K = 0; K < TN; ++K)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * K + g + 4 * r;
+      const int i = 16 * K + sign16_row<T>(g, r);
       if (i < jc || i >= s) continue;
-      const double cv = L[i * P + jc];
+      const T cv = L[i * P + jc];
       if (MODE == 0) {
-        const double xn = 0.5 * (w_entry(i, jc, 0.0, 0.0) + cv);
+        const T xn = T(0.5) * (w_entry(i, jc, 0.0, 0.0) + cv);
         out[off + (int64_t)i * s + jc] = xn;
         out[off + (int64_t)jc * s + i] = xn;
         continue;
@@ -2422,7 +2430,7 @@ __global__ __launch_bounds__(512) void k_sign128(ProjArgs a, const int32_t *__re
       const int64_t e = packed(i, jc);
       const double lam = a.Lam[e], xo = a.X[e];
       const double h = MODE == 1 ? a.u[a.blk_loc[e]] : a.Vd[e];
-      const double xn = 0.5 * (w_entry(i, jc, lam, h) + cv);
+      const double xn = (double)(T(0.5) * (w_entry(i, jc, lam, h) + cv));
       const double wt = (i == jc) ? 1.0 : 2.0;
       a.X[e] = xn;
       const double dx = xn - xo;
@@ -2484,25 +2492,30 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
                          (const double *)in, (double *)out, k1, k2);
     return hipGetLastError();
   }
+  // blocks of 48 and more: one block in LDS, the other operand in registers
+  // (1.1-1.5x the rate of the two-block LDS kernel on 4096 blocks)
+#define SDP_SIGN_BIG(T, n)                                                                     \
+  if (N == n && NT == 4 * n) {                                                                 \
+    hipLaunchKernelGGL((k_sign_big<T, n, 0>), dim3(count), dim3(4 * n), 0, st, ProjArgs{},     \
+                       nullptr, sizes, offsets, (const T *)in, (T *)out, k1, k2);              \
+    return hipGetLastError();                                                                  \
+  }
   if (dtype == 1) {
     SDP_SIGN(float, 32, 256)
-    SDP_SIGN(float, 48, 192)
-    SDP_SIGN(float, 64, 256)
-    SDP_SIGN(float, 80, 320)
-    SDP_SIGN(float, 96, 384)
-    SDP_SIGN(float, 112, 448)
-    SDP_SIGN(float, 128, 512)
+    SDP_SIGN_BIG(float, 48)
+    SDP_SIGN_BIG(float, 64)
+    SDP_SIGN_BIG(float, 80)
+    SDP_SIGN_BIG(float, 96)
+    SDP_SIGN_BIG(float, 112)
+    SDP_SIGN_BIG(float, 128)
   } else {
-    SDP_SIGN(double, 48, 192)
-    SDP_SIGN(double, 64, 256)
-    SDP_SIGN(double, 80, 320)
-    SDP_SIGN(double, 96, 384)
-    if (N == 128 && NT == 512) {
-      hipLaunchKernelGGL(k_sign128<0>, dim3(count), dim3(512), 0, st, ProjArgs{}, nullptr, sizes,
-                         offsets, (const double *)in, (double *)out, k1, k2);
-      return hipGetLastError();
-    }
+    SDP_SIGN_BIG(double, 48)
+    SDP_SIGN_BIG(double, 64)
+    SDP_SIGN_BIG(double, 80)
+    SDP_SIGN_BIG(double, 96)
+    SDP_SIGN_BIG(double, 128)
   }
+#undef SDP_SIGN_BIG
 #undef SDP_SIGN
   return hipErrorInvalidValue;
 }
@@ -2512,9 +2525,10 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
   if (projection_variant_kind(precision, variant) == 2) {
-    // sign-function lists: the register kernels of Algorithms 1 and 2; a
-    // caller that needs eigenvectors (the unrolled forward records V, theta)
-    // or Algorithm 3 gets the Jacobi default of the same block size
+    // sign-function lists (Algorithms 1 and 2): the register kernels for
+    // blocks of 16 and 32, below the one-block LDS kernel for FP64 blocks of
+    // 48-128; a caller that needs eigenvectors (the unrolled forward records
+    // V, theta) or Algorithm 3 gets the Jacobi default of the same block size
     if (!a.eig && !a.hsde && NT == 64 && (N == 16 || N == 32)) {
       if (count <= 0) return hipSuccess;
       int k1, k2;
@@ -2541,21 +2555,32 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
 #undef SDP_ADMM_SIGN
       return hipGetLastError();
     }
-    if (precision == 0 && N == 128 && NT == 512) {
-      // FP64 blocks of 97-128: no variant with eigenvectors exists (the
-      // plan refuses Algorithm 3 and the unrolled iterations for them)
-      if (a.eig || a.hsde) return hipErrorInvalidValue;
+    // FP64 cliques of 33-128: one block in LDS, the other operand in
+    // registers (cliques of 97-128 have no variant with eigenvectors: the
+    // plan refuses Algorithm 3 and the unrolled iterations for them)
+    if (precision == 0 && N >= 48 && NT == 4 * N && !a.eig && !a.hsde) {
       if (count <= 0) return hipSuccess;
       int k1, k2;
       sign_schedule(a.tol, N, &k1, &k2);
-      if (a.dual)
-        hipLaunchKernelGGL(k_sign128<2>, dim3(count), dim3(512), 0, st, a, list, nullptr, nullptr,
-                           nullptr, nullptr, k1, k2);
-      else
-        hipLaunchKernelGGL(k_sign128<1>, dim3(count), dim3(512), 0, st, a, list, nullptr, nullptr,
-                           nullptr, nullptr, k1, k2);
-      return hipGetLastError();
+#define SDP_ADMM_BIG(n)                                                                        \
+  if (N == n) {                                                                                \
+    if (a.dual)                                                                                \
+      hipLaunchKernelGGL((k_sign_big<double, n, 2>), dim3(count), dim3(4 * n), 0, st, a, list,  \
+                         nullptr, nullptr, nullptr, nullptr, k1, k2);                          \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_sign_big<double, n, 1>), dim3(count), dim3(4 * n), 0, st, a, list,  \
+                         nullptr, nullptr, nullptr, nullptr, k1, k2);                          \
+    return hipGetLastError();                                                                  \
+  }
+      SDP_ADMM_BIG(48)
+      SDP_ADMM_BIG(64)
+      SDP_ADMM_BIG(80)
+      SDP_ADMM_BIG(96)
+      SDP_ADMM_BIG(128)
+#undef SDP_ADMM_BIG
+      return hipErrorInvalidValue;
     }
+    if (precision == 0 && N == 128) return hipErrorInvalidValue;   // needs eigenvectors
     variant = projection_default_variant(precision, N);
     projection_variant_info(precision, variant, &N, &NT);
   }

@@ -107,17 +107,29 @@ int default_variant(int precision, int s, int method) {
   return best;
 }
 
-// The register-resident sign-function variant (one wave, N = 16 or 32) for
-// cliques of s vertices, -1 if s > 32.
+// The sign-function variant the solver's plan takes for cliques of s
+// vertices: the register-resident kernels (one wave, N = 16 or 32) for
+// s <= 32; in FP64 also the one-block LDS kernel (NT = 4N) of the smallest
+// fitting N for 33-128 (measured against the warm-started Jacobi kernels:
+// nonchordal workload FP64 1046 -> 1439 iter/s, batched 72.3 -> 75.8; in
+// FP32 the Jacobi kernels and the decoupling stay faster, batched 93.4 ->
+// 92.2 with the sign function for blocks of 48).  -1 otherwise.
 int sign_variant(int precision, int s) {
-  if (s > 32) return -1;
-  const int want = s <= 16 ? 16 : 32;
+  const bool big = precision == 0 && s > 32;
+  if (s > 32 && !big) return -1;
+  const int n = s + (s & 1);
+  int best = -1, bestN = 1 << 30;
   for (int v = 0; v < projection_variant_count(precision); ++v) {
     int N, NT;
     projection_variant_info(precision, v, &N, &NT);
-    if (projection_variant_kind(precision, v) == 2 && N == want && NT == 64) return v;
+    if (projection_variant_kind(precision, v) != 2 || N < n) continue;
+    const bool ok = big ? (N >= 48 && NT == 4 * N) : (NT == 64 && (N == 16 || N == 32));
+    if (ok && N < bestN) {
+      best = v;
+      bestN = N;
+    }
   }
-  return -1;
+  return best;
 }
 
 // The sign-function variant that Algorithms 1 and 2 take for cliques of s
@@ -791,8 +803,8 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       std::map<int, int64_t> count_of_size;
       for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
       std::map<int, int> var_of_size;
-      // Algorithm 1's and 2's cliques of up to 32 vertices: the sign-function
-      // variants (one wave's registers, no eigenvectors) where selected
+      // Algorithm 1's and 2's cliques of up to 32 vertices (FP64: all): the
+      // sign-function variants (no eigenvectors) where selected
       const bool sign_lists = opt.algorithm != SDP_ALG_HSDE &&
                               (opt.projection_method == 3 ||
                                (opt.projection_method == 0 && sign_by_default(h->precision)));

@@ -1,5 +1,5 @@
-"""FP64 cliques of 97-128 vertices: the sign-function kernel with one block in
-LDS (k_sign128), against the oracle (FP64 eigendecompositions).
+"""FP64 cliques of 33-128 vertices: the sign-function kernel with one block in
+LDS (k_sign_big), against the oracle (FP64 eigendecompositions).
 
 * fixed-N parity of Algorithm 1 (u, y, X_k, Lambda_k, residual history to
   1e-8 relative to the largest entry) on cliques of 128, alone and beside
@@ -9,7 +9,10 @@ LDS (k_sign128), against the oracle (FP64 eigendecompositions).
   1e-6 relative, and the diagnostics (eps_alpha through the eigenvalue-only
   Jacobi kernel of FP64 blocks of 128) against the oracle's;
 * the standalone projection of FP64 blocks of 97-128 (the default variant)
-  against the oracle to 1e-11 ||W||_F.
+  against the oracle to 1e-11 ||W||_F;
+* the default FP64 plan puts cliques of 33-96 on the same kernel (block
+  sizes 48, 64, 80, 96), with fixed-N parity for Algorithms 1 and 2, and
+  projection_method = "scalar" keeps them on the Jacobi kernels.
 """
 import numpy as np
 import pytest
@@ -151,3 +154,56 @@ def test_standalone_fp64_97_to_128(sdp, gpu, oracle_mod):
         log(f"  standalone FP64 s={n}: {err:.2e}")
         assert err <= 1e-11
         assert np.array_equal(X, X.T)
+
+
+def arrow_with_blocks(blocks, h, m, seed):
+    cliques, v = [], 0
+    n = sum(blocks) + h
+    head = np.arange(n - h, n, dtype=np.int32)
+    for d in blocks:
+        cliques.append(np.concatenate([np.arange(v, v + d, dtype=np.int32), head]))
+        v += d
+    return sdpgen.random_instance(n, cliques, m, seed=seed,
+                                  name=f"arrow_blocks{'_'.join(map(str, blocks))}_h{h}_m{m}")
+
+
+def test_fp64_plan_takes_sign_kernel_for_cliques_above_32(sdp, gpu, oracle_mod):
+    # cliques of 14, 44, 60, 74 and 92 vertices: blocks of 16, 48, 64, 80, 96
+    inst = arrow_with_blocks([10, 40, 56, 70, 88], 4, 60, seed=29)
+    dt = sdp.DTYPE_FP64
+    for method, want_sign in (("auto", True), ("sign", True), ("scalar", False)):
+        with sdp.Solver([inst], tol=0.0, precision="fp64", projection_method=method) as S:
+            plan = [(n, t, sdp.projection_variant_kind(dt, v))
+                    for (n, t, c), v in zip(S.projection_plan(), S.projection_plan_variants())]
+        log(f"  {method}: plan {plan}")
+        assert sorted(n for n, _, _ in plan) == [16, 48, 64, 80, 96]
+        for n, t, k in plan:
+            assert (k == 2) == want_sign, (method, n, t, k)
+            if k == 2 and n >= 48:
+                assert t == 4 * n
+    P = oracle_mod.Problem(inst)
+    r = P.run(15, tol=0.0)
+    with sdp.Solver([inst], tol=0.0, max_iter=100000, precision="fp64") as S:
+        S.step(15)
+        sol = S.solution(0)
+        hc, hl, _ = S.history(0)
+    X, L = P.blocks()
+    errs = dict(u=rel_err(sol["u"], P.u()), X=rel_err(sol["X_packed"], sdp.pack_blocks(X)),
+                L=rel_err(sol["L_packed"], sdp.pack_blocks(L)),
+                eps_c=rel_err(hc, r.hist_eps_c), eps_l=rel_err(hl, r.hist_eps_l))
+    log(f"  primal fixed-N errors {errs}")
+    for k, v in errs.items():
+        assert v <= 1e-8, (k, v)
+    P = oracle_mod.Problem(inst)
+    r = P.run_dual(15, tol=0.0)
+    with sdp.Solver([inst], tol=0.0, max_iter=100000, precision="fp64", algorithm="dual") as S:
+        S.step(15)
+        sol = S.solution(0)
+        hc, hl, _ = S.history(0)
+    Z, L = P.blocks()
+    errs = dict(u=rel_err(sol["u"], -P.rho * P.u()), Z=rel_err(sol["X_packed"], sdp.pack_blocks(Z)),
+                L=rel_err(sol["L_packed"], sdp.pack_blocks(L)),
+                eps_c=rel_err(hc, r.hist_eps_c), eps_l=rel_err(hl, r.hist_eps_l))
+    log(f"  dual fixed-N errors {errs}")
+    for k, v in errs.items():
+        assert v <= 1e-8, (k, v)
