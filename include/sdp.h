@@ -20,8 +20,8 @@
  *    pairs (a chordal graph or a chordal extension).
  *  - Cliques are 0-based vertex lists in strictly increasing order, at most
  *    128 vertices each.  In SDP_FP64, cliques of more than 96 vertices are
- *    projected by the matrix sign function (no eigenvectors), so Algorithm 3
- *    and the unrolled iterations refuse them (SDP_ERR_UNSUPPORTED).
+ *    projected by the matrix sign function (no eigenvectors), so the unrolled
+ *    iterations refuse them (SDP_ERR_UNSUPPORTED).
  *  - A clique block X_k (s x s) is stored "packed": lower triangle row by
  *    row, entry (i, j), i >= j, at i*(i+1)/2 + j.
  *  - All functions return an int status: 0 = SDP_OK, >0 informational,
@@ -116,7 +116,7 @@ typedef struct {
                                    u = P_K(u_hat - v), v += u - u_hat; stops on
                                    max(eps_p, eps_d, eps_g, eps_c) <= tol or on an
                                    infeasibility certificate; no penalty, so adaptive_rho
-                                   must be 0; in SDP_FP64 cliques of up to 96 vertices) */
+                                   must be 0) */
   int32_t cg_max_iter;          /* 0: the affine step solves with the cached Cholesky factor
                                    of A D^-1 A^T.  > 0 (Algorithm 1 only): no factor is
                                    formed; each iteration solves (A W D^-1 A^T) y = rhs by
@@ -128,14 +128,12 @@ typedef struct {
   double cg_tol;                /* the solve also stops once ||r||_2 <= cg_tol (1 + ||b||_2);
                                    0: always cg_max_iter steps */
   int32_t projection_method;    /* eigensolver of the clique projections: 0 the autotuner (or,
-                                   with autotune = 0, the default variant) chooses, and with
-                                   Algorithms 1 and 2 the cliques listed under 3 take the
-                                   sign function; 1 scalar parallel-order Jacobi only (FP64
+                                   with autotune = 0, the default variant) chooses, and the
+                                   cliques listed under 3 take the sign function; 1 scalar parallel-order Jacobi only (FP64
                                    cliques of 97-128 still take the sign function, the only
                                    kernel for them); 2 the two-level (block) Jacobi wherever a
                                    variant for the clique size exists (blocks of 64 and more),
-                                   scalar elsewhere; 3 (Algorithms 1 and 2) the matrix sign
-                                   function, X_k = (W + W sign(W)) / 2 (no eigenvectors, no
+                                   scalar elsewhere; 3 the matrix sign function, X_k = (W + W sign(W)) / 2 (no eigenvectors, no
                                    warm start), for cliques of up to 32 vertices (in one
                                    wave's registers) and in SDP_FP64 for all cliques (larger
                                    ones with one block in LDS); the rest as with 0 */

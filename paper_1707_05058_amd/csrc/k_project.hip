@@ -1964,13 +1964,17 @@ __global__ __launch_bounds__(64) void k_project_sign32(const int32_t *__restrict
 // and the five residual partials of k_project's ADMM epilogue.  With DUAL,
 // Algorithm 2's z-update instead: z_k = P+(v_k - lambda_k / rho) (zkUpdate)
 // and ||z_k - z_k_prev||^2, the rest following the affine step as with the
-// Jacobi kernels.  The register layout is the sign kernels': tile t = TB I + J
+// Jacobi kernels.  With HSDE, Algorithm 3's cone step on the PSD blocks:
+// u_s = P+(u_hat_s - v_z), v_z += u_s - u_hat_s, u_t = u_hat_t and the six
+// consensus partials of the Jacobi kernel's embedding mode.  The register
+// layout is the sign kernels': tile t = TB I + J
 // holds rows 16 I + R(g, r) at column 16 J + l mod 16.  W_k(i, k) and
 // W_k(k, i) come from the same packed entry, so W_k is exactly symmetric.
 // ---------------------------------------------------------------------------
-template <typename T, int TB, bool DUAL>
+template <typename T, int TB, bool DUAL, bool HSDE = false>
 __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__restrict__ list,
                                                   int k1, int k2) {
+  static_assert(!(DUAL && HSDE), "one algorithm per kernel");
   constexpr int NTL = TB * TB, NB = 16 * TB, CP = NB + 1;
   typedef typename Mma<T>::v4 v4;
   __shared__ T C[NB * CP];
@@ -1992,10 +1996,13 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   // the epilogue in registers; blocks of 32 (16 entries per lane) load them
   // again there, from the cache, so that the sign iteration keeps two waves
   // per SIMD.
-  constexpr bool KEEP = TB == 1;
+  // (Algorithm 3 reloads its inputs in the epilogue, which needs more of
+  // them: its gather keeps nothing)
+  constexpr bool KEEP = TB == 1 && !HSDE;
   constexpr int KT = KEEP ? NTL : 1;
   int32_t loc[DUAL ? 1 : NTL][4];
-  double lam[NTL][4], xo[KT][4], hu[DUAL ? 1 : KT][4], vd[DUAL ? NTL : 1][4];
+  double lam[NTL][4], xo[KT][4], hu[DUAL ? 1 : KT][4], vd[(DUAL || HSDE) ? NTL : 1][4];
+  const double hf = HSDE ? a.hs[inst].f : 0.0;
 #pragma unroll
   for (int t = 0; t < NTL; ++t)
 #pragma unroll
@@ -2007,6 +2014,7 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
       lam[t][r] = a.Lam[e];
       if constexpr (KEEP) xo[t][r] = a.X[e];
       if constexpr (DUAL) vd[t][r] = a.Vd[e];   // the slack block v_k
+      if constexpr (HSDE) vd[t][r] = a.h_ns[e] - a.h_nt[e];   // Algorithm 3: n_s - n_t
     }
   T w[NTL][4];
   double f2 = 0.0;
@@ -2015,14 +2023,22 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = rowof(t, r), k = colof(t);
-      double h;
+      double wd;
       if constexpr (DUAL) {
-        h = vd[t][r];
+        wd = vd[t][r] - lam[t][r] / rho;
+      } else if constexpr (HSDE) {
+        // u_hat_s - v_z, u_hat_s = 0.5 (n_s - n_t + s_x) - f m_s (the Jacobi
+        // kernel's arithmetic, term for term)
+        const int ii = i > k ? i : k, kk = i > k ? k : i;
+        const int64_t e = (i < s && k < s) ? off + (int64_t)ii * (ii + 1) / 2 + kk : off;
+        const double ss = 0.5 * (vd[t][r] + a.h_sx[loc[t][r]]);
+        wd = ss - hf * a.h_mzs[e] - lam[t][r];
       } else {
-        h = a.u[loc[t][r]];
+        const double h = a.u[loc[t][r]];
         if constexpr (KEEP) hu[t][r] = h;
+        wd = h - lam[t][r] / rho;
       }
-      const T v = (i < s && k < s) ? (T)(h - lam[t][r] / rho) : T(0);
+      const T v = (i < s && k < s) ? (T)wd : T(0);
       w[t][r] = v;
       f2 += (double)v * (double)v;
     }
@@ -2106,7 +2122,38 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   // epilogue on the lower entries: X_k, Lambda_k and the residual partials
   // (||X - Hx||^2, ||X||^2, ||Hx||^2, ||X - X_prev||^2, ||Lambda||^2, full
   // Frobenius norms: off-diagonal entries count twice)
-  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
+  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p6 = 0;
+  if constexpr (HSDE) {
+    // Algorithm 3: u_s = P+(u_hat_s - v_z), v_z += u_s - u_hat_s,
+    // u_t = u_hat_t, and the partials of the consensus residuals on (u_s,
+    // H u_x) and (v_z, u_t) (the Jacobi kernel's embedding epilogue)
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rowof(t, r), k = colof(t);
+        if (!(i < s && k <= i)) continue;
+        const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
+        const int32_t lc = loc[t][r];
+        const double hx = a.h_sx[lc], nt = a.h_nt[e];
+        const double ss = 0.5 * (a.h_ns[e] - nt + hx);
+        const double us_hat = ss - hf * a.h_mzs[e];
+        const double ut = ss - hx + nt - hf * a.h_mzt[e];
+        const double usn = (double)(T(0.5) * (w[t][r] + cs[t][r]));
+        const double vzn = a.Lam[e] - us_hat + usn;
+        a.X[e] = usn;
+        a.Lam[e] = vzn;
+        a.h_ut[e] = ut;
+        const double hux = a.h_ux[lc];
+        const double wt = (i == k) ? 1.0 : 2.0;
+        p0 += wt * (usn - hux) * (usn - hux);
+        p1 += wt * usn * usn;
+        p2 += wt * hux * hux;
+        p3 += wt * (vzn - ut) * (vzn - ut);
+        p4 += wt * vzn * vzn;
+        p6 += wt * ut * ut;
+      }
+  }
   double lo[NTL][4], xp[NTL][4], hp[NTL][4];
 #pragma unroll
   for (int t = 0; t < NTL; ++t)
@@ -2114,8 +2161,10 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
     for (int r = 0; r < 4; ++r) {
       const int i = rowof(t, r), k = colof(t);
       const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
-      const bool lower = i < s && k <= i;
-      if constexpr (DUAL) {
+      const bool lower = !HSDE && i < s && k <= i;
+      if constexpr (HSDE) {
+        lo[t][r] = xp[t][r] = hp[t][r] = 0.0;
+      } else if constexpr (DUAL) {
         lo[t][r] = hp[t][r] = 0.0;
         if constexpr (KEEP) xp[t][r] = xo[t][r];
         else xp[t][r] = lower ? a.X[e] : 0.0;
@@ -2142,7 +2191,7 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
         const double wt = (i == k) ? 1.0 : 2.0;
         const double dz = zn - xp[t][r];
         p3 += wt * dz * dz;
-      } else if (!DUAL && i < s && k <= i) {
+      } else if (!DUAL && !HSDE && i < s && k <= i) {
         const int64_t e = off + (int64_t)i * (i + 1) / 2 + k;
         const double xn = (double)(T(0.5) * (w[t][r] + cs[t][r]));
         const double hx = hp[t][r];
@@ -2163,6 +2212,7 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
   p2 = wave_sum(p2);
   p3 = wave_sum(p3);
   p4 = wave_sum(p4);
+  if (HSDE) p6 = wave_sum(p6);
   if (l == 0) {
     double *pp = a.part + NPART * (int64_t)cl;
     if (!DUAL) {   // (Algorithm 2: the multiplier update writes these)
@@ -2173,7 +2223,7 @@ __global__ __launch_bounds__(64) void k_admm_sign(ProjArgs a, const int32_t *__r
     }
     pp[3] = p3;
     pp[5] = 0.0;   // no Jacobi sweeps
-    pp[6] = 0.0;
+    pp[6] = p6;    // Algorithm 3: ||u_t||^2; else 0 (no sign fallback)
   }
 }
 
@@ -2261,7 +2311,8 @@ __device__ __forceinline__ void sb_pass(T *L, const T (&x)[N / 16][4], bool from
 // which also goes to LDS for the epilogue.
 // MODE: 0 standalone (row-major s x s blocks in `in` / `out`), 1 Algorithm
 // 1's clique step (X_k, Lambda_k and the five residual partials, as
-// k_admm_sign), 2 Algorithm 2's z-update (z_k and ||z_k - z_k_prev||^2).
+// k_admm_sign), 2 Algorithm 2's z-update (z_k and ||z_k - z_k_prev||^2), 3
+// Algorithm 3's cone step on the PSD blocks (as k_admm_sign's HSDE mode).
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *__restrict__ list,
                                                     const int32_t *__restrict__ sizes,
@@ -2271,14 +2322,14 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
   constexpr int P = N + 1, TN = N / 16, NT = 4 * N;
   static_assert(N % 16 == 0 && N >= 48 && N <= 128, "column blocks of 16");
   __shared__ T L[N * P];
-  __shared__ double red[5 * (NT / 64)];
+  __shared__ double red[6 * (NT / 64)];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
   const int J = (TN == 8 && w >= 4) ? 11 - w : w, nt = TN - J, jc = 16 * J + c;
 
   int s, cl = 0;
   int64_t off;
   bool inst_done = false;
-  double rho = 1.0;
+  double rho = 1.0, hf = 0.0;
   if (MODE == 0) {
     s = sizes[blockIdx.x];
     off = offsets[blockIdx.x];
@@ -2292,6 +2343,7 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
     off = a.cl_off[cl];
     inst_done = a.state[inst].done != 0;
     rho = a.state[inst].rho;
+    if (MODE == 3) hf = a.hs[inst].f;
   }
   // packed position of (i, j) in the clique's lower triangle (i, j < s)
   const auto packed = [&](int i, int j) {
@@ -2299,10 +2351,12 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
     return off + (int64_t)ii * (ii + 1) / 2 + jj;
   };
   // W(i, j) inside the clique in the block's precision, the same arithmetic
-  // at every call
-  const auto w_entry = [&](int i, int j, double lam, double h) {
-    return MODE == 0 ? T(0.5) * (in[off + (int64_t)i * s + j] + in[off + (int64_t)j * s + i])
-                     : (T)(h - lam / rho);
+  // at every call (MODE 3: h = n_s - n_t, sx = s_x at the entry's
+  // coordinate, mz = m_s; u_hat_s - v_z as the Jacobi kernel forms it)
+  const auto w_entry = [&](int i, int j, double lam, double h, double sx, double mz) {
+    if (MODE == 0) return T(0.5) * (in[off + (int64_t)i * s + j] + in[off + (int64_t)j * s + i]);
+    if (MODE == 3) return (T)(0.5 * (h + sx) - hf * mz - lam);
+    return (T)(h - lam / rho);
   };
   // the wave's column block of W (zero outside the clique) into x; returns
   // its sum of squares
@@ -2313,21 +2367,47 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
     // iteration loop and kept live across it
     int gl = g;
     asm volatile("" : "+v"(gl));
-    int32_t loc[TN][4];
-    double lam[TN][4], hv[TN][4];
+    double f2 = 0.0;
+    if constexpr (MODE == 3) {
+      // Algorithm 3's six operands per entry, one row of tiles at a time
+      // (entries outside the clique read the clique's first entry)
+#pragma unroll
+      for (int K = 0; K < TN; ++K) {
+        int32_t lc[4];
+        double ns[4], ntv[4], lm[4], mz[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * K + sign16_row<T>(gl, r);
+          const int64_t e = (i < s && jc < s) ? packed(i, jc) : off;
+          lc[r] = a.blk_loc[e];
+          ns[r] = a.h_ns[e];
+          ntv[r] = a.h_nt[e];
+          lm[r] = a.Lam[e];
+          mz[r] = a.h_mzs[e];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * K + sign16_row<T>(gl, r);
+          const T v = (i < s && jc < s) ? w_entry(i, jc, lm[r], ns[r] - ntv[r], a.h_sx[lc[r]], mz[r])
+                                        : T(0);
+          x[K][r] = v;
+          f2 += (double)v * (double)v;
+        }
+      }
+      return f2;
+    }
+    int32_t loc[MODE == 1 ? TN : 1][4];
+    double lam[MODE == 0 ? 1 : TN][4], hv[MODE == 2 ? TN : 1][4];
 #pragma unroll
     for (int K = 0; K < TN; ++K)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * K + sign16_row<T>(gl, r);
         const int64_t e = (i < s && jc < s) ? packed(i, jc) : off;
-        if (MODE != 0) {
-          lam[K][r] = a.Lam[e];
-          if (MODE == 1) loc[K][r] = a.blk_loc[e];
-          else hv[K][r] = a.Vd[e];   // the slack block v_k
-        }
+        if constexpr (MODE != 0) lam[K][r] = a.Lam[e];
+        if constexpr (MODE == 1) loc[K][r] = a.blk_loc[e];
+        if constexpr (MODE == 2) hv[K][r] = a.Vd[e];   // the slack block v_k
       }
-    double f2 = 0.0;
 #pragma unroll
     for (int K = 0; K < TN; ++K)
 #pragma unroll
@@ -2335,8 +2415,13 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
         const int i = 16 * K + sign16_row<T>(gl, r);
         T v = T(0);
         if (i < s && jc < s) {
-          if (MODE == 0) v = w_entry(i, jc, 0.0, 0.0);
-          else v = w_entry(i, jc, lam[K][r], MODE == 1 ? a.u[loc[K][r]] : hv[K][r]);
+          if constexpr (MODE == 0) {
+            v = w_entry(i, jc, 0.0, 0.0, 0.0, 0.0);
+          } else if constexpr (MODE == 1) {
+            v = w_entry(i, jc, lam[K][r], a.u[loc[K][r]], 0.0, 0.0);
+          } else {
+            v = w_entry(i, jc, lam[K][r], hv[K][r], 0.0, 0.0);
+          }
         }
         x[K][r] = v;
         f2 += (double)v * (double)v;
@@ -2413,7 +2498,7 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
   }
 
   // P+(W) = (W + C) / 2 on the lower entries of the wave's column block
-  double pv[5] = {0, 0, 0, 0, 0};
+  double pv[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int K = 0; K < TN; ++K)
 #pragma unroll
@@ -2422,15 +2507,39 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
       if (i < jc || i >= s) continue;
       const T cv = L[i * P + jc];
       if (MODE == 0) {
-        const T xn = T(0.5) * (w_entry(i, jc, 0.0, 0.0) + cv);
+        const T xn = T(0.5) * (w_entry(i, jc, 0.0, 0.0, 0.0, 0.0) + cv);
         out[off + (int64_t)i * s + jc] = xn;
         out[off + (int64_t)jc * s + i] = xn;
         continue;
       }
       const int64_t e = packed(i, jc);
+      if (MODE == 3) {
+        // Algorithm 3: u_s = P+(u_hat_s - v_z), v_z += u_s - u_hat_s,
+        // u_t = u_hat_t and the six consensus partials
+        const int32_t lc = a.blk_loc[e];
+        const double lam = a.Lam[e], hx = a.h_sx[lc], ntv = a.h_nt[e], nsv = a.h_ns[e];
+        const double mzs = a.h_mzs[e];
+        const double ss = 0.5 * (nsv - ntv + hx);
+        const double us_hat = ss - hf * mzs;
+        const double ut = ss - hx + ntv - hf * a.h_mzt[e];
+        const double usn = (double)(T(0.5) * (w_entry(i, jc, lam, nsv - ntv, hx, mzs) + cv));
+        const double vzn = lam - us_hat + usn;
+        a.X[e] = usn;
+        a.Lam[e] = vzn;
+        a.h_ut[e] = ut;
+        const double hux = a.h_ux[lc];
+        const double wt = (i == jc) ? 1.0 : 2.0;
+        pv[0] += wt * (usn - hux) * (usn - hux);
+        pv[1] += wt * usn * usn;
+        pv[2] += wt * hux * hux;
+        pv[3] += wt * (vzn - ut) * (vzn - ut);
+        pv[4] += wt * vzn * vzn;
+        pv[5] += wt * ut * ut;
+        continue;
+      }
       const double lam = a.Lam[e], xo = a.X[e];
       const double h = MODE == 1 ? a.u[a.blk_loc[e]] : a.Vd[e];
-      const double xn = (double)(T(0.5) * (w_entry(i, jc, lam, h) + cv));
+      const double xn = (double)(T(0.5) * (w_entry(i, jc, lam, h, 0.0, 0.0) + cv));
       const double wt = (i == jc) ? 1.0 : 2.0;
       a.X[e] = xn;
       const double dx = xn - xo;
@@ -2446,18 +2555,18 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
       }
     }
   if (MODE == 0) return;
-  block_sum_n<NT, 5>(pv, red);
+  block_sum_n<NT, 6>(pv, red);
   if (tid == 0) {
     double *pp = a.part + NPART * (int64_t)cl;
-    if (MODE == 1) {   // (Algorithm 2: the multiplier update writes these)
+    if (MODE != 2) {   // (Algorithm 2: the multiplier update writes these)
       pp[0] = pv[0];
       pp[1] = pv[1];
       pp[2] = pv[2];
       pp[4] = pv[4];
     }
     pp[3] = pv[3];
-    pp[5] = 0.0;   // no Jacobi sweeps
-    pp[6] = 0.0;
+    pp[5] = 0.0;     // no Jacobi sweeps
+    pp[6] = pv[5];   // Algorithm 3: ||u_t||^2; else 0 (no sign fallback)
   }
 }
 
@@ -2525,31 +2634,35 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
   if (projection_variant_kind(precision, variant) == 2) {
-    // sign-function lists (Algorithms 1 and 2): the register kernels for
+    // sign-function lists (Algorithms 1, 2 and 3): the register kernels for
     // blocks of 16 and 32, below the one-block LDS kernel for FP64 blocks of
     // 48-128; a caller that needs eigenvectors (the unrolled forward records
-    // V, theta) or Algorithm 3 gets the Jacobi default of the same block size
-    if (!a.eig && !a.hsde && NT == 64 && (N == 16 || N == 32)) {
+    // V, theta) gets the Jacobi default of the same block size
+    if (!a.eig && NT == 64 && (N == 16 || N == 32)) {
       if (count <= 0) return hipSuccess;
       int k1, k2;
       sign_schedule(a.tol, N, &k1, &k2);
-#define SDP_ADMM_SIGN(T, tb, dual)                                                              \
-  hipLaunchKernelGGL((k_admm_sign<T, tb, dual>), dim3(count), dim3(64), 0, st, a, list, k1, k2)
+#define SDP_ADMM_SIGN(T, tb)                                                                    \
+  if (a.hsde)                                                                                   \
+    hipLaunchKernelGGL((k_admm_sign<T, tb, false, true>), dim3(count), dim3(64), 0, st, a, list, \
+                       k1, k2);                                                                 \
+  else if (a.dual)                                                                              \
+    hipLaunchKernelGGL((k_admm_sign<T, tb, true>), dim3(count), dim3(64), 0, st, a, list, k1,    \
+                       k2);                                                                     \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_admm_sign<T, tb, false>), dim3(count), dim3(64), 0, st, a, list, k1,   \
+                       k2);
       if (precision == 1) {
         if (N == 16) {
-          if (a.dual) SDP_ADMM_SIGN(float, 1, true);
-          else SDP_ADMM_SIGN(float, 1, false);
+          SDP_ADMM_SIGN(float, 1)
         } else {
-          if (a.dual) SDP_ADMM_SIGN(float, 2, true);
-          else SDP_ADMM_SIGN(float, 2, false);
+          SDP_ADMM_SIGN(float, 2)
         }
       } else {
         if (N == 16) {
-          if (a.dual) SDP_ADMM_SIGN(double, 1, true);
-          else SDP_ADMM_SIGN(double, 1, false);
+          SDP_ADMM_SIGN(double, 1)
         } else {
-          if (a.dual) SDP_ADMM_SIGN(double, 2, true);
-          else SDP_ADMM_SIGN(double, 2, false);
+          SDP_ADMM_SIGN(double, 2)
         }
       }
 #undef SDP_ADMM_SIGN
@@ -2557,14 +2670,17 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
     }
     // FP64 cliques of 33-128: one block in LDS, the other operand in
     // registers (cliques of 97-128 have no variant with eigenvectors: the
-    // plan refuses Algorithm 3 and the unrolled iterations for them)
-    if (precision == 0 && N >= 48 && NT == 4 * N && !a.eig && !a.hsde) {
+    // plan refuses the unrolled iterations for them)
+    if (precision == 0 && N >= 48 && NT == 4 * N && !a.eig) {
       if (count <= 0) return hipSuccess;
       int k1, k2;
       sign_schedule(a.tol, N, &k1, &k2);
 #define SDP_ADMM_BIG(n)                                                                        \
   if (N == n) {                                                                                \
-    if (a.dual)                                                                                \
+    if (a.hsde)                                                                                \
+      hipLaunchKernelGGL((k_sign_big<double, n, 3>), dim3(count), dim3(4 * n), 0, st, a, list,  \
+                         nullptr, nullptr, nullptr, nullptr, k1, k2);                          \
+    else if (a.dual)                                                                           \
       hipLaunchKernelGGL((k_sign_big<double, n, 2>), dim3(count), dim3(4 * n), 0, st, a, list,  \
                          nullptr, nullptr, nullptr, nullptr, k1, k2);                          \
     else                                                                                       \

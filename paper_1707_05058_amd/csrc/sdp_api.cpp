@@ -696,15 +696,6 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
     }
   }
 
-  // Algorithm 3 needs eigenvectors, which no FP64 kernel keeps for blocks of
-  // more than 96 (two such blocks do not fit in LDS)
-  if (opt.algorithm == SDP_ALG_HSDE && opt.precision == SDP_FP64)
-    for (int i = 0; i < batch; ++i)
-      for (int q = 0; q < H[i].p; ++q)
-        if (inst[i].clique_ptr[q + 1] - inst[i].clique_ptr[q] > 96)
-          fail(SDP_ERR_UNSUPPORTED, "instance " + std::to_string(i) +
-                                        ": Algorithm 3 in FP64 takes cliques of up to 96 vertices");
-
   sdp_handle *h = new sdp_handle();
   try {
     h->B = batch;
@@ -803,11 +794,10 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       std::map<int, int64_t> count_of_size;
       for (int64_t k = 0; k < cl; ++k) count_of_size[cl_size[k]]++;
       std::map<int, int> var_of_size;
-      // Algorithm 1's and 2's cliques of up to 32 vertices (FP64: all): the
-      // sign-function variants (no eigenvectors) where selected
-      const bool sign_lists = opt.algorithm != SDP_ALG_HSDE &&
-                              (opt.projection_method == 3 ||
-                               (opt.projection_method == 0 && sign_by_default(h->precision)));
+      // cliques of up to 32 vertices (FP64: all): the sign-function
+      // variants (no eigenvectors) where selected
+      const bool sign_lists = opt.projection_method == 3 ||
+                              (opt.projection_method == 0 && sign_by_default(h->precision));
       // with the decoupling (FP32, warm start) the large blocks take the
       // scalar variants, which carry it
       const int pm = opt.projection_method == 3 ? 0 : opt.projection_method;
@@ -818,8 +808,7 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
       for (auto &kv : count_of_size) {
         int sv = sign_lists ? sign_variant(h->precision, kv.first) : -1;
         if (fitting_variants(h->precision, kv.first, 0).empty()) {
-          // FP64 cliques of 97-128 (Algorithms 1 and 2; Algorithm 3 was
-          // refused above): the sign-function kernel is the only one
+          // FP64 cliques of 97-128: the sign-function kernel is the only one
           sv = big_sign_variant(h->precision, kv.first);
           if (sv < 0) fail(SDP_ERR_UNSUPPORTED, "clique too large");
         }

@@ -75,14 +75,13 @@ def test_invalid_options_rejected(sdp):
 
 
 def test_projection_size_limits(sdp):
-    """Blocks of up to 128 in both precisions; Algorithm 3 needs eigenvectors,
-    which FP64 keeps for blocks of up to 96 only (host checks, before any
-    device work)."""
-    assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(129)], precision=sdp.FP64) == -7
-    assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(129)], precision=sdp.FP32_EIG) == -7
-    assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(97)], precision=sdp.FP64,
-                            algorithm="hsde") == -7
-    assert "96" in sdp.lib.sdp_last_error().decode()
+    """Blocks of up to 128 in both precisions and every algorithm (host
+    checks, before any device work)."""
+    for prec in (sdp.FP64, sdp.FP32_EIG):
+        for alg in ("primal", "dual", "hsde"):
+            assert sdp.setup_status([sdpgen.lovasz_theta_odd_cycle(129)], precision=prec,
+                                    algorithm=alg) == -7
+            assert "128" in sdp.lib.sdp_last_error().decode()
 
 
 def test_batch_error_names_instance(sdp):
