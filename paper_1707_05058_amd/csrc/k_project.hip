@@ -2570,6 +2570,257 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same sign iteration for a few large FP64 cliques, split over
+// workgroups.  k_sign_big puts one clique on one compute unit, so a handful
+// of large cliques leaves most of the chip idle for all 3 k1 + 2 k2 + 1
+// products.  Here every product is a launch of its own over all the
+// clique's lower 16 x 16 tiles, one wave per tile (36 waves for a block of
+// 128), and the iterates live in a per-clique workspace of four N x N
+// row-major matrices (three that the products rotate through, and W for the
+// last product).  A product reads its left operand A(i, k) as A(k, i): every
+// iterate is exactly symmetric (the lower tiles are computed and mirrored),
+// so each step of the matrix cores loads four rows of 16 consecutive
+// entries.  The accumulation runs over k in the order k_sign_big uses, so the
+// iterates are the same bit for bit; only ||W||_F is summed in another order.
+// ---------------------------------------------------------------------------
+constexpr int SPLIT_GNT = 512;   // threads of the gather and epilogue launches
+
+__device__ inline int split_slot(int b, int nb) {
+  // consecutive slots on one XCD (a clique's tiles share its operands in L2)
+  const int q8 = nb / 8, r8 = nb % 8, x8 = b % 8;
+  return x8 * q8 + min(x8, r8) + b / 8;
+}
+
+// W = the projection input (zero outside the clique) into matrix 3 of the
+// clique's workspace, X0 = W / ||W||_F into matrix 0.
+template <int N, int MODE>
+__global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const int32_t *__restrict__ list,
+                                                            double *__restrict__ ws) {
+  constexpr int PER = (N * N + SPLIT_GNT - 1) / SPLIT_GNT;
+  __shared__ double red[SPLIT_GNT / 64];
+  const int q = split_slot(blockIdx.x, gridDim.x);
+  const int cl = list[q];
+  const int inst = a.cl_inst[cl];
+  const int s = a.cl_size[cl];
+  const int64_t off = a.cl_off[cl];
+  if (a.state[inst].done != 0) return;   // a finished instance: nothing (uniform)
+  const double rho = a.state[inst].rho;
+  const double hf = MODE == 3 ? a.hs[inst].f : 0.0;
+  double *W = ws + ((int64_t)q * 4 + 3) * N * N, *X0 = ws + (int64_t)q * 4 * N * N;
+  double v[PER], f2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int idx = threadIdx.x + SPLIT_GNT * t;
+    const int i = idx / N, j = idx % N;
+    double w = 0.0;
+    if (idx < N * N && i < s && j < s) {
+      const int ii = i > j ? i : j, jj = i > j ? j : i;
+      const int64_t e = off + (int64_t)ii * (ii + 1) / 2 + jj;
+      // the arithmetic of k_sign_big's gather, term for term
+      if (MODE == 1) w = a.u[a.blk_loc[e]] - a.Lam[e] / rho;
+      else if (MODE == 2) w = a.Vd[e] - a.Lam[e] / rho;
+      else w = 0.5 * ((a.h_ns[e] - a.h_nt[e]) + a.h_sx[a.blk_loc[e]]) - hf * a.h_mzs[e] - a.Lam[e];
+    }
+    v[t] = w;
+    f2 += w * w;
+  }
+  f2 = block_sum<SPLIT_GNT>(f2, red);
+  const double scale = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int idx = threadIdx.x + SPLIT_GNT * t;
+    if (idx < N * N) {
+      W[idx] = v[t];
+      X0[idx] = v[t] * scale;
+    }
+  }
+}
+
+// One product of the split iteration: matrix ob = sa I + sb (A M) on the
+// lower tiles, mirrored, with A = matrix lb and M = matrix mb or (from_l)
+// alpha I + beta A.  A workgroup of four waves takes a 2 x 2 block of tiles
+// (rows 32 I2 .. + 31, columns 32 J2 .. + 31, I2 >= J2; in a diagonal block
+// the wave of the upper tile only loads): it stages the two 32-column slabs
+// A(:, 32 I2 ..) and M(:, 32 J2 ..) in LDS with 16-byte loads, and each wave
+// forms its tile from there, so a workgroup reads 2 N x 32 entries for four
+// tiles instead of 2 N x 16 per tile.
+template <int N>
+__global__ __launch_bounds__(256) void k_split_pass(ProjArgs a, const int32_t *__restrict__ list,
+                                                    double *__restrict__ ws, int lb, int mb, int ob,
+                                                    int from_l, double alpha, double beta,
+                                                    double sa, double sb) {
+  constexpr int TN2 = N / 32, WPC = TN2 * (TN2 + 1) / 2, STEPS = N / 4, SP = 33;
+  static_assert(N % 32 == 0, "blocks of 2 x 2 tiles");
+  typedef Mma<double>::v4 v4;
+  __shared__ double sA[N * SP], sM[N * SP];
+  __shared__ double tr[4][16][17];
+  const int lin = split_slot(blockIdx.x, gridDim.x);
+  const int q = lin / WPC, blk = lin % WPC;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  if (a.state[a.cl_inst[list[q]]].done != 0) return;   // uniform per workgroup
+  const double *A = ws + ((int64_t)q * 4 + lb) * N * N;
+  const double *M = ws + ((int64_t)q * 4 + mb) * N * N;
+  double *O = ws + ((int64_t)q * 4 + ob) * N * N;
+  // block -> (I2, J2), I2 >= J2, row by row of the lower triangle
+  int I2 = 0;
+  while ((I2 + 1) * (I2 + 2) / 2 <= blk) ++I2;
+  const int J2 = blk - I2 * (I2 + 1) / 2;
+  // the slabs: row k, columns 32 I2 + 2 m, +1 (A) and 32 J2 + 2 m, +1 (M)
+  for (int f = tid; f < N * 16; f += 256) {
+    const int k = f >> 4, m = f & 15;
+    const double2 va = *reinterpret_cast<const double2 *>(A + k * N + 32 * I2 + 2 * m);
+    const int jb = 32 * J2 + 2 * m;
+    double2 vm;
+    if (from_l) {
+      vm = *reinterpret_cast<const double2 *>(A + k * N + jb);
+      vm.x = (k == jb ? alpha : 0.0) + beta * vm.x;
+      vm.y = (k == jb + 1 ? alpha : 0.0) + beta * vm.y;
+    } else {
+      vm = *reinterpret_cast<const double2 *>(M + k * N + jb);
+    }
+    sA[k * SP + 2 * m] = va.x;
+    sA[k * SP + 2 * m + 1] = va.y;
+    sM[k * SP + 2 * m] = vm.x;
+    sM[k * SP + 2 * m + 1] = vm.y;
+  }
+  __syncthreads();
+  const int I = 2 * I2 + (w >> 1), J = 2 * J2 + (w & 1);
+  const bool live = I >= J;
+  const int xa = 16 * (w >> 1) + c, xb = 16 * (w & 1) + c;   // slab columns
+  v4 acc = v4{0, 0, 0, 0};
+  if (live) {
+#pragma unroll 8
+    for (int st = 0; st < STEPS; ++st) {
+      const int k = 4 * st + g;
+      acc = Mma<double>::step(sA[k * SP + xa], sM[k * SP + xb], acc);
+    }
+  }
+  // rows 16 I + g + 4 r, column 16 J + c: the lower entries directly, the
+  // mirrored ones through a transpose in LDS (coalesced rows both ways)
+  const int ca = 16 * I + c, cb = 16 * J + c;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int il = g + 4 * r;
+    const double v = (I == J && il == c ? sa : 0.0) + sb * acc[r];
+    tr[w][il][c] = v;
+    if (live && (I > J || il >= c)) O[(16 * I + il) * N + cb] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int il = g + 4 * r;   // target row 16 J + il, column 16 I + c
+    if (live && (I > J || il < c)) O[(16 * J + il) * N + ca] = tr[w][c][il];
+  }
+}
+
+// P+(W) = (W + S W) / 2 from matrices cb (S W) and 3 (W) of the workspace,
+// and the clique step of each algorithm, as k_sign_big's epilogue.
+template <int N, int MODE>
+__global__ __launch_bounds__(SPLIT_GNT) void k_split_epilogue(ProjArgs a, const int32_t *__restrict__ list,
+                                                              const double *__restrict__ ws, int cb) {
+  __shared__ double red[6 * (SPLIT_GNT / 64)];
+  const int q = split_slot(blockIdx.x, gridDim.x);
+  const int cl = list[q];
+  const int inst = a.cl_inst[cl];
+  const int s = a.cl_size[cl];
+  const int64_t off = a.cl_off[cl];
+  if (a.state[inst].done != 0) return;
+  const double rho = a.state[inst].rho;
+  const double hf = MODE == 3 ? a.hs[inst].f : 0.0;
+  const double *C = ws + ((int64_t)q * 4 + cb) * N * N, *W = ws + ((int64_t)q * 4 + 3) * N * N;
+  double pv[6] = {0, 0, 0, 0, 0, 0};
+  for (int idx = threadIdx.x; idx < s * N; idx += SPLIT_GNT) {
+    const int i = idx / N, j = idx % N;
+    if (j > i) continue;
+    const int64_t e = off + (int64_t)i * (i + 1) / 2 + j;
+    const double wv = W[idx];
+    const double xn = 0.5 * (wv + C[idx]);
+    const double wt = (i == j) ? 1.0 : 2.0;
+    if (MODE == 3) {
+      const int32_t lc = a.blk_loc[e];
+      const double lam = a.Lam[e], hx = a.h_sx[lc], ntv = a.h_nt[e];
+      const double ss = 0.5 * (a.h_ns[e] - ntv + hx);
+      const double us_hat = ss - hf * a.h_mzs[e];
+      const double ut = ss - hx + ntv - hf * a.h_mzt[e];
+      const double vzn = lam - us_hat + xn;
+      a.X[e] = xn;
+      a.Lam[e] = vzn;
+      a.h_ut[e] = ut;
+      const double hux = a.h_ux[lc];
+      pv[0] += wt * (xn - hux) * (xn - hux);
+      pv[1] += wt * xn * xn;
+      pv[2] += wt * hux * hux;
+      pv[3] += wt * (vzn - ut) * (vzn - ut);
+      pv[4] += wt * vzn * vzn;
+      pv[5] += wt * ut * ut;
+      continue;
+    }
+    const double xo = a.X[e];
+    a.X[e] = xn;
+    const double dx = xn - xo;
+    pv[3] += wt * dx * dx;
+    if (MODE == 1) {
+      const double lam = a.Lam[e], h = a.u[a.blk_loc[e]];
+      const double ln = lam + rho * (xn - h);
+      a.Lam[e] = ln;
+      const double dc = xn - h;
+      pv[0] += wt * dc * dc;
+      pv[1] += wt * xn * xn;
+      pv[2] += wt * h * h;
+      pv[4] += wt * ln * ln;
+    }
+  }
+  block_sum_n<SPLIT_GNT, 6>(pv, red);
+  if (threadIdx.x == 0) {
+    double *pp = a.part + NPART * (int64_t)cl;
+    if (MODE != 2) {
+      pp[0] = pv[0];
+      pp[1] = pv[1];
+      pp[2] = pv[2];
+      pp[4] = pv[4];
+    }
+    pp[3] = pv[3];
+    pp[5] = 0.0;
+    pp[6] = pv[5];
+  }
+}
+
+// The launches of one split projection: gather, 3 k1 + 2 k2 + 1 products,
+// epilogue.  ws holds 4 N^2 doubles per clique of the list.
+template <int N, int MODE>
+hipError_t launch_split(const ProjArgs &a, const int32_t *list, int count, double *ws, int k1,
+                        int k2, hipStream_t st) {
+  constexpr int WPC = (N / 32) * (N / 32 + 1) / 2;
+  hipLaunchKernelGGL((k_split_gather<N, MODE>), dim3(count), dim3(SPLIT_GNT), 0, st, a, list, ws);
+  const auto pass = [&](int lb, int mb, int ob, int from_l, double alpha, double beta, double sa,
+                        double sb) {
+    hipLaunchKernelGGL((k_split_pass<N>), dim3(count * WPC), dim3(256), 0, st, a, list, ws, lb, mb,
+                       ob, from_l, alpha, beta, sa, sb);
+  };
+  // matrices 0-2 rotate (x: the iterate; the other two: free), 3 is W
+  int bx = 0;
+  const auto other = [](int u, int v) { return 3 - u - v; };   // the third of 0, 1, 2
+  for (int it = 0; it < k1; ++it) {
+    const int by = (bx + 1) % 3, bz = other(bx, by);
+    pass(bx, bx, by, 0, 0.0, 0.0, 0.0, 1.0);      // Y = X X
+    pass(by, by, bz, 1, -3.2, 1.2, 3.0, 1.0);     // Z' = 3 I + Y (-3.2 I + 1.2 Y)
+    pass(bz, bx, by, 0, 0.0, 0.0, 0.0, 1.0);      // X <- Z' X
+    bx = by;
+  }
+  for (int it = 0; it < k2; ++it) {
+    const int by = (bx + 1) % 3, bz = other(bx, by);
+    pass(bx, bx, by, 0, 0.0, 0.0, 1.5, -0.5);     // 1.5 I - 0.5 X X
+    pass(by, bx, bz, 0, 0.0, 0.0, 0.0, 1.0);      // X <- (1.5 I - 0.5 X^2) X
+    bx = bz;
+  }
+  const int bc = (bx + 1) % 3;
+  pass(bx, 3, bc, 0, 0.0, 0.0, 0.0, 1.0);         // S W
+  hipLaunchKernelGGL((k_split_epilogue<N, MODE>), dim3(count), dim3(SPLIT_GNT), 0, st, a, list,
+                     (const double *)ws, bc);
+  return hipGetLastError();
+}
+
 template <typename T, int N, int NT>
 hipError_t launch_sign(int count, const int32_t *sizes, const int64_t *offsets, const void *in,
                        void *out, int k1, int k2, hipStream_t st) {
@@ -2629,8 +2880,22 @@ hipError_t dispatch_sign(int dtype, int N, int NT, int count, const int32_t *siz
   return hipErrorInvalidValue;
 }
 
+// A few large FP64 cliques leave most compute units idle with one workgroup
+// per clique: up to SPLIT_MAX_CLIQUES cliques of blocks of 96 or 128 take
+// the split iteration (a block of 128 spreads over 36 waves instead of 8).
+constexpr int SPLIT_MAX_CLIQUES = 64;
+
+int64_t split_workspace(int precision, int variant, int count) {
+  int N, NT;
+  projection_variant_info(precision, variant, &N, &NT);
+  if (precision != 0 || projection_variant_kind(precision, variant) != 2 || NT != 4 * N ||
+      (N != 96 && N != 128) || count <= 0 || count > SPLIT_MAX_CLIQUES)
+    return 0;
+  return (int64_t)count * 4 * N * N;
+}
+
 hipError_t launch_admm_projection(int precision, int variant, const int32_t *list, int count,
-                                  const ProjArgs &a, hipStream_t st) {
+                                  const ProjArgs &a, hipStream_t st, double *split_ws) {
   int N, NT;
   projection_variant_info(precision, variant, &N, &NT);
   if (projection_variant_kind(precision, variant) == 2) {
@@ -2675,6 +2940,19 @@ hipError_t launch_admm_projection(int precision, int variant, const int32_t *lis
       if (count <= 0) return hipSuccess;
       int k1, k2;
       sign_schedule(a.tol, N, &k1, &k2);
+      if (split_ws && split_workspace(precision, variant, count) > 0) {
+        const int mode = a.hsde ? 3 : a.dual ? 2 : 1;
+#define SDP_SPLIT(n)                                                                           \
+  if (N == n) {                                                                                \
+    if (mode == 3) return launch_split<n, 3>(a, list, count, split_ws, k1, k2, st);            \
+    if (mode == 2) return launch_split<n, 2>(a, list, count, split_ws, k1, k2, st);            \
+    return launch_split<n, 1>(a, list, count, split_ws, k1, k2, st);                           \
+  }
+        SDP_SPLIT(96)
+        SDP_SPLIT(128)
+#undef SDP_SPLIT
+        return hipErrorInvalidValue;
+      }
 #define SDP_ADMM_BIG(n)                                                                        \
   if (N == n) {                                                                                \
     if (a.hsde)                                                                                \

@@ -282,6 +282,9 @@ struct sdp_handle {
   std::vector<HsdeState> h_hs;
   std::vector<int32_t *> bucket_list;
   std::vector<int> bucket_count;
+  // per bucket: the workspace of the split sign iteration (a few large FP64
+  // cliques, split_projection), else nullptr
+  std::vector<double *> bucket_ws;
   // Buckets of different block sizes run concurrently: bucket_order[0] (the
   // largest block size, the longest per-clique latency) is enqueued first on
   // an auxiliary stream forked from the iteration's stream, the others after
@@ -323,7 +326,7 @@ void enqueue_projections(sdp_handle *h, const ProjArgs &p, hipStream_t st) {
   if (nb <= 1 || h->aux_stream.size() + 1 != nb) {
     for (size_t b = 0; b < h->bucket_size.size(); ++b)
       HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                    h->bucket_count[b], p, st));
+                                    h->bucket_count[b], p, st, h->bucket_ws[b]));
     return;
   }
   // fork: every bucket but the last on its own stream, ordered after st
@@ -332,12 +335,12 @@ void enqueue_projections(sdp_handle *h, const ProjArgs &p, hipStream_t st) {
     const int b = h->bucket_order[i];
     HIPCHK(hipStreamWaitEvent(h->aux_stream[i], h->ev_fork, 0));
     HIPCHK(launch_admm_projection(h->precision, h->bucket_size[b], h->bucket_list[b],
-                                  h->bucket_count[b], p, h->aux_stream[i]));
+                                  h->bucket_count[b], p, h->aux_stream[i], h->bucket_ws[b]));
     HIPCHK(hipEventRecord(h->ev_join[i], h->aux_stream[i]));
   }
   const int last = h->bucket_order[nb - 1];
   HIPCHK(launch_admm_projection(h->precision, h->bucket_size[last], h->bucket_list[last],
-                                h->bucket_count[last], p, st));
+                                h->bucket_count[last], p, st, h->bucket_ws[last]));
   // join: st continues only after every bucket
   for (size_t i = 0; i + 1 < nb; ++i) HIPCHK(hipStreamWaitEvent(st, h->ev_join[i], 0));
 }
@@ -1047,9 +1050,11 @@ void setup_impl(int32_t batch, const sdp_instance *inst, const sdp_options *opt_
 
     a.X = p.X;
     a.Lam = p.Lam;
-    for (auto &l : lists) {
-      h->bucket_list.push_back(dev_upload(l, own));
-      h->bucket_count.push_back((int)l.size());
+    for (size_t b = 0; b < lists.size(); ++b) {
+      h->bucket_list.push_back(dev_upload(lists[b], own));
+      h->bucket_count.push_back((int)lists[b].size());
+      const int64_t wsz = split_workspace(h->precision, h->bucket_size[b], (int)lists[b].size());
+      h->bucket_ws.push_back(wsz > 0 ? dev_zeros<double>(wsz, own) : nullptr);
     }
     h->bucket_order.resize(lists.size());
     for (size_t b = 0; b < lists.size(); ++b) h->bucket_order[b] = (int)b;

@@ -140,9 +140,16 @@ hipError_t launch_identity_bases(int precision, void *vw, const int64_t *vw_off,
                                  const int32_t *cl_n, int64_t c0, int64_t count, hipStream_t st);
 
 // Launch the ADMM projection for the cliques in `list` (all handled by one
-// kernel variant).  precision: 0 = FP64, 1 = FP32.
+// kernel variant).  precision: 0 = FP64, 1 = FP32.  split_ws: the list's
+// workspace of split_workspace(precision, variant, count) doubles where that
+// is positive (the sign iteration split over workgroups), else nullptr.
 hipError_t launch_admm_projection(int precision, int variant, const int32_t *list,
-                                  int count, const ProjArgs &a, hipStream_t st);
+                                  int count, const ProjArgs &a, hipStream_t st,
+                                  double *split_ws = nullptr);
+// Doubles of workspace the split sign iteration needs for `count` cliques of
+// this variant; 0 where the list takes one workgroup per clique (FP32,
+// blocks below 96, or enough cliques to fill the chip).
+int64_t split_workspace(int precision, int variant, int count);
 
 // Standalone batched projection of full row-major blocks.
 hipError_t launch_standalone_projection(int dtype, int variant, int count,

@@ -1,5 +1,10 @@
 """FP64 cliques of 33-128 vertices: the sign-function kernel with one block in
-LDS (k_sign_big), against the oracle (FP64 eigendecompositions).
+LDS (k_sign_big), and for lists of up to 64 blocks of 96 or 128 the same
+iteration split over workgroups (one launch per product, one wave per lower
+tile), against the oracle (FP64 eigendecompositions).
+
+* the split path on every list below with blocks of 96 or 128 (they hold 1-3
+  cliques); 66 cliques of 92 vertices keep one workgroup per clique;
 
 * fixed-N parity of Algorithm 1 (u, y, X_k, Lambda_k, residual history to
   1e-8 relative to the largest entry) on cliques of 128, alone and beside
@@ -68,6 +73,30 @@ def fixed_n(sdp, oracle_mod, inst, n_iter, tol_rel=1e-8, **opts):
 
 def test_fixed_n_cliques_of_128(sdp, gpu, oracle_mod):
     fixed_n(sdp, oracle_mod, sdpgen.block_arrow_instance(3, 120, 8, 200, seed=21), 12)
+
+
+def test_fixed_n_more_than_64_large_cliques(sdp, gpu, oracle_mod):
+    # 66 blocks of 96: above the split path's 64, so k_sign_big (one
+    # workgroup per clique) takes them
+    # (m = 150 and 12 iterations: the blocks X_k leave zero at iteration 5)
+    inst = sdpgen.block_arrow_instance(66, 90, 2, 150, seed=30)
+    log(f"FP64 66 cliques of 92 fixed-N")
+    P = oracle_mod.Problem(inst)
+    r = P.run(12, tol=0.0)
+    with sdp.Solver([inst], tol=0.0, max_iter=100000, precision="fp64") as S:
+        plan = S.projection_plan()
+        S.step(12)
+        sol = S.solution(0)
+        hc, hl, _ = S.history(0)
+    assert plan == [(96, 384, 66)], plan
+    X, L = P.blocks()
+    errs = dict(u=rel_err(sol["u"], P.u()), X=rel_err(sol["X_packed"], sdp.pack_blocks(X)),
+                L=rel_err(sol["L_packed"], sdp.pack_blocks(L)),
+                eps_c=rel_err(hc, r.hist_eps_c), eps_l=rel_err(hl, r.hist_eps_l))
+    log(f"  errors {errs}")
+    assert np.abs(X[0]).max() > 1e-3
+    for k, v in errs.items():
+        assert v <= 1e-8, (k, v)
 
 
 def test_fixed_n_cliques_of_97_to_128_eager(sdp, gpu, oracle_mod):
