@@ -2585,6 +2585,11 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
 // iterates are the same bit for bit; only ||W||_F is summed in another order.
 // ---------------------------------------------------------------------------
 constexpr int SPLIT_GNT = 512;   // threads of the gather and epilogue launches
+// After the count * 4 matrices the workspace holds SPLIT_META doubles per
+// clique, written by the gather: done flag, rho, Algorithm 3's f, size s,
+// packed offset and clique index (all exact in a double), so that the later
+// launches read them with one load instead of three dependent ones.
+constexpr int SPLIT_META = 8;
 
 __device__ inline int split_slot(int b, int nb) {
   // consecutive slots on one XCD (a clique's tiles share its operands in L2)
@@ -2604,26 +2609,69 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const in
   const int inst = a.cl_inst[cl];
   const int s = a.cl_size[cl];
   const int64_t off = a.cl_off[cl];
-  if (a.state[inst].done != 0) return;   // a finished instance: nothing (uniform)
+  const bool done = a.state[inst].done != 0;
   const double rho = a.state[inst].rho;
   const double hf = MODE == 3 ? a.hs[inst].f : 0.0;
+  if (threadIdx.x == 0) {
+    double *meta = ws + (int64_t)gridDim.x * 4 * N * N + (int64_t)q * SPLIT_META;
+    meta[0] = done ? 1.0 : 0.0;
+    meta[1] = rho;
+    meta[2] = hf;
+    meta[3] = (double)s;
+    meta[4] = (double)off;
+    meta[5] = (double)cl;
+  }
+  if (done) return;   // a finished instance: nothing (uniform)
   double *W = ws + ((int64_t)q * 4 + 3) * N * N, *X0 = ws + (int64_t)q * 4 * N * N;
-  double v[PER], f2 = 0.0;
+  // chunks of CH entries per thread: every load of a chunk is issued before
+  // the first is used (entries outside the clique read its first entry and
+  // are zeroed)
+  // (Algorithm 3's six operands leave no room to keep the values: it stores
+  // W at once and reads it back for X0)
+  constexpr int CH = MODE == 3 ? 8 : 16;
+  constexpr bool KEEPV = MODE != 3;
+  double v[KEEPV ? PER : 1], f2 = 0.0;
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int idx = threadIdx.x + SPLIT_GNT * t;
-    const int i = idx / N, j = idx % N;
-    double w = 0.0;
-    if (idx < N * N && i < s && j < s) {
+  for (int t0 = 0; t0 < PER; t0 += CH) {
+    int64_t ge[CH];
+    int32_t lc[CH];
+    double lam[CH], h1[CH], h2[CH], h3[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int idx = threadIdx.x + SPLIT_GNT * (t0 + c);
+      const int i = idx / N, j = idx % N;
       const int ii = i > j ? i : j, jj = i > j ? j : i;
-      const int64_t e = off + (int64_t)ii * (ii + 1) / 2 + jj;
-      // the arithmetic of k_sign_big's gather, term for term
-      if (MODE == 1) w = a.u[a.blk_loc[e]] - a.Lam[e] / rho;
-      else if (MODE == 2) w = a.Vd[e] - a.Lam[e] / rho;
-      else w = 0.5 * ((a.h_ns[e] - a.h_nt[e]) + a.h_sx[a.blk_loc[e]]) - hf * a.h_mzs[e] - a.Lam[e];
+      const bool in = t0 + c < PER && idx < N * N && i < s && j < s;
+      ge[c] = in ? off + (int64_t)ii * (ii + 1) / 2 + jj : off;
+      lam[c] = a.Lam[ge[c]];
+      if (MODE != 2) lc[c] = a.blk_loc[ge[c]];
+      if (MODE == 2) h1[c] = a.Vd[ge[c]];
+      if (MODE == 3) {
+        h1[c] = a.h_ns[ge[c]];
+        h2[c] = a.h_nt[ge[c]];
+        h3[c] = a.h_mzs[ge[c]];
+      }
     }
-    v[t] = w;
-    f2 += w * w;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (MODE == 1) h1[c] = a.u[lc[c]];
+      if (MODE == 3) h2[c] = (h1[c] - h2[c]) + a.h_sx[lc[c]];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (t0 + c >= PER) continue;
+      const int idx = threadIdx.x + SPLIT_GNT * (t0 + c);
+      const int i = idx / N, j = idx % N;
+      // the arithmetic of k_sign_big's gather, term for term
+      double w;
+      if (MODE == 3) w = 0.5 * h2[c] - hf * h3[c] - lam[c];
+      else w = h1[c] - lam[c] / rho;
+      w = (idx < N * N && i < s && j < s) ? w : 0.0;
+      if (KEEPV) v[t0 + c] = w;
+      else if (idx < N * N) W[idx] = w;
+      f2 += w * w;
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
   f2 = block_sum<SPLIT_GNT>(f2, red);
   const double scale = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
@@ -2631,8 +2679,12 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const in
   for (int t = 0; t < PER; ++t) {
     const int idx = threadIdx.x + SPLIT_GNT * t;
     if (idx < N * N) {
-      W[idx] = v[t];
-      X0[idx] = v[t] * scale;
+      if (KEEPV) {
+        W[idx] = v[t];
+        X0[idx] = v[t] * scale;
+      } else {
+        X0[idx] = W[idx] * scale;   // this thread's own store above
+      }
     }
   }
 }
@@ -2646,10 +2698,9 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const in
 // forms its tile from there, so a workgroup reads 2 N x 32 entries for four
 // tiles instead of 2 N x 16 per tile.
 template <int N>
-__global__ __launch_bounds__(256) void k_split_pass(ProjArgs a, const int32_t *__restrict__ list,
-                                                    double *__restrict__ ws, int lb, int mb, int ob,
-                                                    int from_l, double alpha, double beta,
-                                                    double sa, double sb) {
+__global__ __launch_bounds__(256) void k_split_pass(double *__restrict__ ws, int count, int lb,
+                                                    int mb, int ob, int from_l, double alpha,
+                                                    double beta, double sa, double sb) {
   constexpr int TN2 = N / 32, WPC = TN2 * (TN2 + 1) / 2, STEPS = N / 4, SP = 33;
   static_assert(N % 32 == 0, "blocks of 2 x 2 tiles");
   typedef Mma<double>::v4 v4;
@@ -2658,7 +2709,9 @@ __global__ __launch_bounds__(256) void k_split_pass(ProjArgs a, const int32_t *_
   const int lin = split_slot(blockIdx.x, gridDim.x);
   const int q = lin / WPC, blk = lin % WPC;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
-  if (a.state[a.cl_inst[list[q]]].done != 0) return;   // uniform per workgroup
+  // a finished instance's clique computes nothing (its flag loads beside
+  // the operands; the workspace is the split iteration's own)
+  const double done = ws[(int64_t)count * 4 * N * N + (int64_t)q * SPLIT_META];
   const double *A = ws + ((int64_t)q * 4 + lb) * N * N;
   const double *M = ws + ((int64_t)q * 4 + mb) * N * N;
   double *O = ws + ((int64_t)q * 4 + ob) * N * N;
@@ -2666,27 +2719,32 @@ __global__ __launch_bounds__(256) void k_split_pass(ProjArgs a, const int32_t *_
   int I2 = 0;
   while ((I2 + 1) * (I2 + 2) / 2 <= blk) ++I2;
   const int J2 = blk - I2 * (I2 + 1) / 2;
-  // the slabs: row k, columns 32 I2 + 2 m, +1 (A) and 32 J2 + 2 m, +1 (M)
-  for (int f = tid; f < N * 16; f += 256) {
-    const int k = f >> 4, m = f & 15;
-    const double2 va = *reinterpret_cast<const double2 *>(A + k * N + 32 * I2 + 2 * m);
-    const int jb = 32 * J2 + 2 * m;
-    double2 vm;
+  // the slabs: row k, columns 32 I2 + 2 m, +1 (A) and 32 J2 + 2 m, +1 (M);
+  // every load of the thread is issued before the first is used
+  constexpr int LD = N * 16 / 256;
+  const double *Ms = from_l ? A : M;
+  double2 va[LD], vm[LD];
+#pragma unroll
+  for (int it = 0; it < LD; ++it) {
+    const int f = tid + 256 * it, k = f >> 4, m = f & 15;
+    va[it] = *reinterpret_cast<const double2 *>(A + k * N + 32 * I2 + 2 * m);
+    vm[it] = *reinterpret_cast<const double2 *>(Ms + k * N + 32 * J2 + 2 * m);
+  }
+#pragma unroll
+  for (int it = 0; it < LD; ++it) {
+    const int f = tid + 256 * it, k = f >> 4, m = f & 15, jb = 32 * J2 + 2 * m;
     if (from_l) {
-      vm = *reinterpret_cast<const double2 *>(A + k * N + jb);
-      vm.x = (k == jb ? alpha : 0.0) + beta * vm.x;
-      vm.y = (k == jb + 1 ? alpha : 0.0) + beta * vm.y;
-    } else {
-      vm = *reinterpret_cast<const double2 *>(M + k * N + jb);
+      vm[it].x = (k == jb ? alpha : 0.0) + beta * vm[it].x;
+      vm[it].y = (k == jb + 1 ? alpha : 0.0) + beta * vm[it].y;
     }
-    sA[k * SP + 2 * m] = va.x;
-    sA[k * SP + 2 * m + 1] = va.y;
-    sM[k * SP + 2 * m] = vm.x;
-    sM[k * SP + 2 * m + 1] = vm.y;
+    sA[k * SP + 2 * m] = va[it].x;
+    sA[k * SP + 2 * m + 1] = va[it].y;
+    sM[k * SP + 2 * m] = vm[it].x;
+    sM[k * SP + 2 * m + 1] = vm[it].y;
   }
   __syncthreads();
   const int I = 2 * I2 + (w >> 1), J = 2 * J2 + (w & 1);
-  const bool live = I >= J;
+  const bool live = I >= J && done == 0.0;
   const int xa = 16 * (w >> 1) + c, xb = 16 * (w & 1) + c;   // slab columns
   v4 acc = v4{0, 0, 0, 0};
   if (live) {
@@ -2721,55 +2779,88 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_epilogue(ProjArgs a, const 
                                                               const double *__restrict__ ws, int cb) {
   __shared__ double red[6 * (SPLIT_GNT / 64)];
   const int q = split_slot(blockIdx.x, gridDim.x);
-  const int cl = list[q];
-  const int inst = a.cl_inst[cl];
-  const int s = a.cl_size[cl];
-  const int64_t off = a.cl_off[cl];
-  if (a.state[inst].done != 0) return;
-  const double rho = a.state[inst].rho;
-  const double hf = MODE == 3 ? a.hs[inst].f : 0.0;
+  const double *meta = ws + (int64_t)gridDim.x * 4 * N * N + (int64_t)q * SPLIT_META;
+  if (meta[0] != 0.0) return;   // a finished instance writes nothing (uniform)
+  const double rho = meta[1], hf = meta[2];
+  const int s = (int)meta[3];
+  const int64_t off = (int64_t)meta[4];
+  const int cl = (int)meta[5];
   const double *C = ws + ((int64_t)q * 4 + cb) * N * N, *W = ws + ((int64_t)q * 4 + 3) * N * N;
   double pv[6] = {0, 0, 0, 0, 0, 0};
-  for (int idx = threadIdx.x; idx < s * N; idx += SPLIT_GNT) {
-    const int i = idx / N, j = idx % N;
-    if (j > i) continue;
-    const int64_t e = off + (int64_t)i * (i + 1) / 2 + j;
-    const double wv = W[idx];
-    const double xn = 0.5 * (wv + C[idx]);
-    const double wt = (i == j) ? 1.0 : 2.0;
-    if (MODE == 3) {
-      const int32_t lc = a.blk_loc[e];
-      const double lam = a.Lam[e], hx = a.h_sx[lc], ntv = a.h_nt[e];
-      const double ss = 0.5 * (a.h_ns[e] - ntv + hx);
-      const double us_hat = ss - hf * a.h_mzs[e];
-      const double ut = ss - hx + ntv - hf * a.h_mzt[e];
-      const double vzn = lam - us_hat + xn;
+  // packed entries el = tid + SPLIT_GNT t of the clique, CH at a time with
+  // all their loads issued first (entries past the end read the first one
+  // and are skipped)
+  constexpr int EPT = (N * (N + 1) / 2 + SPLIT_GNT - 1) / SPLIT_GNT;
+  constexpr int CH = MODE == 3 ? 6 : 9;
+  const int npk = s * (s + 1) / 2;
+#pragma unroll
+  for (int t0 = 0; t0 < EPT; t0 += CH) {
+    int ix[CH];
+    int32_t lc[CH];
+    double wv[CH], cv[CH], lam[CH], xo[CH], h[CH], hx[CH], ux[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int el = threadIdx.x + SPLIT_GNT * (t0 + c);
+      const bool ok = t0 + c < EPT && el < npk;
+      int i, j;
+      tri_inv(ok ? el : 0, i, j);
+      ix[c] = i * N + j;
+      const int64_t e = off + (ok ? el : 0);
+      wv[c] = W[ix[c]];
+      cv[c] = C[ix[c]];
+      lam[c] = a.Lam[e];
+      if (MODE != 3) xo[c] = a.X[e];
+      if (MODE != 2) lc[c] = a.blk_loc[e];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (MODE == 1) h[c] = a.u[lc[c]];
+      if (MODE == 3) {
+        hx[c] = a.h_sx[lc[c]];
+        ux[c] = a.h_ux[lc[c]];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int el = threadIdx.x + SPLIT_GNT * (t0 + c);
+      if (t0 + c >= EPT || el >= npk) continue;
+      int i, j;
+      tri_inv(el, i, j);
+      const int64_t e = off + el;
+      const double xn = 0.5 * (wv[c] + cv[c]);
+      const double wt = (i == j) ? 1.0 : 2.0;
+      if (MODE == 3) {
+        const double ntv = a.h_nt[e];
+        const double ss = 0.5 * (a.h_ns[e] - ntv + hx[c]);
+        const double us_hat = ss - hf * a.h_mzs[e];
+        const double ut = ss - hx[c] + ntv - hf * a.h_mzt[e];
+        const double vzn = lam[c] - us_hat + xn;
+        a.X[e] = xn;
+        a.Lam[e] = vzn;
+        a.h_ut[e] = ut;
+        const double hux = ux[c];
+        pv[0] += wt * (xn - hux) * (xn - hux);
+        pv[1] += wt * xn * xn;
+        pv[2] += wt * hux * hux;
+        pv[3] += wt * (vzn - ut) * (vzn - ut);
+        pv[4] += wt * vzn * vzn;
+        pv[5] += wt * ut * ut;
+        continue;
+      }
       a.X[e] = xn;
-      a.Lam[e] = vzn;
-      a.h_ut[e] = ut;
-      const double hux = a.h_ux[lc];
-      pv[0] += wt * (xn - hux) * (xn - hux);
-      pv[1] += wt * xn * xn;
-      pv[2] += wt * hux * hux;
-      pv[3] += wt * (vzn - ut) * (vzn - ut);
-      pv[4] += wt * vzn * vzn;
-      pv[5] += wt * ut * ut;
-      continue;
+      const double dx = xn - xo[c];
+      pv[3] += wt * dx * dx;
+      if (MODE == 1) {
+        const double ln = lam[c] + rho * (xn - h[c]);
+        a.Lam[e] = ln;
+        const double dc = xn - h[c];
+        pv[0] += wt * dc * dc;
+        pv[1] += wt * xn * xn;
+        pv[2] += wt * h[c] * h[c];
+        pv[4] += wt * ln * ln;
+      }
     }
-    const double xo = a.X[e];
-    a.X[e] = xn;
-    const double dx = xn - xo;
-    pv[3] += wt * dx * dx;
-    if (MODE == 1) {
-      const double lam = a.Lam[e], h = a.u[a.blk_loc[e]];
-      const double ln = lam + rho * (xn - h);
-      a.Lam[e] = ln;
-      const double dc = xn - h;
-      pv[0] += wt * dc * dc;
-      pv[1] += wt * xn * xn;
-      pv[2] += wt * h * h;
-      pv[4] += wt * ln * ln;
-    }
+    __builtin_amdgcn_sched_barrier(0);
   }
   block_sum_n<SPLIT_GNT, 6>(pv, red);
   if (threadIdx.x == 0) {
@@ -2787,7 +2878,7 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_epilogue(ProjArgs a, const 
 }
 
 // The launches of one split projection: gather, 3 k1 + 2 k2 + 1 products,
-// epilogue.  ws holds 4 N^2 doubles per clique of the list.
+// epilogue.  ws holds 4 N^2 + SPLIT_META doubles per clique of the list.
 template <int N, int MODE>
 hipError_t launch_split(const ProjArgs &a, const int32_t *list, int count, double *ws, int k1,
                         int k2, hipStream_t st) {
@@ -2795,7 +2886,7 @@ hipError_t launch_split(const ProjArgs &a, const int32_t *list, int count, doubl
   hipLaunchKernelGGL((k_split_gather<N, MODE>), dim3(count), dim3(SPLIT_GNT), 0, st, a, list, ws);
   const auto pass = [&](int lb, int mb, int ob, int from_l, double alpha, double beta, double sa,
                         double sb) {
-    hipLaunchKernelGGL((k_split_pass<N>), dim3(count * WPC), dim3(256), 0, st, a, list, ws, lb, mb,
+    hipLaunchKernelGGL((k_split_pass<N>), dim3(count * WPC), dim3(256), 0, st, ws, count, lb, mb,
                        ob, from_l, alpha, beta, sa, sb);
   };
   // matrices 0-2 rotate (x: the iterate; the other two: free), 3 is W
@@ -2891,7 +2982,7 @@ int64_t split_workspace(int precision, int variant, int count) {
   if (precision != 0 || projection_variant_kind(precision, variant) != 2 || NT != 4 * N ||
       (N != 96 && N != 128) || count <= 0 || count > SPLIT_MAX_CLIQUES)
     return 0;
-  return (int64_t)count * 4 * N * N;
+  return (int64_t)count * (4 * N * N + SPLIT_META);
 }
 
 hipError_t launch_admm_projection(int precision, int variant, const int32_t *list, int count,
