@@ -2598,11 +2598,15 @@ __device__ inline int split_slot(int b, int nb) {
 }
 
 // W = the projection input (zero outside the clique) into matrix 3 of the
-// clique's workspace, X0 = W / ||W||_F into matrix 0.
+// clique's workspace, X0 = W / ||W||_F into matrix 0.  The threads walk the
+// packed lower triangle in order (coalesced loads of the clique's blocks),
+// keep their values and write both triangles once ||W||_F is known; the
+// padding is written too (as zeros), since the products leave other values
+// there that must not reach the next iteration.
 template <int N, int MODE>
 __global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const int32_t *__restrict__ list,
                                                             double *__restrict__ ws) {
-  constexpr int PER = (N * N + SPLIT_GNT - 1) / SPLIT_GNT;
+  constexpr int EPT = (N * (N + 1) / 2 + SPLIT_GNT - 1) / SPLIT_GNT;
   __shared__ double red[SPLIT_GNT / 64];
   const int q = split_slot(blockIdx.x, gridDim.x);
   const int cl = list[q];
@@ -2623,33 +2627,26 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const in
   }
   if (done) return;   // a finished instance: nothing (uniform)
   double *W = ws + ((int64_t)q * 4 + 3) * N * N, *X0 = ws + (int64_t)q * 4 * N * N;
-  // chunks of CH entries per thread: every load of a chunk is issued before
-  // the first is used (entries outside the clique read its first entry and
-  // are zeroed)
-  // (Algorithm 3's six operands leave no room to keep the values: it stores
-  // W at once and reads it back for X0)
-  constexpr int CH = MODE == 3 ? 8 : 16;
-  constexpr bool KEEPV = MODE != 3;
-  double v[KEEPV ? PER : 1], f2 = 0.0;
+  const int npk = s * (s + 1) / 2;
+  // chunks of CH entries: every load of a chunk is issued before the first
+  // is used (entries past the end read the clique's first entry)
+  constexpr int CH = MODE == 3 ? 6 : 9;
+  double v[EPT], f2 = 0.0;
 #pragma unroll
-  for (int t0 = 0; t0 < PER; t0 += CH) {
-    int64_t ge[CH];
+  for (int t0 = 0; t0 < EPT; t0 += CH) {
     int32_t lc[CH];
     double lam[CH], h1[CH], h2[CH], h3[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int idx = threadIdx.x + SPLIT_GNT * (t0 + c);
-      const int i = idx / N, j = idx % N;
-      const int ii = i > j ? i : j, jj = i > j ? j : i;
-      const bool in = t0 + c < PER && idx < N * N && i < s && j < s;
-      ge[c] = in ? off + (int64_t)ii * (ii + 1) / 2 + jj : off;
-      lam[c] = a.Lam[ge[c]];
-      if (MODE != 2) lc[c] = a.blk_loc[ge[c]];
-      if (MODE == 2) h1[c] = a.Vd[ge[c]];
+      const int el = threadIdx.x + SPLIT_GNT * (t0 + c);
+      const int64_t e = off + ((t0 + c < EPT && el < npk) ? el : 0);
+      lam[c] = a.Lam[e];
+      if (MODE != 2) lc[c] = a.blk_loc[e];
+      if (MODE == 2) h1[c] = a.Vd[e];
       if (MODE == 3) {
-        h1[c] = a.h_ns[ge[c]];
-        h2[c] = a.h_nt[ge[c]];
-        h3[c] = a.h_mzs[ge[c]];
+        h1[c] = a.h_ns[e];
+        h2[c] = a.h_nt[e];
+        h3[c] = a.h_mzs[e];
       }
     }
 #pragma unroll
@@ -2659,32 +2656,40 @@ __global__ __launch_bounds__(SPLIT_GNT) void k_split_gather(ProjArgs a, const in
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      if (t0 + c >= PER) continue;
-      const int idx = threadIdx.x + SPLIT_GNT * (t0 + c);
-      const int i = idx / N, j = idx % N;
+      if (t0 + c >= EPT) continue;
+      const int el = threadIdx.x + SPLIT_GNT * (t0 + c);
       // the arithmetic of k_sign_big's gather, term for term
-      double w;
-      if (MODE == 3) w = 0.5 * h2[c] - hf * h3[c] - lam[c];
-      else w = h1[c] - lam[c] / rho;
-      w = (idx < N * N && i < s && j < s) ? w : 0.0;
-      if (KEEPV) v[t0 + c] = w;
-      else if (idx < N * N) W[idx] = w;
-      f2 += w * w;
+      double w = MODE == 3 ? 0.5 * h2[c] - hf * h3[c] - lam[c] : h1[c] - lam[c] / rho;
+      if (el >= npk) w = 0.0;
+      int i, j;
+      tri_inv(el < npk ? el : 0, i, j);
+      v[t0 + c] = w;
+      f2 += (i == j ? 1.0 : 2.0) * w * w;
     }
     __builtin_amdgcn_sched_barrier(0);
   }
   f2 = block_sum<SPLIT_GNT>(f2, red);
   const double scale = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int idx = threadIdx.x + SPLIT_GNT * t;
-    if (idx < N * N) {
-      if (KEEPV) {
-        W[idx] = v[t];
-        X0[idx] = v[t] * scale;
-      } else {
-        X0[idx] = W[idx] * scale;   // this thread's own store above
+  for (int t = 0; t < EPT; ++t) {
+    const int el = threadIdx.x + SPLIT_GNT * t;
+    if (el < npk) {
+      int i, j;
+      tri_inv(el, i, j);
+      const double x0 = v[t] * scale;
+      W[i * N + j] = v[t];
+      X0[i * N + j] = x0;
+      if (i != j) {
+        W[j * N + i] = v[t];
+        X0[j * N + i] = x0;
       }
+    }
+  }
+  // the padding rows and columns
+  for (int idx = threadIdx.x; idx < N * N; idx += SPLIT_GNT) {
+    if (idx / N >= s || idx % N >= s) {
+      W[idx] = 0.0;
+      X0[idx] = 0.0;
     }
   }
 }
