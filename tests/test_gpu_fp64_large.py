@@ -160,6 +160,28 @@ def test_solve_and_diagnostics_cliques_of_128(sdp, gpu, oracle_mod):
         assert abs(dg[k] - do[k]) <= 1e-6 * max(do[k], 1e-12) + absbar, k
 
 
+def test_batched_solve_cliques_of_128_instances_stop_apart(sdp, gpu, oracle_mod):
+    # two instances on one split list: the first to converge stops writing
+    # (its cliques' done flag) while the other keeps iterating
+    insts = [sdpgen.block_arrow_instance(2, 120, 8, 150, seed=25),
+             sdpgen.block_arrow_instance(2, 118, 6, 120, seed=31)]
+    refs = []
+    for inst in insts:
+        P = oracle_mod.Problem(inst)
+        r = P.run(20000, tol=1e-4)
+        assert r.status == 0
+        refs.append((r.iters, P.objective()))
+    with sdp.Solver(insts, tol=1e-4, max_iter=20000, precision="fp64") as S:
+        assert [n for n, _, _ in S.projection_plan()] == [128]
+        res = S.solve()
+    log(f"two instances: gpu {[(g['iters'], g['objective']) for g in res]} oracle {refs}")
+    assert refs[0][0] != refs[1][0]   # they do stop apart
+    for g, (it, obj) in zip(res, refs):
+        assert g["status"] == 0
+        assert abs(g["iters"] - it) <= 1
+        assert abs(g["objective"] - obj) <= 1e-6 * max(1.0, abs(obj))
+
+
 def hsde_fixed_n(sdp, oracle_mod, inst, n_iter, tol_rel=1e-8, **opts):
     """Algorithm 3 from u = v = (0, ..., 0, 1): x = u_x / tau, y = u_y / tau,
     u_s, v_z and the residual history against the oracle's."""
