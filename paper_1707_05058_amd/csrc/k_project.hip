@@ -2581,8 +2581,9 @@ __global__ __launch_bounds__(4 * N) void k_sign_big(ProjArgs a, const int32_t *_
 // last product).  A product reads its left operand A(i, k) as A(k, i): every
 // iterate is exactly symmetric (the lower tiles are computed and mirrored),
 // so each step of the matrix cores loads four rows of 16 consecutive
-// entries.  The accumulation runs over k in the order k_sign_big uses, so the
-// iterates are the same bit for bit; only ||W||_F is summed in another order.
+// entries.  The products accumulate over k in the order k_sign_big uses;
+// ||W||_F is summed in another order, so the iterates agree with k_sign_big's
+// to rounding, not bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int SPLIT_GNT = 512;   // threads of the gather and epilogue launches
 // After the count * 4 matrices the workspace holds SPLIT_META doubles per
