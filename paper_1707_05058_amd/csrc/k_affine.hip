@@ -526,11 +526,13 @@ __device__ inline double cg_block_sum(double x, double *red) {
   return s;
 }
 
-// sum of one partial over the tiles of an instance, in tile order
+// sum of one partial over the tiles of an instance, by one whole wave (lane
+// l takes tiles t0 + l, t0 + l + 64, ..., then the butterfly): every lane
+// gets the same total, formed in a fixed order
 __device__ inline double cg_tiles_sum(const double *part, int t0, int t1) {
   double s = 0.0;
-  for (int t = t0; t < t1; ++t) s += part[t];
-  return s;
+  for (int t = t0 + (int)(threadIdx.x & 63); t < t1; t += 64) s += part[t];
+  return wave_sum(s);
 }
 
 // MODE 0 (start): z = r / diag, p = z; partials r^T z, ||r||^2.
@@ -599,14 +601,15 @@ __global__ __launch_bounds__(CG_NT) void k_cg_rows(AffineArgs a) {
 // Per instance, after MODE 0 (start = 1) or MODE 3 (start = 0): r^T z and
 // ||r||^2 from the partials, step count and the stopping test.
 __global__ __launch_bounds__(256) void k_cg_scalars(AffineArgs a, int start) {
-  const int inst = blockIdx.x * 256 + threadIdx.x;
-  if (inst >= a.batch) return;
+  const int inst = blockIdx.x * 4 + (int)(threadIdx.x >> 6);   // one wave per instance
+  if (inst >= a.batch) return;                                 // (uniform per wave)
   if (!a.ignore_done && a.state[inst].done) return;
   CgState c = a.cg[inst];
   if (!start && c.done) return;
   const int t0 = a.cg_tile_first[inst], t1 = a.cg_tile_first[inst + 1];
   c.rz = cg_tiles_sum(a.cg_part + a.cg_ntiles, t0, t1);
   c.rn2 = cg_tiles_sum(a.cg_part + 2 * a.cg_ntiles, t0, t1);
+  if ((threadIdx.x & 63) != 0) return;
   if (start) {
     c.steps = 0;
     c.done = (a.cg_max_iter <= 0 || c.rn2 <= a.cg_tol2[inst]) ? 1 : 0;
@@ -777,7 +780,7 @@ void launch_rowdots(const AffineArgs &a, hipStream_t st) {
 
 hipError_t launch_cg_stage(const AffineArgs &a, int stage, hipStream_t st) {
   if (stage != 2) return launch_affine_stage(a, stage, st);
-  const dim3 tg(a.cg_ntiles), sg((a.batch + 255) / 256);
+  const dim3 tg(a.cg_ntiles), sg((a.batch + 3) / 4);
   hipLaunchKernelGGL(k_cg_rows<0>, tg, dim3(CG_NT), 0, st, a);
   hipLaunchKernelGGL(k_cg_scalars, sg, dim3(256), 0, st, a, 1);
   AffineArgs at = a;        // v = W D^-1 A^T p

@@ -51,6 +51,27 @@ __device__ inline double block_total(double v, double *red) {
   return s;
 }
 
+// NV workgroup totals at once (one pair of barriers; red holds NV * NT / 64
+// doubles), each summed in block_total's order, so the totals are the same
+// bit for bit.
+template <int NT, int NV>
+__device__ inline void block_total_n(double (&v)[NV], double *red) {
+#pragma unroll
+  for (int n = 0; n < NV; ++n) v[n] = wsum(v[n]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int n = 0; n < NV; ++n) red[n * (NT / 64) + (threadIdx.x >> 6)] = v[n];
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < NV; ++n) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[n * (NT / 64) + i];
+    v[n] = s;
+  }
+}
+
 __device__ inline double cratio(double num, double a, double b) {
   const double den = a > b ? a : b;
   if (den > 0.0) return num / den;
@@ -190,15 +211,22 @@ __global__ __launch_bounds__(256) void k_hsde_zs_partials(HsdeArgs h) {
   }
 }
 
-// One thread per instance: f = kz zeta^T sigma, u_hat_tau = omega_2 + f,
-// tau = max(0, u_hat_tau - kappa), kappa -= u_hat_tau - tau.
+// One workgroup per instance: zeta^T sigma from the wave partials (each
+// thread a strided share, summed over the workgroup in a fixed order), then
+// f = kz zeta^T sigma, u_hat_tau = omega_2 + f, tau = max(0, u_hat_tau -
+// kappa), kappa -= u_hat_tau - tau.
 __global__ __launch_bounds__(256) void k_hsde_scalars(HsdeArgs h) {
-  const int inst = blockIdx.x * 256 + threadIdx.x;
-  if (inst >= h.batch || h.state[inst].done) return;
+  __shared__ double red[4];
+  const int inst = blockIdx.x;
+  if (h.state[inst].done) return;   // uniform per workgroup
   const InstDesc d = h.inst[inst];
   double zs = 0.0;
-  for (int64_t q = d.coord_off >> 6; q < (d.coord_off + d.ld) >> 6; ++q) zs += h.cw_part[q * WSLOT];
-  for (int64_t q = d.row_off >> 6; q < (d.row_off + d.ldm) >> 6; ++q) zs += h.rw_part[q * WSLOT];
+  for (int64_t q = (d.coord_off >> 6) + threadIdx.x; q < (d.coord_off + d.ld) >> 6; q += 256)
+    zs += h.cw_part[q * WSLOT];
+  for (int64_t q = (d.row_off >> 6) + threadIdx.x; q < (d.row_off + d.ldm) >> 6; q += 256)
+    zs += h.rw_part[q * WSLOT];
+  zs = block_total<256>(zs, red);
+  if (threadIdx.x != 0) return;
   HsdeState &s = h.hs[inst];
   const double f = s.kz * zs;
   const double uhat_tau = s.w2 + f;
@@ -283,7 +311,7 @@ __global__ __launch_bounds__(256) void k_hsde_finish(HsdeArgs h) {
   if (st.done) return;
   const InstDesc d = h.inst[inst];
   HsdeState &s = h.hs[inst];
-  __shared__ double red[4];
+  __shared__ double red[13 * 4];
   double ctx = 0.0, r2 = 0.0, rd2 = 0.0, bty = 0.0, ax2 = 0.0, rp2 = 0.0;
   for (int64_t q = (d.coord_off >> 6) + threadIdx.x; q < (d.coord_off + d.ld) >> 6; q += 256) {
     const double *p = h.cw_part + q * WSLOT;
@@ -304,15 +332,17 @@ __global__ __launch_bounds__(256) void k_hsde_finish(HsdeArgs h) {
 #pragma unroll
     for (int q = 0; q < 7; ++q) S[q] += pk[q];
   }
-  ctx = block_total<256>(ctx, red);
-  r2 = block_total<256>(r2, red);
-  rd2 = block_total<256>(rd2, red);
-  bty = block_total<256>(bty, red);
-  ax2 = block_total<256>(ax2, red);
-  rp2 = block_total<256>(rp2, red);
-#pragma unroll
-  for (int q = 0; q < 7; ++q) S[q] = block_total<256>(S[q], red);
+  double tot[13] = {ctx, r2, rd2, bty, ax2, rp2, S[0], S[1], S[2], S[3], S[4], S[5], S[6]};
+  block_total_n<256, 13>(tot, red);
   if (threadIdx.x != 0) return;
+  ctx = tot[0];
+  r2 = tot[1];
+  rd2 = tot[2];
+  bty = tot[3];
+  ax2 = tot[4];
+  rp2 = tot[5];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) S[q] = tot[6 + q];
   s.ctx = ctx;
   s.bty = bty;
   const SolverParams &P = h.params;
@@ -412,7 +442,7 @@ hipError_t launch_hsde_update(const HsdeArgs &h, hipStream_t st) {
   const int64_t n = h.ncoord > h.nrow ? h.ncoord : h.nrow;
   const unsigned nb = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_hsde_zs_partials, dim3(nb), dim3(256), 0, st, h);
-  hipLaunchKernelGGL(k_hsde_scalars, dim3((h.batch + 255) / 256), dim3(256), 0, st, h);
+  hipLaunchKernelGGL(k_hsde_scalars, dim3(h.batch), dim3(256), 0, st, h);
   hipLaunchKernelGGL(k_hsde_apply, dim3(nb), dim3(256), 0, st, h);
   return hipGetLastError();
 }
