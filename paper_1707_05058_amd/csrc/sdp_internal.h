@@ -142,7 +142,8 @@ hipError_t launch_identity_bases(int precision, void *vw, const int64_t *vw_off,
 // Launch the ADMM projection for the cliques in `list` (all handled by one
 // kernel variant).  precision: 0 = FP64, 1 = FP32.  split_ws: the list's
 // workspace of split_workspace(precision, variant, count) doubles where that
-// is positive (the sign iteration split over workgroups), else nullptr.
+// is positive and the list is the plan's only one (the sign iteration split
+// over workgroups), else nullptr.
 hipError_t launch_admm_projection(int precision, int variant, const int32_t *list,
                                   int count, const ProjArgs &a, hipStream_t st,
                                   double *split_ws = nullptr);

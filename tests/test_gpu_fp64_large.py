@@ -1,10 +1,11 @@
 """FP64 cliques of 33-128 vertices: the sign-function kernel with one block in
-LDS (k_sign_big), and for lists of up to 64 blocks of 96 or 128 the same
-iteration split over workgroups (one launch per product, one wave per lower
-tile), against the oracle (FP64 eigendecompositions).
+LDS (k_sign_big), and for a plan whose only list holds up to 64 blocks of 96
+or 128 the same iteration split over workgroups (one launch per product),
+against the oracle (FP64 eigendecompositions).
 
-* the split path on every list below with blocks of 96 or 128 (they hold 1-3
-  cliques); 66 cliques of 92 vertices keep one workgroup per clique;
+* the split path on every single-list instance below (1-3 cliques of 97-128,
+  3 of 92 vertices); plans with several lists (the mixed instances) and 66
+  cliques of 92 vertices keep one workgroup per clique;
 
 * fixed-N parity of Algorithm 1 (u, y, X_k, Lambda_k, residual history to
   1e-8 relative to the largest entry) on cliques of 128, alone and beside
@@ -50,7 +51,7 @@ def hist_err(a, b):
     return rel_err(a[f], b[f]) if f.any() else 0.0
 
 
-def fixed_n(sdp, oracle_mod, inst, n_iter, tol_rel=1e-8, **opts):
+def fixed_n(sdp, oracle_mod, inst, n_iter, tol_rel=1e-8, expect_n=128, **opts):
     log(f"FP64 large-clique fixed-N {inst.name} N={n_iter} {opts}")
     P = oracle_mod.Problem(inst)
     r = P.run(n_iter, tol=0.0)
@@ -60,7 +61,7 @@ def fixed_n(sdp, oracle_mod, inst, n_iter, tol_rel=1e-8, **opts):
         sol = S.solution(0)
         hc, hl, _ = S.history(0)
     log(f"  plan {plan}")
-    assert any(n == 128 for n, _, _ in plan)
+    assert any(n == expect_n for n, _, _ in plan)
     X, L = P.blocks()
     errs = dict(u=rel_err(sol["u"], P.u()), y=rel_err(sol["y_dual"], P.y_dual()),
                 X=rel_err(sol["X_packed"], sdp.pack_blocks(X)),
@@ -97,6 +98,28 @@ def test_fixed_n_more_than_64_large_cliques(sdp, gpu, oracle_mod):
     assert np.abs(X[0]).max() > 1e-3
     for k, v in errs.items():
         assert v <= 1e-8, (k, v)
+
+
+def test_split_cliques_of_96_all_algorithms(sdp, gpu, oracle_mod):
+    # three cliques of 92 vertices, the plan's only list: the split iteration
+    # at blocks of 96 for Algorithms 1, 2 and 3
+    inst = sdpgen.block_arrow_instance(3, 88, 4, 150, seed=32)
+    fixed_n(sdp, oracle_mod, inst, 12, expect_n=96)
+    P = oracle_mod.Problem(inst)
+    r = P.run_dual(12, tol=0.0)
+    with sdp.Solver([inst], tol=0.0, max_iter=100000, precision="fp64", algorithm="dual") as S:
+        S.step(12)
+        sol = S.solution(0)
+        hc, hl, _ = S.history(0)
+    Z, L = P.blocks()
+    errs = dict(u=rel_err(sol["u"], -P.rho * P.u()), Z=rel_err(sol["X_packed"], sdp.pack_blocks(Z)),
+                L=rel_err(sol["L_packed"], sdp.pack_blocks(L)),
+                eps_c=rel_err(hc, r.hist_eps_c), eps_l=rel_err(hl, r.hist_eps_l))
+    log(f"  dual fixed-N errors {errs}")
+    for k, v in errs.items():
+        assert v <= 1e-8, (k, v)
+    plan = hsde_fixed_n(sdp, oracle_mod, inst, 60)
+    assert plan == [(96, 384, 3)], plan
 
 
 def test_fixed_n_cliques_of_97_to_128_eager(sdp, gpu, oracle_mod):
