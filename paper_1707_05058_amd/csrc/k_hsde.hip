@@ -279,26 +279,35 @@ __global__ __launch_bounds__(256) void k_hsde_apply(HsdeArgs h) {
 }
 
 // After the projections: A^T u_y + H^T v_z on the coordinates (A^T g from the
-// inner solve as x' - P sigma_x) and the dual-residual wave sums.
+// inner solve as x' - P sigma_x) and the dual-residual sums of each group of
+// 64 coordinates.  A workgroup takes one group, four lanes per coordinate
+// (each lane a strided share of the coordinate's clique entries, joined by a
+// fixed butterfly), so the gathers of v_z overlap.
 __global__ __launch_bounds__(256) void k_hsde_dual_partials(HsdeArgs h) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= h.ncoord) return;                           // uniform per wave
+  __shared__ double red[2 * 4];
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2);   // < ncoord (padded)
+  const int q4 = threadIdx.x & 3;
   const int inst = h.coord_inst[j];
   const HsdeState &s = h.hs[inst];
   double hz = 0.0;
-  for (int64_t t = h.contrib_ptr[j]; t < h.contrib_ptr[j + 1]; ++t) hz += h.vz[h.contrib_idx[t]];
-  const double aty = -(h.xp[j] - h.P[j] * h.sx[j]) - s.f * h.atmz[j];
-  const double q = aty + hz;
-  double r2 = h.w[j] * q * q, rd2 = 0.0;
-  if (s.tau > 0.0) {
-    const double dd = q / s.tau - h.c[j];
-    rd2 = h.w[j] * dd * dd;
+  for (int64_t t = h.contrib_ptr[j] + q4; t < h.contrib_ptr[j + 1]; t += 4)
+    hz += h.vz[h.contrib_idx[t]];
+  hz += __shfl_xor(hz, 1, 64);
+  hz += __shfl_xor(hz, 2, 64);
+  double v[2] = {0.0, 0.0};
+  if (q4 == 0) {
+    const double aty = -(h.xp[j] - h.P[j] * h.sx[j]) - s.f * h.atmz[j];
+    const double q = aty + hz;
+    v[0] = h.w[j] * q * q;
+    if (s.tau > 0.0) {
+      const double dd = q / s.tau - h.c[j];
+      v[1] = h.w[j] * dd * dd;
+    }
   }
-  r2 = wsum(r2);
-  rd2 = wsum(rd2);
-  if ((threadIdx.x & 63) == 0) {
-    h.cw_part[(j >> 6) * WSLOT + 2] = r2;
-    h.cw_part[(j >> 6) * WSLOT + 3] = rd2;
+  block_total_n<256, 2>(v, red);
+  if (threadIdx.x == 0) {
+    h.cw_part[(int64_t)blockIdx.x * WSLOT + 2] = v[0];
+    h.cw_part[(int64_t)blockIdx.x * WSLOT + 3] = v[1];
   }
 }
 
@@ -448,7 +457,7 @@ hipError_t launch_hsde_update(const HsdeArgs &h, hipStream_t st) {
 }
 
 hipError_t launch_hsde_finish(const HsdeArgs &h, hipStream_t st) {
-  hipLaunchKernelGGL(k_hsde_dual_partials, dim3((unsigned)((h.ncoord + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL(k_hsde_dual_partials, dim3((unsigned)(h.ncoord / 64)), dim3(256), 0,
                      st, h);
   hipLaunchKernelGGL(k_hsde_finish, dim3(h.batch), dim3(256), 0, st, h);
   return hipGetLastError();
