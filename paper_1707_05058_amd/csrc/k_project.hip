@@ -1467,14 +1467,13 @@ __global__ __launch_bounds__(256) void k_dual_update(ProjArgs a) {
     p2 += wt * v * v;
     p4 += wt * ln * ln;
   }
-  __shared__ double red[4];
-  p0 = block_sum<256>(p0, red);
-  p1 = block_sum<256>(p1, red);
-  p2 = block_sum<256>(p2, red);
-  p4 = block_sum<256>(p4, red);
+  // (the four sums in one barrier pair, each in block_sum's order)
+  __shared__ double red[4 * 4];
+  double pv[4] = {p0, p1, p2, p4};
+  block_sum_n<256, 4>(pv, red);
   if (threadIdx.x == 0) {
     double *pp = a.part + NPART * (int64_t)cl;
-    pp[0] = p0; pp[1] = p1; pp[2] = p2; pp[4] = p4;
+    pp[0] = pv[0]; pp[1] = pv[1]; pp[2] = pv[2]; pp[4] = pv[3];
   }
 }
 
